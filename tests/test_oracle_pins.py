@@ -1,0 +1,467 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+Each test names what fixes the expected value: a closed form, a brute-force
+characteristic polynomial, an exactly known factorization, an invariant of the
+mathematics, or a special case that reduces to a textbook or library routine.
+Together they are chosen so that a dropped term, a wrong sign, a wrong index or a
+transposed operand anywhere in the oracle fails at least one of them.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2606_09058_amd import inputs as I
+
+
+def herm(rng, n, cplx):
+    return I.random_hermitian(rng, n, cplx)
+
+
+def spd(rng, n, cplx):
+    X = rng.normal(size=(n, n)) + (1j * rng.normal(size=(n, n)) if cplx else 0)
+    return X @ X.conj().T + n * np.eye(n)
+
+
+# ---------------------------------------------------------------- Cholesky
+def pascal(n):
+    """Symmetric Pascal matrix P_ij = C(i+j, i); its Cholesky factor is the lower
+    Pascal matrix L_ij = C(i, j) (Vandermonde's identity), all integers."""
+    P = np.array([[math.comb(i + j, i) for j in range(n)] for i in range(n)], dtype=np.float64)
+    L = np.array([[math.comb(i, j) if j <= i else 0 for j in range(n)] for i in range(n)],
+                 dtype=np.float64)
+    return P, L
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 12])
+def test_cholesky_pascal_exact(n):
+    P, L = pascal(n)
+    Lo = O.cholesky(P)
+    assert np.array_equal(Lo, L), "Pascal factor must be reproduced exactly in FP64"
+
+
+def test_cholesky_pascal_complex_phase():
+    """D P D^H with D = diag(e^{i t}) has factor D L D^H (L = lower Pascal; the
+    factor must keep a real positive diagonal)."""
+    n = 8
+    P, L = pascal(n)
+    rng = np.random.default_rng(3)
+    D = np.diag(np.exp(1j * rng.uniform(0, 2 * np.pi, n)))
+    Lo = O.cholesky(D @ P @ D.conj().T)
+    assert np.allclose(Lo, D @ L @ D.conj().T, rtol=0, atol=1e-12 * np.abs(L).max())
+
+
+def test_cholesky_diagonal_and_lower_only():
+    d = np.array([4.0, 9.0, 2.25, 1e-6])
+    S = np.diag(d)
+    S[0, 3] = 123.0  # upper triangle must be ignored
+    assert np.array_equal(np.diag(O.cholesky(S)), np.sqrt(d))
+
+
+def test_cholesky_not_posdef_column():
+    S = np.eye(5)
+    S[3, 3] = -1.0
+    with pytest.raises(O.OracleError, match="column 4"):
+        O.cholesky(S)
+    S = np.eye(4)
+    S[2, 1] = S[1, 2] = 1.0  # pivot of column 3 becomes 0
+    with pytest.raises(O.OracleError, match="column 3"):
+        O.cholesky(S)
+
+
+def test_triangular_solves_pascal_inverse():
+    """The inverse of the lower Pascal matrix is (-1)^(i-j) C(i, j)."""
+    n = 10
+    _, L = pascal(n)
+    Linv = np.array([[(-1) ** (i - j) * math.comb(i, j) if j <= i else 0 for j in range(n)]
+                     for i in range(n)], dtype=np.float64)
+    assert np.array_equal(O.solve_lower(L, np.eye(n)), Linv)
+    assert np.array_equal(O.solve_lower_h(L, np.eye(n)), Linv.T)
+
+
+def test_triangular_solves_complex_residual():
+    rng = np.random.default_rng(1)
+    n = 9
+    L = np.tril(rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n)))
+    L[np.diag_indices(n)] = np.abs(L[np.diag_indices(n)]) + 1.0
+    B = rng.normal(size=(n, 4)) + 1j * rng.normal(size=(n, 4))
+    X = O.solve_lower(L, B)
+    assert np.abs(L @ X - B).max() < 1e-12
+    Y = O.solve_lower_h(L, B)
+    assert np.abs(L.conj().T @ Y - B).max() < 1e-12
+
+
+# ---------------------------------------------------------------- Jacobi
+@pytest.mark.parametrize("n", [1, 2, 7, 30])
+@pytest.mark.parametrize("cplx", [False, True])
+def test_jacobi_toeplitz_tridiagonal(n, cplx):
+    """tridiag(b, a, b): lambda_k = a + 2|b| cos(k pi/(n+1)), v_jk ~ sin(j k pi/(n+1)).
+    With a complex b the matrix is unitarily similar to the real one."""
+    a, b = 0.7, -1.3
+    bb = b * np.exp(0.4j) if cplx else b
+    T = np.diag(np.full(n, a)).astype(np.complex128 if cplx else np.float64)
+    for i in range(n - 1):
+        T[i + 1, i] = bb
+        T[i, i + 1] = np.conj(bb)
+    w, V, _ = O.jacobi(T)
+    k = np.arange(1, n + 1)
+    ref = np.sort(a + 2 * abs(b) * np.cos(k * np.pi / (n + 1)))
+    assert np.abs(w - ref).max() < 1e-14 * 4
+    # eigenvector moduli are fixed by the closed form (phases are a gauge)
+    j = np.arange(1, n + 1)
+    for col in range(n):
+        kk = np.argmin(np.abs(a + 2 * abs(b) * np.cos(k * np.pi / (n + 1)) - w[col]))
+        v = np.sin(j * (kk + 1) * np.pi / (n + 1))
+        v /= np.linalg.norm(v)
+        assert np.abs(np.abs(V[:, col]) - np.abs(v)).max() < 1e-12
+
+
+@pytest.mark.parametrize("n", [2, 5, 16])
+def test_jacobi_clement_integer_spectrum(n):
+    """Clement (Kac-Sylvester) matrix, symmetrized: off-diagonals sqrt(i (n - i));
+    eigenvalues -(n-1), -(n-3), ..., n-1."""
+    C = np.zeros((n, n))
+    for i in range(1, n):
+        C[i - 1, i] = C[i, i - 1] = math.sqrt(i * (n - i))
+    w, V, _ = O.jacobi(C)
+    ref = np.arange(-(n - 1), n, 2, dtype=np.float64)
+    assert np.abs(w - ref).max() < 1e-13 * n
+
+
+def test_jacobi_diagonal_stable_sort():
+    d = np.array([3.0, -1.0, 2.0, -1.0, 0.5])
+    w, V, sw = O.jacobi(np.diag(d))
+    assert np.array_equal(w, np.sort(d))
+    # ties keep index order: the two -1 eigenvalues are e_1 then e_3
+    assert V[1, 0] == 1.0 and V[3, 1] == 1.0
+    assert sw == 0
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_jacobi_vs_library_and_invariants(cplx):
+    """S = I special case of a library routine (LAPACK via numpy) + V^H V = I."""
+    rng = np.random.default_rng(7)
+    A = herm(rng, 40, cplx)
+    w, V, sw = O.jacobi(A)
+    assert sw > 0
+    assert np.abs(w - np.linalg.eigvalsh(A)).max() < 1e-13
+    assert np.abs(V.conj().T @ V - np.eye(40)).max() < 1e-13
+    assert np.abs(A @ V - V * w).max() < 1e-13
+    assert np.abs(np.trace(A).real - w.sum()) < 1e-12
+
+
+# ---------------------------------------------------------------- whole GEVP
+def closed_form_2x2(H, S):
+    """Roots of det(H - l S) = 0 for 2x2 Hermitian H, S."""
+    a = (S[0, 0] * S[1, 1] - abs(S[0, 1]) ** 2).real
+    b = -(H[0, 0] * S[1, 1] + H[1, 1] * S[0, 0] - 2 * (H[0, 1] * np.conj(S[0, 1])).real).real
+    c = (H[0, 0] * H[1, 1] - abs(H[0, 1]) ** 2).real
+    disc = math.sqrt(b * b - 4 * a * c)
+    return np.sort([(-b - disc) / (2 * a), (-b + disc) / (2 * a)])
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_gevd_2x2_closed_form(cplx):
+    rng = np.random.default_rng(11)
+    for _ in range(20):
+        H = herm(rng, 2, cplx)
+        S = spd(rng, 2, cplx)
+        eps, C = O.gevd(H, S)
+        assert np.abs(eps - closed_form_2x2(H, S)).max() < 1e-12
+
+
+def charpoly_roots(H, S):
+    """Brute force: det(H - l S) by the Leibniz expansion with polynomial entries."""
+    n = H.shape[0]
+    total = np.zeros(n + 1, np.complex128)
+    for perm in itertools.permutations(range(n)):
+        sign = np.linalg.det(np.eye(n)[list(perm)])
+        p = np.array([1.0 + 0j])
+        for i in range(n):
+            p = np.polynomial.polynomial.polymul(p, [H[i, perm[i]], -S[i, perm[i]]])
+        total[:len(p)] += sign * p
+    r = np.roots(total[::-1].real)
+    return np.sort(r.real)
+
+
+@pytest.mark.parametrize("n", [3, 4])
+@pytest.mark.parametrize("cplx", [False, True])
+def test_gevd_charpoly_brute_force(n, cplx):
+    rng = np.random.default_rng(100 + n)
+    for _ in range(5):
+        H = herm(rng, n, cplx)
+        S = spd(rng, n, cplx)
+        eps, C = O.gevd(H, S)
+        assert np.abs(eps - charpoly_roots(H, S)).max() < 1e-9
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_gevd_identity_overlap_is_standard_problem(cplx):
+    rng = np.random.default_rng(5)
+    H = herm(rng, 25, cplx)
+    eps, C = O.gevd(H, np.eye(25))
+    assert np.abs(eps - np.linalg.eigvalsh(H)).max() < 1e-13
+    d = rng.normal(size=25)
+    eps, C = O.gevd(np.diag(d), np.eye(25))
+    assert np.array_equal(eps, np.sort(d))
+
+
+def test_gevd_diagonal_overlap():
+    """S = D diagonal: eigenvalues of D^-1/2 H D^-1/2."""
+    rng = np.random.default_rng(6)
+    H = herm(rng, 20, True)
+    d = rng.uniform(0.5, 3, 20)
+    eps, _ = O.gevd(H, np.diag(d))
+    ref = np.linalg.eigvalsh(H / np.sqrt(np.outer(d, d)))
+    assert np.abs(eps - ref).max() < 1e-12
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("nsp", [1, 2])
+def test_gevd_invariants_and_lowdin_route(cplx, nsp):
+    """Residual, C^H S_NC C = I, and the Loewdin route of Sec. 3.1 / 3.2 gives the
+    same eigenvalues and density (rho does not depend on the S-orthonormal basis)."""
+    rng = np.random.default_rng(21)
+    n = 24
+    cp = cplx or nsp == 2
+    H = herm(rng, n * nsp, cp)
+    S = spd(rng, n, cp)
+    SN = np.kron(np.eye(nsp), S)
+    eps, C = O.gevd(H, S, nsp=nsp)
+    assert np.abs(C.conj().T @ SN @ C - np.eye(n * nsp)).max() < 1e-12
+    assert np.abs(H @ C - SN @ C * eps).max() < 1e-11
+    e2, C2 = O.gevd_lowdin(H, S, nsp=nsp)
+    assert np.abs(eps - e2).max() < 1e-11
+    occ = np.where(np.arange(n * nsp) < n // 2, 1.0, 0.0)
+    assert np.abs(O.density(C, occ) - O.density(C2, occ)).max() < 1e-10
+
+
+def test_gevd_reads_lower_triangle_only():
+    rng = np.random.default_rng(8)
+    H = herm(rng, 12, True)
+    S = spd(rng, 12, True)
+    Hg = H + np.triu(rng.normal(size=(12, 12)), 1)
+    Sg = S + np.triu(rng.normal(size=(12, 12)), 1)
+    e1, _ = O.gevd(H, S)
+    e2, _ = O.gevd(Hg, Sg)
+    assert np.array_equal(e1, e2)
+
+
+def test_gevd_not_posdef():
+    with pytest.raises(O.OracleError, match="column 2"):
+        O.gevd(np.eye(3), np.diag([1.0, -1.0, 1.0]))
+
+
+# ---------------------------------------------------------------- Fermi / mu
+def test_fermi_two_levels_mu_midpoint():
+    """Levels {0, D} with N_e = g: F(x) + F(-x) = 1 fixes mu = D/2.  With D = 30 kT
+    mu sits in a gap where dN/dmu ~ 1e-4/Ha, so rounding of N moves it ~1e-12."""
+    for g in (1.0, 2.0):
+        r = O.fermi(np.array([0.0, 0.03]), g, 0.01, g)
+        assert abs(r["mu"] - 0.015) < 1e-14
+        assert abs(r["occ"].sum() - g) < 1e-12
+        r = O.fermi(np.array([0.0, 0.3]), g, 0.01, g)
+        assert abs(r["mu"] - 0.15) < 1e-11
+
+
+def test_fermi_symmetric_half_filling():
+    e = np.concatenate([-np.abs(np.linspace(0.1, 1, 8)), np.abs(np.linspace(0.1, 1, 8))])
+    r = O.fermi(np.sort(e), 16.0, 0.05, 2.0)
+    assert abs(r["mu"]) < 1e-13
+
+
+def test_fermi_monotone_count_and_bounds():
+    rng = np.random.default_rng(2)
+    e = np.sort(rng.normal(size=50))
+    prev = -np.inf
+    for ne in (1.0, 10.0, 33.3, 99.0):
+        r = O.fermi(e, ne, 0.02, 2.0)
+        assert r["mu"] > prev
+        prev = r["mu"]
+        assert abs(r["occ"].sum() - ne) < 1e-10
+        assert (r["occ"] >= 0).all() and (r["occ"] <= 2.0).all()
+        assert abs(r["eband"] - (r["occ"] * e).sum()) < 1e-12
+
+
+def test_fermi_common_mu_over_kpoints():
+    """One mu for all k: weighted count equals N_e; a duplicated k-point with half
+    weight each gives the single-k result."""
+    rng = np.random.default_rng(4)
+    e1 = np.sort(rng.normal(size=20))
+    e2 = np.sort(rng.normal(size=20) + 0.3)
+    r = O.fermi(np.stack([e1, e2]), 12.0, 0.03, 2.0, wk=np.array([0.25, 0.75]))
+    cnt = 0.25 * r["occ"][0].sum() + 0.75 * r["occ"][1].sum()
+    assert abs(cnt - 12.0) < 1e-10
+    r1 = O.fermi(e1, 12.0, 0.03, 2.0)
+    r2 = O.fermi(np.stack([e1, e1]), 12.0, 0.03, 2.0)
+    assert abs(r1["mu"] - r2["mu"]) < 1e-13
+
+
+# ---------------------------------------------------------------- density
+@pytest.mark.parametrize("cplx", [False, True])
+def test_density_invariants(cplx):
+    """tr(rho S) = N_e, H rho S = S rho H, rho Hermitian PSD, eigenvalues of
+    rho S are the occupations."""
+    p = I.toy(seed=1, natoms=6, norb=8, n_electrons=20.0, phases=cplx)
+    r = O.solve(p.H, p.S, p.n_electrons, p.kT)
+    rho = r["rho"]
+    assert abs(np.trace(rho @ p.S).real - p.n_electrons) < 1e-11
+    assert np.abs(p.H @ rho @ p.S - p.S @ rho @ p.H).max() < 1e-11
+    assert np.abs(rho - rho.conj().T).max() < 1e-13
+    ev = np.linalg.eigvalsh(rho)
+    assert ev.min() > -1e-12
+    occ_from_rho = np.sort(np.linalg.eigvals(rho @ p.S).real)
+    assert np.abs(occ_from_rho - np.sort(r["occ"])).max() < 1e-10
+
+
+def test_density_full_filling_is_g_inverse_S():
+    p = I.toy(seed=2, natoms=4, norb=8, n_electrons=64.0, kT=0.001)
+    r = O.solve(p.H, p.S, p.n_electrons, p.kT)
+    assert np.abs(r["rho"] - 2.0 * np.linalg.inv(p.S)).max() < 1e-9
+
+
+def test_density_convention_is_conjugate_of_paper_n():
+    """rho_lm = sum f c_li conj(c_mi); the paper's n_lm = sum f conj(c_li) c_mi = conj(rho_lm)."""
+    rng = np.random.default_rng(9)
+    C = rng.normal(size=(5, 3)) + 1j * rng.normal(size=(5, 3))
+    f = np.array([2.0, 1.5, 0.25])
+    rho = O.density(C, f)
+    n_paper = np.einsum("i,li,mi->lm", f, C.conj(), C)
+    assert np.abs(rho - n_paper.conj()).max() < 1e-14
+
+
+def test_noncollinear_zero_spin_coupling_matches_two_collinear_solves():
+    """B = 0: the spinor problem splits into two collinear problems sharing one mu
+    (g = 1 each); with H_aa = H_bb, rho_aa = rho_bb = rho_col(g=2)/2."""
+    p = I.toy(seed=3, natoms=5, norb=8, n_electrons=24.0, phases=True)
+    n = p.H.shape[0]
+    HN = np.zeros((2 * n, 2 * n), np.complex128)
+    HN[:n, :n] = p.H
+    HN[n:, n:] = p.H
+    rN = O.solve(HN, p.S, p.n_electrons, p.kT, nsp=2)
+    rc = O.solve(p.H, p.S, p.n_electrons, p.kT, nsp=1)
+    assert abs(rN["mu"] - rc["mu"]) < 1e-12
+    assert np.abs(rN["rho"][:n, :n] - 0.5 * rc["rho"]).max() < 1e-10
+    assert np.abs(rN["rho"][n:, n:] - 0.5 * rc["rho"]).max() < 1e-10
+    assert np.abs(rN["rho"][:n, n:]).max() < 1e-10
+    # different diagonal blocks: union of the two collinear spectra
+    H2 = p.H + 0.05 * np.eye(n)
+    HN[n:, n:] = H2
+    rN = O.solve(HN, p.S, p.n_electrons, p.kT, nsp=2)
+    ea, _ = O.gevd(p.H, p.S)
+    eb, _ = O.gevd(H2, p.S)
+    assert np.abs(rN["eps"] - np.sort(np.concatenate([ea, eb]))).max() < 1e-11
+
+
+def test_noncollinear_global_spin_rotation():
+    """(U (x) I) H (U (x) I)^H keeps eps and rotates rho (U in SU(2))."""
+    p = I.toy(seed=4, natoms=4, norb=8, n_electrons=30.0, phases=True)
+    n = p.H.shape[0]
+    rng = np.random.default_rng(4)
+    B = I.spin_block(rng, 4, 8, 0.3, d_lo=3, d_hi=8)
+    HN = np.block([[p.H, B], [B.conj().T, p.H + 0.02 * np.eye(n)]])
+    th, ph = 0.7, 1.9
+    U = np.array([[np.cos(th), -np.exp(-1j * ph) * np.sin(th)],
+                  [np.exp(1j * ph) * np.sin(th), np.cos(th)]])
+    R = np.kron(U, np.eye(n))
+    r0 = O.solve(HN, p.S, p.n_electrons, p.kT, nsp=2)
+    r1 = O.solve(R @ HN @ R.conj().T, p.S, p.n_electrons, p.kT, nsp=2)
+    assert np.abs(r0["eps"] - r1["eps"]).max() < 1e-11
+    assert np.abs(R @ r0["rho"] @ R.conj().T - r1["rho"]).max() < 1e-10
+
+
+def test_kpoints_time_reversal_pairs():
+    """H(-k) = conj H(k) for real H_R (Bloch sums of Sec. 2) => eps(k) = eps(-k)."""
+    p = I.kpoint_batch(natoms=6, norb=4, kgrid=(4, 1, 1))
+    e = [O.gevd(p.H[k], p.S[k])[0] for k in range(4)]
+    # k index 1 and 3 are +-2pi/4L
+    assert np.abs(e[1] - e[3]).max() < 1e-12
+    assert np.abs(p.H[1] - p.H[3].conj()).max() < 1e-13
+
+
+# ---------------------------------------------------------------- adjoint
+def _fd_problem(cplx, nsp=1, seed=0):
+    rng = np.random.default_rng(seed)
+    n = 6
+    order = n * nsp
+    cp = cplx or nsp == 2
+    H = herm(rng, order, cp) * 0.5
+    S = spd(rng, n, cp) / n
+    ne = 0.45 * order * (2.0 if nsp == 1 else 1.0)
+    return H, S, ne, 0.3
+
+
+def _forward(H, S, ne, kT, nsp, W, wE):
+    r = O.solve(H, S, ne, kT, nsp=nsp)
+    return (np.sum(W * r["rho"]).real + wE * r["eband"]), r
+
+
+@pytest.mark.parametrize("cplx,nsp", [(False, 1), (True, 1), (True, 2)])
+def test_adjoint_central_differences(cplx, nsp):
+    """Central FD (h = 1e-6) of L = Re sum W_ij rho_ij + wE E_band along random
+    Hermitian directions equals Re tr(Hbar^H dH) + Re tr(Sbar^H dS)."""
+    H, S, ne, kT = _fd_problem(cplx, nsp, seed=3)
+    rng = np.random.default_rng(12)
+    order = H.shape[0]
+    W = rng.normal(size=(order, order))
+    wE = 0.7
+    _, r = _forward(H, S, ne, kT, nsp, W, wE)
+    g = r["g"]
+    Hb, Sb = O.adjoint(r["eps"], r["C"], r["mu"], kT, g, Gbar=W.astype(r["C"].dtype), ebar=wE, nsp=nsp)
+    h = 1e-6
+    for t in range(6):
+        dH = herm(rng, order, np.iscomplexobj(H))
+        dS = herm(rng, S.shape[0], np.iscomplexobj(S)) * 0.1
+        lp, _ = _forward(H + h * dH, S + h * dS, ne, kT, nsp, W, wE)
+        lm, _ = _forward(H - h * dH, S - h * dS, ne, kT, nsp, W, wE)
+        fd = (lp - lm) / (2 * h)
+        an = np.sum(Hb.conj() * dH).real + np.sum(Sb.conj() * dS).real
+        assert abs(fd - an) < 1e-6 * max(1.0, abs(fd)), (t, fd, an)
+
+
+@pytest.mark.parametrize("cplx,nsp", [(False, 1), (True, 2)])
+def test_free_energy_gradient_is_rho_and_minus_edm(cplx, nsp):
+    """Mermin free energy Omega = E_band - TS at fixed N_e: dOmega = sum f_i d eps_i,
+    so dOmega/dH = rho and dOmega/dS = -C f eps C^H (summed over spin blocks)."""
+    H, S, ne, kT = _fd_problem(cplx, nsp, seed=5)
+    r = O.solve(H, S, ne, kT, nsp=nsp)
+    rng = np.random.default_rng(13)
+    n = S.shape[0]
+    edm = O.density(r["C"], r["occ"] * r["eps"])
+    edm_s = sum(edm[b * n:(b + 1) * n, b * n:(b + 1) * n] for b in range(nsp))
+    h = 1e-6
+    for _ in range(4):
+        dH = herm(rng, H.shape[0], np.iscomplexobj(H))
+        dS = herm(rng, n, np.iscomplexobj(S)) * 0.1
+        rp = O.solve(H + h * dH, S + h * dS, ne, kT, nsp=nsp)
+        rm = O.solve(H - h * dH, S - h * dS, ne, kT, nsp=nsp)
+        fd = ((rp["eband"] - rp["ts"]) - (rm["eband"] - rm["ts"])) / (2 * h)
+        an = np.sum(r["rho"].conj() * dH).real - np.sum(edm_s.conj() * dS).real
+        assert abs(fd - an) < 1e-6 * max(1.0, abs(fd))
+
+
+def test_adjoint_shift_invariance_and_trace_loss():
+    """H -> H + c S leaves rho unchanged, so Re tr(Hbar^H S) = 0 for any Gbar;
+    L = Re tr(rho S0) with S0 = S is the electron count, so Hbar = 0."""
+    H, S, ne, kT = _fd_problem(True, 1, seed=7)
+    r = O.solve(H, S, ne, kT)
+    rng = np.random.default_rng(3)
+    G = rng.normal(size=H.shape) + 1j * rng.normal(size=H.shape)
+    Hb, Sb = O.adjoint(r["eps"], r["C"], r["mu"], kT, 2.0, Gbar=G)
+    assert abs(np.sum(Hb.conj() * S).real) < 1e-11
+    # L = Re tr(S rho) = Re sum_ij S_ji rho_ij; with dL = Re tr(Gbar^H drho),
+    # Gbar_ij = conj(S_ji) = S_ij.
+    Hb, Sb = O.adjoint(r["eps"], r["C"], r["mu"], kT, 2.0, Gbar=S.copy())
+    assert np.abs(Hb).max() < 1e-11
+
+
+def test_adjoint_one_by_one_closed_form():
+    """n = 1: rho = N_e/s, so drho/dh = 0 and drho/ds = -N_e/s^2."""
+    H = np.array([[0.3]])
+    S = np.array([[1.7]])
+    r = O.solve(H, S, 1.2, 0.1)
+    Hb, Sb = O.adjoint(r["eps"], r["C"], r["mu"], 0.1, 2.0, Gbar=np.array([[1.0]]))
+    assert abs(Hb[0, 0]) < 1e-12
+    assert abs(Sb[0, 0] - (-1.2 / 1.7 ** 2)) < 1e-12
