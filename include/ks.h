@@ -1,0 +1,186 @@
+/*
+ * ks.h -- C-ABI of the MI355X (gfx950) generalized Kohn-Sham eigensolver and
+ * density build.
+ *
+ * The library solves, per k-point, the generalized Hermitian-definite
+ * eigenproblem H C = S C eps of a numerical-atomic-orbital Hamiltonian
+ * (paper Sec. 2, the equation after the basis expansion, and its Bloch form
+ * per k-point), in the collinear form (real symmetric or complex Hermitian,
+ * order n) and in the noncollinear spinor form (complex Hermitian H of order
+ * 2n in spin blocks [[aa, ab], [ba, bb]], overlap diag(S, S) with S of order
+ * n; paper Sec. 2 end and the definitions of H_NC, C_NC, S_NC in Sec. 3.2).
+ * It then forms the Fermi-Dirac occupations, the chemical potential (one mu
+ * common to all k-points, from the electron count), the band energy and the
+ * density matrix (paper Sec. 2 density-matrix equation and its spinor form;
+ * Parts 3-4 of the collinear flow of Sec. 3.1, Parts 4-5 of Sec. 3.2).
+ *
+ * Route: Cholesky S = L L^H; A = L^-1 H L^-H (spinor form: with L applied to
+ * each spin block, i.e. (I2 (x) L)); blocked Householder tridiagonalisation
+ * A = Q T Q^H; divide-and-conquer eigensolver of T; back-transform
+ * C = L^-H Q Z.  Everything runs in HIP kernels on the device, asynchronously
+ * on the plan's stream; the host only validates arguments and enqueues.
+ *
+ * Conventions shared by all entry points
+ *   - Matrices are row-major with a row stride ("leading dimension") in
+ *     elements; complex matrices interleave (re, im) doubles exactly like
+ *     C99 double complex and torch.complex128.
+ *   - Every matrix/vector pointer is DEVICE memory owned by the caller, unless
+ *     a parameter says "host".  The library never frees caller memory.
+ *   - H and S must be Hermitian; only their LOWER triangle (diagonal included)
+ *     is read.  Outputs rho, grad_H, grad_S are written full (both triangles).
+ *   - Eigenvectors are the COLUMNS of C (C[:, i] belongs to eps[i]), eps is
+ *     ascending per k-point, and C^H S_NC C = I.
+ *   - Batches of k-points are contiguous: matrix b of H/C/rho/grad_H starts at
+ *     b * order * ld_h elements, of S/grad_S at b * n * ld_s, vectors at
+ *     b * order.
+ *   - The density convention is rho = C f C^H, i.e. rho_lm = sum_i f_i c_li
+ *     conj(c_mi); the paper's n_lm = sum_i f_i conj(c_li) c_mi equals conj(rho_lm)
+ *     (spinor blocks likewise).  Occupations include the spin factor g
+ *     (g = 2 collinear, g = 1 noncollinear), so 0 <= f <= g and
+ *     sum_k w_k tr(rho_k S_NC,k) = n_electrons.
+ *   - Argument errors are returned synchronously BEFORE any device work.
+ *     Numerical failures found on the device (non-positive pivot of S,
+ *     non-finite input, no convergence, occupied states outside the computed
+ *     window) are recorded in the plan's device info word and read back with
+ *     ks_plan_get_info; outputs are undefined after such a failure.
+ *   - A plan is used by one host thread at a time.
+ */
+#ifndef KS_H
+#define KS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KS_OK = 0,
+    KS_ERR_INVALID_ARG = 1,     /* bad pointer, size, stride, flag or range       */
+    KS_ERR_NOT_POSDEF = 2,      /* S has a non-positive pivot (info = column)     */
+    KS_ERR_NO_CONVERGENCE = 3,  /* an iterative step hit its iteration cap        */
+    KS_ERR_ELECTRON_COUNT = 4,  /* n_electrons <= 0 or above g * order            */
+    KS_ERR_WINDOW = 5,          /* occupied states outside the eigenvector window */
+    KS_ERR_NONFINITE = 6,       /* NaN or Inf in H or S                           */
+    KS_ERR_ALLOC = 7,           /* workspace does not fit in device memory        */
+    KS_ERR_HIP = 8,             /* a HIP runtime call failed                      */
+    KS_ERR_NOT_SUPPORTED = 9    /* valid but unsupported combination              */
+} ks_status;
+
+enum { KS_REAL64 = 0, KS_COMPLEX128 = 1 };           /* element type of H, S, C, rho */
+enum { KS_COLLINEAR = 0, KS_NONCOLLINEAR = 1 };      /* spin form                    */
+enum { KS_FP64 = 0, KS_MIXED = 1 };                  /* arithmetic of the solve      */
+enum { KS_PLAN_GRAPH = 1u };                         /* plan flags                   */
+enum { KS_REUSE_S = 1u };                            /* ks_gevd flags                */
+
+typedef struct ks_plan ks_plan; /* opaque: workspace, cached Cholesky factor, info */
+
+typedef struct {
+    int32_t n;          /* orbitals per spin block; order = n (collinear) or 2n   */
+    int32_t batch;      /* k-points solved together (>= 1)                         */
+    int32_t dtype;      /* KS_REAL64 or KS_COMPLEX128; noncollinear needs complex  */
+    int32_t spin;       /* KS_COLLINEAR (g = 2) or KS_NONCOLLINEAR (g = 1)         */
+    int32_t precision;  /* KS_FP64 (KS_MIXED is reserved)                          */
+    int32_t ld_h;       /* row stride of H, C, rho, grad_H; >= order               */
+    int32_t ld_s;       /* row stride of S, grad_S; >= n                           */
+    void*   stream;     /* hipStream_t every call is enqueued on (NULL = default)  */
+    uint32_t flags;     /* plan flags                                              */
+} ks_plan_desc;
+
+/* Validate the descriptor, size the workspace for it and allocate it on the
+ * current device.  KS_ERR_INVALID_ARG for a bad descriptor (no allocation is
+ * attempted), KS_ERR_NOT_SUPPORTED for a valid but unsupported one,
+ * KS_ERR_ALLOC if the workspace does not fit.  On success *out owns the
+ * workspace until ks_plan_destroy. */
+ks_status ks_plan_create(const ks_plan_desc* desc, ks_plan** out);
+
+/* Free the plan's workspace (synchronizes its stream first).  NULL is a no-op. */
+void ks_plan_destroy(ks_plan* plan);
+
+/* Generalized eigen-decomposition of every k-point (paper Sec. 2, H C = S C eps;
+ * Sec. 3.2 for the spinor form).
+ *   H    [batch][order][ld_h]  lower triangle read
+ *   S    [batch][n][ld_s]      lower triangle read; ignored when flags has
+ *                              KS_REUSE_S and a previous call factored it
+ *   eps  [batch][order]        all eigenvalues, ascending
+ *   C    [batch][order][ld_h]  columns 0 .. iu-il hold eigenvectors il .. iu
+ *   il, iu  1-based inclusive eigenvector range, 1 <= il <= iu <= order
+ *   flags   KS_REUSE_S: S is unchanged since the last call on this plan, reuse
+ *           its cached Cholesky factor (the self-consistent cycle after the
+ *           first, paper Sec. 5, cycles 2 onwards reuse the overlap work).
+ * Device failures: KS_ERR_NOT_POSDEF (info = failing column, 1-based),
+ * KS_ERR_NONFINITE, KS_ERR_NO_CONVERGENCE via ks_plan_get_info. */
+ks_status ks_gevd(ks_plan* plan, const void* H, const void* S, double* eps, void* C,
+                  int32_t il, int32_t iu, uint32_t flags);
+
+/* Occupations, chemical potential, band energy and density matrix (paper Sec. 2
+ * density-matrix equation; Part 3 and Part 4 of Sec. 3.1).
+ *   eps       [batch][order] eigenvalues from ks_gevd
+ *   C         [batch][order][ld_h], columns 0 .. iu-il = eigenvectors il .. iu
+ *   n_electrons  total electron count per cell, 0 < n_electrons <= g*order
+ *   kT        Fermi-Dirac temperature (Ha), > 0;  f = g / (1 + exp((eps-mu)/kT))
+ *   kweights  HOST array [batch] of k weights (sum 1), NULL = uniform 1/batch
+ *   rho       [batch][order][ld_h] output, rho_k = C_k f_k C_k^H
+ *   mu, eband DEVICE scalars: the common chemical potential (bisection on the
+ *             weighted electron count) and sum_k w_k sum_i f_ik eps_ik
+ *   occ       DEVICE [batch][order] occupations f_ik, or NULL
+ * Device failure KS_ERR_WINDOW if some f_ik > g*1e-15 lies outside [il, iu]. */
+ks_status ks_density(ks_plan* plan, const double* eps, const void* C, int32_t il, int32_t iu,
+                     double n_electrons, double kT, const double* kweights, void* rho,
+                     double* mu, double* eband, double* occ);
+
+/* Adjoint of (rho, E_band) with respect to (H, S): given dL/drho (grad_rho,
+ * full, may be NULL for zero) and dL/dE_band (grad_eband, DEVICE scalar or
+ * NULL for zero), writes grad_H [batch][order][ld_h] and grad_S [batch][n][ld_s]
+ * such that dL = sum_k Re tr(grad_H^H dH) + Re tr(grad_S^H dS).  Needs ALL
+ * eigenvectors (C from ks_gevd with il = 1, iu = order) and mu, occ from
+ * ks_density; it keeps no state from the forward calls.  Spinor form: grad_S
+ * is the sum of the two diagonal spin blocks of the gradient of diag(S, S). */
+ks_status ks_density_backward(ks_plan* plan, const double* eps, const void* C, const double* mu,
+                              const double* occ, double kT, const void* grad_rho,
+                              const double* grad_eband, void* grad_H, void* grad_S);
+
+/* Per-part timing, the analogue of the paper's per-Part GPU time tables (Sec. 5,
+ * e.g. the breakdown of Parts 2-1 .. 4 per SCF cycle).  With profiling enabled the
+ * plan records HIP events on its stream around each phase below and around every
+ * `stride`-th launch of the tridiagonalisation's trailing matrix-vector kernel
+ * (the bandwidth-bound half of the eigensolver, Sec. 6).  Profiling adds a few
+ * event records per phase; keep it off for plain timing. */
+enum {
+    KS_PHASE_CHOLESKY = 0, KS_PHASE_REDUCE = 1, KS_PHASE_TRIDIAG = 2, KS_PHASE_DC = 3,
+    KS_PHASE_BACKTR = 4, KS_PHASE_DENSITY = 5, KS_PHASE_ADJOINT = 6, KS_NPHASE = 7
+};
+typedef struct {
+    double phase_ms[8];       /* summed over the calls since the last read          */
+    int64_t phase_calls[8];
+    double hemv_ms;           /* summed duration of the sampled kernel launches     */
+    int64_t hemv_launches;    /* sampled launches                                   */
+    double hemv_bytes;        /* their algorithmic bytes: the lower triangle of the  */
+                              /* trailing matrix, read once per launch              */
+} ks_profile;
+
+/* enable != 0 turns recording on (stride >= 1), 0 turns it off.  Host-only. */
+ks_status ks_plan_set_profiling(ks_plan* plan, int32_t enable, int32_t stride);
+
+/* Synchronize the plan's stream, fill *out with what was recorded since the last
+ * read, and clear it. */
+ks_status ks_plan_get_profile(ks_plan* plan, ks_profile* out);
+
+/* Synchronize the plan's stream and read its info word: 0 if no device failure
+ * was recorded since the last call, else the failing Cholesky column (>0) for
+ * KS_ERR_NOT_POSDEF, or -status for other device failures.  Clears the word.
+ * Returns KS_OK or the status of the recorded failure. */
+ks_status ks_plan_get_info(ks_plan* plan, int32_t* info);
+
+/* Static, never NULL. */
+const char* ks_status_string(ks_status s);
+
+/* Bytes of device workspace ks_plan_create would allocate for desc
+ * (0 if desc is invalid).  Host-only, no device call. */
+uint64_t ks_plan_workspace_bytes(const ks_plan_desc* desc);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KS_H */

@@ -1,0 +1,49 @@
+/*
+ * ks_testing.h -- test hooks of libks.so.  They expose single stages of the
+ * solve (the matrix-core GEMM, the Cholesky factorisation, the tridiagonal
+ * divide-and-conquer eigensolver and the raw layout of one MFMA instruction)
+ * so that the GPU tests can check each stage against the oracle in isolation.
+ * Same conventions as ks.h: row-major, device pointers owned by the caller,
+ * synchronous on the given stream (the hooks synchronize before returning).
+ * They return a ks_status value (0 on success).
+ */
+#ifndef KS_TESTING_H
+#define KS_TESTING_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* C = alpha op(A) op(B) + beta C; dtype 0 real / 1 complex; op 0 = N, 1 = T,
+ * 2 = conjugate transpose; lower != 0 writes only the lower triangle of C. */
+int32_t ks_test_gemm(int32_t dtype, int32_t opa, int32_t opb, int32_t m, int32_t n, int32_t k,
+                     double alpha, const void* A, int32_t lda, const void* B, int32_t ldb, double beta,
+                     void* C, int32_t ldc, int32_t lower, void* stream);
+
+/* In-place Cholesky of the n x n lower triangle of A (upper left untouched);
+ * *info = failing 1-based column or 0. */
+int32_t ks_test_potrf(int32_t dtype, int32_t n, void* A, int32_t lda, int32_t* info, void* stream);
+
+/* Eigen-decomposition of the symmetric tridiagonal (d[n], e[n-1]) by divide
+ * and conquer: lam[n] ascending, Z[n][n] eigenvectors as columns. */
+int32_t ks_test_stedc(int32_t n, const double* d, const double* e, double* lam, double* Z,
+                      int32_t* info, void* stream);
+
+/* Householder tridiagonalisation of the n x n Hermitian matrix A (full storage,
+ * overwritten): d[n], e[n-1] of T with A = Q T Q^H, then Q X for the n x ncols
+ * real matrix X (row stride n) into Y (dtype, row stride ncols). */
+int32_t ks_test_hetrd(int32_t dtype, int32_t n, void* A, double* d, double* e, const double* X,
+                      int32_t ncols, void* Y, void* stream);
+
+/* One v_mfma_f64_16x16x4_f64 where lane l feeds A[l%16][l/16] and B[l/16][l%16]
+ * with A[i][0] = 100 i, A[i][1] = 1, B[0][j] = 1, B[1][j] = j (other k zero), so
+ * D[i][j] = 100 i + j; out[lane * 4 + r] = accumulator register r of each lane. */
+int32_t ks_test_mfma_layout(double* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KS_TESTING_H */

@@ -55,6 +55,8 @@ static void set_threads(int nthreads) {
 #endif
 }
 
+void ko_set_threads(int nthreads) { set_threads(nthreads); }
+
 int ko_max_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();

@@ -43,6 +43,7 @@ def build(force: bool = False) -> str:
 
 
 _lib = None
+_lib_threads = [1]
 
 
 def lib():
@@ -55,6 +56,9 @@ def lib():
         I = ctypes.c_int
         D = ctypes.c_double
         L.ko_max_threads.restype = I
+        L.ko_set_threads.argtypes = [I]
+        L.ko_set_threads.restype = None
+        _lib_threads[0] = L.ko_max_threads()
         L.ko_cholesky.argtypes = [I, I, P, I, P]
         L.ko_cholesky.restype = I
         L.ko_solve_lower.argtypes = [I, I, I, P, P, I]
@@ -88,6 +92,18 @@ def _ptr(a):
 
 def _dt(a):
     return np.complex128 if np.iscomplexobj(a) else np.float64
+
+
+def _threads(nthreads, order):
+    """Threads for a call: 1 for small orders (OpenMP start-up dominates there)."""
+    if nthreads and nthreads > 0:
+        return int(nthreads)
+    return 1 if order <= 256 else 0
+
+
+def _set(nthreads, order):
+    t = _threads(nthreads, order)
+    lib().ko_set_threads(t if t > 0 else _lib_threads[0])
 
 
 def max_threads() -> int:
@@ -135,7 +151,8 @@ def jacobi(A, maxsweeps=50, nthreads=0):
     n = A.shape[0]
     w = np.zeros(n)
     V = np.zeros((n, n), dt)
-    sw = lib().ko_jacobi(n, int(dt == np.complex128), _ptr(A), _ptr(w), _ptr(V), maxsweeps, nthreads)
+    sw = lib().ko_jacobi(n, int(dt == np.complex128), _ptr(A), _ptr(w), _ptr(V), maxsweeps,
+                         _threads(nthreads, n))
     if sw < 0:
         raise OracleError("Jacobi did not converge in %d sweeps" % maxsweeps)
     return w, V, sw
@@ -154,6 +171,7 @@ def gevd(H, S, nsp=1, nthreads=0, route="cholesky"):
     eps = np.zeros(order)
     C = np.zeros((order, order), dt)
     cp = int(dt == np.complex128)
+    nthreads = _threads(nthreads, order)
     if route == "cholesky":
         sw = ctypes.c_int(0)
         info = lib().ko_gevd(n, nsp, cp, _ptr(H), order, _ptr(S), n, _ptr(eps), _ptr(C), nthreads,
@@ -197,6 +215,7 @@ def density(C, w):
     order, ncols = C.shape
     assert w.shape == (ncols,)
     rho = np.zeros((order, order), dt)
+    _set(0, order)
     lib().ko_density(order, ncols, int(dt == np.complex128), _ptr(C), ncols, _ptr(w), _ptr(rho))
     return rho
 
@@ -217,6 +236,7 @@ def adjoint(eps, C, mu, kT, g, Gbar=None, ebar=0.0, nsp=1, wk=None):
     G = None if Gbar is None else _c(Gbar, dt).reshape(nk, order, order)
     Hb = np.zeros((nk, order, order), dt)
     Sb = np.zeros((nk, n, n), dt)
+    _set(0, order)
     lib().ko_adjoint(n, nsp, int(dt == np.complex128), nk, _ptr(e), _ptr(Cc), float(mu), float(kT),
                      float(g), _ptr(w), None if G is None else _ptr(G), float(ebar), _ptr(Hb), _ptr(Sb))
     if single:

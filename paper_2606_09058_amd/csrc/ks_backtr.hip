@@ -1,0 +1,167 @@
+// ks_backtr.hip -- back-transform of the tridiagonal eigenvectors,
+// C = (I (x) L)^-H Q Z (Part 2-5 / Part 3-6 of the paper's flows, with the
+// Cholesky factor in place of the Loewdin V), and the density build with
+// Fermi-Dirac occupations (Parts 3-4 of Sec. 3.1, Parts 4-5 of Sec. 3.2).
+//
+// Q = H_0 H_1 ... H_{n-2} is applied in blocks of BT reflectors in compact-WY
+// form, H_b ... H_{b+BT-1} = I - V T V^H (T upper triangular, built from
+// G = V^H V and tau), so each block is three MFMA GEMMs:
+// W1 = V^H X, W2 = T W1, X -= V W2.
+#include "ks_internal.hpp"
+
+namespace ks {
+
+// X (n x ncols, ld ldx, type T) = Z[:, c0 : c0 + ncols] (real).
+template <typename T>
+__global__ void load_z_kernel(int n, int ncols, const double* Z, int c0, T* X, int ldx) {
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)n * ncols) return;
+    int r = (int)(e / ncols), c = (int)(e % ncols);
+    X[(long)r * ldx + c] = from_re<T>(Z[(long)r * n + c0 + c]);
+}
+
+// T factor of one block: T_jj = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j].
+template <typename T>
+__global__ __launch_bounds__(256) void tfactor_kernel(int jb, const T* tau, const T* G, T* Tm) {
+    int t = threadIdx.x;
+    for (int e = t; e < jb * jb; e += blockDim.x) Tm[e] = zero_<T>();
+    __syncthreads();
+    for (int j = 0; j < jb; ++j) {
+        T tj = tau[j];
+        T acc = zero_<T>();
+        if (t < j) {
+            for (int l = t; l < j; ++l) acc += Tm[(long)t * jb + l] * G[(long)l * jb + j];
+        }
+        __syncthreads();
+        if (t < j) Tm[(long)t * jb + j] = -(tj * acc);
+        if (t == 0) Tm[(long)j * jb + j] = tj;
+        __syncthreads();
+    }
+}
+
+template <typename T>
+void backtransform_q(hipStream_t s, int n, const T* Vall, const T* tau, int ncols, T* X, int ldx,
+                     BacktrWork<T>& w) {
+    const int bt = BACKTR_BT;
+    int nref = n - 1;
+    if (nref <= 0 || ncols <= 0) return;
+    int nblk = cdiv(nref, bt);
+    for (int b = nblk - 1; b >= 0; --b) {
+        int b0 = b * bt;
+        int jb = min(bt, nref - b0);
+        int m = n - b0 - 1;
+        const T* Vb = Vall + (long)(b0 + 1) * n + b0;
+        T* Xb = X + (long)(b0 + 1) * ldx;
+        gemm<T>(s, OP_C, OP_N, jb, jb, m, 1.0, Vb, n, 0, Vb, n, 0, 0.0, w.G, jb, 0, 1);
+        hipLaunchKernelGGL((tfactor_kernel<T>), dim3(1), dim3(256), 0, s, jb, tau + b0, w.G, w.Tf);
+        gemm<T>(s, OP_C, OP_N, jb, ncols, m, 1.0, Vb, n, 0, Xb, ldx, 0, 0.0, w.W1, ncols, 0, 1);
+        gemm<T>(s, OP_N, OP_N, jb, ncols, jb, 1.0, w.Tf, jb, 0, w.W1, ncols, 0, 0.0, w.W2, ncols, 0, 1);
+        gemm<T>(s, OP_N, OP_N, m, ncols, jb, -1.0, Vb, n, 0, w.W2, ncols, 0, 1.0, Xb, ldx, 0, 1);
+    }
+}
+
+template <typename T>
+void load_z(hipStream_t s, int n, int ncols, const double* Z, int c0, T* X, int ldx) {
+    long tot = (long)n * ncols;
+    hipLaunchKernelGGL((load_z_kernel<T>), dim3(cdiv(tot, 256)), dim3(256), 0, s, n, ncols, Z, c0, X, ldx);
+}
+
+// ---------------------------------------------------------------- Fermi level
+__device__ inline double fermi_F(double x) {
+    if (x > 0.0) {
+        double e = exp(-x);
+        return e / (1.0 + e);
+    }
+    return 1.0 / (1.0 + exp(x));
+}
+
+// One workgroup: mu by bisection on sum_k w_k sum_i g F((eps_ik - mu)/kT) = ne over
+// [min eps - 50 kT, max eps + 50 kT] until hi - lo <= 1e-14 max(1, |mu|) (at most
+// 200 halvings), mu = midpoint; then occ, E_band and the window check.
+__global__ __launch_bounds__(1024) void fermi_kernel(int batch, int order, const double* eps,
+                                                     KWeights kw, double g, double ne, double kT,
+                                                     int il, int iu, double* occ, double* mu_out,
+                                                     double* eband_out, int* kwin, int* info) {
+    __shared__ double red[16];
+    __shared__ int lastw[16];
+    int t = threadIdx.x;
+    long tot = (long)batch * order;
+    double mn = INFINITY, mx = -INFINITY;
+    for (long i = t; i < tot; i += blockDim.x) {
+        mn = fmin(mn, eps[i]);
+        mx = fmax(mx, eps[i]);
+    }
+    mn = wave_min(mn);
+    mx = wave_max(mx);
+    __shared__ double smn[16], smx[16];
+    if ((t & 63) == 0) {
+        smn[t >> 6] = mn;
+        smx[t >> 6] = mx;
+    }
+    __syncthreads();
+    double lo = INFINITY, hi = -INFINITY;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+        lo = fmin(lo, smn[i]);
+        hi = fmax(hi, smx[i]);
+    }
+    lo -= 50.0 * kT;
+    hi += 50.0 * kT;
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (hi - lo <= 1e-14 * fmax(1.0, fabs(mid))) break;
+        double cnt = 0.0;
+        for (int b = 0; b < batch; ++b) {
+            double sb = 0.0;
+            for (int i = t; i < order; i += blockDim.x) sb += fermi_F((eps[(long)b * order + i] - mid) / kT);
+            cnt += kw.w[b] * g * sb;
+        }
+        cnt = block_sum(cnt, red);
+        if (cnt < ne) lo = mid;
+        else hi = mid;
+    }
+    double mu = 0.5 * (lo + hi);
+    double eb = 0.0;
+    int last = -1;  // last window column (0-based within [il-1, iu-1]) with f > g 1e-15
+    for (int b = 0; b < batch; ++b) {
+        double sb = 0.0;
+        for (int i = t; i < order; i += blockDim.x) {
+            double ei = eps[(long)b * order + i];
+            double f = g * fermi_F((ei - mu) / kT);
+            occ[(long)b * order + i] = f;
+            sb += f * ei;
+            bool occd = f > g * 1e-15;
+            if ((i < il - 1 || i > iu - 1) && occd) set_info(info, KS_ERR_WINDOW, i + 1);
+            if (occd && i >= il - 1 && i <= iu - 1) last = max(last, i - (il - 1));
+        }
+        eb += kw.w[b] * sb;
+    }
+    eb = block_sum(eb, red);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) last = max(last, __shfl_xor(last, o, 64));
+    if ((t & 63) == 0) lastw[t >> 6] = last;
+    __syncthreads();
+    if (t == 0) {
+        int lw = -1;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) lw = max(lw, lastw[i]);
+        *kwin = lw + 1;
+        *mu_out = mu;
+        *eband_out = eb;
+    }
+}
+
+void fermi(hipStream_t s, int batch, int order, const double* eps, const KWeights& kw, double g,
+           double ne, double kT, int il, int iu, double* occ, double* mu, double* eband, int* kwin,
+           int* info) {
+    hipLaunchKernelGGL(fermi_kernel, dim3(1), dim3(1024), 0, s, batch, order, eps, kw, g, ne, kT, il, iu,
+                       occ, mu, eband, kwin, info);
+}
+
+#define KS_INST(T)                                                                                 \
+    template void backtransform_q<T>(hipStream_t, int, const T*, const T*, int, T*, int,           \
+                                     BacktrWork<T>&);                                             \
+    template void load_z<T>(hipStream_t, int, int, const double*, int, T*, int);
+KS_INST(double)
+KS_INST(cplx)
+#undef KS_INST
+
+}  // namespace ks

@@ -1,0 +1,129 @@
+// ks_common.hpp -- element types, small device helpers and the internal
+// launch interface shared by the gfx950 kernels of the eigensolver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <math.h>
+
+#include "../../include/ks.h"
+
+namespace ks {
+
+// ---------------------------------------------------------------- complex
+struct cplx {
+    double x, y;  // re, im (layout of double complex / torch.complex128)
+};
+
+__host__ __device__ inline cplx mk(double r, double i) { cplx c; c.x = r; c.y = i; return c; }
+__host__ __device__ inline cplx operator+(cplx a, cplx b) { return mk(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline cplx operator-(cplx a, cplx b) { return mk(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline cplx operator-(cplx a) { return mk(-a.x, -a.y); }
+__host__ __device__ inline cplx operator*(cplx a, cplx b) {
+    return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline cplx operator*(double s, cplx a) { return mk(s * a.x, s * a.y); }
+__host__ __device__ inline cplx operator*(cplx a, double s) { return mk(s * a.x, s * a.y); }
+__host__ __device__ inline cplx& operator+=(cplx& a, cplx b) { a.x += b.x; a.y += b.y; return a; }
+__host__ __device__ inline cplx& operator-=(cplx& a, cplx b) { a.x -= b.x; a.y -= b.y; return a; }
+
+// Uniform helpers over double and cplx.
+__host__ __device__ inline double conj_(double a) { return a; }
+__host__ __device__ inline cplx conj_(cplx a) { return mk(a.x, -a.y); }
+__host__ __device__ inline double re_(double a) { return a; }
+__host__ __device__ inline double re_(cplx a) { return a.x; }
+__host__ __device__ inline double im_(double) { return 0.0; }
+__host__ __device__ inline double im_(cplx a) { return a.y; }
+__host__ __device__ inline double abs2_(double a) { return a * a; }
+__host__ __device__ inline double abs2_(cplx a) { return a.x * a.x + a.y * a.y; }
+template <typename T> __host__ __device__ inline T zero_();
+template <> __host__ __device__ inline double zero_<double>() { return 0.0; }
+template <> __host__ __device__ inline cplx zero_<cplx>() { return mk(0.0, 0.0); }
+template <typename T> __host__ __device__ inline T from_re(double r);
+template <> __host__ __device__ inline double from_re<double>(double r) { return r; }
+template <> __host__ __device__ inline cplx from_re<cplx>(double r) { return mk(r, 0.0); }
+__host__ __device__ inline bool finite_(double a) { return isfinite(a); }
+__host__ __device__ inline bool finite_(cplx a) { return isfinite(a.x) && isfinite(a.y); }
+// 1/a for complex a (Smith's algorithm not needed at these magnitudes).
+__host__ __device__ inline cplx inv_(cplx a) {
+    double d = a.x * a.x + a.y * a.y;
+    return mk(a.x / d, -a.y / d);
+}
+__host__ __device__ inline double inv_(double a) { return 1.0 / a; }
+
+template <typename T> struct is_cplx { static constexpr bool value = false; };
+template <> struct is_cplx<cplx> { static constexpr bool value = true; };
+
+// ---------------------------------------------------------------- wavefront
+constexpr int WAVE = 64;
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+__device__ inline cplx wave_sum(cplx v) { return mk(wave_sum(v.x), wave_sum(v.y)); }
+__device__ inline double wave_prod(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v *= __shfl_xor(v, o, WAVE);
+    return v;
+}
+__device__ inline double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
+    return v;
+}
+__device__ inline double wave_min(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, WAVE));
+    return v;
+}
+
+// Deterministic block-wide sum of one double (fixed tree order).  `scratch`
+// must hold blockDim.x/64 doubles; all threads receive the result.
+__device__ inline double block_sum(double v, double* scratch) {
+    v = wave_sum(v);
+    int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE, nw = blockDim.x / WAVE;
+    __syncthreads();
+    if (l == 0) scratch[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < nw; ++i) t += scratch[i];
+    __syncthreads();
+    return t;
+}
+
+// Record a device failure in the plan's info word: the first one wins.
+// info layout: info[0] = status code, info[1] = detail (e.g. failing column).
+__device__ inline void set_info(int* info, int code, int detail) {
+    if (atomicCAS(info, 0, code) == 0) info[1] = detail;
+}
+
+// ---------------------------------------------------------------- host side
+#define KS_HIP(x)                                   \
+    do {                                            \
+        hipError_t e_ = (x);                        \
+        if (e_ != hipSuccess) return KS_ERR_HIP;    \
+    } while (0)
+
+inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+enum Op { OP_N = 0, OP_T = 1, OP_C = 2 };
+enum Uplo { UPLO_FULL = 0, UPLO_LOWER = 1 };
+
+// C = alpha op(A) op(B) (diag kscale between them if given) + beta C,
+// row-major, for `batch` problems with element strides sa, sb, sc.
+template <typename T>
+void gemm(hipStream_t s, Op opa, Op opb, int m, int n, int k, double alpha, const T* A, int lda,
+          long sa, const T* B, int ldb, long sb, double beta, T* C, int ldc, long sc, int batch = 1,
+          const double* kscale = nullptr, long sk = 0, Uplo uplo = UPLO_FULL,
+          const int* kdev = nullptr);
+
+// Grouped real GEMM for the divide-and-conquer merges: group g multiplies the
+// (rows_g x kk_g) block of A at (lo_g, lo_g) by the (kk_g x kk_g) block of B at
+// (lo_g, lo_g) into C at (lo_g, lo_g); all with row stride ld.  rows_g = hi_g -
+// lo_g comes from the host bounds, kk_g from device memory (deflation count).
+void gemm_grouped_dc(hipStream_t s, int ngroups, int max_rows, const int* d_lo, const int* d_hi,
+                     const int* d_kk, const double* A, const double* B, double* C, int ld);
+
+}  // namespace ks

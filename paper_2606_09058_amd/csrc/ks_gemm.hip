@@ -1,0 +1,287 @@
+// ks_gemm.hip -- FP64 matrix-core (MFMA) GEMM for gfx950, real and complex.
+//
+// Every dense contraction of the eigensolver goes through this kernel: the
+// Cholesky trailing update, the triangular-solve updates of the reduction
+// L^-1 H L^-H, the two-sided rank-2k trailing update of the Householder
+// tridiagonalisation, the divide-and-conquer merge products, the compact-WY
+// back-transform and the density C f C^H.
+//
+// Tile: 64 x 64 outputs per 256-thread workgroup, K step 16, staged through
+// LDS with a register prefetch of the next K step.  Each of the 4 waves owns
+// a 32 x 32 quadrant = 2 x 2 blocks of v_mfma_f64_16x16x4_f64.  Lane l of an
+// MFMA supplies A[l%16][l/16] and B[l/16][l%16] of the 16x4 / 4x16 operands
+// and receives D[l/16 + 4r][l%16] in accumulator register r.  A complex
+// product uses four real MFMAs (re*re - im*im, re*im + im*re) into separate
+// real and imaginary accumulators.
+#include "ks_common.hpp"
+
+namespace ks {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 64, BN = 64, BK = 16, LPAD = 2;
+
+__device__ inline d4 mfma(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <typename T, int OP>
+__device__ inline T ld_op(const T* p) {
+    T v = *p;
+    if constexpr (OP == OP_C) v = conj_(v);
+    return v;
+}
+
+// Load the BM x BK tile of op(A) starting at (m0, k0) into registers.
+// Mapping A: element (m, k) of op(A) is A[m*lda + k] for OP_N, A[k*lda + m]
+// otherwise.  The four elements a thread loads are contiguous in memory.
+template <typename T, int OPA>
+__device__ inline void load_a(T (&r)[4], const T* A, int lda, int m, int K, int m0, int k0,
+                              const double* ks) {
+    int t = threadIdx.x;
+    if constexpr (OPA == OP_N) {
+        int mm = m0 + (t >> 2), kk = k0 + (t & 3) * 4;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            bool ok = mm < m && kk + i < K;
+            r[i] = ok ? ld_op<T, OPA>(A + (long)mm * lda + kk + i) : zero_<T>();
+            if (ks && ok) r[i] = r[i] * ks[kk + i];
+        }
+    } else {
+        int kk = k0 + (t >> 4), mm = m0 + (t & 15) * 4;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            bool ok = mm + i < m && kk < K;
+            r[i] = ok ? ld_op<T, OPA>(A + (long)kk * lda + mm + i) : zero_<T>();
+            if (ks && ok) r[i] = r[i] * ks[kk];
+        }
+    }
+}
+
+template <typename T, int OPA>
+__device__ inline void store_a(const T (&r)[4], T (*sA)[BM + LPAD]) {
+    int t = threadIdx.x;
+    if constexpr (OPA == OP_N) {
+        int mm = t >> 2, kk = (t & 3) * 4;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sA[kk + i][mm] = r[i];
+    } else {
+        int kk = t >> 4, mm = (t & 15) * 4;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sA[kk][mm + i] = r[i];
+    }
+}
+
+// op(B) is K x N: element (k, n) is B[k*ldb + n] for OP_N, B[n*ldb + k] otherwise.
+template <typename T, int OPB>
+__device__ inline void load_b(T (&r)[4], const T* B, int ldb, int n, int K, int n0, int k0) {
+    int t = threadIdx.x;
+    if constexpr (OPB == OP_N) {
+        int kk = k0 + (t >> 4), nn = n0 + (t & 15) * 4;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            bool ok = nn + i < n && kk < K;
+            r[i] = ok ? B[(long)kk * ldb + nn + i] : zero_<T>();
+        }
+    } else {
+        int nn = n0 + (t >> 2), kk = k0 + (t & 3) * 4;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            bool ok = nn < n && kk + i < K;
+            r[i] = ok ? ld_op<T, OPB>(B + (long)nn * ldb + kk + i) : zero_<T>();
+        }
+    }
+}
+
+template <typename T, int OPB>
+__device__ inline void store_b(const T (&r)[4], T (*sB)[BN + LPAD]) {
+    int t = threadIdx.x;
+    if constexpr (OPB == OP_N) {
+        int kk = t >> 4, nn = (t & 15) * 4;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sB[kk][nn + i] = r[i];
+    } else {
+        int nn = t >> 2, kk = (t & 3) * 4;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sB[kk + i][nn] = r[i];
+    }
+}
+
+template <typename T>
+struct Acc;
+template <>
+struct Acc<double> {
+    d4 c[2][2];
+};
+template <>
+struct Acc<cplx> {
+    d4 re[2][2], im[2][2];
+};
+
+__device__ inline void acc_zero(Acc<double>& a) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) a.c[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+}
+__device__ inline void acc_zero(Acc<cplx>& a) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            a.re[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+            a.im[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+        }
+}
+
+__device__ inline void tile_mma(Acc<double>& acc, double (*sA)[BM + LPAD], double (*sB)[BN + LPAD]) {
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
+    int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+        int kr = ks * 4 + lk;
+        double a0 = sA[kr][wm * 32 + li], a1 = sA[kr][wm * 32 + 16 + li];
+        double b0 = sB[kr][wn * 32 + li], b1 = sB[kr][wn * 32 + 16 + li];
+        acc.c[0][0] = mfma(a0, b0, acc.c[0][0]);
+        acc.c[0][1] = mfma(a0, b1, acc.c[0][1]);
+        acc.c[1][0] = mfma(a1, b0, acc.c[1][0]);
+        acc.c[1][1] = mfma(a1, b1, acc.c[1][1]);
+    }
+}
+
+__device__ inline void tile_mma(Acc<cplx>& acc, cplx (*sA)[BM + LPAD], cplx (*sB)[BN + LPAD]) {
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
+    int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+        int kr = ks * 4 + lk;
+        cplx a[2] = {sA[kr][wm * 32 + li], sA[kr][wm * 32 + 16 + li]};
+        cplx b[2] = {sB[kr][wn * 32 + li], sB[kr][wn * 32 + 16 + li]};
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                acc.re[i][j] = mfma(a[i].x, b[j].x, acc.re[i][j]);
+                acc.re[i][j] = mfma(-a[i].y, b[j].y, acc.re[i][j]);
+                acc.im[i][j] = mfma(a[i].x, b[j].y, acc.im[i][j]);
+                acc.im[i][j] = mfma(a[i].y, b[j].x, acc.im[i][j]);
+            }
+    }
+}
+
+__device__ inline double acc_get(const Acc<double>& a, int i, int j, int r) { return a.c[i][j][r]; }
+__device__ inline cplx acc_get(const Acc<cplx>& a, int i, int j, int r) {
+    return mk(a.re[i][j][r], a.im[i][j][r]);
+}
+
+// One 64 x 64 output tile at (m0, n0).
+template <typename T, int OPA, int OPB>
+__device__ inline void gemm_tile(int m, int n, int K, double alpha, const T* A, int lda, const T* B,
+                                 int ldb, double beta, T* C, int ldc, const double* kscale, int uplo,
+                                 int m0, int n0) {
+    __shared__ T sA[BK][BM + LPAD];
+    __shared__ T sB[BK][BN + LPAD];
+    Acc<T> acc;
+    acc_zero(acc);
+    T ra[4], rb[4];
+    if (K > 0) {
+        load_a<T, OPA>(ra, A, lda, m, K, m0, 0, kscale);
+        load_b<T, OPB>(rb, B, ldb, n, K, n0, 0);
+    }
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        __syncthreads();
+        store_a<T, OPA>(ra, sA);
+        store_b<T, OPB>(rb, sB);
+        __syncthreads();
+        if (k0 + BK < K) {
+            load_a<T, OPA>(ra, A, lda, m, K, m0, k0 + BK, kscale);
+            load_b<T, OPB>(rb, B, ldb, n, K, n0, k0 + BK);
+        }
+        tile_mma(acc, sA, sB);
+    }
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                int row = m0 + wm * 32 + i * 16 + (lane >> 4) + 4 * r;
+                int col = n0 + wn * 32 + j * 16 + (lane & 15);
+                if (row < m && col < n && (uplo == UPLO_FULL || col <= row)) {
+                    T v = alpha * acc_get(acc, i, j, r);
+                    T* pc = C + (long)row * ldc + col;
+                    if (beta != 0.0) v += beta * (*pc);
+                    *pc = v;
+                }
+            }
+}
+
+template <typename T, int OPA, int OPB>
+__global__ __launch_bounds__(256) void gemm_kernel(int m, int n, int K, double alpha, const T* A,
+                                                   int lda, long sa, const T* B, int ldb, long sb,
+                                                   double beta, T* C, int ldc, long sc,
+                                                   const double* kscale, long sk, int uplo,
+                                                   const int* kdev) {
+    int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    if (uplo == UPLO_LOWER && m0 + BM - 1 < n0) return;  // tile strictly above the diagonal
+    long b = blockIdx.z;
+    if (kdev) K = min(K, *kdev);  // inner size decided on the device (occupied window)
+    gemm_tile<T, OPA, OPB>(m, n, K, alpha, A + b * sa, lda, B + b * sb, ldb, beta, C + b * sc, ldc,
+                           kscale ? kscale + b * sk : nullptr, uplo, m0, n0);
+}
+
+template <typename T, int OPA, int OPB>
+static void launch(hipStream_t s, int m, int n, int k, double alpha, const T* A, int lda, long sa,
+                   const T* B, int ldb, long sb, double beta, T* C, int ldc, long sc, int batch,
+                   const double* kscale, long sk, Uplo uplo, const int* kdev) {
+    dim3 grid(cdiv(n, BN), cdiv(m, BM), batch);
+    hipLaunchKernelGGL((gemm_kernel<T, OPA, OPB>), grid, dim3(256), 0, s, m, n, k, alpha, A, lda, sa,
+                       B, ldb, sb, beta, C, ldc, sc, kscale, sk, (int)uplo, kdev);
+}
+
+template <typename T>
+void gemm(hipStream_t s, Op opa, Op opb, int m, int n, int k, double alpha, const T* A, int lda,
+          long sa, const T* B, int ldb, long sb, double beta, T* C, int ldc, long sc, int batch,
+          const double* kscale, long sk, Uplo uplo, const int* kdev) {
+    if (m <= 0 || n <= 0 || batch <= 0) return;
+#define KS_GEMM_CASE(OA, OB)                                                                      \
+    if (opa == OA && opb == OB)                                                                   \
+        return launch<T, OA, OB>(s, m, n, k, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, batch, \
+                                 kscale, sk, uplo, kdev);
+    KS_GEMM_CASE(OP_N, OP_N)
+    KS_GEMM_CASE(OP_N, OP_T)
+    KS_GEMM_CASE(OP_N, OP_C)
+    KS_GEMM_CASE(OP_T, OP_N)
+    KS_GEMM_CASE(OP_C, OP_N)
+#undef KS_GEMM_CASE
+}
+
+template void gemm<double>(hipStream_t, Op, Op, int, int, int, double, const double*, int, long,
+                           const double*, int, long, double, double*, int, long, int, const double*,
+                           long, Uplo, const int*);
+template void gemm<cplx>(hipStream_t, Op, Op, int, int, int, double, const cplx*, int, long,
+                         const cplx*, int, long, double, cplx*, int, long, int, const double*, long,
+                         Uplo, const int*);
+
+// ---------------------------------------------------------------- grouped
+__global__ __launch_bounds__(256) void gemm_grouped_dc_kernel(const int* lo, const int* hi,
+                                                              const int* kk, const double* A,
+                                                              const double* B, double* C, int ld) {
+    int g = blockIdx.z;
+    int l = lo[g], rows = hi[g] - l, K = kk[g];
+    int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    if (m0 >= rows || n0 >= K) return;
+    long off = (long)l * ld + l;
+    gemm_tile<double, OP_N, OP_N>(rows, K, K, 1.0, A + off, ld, B + off, ld, 0.0, C + off, ld,
+                                  nullptr, UPLO_FULL, m0, n0);
+}
+
+void gemm_grouped_dc(hipStream_t s, int ngroups, int max_rows, const int* d_lo, const int* d_hi,
+                     const int* d_kk, const double* A, const double* B, double* C, int ld) {
+    if (ngroups <= 0 || max_rows <= 0) return;
+    dim3 grid(cdiv(max_rows, BN), cdiv(max_rows, BM), ngroups);
+    hipLaunchKernelGGL(gemm_grouped_dc_kernel, grid, dim3(256), 0, s, d_lo, d_hi, d_kk, A, B, C, ld);
+}
+
+}  // namespace ks

@@ -1,0 +1,174 @@
+// ks_internal.hpp -- internal interfaces between the host orchestration
+// (ks_api.hip) and the kernel files.
+#pragma once
+
+#include <vector>
+#include <algorithm>
+
+#include "ks_common.hpp"
+
+namespace ks {
+
+template <> __host__ __device__ inline int zero_<int>() { return 0; }
+
+constexpr int HETRD_NB = 32;   // panel width of the tridiagonalisation
+constexpr int BACKTR_BT = 64;  // reflectors per compact-WY block of the back-transform
+constexpr int DC_LEAF = 32;    // largest divide-and-conquer leaf
+constexpr int MAX_KW = 64;     // k-point weights passed by value
+
+struct KWeights {
+    double w[MAX_KW];
+};
+
+// Event-based profiler of a plan: phases of the solve and sampled launches of
+// the trailing matrix-vector kernel of the tridiagonalisation.  Host code only;
+// events are recorded on the plan's stream and read back on request.
+struct Prof {
+    bool on = false;
+    int stride = 1;
+    long counter = 0;
+    hipStream_t s = nullptr;
+    struct Rec {
+        int tag;
+        hipEvent_t a, b;
+        double bytes;
+    };
+    std::vector<hipEvent_t> pool;
+    std::vector<Rec> recs;
+    hipEvent_t rec_event() {
+        hipEvent_t e = nullptr;
+        if (!pool.empty()) {
+            e = pool.back();
+            pool.pop_back();
+        } else if (hipEventCreate(&e) != hipSuccess) {
+            return nullptr;
+        }
+        (void)hipEventRecord(e, s);
+        return e;
+    }
+    hipEvent_t begin() { return on ? rec_event() : nullptr; }
+    void end(int tag, hipEvent_t a, double bytes = 0.0) {
+        if (!on || !a) return;
+        hipEvent_t b = rec_event();
+        if (b) recs.push_back({tag, a, b, bytes});
+    }
+    bool sample() { return on && (counter++ % stride == 0); }
+    ~Prof() {
+        for (auto& r : recs) {
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+constexpr int PROF_HEMV = 100;  // tag of the sampled kernel
+
+template <typename T>
+struct HetrdWork {
+    Prof* prof = nullptr;
+    T* VW;          // n x 2NB   [V | W] of the current panel
+    T* WV;          // n x 2NB   [W | V]
+    T* x;           // n         updated column
+    T* v;           // n         reflector
+    T* y;           // n         trailing product
+    T* w;           // n         W column before its final correction
+    double* part1;  // cdiv(n, 256)
+    T* partPQ;      // cdiv(n, 16) x 2NB
+    double* partS;  // 2 cdiv(n, 256)
+};
+
+template <typename T>
+struct BacktrWork {
+    T* G;   // BT x BT
+    T* Tf;  // BT x BT
+    T* W1;  // BT x n
+    T* W2;  // BT x n
+};
+
+// Divide-and-conquer scratch; all position-indexed arrays have n entries and
+// each merge uses the slice [lo, hi) of its rows.
+struct DcWork {
+    double* dw;
+    double* ds;
+    double* zs;
+    int* perm;
+    int* ndl;
+    int* dfl;
+    double* dfval;
+    double* dnd;
+    double* znd;
+    int* rot_idx;   // 2 n
+    double* rot_cs; // 2 n
+    int* orig;
+    double* tau;
+    double* zhat;
+    double* cinv;
+    double* fval;
+    int* fsrc;
+    int* kk;        // per merge of the current level
+    int* nrot;
+    double* rho;
+};
+
+struct DcTree {
+    int n = 0, depth = 0, nleaf = 0, nmerge_total = 0;
+    std::vector<int> max_k0;  // per level (index = level)
+    int* d_mlo = nullptr;     // merges, level l at offset 2^l - 1
+    int* d_mmid = nullptr;
+    int* d_mhi = nullptr;
+    int* d_mid_all = nullptr; // same as d_mmid (all tears)
+    int* d_leaf_lo = nullptr;
+    int* d_leaf_hi = nullptr;
+};
+
+template <typename T>
+void fill_zero(hipStream_t s, T* p, long n);
+
+template <typename T>
+void potrf(hipStream_t s, int n, T* A, int lda, long sa, int batch, int* info);
+
+template <typename T>
+void trsm_left(hipStream_t s, bool conjt, int nl, int cols, const T* L, int ldl, long sl, T* B,
+               int ldb, long sb, int batch);
+
+template <typename T>
+void herm_complete(hipStream_t s, int n, const T* src, int lds, long ss, T* dst, int ldd, long sd,
+                   int batch, int* info);
+
+template <typename T>
+void reduce_to_standard(hipStream_t s, int n, int nsp, const T* H, int ldh, const T* L, int ldl, T* A,
+                        T* W, int* info);
+
+template <typename T>
+void hetrd(hipStream_t s, int n, T* A, int lda, double* d, double* e, T* tau, T* Vall,
+           HetrdWork<T>& w);
+
+void stedc(hipStream_t s, const DcTree& tr, const double* d, const double* e, double* lam, double* Z,
+           double* Z2, double* U, double* Qp, DcWork& w, int* info);
+
+void dc_tree_host(int n, std::vector<int>& mlo, std::vector<int>& mmid, std::vector<int>& mhi,
+                  std::vector<int>& leaf_lo, std::vector<int>& leaf_hi, int& depth,
+                  std::vector<int>& max_k0);
+
+template <typename T>
+void load_z(hipStream_t s, int n, int ncols, const double* Z, int c0, T* X, int ldx);
+
+template <typename T>
+void backtransform_q(hipStream_t s, int n, const T* Vall, const T* tau, int ncols, T* X, int ldx,
+                     BacktrWork<T>& w);
+
+void fermi(hipStream_t s, int batch, int order, const double* eps, const KWeights& kw, double g,
+           double ne, double kT, int il, int iu, double* occ, double* mu, double* eband, int* kwin,
+           int* info);
+
+template <typename T>
+void density_backward(hipStream_t s, int n, int nsp, int batch, const double* eps, const T* C, int ldc,
+                      const double* mu, double kT, double g, const KWeights& kw, const T* grad_rho,
+                      const double* grad_eband, T* grad_H, T* grad_S, int lds, T* W1, T* W2, T* W3,
+                      double* scal);
+
+}  // namespace ks
+
+// Stage drivers behind the test hooks (defined in ks_api.hip).
+void ks_internal_stedc(ks_plan* p, const double* d, const double* e, double* lam, double* Z);
+void ks_internal_hetrd(ks_plan* p, void* A, double* d, double* e, const double* X, int ncols, void* Y);

@@ -1,0 +1,599 @@
+// ks_stedc.hip -- divide-and-conquer eigensolver of the real symmetric
+// tridiagonal T = tridiag(e, d, e) (Cuppen's method with Gu-Eisenstat
+// eigenvectors), the second half of the "diagonalize H'" step that the paper
+// (Sec. 6) describes as dominated by matrix products.
+//
+// Tree: T is torn at the midpoints down to leaves of at most DC_LEAF rows; the
+// tear at m uses T = diag(T1', T2') + |b| w w^T with b = e[m-1],
+// w = e_{m-1} + sign(b) e_m and d[m-1], d[m] reduced by |b|.
+// Leaves: parallel cyclic Jacobi in LDS (one workgroup per leaf).
+// Merge of (D1, Q1), (D2, Q2) into D + rho z z^T, z = [Q1 row m-1;
+// sign(b) Q2 row m] / sqrt(2), rho = 2|b|:
+//   deflate  sort (D, z); drop |rho z_i| <= tol; rotate away z of nearly equal
+//            pairs (tol = 8 eps max(|D|, |z|));
+//   secular  one wavefront per root of 1 + rho sum z_i^2/(d_i - x) = 0, origin
+//            at the nearer pole, safeguarded two-pole rational iteration with
+//            bisection fallback;
+//   vectors  z_hat from the computed roots (Gu-Eisenstat), u_j ~ z_hat/(d - x_j);
+//   product  Q_new = Q_perm U on the matrix cores (grouped GEMM);
+//   order    rank sort of the merged eigenvalues, columns permuted to match.
+// Every size that depends on deflation stays on the device: kernels are
+// launched for the undeflated size and idle workgroups exit, so the whole
+// solve is enqueued without a host synchronisation.
+#include "ks_internal.hpp"
+
+namespace ks {
+
+constexpr double DEPS = 1.1102230246251565e-16;  // unit roundoff 2^-53
+
+// ---------------------------------------------------------------- setup
+__global__ void dc_init_kernel(int n, const double* d, const double* e, const int* mids, int nmid,
+                               double* dw) {
+    // single thread: the tears modify neighbouring diagonal entries
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int i = 0; i < n; ++i) dw[i] = d[i];
+    for (int q = 0; q < nmid; ++q) {
+        int m = mids[q];
+        double b = fabs(e[m - 1]);
+        dw[m - 1] -= b;
+        dw[m] -= b;
+    }
+}
+
+// ---------------------------------------------------------------- leaves
+// Parallel cyclic Jacobi on the dense leaf (size <= DC_LEAF) in LDS.
+__global__ __launch_bounds__(64) void dc_leaf_kernel(int n, const int* leaf_lo, const int* leaf_hi,
+                                                     const double* dw, const double* e, double* lam,
+                                                     double* Z, int* info) {
+    constexpr int L = DC_LEAF;
+    __shared__ double A[L][L + 1];
+    __shared__ double VT[L][L + 1];
+    __shared__ double rc[L / 2], rs[L / 2], rpp[L / 2], rqq[L / 2];
+    __shared__ int rp[L / 2], rq[L / 2], ract[L / 2];
+    __shared__ int any_rot;
+    __shared__ double w[L];
+    __shared__ int idx[L];
+    int lo = leaf_lo[blockIdx.x], hi = leaf_hi[blockIdx.x];
+    int s = hi - lo;
+    int t = threadIdx.x;
+    for (int q = t; q < L * L; q += 64) {
+        int i = q / L, j = q % L;
+        double v = 0.0;
+        if (i < s && j < s) {
+            if (i == j) v = dw[lo + i];
+            else if (j == i + 1) v = e[lo + i];
+            else if (i == j + 1) v = e[lo + j];
+        }
+        A[i][j] = v;
+        VT[i][j] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    double nrm = 0.0;
+    for (int i = 0; i < s; ++i) nrm += A[i][i] * A[i][i] + (i + 1 < s ? 2.0 * A[i][i + 1] * A[i][i + 1] : 0.0);
+    nrm = sqrt(nrm);
+    double tol = 1e-18 * nrm;
+    int m = s + (s & 1);
+    int np = m / 2;
+    int sweep = 0;
+    for (; sweep < 40 && s > 1; ++sweep) {
+        if (t == 0) any_rot = 0;
+        __syncthreads();
+        for (int r = 0; r < m - 1; ++r) {
+            if (t < np) {
+                int a = (t == 0) ? 0 : 1 + ((t - 1 + r) % (m - 1));
+                int b = 1 + ((m - 2 - t + r) % (m - 1));
+                int p = min(a, b), q = max(a, b);
+                rp[t] = p;
+                rq[t] = q;
+                ract[t] = 0;
+                if (q < s) {
+                    double apq = A[p][q], app = A[p][p], aqq = A[q][q];
+                    if (fabs(apq) > tol) {
+                        double tau = (aqq - app) / (2.0 * apq);
+                        double tt = (tau >= 0.0) ? 1.0 / (tau + sqrt(1.0 + tau * tau))
+                                                 : -1.0 / (-tau + sqrt(1.0 + tau * tau));
+                        double c = 1.0 / sqrt(1.0 + tt * tt);
+                        rc[t] = c;
+                        rs[t] = tt * c;
+                        rpp[t] = app - tt * apq;
+                        rqq[t] = aqq + tt * apq;
+                        ract[t] = 1;
+                        any_rot = 1;
+                    } else {
+                        A[p][q] = 0.0;
+                        A[q][p] = 0.0;
+                    }
+                }
+            }
+            __syncthreads();
+            // rows: A <- J^T A ; VT <- J^T VT
+            for (int q = t; q < np * L; q += 64) {
+                int pi = q / L, col = q % L;
+                if (!ract[pi] || col >= s) continue;
+                int p = rp[pi], qq = rq[pi];
+                double c = rc[pi], sn = rs[pi];
+                double x = A[p][col], y = A[qq][col];
+                A[p][col] = c * x - sn * y;
+                A[qq][col] = sn * x + c * y;
+                x = VT[p][col];
+                y = VT[qq][col];
+                VT[p][col] = c * x - sn * y;
+                VT[qq][col] = sn * x + c * y;
+            }
+            __syncthreads();
+            // columns: A <- A J
+            for (int q = t; q < np * L; q += 64) {
+                int pi = q / L, row = q % L;
+                if (!ract[pi] || row >= s) continue;
+                int p = rp[pi], qq = rq[pi];
+                double c = rc[pi], sn = rs[pi];
+                double x = A[row][p], y = A[row][qq];
+                A[row][p] = c * x - sn * y;
+                A[row][qq] = sn * x + c * y;
+            }
+            __syncthreads();
+            if (t < np && ract[t]) {
+                int p = rp[t], qq = rq[t];
+                A[p][p] = rpp[t];
+                A[qq][qq] = rqq[t];
+                A[p][qq] = 0.0;
+                A[qq][p] = 0.0;
+            }
+            __syncthreads();
+        }
+        if (!any_rot) break;
+    }
+    if (sweep >= 40 && t == 0) set_info(info, KS_ERR_NO_CONVERGENCE, 1);
+    // stable ascending rank sort of the diagonal
+    if (t < s) w[t] = A[t][t];
+    __syncthreads();
+    if (t < s) {
+        int rk = 0;
+        for (int q = 0; q < s; ++q) rk += (w[q] < w[t]) || (w[q] == w[t] && q < t);
+        idx[rk] = t;
+    }
+    __syncthreads();
+    if (t < s) lam[lo + t] = w[idx[t]];
+    for (int q = t; q < s * s; q += 64) {
+        int row = q / s, col = q % s;
+        Z[(long)(lo + row) * n + lo + col] = VT[idx[col]][row];
+    }
+}
+
+// ---------------------------------------------------------------- merges
+// One workgroup per merge: form (D, z), merge-sort, deflate.
+__global__ __launch_bounds__(256) void dc_deflate_kernel(int n, const int* mlo, const int* mmid,
+                                                         const int* mhi, const double* e,
+                                                         const double* lam, const double* Z,
+                                                         DcWork w) {
+    __shared__ double red[4];
+    __shared__ double sd[64], sz[64];
+    int g = blockIdx.x;
+    int lo = mlo[g], mid = mmid[g], hi = mhi[g];
+    int K0 = hi - lo, n1 = mid - lo;
+    int t = threadIdx.x;
+    double b = e[mid - 1];
+    double rho = 2.0 * fabs(b);
+    double sg = (b >= 0.0) ? 1.0 : -1.0;
+    const double rs2 = 0.70710678118654752440;
+    double dmax = 0.0, zmax = 0.0;
+    for (int c = t; c < K0; c += blockDim.x) {
+        double D = lam[lo + c];
+        double z = (c < n1) ? Z[(long)(mid - 1) * n + lo + c] : sg * Z[(long)mid * n + lo + c];
+        z *= rs2;
+        // rank in the merged order (ties: first list first)
+        int rank;
+        if (c < n1) {
+            int a = 0, bb = K0 - n1;  // count of second-list entries < D
+            while (a < bb) {
+                int h = (a + bb) >> 1;
+                if (lam[mid + h] < D) a = h + 1;
+                else bb = h;
+            }
+            rank = c + a;
+        } else {
+            int a = 0, bb = n1;  // count of first-list entries <= D
+            while (a < bb) {
+                int h = (a + bb) >> 1;
+                if (lam[lo + h] <= D) a = h + 1;
+                else bb = h;
+            }
+            rank = (c - n1) + a;
+        }
+        w.perm[lo + rank] = c;
+        w.ds[lo + rank] = D;
+        w.zs[lo + rank] = z;
+        dmax = fmax(dmax, fabs(D));
+        zmax = fmax(zmax, fabs(z));
+    }
+    // block max (fixed order)
+    dmax = wave_max(dmax);
+    zmax = wave_max(zmax);
+    __shared__ double mx[2][4];
+    if ((t & 63) == 0) {
+        mx[0][t >> 6] = dmax;
+        mx[1][t >> 6] = zmax;
+    }
+    __threadfence_block();
+    __syncthreads();
+    double tol = 0.0;
+    for (int i = 0; i < 4; ++i) tol = fmax(tol, fmax(mx[0][i], mx[1][i]));
+    tol *= 8.0 * DEPS;
+    (void)red;
+    // sequential deflation scan, streamed through LDS in chunks of 64
+    if (t < 64) {
+        int K = 0, nd = 0, nrot = 0, pj = -1;
+        double dpj = 0.0, zpj = 0.0;
+        for (int base = 0; base < K0; base += 64) {
+            int cnt = min(64, K0 - base);
+            if (t < cnt) {
+                sd[t] = w.ds[lo + base + t];
+                sz[t] = w.zs[lo + base + t];
+            }
+            __threadfence_block();
+            if (t == 0) {
+                for (int q = 0; q < cnt; ++q) {
+                    int jj = base + q;
+                    double dj = sd[q], zj = sz[q];
+                    if (rho * fabs(zj) <= tol) {
+                        w.dfl[lo + nd] = jj;
+                        w.dfval[lo + nd] = dj;
+                        ++nd;
+                        continue;
+                    }
+                    if (pj < 0) {
+                        pj = jj;
+                        dpj = dj;
+                        zpj = zj;
+                        continue;
+                    }
+                    double sn = zpj, cs = zj;
+                    double tau = hypot(cs, sn);
+                    double tt = dj - dpj;
+                    cs /= tau;
+                    sn = -sn / tau;
+                    if (fabs(tt * cs * sn) <= tol) {
+                        w.rot_idx[2 * (lo + nrot)] = pj;
+                        w.rot_idx[2 * (lo + nrot) + 1] = jj;
+                        w.rot_cs[2 * (lo + nrot)] = cs;
+                        w.rot_cs[2 * (lo + nrot) + 1] = sn;
+                        ++nrot;
+                        double tp = dpj * cs * cs + dj * sn * sn;
+                        dj = dpj * sn * sn + dj * cs * cs;
+                        w.dfl[lo + nd] = pj;
+                        w.dfval[lo + nd] = tp;
+                        ++nd;
+                        pj = jj;
+                        dpj = dj;
+                        zpj = tau;
+                    } else {
+                        w.ndl[lo + K] = pj;
+                        w.dnd[lo + K] = dpj;
+                        w.znd[lo + K] = zpj;
+                        ++K;
+                        pj = jj;
+                        dpj = dj;
+                        zpj = zj;
+                    }
+                }
+            }
+            __threadfence_block();
+        }
+        if (t == 0) {
+            if (pj >= 0) {
+                w.ndl[lo + K] = pj;
+                w.dnd[lo + K] = dpj;
+                w.znd[lo + K] = zpj;
+                ++K;
+            }
+            w.kk[g] = K;
+            w.nrot[g] = nrot;
+            w.rho[g] = rho;
+        }
+    }
+}
+
+// Apply the deflation rotations to the merge's columns of Z, one thread per row.
+__global__ __launch_bounds__(256) void dc_rotate_kernel(int n, const int* mlo, const int* mhi, DcWork w,
+                                                        double* Z) {
+    int g = blockIdx.y;
+    int lo = mlo[g], hi = mhi[g];
+    int r = lo + blockIdx.x * blockDim.x + threadIdx.x;
+    int nr = w.nrot[g];
+    if (r >= hi || nr == 0) return;
+    double* zr = Z + (long)r * n + lo;
+    for (int q = 0; q < nr; ++q) {
+        int pj = w.rot_idx[2 * (lo + q)], jj = w.rot_idx[2 * (lo + q) + 1];
+        double c = w.rot_cs[2 * (lo + q)], s = w.rot_cs[2 * (lo + q) + 1];
+        int cp = w.perm[lo + pj], cj = w.perm[lo + jj];
+        double x = zr[cp], y = zr[cj];
+        zr[cp] = c * x + s * y;
+        zr[cj] = c * y - s * x;
+    }
+}
+
+// Secular equation: one wavefront per root.
+__global__ __launch_bounds__(256) void dc_secular_kernel(const int* mlo, DcWork w, int* info) {
+    int g = blockIdx.y;
+    int lo = mlo[g];
+    int K = w.kk[g];
+    int jr = blockIdx.x * 4 + (threadIdx.x >> 6);
+    int lane = threadIdx.x & 63;
+    if (jr >= K) return;
+    const double* d = w.dnd + lo;
+    const double* z = w.znd + lo;
+    double rho = w.rho[g];
+    if (K == 1) {
+        if (lane == 0) {
+            w.orig[lo] = 0;
+            w.tau[lo] = rho * z[0] * z[0];
+        }
+        return;
+    }
+    int o;
+    double blo, bhi;
+    if (jr < K - 1) {
+        double D = d[jr + 1] - d[jr];
+        double f = 0.0;
+        for (int i = lane; i < K; i += 64) f += z[i] * z[i] / ((d[i] - d[jr]) - 0.5 * D);
+        f = 1.0 + rho * wave_sum(f);
+        if (f >= 0.0) {
+            o = jr;
+            blo = 0.0;
+            bhi = 0.5 * D;
+        } else {
+            o = jr + 1;
+            blo = -0.5 * D;
+            bhi = 0.0;
+        }
+    } else {
+        double zz = 0.0;
+        for (int i = lane; i < K; i += 64) zz += z[i] * z[i];
+        zz = wave_sum(zz);
+        o = K - 1;
+        blo = 0.0;
+        bhi = rho * zz;
+    }
+    double dor = d[o];
+    double tau = 0.5 * (blo + bhi);
+    bool conv = false;
+    for (int it = 0; it < 120; ++it) {
+        double psi = 0.0, phi = 0.0, dpsi = 0.0, dphi = 0.0, eabs = 0.0;
+        for (int i = lane; i < K; i += 64) {
+            double del = (d[i] - dor) - tau;
+            double tm = z[i] * z[i] / del;
+            if (i <= jr) {
+                psi += tm;
+                dpsi += tm / del;
+            } else {
+                phi += tm;
+                dphi += tm / del;
+            }
+            eabs += fabs(tm);
+        }
+        psi = wave_sum(psi);
+        phi = wave_sum(phi);
+        dpsi = wave_sum(dpsi);
+        dphi = wave_sum(dphi);
+        eabs = wave_sum(eabs);
+        double f = 1.0 + rho * (psi + phi);
+        double err = 16.0 * DEPS * (1.0 + rho * eabs + fabs(tau) * rho * (dpsi + dphi));
+        if (fabs(f) <= err) {
+            conv = true;
+            break;
+        }
+        if (f < 0.0) blo = tau;
+        else bhi = tau;
+        if (bhi - blo <= 2.0 * DEPS * fmax(fabs(blo), fabs(bhi))) {
+            conv = true;
+            break;
+        }
+        double tn;
+        if (jr < K - 1) {
+            double D1 = (d[jr] - dor) - tau, D2 = (d[jr + 1] - dor) - tau;
+            double S1 = D1 * D1 * dpsi, S2 = D2 * D2 * dphi;
+            double c = f - rho * (S1 / D1 + S2 / D2);
+            double a2 = c, a1 = -(c * (D1 + D2) + rho * (S1 + S2)), a0 = D1 * D2 * f;
+            double eta;
+            if (a2 == 0.0) {
+                eta = -a0 / a1;
+            } else {
+                double disc = fmax(0.0, a1 * a1 - 4.0 * a2 * a0);
+                double q = -0.5 * (a1 + copysign(sqrt(disc), a1));
+                double e1 = q / a2, e2 = (q != 0.0) ? a0 / q : e1;
+                bool in1 = (tau + e1 > blo) && (tau + e1 < bhi);
+                bool in2 = (tau + e2 > blo) && (tau + e2 < bhi);
+                if (in1 && in2) eta = (fabs(e1) < fabs(e2)) ? e1 : e2;
+                else if (in2) eta = e2;
+                else eta = e1;
+            }
+            tn = tau + eta;
+        } else {
+            double D1 = -tau;
+            double S1 = D1 * D1 * dpsi;
+            double c = f - rho * S1 / D1;
+            tn = (c > 0.0) ? tau + D1 + rho * S1 / c : 0.5 * (blo + bhi);
+        }
+        if (!(tn > blo && tn < bhi) || it >= 60) tn = 0.5 * (blo + bhi);
+        tau = tn;
+    }
+    if (lane == 0) {
+        if (!conv) set_info(info, KS_ERR_NO_CONVERGENCE, 2);
+        w.orig[lo + jr] = o;
+        w.tau[lo + jr] = tau;
+    }
+}
+
+// Gu-Eisenstat: z_hat_i^2 = prod_j (x_j - d_i) / (rho prod_{j != i} (d_j - d_i)),
+// paired so that every factor lies in (0, 1].
+__global__ __launch_bounds__(256) void dc_zhat_kernel(const int* mlo, DcWork w) {
+    int g = blockIdx.y;
+    int lo = mlo[g];
+    int K = w.kk[g];
+    int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    int lane = threadIdx.x & 63;
+    if (i >= K) return;
+    const double* d = w.dnd + lo;
+    double di = d[i];
+    double p = 1.0;
+    for (int j = lane; j < K; j += 64) {
+        double xj = (d[w.orig[lo + j]] - di) + w.tau[lo + j];  // x_j - d_i
+        if (j < i) p *= xj / (d[j] - di);
+        else if (j < K - 1) p *= xj / (d[j + 1] - di);
+        else p *= xj;
+    }
+    p = wave_prod(p);
+    if (lane == 0) {
+        double zh = sqrt(fabs(p / w.rho[g]));
+        w.zhat[lo + i] = copysign(zh, w.znd[lo + i]);
+    }
+}
+
+// 1/||u_j|| with u_ij = z_hat_i / (d_i - x_j).
+__global__ __launch_bounds__(256) void dc_colnorm_kernel(const int* mlo, DcWork w) {
+    int g = blockIdx.y;
+    int lo = mlo[g];
+    int K = w.kk[g];
+    int jr = blockIdx.x * 4 + (threadIdx.x >> 6);
+    int lane = threadIdx.x & 63;
+    if (jr >= K) return;
+    const double* d = w.dnd + lo;
+    double dor = d[w.orig[lo + jr]], tj = w.tau[lo + jr];
+    double s = 0.0;
+    for (int i = lane; i < K; i += 64) {
+        double u = w.zhat[lo + i] / ((d[i] - dor) - tj);
+        s += u * u;
+    }
+    s = wave_sum(s);
+    if (lane == 0) w.cinv[lo + jr] = 1.0 / sqrt(s);
+}
+
+// U block (K x K at (lo, lo), row stride n): U_ij = z_hat_i / (d_i - x_j) / ||u_j||.
+__global__ __launch_bounds__(256) void dc_ugen_kernel(int n, const int* mlo, DcWork w, double* U) {
+    int g = blockIdx.z;
+    int lo = mlo[g];
+    int K = w.kk[g];
+    int i = blockIdx.y;
+    int jr = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= K || jr >= K) return;
+    const double* d = w.dnd + lo;
+    double u = w.zhat[lo + i] / ((d[i] - d[w.orig[lo + jr]]) - w.tau[lo + jr]);
+    U[(long)(lo + i) * n + lo + jr] = u * w.cinv[lo + jr];
+}
+
+// Gather: Qp columns [0, K) = undeflated columns of Z in secular order; Z2
+// columns [K, K0) = deflated columns (both at the merge's block).
+__global__ __launch_bounds__(256) void dc_gather_kernel(int n, const int* mlo, const int* mhi, DcWork w,
+                                                        const double* Z, double* Qp, double* Z2) {
+    int g = blockIdx.z;
+    int lo = mlo[g], hi = mhi[g];
+    int K0 = hi - lo, K = w.kk[g];
+    int r = lo + blockIdx.y;
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= hi || c >= K0) return;
+    if (c < K) {
+        int src = w.perm[lo + w.ndl[lo + c]];
+        Qp[(long)r * n + lo + c] = Z[(long)r * n + lo + src];
+    } else {
+        int src = w.perm[lo + w.dfl[lo + (c - K)]];
+        Z2[(long)r * n + lo + c] = Z[(long)r * n + lo + src];
+    }
+}
+
+// Final order: value of merged column c is x_c (c < K) or the deflated value;
+// stable rank sort; lam[lo + rank] = value, src[lo + rank] = c.
+__global__ __launch_bounds__(256) void dc_rank_kernel(const int* mlo, const int* mhi, DcWork w,
+                                                      double* lam) {
+    int g = blockIdx.y;
+    int lo = mlo[g], hi = mhi[g];
+    int K0 = hi - lo, K = w.kk[g];
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= K0) return;
+    const double* d = w.dnd + lo;
+    auto val = [&](int q) -> double {
+        return (q < K) ? d[w.orig[lo + q]] + w.tau[lo + q] : w.dfval[lo + q - K];
+    };
+    double v = val(c);
+    int rk = 0;
+    for (int q = 0; q < K0; ++q) {
+        double u = val(q);
+        rk += (u < v) || (u == v && q < c);
+    }
+    w.fval[lo + rk] = v;
+    w.fsrc[lo + rk] = c;
+}
+
+__global__ __launch_bounds__(256) void dc_permute_kernel(int n, const int* mlo, const int* mhi, DcWork w,
+                                                         const double* Z2, double* Z, double* lam) {
+    int g = blockIdx.z;
+    int lo = mlo[g], hi = mhi[g];
+    int K0 = hi - lo;
+    int r = lo + blockIdx.y;
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= hi || p >= K0) return;
+    Z[(long)r * n + lo + p] = Z2[(long)r * n + lo + w.fsrc[lo + p]];
+    if (r == lo) lam[lo + p] = w.fval[lo + p];
+}
+
+void stedc(hipStream_t s, const DcTree& tr, const double* d, const double* e, double* lam, double* Z,
+           double* Z2, double* U, double* Qp, DcWork& w, int* info) {
+    int n = tr.n;
+    fill_zero<double>(s, Z, (long)n * n);
+    hipLaunchKernelGGL(dc_init_kernel, dim3(1), dim3(1), 0, s, n, d, e, tr.d_mid_all, tr.nmerge_total, w.dw);
+    hipLaunchKernelGGL(dc_leaf_kernel, dim3(tr.nleaf), dim3(64), 0, s, n, tr.d_leaf_lo, tr.d_leaf_hi,
+                       (const double*)w.dw, e, lam, Z, info);
+    for (int l = tr.depth - 1; l >= 0; --l) {
+        int nm = 1 << l;
+        int off = nm - 1;
+        const int* mlo = tr.d_mlo + off;
+        const int* mmid = tr.d_mmid + off;
+        const int* mhi = tr.d_mhi + off;
+        int mk = tr.max_k0[l];
+        hipLaunchKernelGGL(dc_deflate_kernel, dim3(nm), dim3(256), 0, s, n, mlo, mmid, mhi, e, lam, Z, w);
+        hipLaunchKernelGGL(dc_rotate_kernel, dim3(cdiv(mk, 256), nm), dim3(256), 0, s, n, mlo, mhi, w, Z);
+        hipLaunchKernelGGL(dc_secular_kernel, dim3(cdiv(mk, 4), nm), dim3(256), 0, s, mlo, w, info);
+        hipLaunchKernelGGL(dc_zhat_kernel, dim3(cdiv(mk, 4), nm), dim3(256), 0, s, mlo, w);
+        hipLaunchKernelGGL(dc_colnorm_kernel, dim3(cdiv(mk, 4), nm), dim3(256), 0, s, mlo, w);
+        hipLaunchKernelGGL(dc_ugen_kernel, dim3(cdiv(mk, 256), mk, nm), dim3(256), 0, s, n, mlo, w, U);
+        hipLaunchKernelGGL(dc_gather_kernel, dim3(cdiv(mk, 256), mk, nm), dim3(256), 0, s, n, mlo, mhi, w,
+                           (const double*)Z, Qp, Z2);
+        gemm_grouped_dc(s, nm, mk, mlo, mhi, w.kk, Qp, U, Z2, n);
+        hipLaunchKernelGGL(dc_rank_kernel, dim3(cdiv(mk, 256), nm), dim3(256), 0, s, mlo, mhi, w, lam);
+        hipLaunchKernelGGL(dc_permute_kernel, dim3(cdiv(mk, 256), mk, nm), dim3(256), 0, s, n, mlo, mhi, w,
+                           (const double*)Z2, Z, lam);
+    }
+}
+
+// Host: the tear tree for order n (depth = smallest with ceil(n / 2^depth) <= DC_LEAF).
+void dc_tree_host(int n, std::vector<int>& mlo, std::vector<int>& mmid, std::vector<int>& mhi,
+                  std::vector<int>& leaf_lo, std::vector<int>& leaf_hi, int& depth,
+                  std::vector<int>& max_k0) {
+    depth = 0;
+    while ((n + (1 << depth) - 1) / (1 << depth) > DC_LEAF) ++depth;
+    // nodes level by level: level l has 2^l nodes, stored at offset 2^l - 1
+    std::vector<int> lo{0}, hi{n};
+    mlo.clear();
+    mmid.clear();
+    mhi.clear();
+    max_k0.assign(depth > 0 ? depth : 1, 0);
+    for (int l = 0; l < depth; ++l) {
+        std::vector<int> nlo, nhi;
+        for (size_t q = 0; q < lo.size(); ++q) {
+            int a = lo[q], b = hi[q], m = a + (b - a) / 2;
+            mlo.push_back(a);
+            mmid.push_back(m);
+            mhi.push_back(b);
+            max_k0[l] = std::max(max_k0[l], b - a);
+            nlo.push_back(a);
+            nhi.push_back(m);
+            nlo.push_back(m);
+            nhi.push_back(b);
+        }
+        lo.swap(nlo);
+        hi.swap(nhi);
+    }
+    leaf_lo = lo;
+    leaf_hi = hi;
+}
+
+}  // namespace ks

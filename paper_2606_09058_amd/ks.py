@@ -1,0 +1,276 @@
+"""Thin Python binding of include/ks.h (ctypes; argument marshalling only).
+
+Every step of the solve runs in the HIP library ``libks.so``; this module only
+checks tensor shapes/dtypes/devices, passes device pointers and the current
+torch stream, and maps status codes to exceptions.  If the library is missing
+the import of the binding fails loudly; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libks.so")
+
+KS_REAL64, KS_COMPLEX128 = 0, 1
+KS_COLLINEAR, KS_NONCOLLINEAR = 0, 1
+KS_FP64, KS_MIXED = 0, 1
+KS_PLAN_GRAPH = 1
+KS_REUSE_S = 1
+
+STATUS = {
+    0: "KS_OK", 1: "KS_ERR_INVALID_ARG", 2: "KS_ERR_NOT_POSDEF", 3: "KS_ERR_NO_CONVERGENCE",
+    4: "KS_ERR_ELECTRON_COUNT", 5: "KS_ERR_WINDOW", 6: "KS_ERR_NONFINITE", 7: "KS_ERR_ALLOC",
+    8: "KS_ERR_HIP", 9: "KS_ERR_NOT_SUPPORTED",
+}
+
+EXPORTS = ["ks_plan_create", "ks_plan_destroy", "ks_gevd", "ks_density", "ks_density_backward",
+           "ks_plan_get_info", "ks_status_string", "ks_plan_workspace_bytes", "ks_plan_set_profiling",
+           "ks_plan_get_profile"]
+
+
+class KSError(RuntimeError):
+    def __init__(self, status, where="", info=0):
+        self.status = int(status)
+        self.info = int(info)
+        msg = "%s: %s (%s)" % (where, STATUS.get(self.status, "?"), _status_string(self.status))
+        if info:
+            msg += " info=%d" % info
+        super().__init__(msg)
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("batch", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("spin", ctypes.c_int32), ("precision", ctypes.c_int32), ("ld_h", ctypes.c_int32),
+                ("ld_s", ctypes.c_int32), ("stream", ctypes.c_void_p), ("flags", ctypes.c_uint32)]
+
+
+class Profile(ctypes.Structure):
+    """ks_profile: per-phase times and the sampled matrix-vector kernel launches."""
+    _fields_ = [("phase_ms", ctypes.c_double * 8), ("phase_calls", ctypes.c_int64 * 8),
+                ("hemv_ms", ctypes.c_double), ("hemv_launches", ctypes.c_int64),
+                ("hemv_bytes", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libks.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("HIP library %s is missing; build it with "
+                               "`python -m paper_2606_09058_amd.build`" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        P, I, U, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_double
+        L.ks_plan_create.argtypes = [ctypes.POINTER(PlanDesc), ctypes.POINTER(ctypes.c_void_p)]
+        L.ks_plan_create.restype = I
+        L.ks_plan_destroy.argtypes = [P]
+        L.ks_plan_destroy.restype = None
+        L.ks_gevd.argtypes = [P, P, P, P, P, I, I, U]
+        L.ks_gevd.restype = I
+        L.ks_density.argtypes = [P, P, P, I, I, D, D, P, P, P, P, P]
+        L.ks_density.restype = I
+        L.ks_density_backward.argtypes = [P, P, P, P, P, D, P, P, P, P]
+        L.ks_density_backward.restype = I
+        L.ks_plan_get_info.argtypes = [P, ctypes.POINTER(I)]
+        L.ks_plan_get_info.restype = I
+        L.ks_status_string.argtypes = [I]
+        L.ks_status_string.restype = ctypes.c_char_p
+        L.ks_plan_workspace_bytes.argtypes = [ctypes.POINTER(PlanDesc)]
+        L.ks_plan_workspace_bytes.restype = ctypes.c_uint64
+        L.ks_plan_set_profiling.argtypes = [P, I, I]
+        L.ks_plan_set_profiling.restype = I
+        L.ks_plan_get_profile.argtypes = [P, ctypes.POINTER(Profile)]
+        L.ks_plan_get_profile.restype = I
+        _lib = L
+    return _lib
+
+
+def _status_string(st):
+    try:
+        return lib().ks_status_string(int(st)).decode()
+    except Exception:  # noqa: BLE001 - message only
+        return "?"
+
+
+def _check(st, where):
+    if st != 0:
+        raise KSError(st, where)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t, name, dtype, shape=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if t.device.type != "cuda":
+        raise ValueError("%s must live on the GPU" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
+
+
+class Plan:
+    """Owns a ks_plan: workspace for `batch` problems of `n` orbitals per spin block."""
+
+    def __init__(self, n, batch=1, complex=False, noncollinear=False, precision=KS_FP64, stream=None,
+                 ld_h=None, ld_s=None, flags=0):
+        self.n = int(n)
+        self.batch = int(batch)
+        self.nsp = 2 if noncollinear else 1
+        self.order = self.n * self.nsp
+        self.complex = bool(complex or noncollinear)
+        self.g = 1.0 if noncollinear else 2.0
+        self.mdtype = torch.complex128 if self.complex else torch.float64
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        self.desc = PlanDesc(self.n, self.batch, KS_COMPLEX128 if self.complex else KS_REAL64,
+                             KS_NONCOLLINEAR if noncollinear else KS_COLLINEAR, int(precision),
+                             int(ld_h or self.order), int(ld_s or self.n), ctypes.c_void_p(handle),
+                             int(flags))
+        self._h = ctypes.c_void_p()
+        _check(lib().ks_plan_create(ctypes.byref(self.desc), ctypes.byref(self._h)), "ks_plan_create")
+
+    # shapes --------------------------------------------------------------------------------
+    def _mshape(self):
+        return (self.batch, self.order, self.order) if self.batch > 1 else (self.order, self.order)
+
+    def _sshape(self):
+        return (self.batch, self.n, self.n) if self.batch > 1 else (self.n, self.n)
+
+    def _vshape(self):
+        return (self.batch, self.order) if self.batch > 1 else (self.order,)
+
+    # entry points --------------------------------------------------------------------------
+    def gevd(self, H, S, eps, C, il=1, iu=None, reuse_s=False):
+        iu = self.order if iu is None else iu
+        _need(H, "H", self.mdtype, self._mshape())
+        if S is not None:
+            _need(S, "S", self.mdtype, self._sshape())
+        _need(eps, "eps", torch.float64, self._vshape())
+        _need(C, "C", self.mdtype, self._mshape())
+        st = lib().ks_gevd(self._h, _ptr(H), _ptr(S), _ptr(eps), _ptr(C), int(il), int(iu),
+                           KS_REUSE_S if reuse_s else 0)
+        _check(st, "ks_gevd")
+
+    def density(self, eps, C, n_electrons, kT, rho, mu, eband, occ=None, il=1, iu=None,
+                kweights=None):
+        iu = self.order if iu is None else iu
+        _need(eps, "eps", torch.float64, self._vshape())
+        _need(C, "C", self.mdtype, self._mshape())
+        _need(rho, "rho", self.mdtype, self._mshape())
+        _need(mu, "mu", torch.float64, (1,))
+        _need(eband, "eband", torch.float64, (1,))
+        if occ is not None:
+            _need(occ, "occ", torch.float64, self._vshape())
+        kw = None
+        if kweights is not None:
+            arr = (ctypes.c_double * self.batch)(*[float(x) for x in kweights])
+            kw = ctypes.cast(arr, ctypes.c_void_p)
+        st = lib().ks_density(self._h, _ptr(eps), _ptr(C), int(il), int(iu), float(n_electrons),
+                              float(kT), kw, _ptr(rho), _ptr(mu), _ptr(eband), _ptr(occ))
+        _check(st, "ks_density")
+
+    def density_backward(self, eps, C, mu, occ, kT, grad_rho, grad_eband, grad_H, grad_S):
+        _need(eps, "eps", torch.float64, self._vshape())
+        _need(C, "C", self.mdtype, self._mshape())
+        _need(mu, "mu", torch.float64, (1,))
+        _need(occ, "occ", torch.float64, self._vshape())
+        if grad_rho is not None:
+            _need(grad_rho, "grad_rho", self.mdtype, self._mshape())
+        if grad_eband is not None:
+            _need(grad_eband, "grad_eband", torch.float64, (1,))
+        _need(grad_H, "grad_H", self.mdtype, self._mshape())
+        _need(grad_S, "grad_S", self.mdtype, self._sshape())
+        st = lib().ks_density_backward(self._h, _ptr(eps), _ptr(C), _ptr(mu), _ptr(occ), float(kT),
+                                       _ptr(grad_rho), _ptr(grad_eband), _ptr(grad_H), _ptr(grad_S))
+        _check(st, "ks_density_backward")
+
+    def set_profiling(self, enable, stride=1):
+        _check(lib().ks_plan_set_profiling(self._h, int(bool(enable)), int(stride)), "ks_plan_set_profiling")
+
+    def get_profile(self):
+        pr = Profile()
+        _check(lib().ks_plan_get_profile(self._h, ctypes.byref(pr)), "ks_plan_get_profile")
+        return pr
+
+    def get_info(self):
+        """Synchronize and return (status, info); clears the device info word."""
+        v = ctypes.c_int32(0)
+        st = lib().ks_plan_get_info(self._h, ctypes.byref(v))
+        return int(st), int(v.value)
+
+    def check(self, where="device"):
+        st, info = self.get_info()
+        if st != 0:
+            raise KSError(st, where, info)
+
+    def close(self):
+        if self._h:
+            lib().ks_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter teardown
+            pass
+
+    # convenience ---------------------------------------------------------------------------
+    def empty_matrix(self):
+        return torch.empty(self._mshape(), dtype=self.mdtype, device="cuda")
+
+    def solve(self, H, S, n_electrons, kT, il=1, iu=None, kweights=None, reuse_s=False, check=True):
+        """ks_gevd + ks_density; returns dict of device tensors."""
+        dev = H.device
+        eps = torch.empty(self._vshape(), dtype=torch.float64, device=dev)
+        C = torch.zeros(self._mshape(), dtype=self.mdtype, device=dev)
+        rho = torch.empty(self._mshape(), dtype=self.mdtype, device=dev)
+        mu = torch.empty(1, dtype=torch.float64, device=dev)
+        eband = torch.empty(1, dtype=torch.float64, device=dev)
+        occ = torch.empty(self._vshape(), dtype=torch.float64, device=dev)
+        self.gevd(H, S, eps, C, il=il, iu=iu, reuse_s=reuse_s)
+        self.density(eps, C, n_electrons, kT, rho, mu, eband, occ=occ, il=il, iu=iu, kweights=kweights)
+        if check:
+            self.check("solve")
+        return dict(eps=eps, C=C, rho=rho, mu=mu, eband=eband, occ=occ)
+
+
+class KSDensity(torch.autograd.Function):
+    """(H, S) -> (rho, E_band) through ks_gevd + ks_density; backward through
+    ks_density_backward.  Gradients are the Hermitian matrices grad_H, grad_S with
+    dL = Re tr(grad_H^H dH) + Re tr(grad_S^H dS) (torch's convention for real L)."""
+
+    @staticmethod
+    def forward(ctx, H, S, n_electrons, kT, noncollinear=False):
+        n = S.shape[-1]
+        plan = Plan(n, complex=H.is_complex(), noncollinear=noncollinear)
+        out = plan.solve(H.contiguous(), S.contiguous(), n_electrons, kT)
+        ctx.plan = plan
+        ctx.kT = float(kT)
+        ctx.save_for_backward(out["eps"], out["C"], out["mu"], out["occ"])
+        return out["rho"], out["eband"]
+
+    @staticmethod
+    def backward(ctx, grad_rho, grad_eband):
+        eps, C, mu, occ = ctx.saved_tensors
+        plan = ctx.plan
+        gH = plan.empty_matrix()
+        gS = torch.empty(plan._sshape(), dtype=plan.mdtype, device=C.device)
+        gr = None if grad_rho is None else grad_rho.contiguous()
+        ge = None if grad_eband is None else grad_eband.contiguous().reshape(1).to(torch.float64)
+        plan.density_backward(eps, C, mu, occ, ctx.kT, gr, ge, gH, gS)
+        plan.check("ks_density_backward")
+        return gH, gS, None, None, None

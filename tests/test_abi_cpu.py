@@ -1,0 +1,102 @@
+"""CPU-only checks of the C-ABI library: it loads, exports every symbol its headers
+declare, and rejects bad arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2606_09058_amd import ks
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("ks.h", "ks_testing.h")]
+
+
+def declared_functions():
+    names = []
+    for h in HEADERS:
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names += re.findall(r"\b(ks_[a-z_0-9]+)\s*\(", src)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(ks.LIB_PATH):
+        pytest.fail("libks.so is not built (run python -m paper_2606_09058_amd.build)")
+    return ks.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared_functions()
+    assert "ks_gevd" in names and "ks_density_backward" in names
+    for nm in names:
+        assert hasattr(L, nm), nm
+    assert set(ks.EXPORTS) <= set(names)
+
+
+def test_status_strings(L):
+    for code in range(10):
+        s = L.ks_status_string(code)
+        assert s and s != b"unknown status"
+    assert L.ks_status_string(99) == b"unknown status"
+
+
+def desc(n=100, batch=1, dtype=0, spin=0, prec=0, ldh=None, lds=None, flags=0):
+    order = n * (2 if spin else 1)
+    return ks.PlanDesc(n, batch, dtype, spin, prec, order if ldh is None else ldh,
+                       n if lds is None else lds, None, flags)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n=0), dict(batch=0), dict(dtype=2), dict(spin=3), dict(prec=7), dict(ldh=99),
+    dict(lds=50), dict(flags=8), dict(n=40000, spin=1, dtype=1),
+])
+def test_plan_create_rejects_bad_descriptors_without_device(L, bad):
+    h = ctypes.c_void_p()
+    d = desc(**bad)
+    assert L.ks_plan_create(ctypes.byref(d), ctypes.byref(h)) == 1
+    assert not h.value
+    assert L.ks_plan_workspace_bytes(ctypes.byref(d)) == 0
+
+
+def test_plan_create_unsupported_combinations(L):
+    h = ctypes.c_void_p()
+    assert L.ks_plan_create(ctypes.byref(desc(spin=1, dtype=0)), ctypes.byref(h)) == 9
+    assert L.ks_plan_create(ctypes.byref(desc(prec=1)), ctypes.byref(h)) == 9
+    assert L.ks_plan_create(ctypes.byref(desc(batch=65)), ctypes.byref(h)) == 9
+    assert L.ks_plan_create(ctypes.byref(desc()), None) == 1
+    assert L.ks_plan_create(None, ctypes.byref(h)) == 1
+
+
+def test_workspace_bytes_scale(L):
+    b1 = L.ks_plan_workspace_bytes(ctypes.byref(desc(n=1000)))
+    b2 = L.ks_plan_workspace_bytes(ctypes.byref(desc(n=2000)))
+    bc = L.ks_plan_workspace_bytes(ctypes.byref(desc(n=1000, dtype=1)))
+    assert b1 > 0 and 3.5 < b2 / b1 < 4.5
+    assert bc > b1
+    # the 512-atom and 384-atom shaped problems fit easily in 288 GB
+    assert L.ks_plan_workspace_bytes(ctypes.byref(desc(n=6656))) < 4e9
+    assert L.ks_plan_workspace_bytes(ctypes.byref(desc(n=4992, spin=1, dtype=1))) < 1e10
+
+
+def test_entry_points_reject_null_plan(L):
+    assert L.ks_gevd(None, None, None, None, None, 1, 1, 0) == 1
+    assert L.ks_density(None, None, None, 1, 1, 1.0, 0.01, None, None, None, None, None) == 1
+    assert L.ks_density_backward(None, None, None, None, None, 0.01, None, None, None, None) == 1
+    v = ctypes.c_int32(0)
+    assert L.ks_plan_get_info(None, ctypes.byref(v)) == 1
+    L.ks_plan_destroy(None)
+
+
+def test_binding_raises_when_library_missing(monkeypatch, tmp_path):
+    monkeypatch.setattr(ks, "LIB_PATH", str(tmp_path / "nope.so"))
+    monkeypatch.setattr(ks, "_lib", None)
+    with pytest.raises(RuntimeError, match="missing"):
+        ks.lib()
+
+
+def test_oracle_library_builds_and_loads():
+    from oracle import oracle as O
+    assert O.max_threads() >= 1

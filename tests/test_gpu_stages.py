@@ -1,0 +1,223 @@
+"""Stage-by-stage parity of the HIP kernels (through the test hooks of
+include/ks_testing.h) against the oracle and closed forms."""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2606_09058_amd import inputs as I
+from paper_2606_09058_amd import ks
+from tests.gpu_helpers import announce, dev, host, stream_handle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    lib = ks.lib()
+    V, I32, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    lib.ks_test_gemm.argtypes = [I32, I32, I32, I32, I32, I32, D, V, I32, V, I32, D, V, I32, I32, V]
+    lib.ks_test_gemm.restype = I32
+    lib.ks_test_potrf.argtypes = [I32, I32, V, I32, ctypes.POINTER(I32), V]
+    lib.ks_test_potrf.restype = I32
+    lib.ks_test_stedc.argtypes = [I32, V, V, V, V, ctypes.POINTER(I32), V]
+    lib.ks_test_stedc.restype = I32
+    lib.ks_test_hetrd.argtypes = [I32, I32, V, V, V, V, I32, V, V]
+    lib.ks_test_hetrd.restype = I32
+    lib.ks_test_mfma_layout.argtypes = [V, V]
+    lib.ks_test_mfma_layout.restype = I32
+    return lib
+
+
+def P(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def test_mfma_f64_lane_layout(L):
+    announce("mfma layout")
+    out = torch.zeros(256, dtype=torch.float64, device="cuda")
+    assert L.ks_test_mfma_layout(P(out), stream_handle()) == 0
+    o = host(out).reshape(64, 4)
+    lane = np.arange(64)[:, None]
+    r = np.arange(4)[None, :]
+    expect = 100.0 * (lane // 16 + 4 * r) + lane % 16
+    assert np.array_equal(o, expect), o
+
+
+GEMM_SHAPES = [(1, 1, 1), (64, 64, 16), (65, 130, 17), (200, 77, 300), (5, 300, 64), (130, 1, 2)]
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("opa,opb", [(0, 0), (0, 1), (0, 2), (1, 0), (2, 0)])
+def test_gemm_matches_numpy(L, cplx, opa, opb):
+    rng = np.random.default_rng(opa * 3 + opb)
+    for (m, n, k) in GEMM_SHAPES:
+        announce("gemm", cplx, opa, opb, m, n, k)
+        dt = np.complex128 if cplx else np.float64
+
+        def rnd(*s):
+            x = rng.normal(size=s)
+            return (x + 1j * rng.normal(size=s)) if cplx else x
+        A = rnd(m, k) if opa == 0 else rnd(k, m)
+        B = rnd(k, n) if opb == 0 else rnd(n, k)
+        C0 = rnd(m, n)
+        op = lambda X, o: X if o == 0 else (X.T if o == 1 else X.conj().T)  # noqa: E731
+        alpha, beta = -0.7, 0.3
+        ref = alpha * op(A, opa) @ op(B, opb) + beta * C0
+        Ad, Bd, Cd = dev(A.astype(dt)), dev(B.astype(dt)), dev(C0.astype(dt))
+        st = L.ks_test_gemm(int(cplx), opa, opb, m, n, k, alpha, P(Ad), A.shape[1], P(Bd), B.shape[1],
+                            beta, P(Cd), n, 0, stream_handle())
+        assert st == 0
+        got = host(Cd)
+        scale = np.abs(A).max() * np.abs(B).max() * k + 1
+        assert np.abs(got - ref).max() < 1e-13 * scale, (m, n, k)
+
+
+def test_gemm_lower_only(L):
+    rng = np.random.default_rng(5)
+    m = 150
+    A = rng.normal(size=(m, 40))
+    C0 = rng.normal(size=(m, m))
+    Cd = dev(C0)
+    Ad = dev(A)
+    announce("gemm lower")
+    assert L.ks_test_gemm(0, 0, 1, m, m, 40, 1.0, P(Ad), 40, P(Ad), 40, 1.0, P(Cd), m, 1,
+                          stream_handle()) == 0
+    got = host(Cd)
+    ref = C0 + A @ A.T
+    low = np.tril(np.ones((m, m), bool))
+    assert np.abs(got[low] - ref[low]).max() < 1e-12
+    assert np.array_equal(got[~low], C0[~low])
+
+
+@pytest.mark.parametrize("n", [1, 31, 32, 33, 100, 257])
+@pytest.mark.parametrize("cplx", [False, True])
+def test_potrf_matches_oracle(L, n, cplx):
+    announce("potrf", n, cplx)
+    rng = np.random.default_rng(n)
+    S = I.random_spd(rng, n, cplx)
+    A = dev(S)
+    info = ctypes.c_int32(-1)
+    assert L.ks_test_potrf(int(cplx), n, P(A), n, ctypes.byref(info), stream_handle()) == 0
+    assert info.value == 0
+    Lg = np.tril(host(A))
+    Lo = O.cholesky(S)
+    assert np.abs(Lg - Lo).max() < 1e-12 * np.abs(Lo).max()
+
+
+def test_potrf_reports_failing_column(L):
+    n = 70
+    rng = np.random.default_rng(1)
+    S = I.random_spd(rng, n, False)
+    S[50, 50] = -5.0
+    with pytest.raises(O.OracleError) as ex:
+        O.cholesky(S)
+    col = int(str(ex.value).split()[-1])
+    A = dev(S)
+    info = ctypes.c_int32(-1)
+    announce("potrf failure")
+    assert L.ks_test_potrf(0, n, P(A), n, ctypes.byref(info), stream_handle()) == 0
+    assert info.value == col
+
+
+def run_stedc(L, d, e):
+    n = len(d)
+    dd, ed = dev(d), dev(e if n > 1 else np.zeros(1))
+    lam = torch.zeros(n, dtype=torch.float64, device="cuda")
+    Z = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    info = ctypes.c_int32(-1)
+    st = L.ks_test_stedc(n, P(dd), P(ed), P(lam), P(Z), ctypes.byref(info), stream_handle())
+    assert st == 0
+    return host(lam), host(Z), info.value
+
+
+def tridiag(d, e):
+    return np.diag(d) + np.diag(e, 1) + np.diag(e, -1)
+
+
+@pytest.mark.parametrize("n", [1, 2, 31, 32, 33, 64, 100, 1000])
+def test_stedc_toeplitz_closed_form(L, n):
+    """tridiag(b, a, b): lambda_k = a + 2|b| cos(k pi / (n+1))."""
+    announce("stedc toeplitz", n)
+    a, b = 0.3, -0.9
+    lam, Z, info = run_stedc(L, np.full(n, a), np.full(max(n - 1, 0), b))
+    assert info == 0
+    k = np.arange(1, n + 1)
+    ref = np.sort(a + 2 * abs(b) * np.cos(k * np.pi / (n + 1)))
+    assert np.abs(lam - ref).max() < 1e-13 * n
+    T = tridiag(np.full(n, a), np.full(n - 1, b))
+    assert np.abs(Z.T @ Z - np.eye(n)).max() < 1e-12
+    assert np.abs(T @ Z - Z * lam).max() < 1e-12
+
+
+@pytest.mark.parametrize("n", [10, 100, 401])
+def test_stedc_clement_integer_spectrum(L, n):
+    announce("stedc clement", n)
+    e = np.sqrt(np.arange(1, n) * (n - np.arange(1, n)))
+    lam, Z, info = run_stedc(L, np.zeros(n), e)
+    assert info == 0
+    ref = np.arange(-(n - 1), n, 2, dtype=np.float64)
+    assert np.abs(lam - ref).max() < 1e-11 * n
+
+
+@pytest.mark.parametrize("n,seed", [(50, 0), (333, 1), (1024, 2)])
+def test_stedc_random_vs_oracle(L, n, seed):
+    announce("stedc random", n)
+    rng = np.random.default_rng(seed)
+    d = rng.normal(size=n)
+    e = rng.normal(size=n - 1)
+    lam, Z, info = run_stedc(L, d, e)
+    assert info == 0
+    T = tridiag(d, e)
+    w, V, _ = O.jacobi(T)
+    assert np.abs(lam - w).max() < 1e-12 * np.abs(w).max() * 10
+    assert np.abs(Z.T @ Z - np.eye(n)).max() < 1e-12
+    assert np.abs(T @ Z - Z * lam).max() < 1e-12 * np.abs(w).max() * 10
+
+
+def test_stedc_exact_deflation_and_clusters(L):
+    """Block-diagonal T (zero couplings), repeated diagonal values (clusters) and a
+    Wilkinson-type matrix with pairs close to machine precision."""
+    announce("stedc deflation")
+    n = 300
+    rng = np.random.default_rng(3)
+    d = np.round(rng.normal(size=n), 1)  # many exact ties
+    e = rng.normal(size=n - 1) * 1e-3
+    e[::7] = 0.0
+    for dd, ee in [(d, e), (np.abs(np.arange(-(n // 2), n - n // 2)).astype(float), np.ones(n - 1))]:
+        lam, Z, info = run_stedc(L, dd, ee)
+        assert info == 0
+        T = tridiag(dd, ee)
+        w, _, _ = O.jacobi(T)
+        scale = max(1.0, np.abs(w).max())
+        assert np.abs(lam - w).max() < 1e-12 * scale * 10
+        assert np.abs(Z.T @ Z - np.eye(n)).max() < 1e-12
+        assert np.abs(T @ Z - Z * lam).max() < 1e-12 * scale * 10
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 33, 100, 130])
+@pytest.mark.parametrize("cplx", [False, True])
+def test_hetrd_similarity(L, n, cplx):
+    """A = Q T Q^H: eig(T) = eig(A) (oracle), Q unitary, Q T Q^H reproduces A."""
+    announce("hetrd", n, cplx)
+    rng = np.random.default_rng(n + 7)
+    A = I.random_hermitian(rng, n, cplx)
+    dt = np.complex128 if cplx else np.float64
+    Ad = dev(A.astype(dt))
+    d = torch.zeros(n, dtype=torch.float64, device="cuda")
+    e = torch.zeros(max(n, 1), dtype=torch.float64, device="cuda")
+    X = dev(np.eye(n))
+    Y = torch.zeros((n, n), dtype=torch.complex128 if cplx else torch.float64, device="cuda")
+    st = L.ks_test_hetrd(int(cplx), n, P(Ad), P(d), P(e), P(X), n, P(Y), stream_handle())
+    assert st == 0
+    dh, eh, Q = host(d), host(e)[:n - 1], host(Y)
+    T = tridiag(dh, eh)
+    assert np.abs(Q.conj().T @ Q - np.eye(n)).max() < 1e-12
+    assert np.abs(Q @ T @ Q.conj().T - A).max() < 1e-12 * max(1.0, np.abs(A).max()) * n
+    wT, _, _ = O.jacobi(T)
+    wA, _, _ = O.jacobi(A)
+    assert np.abs(wT - wA).max() < 1e-12 * n
