@@ -129,7 +129,7 @@ def main():
     plan.check("warm steps")
 
     # cheap property checks of the last solve
-    tr = float(torch.einsum("ij,ji->", rho, S.to(rho.dtype)).real.item())
+    tr = float((rho * S.to(rho.dtype).T).sum().real.item())
     m_occ = int((occ > 2e-15 * p.g).sum().item())
     flops = nominal_flops(p.order, p.order, m_occ, cplx, p.n)
     hemv_avg_us = 1e3 * prof.hemv_ms / max(1, prof.hemv_launches)

@@ -21,6 +21,7 @@ struct ks_plan {
     char* base = nullptr;      // the one workspace allocation
     size_t bytes = 0;
     void* L = nullptr;         // batch x n x n cached Cholesky factors
+    void* Li = nullptr;        // batch x n x n their inverses
     void* A = nullptr;         // order x order
     void* W = nullptr;         // order x order (reduction scratch, then reflectors)
     void* tau = nullptr;       // order
@@ -93,6 +94,7 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
     size_t maxm = depth > 0 ? ((size_t)1 << (depth - 1)) : 1;
     Layout L;
     size_t oL = L.take(B * n * n * es);
+    size_t oLi = L.take(B * n * n * es);
     size_t oA = L.take(order * order * es);
     size_t oW = L.take(order * order * es);
     size_t oTau = L.take(order * es);
@@ -106,10 +108,15 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
     size_t oVW = L.take(order * 2 * nb * es), oWV = L.take(order * 2 * nb * es);
     size_t oX = L.take(order * es), oV = L.take(order * es), oY = L.take(order * es), oWw = L.take(order * es);
     size_t np1 = (order + 255) / 256, np3 = (order + 15) / 16;
-    size_t oP1 = L.take(np1 * 8), oPQ = L.take(np3 * 2 * nb * es), oPS = L.take(2 * np1 * 8);
+    size_t oP1 = L.take(np1 * 8), oPQ = L.take((np1 * (1 + 2 * nb) + np3 * 2 * nb) * es);
+    size_t oPS = L.take(2 * (np1 + np3) * 8);
+    size_t ntl = (order + HETRD_TILE - 1) / HETRD_TILE, nchl = (ntl + HETRD_SCH - 1) / HETRD_SCH;
+    size_t oPR = L.take(ntl * nchl * HETRD_TILE * es), oPC = L.take(ntl * ntl * HETRD_TILE * es);
     // back-transform
     size_t oG = L.take(bt * bt * es), oT = L.take(bt * bt * es);
     size_t oW1 = L.take(bt * order * es), oW2 = L.take(bt * order * es);
+    size_t pel = 16 * bt * order;  // up to 16 K-chunks of a BT x order product
+    size_t oSK = L.take(pel * es);
     // divide and conquer
     size_t oDd[10];
     for (int i = 0; i < 10; ++i) oDd[i] = L.take(order * 8);
@@ -125,6 +132,7 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
     if (!p) return total;
     char* b = p->base;
     p->L = b + oL;
+    p->Li = b + oLi;
     p->A = b + oA;
     p->W = b + oW;
     p->tau = b + oTau;
@@ -148,6 +156,8 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
         h.part1 = (double*)(b + oP1);
         h.partPQ = (T*)(b + oPQ);
         h.partS = (double*)(b + oPS);
+        h.prow = (T*)(b + oPR);
+        h.pcol = (T*)(b + oPC);
         h.prof = &p->prof;
     };
     setH(p->hr, (double*)nullptr);
@@ -158,6 +168,8 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
         w.Tf = (T*)(b + oT);
         w.W1 = (T*)(b + oW1);
         w.W2 = (T*)(b + oW2);
+        w.P = (T*)(b + oSK);
+        w.pelems = (long)pel;
     };
     setB(p->br, (double*)nullptr);
     setB(p->bc, (cplx*)nullptr);
@@ -227,10 +239,12 @@ ks_status gevd_impl(ks_plan* p, const T* H, const T* S, double* eps, T* C, int i
     HetrdWork<T>& hw = *reinterpret_cast<HetrdWork<T>*>(is_cplx<T>::value ? (void*)&p->hc : (void*)&p->hr);
     BacktrWork<T>& bw = *reinterpret_cast<BacktrWork<T>*>(is_cplx<T>::value ? (void*)&p->bc : (void*)&p->br);
     Prof& pf = p->prof;
+    T* Li = (T*)p->Li;
     if (!(flags & KS_REUSE_S)) {
         hipEvent_t e = pf.begin();
         herm_complete<T>(s, n, S, lds, (long)n * lds, L, n, (long)n * n, B, p->info);
         potrf<T>(s, n, L, n, (long)n * n, B, p->info);
+        tri_inverse<T>(s, n, L, n, (long)n * n, Li, (long)n * n, B);
         pf.end(KS_PHASE_CHOLESKY, e);
         p->have_L = true;
     }
@@ -238,9 +252,9 @@ ks_status gevd_impl(ks_plan* p, const T* H, const T* S, double* eps, T* C, int i
     for (int b = 0; b < B; ++b) {
         const T* Hb = H + (long)b * order * ldh;
         T* Cb = C + (long)b * order * ldh;
-        const T* Lb = L + (long)b * n * n;
+        const T* Lib = Li + (long)b * n * n;
         hipEvent_t e = pf.begin();
-        reduce_to_standard<T>(s, n, nsp, Hb, ldh, Lb, n, A, W, p->info);
+        reduce_to_standard<T>(s, n, nsp, Hb, ldh, Lib, n, A, W, p->info);
         pf.end(KS_PHASE_REDUCE, e);
         e = pf.begin();
         hetrd<T>(s, order, A, order, p->dv, p->ev, tau, W, hw);
@@ -249,9 +263,11 @@ ks_status gevd_impl(ks_plan* p, const T* H, const T* S, double* eps, T* C, int i
         stedc(s, p->tree, p->dv, p->ev, eps + (long)b * order, p->Z, p->Z2, p->U, p->Qp, p->dc, p->info);
         pf.end(KS_PHASE_DC, e);
         e = pf.begin();
-        load_z<T>(s, order, ncols, p->Z, il - 1, Cb, ldh);
-        backtransform_q<T>(s, order, W, tau, ncols, Cb, ldh, bw);
-        trsm_left<T>(s, true, n, ncols, Lb, n, 0, Cb, ldh, (long)n * ldh, nsp);
+        // X = Q Z[:, il-1 : iu] in A (order x ncols), then C_sigma = Linv^H X_sigma per spin block
+        load_z<T>(s, order, ncols, p->Z, il - 1, A, ncols);
+        backtransform_q<T>(s, order, W, tau, ncols, A, ncols, bw);
+        gemm<T>(s, OP_C, OP_N, n, ncols, n, 1.0, Lib, n, 0, A, ncols, (long)n * ncols, 0.0, Cb, ldh,
+                (long)n * ldh, nsp, nullptr, 0, UPLO_FULL, nullptr, TRI_A_UPPER);
         pf.end(KS_PHASE_BACKTR, e);
     }
     if (hipPeekAtLastError() != hipSuccess) return KS_ERR_HIP;

@@ -20,22 +20,38 @@ __global__ void load_z_kernel(int n, int ncols, const double* Z, int c0, T* X, i
     X[(long)r * ldx + c] = from_re<T>(Z[(long)r * n + c0 + c]);
 }
 
-// T factor of one block: T_jj = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j].
+// W2 = T W1 for the compact-WY factor T of a block of reflectors, without
+// forming T: T^-1 = diag(1/tau) + strictly-upper(G) with G = V^H V, so W2 solves
+// the upper triangular system row by row from the bottom,
+// W2[i] = tau_i (W1[i] - sum_{l > i} G[i][l] W2[l])  (tau_i = 0 gives a zero row,
+// as the identity reflector contributes nothing).  One thread per column of W1;
+// the strict upper triangle of G is staged in LDS.
 template <typename T>
-__global__ __launch_bounds__(256) void tfactor_kernel(int jb, const T* tau, const T* G, T* Tm) {
-    int t = threadIdx.x;
-    for (int e = t; e < jb * jb; e += blockDim.x) Tm[e] = zero_<T>();
+__global__ __launch_bounds__(256) void apply_t_kernel(int jb, int ncols, const T* tau, const T* G,
+                                                      const T* W1, T* W2) {
+    constexpr int B = BACKTR_BT;
+    __shared__ T sg[B * (B - 1) / 2];
+    __shared__ T st[B];
+    for (int e = threadIdx.x; e < jb * jb; e += blockDim.x) {
+        int i = e / jb, l = e % jb;
+        if (l > i) sg[i * (2 * B - i - 1) / 2 + (l - i - 1)] = G[(long)i * jb + l];
+    }
+    if (threadIdx.x < jb) st[threadIdx.x] = tau[threadIdx.x];
     __syncthreads();
-    for (int j = 0; j < jb; ++j) {
-        T tj = tau[j];
-        T acc = zero_<T>();
-        if (t < j) {
-            for (int l = t; l < j; ++l) acc += Tm[(long)t * jb + l] * G[(long)l * jb + j];
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncols) return;
+    T w[B];
+#pragma unroll
+    for (int i = B - 1; i >= 0; --i) {
+        if (i < jb) {
+            T s = W1[(long)i * ncols + c];
+            const T* gi = sg + i * (2 * B - i - 1) / 2;
+#pragma unroll
+            for (int l = i + 1; l < B; ++l)
+                if (l < jb) s -= gi[l - i - 1] * w[l];
+            w[i] = st[i] * s;
+            W2[(long)i * ncols + c] = w[i];
         }
-        __syncthreads();
-        if (t < j) Tm[(long)t * jb + j] = -(tj * acc);
-        if (t == 0) Tm[(long)j * jb + j] = tj;
-        __syncthreads();
     }
 }
 
@@ -52,10 +68,10 @@ void backtransform_q(hipStream_t s, int n, const T* Vall, const T* tau, int ncol
         int m = n - b0 - 1;
         const T* Vb = Vall + (long)(b0 + 1) * n + b0;
         T* Xb = X + (long)(b0 + 1) * ldx;
-        gemm<T>(s, OP_C, OP_N, jb, jb, m, 1.0, Vb, n, 0, Vb, n, 0, 0.0, w.G, jb, 0, 1);
-        hipLaunchKernelGGL((tfactor_kernel<T>), dim3(1), dim3(256), 0, s, jb, tau + b0, w.G, w.Tf);
-        gemm<T>(s, OP_C, OP_N, jb, ncols, m, 1.0, Vb, n, 0, Xb, ldx, 0, 0.0, w.W1, ncols, 0, 1);
-        gemm<T>(s, OP_N, OP_N, jb, ncols, jb, 1.0, w.Tf, jb, 0, w.W1, ncols, 0, 0.0, w.W2, ncols, 0, 1);
+        gemm_splitk<T>(s, OP_C, OP_N, jb, jb, m, 1.0, Vb, n, Vb, n, 0.0, w.G, jb, w.P, w.pelems);
+        gemm_splitk<T>(s, OP_C, OP_N, jb, ncols, m, 1.0, Vb, n, Xb, ldx, 0.0, w.W1, ncols, w.P, w.pelems);
+        hipLaunchKernelGGL((apply_t_kernel<T>), dim3(cdiv(ncols, 256)), dim3(256), 0, s, jb, ncols, tau + b0,
+                           w.G, w.W1, w.W2);
         gemm<T>(s, OP_N, OP_N, m, ncols, jb, -1.0, Vb, n, 0, w.W2, ncols, 0, 1.0, Xb, ldx, 0, 1);
     }
 }

@@ -110,6 +110,10 @@ inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
 enum Op { OP_N = 0, OP_T = 1, OP_C = 2 };
 enum Uplo { UPLO_FULL = 0, UPLO_LOWER = 1 };
+// Known-zero structure of an operand, used to shorten the K loop of a tile:
+// op(A) lower triangular (zero for k > m), op(B) upper triangular (zero for
+// k > n), op(A) upper triangular (zero for k < m).
+enum Tri { TRI_NONE = 0, TRI_A_LOWER = 1, TRI_B_UPPER = 2, TRI_A_UPPER = 3 };
 
 // C = alpha op(A) op(B) (diag kscale between them if given) + beta C,
 // row-major, for `batch` problems with element strides sa, sb, sc.
@@ -117,7 +121,13 @@ template <typename T>
 void gemm(hipStream_t s, Op opa, Op opb, int m, int n, int k, double alpha, const T* A, int lda,
           long sa, const T* B, int ldb, long sb, double beta, T* C, int ldc, long sc, int batch = 1,
           const double* kscale = nullptr, long sk = 0, Uplo uplo = UPLO_FULL,
-          const int* kdev = nullptr);
+          const int* kdev = nullptr, Tri tri = TRI_NONE);
+
+// Same product for small m x n and long K: K is cut into chunks whose partial
+// products go to `work` (room for work_elems elements) and are summed in order.
+template <typename T>
+void gemm_splitk(hipStream_t s, Op opa, Op opb, int m, int n, int k, double alpha, const T* A, int lda,
+                 const T* B, int ldb, double beta, T* C, int ldc, T* work, long work_elems);
 
 // Grouped real GEMM for the divide-and-conquer merges: group g multiplies the
 // (rows_g x kk_g) block of A at (lo_g, lo_g) by the (kk_g x kk_g) block of B at

@@ -13,6 +13,8 @@
 // and receives D[l/16 + 4r][l%16] in accumulator register r.  A complex
 // product uses four real MFMAs (re*re - im*im, re*im + im*re) into separate
 // real and imaginary accumulators.
+#include <algorithm>
+
 #include "ks_common.hpp"
 
 namespace ks {
@@ -178,17 +180,17 @@ __device__ inline cplx acc_get(const Acc<cplx>& a, int i, int j, int r) {
 template <typename T, int OPA, int OPB>
 __device__ inline void gemm_tile(int m, int n, int K, double alpha, const T* A, int lda, const T* B,
                                  int ldb, double beta, T* C, int ldc, const double* kscale, int uplo,
-                                 int m0, int n0) {
+                                 int m0, int n0, int klo = 0) {
     __shared__ T sA[BK][BM + LPAD];
     __shared__ T sB[BK][BN + LPAD];
     Acc<T> acc;
     acc_zero(acc);
     T ra[4], rb[4];
-    if (K > 0) {
-        load_a<T, OPA>(ra, A, lda, m, K, m0, 0, kscale);
-        load_b<T, OPB>(rb, B, ldb, n, K, n0, 0);
+    if (K > klo) {
+        load_a<T, OPA>(ra, A, lda, m, K, m0, klo, kscale);
+        load_b<T, OPB>(rb, B, ldb, n, K, n0, klo);
     }
-    for (int k0 = 0; k0 < K; k0 += BK) {
+    for (int k0 = klo; k0 < K; k0 += BK) {
         __syncthreads();
         store_a<T, OPA>(ra, sA);
         store_b<T, OPB>(rb, sB);
@@ -222,33 +224,38 @@ __global__ __launch_bounds__(256) void gemm_kernel(int m, int n, int K, double a
                                                    int lda, long sa, const T* B, int ldb, long sb,
                                                    double beta, T* C, int ldc, long sc,
                                                    const double* kscale, long sk, int uplo,
-                                                   const int* kdev) {
+                                                   const int* kdev, int tri) {
     int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     if (uplo == UPLO_LOWER && m0 + BM - 1 < n0) return;  // tile strictly above the diagonal
     long b = blockIdx.z;
     if (kdev) K = min(K, *kdev);  // inner size decided on the device (occupied window)
+    // triangular operands: skip the K range where the operand is known to be zero
+    int klo = 0;
+    if (tri == TRI_A_LOWER) K = min(K, m0 + BM);
+    if (tri == TRI_B_UPPER) K = min(K, n0 + BN);
+    if (tri == TRI_A_UPPER) klo = (m0 / BK) * BK;
     gemm_tile<T, OPA, OPB>(m, n, K, alpha, A + b * sa, lda, B + b * sb, ldb, beta, C + b * sc, ldc,
-                           kscale ? kscale + b * sk : nullptr, uplo, m0, n0);
+                           kscale ? kscale + b * sk : nullptr, uplo, m0, n0, klo);
 }
 
 template <typename T, int OPA, int OPB>
 static void launch(hipStream_t s, int m, int n, int k, double alpha, const T* A, int lda, long sa,
                    const T* B, int ldb, long sb, double beta, T* C, int ldc, long sc, int batch,
-                   const double* kscale, long sk, Uplo uplo, const int* kdev) {
+                   const double* kscale, long sk, Uplo uplo, const int* kdev, Tri tri) {
     dim3 grid(cdiv(n, BN), cdiv(m, BM), batch);
     hipLaunchKernelGGL((gemm_kernel<T, OPA, OPB>), grid, dim3(256), 0, s, m, n, k, alpha, A, lda, sa,
-                       B, ldb, sb, beta, C, ldc, sc, kscale, sk, (int)uplo, kdev);
+                       B, ldb, sb, beta, C, ldc, sc, kscale, sk, (int)uplo, kdev, (int)tri);
 }
 
 template <typename T>
 void gemm(hipStream_t s, Op opa, Op opb, int m, int n, int k, double alpha, const T* A, int lda,
           long sa, const T* B, int ldb, long sb, double beta, T* C, int ldc, long sc, int batch,
-          const double* kscale, long sk, Uplo uplo, const int* kdev) {
+          const double* kscale, long sk, Uplo uplo, const int* kdev, Tri tri) {
     if (m <= 0 || n <= 0 || batch <= 0) return;
 #define KS_GEMM_CASE(OA, OB)                                                                      \
     if (opa == OA && opb == OB)                                                                   \
         return launch<T, OA, OB>(s, m, n, k, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, batch, \
-                                 kscale, sk, uplo, kdev);
+                                 kscale, sk, uplo, kdev, tri);
     KS_GEMM_CASE(OP_N, OP_N)
     KS_GEMM_CASE(OP_N, OP_T)
     KS_GEMM_CASE(OP_N, OP_C)
@@ -259,10 +266,71 @@ void gemm(hipStream_t s, Op opa, Op opb, int m, int n, int k, double alpha, cons
 
 template void gemm<double>(hipStream_t, Op, Op, int, int, int, double, const double*, int, long,
                            const double*, int, long, double, double*, int, long, int, const double*,
-                           long, Uplo, const int*);
+                           long, Uplo, const int*, Tri);
 template void gemm<cplx>(hipStream_t, Op, Op, int, int, int, double, const cplx*, int, long,
                          const cplx*, int, long, double, cplx*, int, long, int, const double*, long,
-                         Uplo, const int*);
+                         Uplo, const int*, Tri);
+
+// ---------------------------------------------------------------- split K
+// Partial products over K chunks: P[z] = op(A)[:, Kz] op(B)[Kz, :] for chunk z.
+template <typename T, int OPA, int OPB>
+__global__ __launch_bounds__(256) void gemm_splitk_kernel(int m, int n, int K, int kc, const T* A, int lda,
+                                                          const T* B, int ldb, T* P) {
+    int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN, z = blockIdx.z;
+    int k0 = z * kc;
+    int kz = min(kc, K - k0);
+    const T* Az = (OPA == OP_N) ? A + k0 : A + (long)k0 * lda;
+    const T* Bz = (OPB == OP_N) ? B + (long)k0 * ldb : B + k0;
+    gemm_tile<T, OPA, OPB>(m, n, kz, 1.0, Az, lda, Bz, ldb, 0.0, P + (long)z * m * n, n, nullptr, UPLO_FULL,
+                           m0, n0);
+}
+
+// C = alpha sum_z P[z] + beta C, summed in chunk order (deterministic).
+template <typename T>
+__global__ void splitk_reduce_kernel(int m, int n, int nz, const T* P, double alpha, double beta, T* C,
+                                     int ldc) {
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)m * n) return;
+    int i = (int)(e / n), j = (int)(e % n);
+    T s = zero_<T>();
+    for (int z = 0; z < nz; ++z) s += P[(long)z * m * n + e];
+    T v = alpha * s;
+    T* pc = C + (long)i * ldc + j;
+    if (beta != 0.0) v += beta * (*pc);
+    *pc = v;
+}
+
+template <typename T>
+void gemm_splitk(hipStream_t s, Op opa, Op opb, int m, int n, int k, double alpha, const T* A, int lda,
+                 const T* B, int ldb, double beta, T* C, int ldc, T* work, long work_elems) {
+    if (m <= 0 || n <= 0) return;
+    long tiles = (long)cdiv(m, BM) * cdiv(n, BN);
+    int nz = (int)std::max<long>(1, std::min<long>(cdiv(1024, tiles), cdiv(k, 256)));
+    while (nz > 1 && (long)nz * m * n > work_elems) --nz;
+    int kc = ((cdiv(k, nz) + BK - 1) / BK) * BK;
+    nz = cdiv(k, kc);
+    if (nz <= 1 || k <= 0) {
+        gemm<T>(s, opa, opb, m, n, k, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1);
+        return;
+    }
+    dim3 grid(cdiv(n, BN), cdiv(m, BM), nz);
+#define KS_SK_CASE(OA, OB)                                                                            \
+    if (opa == OA && opb == OB)                                                                      \
+        hipLaunchKernelGGL((gemm_splitk_kernel<T, OA, OB>), grid, dim3(256), 0, s, m, n, k, kc, A, lda, B, \
+                           ldb, work);
+    KS_SK_CASE(OP_N, OP_N)
+    KS_SK_CASE(OP_C, OP_N)
+    KS_SK_CASE(OP_T, OP_N)
+#undef KS_SK_CASE
+    long tot = (long)m * n;
+    hipLaunchKernelGGL((splitk_reduce_kernel<T>), dim3(cdiv(tot, 256)), dim3(256), 0, s, m, n, nz, work, alpha,
+                       beta, C, ldc);
+}
+
+template void gemm_splitk<double>(hipStream_t, Op, Op, int, int, int, double, const double*, int, const double*,
+                                  int, double, double*, int, double*, long);
+template void gemm_splitk<cplx>(hipStream_t, Op, Op, int, int, int, double, const cplx*, int, const cplx*, int,
+                                double, cplx*, int, cplx*, long);
 
 // ---------------------------------------------------------------- grouped
 __global__ __launch_bounds__(256) void gemm_grouped_dc_kernel(const int* lo, const int* hi,

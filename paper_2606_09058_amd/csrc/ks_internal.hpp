@@ -12,6 +12,8 @@ namespace ks {
 template <> __host__ __device__ inline int zero_<int>() { return 0; }
 
 constexpr int HETRD_NB = 32;   // panel width of the tridiagonalisation
+constexpr int HETRD_TILE = 64; // tile edge of the trailing symmetric product
+constexpr int HETRD_SCH = 4;   // tiles per workgroup of the trailing symmetric product
 constexpr int BACKTR_BT = 64;  // reflectors per compact-WY block of the back-transform
 constexpr int DC_LEAF = 32;    // largest divide-and-conquer leaf
 constexpr int MAX_KW = 64;     // k-point weights passed by value
@@ -66,23 +68,27 @@ constexpr int PROF_HEMV = 100;  // tag of the sampled kernel
 template <typename T>
 struct HetrdWork {
     Prof* prof = nullptr;
-    T* VW;          // n x 2NB   [V | W] of the current panel
-    T* WV;          // n x 2NB   [W | V]
+    T* VW;          // 2NB x n   V then W of the current panel, transposed
+    T* WV;          // 2NB x n   conj(W) then conj(V), transposed
     T* x;           // n         updated column
-    T* v;           // n         reflector
-    T* y;           // n         trailing product
+    T* v;           // n         (spare)
+    T* y;           // n         (spare)
     T* w;           // n         W column before its final correction
     double* part1;  // cdiv(n, 256)
-    T* partPQ;      // cdiv(n, 16) x 2NB
-    double* partS;  // 2 cdiv(n, 256)
+    T* partPQ;      // cdiv(n, 256) x (1 + 2NB) partial |x|^2, W^H x, V^H x
+    double* partS;  // 2 cdiv(n, 16) partial w^H v
+    T* prow;        // nt x cdiv(nt, HETRD_SCH) x HETRD_TILE, nt = cdiv(n, HETRD_TILE): row partials
+    T* pcol;        // nt x nt x HETRD_TILE                                           column partials
 };
 
 template <typename T>
 struct BacktrWork {
-    T* G;   // BT x BT
-    T* Tf;  // BT x BT
-    T* W1;  // BT x n
-    T* W2;  // BT x n
+    T* G;         // BT x BT
+    T* Tf;        // BT x BT (spare)
+    T* W1;        // BT x n
+    T* W2;        // BT x n
+    T* P;         // split-K partial products
+    long pelems;  // capacity of P in elements
 };
 
 // Divide-and-conquer scratch; all position-indexed arrays have n entries and
@@ -136,8 +142,11 @@ void herm_complete(hipStream_t s, int n, const T* src, int lds, long ss, T* dst,
                    int batch, int* info);
 
 template <typename T>
-void reduce_to_standard(hipStream_t s, int n, int nsp, const T* H, int ldh, const T* L, int ldl, T* A,
+void reduce_to_standard(hipStream_t s, int n, int nsp, const T* H, int ldh, const T* Linv, int ldi, T* A,
                         T* W, int* info);
+
+template <typename T>
+void tri_inverse(hipStream_t s, int n, const T* L, int ldl, long sl, T* Linv, long si, int batch);
 
 template <typename T>
 void hetrd(hipStream_t s, int n, T* A, int lda, double* d, double* e, T* tau, T* Vall,

@@ -4,9 +4,11 @@
 // Cholesky and the triangular solves are recursive: the diagonal 32 x 32
 // blocks are factored/solved by LDS-resident single-workgroup kernels and
 // everything else is an MFMA GEMM (ks_gemm.hip), so the O(n^3) work runs on
-// the matrix cores.  The spinor form applies L to each spin block, i.e.
-// (I2 (x) L)^-1 H (I2 (x) L)^-H, by treating the 2n x 2n matrix as two n-row
-// blocks (batch 2 with a stride of n rows).
+// the matrix cores.  The inverse factor L^-1 is formed once per overlap (and
+// cached with L), so the reduction and the final back-substitution of every
+// solve are plain triangular-aware GEMMs.  The spinor form applies L^-1 to each
+// spin block, i.e. (I2 (x) L)^-1 H (I2 (x) L)^-H, by treating the 2n x 2n
+// matrix as two n-row (then n-column) blocks: a batch of 2 with a block stride.
 #include "ks_internal.hpp"
 
 namespace ks {
@@ -283,22 +285,39 @@ __global__ __launch_bounds__(256) void hermitize_kernel(int n, T* A, int lda) {
     *b = conj_(v);
 }
 
-// Reduction of H to A = (I (x) L)^-1 H (I (x) L)^-H, A full Hermitian.
-// nsp spin blocks of n rows each; order = nsp * n.  W is order x order scratch.
+// Explicit inverse of the lower triangular factor, Linv = L^-1 (solve L X = I);
+// the upper triangle of Linv comes out exactly zero.
 template <typename T>
-void reduce_to_standard(hipStream_t s, int n, int nsp, const T* H, int ldh, const T* L, int ldl,
+__global__ void set_identity_kernel(int n, T* X, long sx) {
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    X += blockIdx.y * sx;
+    if (e >= (long)n * n) return;
+    int i = (int)(e / n), j = (int)(e % n);
+    X[e] = (i == j) ? from_re<T>(1.0) : zero_<T>();
+}
+
+template <typename T>
+void tri_inverse(hipStream_t s, int n, const T* L, int ldl, long sl, T* Linv, long si, int batch) {
+    long tot = (long)n * n;
+    hipLaunchKernelGGL((set_identity_kernel<T>), dim3(cdiv(tot, 256), batch), dim3(256), 0, s, n, Linv, si);
+    trsm_left<T>(s, false, n, n, L, ldl, sl, Linv, n, si, batch);
+}
+
+// Reduction of H to A = (I (x) L)^-1 H (I (x) L)^-H with the explicit inverse:
+// two MFMA GEMMs whose triangular operand lets each tile skip the zero half of
+// its K range (~order^3 flops together for real input).  nsp spin blocks of n
+// rows; order = nsp * n.  Only the lower triangle of A is used afterwards.
+template <typename T>
+void reduce_to_standard(hipStream_t s, int n, int nsp, const T* H, int ldh, const T* Linv, int ldi,
                         T* A, T* W, int* info) {
     int order = n * nsp;
-    herm_complete<T>(s, order, H, ldh, 0, W, order, 0, 1, info);
-    // W <- (I (x) L)^-1 W : each spin row-block solved with L
-    trsm_left<T>(s, false, n, order, L, ldl, 0, W, order, (long)n * order, nsp);
-    // A <- W^H = H (I (x) L)^-H
-    dim3 grid(cdiv(order, 32), cdiv(order, 32));
-    hipLaunchKernelGGL((conj_transpose_kernel<T>), grid, dim3(256), 0, s, order, order, W, order, A,
-                       order);
-    trsm_left<T>(s, false, n, order, L, ldl, 0, A, order, (long)n * order, nsp);
-    long tot = (long)order * order;
-    hipLaunchKernelGGL((hermitize_kernel<T>), dim3(cdiv(tot, 256)), dim3(256), 0, s, order, A, order);
+    herm_complete<T>(s, order, H, ldh, 0, A, order, 0, 1, info);
+    // W = (I (x) Linv) A : spin row-block b of W is Linv times row-block b of A
+    gemm<T>(s, OP_N, OP_N, n, order, n, 1.0, Linv, ldi, 0, A, order, (long)n * order, 0.0, W, order,
+            (long)n * order, nsp, nullptr, 0, UPLO_FULL, nullptr, TRI_A_LOWER);
+    // A = W (I (x) Linv)^H : spin column-block b of A is column-block b of W times Linv^H
+    gemm<T>(s, OP_N, OP_C, order, n, n, 1.0, W, order, n, Linv, ldi, 0, 0.0, A, order, n, nsp, nullptr, 0,
+            UPLO_FULL, nullptr, TRI_B_UPPER);
 }
 
 #define KS_INST(T)                                                                                 \
@@ -306,7 +325,8 @@ void reduce_to_standard(hipStream_t s, int n, int nsp, const T* H, int ldh, cons
     template void trsm_left<T>(hipStream_t, bool, int, int, const T*, int, long, T*, int, long, int); \
     template void herm_complete<T>(hipStream_t, int, const T*, int, long, T*, int, long, int, int*); \
     template void reduce_to_standard<T>(hipStream_t, int, int, const T*, int, const T*, int, T*, T*, \
-                                        int*);
+                                        int*);                                                      \
+    template void tri_inverse<T>(hipStream_t, int, const T*, int, long, T*, long, int);
 KS_INST(double)
 KS_INST(cplx)
 #undef KS_INST

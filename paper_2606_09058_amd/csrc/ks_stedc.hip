@@ -27,17 +27,26 @@ namespace ks {
 constexpr double DEPS = 1.1102230246251565e-16;  // unit roundoff 2^-53
 
 // ---------------------------------------------------------------- setup
-__global__ void dc_init_kernel(int n, const double* d, const double* e, const int* mids, int nmid,
-                               double* dw) {
-    // single thread: the tears modify neighbouring diagonal entries
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    for (int i = 0; i < n; ++i) dw[i] = d[i];
-    for (int q = 0; q < nmid; ++q) {
-        int m = mids[q];
-        double b = fabs(e[m - 1]);
-        dw[m - 1] -= b;
-        dw[m] -= b;
+// dw = d with |e[m-1]| taken off both neighbours of every tear m; the tears are
+// exactly the leaf starts > 0 (sorted), so each entry looks itself up.
+__device__ inline bool is_leaf_start(const int* leaf_lo, int nleaf, int i) {
+    int a = 0, b = nleaf;
+    while (a < b) {
+        int h = (a + b) >> 1;
+        if (leaf_lo[h] < i) a = h + 1;
+        else b = h;
     }
+    return a < nleaf && leaf_lo[a] == i;
+}
+
+__global__ void dc_init_kernel(int n, const double* d, const double* e, const int* leaf_lo, int nleaf,
+                               double* dw) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double v = d[i];
+    if (i > 0 && is_leaf_start(leaf_lo, nleaf, i)) v -= fabs(e[i - 1]);
+    if (i + 1 < n && is_leaf_start(leaf_lo, nleaf, i + 1)) v -= fabs(e[i]);
+    dw[i] = v;
 }
 
 // ---------------------------------------------------------------- leaves
@@ -539,7 +548,7 @@ void stedc(hipStream_t s, const DcTree& tr, const double* d, const double* e, do
            double* Z2, double* U, double* Qp, DcWork& w, int* info) {
     int n = tr.n;
     fill_zero<double>(s, Z, (long)n * n);
-    hipLaunchKernelGGL(dc_init_kernel, dim3(1), dim3(1), 0, s, n, d, e, tr.d_mid_all, tr.nmerge_total, w.dw);
+    hipLaunchKernelGGL(dc_init_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, n, d, e, tr.d_leaf_lo, tr.nleaf, w.dw);
     hipLaunchKernelGGL(dc_leaf_kernel, dim3(tr.nleaf), dim3(64), 0, s, n, tr.d_leaf_lo, tr.d_leaf_hi,
                        (const double*)w.dw, e, lam, Z, info);
     for (int l = tr.depth - 1; l >= 0; --l) {

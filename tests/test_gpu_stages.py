@@ -199,7 +199,7 @@ def test_stedc_exact_deflation_and_clusters(L):
         assert np.abs(T @ Z - Z * lam).max() < 1e-12 * scale * 10
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 33, 100, 130])
+@pytest.mark.parametrize("n", [1, 2, 3, 33, 100, 130, 333, 600])
 @pytest.mark.parametrize("cplx", [False, True])
 def test_hetrd_similarity(L, n, cplx):
     """A = Q T Q^H: eig(T) = eig(A) (oracle), Q unitary, Q T Q^H reproduces A."""
