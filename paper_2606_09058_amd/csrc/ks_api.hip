@@ -112,6 +112,7 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
     size_t oPS = L.take(2 * (np1 + np3) * 8);
     size_t ntl = (order + HETRD_TILE - 1) / HETRD_TILE, nchl = (ntl + HETRD_SCH - 1) / HETRD_SCH;
     size_t oPR = L.take(ntl * nchl * HETRD_TILE * es), oPC = L.take(ntl * ntl * HETRD_TILE * es);
+    size_t oPQv = L.take((2 + 2 * nb) * es);
     // back-transform
     size_t oG = L.take(bt * bt * es), oT = L.take(bt * bt * es);
     size_t oW1 = L.take(bt * order * es), oW2 = L.take(bt * order * es);
@@ -158,6 +159,7 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
         h.partS = (double*)(b + oPS);
         h.prow = (T*)(b + oPR);
         h.pcol = (T*)(b + oPC);
+        h.pq = (T*)(b + oPQv);
         h.prof = &p->prof;
     };
     setH(p->hr, (double*)nullptr);

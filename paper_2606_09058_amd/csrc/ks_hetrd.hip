@@ -144,33 +144,18 @@ __global__ __launch_bounds__(64) void colupd_kernel(int n, int k, int j, int nb,
 }
 
 // Reflector scalars from the per-workgroup partials of colupd (every workgroup
-// reduces them in the same order, so all see identical values).  Fills
-// tmp[0] = |x_{k+2..}|^2, tmp[1+i] = (W^H x)_i, tmp[1+j+i] = (V^H x)_i, and
-// returns s = 1/(alpha - beta) and tau; block (0,0) stores d[k], e[k], tau[k].
+// reduces them in the same order, so all see identical values).  Only the
+// norm |x_{k+2..}|^2 is reduced here; sh[0] = s = 1/(alpha - beta), sh[1] = tau,
+// and the writer stores d[k], e[k], tau[k].
 template <typename T>
-__device__ inline void reflector_scalars(int k, int j, int nb, const T* x, const T* partA, int nA,
-                                         T* tmp, T* sh, double* d, double* e, T* taua, bool writer) {
-    __shared__ T part4[4][64];
-    int t = threadIdx.x, lane = t & 63, g = t >> 6;
+__device__ inline void reflector_scalars(int k, int nb, const T* x, const T* partA, int nA, T* sh,
+                                         double* d, double* e, T* taua, bool writer, double* red) {
+    int t = threadIdx.x;
     const int ld = 1 + 2 * nb;
-    const int nv = 1 + 2 * j;
-    // 4 groups of workgroups x up to 64 quantities; two independent chains each
-    if (lane < nv) {
-        int idx = (lane == 0) ? 0 : (lane <= j ? lane : 1 + nb + (lane - 1 - j));
-        T a0 = zero_<T>(), a1 = zero_<T>();
-        int b = g;
-        for (; b + 4 < nA; b += 8) {
-            a0 += partA[(long)b * ld + idx];
-            a1 += partA[(long)(b + 4) * ld + idx];
-        }
-        if (b < nA) a0 += partA[(long)b * ld + idx];
-        part4[g][lane] = a0 + a1;
-    }
-    __syncthreads();
-    if (t < nv) tmp[t] = (part4[0][t] + part4[1][t]) + (part4[2][t] + part4[3][t]);
-    __syncthreads();
+    double a = 0.0;
+    for (int b = t; b < nA; b += blockDim.x) a += re_(partA[(long)b * ld]);
+    double xn2 = block_sum(a, red);
     if (t == 0) {
-        double xn2 = re_(tmp[0]);
         T alpha = x[k + 1];
         double ar = re_(alpha), ai = im_(alpha);
         T tv, sc;
@@ -195,6 +180,39 @@ __device__ inline void reflector_scalars(int k, int j, int nb, const T* x, const
     __syncthreads();
 }
 
+// The panel corrections p = W^H v and q = V^H v (v_{k+1} = 1, v = s x beyond),
+// reduced once per column by one workgroup and stored with s and tau in pq:
+// pq[0] = s, pq[1] = tau, pq[2 + i] = p_i, pq[2 + nb + i] = q_i.
+template <typename T>
+__device__ inline void panel_corrections(int n, int k, int j, int nb, const T* partA, int nA, const T* VWt,
+                                         T sc, T tv, T* pq) {
+    __shared__ T part4[4][64];
+    int t = threadIdx.x, lane = t & 63, g = t >> 6;
+    const int ld = 1 + 2 * nb;
+    const int nv = 2 * j;
+    if (lane < nv) {
+        int idx = lane < j ? 1 + lane : 1 + nb + (lane - j);
+        T a0 = zero_<T>(), a1 = zero_<T>();
+        int b = g;
+        for (; b + 4 < nA; b += 8) {
+            a0 += partA[(long)b * ld + idx];
+            a1 += partA[(long)(b + 4) * ld + idx];
+        }
+        if (b < nA) a0 += partA[(long)b * ld + idx];
+        part4[g][lane] = a0 + a1;
+    }
+    __syncthreads();
+    if (t < nv) {
+        T P = (part4[0][t] + part4[1][t]) + (part4[2][t] + part4[3][t]);
+        if (t < j) pq[2 + t] = conj_(VWt[(long)(nb + t) * n + k + 1]) + sc * P;
+        else pq[2 + nb + (t - j)] = conj_(VWt[(long)(t - j) * n + k + 1]) + sc * P;
+    }
+    if (t == 0) {
+        pq[0] = sc;
+        pq[1] = tv;
+    }
+}
+
 // Trailing Hermitian matrix-vector product y = A_trail v from the LOWER
 // triangle only.  The trailing matrix (rows/cols k+1 .. n-1) is cut into
 // 64 x 64 tiles; workgroup (c, I) takes tiles J = 8c .. 8c+7 (J <= I) of tile
@@ -213,15 +231,15 @@ template <typename T>
 __global__ __launch_bounds__(256) void symv_tiles_kernel(int n, int k, int j, int nb, const T* A, int lda,
                                                          const T* x, const T* partA, int nA, T* prow,
                                                          T* pcol, int nt, int nch, double* d, double* e,
-                                                         T* taua) {
+                                                         T* taua, const T* VWt, T* pq) {
     constexpr int SH = Stage<T>::rows;
     constexpr int NSTG = ST / SH;
     __shared__ T tile[SH][ST + 1];
     __shared__ T vI[ST], vJ[2][ST];
     __shared__ T racc[ST];
     __shared__ T red[8][ST];
-    __shared__ T tmp[1 + 2 * 64];
     __shared__ T sh[2];
+    __shared__ double redd[4];
     int c = blockIdx.x, I = blockIdx.y;
     int J0 = c * SCH;
     if (J0 > I) return;
@@ -246,8 +264,9 @@ __global__ __launch_bounds__(256) void symv_tiles_kernel(int n, int k, int j, in
         }
     };
     load_stage(0);
-    reflector_scalars<T>(k, j, nb, x, partA, nA, tmp, sh, d, e, taua, c == 0 && I == 0);
+    reflector_scalars<T>(k, nb, x, partA, nA, sh, d, e, taua, c == 0 && I == 0, redd);
     T sc = sh[0];
+    if (c == 0 && I == 0) panel_corrections<T>(n, k, j, nb, partA, nA, VWt, sc, sh[1], pq);
     auto vof = [&](int g) -> T {
         if (g >= n) return zero_<T>();
         return (g == o) ? from_re<T>(1.0) : sc * x[g];
@@ -315,21 +334,17 @@ __global__ __launch_bounds__(256) void symv_tiles_kernel(int n, int k, int j, in
 // threads per row share the partial sums and the correction terms.
 constexpr int WC_ROWS = 64;
 template <typename T>
-__global__ __launch_bounds__(256) void wcorrect_kernel(int n, int k, int j, int nb, const T* x, const T* partA,
-                                                       int nA, const T* prow, const T* pcol, int nt, int nch,
-                                                       T* VWt, T* WVc, T* wraw, double* partS, double* d,
-                                                       double* e, T* taua) {
-    __shared__ T tmp[1 + 2 * 64];
-    __shared__ T sh[2];
+__global__ __launch_bounds__(256) void wcorrect_kernel(int n, int k, int j, int nb, const T* x, const T* pq,
+                                                       const T* prow, const T* pcol, int nt, int nch,
+                                                       T* VWt, T* WVc, T* wraw, double* partS) {
     __shared__ T sp[64], sq[64];
     __shared__ T part[4][WC_ROWS];
     __shared__ double red[4];
     int t = threadIdx.x, lr = t & 63, pp = t >> 6;
-    reflector_scalars<T>(k, j, nb, x, partA, nA, tmp, sh, d, e, taua, false);
-    T sc = sh[0], tv = sh[1];
+    T sc = pq[0], tv = pq[1];
     if (t < j) {
-        sp[t] = conj_(VWt[(long)(nb + t) * n + k + 1]) + sc * tmp[1 + t];
-        sq[t] = conj_(VWt[(long)t * n + k + 1]) + sc * tmp[1 + j + t];
+        sp[t] = pq[2 + t];
+        sq[t] = pq[2 + nb + t];
     }
     __syncthreads();
     int r = k + 1 + blockIdx.x * WC_ROWS + lr;
@@ -417,12 +432,12 @@ void hetrd(hipStream_t s, int n, T* A, int lda, double* d, double* e, T* tau, T*
             bool smp = w.prof && w.prof->sample();
             hipEvent_t e0 = smp ? w.prof->begin() : nullptr;
             hipLaunchKernelGGL((symv_tiles_kernel<T>), dim3(nch, nt), dim3(256), 0, s, n, k, j, nb, A, lda,
-                               w.x, w.partPQ, nb1, w.prow, w.pcol, nt, nch, d, e, tau);
+                               w.x, w.partPQ, nb1, w.prow, w.pcol, nt, nch, d, e, tau, VWt, w.pq);
             // algorithmic bytes of a Hermitian matrix-vector product: the lower triangle once
             if (smp) w.prof->end(PROF_HEMV, e0, (double)sizeof(T) * m * (m + 1) / 2.0);
             int nb4 = cdiv(m, WC_ROWS);
-            hipLaunchKernelGGL((wcorrect_kernel<T>), dim3(nb4), dim3(256), 0, s, n, k, j, nb, w.x, w.partPQ,
-                               nb1, w.prow, w.pcol, nt, nch, VWt, WVc, w.w, w.partS, d, e, tau);
+            hipLaunchKernelGGL((wcorrect_kernel<T>), dim3(nb4), dim3(256), 0, s, n, k, j, nb, w.x, w.pq,
+                               w.prow, w.pcol, nt, nch, VWt, WVc, w.w, w.partS);
             nS = nb4;
         }
         int kl = k0 + jb - 1;

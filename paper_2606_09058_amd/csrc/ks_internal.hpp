@@ -79,6 +79,7 @@ struct HetrdWork {
     double* partS;  // 2 cdiv(n, 16) partial w^H v
     T* prow;        // nt x cdiv(nt, HETRD_SCH) x HETRD_TILE, nt = cdiv(n, HETRD_TILE): row partials
     T* pcol;        // nt x nt x HETRD_TILE                                           column partials
+    T* pq;          // 2 + 2 NB: s, tau, W^H v, V^H v of the current column
 };
 
 template <typename T>
