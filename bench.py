@@ -158,7 +158,7 @@ def main():
         "warm_s_per_solve": ms_warm / 1e3,
         "wall_s_timed": wall,
         "phases_ms": phases,
-        "roofline": {"bound": "hbm", "kernel": "hemv_kernel (trailing Hermitian matrix-vector "
+        "roofline": {"bound": "hbm", "kernel": "symv_kernel (trailing Hermitian matrix-vector "
                                                "product of the tridiagonalisation)",
                      "achieved": hemv_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": hemv_gbs / PEAK_HBM_GBS, "traffic": None,

@@ -70,14 +70,21 @@ typedef enum {
 enum { KS_REAL64 = 0, KS_COMPLEX128 = 1 };           /* element type of H, S, C, rho */
 enum { KS_COLLINEAR = 0, KS_NONCOLLINEAR = 1 };      /* spin form                    */
 enum { KS_FP64 = 0, KS_MIXED = 1 };                  /* arithmetic of the solve      */
-enum { KS_PLAN_GRAPH = 1u };                         /* plan flags                   */
+/* Plan flags.  KS_PLAN_GRAPH: ks_gevd captures its launch sequence from the
+ * plan stream into a HIP graph the first time it sees an argument set (H, S,
+ * eps, C, il, iu, flags) and replays the graph while the same set repeats; a
+ * different set is captured afresh.  Needs a non-NULL stream.  The batched
+ * launches (all k-points of the plan in each kernel) are the same either way,
+ * so results do not depend on the flag. */
+enum { KS_PLAN_GRAPH = 1u };
 enum { KS_REUSE_S = 1u };                            /* ks_gevd flags                */
 
 typedef struct ks_plan ks_plan; /* opaque: workspace, cached Cholesky factor, info */
 
 typedef struct {
     int32_t n;          /* orbitals per spin block; order = n (collinear) or 2n   */
-    int32_t batch;      /* k-points solved together (>= 1)                         */
+    int32_t batch;      /* k-points solved together (>= 1, <= 64): every kernel of  */
+                        /* the solve takes all of them in one launch               */
     int32_t dtype;      /* KS_REAL64 or KS_COMPLEX128; noncollinear needs complex  */
     int32_t spin;       /* KS_COLLINEAR (g = 2) or KS_NONCOLLINEAR (g = 1)         */
     int32_t precision;  /* KS_FP64 (KS_MIXED is reserved)                          */
@@ -165,6 +172,10 @@ ks_status ks_plan_set_profiling(ks_plan* plan, int32_t enable, int32_t stride);
 /* Synchronize the plan's stream, fill *out with what was recorded since the last
  * read, and clear it. */
 ks_status ks_plan_get_profile(ks_plan* plan, ks_profile* out);
+
+/* Graph use under KS_PLAN_GRAPH: how many argument sets were captured and how
+ * many ks_gevd calls replayed a captured graph.  Host-only. */
+ks_status ks_plan_get_graph_stats(ks_plan* plan, int64_t* captures, int64_t* replays);
 
 /* Synchronize the plan's stream and read its info word: 0 if no device failure
  * was recorded since the last call, else the failing Cholesky column (>0) for

@@ -22,6 +22,7 @@ struct ks_plan {
     size_t bytes = 0;
     void* L = nullptr;         // batch x n x n cached Cholesky factors
     void* Li = nullptr;        // batch x n x n their inverses
+    // per matrix of the batch, consecutive:
     void* A = nullptr;         // order x order
     void* W = nullptr;         // order x order (reduction scratch, then reflectors)
     void* tau = nullptr;       // order
@@ -42,6 +43,24 @@ struct ks_plan {
     DcWork dc;
     DcTree tree;
     bool have_L = false;
+    // KS_PLAN_GRAPH: the launch sequence of the last ks_gevd argument set,
+    // captured from the plan stream once and replayed while the arguments repeat
+    struct GraphKey {
+        const void* H;
+        const void* S;
+        double* eps;
+        void* C;
+        int il, iu;
+        uint32_t flags;
+        bool operator==(const GraphKey& o) const {
+            return H == o.H && S == o.S && eps == o.eps && C == o.C && il == o.il && iu == o.iu &&
+                   flags == o.flags;
+        }
+    };
+    GraphKey gkey{};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    long graph_captures = 0, graph_replays = 0;
     // adjoint scratch, allocated at the first backward call
     char* adj = nullptr;
     void* aW1 = nullptr;
@@ -75,6 +94,7 @@ bool desc_valid(const ks_plan_desc* d) {
 }
 
 ks_status desc_supported(const ks_plan_desc* d) {
+    if ((d->flags & KS_PLAN_GRAPH) && d->stream == nullptr) return KS_ERR_NOT_SUPPORTED;  // no capture there
     if (d->spin == KS_NONCOLLINEAR && d->dtype != KS_COMPLEX128) return KS_ERR_NOT_SUPPORTED;
     if (d->precision != KS_FP64) return KS_ERR_NOT_SUPPORTED;
     if (d->batch > MAX_KW) return KS_ERR_NOT_SUPPORTED;
@@ -95,37 +115,41 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
     Layout L;
     size_t oL = L.take(B * n * n * es);
     size_t oLi = L.take(B * n * n * es);
-    size_t oA = L.take(order * order * es);
-    size_t oW = L.take(order * order * es);
-    size_t oTau = L.take(order * es);
-    size_t oD = L.take(order * 8), oE = L.take(order * 8);
-    size_t oZ = L.take(order * order * 8), oZ2 = L.take(order * order * 8);
-    size_t oU = L.take(order * order * 8), oQp = L.take(order * order * 8);
+    size_t oA = L.take(B * order * order * es);
+    size_t oW = L.take(B * order * order * es);
+    size_t oTau = L.take(B * order * es);
+    size_t oD = L.take(B * order * 8), oE = L.take(B * order * 8);
+    size_t oZ = L.take(B * order * order * 8), oZ2 = L.take(B * order * order * 8);
+    size_t oU = L.take(B * order * order * 8), oQp = L.take(B * order * order * 8);
     size_t oOcc = L.take(B * order * 8);
     size_t oInfo = L.take(2 * sizeof(int));
     size_t oKwin = L.take(sizeof(int));
-    // tridiagonalisation
-    size_t oVW = L.take(order * 2 * nb * es), oWV = L.take(order * 2 * nb * es);
-    size_t oX = L.take(order * es), oV = L.take(order * es), oY = L.take(order * es), oWw = L.take(order * es);
-    size_t np1 = (order + 255) / 256, np3 = (order + 15) / 16;
-    size_t oP1 = L.take(np1 * 8), oPQ = L.take((np1 * (1 + 2 * nb) + np3 * 2 * nb) * es);
-    size_t oPS = L.take(2 * (np1 + np3) * 8);
+    // tridiagonalisation (per matrix of the batch)
     size_t ntl = (order + HETRD_TILE - 1) / HETRD_TILE, nchl = (ntl + HETRD_SCH - 1) / HETRD_SCH;
-    size_t oPR = L.take(ntl * nchl * HETRD_TILE * es), oPC = L.take(ntl * ntl * HETRD_TILE * es);
-    size_t oPQv = L.take((2 + 2 * nb) * es);
+    size_t hVW = order * 2 * nb, hX = order, hPQ = ntl * (1 + 2 * nb), hPR = ntl * nchl * HETRD_TILE;
+    size_t hPC = ntl * ntl * HETRD_TILE, hPV = ntl * nchl, hPQv = 2 + 2 * nb;
+    size_t oVW = L.take(B * hVW * es), oWV = L.take(B * hVW * es);
+    size_t oX = L.take(B * hX * es);
+    size_t oPQ = L.take(B * hPQ * es);
+    size_t oPR = L.take(B * hPR * es), oPC = L.take(B * hPC * es);
+    size_t oPV = L.take(B * hPV * 8);
+    size_t oPQv = L.take(B * hPQv * es);
     // back-transform
-    size_t oG = L.take(bt * bt * es), oT = L.take(bt * bt * es);
-    size_t oW1 = L.take(bt * order * es), oW2 = L.take(bt * order * es);
-    size_t pel = 16 * bt * order;  // up to 16 K-chunks of a BT x order product
+    size_t oG = L.take(B * bt * bt * es), oT = L.take(bt * bt * es);
+    size_t oW1 = L.take(B * bt * order * es), oW2 = L.take(B * bt * order * es);
+    // split-K partial products of a BT x order product: as many K-chunks as the
+    // GEMM cuts K = order into (at most max(16, order / 256)), for every matrix
+    size_t pel = std::max<size_t>(16, (order + 255) / 256) * bt * order * B;
     size_t oSK = L.take(pel * es);
-    // divide and conquer
+    // divide and conquer (per matrix of the batch)
     size_t oDd[10];
-    for (int i = 0; i < 10; ++i) oDd[i] = L.take(order * 8);
-    size_t oRcs = L.take(2 * order * 8);
+    for (int i = 0; i < 10; ++i) oDd[i] = L.take(B * order * 8);
+    size_t oRcs = L.take(B * 2 * order * 8);
     size_t oDi[5];
-    for (int i = 0; i < 5; ++i) oDi[i] = L.take(order * sizeof(int));
-    size_t oRidx = L.take(2 * order * sizeof(int));
-    size_t oKK = L.take(maxm * sizeof(int)), oNR = L.take(maxm * sizeof(int)), oRho = L.take(maxm * 8);
+    for (int i = 0; i < 5; ++i) oDi[i] = L.take(B * order * sizeof(int));
+    size_t oRidx = L.take(B * 2 * order * sizeof(int));
+    size_t oKK = L.take(B * maxm * sizeof(int)), oNR = L.take(B * maxm * sizeof(int));
+    size_t oRho = L.take(B * maxm * 8);
     size_t oT1 = L.take((nm + 1) * sizeof(int)), oT2 = L.take((nm + 1) * sizeof(int));
     size_t oT3 = L.take((nm + 1) * sizeof(int));
     size_t oL1 = L.take(nl * sizeof(int)), oL2 = L.take(nl * sizeof(int));
@@ -151,15 +175,18 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
         h.VW = (T*)(b + oVW);
         h.WV = (T*)(b + oWV);
         h.x = (T*)(b + oX);
-        h.v = (T*)(b + oV);
-        h.y = (T*)(b + oY);
-        h.w = (T*)(b + oWw);
-        h.part1 = (double*)(b + oP1);
         h.partPQ = (T*)(b + oPQ);
-        h.partS = (double*)(b + oPS);
         h.prow = (T*)(b + oPR);
         h.pcol = (T*)(b + oPC);
+        h.pvav = (double*)(b + oPV);
         h.pq = (T*)(b + oPQv);
+        h.sVW = (long)hVW;
+        h.sx = (long)hX;
+        h.spart = (long)hPQ;
+        h.sprow = (long)hPR;
+        h.spcol = (long)hPC;
+        h.spvav = (long)hPV;
+        h.spq = (long)hPQv;
         h.prof = &p->prof;
     };
     setH(p->hr, (double*)nullptr);
@@ -221,6 +248,13 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
 
 bool range_ok(const ks_plan* p, int il, int iu) { return il >= 1 && il <= iu && iu <= p->order; }
 
+void graph_release(ks_plan* p) {
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->gexec = nullptr;
+    p->graph = nullptr;
+}
+
 KWeights make_weights(const ks_plan* p, const double* kw) {
     KWeights w;
     for (int i = 0; i < MAX_KW; ++i) w.w[i] = 0.0;
@@ -250,28 +284,31 @@ ks_status gevd_impl(ks_plan* p, const T* H, const T* S, double* eps, T* C, int i
         pf.end(KS_PHASE_CHOLESKY, e);
         p->have_L = true;
     }
-    int ncols = iu - il + 1;
-    for (int b = 0; b < B; ++b) {
-        const T* Hb = H + (long)b * order * ldh;
-        T* Cb = C + (long)b * order * ldh;
-        const T* Lib = Li + (long)b * n * n;
-        hipEvent_t e = pf.begin();
-        reduce_to_standard<T>(s, n, nsp, Hb, ldh, Lib, n, A, W, p->info);
-        pf.end(KS_PHASE_REDUCE, e);
-        e = pf.begin();
-        hetrd<T>(s, order, A, order, p->dv, p->ev, tau, W, hw);
-        pf.end(KS_PHASE_TRIDIAG, e);
-        e = pf.begin();
-        stedc(s, p->tree, p->dv, p->ev, eps + (long)b * order, p->Z, p->Z2, p->U, p->Qp, p->dc, p->info);
-        pf.end(KS_PHASE_DC, e);
-        e = pf.begin();
-        // X = Q Z[:, il-1 : iu] in A (order x ncols), then C_sigma = Linv^H X_sigma per spin block
-        load_z<T>(s, order, ncols, p->Z, il - 1, A, ncols);
-        backtransform_q<T>(s, order, W, tau, ncols, A, ncols, bw);
-        gemm<T>(s, OP_C, OP_N, n, ncols, n, 1.0, Lib, n, 0, A, ncols, (long)n * ncols, 0.0, Cb, ldh,
-                (long)n * ldh, nsp, nullptr, 0, UPLO_FULL, nullptr, TRI_A_UPPER);
-        pf.end(KS_PHASE_BACKTR, e);
+    // every step below takes the whole batch of k-points in each launch
+    const int ncols = iu - il + 1;
+    const long sA = (long)order * order, sL = (long)n * n, sH = (long)order * ldh;
+    hipEvent_t e = pf.begin();
+    reduce_to_standard<T>(s, n, nsp, B, H, ldh, sH, Li, n, sL, A, W, p->info);
+    pf.end(KS_PHASE_REDUCE, e);
+    e = pf.begin();
+    hetrd<T>(s, order, A, order, sA, B, p->dv, p->ev, tau, W, hw);
+    pf.end(KS_PHASE_TRIDIAG, e);
+    e = pf.begin();
+    stedc(s, p->tree, B, p->dv, p->ev, eps, p->Z, p->Z2, p->U, p->Qp, p->dc, p->info);
+    pf.end(KS_PHASE_DC, e);
+    e = pf.begin();
+    // X = Q Z[:, il-1 : iu] in A (order x ncols per matrix), then C_sigma = Linv^H X_sigma per spin block
+    load_z<T>(s, order, B, ncols, p->Z, il - 1, A, ncols, sA);
+    backtransform_q<T>(s, order, B, W, tau, ncols, A, ncols, sA, bw);
+    if (nsp == 1) {
+        gemm<T>(s, OP_C, OP_N, n, ncols, n, 1.0, Li, n, sL, A, ncols, sA, 0.0, C, ldh, sH, B, nullptr, 0,
+                UPLO_FULL, nullptr, TRI_A_UPPER);
+    } else {
+        for (int b = 0; b < B; ++b)
+            gemm<T>(s, OP_C, OP_N, n, ncols, n, 1.0, Li + b * sL, n, 0, A + b * sA, ncols, (long)n * ncols, 0.0,
+                    C + b * sH, ldh, (long)n * ldh, nsp, nullptr, 0, UPLO_FULL, nullptr, TRI_A_UPPER);
     }
+    pf.end(KS_PHASE_BACKTR, e);
     if (hipPeekAtLastError() != hipSuccess) return KS_ERR_HIP;
     return KS_OK;
 }
@@ -338,9 +375,17 @@ ks_status ks_plan_create(const ks_plan_desc* d, ks_plan** out) {
 void ks_plan_destroy(ks_plan* p) {
     if (!p) return;
     (void)hipStreamSynchronize(p->s);
+    graph_release(p);
     if (p->base) (void)hipFree(p->base);
     if (p->adj) (void)hipFree(p->adj);
     delete p;
+}
+
+ks_status ks_plan_get_graph_stats(ks_plan* p, int64_t* captures, int64_t* replays) {
+    if (!p || !captures || !replays) return KS_ERR_INVALID_ARG;
+    *captures = p->graph_captures;
+    *replays = p->graph_replays;
+    return KS_OK;
 }
 
 ks_status ks_gevd(ks_plan* p, const void* H, const void* S, double* eps, void* C, int32_t il,
@@ -350,9 +395,43 @@ ks_status ks_gevd(ks_plan* p, const void* H, const void* S, double* eps, void* C
     if (!(flags & KS_REUSE_S) && !S) return KS_ERR_INVALID_ARG;
     if ((flags & KS_REUSE_S) && !p->have_L) return KS_ERR_INVALID_ARG;
     if (!range_ok(p, il, iu)) return KS_ERR_INVALID_ARG;
-    if (p->is_c)
-        return gevd_impl<cplx>(p, (const cplx*)H, (const cplx*)S, eps, (cplx*)C, il, iu, flags);
-    return gevd_impl<double>(p, (const double*)H, (const double*)S, eps, (double*)C, il, iu, flags);
+    auto enqueue = [&]() -> ks_status {
+        if (p->is_c)
+            return gevd_impl<cplx>(p, (const cplx*)H, (const cplx*)S, eps, (cplx*)C, il, iu, flags);
+        return gevd_impl<double>(p, (const double*)H, (const double*)S, eps, (double*)C, il, iu, flags);
+    };
+    if (!(p->d.flags & KS_PLAN_GRAPH)) return enqueue();
+    ks_plan::GraphKey key{H, S, eps, C, il, iu, flags};
+    if (!(p->gexec && key == p->gkey)) {
+        graph_release(p);
+        const bool prof = p->prof.on;
+        p->prof.on = false;  // no timing events inside a graph
+        if (hipStreamBeginCapture(p->s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            p->prof.on = prof;
+            return KS_ERR_HIP;
+        }
+        ks_status st = enqueue();
+        hipGraph_t g = nullptr;
+        hipError_t ec = hipStreamEndCapture(p->s, &g);
+        p->prof.on = prof;
+        if (st != KS_OK || ec != hipSuccess || !g) {
+            if (g) (void)hipGraphDestroy(g);
+            return st != KS_OK ? st : KS_ERR_HIP;
+        }
+        hipGraphExec_t ex = nullptr;
+        if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return KS_ERR_HIP;
+        }
+        p->graph = g;
+        p->gexec = ex;
+        p->gkey = key;
+        ++p->graph_captures;
+    } else {
+        ++p->graph_replays;
+    }
+    if (hipGraphLaunch(p->gexec, p->s) != hipSuccess) return KS_ERR_HIP;
+    return KS_OK;
 }
 
 ks_status ks_density(ks_plan* p, const double* eps, const void* C, int32_t il, int32_t iu,
@@ -472,18 +551,19 @@ ks_status ks_plan_get_info(ks_plan* p, int32_t* info) {
 
 // Internal stage drivers used by the test hooks (ks_testhooks.hip).
 void ks_internal_stedc(ks_plan* p, const double* d, const double* e, double* lam, double* Z) {
-    stedc(p->s, p->tree, d, e, lam, Z, p->Z2, p->U, p->Qp, p->dc, p->info);
+    stedc(p->s, p->tree, 1, d, e, lam, Z, p->Z2, p->U, p->Qp, p->dc, p->info);
 }
 
 void ks_internal_hetrd(ks_plan* p, void* A, double* d, double* e, const double* X, int ncols, void* Y) {
     int n = p->order;
+    long sA = (long)n * n;
     if (p->is_c) {
-        hetrd<cplx>(p->s, n, (cplx*)A, n, d, e, (cplx*)p->tau, (cplx*)p->W, p->hc);
-        load_z<cplx>(p->s, n, ncols, X, 0, (cplx*)Y, ncols);
-        backtransform_q<cplx>(p->s, n, (cplx*)p->W, (cplx*)p->tau, ncols, (cplx*)Y, ncols, p->bc);
+        hetrd<cplx>(p->s, n, (cplx*)A, n, sA, 1, d, e, (cplx*)p->tau, (cplx*)p->W, p->hc);
+        load_z<cplx>(p->s, n, 1, ncols, X, 0, (cplx*)Y, ncols, 0);
+        backtransform_q<cplx>(p->s, n, 1, (cplx*)p->W, (cplx*)p->tau, ncols, (cplx*)Y, ncols, 0, p->bc);
     } else {
-        hetrd<double>(p->s, n, (double*)A, n, d, e, (double*)p->tau, (double*)p->W, p->hr);
-        load_z<double>(p->s, n, ncols, X, 0, (double*)Y, ncols);
-        backtransform_q<double>(p->s, n, (double*)p->W, (double*)p->tau, ncols, (double*)Y, ncols, p->br);
+        hetrd<double>(p->s, n, (double*)A, n, sA, 1, d, e, (double*)p->tau, (double*)p->W, p->hr);
+        load_z<double>(p->s, n, 1, ncols, X, 0, (double*)Y, ncols, 0);
+        backtransform_q<double>(p->s, n, 1, (double*)p->W, (double*)p->tau, ncols, (double*)Y, ncols, 0, p->br);
     }
 }

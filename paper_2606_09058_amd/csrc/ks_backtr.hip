@@ -6,14 +6,17 @@
 // Q = H_0 H_1 ... H_{n-2} is applied in blocks of BT reflectors in compact-WY
 // form, H_b ... H_{b+BT-1} = I - V T V^H (T upper triangular, built from
 // G = V^H V and tau), so each block is three MFMA GEMMs:
-// W1 = V^H X, W2 = T W1, X -= V W2.
+// W1 = V^H X, W2 = T W1, X -= V W2.  A batch of matrices of one order shares
+// every launch (GEMM batch index, or blockIdx.y / z selecting the matrix).
 #include "ks_internal.hpp"
 
 namespace ks {
 
 // X (n x ncols, ld ldx, type T) = Z[:, c0 : c0 + ncols] (real).
 template <typename T>
-__global__ void load_z_kernel(int n, int ncols, const double* Z, int c0, T* X, int ldx) {
+__global__ void load_z_kernel(int n, int ncols, const double* Z, int c0, T* X, int ldx, long sX) {
+    Z += (long)blockIdx.y * n * n;
+    X += blockIdx.y * sX;
     long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (long)n * ncols) return;
     int r = (int)(e / ncols), c = (int)(e % ncols);
@@ -27,9 +30,16 @@ __global__ void load_z_kernel(int n, int ncols, const double* Z, int c0, T* X, i
 // as the identity reflector contributes nothing).  One thread per column of W1;
 // the strict upper triangle of G is staged in LDS.
 template <typename T>
-__global__ __launch_bounds__(256) void apply_t_kernel(int jb, int ncols, const T* tau, const T* G,
+__global__ __launch_bounds__(256) void apply_t_kernel(int jb, int ncols, const T* tau, long stau, const T* G,
                                                       const T* W1, T* W2) {
     constexpr int B = BACKTR_BT;
+    {
+        const int b = blockIdx.y;
+        tau += b * stau;
+        G += (long)b * jb * jb;
+        W1 += (long)b * jb * ncols;
+        W2 += (long)b * jb * ncols;
+    }
     __shared__ T sg[B * (B - 1) / 2];
     __shared__ T st[B];
     for (int e = threadIdx.x; e < jb * jb; e += blockDim.x) {
@@ -56,9 +66,11 @@ __global__ __launch_bounds__(256) void apply_t_kernel(int jb, int ncols, const T
 }
 
 template <typename T>
-void backtransform_q(hipStream_t s, int n, const T* Vall, const T* tau, int ncols, T* X, int ldx,
-                     BacktrWork<T>& w) {
+void backtransform_q(hipStream_t s, int n, int batch, const T* Vall, const T* tau, int ncols, T* X, int ldx,
+                     long sX, BacktrWork<T>& w) {
     const int bt = BACKTR_BT;
+    const int B = batch;
+    const long sV = (long)n * n;
     int nref = n - 1;
     if (nref <= 0 || ncols <= 0) return;
     int nblk = cdiv(nref, bt);
@@ -68,18 +80,21 @@ void backtransform_q(hipStream_t s, int n, const T* Vall, const T* tau, int ncol
         int m = n - b0 - 1;
         const T* Vb = Vall + (long)(b0 + 1) * n + b0;
         T* Xb = X + (long)(b0 + 1) * ldx;
-        gemm_splitk<T>(s, OP_C, OP_N, jb, jb, m, 1.0, Vb, n, Vb, n, 0.0, w.G, jb, w.P, w.pelems);
-        gemm_splitk<T>(s, OP_C, OP_N, jb, ncols, m, 1.0, Vb, n, Xb, ldx, 0.0, w.W1, ncols, w.P, w.pelems);
-        hipLaunchKernelGGL((apply_t_kernel<T>), dim3(cdiv(ncols, 256)), dim3(256), 0, s, jb, ncols, tau + b0,
-                           w.G, w.W1, w.W2);
-        gemm<T>(s, OP_N, OP_N, m, ncols, jb, -1.0, Vb, n, 0, w.W2, ncols, 0, 1.0, Xb, ldx, 0, 1);
+        gemm_splitk<T>(s, OP_C, OP_N, jb, jb, m, 1.0, Vb, n, Vb, n, 0.0, w.G, jb, w.P, w.pelems, B, sV, sV,
+                       (long)jb * jb);
+        gemm_splitk<T>(s, OP_C, OP_N, jb, ncols, m, 1.0, Vb, n, Xb, ldx, 0.0, w.W1, ncols, w.P, w.pelems, B, sV,
+                       sX, (long)jb * ncols);
+        hipLaunchKernelGGL((apply_t_kernel<T>), dim3(cdiv(ncols, 256), B), dim3(256), 0, s, jb, ncols, tau + b0,
+                           (long)n, w.G, w.W1, w.W2);
+        gemm<T>(s, OP_N, OP_N, m, ncols, jb, -1.0, Vb, n, sV, w.W2, ncols, (long)jb * ncols, 1.0, Xb, ldx, sX, B);
     }
 }
 
 template <typename T>
-void load_z(hipStream_t s, int n, int ncols, const double* Z, int c0, T* X, int ldx) {
+void load_z(hipStream_t s, int n, int batch, int ncols, const double* Z, int c0, T* X, int ldx, long sX) {
     long tot = (long)n * ncols;
-    hipLaunchKernelGGL((load_z_kernel<T>), dim3(cdiv(tot, 256)), dim3(256), 0, s, n, ncols, Z, c0, X, ldx);
+    hipLaunchKernelGGL((load_z_kernel<T>), dim3(cdiv(tot, 256), batch), dim3(256), 0, s, n, ncols, Z, c0, X, ldx,
+                       sX);
 }
 
 // ---------------------------------------------------------------- Fermi level
@@ -173,9 +188,9 @@ void fermi(hipStream_t s, int batch, int order, const double* eps, const KWeight
 }
 
 #define KS_INST(T)                                                                                 \
-    template void backtransform_q<T>(hipStream_t, int, const T*, const T*, int, T*, int,           \
+    template void backtransform_q<T>(hipStream_t, int, int, const T*, const T*, int, T*, int, long,  \
                                      BacktrWork<T>&);                                             \
-    template void load_z<T>(hipStream_t, int, int, const double*, int, T*, int);
+    template void load_z<T>(hipStream_t, int, int, int, const double*, int, T*, int, long);
 KS_INST(double)
 KS_INST(cplx)
 #undef KS_INST

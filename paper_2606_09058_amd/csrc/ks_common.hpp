@@ -63,6 +63,8 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 __device__ inline cplx wave_sum(cplx v) { return mk(wave_sum(v.x), wave_sum(v.y)); }
+__device__ inline double shfl_xor_(double v, int m) { return __shfl_xor(v, m, WAVE); }
+__device__ inline cplx shfl_xor_(cplx v, int m) { return mk(__shfl_xor(v.x, m, WAVE), __shfl_xor(v.y, m, WAVE)); }
 __device__ inline double wave_prod(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v *= __shfl_xor(v, o, WAVE);
@@ -127,13 +129,16 @@ void gemm(hipStream_t s, Op opa, Op opb, int m, int n, int k, double alpha, cons
 // products go to `work` (room for work_elems elements) and are summed in order.
 template <typename T>
 void gemm_splitk(hipStream_t s, Op opa, Op opb, int m, int n, int k, double alpha, const T* A, int lda,
-                 const T* B, int ldb, double beta, T* C, int ldc, T* work, long work_elems);
+                 const T* B, int ldb, double beta, T* C, int ldc, T* work, long work_elems, int batch = 1,
+                 long sa = 0, long sb = 0, long sc = 0);
 
 // Grouped real GEMM for the divide-and-conquer merges: group g multiplies the
 // (rows_g x kk_g) block of A at (lo_g, lo_g) by the (kk_g x kk_g) block of B at
 // (lo_g, lo_g) into C at (lo_g, lo_g); all with row stride ld.  rows_g = hi_g -
 // lo_g comes from the host bounds, kk_g from device memory (deflation count).
-void gemm_grouped_dc(hipStream_t s, int ngroups, int max_rows, const int* d_lo, const int* d_hi,
+// A batch of matrices (ld x ld, consecutive) shares the launch; matrix b's
+// group g takes K = kk[b * ngroups + g].
+void gemm_grouped_dc(hipStream_t s, int ngroups, int batch, int max_rows, const int* d_lo, const int* d_hi,
                      const int* d_kk, const double* A, const double* B, double* C, int ld);
 
 }  // namespace ks

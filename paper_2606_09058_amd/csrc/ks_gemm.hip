@@ -272,84 +272,93 @@ template void gemm<cplx>(hipStream_t, Op, Op, int, int, int, double, const cplx*
                          Uplo, const int*, Tri);
 
 // ---------------------------------------------------------------- split K
-// Partial products over K chunks: P[z] = op(A)[:, Kz] op(B)[Kz, :] for chunk z.
+// Partial products over K chunks: P[b][z] = op(A_b)[:, Kz] op(B_b)[Kz, :] for
+// chunk z of matrix b of the batch (blockIdx.z = b * nz + z).
 template <typename T, int OPA, int OPB>
-__global__ __launch_bounds__(256) void gemm_splitk_kernel(int m, int n, int K, int kc, const T* A, int lda,
-                                                          const T* B, int ldb, T* P) {
-    int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN, z = blockIdx.z;
+__global__ __launch_bounds__(256) void gemm_splitk_kernel(int m, int n, int K, int kc, int nz, const T* A,
+                                                          int lda, long sa, const T* B, int ldb, long sb, T* P) {
+    int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    int z = blockIdx.z % nz, b = blockIdx.z / nz;
     int k0 = z * kc;
     int kz = min(kc, K - k0);
+    A += b * sa;
+    B += b * sb;
     const T* Az = (OPA == OP_N) ? A + k0 : A + (long)k0 * lda;
     const T* Bz = (OPB == OP_N) ? B + (long)k0 * ldb : B + k0;
-    gemm_tile<T, OPA, OPB>(m, n, kz, 1.0, Az, lda, Bz, ldb, 0.0, P + (long)z * m * n, n, nullptr, UPLO_FULL,
-                           m0, n0);
+    gemm_tile<T, OPA, OPB>(m, n, kz, 1.0, Az, lda, Bz, ldb, 0.0, P + (long)blockIdx.z * m * n, n, nullptr,
+                           UPLO_FULL, m0, n0);
 }
 
-// C = alpha sum_z P[z] + beta C, summed in chunk order (deterministic).
+// C_b = alpha sum_z P[b][z] + beta C_b, summed in chunk order (deterministic).
 template <typename T>
 __global__ void splitk_reduce_kernel(int m, int n, int nz, const T* P, double alpha, double beta, T* C,
-                                     int ldc) {
+                                     int ldc, long sc) {
     long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (long)m * n) return;
+    const int b = blockIdx.y;
+    P += (long)b * nz * m * n;
     int i = (int)(e / n), j = (int)(e % n);
     T s = zero_<T>();
     for (int z = 0; z < nz; ++z) s += P[(long)z * m * n + e];
     T v = alpha * s;
-    T* pc = C + (long)i * ldc + j;
+    T* pc = C + b * sc + (long)i * ldc + j;
     if (beta != 0.0) v += beta * (*pc);
     *pc = v;
 }
 
 template <typename T>
 void gemm_splitk(hipStream_t s, Op opa, Op opb, int m, int n, int k, double alpha, const T* A, int lda,
-                 const T* B, int ldb, double beta, T* C, int ldc, T* work, long work_elems) {
-    if (m <= 0 || n <= 0) return;
+                 const T* B, int ldb, double beta, T* C, int ldc, T* work, long work_elems, int batch, long sa,
+                 long sb, long sc) {
+    if (m <= 0 || n <= 0 || batch <= 0) return;
+    // the chunking depends on one matrix's shape only, so a batched product
+    // rounds exactly like the same product on its own
     long tiles = (long)cdiv(m, BM) * cdiv(n, BN);
     int nz = (int)std::max<long>(1, std::min<long>(cdiv(1024, tiles), cdiv(k, 256)));
-    while (nz > 1 && (long)nz * m * n > work_elems) --nz;
+    while (nz > 1 && (long)nz * m * n * batch > work_elems) --nz;
     int kc = ((cdiv(k, nz) + BK - 1) / BK) * BK;
     nz = cdiv(k, kc);
     if (nz <= 1 || k <= 0) {
-        gemm<T>(s, opa, opb, m, n, k, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1);
+        gemm<T>(s, opa, opb, m, n, k, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, batch);
         return;
     }
-    dim3 grid(cdiv(n, BN), cdiv(m, BM), nz);
+    dim3 grid(cdiv(n, BN), cdiv(m, BM), nz * batch);
 #define KS_SK_CASE(OA, OB)                                                                            \
     if (opa == OA && opb == OB)                                                                      \
-        hipLaunchKernelGGL((gemm_splitk_kernel<T, OA, OB>), grid, dim3(256), 0, s, m, n, k, kc, A, lda, B, \
-                           ldb, work);
+        hipLaunchKernelGGL((gemm_splitk_kernel<T, OA, OB>), grid, dim3(256), 0, s, m, n, k, kc, nz, A, lda, sa, \
+                           B, ldb, sb, work);
     KS_SK_CASE(OP_N, OP_N)
     KS_SK_CASE(OP_C, OP_N)
     KS_SK_CASE(OP_T, OP_N)
 #undef KS_SK_CASE
     long tot = (long)m * n;
-    hipLaunchKernelGGL((splitk_reduce_kernel<T>), dim3(cdiv(tot, 256)), dim3(256), 0, s, m, n, nz, work, alpha,
-                       beta, C, ldc);
+    hipLaunchKernelGGL((splitk_reduce_kernel<T>), dim3(cdiv(tot, 256), batch), dim3(256), 0, s, m, n, nz, work,
+                       alpha, beta, C, ldc, sc);
 }
 
 template void gemm_splitk<double>(hipStream_t, Op, Op, int, int, int, double, const double*, int, const double*,
-                                  int, double, double*, int, double*, long);
+                                  int, double, double*, int, double*, long, int, long, long, long);
 template void gemm_splitk<cplx>(hipStream_t, Op, Op, int, int, int, double, const cplx*, int, const cplx*, int,
-                                double, cplx*, int, cplx*, long);
+                                double, cplx*, int, cplx*, long, int, long, long, long);
 
 // ---------------------------------------------------------------- grouped
-__global__ __launch_bounds__(256) void gemm_grouped_dc_kernel(const int* lo, const int* hi,
+__global__ __launch_bounds__(256) void gemm_grouped_dc_kernel(int nm, const int* lo, const int* hi,
                                                               const int* kk, const double* A,
                                                               const double* B, double* C, int ld) {
-    int g = blockIdx.z;
-    int l = lo[g], rows = hi[g] - l, K = kk[g];
+    const int G = blockIdx.z, g = G % nm;  // merge g of matrix G / nm of a batch
+    int l = lo[g], rows = hi[g] - l, K = kk[G];
     int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     if (m0 >= rows || n0 >= K) return;
-    long off = (long)l * ld + l;
+    long off = (long)(G / nm) * ld * ld + (long)l * ld + l;
     gemm_tile<double, OP_N, OP_N>(rows, K, K, 1.0, A + off, ld, B + off, ld, 0.0, C + off, ld,
                                   nullptr, UPLO_FULL, m0, n0);
 }
 
-void gemm_grouped_dc(hipStream_t s, int ngroups, int max_rows, const int* d_lo, const int* d_hi,
+void gemm_grouped_dc(hipStream_t s, int ngroups, int batch, int max_rows, const int* d_lo, const int* d_hi,
                      const int* d_kk, const double* A, const double* B, double* C, int ld) {
-    if (ngroups <= 0 || max_rows <= 0) return;
-    dim3 grid(cdiv(max_rows, BN), cdiv(max_rows, BM), ngroups);
-    hipLaunchKernelGGL(gemm_grouped_dc_kernel, grid, dim3(256), 0, s, d_lo, d_hi, d_kk, A, B, C, ld);
+    if (ngroups <= 0 || max_rows <= 0 || batch <= 0) return;
+    dim3 grid(cdiv(max_rows, BN), cdiv(max_rows, BM), ngroups * batch);
+    hipLaunchKernelGGL(gemm_grouped_dc_kernel, grid, dim3(256), 0, s, ngroups, d_lo, d_hi, d_kk, A, B, C, ld);
 }
 
 }  // namespace ks

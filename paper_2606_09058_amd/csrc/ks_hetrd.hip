@@ -4,19 +4,20 @@
 // paper identifies as bandwidth-bound matrix-vector work in Sec. 6).
 //
 // Lower-triangle convention: only the lower triangle of the trailing matrix is
-// read and kept up to date (row-major).  Panels of NB columns; per column k
-// (panel column j) three launches:
-//   colupd   (grid) finish column j-1 of W (w += alpha v, alpha = -tau w^H v / 2),
-//            update column k with the panel's previous reflectors,
-//            x = A[:,k] - V W[k,:]^H - W V[k,:]^H, and per-workgroup partial sums
-//            of |x|^2, W^H x and V^H x;
-//   symv     (grid over 64 x 64 lower tiles) every workgroup reduces those
-//            partials and forms the reflector H_k = I - tau v v^H with
-//            H_k^H x = beta e_1 (beta real, so T is real for complex input), then
-//            the tiles' share of y = A_trail v (the one pass over the trailing
-//            matrix, the memory-bound part, each lower tile read once);
-//   wcorrect (grid) y from the tile partials, w = tau (y - V (W^H v) - W (V^H v))
-//            and partial w^H v.
+// read and kept up to date (row-major).  Panels of NB columns; a panel starts
+// with colstart (column k0 as the previous trailing update left it), then per
+// column k (panel column j) two launches:
+//   symv  (grid over 64 x 64 lower tiles) every workgroup reduces the column's
+//         partial |x|^2 and forms the reflector H_k = I - tau v v^H with
+//         H_k^H x = beta e_1 (beta real, so T is real for complex input); one
+//         workgroup also reduces the panel corrections p = W^H v, q = V^H v;
+//         then the tiles' share of y = A_trail v (the one pass over the
+//         trailing matrix, the memory-bound part, each lower tile read once)
+//         and of v^H A v;
+//   wcol  (grid over 64-row blocks) the final W column
+//         w = tau (y - V p - W q) + alpha v, and, inside the panel, the update
+//         of column k+1 with the panel's reflectors and its partial sums
+//         |x|^2, W^H x, V^H x for the next reflector.
 // After the panel the lower triangle of the trailing matrix takes the rank-2NB
 // update A -= V W^H + W V^H as one MFMA GEMM with K = 2 NB.
 // The panel buffers are stored transposed (NB columns of length n each) so
@@ -45,165 +46,82 @@ __device__ inline double make_c<double>(double re, double) { return re; }
 template <>
 __device__ inline cplx make_c<cplx>(double re, double im) { return mk(re, im); }
 
-// alpha = -tau sigma / 2 from the per-workgroup partial sigma = w^H v of the
-// previous column (every workgroup sums them in the same order).
+// Start of a panel: column k is already up to date (the trailing update of the
+// previous panel has been applied), so x = A[k.., k] and the per-workgroup
+// partial |x_{k+2..}|^2 is all the next reflector needs.  One wavefront per
+// 64 rows; partials laid out as below ([0] of each workgroup's record).
 template <typename T>
-__device__ inline T w_alpha(const double* partS, int nS, T tau, double* red) {
-    double sr = 0.0, si = 0.0;
-    for (int b = threadIdx.x; b < nS; b += blockDim.x) {
-        sr += partS[2 * b];
-        si += partS[2 * b + 1];
-    }
-    sr = block_sum(sr, red);
-    si = block_sum(si, red);
-    return (-0.5) * (tau * make_c<T>(sr, si));
-}
-
-// Layout: VWt[i*n + r] = V[r][i] (i < nb), W[r][i-nb] (nb <= i < 2nb);
-//         WVc[i*n + r] = conj W[r][i] (i < nb), conj V[r][i-nb] (nb <= i < 2nb).
-// One wavefront per 64 rows.  The per-row products of the partial sums go
-// through LDS (lane-major, 16 panel columns per pass) and are summed
-// column-wise, so there is no long chain of cross-lane reductions.
-// Partials per workgroup: [0] |x|^2, [1+i] (W^H x)_i, [1+nb+i] (V^H x)_i.
-constexpr int CU_ROWS = 64;
-constexpr int CU_PI = 16;
-template <typename T>
-__global__ __launch_bounds__(64) void colupd_kernel(int n, int k, int j, int nb, const T* A, int lda,
-                                                    T* VWt, T* WVc, T* x, const T* wraw,
-                                                    const double* partS, int nS, const T* tau,
-                                                    T* partA) {
-    __shared__ T sv[64], sw[64];
-    __shared__ T prod[CU_ROWS][2 * CU_PI + 2];
-    __shared__ double red[1];
+__global__ __launch_bounds__(64) void colstart_kernel(int n, int k, int nb, const T* A, int lda, long sA,
+                                                      HetrdWork<T> hw) {
+    const int z = blockIdx.z;
+    A += z * sA;
+    T* x = hw.x + z * hw.sx;
+    T* partA = hw.partPQ + z * hw.spart;
     int t = threadIdx.x;
-    T alpha = zero_<T>();
-    if (j > 0) alpha = w_alpha<T>(partS, nS, tau[k - 1], red);
-    if (t < j) {
-        sv[t] = VWt[(long)t * n + k];
-        if (t < j - 1) sw[t] = VWt[(long)(nb + t) * n + k];
-        else sw[t] = wraw[k] + alpha * VWt[(long)(j - 1) * n + k];
-    }
-    __syncthreads();
-    int r = k + blockIdx.x * CU_ROWS + t;
-    bool in = r < n;
-    T wf = zero_<T>();
+    int r = k + blockIdx.x * 64 + t;
     T c = zero_<T>();
-    if (in) {
-        if (j > 0) {
-            wf = wraw[r] + alpha * VWt[(long)(j - 1) * n + r];
-            VWt[(long)(nb + j - 1) * n + r] = wf;
-            WVc[(long)(j - 1) * n + r] = conj_(wf);
-        }
+    if (r < n) {
         c = A[(long)r * lda + k];  // column k below the diagonal (lower storage)
-        T c0 = zero_<T>(), c1 = zero_<T>();
-        int i = 0;
-        for (; i + 1 < j - 1; i += 2) {
-            c0 += VWt[(long)i * n + r] * conj_(sw[i]) + VWt[(long)(nb + i) * n + r] * conj_(sv[i]);
-            c1 += VWt[(long)(i + 1) * n + r] * conj_(sw[i + 1]) +
-                  VWt[(long)(nb + i + 1) * n + r] * conj_(sv[i + 1]);
-        }
-        for (; i < j - 1; ++i)
-            c0 += VWt[(long)i * n + r] * conj_(sw[i]) + VWt[(long)(nb + i) * n + r] * conj_(sv[i]);
-        if (j > 0) c0 += VWt[(long)(j - 1) * n + r] * conj_(sw[j - 1]) + wf * conj_(sv[j - 1]);
-        c -= c0 + c1;
         if (r == k) c = from_re<T>(re_(c));
         x[r] = c;
     }
-    T xe = (in && r >= k + 2) ? c : zero_<T>();
-    const int ld = 1 + 2 * nb;
-    T* out = partA + (long)blockIdx.x * ld;
-    int npass = j > 0 ? (j + CU_PI - 1) / CU_PI : 1;
-    for (int ps = 0; ps < npass; ++ps) {
-        int base = ps * CU_PI;
-        if (ps == 0) prod[t][2 * CU_PI] = from_re<T>(abs2_(xe));
-#pragma unroll
-        for (int q = 0; q < CU_PI; ++q) {
-            int i = base + q;
-            if (i < j) {
-                T vri = in ? VWt[(long)i * n + r] : zero_<T>();
-                T wri = (i == j - 1) ? wf : (in ? VWt[(long)(nb + i) * n + r] : zero_<T>());
-                prod[t][q] = conj_(wri) * xe;
-                prod[t][CU_PI + q] = conj_(vri) * xe;
-            }
-        }
-        __syncthreads();
-        bool isP = t < CU_PI && base + t < j;
-        bool isQ = t >= CU_PI && t < 2 * CU_PI && base + t - CU_PI < j;
-        bool isN = t == 2 * CU_PI && ps == 0;
-        if (isP || isQ || isN) {
-            T s0 = zero_<T>(), s1 = zero_<T>();
-            for (int q = 0; q < CU_ROWS; q += 2) {
-                s0 += prod[q][t];
-                s1 += prod[q + 1][t];
-            }
-            int idx = isN ? 0 : (isP ? 1 + base + t : 1 + nb + base + t - CU_PI);
-            out[idx] = s0 + s1;
-        }
-        __syncthreads();
-    }
+    double a = (r < n && r >= k + 2) ? abs2_(c) : 0.0;
+    a = wave_sum(a);
+    if (t == 0) partA[(long)blockIdx.x * (1 + 2 * nb)] = from_re<T>(a);
 }
 
-// Reflector scalars from the per-workgroup partials of colupd (every workgroup
-// reduces them in the same order, so all see identical values).  Only the
-// norm |x_{k+2..}|^2 is reduced here; sh[0] = s = 1/(alpha - beta), sh[1] = tau,
-// and the writer stores d[k], e[k], tau[k].
+// The reflector of column k from the partials of the previous kernel: every
+// wavefront of every workgroup reduces the partial |x_{k+2..}|^2 in the same
+// order and forms H_k = I - tau v v^H with H_k^H x = beta e_1 itself, so no
+// barrier is needed.  Returns s = 1/(alpha - beta) (v = s x below row k+1) and
+// tau; the writer stores d[k], e[k], tau[k].
 template <typename T>
-__device__ inline void reflector_scalars(int k, int nb, const T* x, const T* partA, int nA, T* sh,
-                                         double* d, double* e, T* taua, bool writer, double* red) {
-    int t = threadIdx.x;
+__device__ inline void reflector(int k, int nb, const T* x, const T* partA, int nA, bool writer, double* d,
+                                 double* e, T* taua, T& sc, T& tv) {
+    const int lane = threadIdx.x & 63;
     const int ld = 1 + 2 * nb;
     double a = 0.0;
-    for (int b = t; b < nA; b += blockDim.x) a += re_(partA[(long)b * ld]);
-    double xn2 = block_sum(a, red);
-    if (t == 0) {
-        T alpha = x[k + 1];
-        double ar = re_(alpha), ai = im_(alpha);
-        T tv, sc;
-        double beta;
-        if (xn2 == 0.0 && ai == 0.0) {
-            tv = zero_<T>();
-            beta = ar;
-            sc = zero_<T>();
-        } else {
-            beta = -copysign(sqrt(ar * ar + ai * ai + xn2), ar);
-            tv = make_c<T>((beta - ar) / beta, -ai / beta);
-            sc = inv_(alpha - from_re<T>(beta));
-        }
-        sh[0] = sc;
-        sh[1] = tv;
-        if (writer) {
-            d[k] = re_(x[k]);
-            e[k] = beta;
-            taua[k] = tv;
-        }
+    for (int b = lane; b < nA; b += 64) a += re_(partA[(long)b * ld]);
+    const double xn2 = wave_sum(a);
+    const T alpha = x[k + 1];
+    const double ar = re_(alpha), ai = im_(alpha);
+    double beta;
+    if (xn2 == 0.0 && ai == 0.0) {
+        tv = zero_<T>();
+        beta = ar;
+        sc = zero_<T>();
+    } else {
+        beta = -copysign(sqrt(ar * ar + ai * ai + xn2), ar);
+        tv = make_c<T>((beta - ar) / beta, -ai / beta);
+        sc = inv_(alpha - from_re<T>(beta));
     }
-    __syncthreads();
+    if (writer && threadIdx.x == 0) {
+        d[k] = re_(x[k]);
+        e[k] = beta;
+        taua[k] = tv;
+    }
 }
 
 // The panel corrections p = W^H v and q = V^H v (v_{k+1} = 1, v = s x beyond),
-// reduced once per column by one workgroup and stored with s and tau in pq:
-// pq[0] = s, pq[1] = tau, pq[2 + i] = p_i, pq[2 + nb + i] = q_i.
-template <typename T>
+// reduced once per column by one workgroup of NW wavefronts and stored with s
+// and tau in pq: pq[0] = s, pq[1] = tau, pq[2 + i] = p_i, pq[2 + nb + i] = q_i.
+template <typename T, int NW>
 __device__ inline void panel_corrections(int n, int k, int j, int nb, const T* partA, int nA, const T* VWt,
-                                         T sc, T tv, T* pq) {
-    __shared__ T part4[4][64];
-    int t = threadIdx.x, lane = t & 63, g = t >> 6;
+                                         T sc, T tv, T* pq, T (*part)[64]) {
+    static_assert(NW % 4 == 0, "wavefront count");
+    const int t = threadIdx.x, lane = t & 63, g = t >> 6;
     const int ld = 1 + 2 * nb;
     const int nv = 2 * j;
     if (lane < nv) {
         int idx = lane < j ? 1 + lane : 1 + nb + (lane - j);
-        T a0 = zero_<T>(), a1 = zero_<T>();
-        int b = g;
-        for (; b + 4 < nA; b += 8) {
-            a0 += partA[(long)b * ld + idx];
-            a1 += partA[(long)(b + 4) * ld + idx];
-        }
-        if (b < nA) a0 += partA[(long)b * ld + idx];
-        part4[g][lane] = a0 + a1;
+        T a = zero_<T>();
+        for (int b = g; b < nA; b += NW) a += partA[(long)b * ld + idx];
+        part[g][lane] = a;
     }
     __syncthreads();
     if (t < nv) {
-        T P = (part4[0][t] + part4[1][t]) + (part4[2][t] + part4[3][t]);
+        T P = zero_<T>();
+        for (int q = 0; q < NW; q += 4) P += (part[q][t] + part[q + 1][t]) + (part[q + 2][t] + part[q + 3][t]);
         if (t < j) pq[2 + t] = conj_(VWt[(long)(nb + t) * n + k + 1]) + sc * P;
         else pq[2 + nb + (t - j)] = conj_(VWt[(long)(t - j) * n + k + 1]) + sc * P;
     }
@@ -213,194 +131,335 @@ __device__ inline void panel_corrections(int n, int k, int j, int nb, const T* p
     }
 }
 
+// Sum of r[0..R-1] over the 64 lanes for each of the R rows at once
+// (reduce-scatter by halving, then a butterfly): lanes (64/R) q .. (64/R) q + 64/R - 1
+// end with row q.
+template <typename T>
+__device__ inline T rows_lane_sum(const T (&r)[4], int lane) {
+    const bool b5 = lane & 32, b4 = lane & 16;
+    T w[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        T send = b5 ? r[i] : r[i + 2];
+        T keep = b5 ? r[i + 2] : r[i];
+        w[i] = keep + shfl_xor_(send, 32);
+    }
+    T send = b4 ? w[0] : w[1];
+    T z = (b4 ? w[1] : w[0]) + shfl_xor_(send, 16);
+    z += shfl_xor_(z, 8);
+    z += shfl_xor_(z, 4);
+    z += shfl_xor_(z, 2);
+    z += shfl_xor_(z, 1);
+    return z;
+}
+template <typename T>
+__device__ inline T rows_lane_sum(const T (&r)[8], int lane) {
+    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+    T w[4], u[2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        T send = b5 ? r[i] : r[i + 4];
+        T keep = b5 ? r[i + 4] : r[i];
+        w[i] = keep + shfl_xor_(send, 32);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        T send = b4 ? w[i] : w[i + 2];
+        T keep = b4 ? w[i + 2] : w[i];
+        u[i] = keep + shfl_xor_(send, 16);
+    }
+    T send = b3 ? u[0] : u[1];
+    T z = (b3 ? u[1] : u[0]) + shfl_xor_(send, 8);
+    z += shfl_xor_(z, 4);
+    z += shfl_xor_(z, 2);
+    z += shfl_xor_(z, 1);
+    return z;
+}
+
 // Trailing Hermitian matrix-vector product y = A_trail v from the LOWER
 // triangle only.  The trailing matrix (rows/cols k+1 .. n-1) is cut into
-// 64 x 64 tiles; workgroup (c, I) takes tiles J = 8c .. 8c+7 (J <= I) of tile
-// row I, staged through LDS 32 rows at a time.  Each tile contributes A_IJ v_J
-// to y_I (row sums, accumulated over the workgroup's tiles into prow) and,
-// below the diagonal, A_IJ^H v_I to y_J (column sums, one partial per tile in
-// pcol); a diagonal tile is expanded from its strict lower part.
+// 64 x 64 tiles; workgroup (c, I) takes tiles J = SCH c .. SCH c + SCH-1
+// (J <= I) of tile row I.  Each of its threads holds one column and R rows
+// of a tile in registers (R = 8 for real, 4 for complex data, so that a
+// thread keeps two tiles' worth in flight within 128 registers) (the next tile's loads are issued before the
+// current one is used): the row sums A_IJ v_J stay in registers across the
+// workgroup's tiles and are reduced over the lanes once at the end (into
+// prow); the column sums A_IJ^H v_I, one per tile, go to LDS and are reduced
+// over the row groups at the end (into pcol).  A diagonal tile is
+// expanded from its strict lower part.  Each workgroup also leaves its share
+// of v^H A v (2 Re v_I^H A_IJ v_J off the diagonal, v_I^H A_II v_I on it) in
+// pvav, from which the next kernel gets the W-column correction without a
+// pass over w.
 constexpr int ST = HETRD_TILE;  // tile edge
 constexpr int SCH = HETRD_SCH;  // tiles per workgroup
 template <typename T>
-struct Stage {
-    static constexpr int rows = sizeof(T) == 8 ? 64 : 32;  // tile rows per LDS stage (33 KB)
+struct Sy {
+    static constexpr int R = sizeof(T) == 8 ? 8 : 4;  // tile rows per thread
+    static constexpr int NG = ST / R;                  // row groups = wavefronts
+    static constexpr int THREADS = 64 * NG;            // 512 or 1024
 };
 
 template <typename T>
-__global__ __launch_bounds__(256) void symv_tiles_kernel(int n, int k, int j, int nb, const T* A, int lda,
-                                                         const T* x, const T* partA, int nA, T* prow,
-                                                         T* pcol, int nt, int nch, double* d, double* e,
-                                                         T* taua, const T* VWt, T* pq) {
-    constexpr int SH = Stage<T>::rows;
-    constexpr int NSTG = ST / SH;
-    __shared__ T tile[SH][ST + 1];
-    __shared__ T vI[ST], vJ[2][ST];
-    __shared__ T racc[ST];
-    __shared__ T red[8][ST];
-    __shared__ T sh[2];
-    __shared__ double redd[4];
-    int c = blockIdx.x, I = blockIdx.y;
-    int J0 = c * SCH;
-    if (J0 > I) return;
-    int J1 = min(J0 + SCH, I + 1);
-    int t = threadIdx.x;
-    const int o = k + 1;  // first trailing row / column
-    const int col = t & 63, r0 = t >> 6;
-    const int nstage = NSTG * (J1 - J0);
-    // issue the loads of the first half tile before the scalar prologue
-    T ra[SH / 4];
-    auto load_stage = [&](int st) {
-        int J = J0 + st / NSTG, h = st % NSTG;
-        int gc = o + J * ST + col;
-#pragma unroll
-        for (int q = 0; q < SH / 4; ++q) {
-            int rl = r0 + 4 * q;
-            int gr = o + I * ST + h * SH + rl;
-            T a = zero_<T>();
-            if (gr < n && gc < n) a = A[(long)gr * lda + gc];
-            if (J == I && col > h * SH + rl) a = zero_<T>();  // diagonal tile: lower part only
-            ra[q] = a;
-        }
-    };
-    load_stage(0);
-    reflector_scalars<T>(k, nb, x, partA, nA, sh, d, e, taua, c == 0 && I == 0, redd);
-    T sc = sh[0];
-    if (c == 0 && I == 0) panel_corrections<T>(n, k, j, nb, partA, nA, VWt, sc, sh[1], pq);
-    auto vof = [&](int g) -> T {
-        if (g >= n) return zero_<T>();
-        return (g == o) ? from_re<T>(1.0) : sc * x[g];
-    };
-    if (t < ST) {
-        vI[t] = vof(o + I * ST + t);
-        vJ[0][t] = vof(o + J0 * ST + t);
-        racc[t] = zero_<T>();
+__global__ __launch_bounds__(Sy<T>::THREADS, 4) void symv_kernel(int n, int k, int j, int nb, const T* A, int lda,
+                                                          long sA, int nA, int nt, int nch, double* d,
+                                                          double* e, T* taua, HetrdWork<T> hw) {
+    constexpr int SY_R = Sy<T>::R, NG = Sy<T>::NG;
+    __shared__ T vI[ST], yrow[ST];
+    __shared__ T cred[SCH][NG][ST];
+    __shared__ T part[NG][64];
+    __shared__ double redd[NG];
+    const int c = blockIdx.x, I = blockIdx.y, z = blockIdx.z;
+    const int J0 = c * SCH;
+    const int t = threadIdx.x;
+    double* pvav = hw.pvav + z * hw.spvav;
+    if (J0 > I) {
+        if (t == 0) pvav[(long)I * nch + c] = 0.0;
+        return;
     }
-    T cacc = zero_<T>();  // column partial of column t (t < 64) for the current tile
-    for (int st = 0; st < nstage; ++st) {
-        int J = J0 + st / NSTG, h = st % NSTG;
-        __syncthreads();
+    A += z * sA;
+    d += (long)z * n;
+    e += (long)z * n;
+    taua += (long)z * n;
+    const T* x = hw.x + z * hw.sx;
+    const T* partA = hw.partPQ + z * hw.spart;
+    T* prow = hw.prow + z * hw.sprow;
+    T* pcol = hw.pcol + z * hw.spcol;
+    const int ntile = min(J0 + SCH, I + 1) - J0;
+    const int o = k + 1;  // first trailing row / column
+    const int col = t & 63, g = t >> 6;
+    const int r0 = o + I * ST + g * SY_R;  // first row of this thread
+    T cur[SY_R], nxt[SY_R];
+    {
+        const int gc = o + J0 * ST + col;
 #pragma unroll
-        for (int q = 0; q < SH / 4; ++q) tile[r0 + 4 * q][col] = ra[q];
-        if (h == NSTG - 1 && st + 1 < nstage && t < ST) vJ[(J + 1 - J0) & 1][t] = vof(o + (J + 1) * ST + t);
-        __syncthreads();
-        if (st + 1 < nstage) load_stage(st + 1);  // overlap the next half tile with this one
-        const T* vj = vJ[(J - J0) & 1];
-        // row sums: thread -> row t % SH, a group of RG columns
-        constexpr int RGN = 256 / SH, RG = ST / RGN;
-        {
-            int rl = t % SH, g = t / SH;
-            T sacc = zero_<T>();
+        for (int q = 0; q < SY_R; ++q)
+            cur[q] = (r0 + q < n && gc < n) ? A[(long)(r0 + q) * lda + gc] : zero_<T>();
+    }
+    T sc, tv;
+    reflector<T>(k, nb, x, partA, nA, c == 0 && I == 0, d, e, taua, sc, tv);
+    auto vof = [&](int gi) -> T {
+        if (gi >= n) return zero_<T>();
+        return (gi == o) ? from_re<T>(1.0) : sc * x[gi];
+    };
+    if (t < ST) vI[t] = vof(o + I * ST + t);
+    T vJc = vof(o + J0 * ST + col);
+    __syncthreads();
+    T vr[SY_R], racc[SY_R];
 #pragma unroll
-            for (int q = 0; q < RG; ++q) sacc += tile[rl][g * RG + q] * vj[g * RG + q];
-            red[g][rl] = sacc;
+    for (int q = 0; q < SY_R; ++q) {
+        vr[q] = vI[g * SY_R + q];
+        racc[q] = zero_<T>();
+    }
+    double vav = 0.0;
+    for (int s = 0; s < ntile; ++s) {
+        const int J = J0 + s;
+        const bool more = s + 1 < ntile;
+        T vJn = zero_<T>();
+        if (more) {
+            const int gc = o + (J + 1) * ST + col;
+#pragma unroll
+            for (int q = 0; q < SY_R; ++q)
+                nxt[q] = (r0 + q < n && gc < n) ? A[(long)(r0 + q) * lda + gc] : zero_<T>();
+            vJn = vof(gc);
         }
-        // column sums (strictly below the diagonal): column t%64, rows CG*(t/64) .. +CG-1
-        constexpr int CG = SH / 4;
         T cs = zero_<T>();
-        {
-            int cl = t & 63, g = t >> 6;
+        if (J != I) {
 #pragma unroll
-            for (int q = 0; q < CG; ++q) {
-                int rl = g * CG + q;
-                T a = tile[rl][cl];
-                if (J == I && cl == h * SH + rl) a = zero_<T>();  // diagonal counted once
-                cs += conj_(a) * vI[h * SH + rl];
+            for (int q = 0; q < SY_R; ++q) {
+                racc[q] += cur[q] * vJc;
+                cs += conj_(cur[q]) * vr[q];
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < SY_R; ++q) {
+                const int rl = g * SY_R + q;
+                if (col <= rl) racc[q] += cur[q] * vJc;
+                if (col < rl) cs += conj_(cur[q]) * vr[q];
+                if (col == rl) vav += re_(cur[q]) * abs2_(vr[q]);
             }
         }
-        __syncthreads();
-        if (t < SH) {
-            T sacc = zero_<T>();
+        vav += 2.0 * re_(conj_(vJc) * cs);
+        cred[s][g][col] = cs;
+        if (more) {
 #pragma unroll
-            for (int g = 0; g < RGN; ++g) sacc += red[g][t];
-            racc[h * SH + t] += sacc;
-        }
-        __syncthreads();
-        red[t >> 6][t & 63] = cs;
-        __syncthreads();
-        if (t < ST) cacc += (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
-        if (h == NSTG - 1 && t < ST) {
-            if (J == I) racc[t] += cacc;  // A_II^H v_I belongs to y_I as well
-            else pcol[((long)J * nt + I) * ST + t] = cacc;
-            cacc = zero_<T>();
+            for (int q = 0; q < SY_R; ++q) cur[q] = nxt[q];
+            vJc = vJn;
         }
     }
-    __syncthreads();
-    if (t < ST) prow[((long)I * nch + c) * ST + t] = racc[t];
+    const T rsum = rows_lane_sum<T>(racc, col);
+    constexpr int LPR = 64 / SY_R;  // lanes per row after the reduction
+    if (col % LPR == 0) yrow[g * SY_R + col / LPR] = rsum;
+    const double vsum = block_sum(vav, redd);  // its barriers also publish yrow and cred
+    if (t < ST) {
+        T ysum = yrow[t];
+        for (int s = 0; s < ntile; ++s) {
+            T cs = zero_<T>();
+#pragma unroll
+            for (int q = 0; q < NG; q += 4)
+                cs += (cred[s][q][t] + cred[s][q + 1][t]) + (cred[s][q + 2][t] + cred[s][q + 3][t]);
+            const int J = J0 + s;
+            if (J == I) ysum += cs;  // A_II^H v_I belongs to y_I as well
+            else pcol[((long)J * nt + I) * ST + t] = cs;
+        }
+        prow[((long)I * nch + c) * ST + t] = ysum;
+    }
+    if (t == 0) pvav[(long)I * nch + c] = vsum;
+    if (c == 0 && I == 0)
+        panel_corrections<T, NG>(n, k, j, nb, partA, nA, hw.VW + z * hw.sVW, sc, tv, hw.pq + z * hw.spq, part);
 }
 
-// y from the tile partials, then w = tau (y - V (W^H v) - W (V^H v)), the new V
-// column, and partial w^H v per workgroup.  64 rows per workgroup, four
-// threads per row share the partial sums and the correction terms.
+// Column k has just been reflected (panel column j).  One workgroup per 64
+// trailing rows r = k+1+64b+l, which is exactly tile row b of the symmetric
+// product, and four wavefronts that split every per-row sum four ways:
+//   * alpha = -|tau|^2 (v^H A v - 2 Re q^H p) / 2 from the product's v^H A v
+//     partials, with p = W^H v and q = V^H v, so w = tau (y - V p - W q) + alpha v
+//     is final at once (the usual w += alpha v with alpha = -tau w^H v / 2,
+//     since w^H v = conj(tau) v^H (A - V W^H - W V^H) v);
+//   * y_r from the tile partials, then w_r, stored with v_r in the panel;
+//   * unless column k closes the panel, column k+1 is brought up to date with
+//     the panel's j+1 reflectors, x_r = A[r][k+1] - V_r W_{k+1}^H - W_r V_{k+1}^H,
+//     and the workgroup's partials |x_{k+3..}|^2, W^H x and V^H x are written
+//     for the next reflector.
+// Row k+1 of W (needed by every row for the update of column k+1) is
+// computed by every workgroup in the same order, so all of them agree.
+// Partials per workgroup: [0] |x|^2, [1+i] (W^H x)_i, [1+nb+i] (V^H x)_i.
 constexpr int WC_ROWS = 64;
+static_assert(WC_ROWS == ST, "a row block of wcol is a tile row of the symmetric product");
+static_assert(2 * HETRD_NB <= 64 && HETRD_NB % 4 == 0, "panel width");
+constexpr int WC_MAXU = HETRD_NB / 4;  // panel columns per wavefront
 template <typename T>
-__global__ __launch_bounds__(256) void wcorrect_kernel(int n, int k, int j, int nb, const T* x, const T* pq,
-                                                       const T* prow, const T* pcol, int nt, int nch,
-                                                       T* VWt, T* WVc, T* wraw, double* partS) {
-    __shared__ T sp[64], sq[64];
-    __shared__ T part[4][WC_ROWS];
+__global__ __launch_bounds__(256) void wcol_kernel(int n, int k, int j, int nb, int next, const T* A, int lda,
+                                                   long sA, int nt, int nch, HetrdWork<T> hw) {
+    __shared__ T sp[HETRD_NB], sq[HETRD_NB];          // p = W^H v, q = V^H v
+    __shared__ T vk[HETRD_NB + 1], wk[HETRD_NB + 1];  // V and W on row k+1
+    __shared__ T party[4][WC_ROWS], partc[4][WC_ROWS];
+    __shared__ T rowv[WC_ROWS], roww[WC_ROWS], rowx[WC_ROWS];
     __shared__ double red[4];
-    int t = threadIdx.x, lr = t & 63, pp = t >> 6;
-    T sc = pq[0], tv = pq[1];
+    const int t = threadIdx.x, lr = t & 63, pp = t >> 6;
+    const int I = blockIdx.x, z = blockIdx.z;
+    A += z * sA;
+    T* x = hw.x + z * hw.sx;
+    const T* pq = hw.pq + z * hw.spq;
+    const T* prow = hw.prow + z * hw.sprow;
+    const T* pcol = hw.pcol + z * hw.spcol;
+    const double* pvav = hw.pvav + z * hw.spvav;
+    T* VWt = hw.VW + z * hw.sVW;
+    T* WVc = hw.WV + z * hw.sVW;
+    T* partA = hw.partPQ + z * hw.spart;
+    const int r = k + 1 + I * WC_ROWS + lr;
+    const bool in = r < n;
+    const T sc = pq[0], tv = pq[1];
     if (t < j) {
         sp[t] = pq[2 + t];
         sq[t] = pq[2 + nb + t];
+        vk[t] = VWt[(long)t * n + k + 1];
+        wk[t] = VWt[(long)(nb + t) * n + k + 1];
     }
-    __syncthreads();
-    int r = k + 1 + blockIdx.x * WC_ROWS + lr;
-    T a0 = zero_<T>(), a1 = zero_<T>();
-    if (r < n) {
-        int q = r - (k + 1), I = q / ST, i = q % ST;
+    // this row's panel entries for columns i = pp, pp+4, ... < j
+    T vr[WC_MAXU], wr[WC_MAXU];
+#pragma unroll
+    for (int u = 0; u < WC_MAXU; ++u) {
+        int i = pp + 4 * u;
+        bool ok = in && i < j;
+        vr[u] = ok ? VWt[(long)i * n + r] : zero_<T>();
+        wr[u] = ok ? VWt[(long)(nb + i) * n + r] : zero_<T>();
+    }
+    // y_r: row partials of tile row I, then column partials of the tiles below
+    T y0 = zero_<T>(), y1 = zero_<T>();
+    if (in) {
         int nc = I / SCH + 1;
-        for (int c = pp; c < nc; c += 4) a0 += prow[((long)I * nch + c) * ST + i];
-        const T* pc = pcol + (long)I * nt * ST + i;
+        for (int c = pp; c < nc; c += 4) y0 += prow[((long)I * nch + c) * ST + lr];
+        const T* pc = pcol + (long)I * nt * ST + lr;
         int I2 = I + 1 + pp;
         for (; I2 + 4 < nt; I2 += 8) {
-            a0 += pc[(long)I2 * ST];
-            a1 += pc[(long)(I2 + 4) * ST];
+            y0 += pc[(long)I2 * ST];
+            y1 += pc[(long)(I2 + 4) * ST];
         }
-        if (I2 < nt) a0 += pc[(long)I2 * ST];
-        for (int ii = pp; ii < j; ii += 4)
-            a1 -= VWt[(long)ii * n + r] * sp[ii] + VWt[(long)(nb + ii) * n + r] * sq[ii];
+        if (I2 < nt) y0 += pc[(long)I2 * ST];
     }
-    part[pp][lr] = a0 + a1;
+    // v^H A v from the product's partials (same order in every workgroup)
+    double va = 0.0;
+    for (int f = t; f < nt * nch; f += 256) va += pvav[f];
+    const double vAv = block_sum(va, red);  // its barriers also publish sp, sq, vk, wk
+    double cr = 0.0;
+    for (int i = 0; i < j; ++i) cr += re_(conj_(sq[i]) * sp[i]);
+    const double alpha = -0.5 * abs2_(tv) * (vAv - 2.0 * cr);
+    T cy = zero_<T>(), cx = zero_<T>();
+#pragma unroll
+    for (int u = 0; u < WC_MAXU; ++u) {
+        int i = pp + 4 * u;
+        if (i < j) {
+            cy += vr[u] * sp[i] + wr[u] * sq[i];
+            cx += vr[u] * conj_(wk[i]) + wr[u] * conj_(vk[i]);
+        }
+    }
+    party[pp][lr] = (y0 + y1) - cy;
+    partc[pp][lr] = cx;
+    if (pp == 0) {
+        // W on row k+1 (where v = 1); y_{k+1} is row 0 of tile row 0
+        T ys = zero_<T>();
+        for (int I2 = 1 + lr; I2 < nt; I2 += 64) ys += pcol[(long)I2 * ST];
+        ys = wave_sum(ys);
+        T cs = lr < j ? vk[lr] * sp[lr] + wk[lr] * sq[lr] : zero_<T>();
+        cs = wave_sum(cs);
+        T w1 = tv * ((prow[0] + ys) - cs) + from_re<T>(alpha);
+        if (lr == 0) {
+            wk[j] = w1;
+            vk[j] = from_re<T>(1.0);
+        }
+    }
     __syncthreads();
-    T sig = zero_<T>();
-    if (pp == 0 && r < n) {
-        T y = (part[0][lr] + part[1][lr]) + (part[2][lr] + part[3][lr]);
-        T vr = (r == k + 1) ? from_re<T>(1.0) : sc * x[r];
-        T w = tv * y;
-        wraw[r] = w;
-        sig = conj_(w) * vr;
-        VWt[(long)j * n + r] = vr;
-        WVc[(long)(nb + j) * n + r] = conj_(vr);
+    if (pp == 0) {
+        T v = zero_<T>(), w = zero_<T>(), xn = zero_<T>();
+        if (in) {
+            T y = (party[0][lr] + party[1][lr]) + (party[2][lr] + party[3][lr]);
+            v = (r == k + 1) ? from_re<T>(1.0) : sc * x[r];
+            w = (r == k + 1) ? wk[j] : tv * y + alpha * v;
+            VWt[(long)j * n + r] = v;
+            VWt[(long)(nb + j) * n + r] = w;
+            WVc[(long)j * n + r] = conj_(w);
+            WVc[(long)(nb + j) * n + r] = conj_(v);
+            if (next) {
+                T cc = (partc[0][lr] + partc[1][lr]) + (partc[2][lr] + partc[3][lr]);
+                xn = A[(long)r * lda + k + 1] - cc - (v * conj_(wk[j]) + w);
+                if (r == k + 1) xn = from_re<T>(re_(xn));
+                x[r] = xn;
+            }
+        }
+        rowv[lr] = v;
+        roww[lr] = w;
+        rowx[lr] = (r >= k + 3) ? xn : zero_<T>();
     }
-    double sr = block_sum(re_(sig), red);
-    double si = block_sum(im_(sig), red);
-    if (t == 0) {
-        partS[2 * blockIdx.x] = sr;
-        partS[2 * blockIdx.x + 1] = si;
+    if (!next) return;
+    __syncthreads();
+    // partials for the next reflector over the panel columns 0 .. j
+    const T xe = rowx[lr];
+    T* out = partA + (long)I * (1 + 2 * nb);
+    if (pp == 0) {
+        double a = wave_sum(abs2_(xe));
+        if (lr == 0) out[0] = from_re<T>(a);
     }
-}
-
-// Finish the last W column of a panel (w += alpha v) for rows r > k.
-template <typename T>
-__global__ __launch_bounds__(256) void wfix_kernel(int n, int k, int j, int nb, T* VWt, T* WVc,
-                                                   const T* wraw, const double* partS, int nS,
-                                                   const T* tau) {
-    __shared__ double red[4];
-    T alpha = w_alpha<T>(partS, nS, tau[k], red);
-    int r = k + 1 + blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < n) {
-        T wf = wraw[r] + alpha * VWt[(long)j * n + r];
-        VWt[(long)(nb + j) * n + r] = wf;
-        WVc[(long)j * n + r] = conj_(wf);
+#pragma unroll
+    for (int u = 0; u < WC_MAXU; ++u) {
+        int i = pp + 4 * u;  // wave-uniform; j < HETRD_NB, so i = j is reached
+        if (i <= j) {
+            T vi = (i == j) ? rowv[lr] : vr[u];
+            T wi = (i == j) ? roww[lr] : wr[u];
+            T pw = wave_sum(conj_(wi) * xe);
+            T pv = wave_sum(conj_(vi) * xe);
+            if (lr == 0) {
+                out[1 + i] = pw;
+                out[1 + nb + i] = pv;
+            }
+        }
     }
 }
 
 // Copy the panel's reflectors into columns k0 .. k0+jb-1 of Vall (n x n).
 template <typename T>
-__global__ void store_panel_kernel(int n, int k0, int jb, const T* VWt, T* Vall) {
+__global__ void store_panel_kernel(int n, int k0, int jb, const T* VWt, long sVW, T* Vall) {
+    VWt += blockIdx.z * sVW;
+    Vall += blockIdx.z * (long)n * n;
     long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (long)n * jb) return;
     int i = (int)(e / n), r = (int)(e % n);
@@ -408,57 +467,52 @@ __global__ void store_panel_kernel(int n, int k0, int jb, const T* VWt, T* Vall)
 }
 
 template <typename T>
-__global__ void last_diag_kernel(int n, const T* A, int lda, double* d) {
-    d[n - 1] = re_(A[(long)(n - 1) * lda + n - 1]);
+__global__ void last_diag_kernel(int n, const T* A, int lda, long sA, double* d) {
+    const int z = blockIdx.x;
+    d[(long)z * n + n - 1] = re_(A[z * sA + (long)(n - 1) * lda + n - 1]);
 }
 
 template <typename T>
-void hetrd(hipStream_t s, int n, T* A, int lda, double* d, double* e, T* tau, T* Vall, HetrdWork<T>& w) {
+void hetrd(hipStream_t s, int n, T* A, int lda, long sA, int batch, double* d, double* e, T* tau, T* Vall,
+           HetrdWork<T>& w) {
     const int nb = HETRD_NB;
-    T* VWt = w.VW;  // 2nb x n
-    T* WVc = w.WV;  // 2nb x n
+    const int B = batch;
     for (int k0 = 0; k0 < n - 1; k0 += nb) {
         int jb = min(nb, n - 1 - k0);
-        fill_zero<T>(s, VWt, (long)n * 2 * nb);
-        fill_zero<T>(s, WVc, (long)n * 2 * nb);
-        int nS = 0;
+        fill_zero<T>(s, w.VW, w.sVW * B);
+        fill_zero<T>(s, w.WV, w.sVW * B);
+        hipLaunchKernelGGL((colstart_kernel<T>), dim3(cdiv(n - k0, 64), 1, B), dim3(64), 0, s, n, k0, nb, A, lda,
+                           sA, w);
         for (int j = 0; j < jb; ++j) {
             int k = k0 + j;
-            int nb1 = cdiv(n - k, CU_ROWS);
-            hipLaunchKernelGGL((colupd_kernel<T>), dim3(nb1), dim3(CU_ROWS), 0, s, n, k, j, nb, A, lda, VWt, WVc,
-                               w.x, w.w, w.partS, nS, tau, w.partPQ);
             int m = n - k - 1;
             int nt = cdiv(m, ST), nch = cdiv(nt, SCH);
+            int nA = cdiv(n - k, WC_ROWS);  // workgroups that wrote the partials of column k
             bool smp = w.prof && w.prof->sample();
             hipEvent_t e0 = smp ? w.prof->begin() : nullptr;
-            hipLaunchKernelGGL((symv_tiles_kernel<T>), dim3(nch, nt), dim3(256), 0, s, n, k, j, nb, A, lda,
-                               w.x, w.partPQ, nb1, w.prow, w.pcol, nt, nch, d, e, tau, VWt, w.pq);
+            hipLaunchKernelGGL((symv_kernel<T>), dim3(nch, nt, B), dim3(Sy<T>::THREADS), 0, s, n, k, j, nb, A,
+                               lda, sA, nA, nt, nch, d, e, tau, w);
             // algorithmic bytes of a Hermitian matrix-vector product: the lower triangle once
-            if (smp) w.prof->end(PROF_HEMV, e0, (double)sizeof(T) * m * (m + 1) / 2.0);
-            int nb4 = cdiv(m, WC_ROWS);
-            hipLaunchKernelGGL((wcorrect_kernel<T>), dim3(nb4), dim3(256), 0, s, n, k, j, nb, w.x, w.pq,
-                               w.prow, w.pcol, nt, nch, VWt, WVc, w.w, w.partS);
-            nS = nb4;
+            if (smp) w.prof->end(PROF_HEMV, e0, (double)sizeof(T) * m * (m + 1) / 2.0 * B);
+            hipLaunchKernelGGL((wcol_kernel<T>), dim3(cdiv(m, WC_ROWS), 1, B), dim3(256), 0, s, n, k, j, nb,
+                               (int)(j + 1 < jb), A, lda, sA, nt, nch, w);
         }
-        int kl = k0 + jb - 1;
-        hipLaunchKernelGGL((wfix_kernel<T>), dim3(cdiv(n - kl - 1, 256)), dim3(256), 0, s, n, kl, jb - 1, nb,
-                           VWt, WVc, w.w, w.partS, nS, tau);
         long tot = (long)n * jb;
-        hipLaunchKernelGGL((store_panel_kernel<T>), dim3(cdiv(tot, 256)), dim3(256), 0, s, n, k0, jb, VWt,
-                           Vall);
+        hipLaunchKernelGGL((store_panel_kernel<T>), dim3(cdiv(tot, 256), 1, B), dim3(256), 0, s, n, k0, jb, w.VW,
+                           w.sVW, Vall);
         int t0 = k0 + jb;
         if (t0 < n) {
             int mt = n - t0;
-            gemm<T>(s, OP_T, OP_N, mt, mt, 2 * nb, -1.0, VWt + t0, n, 0, WVc + t0, n, 0, 1.0,
-                    A + (long)t0 * lda + t0, lda, 0, 1, nullptr, 0, UPLO_LOWER);
+            gemm<T>(s, OP_T, OP_N, mt, mt, 2 * nb, -1.0, w.VW + t0, n, w.sVW, w.WV + t0, n, w.sVW, 1.0,
+                    A + (long)t0 * lda + t0, lda, sA, B, nullptr, 0, UPLO_LOWER);
         }
     }
-    hipLaunchKernelGGL((last_diag_kernel<T>), dim3(1), dim3(1), 0, s, n, A, lda, d);
+    hipLaunchKernelGGL((last_diag_kernel<T>), dim3(B), dim3(1), 0, s, n, A, lda, sA, d);
 }
 
-template void hetrd<double>(hipStream_t, int, double*, int, double*, double*, double*, double*,
+template void hetrd<double>(hipStream_t, int, double*, int, long, int, double*, double*, double*, double*,
                             HetrdWork<double>&);
-template void hetrd<cplx>(hipStream_t, int, cplx*, int, double*, double*, cplx*, cplx*,
+template void hetrd<cplx>(hipStream_t, int, cplx*, int, long, int, double*, double*, cplx*, cplx*,
                           HetrdWork<cplx>&);
 template void fill_zero<double>(hipStream_t, double*, long);
 template void fill_zero<cplx>(hipStream_t, cplx*, long);

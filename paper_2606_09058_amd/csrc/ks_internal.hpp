@@ -71,15 +71,13 @@ struct HetrdWork {
     T* VW;          // 2NB x n   V then W of the current panel, transposed
     T* WV;          // 2NB x n   conj(W) then conj(V), transposed
     T* x;           // n         updated column
-    T* v;           // n         (spare)
-    T* y;           // n         (spare)
-    T* w;           // n         W column before its final correction
-    double* part1;  // cdiv(n, 256)
-    T* partPQ;      // cdiv(n, 256) x (1 + 2NB) partial |x|^2, W^H x, V^H x
-    double* partS;  // 2 cdiv(n, 16) partial w^H v
+    T* partPQ;      // cdiv(n, 64) x (1 + 2NB) partial |x|^2, W^H x, V^H x
     T* prow;        // nt x cdiv(nt, HETRD_SCH) x HETRD_TILE, nt = cdiv(n, HETRD_TILE): row partials
     T* pcol;        // nt x nt x HETRD_TILE                                           column partials
+    double* pvav;   // nt x cdiv(nt, HETRD_SCH) partial v^H A v
     T* pq;          // 2 + 2 NB: s, tau, W^H v, V^H v of the current column
+    // strides (elements) between the buffers of consecutive matrices of a batch
+    long sVW = 0, sx = 0, spart = 0, sprow = 0, spcol = 0, spvav = 0, spq = 0;
 };
 
 template <typename T>
@@ -142,30 +140,39 @@ template <typename T>
 void herm_complete(hipStream_t s, int n, const T* src, int lds, long ss, T* dst, int ldd, long sd,
                    int batch, int* info);
 
+// A = (I (x) Linv) H (I (x) Linv)^H for a batch (H: row stride ldh, matrix
+// stride sH; Linv: n x n, stride sL; A, W: order x order, consecutive).
 template <typename T>
-void reduce_to_standard(hipStream_t s, int n, int nsp, const T* H, int ldh, const T* Linv, int ldi, T* A,
-                        T* W, int* info);
+void reduce_to_standard(hipStream_t s, int n, int nsp, int batch, const T* H, int ldh, long sH, const T* Linv,
+                        int ldi, long sL, T* A, T* W, int* info);
 
 template <typename T>
 void tri_inverse(hipStream_t s, int n, const T* L, int ldl, long sl, T* Linv, long si, int batch);
 
 template <typename T>
-void hetrd(hipStream_t s, int n, T* A, int lda, double* d, double* e, T* tau, T* Vall,
+void hetrd(hipStream_t s, int n, T* A, int lda, long sA, int batch, double* d, double* e, T* tau, T* Vall,
            HetrdWork<T>& w);
 
-void stedc(hipStream_t s, const DcTree& tr, const double* d, const double* e, double* lam, double* Z,
-           double* Z2, double* U, double* Qp, DcWork& w, int* info);
+// Divide and conquer for a batch of tridiagonals of order tr.n (d, e, lam:
+// stride n; Z, Z2, U, Qp: stride n^2; the work arrays of w: stride n, with
+// kk, nrot, rho holding batch x (merges of the widest level)).
+void stedc(hipStream_t s, const DcTree& tr, int batch, const double* d, const double* e, double* lam,
+           double* Z, double* Z2, double* U, double* Qp, DcWork& w, int* info);
 
 void dc_tree_host(int n, std::vector<int>& mlo, std::vector<int>& mmid, std::vector<int>& mhi,
                   std::vector<int>& leaf_lo, std::vector<int>& leaf_hi, int& depth,
                   std::vector<int>& max_k0);
 
+// Z columns [c0, c0 + ncols) of each matrix of a batch (Z: n x n, consecutive)
+// into X (n x ncols, row stride ldx, matrix stride sX).
 template <typename T>
-void load_z(hipStream_t s, int n, int ncols, const double* Z, int c0, T* X, int ldx);
+void load_z(hipStream_t s, int n, int batch, int ncols, const double* Z, int c0, T* X, int ldx, long sX);
 
+// X <- Q X for a batch: Q from the reflectors in Vall (n x n per matrix, the
+// tridiagonalisation's layout) and tau (n per matrix).
 template <typename T>
-void backtransform_q(hipStream_t s, int n, const T* Vall, const T* tau, int ncols, T* X, int ldx,
-                     BacktrWork<T>& w);
+void backtransform_q(hipStream_t s, int n, int batch, const T* Vall, const T* tau, int ncols, T* X, int ldx,
+                     long sX, BacktrWork<T>& w);
 
 void fermi(hipStream_t s, int batch, int order, const double* eps, const KWeights& kw, double g,
            double ne, double kT, int il, int iu, double* occ, double* mu, double* eband, int* kwin,

@@ -308,24 +308,38 @@ void tri_inverse(hipStream_t s, int n, const T* L, int ldl, long sl, T* Linv, lo
 // its K range (~order^3 flops together for real input).  nsp spin blocks of n
 // rows; order = nsp * n.  Only the lower triangle of A is used afterwards.
 template <typename T>
-void reduce_to_standard(hipStream_t s, int n, int nsp, const T* H, int ldh, const T* Linv, int ldi,
-                        T* A, T* W, int* info) {
-    int order = n * nsp;
-    herm_complete<T>(s, order, H, ldh, 0, A, order, 0, 1, info);
-    // W = (I (x) Linv) A : spin row-block b of W is Linv times row-block b of A
-    gemm<T>(s, OP_N, OP_N, n, order, n, 1.0, Linv, ldi, 0, A, order, (long)n * order, 0.0, W, order,
-            (long)n * order, nsp, nullptr, 0, UPLO_FULL, nullptr, TRI_A_LOWER);
-    // A = W (I (x) Linv)^H : spin column-block b of A is column-block b of W times Linv^H
-    gemm<T>(s, OP_N, OP_C, order, n, n, 1.0, W, order, n, Linv, ldi, 0, 0.0, A, order, n, nsp, nullptr, 0,
-            UPLO_FULL, nullptr, TRI_B_UPPER);
+void reduce_to_standard(hipStream_t s, int n, int nsp, int batch, const T* H, int ldh, long sH, const T* Linv,
+                        int ldi, long sL, T* A, T* W, int* info) {
+    const int order = n * nsp;
+    const long sA = (long)order * order;
+    herm_complete<T>(s, order, H, ldh, sH, A, order, sA, batch, info);
+    if (nsp == 1) {
+        // W = Linv A, A = W Linv^H for every matrix of the batch
+        gemm<T>(s, OP_N, OP_N, n, n, n, 1.0, Linv, ldi, sL, A, order, sA, 0.0, W, order, sA, batch, nullptr, 0,
+                UPLO_FULL, nullptr, TRI_A_LOWER);
+        gemm<T>(s, OP_N, OP_C, n, n, n, 1.0, W, order, sA, Linv, ldi, sL, 0.0, A, order, sA, batch, nullptr, 0,
+                UPLO_FULL, nullptr, TRI_B_UPPER);
+        return;
+    }
+    for (int b = 0; b < batch; ++b) {
+        const T* Lb = Linv + b * sL;
+        T* Ab = A + b * sA;
+        T* Wb = W + b * sA;
+        // W = (I (x) Linv) A : spin row-block r of W is Linv times row-block r of A
+        gemm<T>(s, OP_N, OP_N, n, order, n, 1.0, Lb, ldi, 0, Ab, order, (long)n * order, 0.0, Wb, order,
+                (long)n * order, nsp, nullptr, 0, UPLO_FULL, nullptr, TRI_A_LOWER);
+        // A = W (I (x) Linv)^H : spin column-block r of A is column-block r of W times Linv^H
+        gemm<T>(s, OP_N, OP_C, order, n, n, 1.0, Wb, order, n, Lb, ldi, 0, 0.0, Ab, order, n, nsp, nullptr, 0,
+                UPLO_FULL, nullptr, TRI_B_UPPER);
+    }
 }
 
 #define KS_INST(T)                                                                                 \
     template void potrf<T>(hipStream_t, int, T*, int, long, int, int*);                            \
     template void trsm_left<T>(hipStream_t, bool, int, int, const T*, int, long, T*, int, long, int); \
     template void herm_complete<T>(hipStream_t, int, const T*, int, long, T*, int, long, int, int*); \
-    template void reduce_to_standard<T>(hipStream_t, int, int, const T*, int, const T*, int, T*, T*, \
-                                        int*);                                                      \
+    template void reduce_to_standard<T>(hipStream_t, int, int, int, const T*, int, long, const T*, int, \
+                                        long, T*, T*, int*);                                        \
     template void tri_inverse<T>(hipStream_t, int, const T*, int, long, T*, long, int);
 KS_INST(double)
 KS_INST(cplx)

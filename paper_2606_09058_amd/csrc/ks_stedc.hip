@@ -20,11 +20,38 @@
 // Every size that depends on deflation stays on the device: kernels are
 // launched for the undeflated size and idle workgroups exit, so the whole
 // solve is enqueued without a host synchronisation.
+// A batch of tridiagonals of one order shares the tree and every launch: the
+// matrix index b is folded into the merge (group) index, G = b * nm + g, and
+// selects the matrix's slices of the vectors (stride n) and matrices (n^2).
 #include "ks_internal.hpp"
 
 namespace ks {
 
 constexpr double DEPS = 1.1102230246251565e-16;  // unit roundoff 2^-53
+
+// The slices of the merge work arrays that belong to matrix b of a batch
+// (kk, nrot and rho are indexed by the folded group index instead).
+__device__ inline DcWork dc_slice(DcWork w, int b, int n) {
+    long o = (long)b * n;
+    w.dw += o;
+    w.ds += o;
+    w.zs += o;
+    w.perm += o;
+    w.ndl += o;
+    w.dfl += o;
+    w.dfval += o;
+    w.dnd += o;
+    w.znd += o;
+    w.rot_idx += 2 * o;
+    w.rot_cs += 2 * o;
+    w.orig += o;
+    w.tau += o;
+    w.zhat += o;
+    w.cinv += o;
+    w.fval += o;
+    w.fsrc += o;
+    return w;
+}
 
 // ---------------------------------------------------------------- setup
 // dw = d with |e[m-1]| taken off both neighbours of every tear m; the tears are
@@ -43,6 +70,10 @@ __global__ void dc_init_kernel(int n, const double* d, const double* e, const in
                                double* dw) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const long o = (long)blockIdx.y * n;
+    d += o;
+    e += o;
+    dw += o;
     double v = d[i];
     if (i > 0 && is_leaf_start(leaf_lo, nleaf, i)) v -= fabs(e[i - 1]);
     if (i + 1 < n && is_leaf_start(leaf_lo, nleaf, i + 1)) v -= fabs(e[i]);
@@ -62,6 +93,13 @@ __global__ __launch_bounds__(64) void dc_leaf_kernel(int n, const int* leaf_lo, 
     __shared__ int any_rot;
     __shared__ double w[L];
     __shared__ int idx[L];
+    {
+        const long o = (long)blockIdx.y * n;
+        dw += o;
+        e += o;
+        lam += o;
+        Z += o * n;
+    }
     int lo = leaf_lo[blockIdx.x], hi = leaf_hi[blockIdx.x];
     int s = hi - lo;
     int t = threadIdx.x;
@@ -171,13 +209,16 @@ __global__ __launch_bounds__(64) void dc_leaf_kernel(int n, const int* leaf_lo, 
 
 // ---------------------------------------------------------------- merges
 // One workgroup per merge: form (D, z), merge-sort, deflate.
-__global__ __launch_bounds__(256) void dc_deflate_kernel(int n, const int* mlo, const int* mmid,
+__global__ __launch_bounds__(256) void dc_deflate_kernel(int n, int nm, const int* mlo, const int* mmid,
                                                          const int* mhi, const double* e,
                                                          const double* lam, const double* Z,
                                                          DcWork w) {
-    __shared__ double red[4];
     __shared__ double sd[64], sz[64];
-    int g = blockIdx.x;
+    const int G = blockIdx.x, g = G % nm, bm = G / nm;
+    w = dc_slice(w, bm, n);
+    e += (long)bm * n;
+    lam += (long)bm * n;
+    Z += (long)bm * n * n;
     int lo = mlo[g], mid = mmid[g], hi = mhi[g];
     int K0 = hi - lo, n1 = mid - lo;
     int t = threadIdx.x;
@@ -228,7 +269,6 @@ __global__ __launch_bounds__(256) void dc_deflate_kernel(int n, const int* mlo, 
     double tol = 0.0;
     for (int i = 0; i < 4; ++i) tol = fmax(tol, fmax(mx[0][i], mx[1][i]));
     tol *= 8.0 * DEPS;
-    (void)red;
     // sequential deflation scan, streamed through LDS in chunks of 64
     if (t < 64) {
         int K = 0, nd = 0, nrot = 0, pj = -1;
@@ -295,20 +335,22 @@ __global__ __launch_bounds__(256) void dc_deflate_kernel(int n, const int* mlo, 
                 w.znd[lo + K] = zpj;
                 ++K;
             }
-            w.kk[g] = K;
-            w.nrot[g] = nrot;
-            w.rho[g] = rho;
+            w.kk[G] = K;
+            w.nrot[G] = nrot;
+            w.rho[G] = rho;
         }
     }
 }
 
 // Apply the deflation rotations to the merge's columns of Z, one thread per row.
-__global__ __launch_bounds__(256) void dc_rotate_kernel(int n, const int* mlo, const int* mhi, DcWork w,
-                                                        double* Z) {
-    int g = blockIdx.y;
+__global__ __launch_bounds__(256) void dc_rotate_kernel(int n, int nm, const int* mlo, const int* mhi,
+                                                        DcWork w, double* Z) {
+    const int G = blockIdx.y, g = G % nm, bm = G / nm;
+    w = dc_slice(w, bm, n);
+    Z += (long)bm * n * n;
     int lo = mlo[g], hi = mhi[g];
     int r = lo + blockIdx.x * blockDim.x + threadIdx.x;
-    int nr = w.nrot[g];
+    int nr = w.nrot[G];
     if (r >= hi || nr == 0) return;
     double* zr = Z + (long)r * n + lo;
     for (int q = 0; q < nr; ++q) {
@@ -322,16 +364,17 @@ __global__ __launch_bounds__(256) void dc_rotate_kernel(int n, const int* mlo, c
 }
 
 // Secular equation: one wavefront per root.
-__global__ __launch_bounds__(256) void dc_secular_kernel(const int* mlo, DcWork w, int* info) {
-    int g = blockIdx.y;
+__global__ __launch_bounds__(256) void dc_secular_kernel(int n, int nm, const int* mlo, DcWork w, int* info) {
+    const int G = blockIdx.y, g = G % nm;
+    w = dc_slice(w, G / nm, n);
     int lo = mlo[g];
-    int K = w.kk[g];
+    int K = w.kk[G];
     int jr = blockIdx.x * 4 + (threadIdx.x >> 6);
     int lane = threadIdx.x & 63;
     if (jr >= K) return;
     const double* d = w.dnd + lo;
     const double* z = w.znd + lo;
-    double rho = w.rho[g];
+    double rho = w.rho[G];
     if (K == 1) {
         if (lane == 0) {
             w.orig[lo] = 0;
@@ -435,10 +478,11 @@ __global__ __launch_bounds__(256) void dc_secular_kernel(const int* mlo, DcWork 
 
 // Gu-Eisenstat: z_hat_i^2 = prod_j (x_j - d_i) / (rho prod_{j != i} (d_j - d_i)),
 // paired so that every factor lies in (0, 1].
-__global__ __launch_bounds__(256) void dc_zhat_kernel(const int* mlo, DcWork w) {
-    int g = blockIdx.y;
+__global__ __launch_bounds__(256) void dc_zhat_kernel(int n, int nm, const int* mlo, DcWork w) {
+    const int G = blockIdx.y, g = G % nm;
+    w = dc_slice(w, G / nm, n);
     int lo = mlo[g];
-    int K = w.kk[g];
+    int K = w.kk[G];
     int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     int lane = threadIdx.x & 63;
     if (i >= K) return;
@@ -453,16 +497,17 @@ __global__ __launch_bounds__(256) void dc_zhat_kernel(const int* mlo, DcWork w) 
     }
     p = wave_prod(p);
     if (lane == 0) {
-        double zh = sqrt(fabs(p / w.rho[g]));
+        double zh = sqrt(fabs(p / w.rho[G]));
         w.zhat[lo + i] = copysign(zh, w.znd[lo + i]);
     }
 }
 
 // 1/||u_j|| with u_ij = z_hat_i / (d_i - x_j).
-__global__ __launch_bounds__(256) void dc_colnorm_kernel(const int* mlo, DcWork w) {
-    int g = blockIdx.y;
+__global__ __launch_bounds__(256) void dc_colnorm_kernel(int n, int nm, const int* mlo, DcWork w) {
+    const int G = blockIdx.y, g = G % nm;
+    w = dc_slice(w, G / nm, n);
     int lo = mlo[g];
-    int K = w.kk[g];
+    int K = w.kk[G];
     int jr = blockIdx.x * 4 + (threadIdx.x >> 6);
     int lane = threadIdx.x & 63;
     if (jr >= K) return;
@@ -478,10 +523,12 @@ __global__ __launch_bounds__(256) void dc_colnorm_kernel(const int* mlo, DcWork 
 }
 
 // U block (K x K at (lo, lo), row stride n): U_ij = z_hat_i / (d_i - x_j) / ||u_j||.
-__global__ __launch_bounds__(256) void dc_ugen_kernel(int n, const int* mlo, DcWork w, double* U) {
-    int g = blockIdx.z;
+__global__ __launch_bounds__(256) void dc_ugen_kernel(int n, int nm, const int* mlo, DcWork w, double* U) {
+    const int G = blockIdx.z, g = G % nm, bm = G / nm;
+    w = dc_slice(w, bm, n);
+    U += (long)bm * n * n;
     int lo = mlo[g];
-    int K = w.kk[g];
+    int K = w.kk[G];
     int i = blockIdx.y;
     int jr = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= K || jr >= K) return;
@@ -492,11 +539,16 @@ __global__ __launch_bounds__(256) void dc_ugen_kernel(int n, const int* mlo, DcW
 
 // Gather: Qp columns [0, K) = undeflated columns of Z in secular order; Z2
 // columns [K, K0) = deflated columns (both at the merge's block).
-__global__ __launch_bounds__(256) void dc_gather_kernel(int n, const int* mlo, const int* mhi, DcWork w,
-                                                        const double* Z, double* Qp, double* Z2) {
-    int g = blockIdx.z;
+__global__ __launch_bounds__(256) void dc_gather_kernel(int n, int nm, const int* mlo, const int* mhi,
+                                                        DcWork w, const double* Z, double* Qp, double* Z2) {
+    const int G = blockIdx.z, g = G % nm, bm = G / nm;
+    w = dc_slice(w, bm, n);
+    const long o = (long)bm * n * n;
+    Z += o;
+    Qp += o;
+    Z2 += o;
     int lo = mlo[g], hi = mhi[g];
-    int K0 = hi - lo, K = w.kk[g];
+    int K0 = hi - lo, K = w.kk[G];
     int r = lo + blockIdx.y;
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= hi || c >= K0) return;
@@ -511,11 +563,11 @@ __global__ __launch_bounds__(256) void dc_gather_kernel(int n, const int* mlo, c
 
 // Final order: value of merged column c is x_c (c < K) or the deflated value;
 // stable rank sort; lam[lo + rank] = value, src[lo + rank] = c.
-__global__ __launch_bounds__(256) void dc_rank_kernel(const int* mlo, const int* mhi, DcWork w,
-                                                      double* lam) {
-    int g = blockIdx.y;
+__global__ __launch_bounds__(256) void dc_rank_kernel(int n, int nm, const int* mlo, const int* mhi, DcWork w) {
+    const int G = blockIdx.y, g = G % nm;
+    w = dc_slice(w, G / nm, n);
     int lo = mlo[g], hi = mhi[g];
-    int K0 = hi - lo, K = w.kk[g];
+    int K0 = hi - lo, K = w.kk[G];
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= K0) return;
     const double* d = w.dnd + lo;
@@ -532,9 +584,14 @@ __global__ __launch_bounds__(256) void dc_rank_kernel(const int* mlo, const int*
     w.fsrc[lo + rk] = c;
 }
 
-__global__ __launch_bounds__(256) void dc_permute_kernel(int n, const int* mlo, const int* mhi, DcWork w,
-                                                         const double* Z2, double* Z, double* lam) {
-    int g = blockIdx.z;
+__global__ __launch_bounds__(256) void dc_permute_kernel(int n, int nm, const int* mlo, const int* mhi,
+                                                         DcWork w, const double* Z2, double* Z, double* lam) {
+    const int G = blockIdx.z, g = G % nm, bm = G / nm;
+    w = dc_slice(w, bm, n);
+    const long o = (long)bm * n * n;
+    Z2 += o;
+    Z += o;
+    lam += (long)bm * n;
     int lo = mlo[g], hi = mhi[g];
     int K0 = hi - lo;
     int r = lo + blockIdx.y;
@@ -544,31 +601,32 @@ __global__ __launch_bounds__(256) void dc_permute_kernel(int n, const int* mlo, 
     if (r == lo) lam[lo + p] = w.fval[lo + p];
 }
 
-void stedc(hipStream_t s, const DcTree& tr, const double* d, const double* e, double* lam, double* Z,
-           double* Z2, double* U, double* Qp, DcWork& w, int* info) {
-    int n = tr.n;
-    fill_zero<double>(s, Z, (long)n * n);
-    hipLaunchKernelGGL(dc_init_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, n, d, e, tr.d_leaf_lo, tr.nleaf, w.dw);
-    hipLaunchKernelGGL(dc_leaf_kernel, dim3(tr.nleaf), dim3(64), 0, s, n, tr.d_leaf_lo, tr.d_leaf_hi,
+void stedc(hipStream_t s, const DcTree& tr, int batch, const double* d, const double* e, double* lam,
+           double* Z, double* Z2, double* U, double* Qp, DcWork& w, int* info) {
+    const int n = tr.n, B = batch;
+    fill_zero<double>(s, Z, (long)n * n * B);
+    hipLaunchKernelGGL(dc_init_kernel, dim3(cdiv(n, 256), B), dim3(256), 0, s, n, d, e, tr.d_leaf_lo, tr.nleaf,
+                       w.dw);
+    hipLaunchKernelGGL(dc_leaf_kernel, dim3(tr.nleaf, B), dim3(64), 0, s, n, tr.d_leaf_lo, tr.d_leaf_hi,
                        (const double*)w.dw, e, lam, Z, info);
     for (int l = tr.depth - 1; l >= 0; --l) {
-        int nm = 1 << l;
-        int off = nm - 1;
+        const int nm = 1 << l, NG = nm * B;
+        const int off = nm - 1;
         const int* mlo = tr.d_mlo + off;
         const int* mmid = tr.d_mmid + off;
         const int* mhi = tr.d_mhi + off;
-        int mk = tr.max_k0[l];
-        hipLaunchKernelGGL(dc_deflate_kernel, dim3(nm), dim3(256), 0, s, n, mlo, mmid, mhi, e, lam, Z, w);
-        hipLaunchKernelGGL(dc_rotate_kernel, dim3(cdiv(mk, 256), nm), dim3(256), 0, s, n, mlo, mhi, w, Z);
-        hipLaunchKernelGGL(dc_secular_kernel, dim3(cdiv(mk, 4), nm), dim3(256), 0, s, mlo, w, info);
-        hipLaunchKernelGGL(dc_zhat_kernel, dim3(cdiv(mk, 4), nm), dim3(256), 0, s, mlo, w);
-        hipLaunchKernelGGL(dc_colnorm_kernel, dim3(cdiv(mk, 4), nm), dim3(256), 0, s, mlo, w);
-        hipLaunchKernelGGL(dc_ugen_kernel, dim3(cdiv(mk, 256), mk, nm), dim3(256), 0, s, n, mlo, w, U);
-        hipLaunchKernelGGL(dc_gather_kernel, dim3(cdiv(mk, 256), mk, nm), dim3(256), 0, s, n, mlo, mhi, w,
+        const int mk = tr.max_k0[l];
+        hipLaunchKernelGGL(dc_deflate_kernel, dim3(NG), dim3(256), 0, s, n, nm, mlo, mmid, mhi, e, lam, Z, w);
+        hipLaunchKernelGGL(dc_rotate_kernel, dim3(cdiv(mk, 256), NG), dim3(256), 0, s, n, nm, mlo, mhi, w, Z);
+        hipLaunchKernelGGL(dc_secular_kernel, dim3(cdiv(mk, 4), NG), dim3(256), 0, s, n, nm, mlo, w, info);
+        hipLaunchKernelGGL(dc_zhat_kernel, dim3(cdiv(mk, 4), NG), dim3(256), 0, s, n, nm, mlo, w);
+        hipLaunchKernelGGL(dc_colnorm_kernel, dim3(cdiv(mk, 4), NG), dim3(256), 0, s, n, nm, mlo, w);
+        hipLaunchKernelGGL(dc_ugen_kernel, dim3(cdiv(mk, 256), mk, NG), dim3(256), 0, s, n, nm, mlo, w, U);
+        hipLaunchKernelGGL(dc_gather_kernel, dim3(cdiv(mk, 256), mk, NG), dim3(256), 0, s, n, nm, mlo, mhi, w,
                            (const double*)Z, Qp, Z2);
-        gemm_grouped_dc(s, nm, mk, mlo, mhi, w.kk, Qp, U, Z2, n);
-        hipLaunchKernelGGL(dc_rank_kernel, dim3(cdiv(mk, 256), nm), dim3(256), 0, s, mlo, mhi, w, lam);
-        hipLaunchKernelGGL(dc_permute_kernel, dim3(cdiv(mk, 256), mk, nm), dim3(256), 0, s, n, mlo, mhi, w,
+        gemm_grouped_dc(s, nm, B, mk, mlo, mhi, w.kk, Qp, U, Z2, n);
+        hipLaunchKernelGGL(dc_rank_kernel, dim3(cdiv(mk, 256), NG), dim3(256), 0, s, n, nm, mlo, mhi, w);
+        hipLaunchKernelGGL(dc_permute_kernel, dim3(cdiv(mk, 256), mk, NG), dim3(256), 0, s, n, nm, mlo, mhi, w,
                            (const double*)Z2, Z, lam);
     }
 }

@@ -29,7 +29,7 @@ STATUS = {
 
 EXPORTS = ["ks_plan_create", "ks_plan_destroy", "ks_gevd", "ks_density", "ks_density_backward",
            "ks_plan_get_info", "ks_status_string", "ks_plan_workspace_bytes", "ks_plan_set_profiling",
-           "ks_plan_get_profile"]
+           "ks_plan_get_profile", "ks_plan_get_graph_stats"]
 
 
 class KSError(RuntimeError):
@@ -87,6 +87,8 @@ def lib():
         L.ks_plan_set_profiling.restype = I
         L.ks_plan_get_profile.argtypes = [P, ctypes.POINTER(Profile)]
         L.ks_plan_get_profile.restype = I
+        L.ks_plan_get_graph_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+        L.ks_plan_get_graph_stats.restype = I
         _lib = L
     return _lib
 
@@ -205,6 +207,12 @@ class Plan:
         pr = Profile()
         _check(lib().ks_plan_get_profile(self._h, ctypes.byref(pr)), "ks_plan_get_profile")
         return pr
+
+    def graph_stats(self):
+        """(captures, replays) of ks_gevd under KS_PLAN_GRAPH."""
+        c, r = ctypes.c_int64(0), ctypes.c_int64(0)
+        _check(lib().ks_plan_get_graph_stats(self._h, ctypes.byref(c), ctypes.byref(r)), "ks_plan_get_graph_stats")
+        return int(c.value), int(r.value)
 
     def get_info(self):
         """Synchronize and return (status, info); clears the device info word."""

@@ -98,6 +98,79 @@ def test_kpoint_batch_common_mu():
         assert res < RES_TOL and orth < ORTH_TOL
 
 
+def _gevd(plan, H, S, il=1, iu=None):
+    eps = torch.empty(plan._vshape(), dtype=torch.float64, device="cuda")
+    C = torch.zeros(plan._mshape(), dtype=plan.mdtype, device="cuda")
+    plan.gevd(H, S, eps, C, il=il, iu=iu)
+    plan.check("gevd")
+    return host(eps), host(C)
+
+
+@pytest.mark.parametrize("kind", ["real", "complex", "noncollinear"])
+def test_batched_gevd_equals_single_solves_bitwise(kind):
+    """A batch of k-points goes through the same kernels with the matrix index in
+    the grid, and nothing in the arithmetic depends on the batch size, so every
+    matrix's eigenvalues and eigenvectors equal those of its own solve bit for
+    bit; the window [il, iu] is taken from the same full decomposition."""
+    announce("batched vs single", kind)
+    if kind == "noncollinear":
+        probs = [I.noncollinear(seed=s, nx=3, ny=1, nz=1, lam_max=0.2) for s in (1, 2, 3)]
+    else:
+        probs = [I.toy(seed=s, natoms=12, norb=13, edge=12.0, n_electrons=40.0, kT=0.01,
+                       phases=kind == "complex") for s in (5, 6, 7, 8, 9)]
+    p0 = probs[0]
+    cplx = np.iscomplexobj(p0.H)
+    B = len(probs)
+    H = dev(np.stack([p.H for p in probs]))
+    S = dev(np.stack([p.S.astype(p0.H.dtype) for p in probs]))
+    for il, iu in [(1, None), (3, p0.order // 2)]:
+        plan = ks.Plan(p0.n, batch=B, complex=cplx, noncollinear=p0.nsp == 2)
+        eb, Cb = _gevd(plan, H, S, il, iu)
+        for b, p in enumerate(probs):
+            one = ks.Plan(p.n, batch=1, complex=cplx, noncollinear=p.nsp == 2)
+            e1, C1 = _gevd(one, dev(p.H), dev(p.S.astype(p0.H.dtype)), il, iu)
+            assert np.array_equal(eb[b], e1)
+            assert np.array_equal(Cb[b], C1)
+        res, orth = residuals(p0.H, p0.S, eb[0], Cb[0], p0.nsp)
+        if iu is None:
+            assert res < RES_TOL and orth < ORTH_TOL
+
+
+def test_graph_replay_matches_eager_solves():
+    """KS_PLAN_GRAPH: the first ks_gevd call of an argument set is captured and
+    later ones replay it.  Every replay, with eager work and synchronisation in
+    between and new contents written into the same input buffers, must give the
+    eager plan's results bit for bit; a new argument set is captured afresh."""
+    announce("graph replay")
+    stream = torch.cuda.Stream()
+    probs = [I.kpoint_batch(natoms=5, norb=13, kgrid=(2, 1, 1), seed=s) for s in (0, 1, 2)]
+    p0 = probs[0]
+    with torch.cuda.stream(stream):
+        gplan = ks.Plan(p0.n, batch=p0.batch, complex=True, stream=stream, flags=ks.KS_PLAN_GRAPH)
+        eplan = ks.Plan(p0.n, batch=p0.batch, complex=True, stream=stream)
+        H = dev(p0.H)
+        S = dev(p0.S.astype(p0.H.dtype))
+        eps = torch.empty(gplan._vshape(), dtype=torch.float64, device="cuda")
+        C = torch.zeros(gplan._mshape(), dtype=torch.complex128, device="cuda")
+        for rep in range(4):
+            p = probs[rep % len(probs)]
+            H.copy_(dev(p.H))
+            S.copy_(dev(p.S.astype(p.H.dtype)))
+            gplan.gevd(H, S, eps, C)
+            _ = (H.abs() * 2.0).sum().item()  # eager work between replays
+            stream.synchronize()
+            ge, gC = host(eps).copy(), host(C).copy()
+            ee, eC = _gevd(eplan, H, S)
+            assert np.array_equal(ge, ee), rep
+            assert np.array_equal(gC, eC), rep
+        assert gplan.graph_stats() == (1, 3)
+        eps2 = torch.empty_like(eps)
+        gplan.gevd(H, S, eps2, C)  # another output buffer: a new capture
+        stream.synchronize()
+        assert gplan.graph_stats() == (2, 3)
+        assert np.array_equal(host(eps2), host(eps))
+
+
 def test_window_and_reuse_of_S():
     """Eigenvectors il..iu only (the occupied window): same density; second call
     with KS_REUSE_S (cached Cholesky factor) gives identical results."""
