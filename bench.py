@@ -26,6 +26,8 @@ WORKLOADS = {
     "noncollinear9984": "2N=9984 complex Hermitian spinor (384 atoms x 13 orbitals), overlap S(x)I2, "
                         "1536 electrons, kT=0.01 Ha, all eigenvectors",
     "toy64": "N=64 real symmetric toy (8 atoms x 8 orbitals), 32 electrons, kT=0.01 Ha",
+    "kpoints16x1300": "16 k-points x N=1300 complex Hermitian (100-atom cell, 27 lattice vectors), "
+                      "400 electrons, kT=0.01 Ha, one common Fermi level, all k in each launch",
 }
 
 
@@ -66,6 +68,9 @@ def main():
     ap.add_argument("--stride", type=int, default=16, help="sample every n-th matrix-vector launch")
     ap.add_argument("--cpu-sample", type=int, default=1300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the FP64-vs-mixed comparison on the occupied window")
+    ap.add_argument("--graph", action="store_true", help="plan with KS_PLAN_GRAPH (capture once, replay)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -82,24 +87,26 @@ def main():
     torch.cuda.set_device(0)
     p = I.workload(args.workload)
     cplx = np.iscomplexobj(p.H)
-    plan = ks.Plan(p.n, complex=cplx, noncollinear=p.nsp == 2)
+    stream = torch.cuda.Stream() if args.graph else torch.cuda.current_stream()
+    torch.cuda.set_stream(stream)
+    plan = ks.Plan(p.n, batch=p.batch, complex=cplx, noncollinear=p.nsp == 2, stream=stream,
+                   flags=ks.KS_PLAN_GRAPH if args.graph else 0)
     H = torch.from_numpy(p.H).cuda()
     S = torch.from_numpy(p.S.astype(p.H.dtype)).cuda()
-    eps = torch.empty(p.order, dtype=torch.float64, device="cuda")
-    C = torch.empty((p.order, p.order), dtype=plan.mdtype, device="cuda")
+    eps = torch.empty(plan._vshape(), dtype=torch.float64, device="cuda")
+    C = torch.empty(plan._mshape(), dtype=plan.mdtype, device="cuda")
     rho = torch.empty_like(C)
     mu = torch.empty(1, dtype=torch.float64, device="cuda")
     eband = torch.empty(1, dtype=torch.float64, device="cuda")
-    occ = torch.empty(p.order, dtype=torch.float64, device="cuda")
+    occ = torch.empty(plan._vshape(), dtype=torch.float64, device="cuda")
 
     def step(reuse=False):
         plan.gevd(H, S, eps, C, reuse_s=reuse)
-        plan.density(eps, C, p.n_electrons, p.kT, rho, mu, eband, occ=occ)
+        plan.density(eps, C, p.n_electrons, p.kT, rho, mu, eband, occ=occ, kweights=p.weights)
 
     for _ in range(args.warmup):
         step()
     plan.check("warmup")
-    stream = torch.cuda.current_stream()
     plan.get_profile()  # clear
     plan.set_profiling(True, args.stride)
 
@@ -129,13 +136,16 @@ def main():
     plan.check("warm steps")
 
     # cheap property checks of the last solve
-    tr = float((rho * S.to(rho.dtype).T).sum().real.item())
-    m_occ = int((occ > 2e-15 * p.g).sum().item())
-    flops = nominal_flops(p.order, p.order, m_occ, cplx, p.n)
+    if p.batch == 1:
+        tr = float((rho * S.to(rho.dtype).T).sum().real.item())
+    else:
+        w = torch.tensor(p.weights, dtype=torch.float64, device="cuda")
+        tr = float((w * (rho * S.to(rho.dtype).transpose(1, 2)).sum(dim=(1, 2)).real).sum().item())
+    m_occ = int((occ > 2e-15 * p.g).sum(dim=-1).max().item())
+    flops = p.batch * nominal_flops(p.order, p.order, m_occ, cplx, p.n)
     hemv_avg_us = 1e3 * prof.hemv_ms / max(1, prof.hemv_launches)
     hemv_gbs = prof.hemv_bytes / max(1e-12, prof.hemv_ms * 1e-3) / 1e9
-    phases = {nm: prof.phase_ms[i] / args.steps for i, nm in enumerate(
-        ["cholesky", "reduce", "tridiag", "dc", "backtransform", "density", "adjoint"])}
+    phases = phase_dict(prof, args.steps)
     out = {
         "metric": "GEVD+density s/solve & TFLOP/s, N=6656 real, 2N=9984 cplx; mixed vs FP64",
         "value": ms / 1e3,
@@ -150,8 +160,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": args.workload + ": " + WORKLOADS[args.workload], "form": "fp64",
-                   "order": p.order, "electrons": p.n_electrons, "kT": p.kT, "eigenvectors": p.order,
-                   "occupied_window": m_occ},
+                   "order": p.order, "batch": p.batch, "electrons": p.n_electrons, "kT": p.kT,
+                   "eigenvectors": p.order, "occupied_window": m_occ, "graph": bool(args.graph)},
         "tflops": flops / (ms * 1e-3) / 1e12,
         "tflops_frac_fp64_peak": flops / (ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
         "nominal_flops": flops,
@@ -167,9 +177,71 @@ def main():
         "checks": {"trace_rho_S_minus_Ne": tr - p.n_electrons, "mu": float(mu.item()),
                    "eband": float(eband.item())},
     }
+    if p.batch > 1:
+        out["ms_per_kpoint"] = ms / p.batch
+    if not args.no_mixed:
+        out["precision_comparison"] = compare_precisions(p, H, S, eps, mu, args.steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_sample)
     print(json.dumps(out), flush=True)
+
+
+def phase_dict(prof, steps):
+    names = ["cholesky", "reduce", "tridiag", "dc", "backtransform", "density", "adjoint", "refine"]
+    return {nm: prof.phase_ms[i] / steps for i, nm in enumerate(names)}
+
+
+def compare_precisions(p, H, S, eps_all, mu, steps, buffer_ha=0.4):
+    """FP64 and mixed forms on the same window [1, iu]: every state below
+    mu + 0.4 Ha (40 kT above the Fermi level, so the refined subspace is
+    separated from the rest).  Both solve the window only (eigenvectors
+    1..iu) and build the density from it; the mixed eigenvalues and density
+    are compared with the FP64 ones of the same GPU."""
+    import torch
+    from paper_2606_09058_amd import ks
+    cplx = torch.is_complex(H)
+    iu = int((eps_all < float(mu.item()) + buffer_ha).sum(dim=-1).max().item())
+    res = {"window": [1, iu], "buffer_ha": buffer_ha}
+    outs = {}
+    for form, prec in (("fp64", ks.KS_FP64), ("mixed", ks.KS_MIXED)):
+        plan = ks.Plan(p.n, batch=p.batch, complex=cplx, noncollinear=p.nsp == 2, precision=prec)
+        eps = torch.empty(plan._vshape(), dtype=torch.float64, device="cuda")
+        C = torch.zeros(plan._mshape(), dtype=plan.mdtype, device="cuda")
+        rho = torch.empty_like(C)
+        m = torch.empty(1, dtype=torch.float64, device="cuda")
+        eb = torch.empty(1, dtype=torch.float64, device="cuda")
+
+        def step():
+            plan.gevd(H, S, eps, C, il=1, iu=iu)
+            plan.density(eps, C, p.n_electrons, p.kT, rho, m, eb, il=1, iu=iu, kweights=p.weights)
+        step()
+        plan.check(form + " window warm-up")
+        plan.get_profile()
+        plan.set_profiling(True, 1 << 30)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            step()
+        e1.record()
+        torch.cuda.synchronize()
+        prof = plan.get_profile()
+        plan.set_profiling(False)
+        plan.check(form + " window steps")
+        res[form + "_s_per_solve"] = e0.elapsed_time(e1) / steps / 1e3
+        res[form + "_phases_ms"] = phase_dict(prof, steps)
+        outs[form] = (eps.clone(), rho.clone(), float(eb.item()))
+        del plan
+    ef, rf, bf = outs["fp64"]
+    em, rm, bm = outs["mixed"]
+    res["speedup_mixed_vs_fp64"] = res["fp64_s_per_solve"] / res["mixed_s_per_solve"]
+    res["mixed_max_eig_err_window_vs_fp64"] = float((em[..., :iu] - ef[..., :iu]).abs().max().item())
+    res["mixed_max_eig_err_outside_vs_fp64"] = float((em[..., iu:] - ef[..., iu:]).abs().max().item()) \
+        if iu < p.order else 0.0
+    res["mixed_max_rho_err_vs_fp64"] = float((rm - rf).abs().max().item())
+    res["mixed_eband_err_vs_fp64"] = abs(bm - bf)
+    return res
 
 
 if __name__ == "__main__":

@@ -76,7 +76,13 @@ enum { KS_FP64 = 0, KS_MIXED = 1 };                  /* arithmetic of the solve 
  * different set is captured afresh.  Needs a non-NULL stream.  The batched
  * launches (all k-points of the plan in each kernel) are the same either way,
  * so results do not depend on the flag. */
-enum { KS_PLAN_GRAPH = 1u };
+enum { KS_PLAN_GRAPH = 1u,
+       /* KS_PLAN_AUTOTUNE: at ks_plan_create, time the candidate tile shapes of
+        * the tridiagonalisation's symmetric product (tiles per workgroup) on the
+        * plan's own order and batch, and keep the fastest (synchronous, a few
+        * milliseconds; without the flag a fixed default is used).  The choice
+        * changes only the grouping of partial sums, not the algorithm. */
+       KS_PLAN_AUTOTUNE = 2u };
 enum { KS_REUSE_S = 1u };                            /* ks_gevd flags                */
 
 typedef struct ks_plan ks_plan; /* opaque: workspace, cached Cholesky factor, info */
@@ -155,7 +161,9 @@ ks_status ks_density_backward(ks_plan* plan, const double* eps, const void* C, c
  * event records per phase; keep it off for plain timing. */
 enum {
     KS_PHASE_CHOLESKY = 0, KS_PHASE_REDUCE = 1, KS_PHASE_TRIDIAG = 2, KS_PHASE_DC = 3,
-    KS_PHASE_BACKTR = 4, KS_PHASE_DENSITY = 5, KS_PHASE_ADJOINT = 6, KS_NPHASE = 7
+    KS_PHASE_BACKTR = 4, KS_PHASE_DENSITY = 5, KS_PHASE_ADJOINT = 6,
+    KS_PHASE_REFINE = 7,      /* KS_MIXED: correction sweeps + Rayleigh-Ritz        */
+    KS_NPHASE = 8
 };
 typedef struct {
     double phase_ms[8];       /* summed over the calls since the last read          */
@@ -172,6 +180,16 @@ ks_status ks_plan_set_profiling(ks_plan* plan, int32_t enable, int32_t stride);
 /* Synchronize the plan's stream, fill *out with what was recorded since the last
  * read, and clear it. */
 ks_status ks_plan_get_profile(ks_plan* plan, ks_profile* out);
+
+/* The tile shape in use and, under KS_PLAN_AUTOTUNE, what was measured:
+ * ms[i] is the time of the timing launches with cand[i] tiles per workgroup. */
+typedef struct {
+    int32_t tiles_per_workgroup;
+    int32_t ncand;
+    int32_t cand[4];
+    double  ms[4];
+} ks_tuning;
+ks_status ks_plan_get_tuning(ks_plan* plan, ks_tuning* out);
 
 /* Graph use under KS_PLAN_GRAPH: how many argument sets were captured and how
  * many ks_gevd calls replayed a captured graph.  Host-only. */

@@ -16,7 +16,8 @@
 extern "C" {
 #endif
 
-/* C = alpha op(A) op(B) + beta C; dtype 0 real / 1 complex; op 0 = N, 1 = T,
+/* C = alpha op(A) op(B) + beta C; dtype 0 real / 1 complex (FP64), 2 real /
+ * 3 complex (FP32 on the FP32 matrix cores, FP32 accumulation); op 0 = N, 1 = T,
  * 2 = conjugate transpose; lower != 0 writes only the lower triangle of C. */
 int32_t ks_test_gemm(int32_t dtype, int32_t opa, int32_t opb, int32_t m, int32_t n, int32_t k,
                      double alpha, const void* A, int32_t lda, const void* B, int32_t ldb, double beta,
@@ -41,6 +42,9 @@ int32_t ks_test_hetrd(int32_t dtype, int32_t n, void* A, double* d, double* e, c
  * with A[i][0] = 100 i, A[i][1] = 1, B[0][j] = 1, B[1][j] = j (other k zero), so
  * D[i][j] = 100 i + j; out[lane * 4 + r] = accumulator register r of each lane. */
 int32_t ks_test_mfma_layout(double* out, void* stream);
+
+/* The same probe for one v_mfma_f32_16x16x4_f32 (FP32 values, D[i][j] = 100 i + j). */
+int32_t ks_test_mfma_layout32(float* out, void* stream);
 
 #ifdef __cplusplus
 }

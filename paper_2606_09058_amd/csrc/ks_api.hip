@@ -58,6 +58,22 @@ struct ks_plan {
         }
     };
     GraphKey gkey{};
+    ks_tuning tuning{};
+    // KS_MIXED: FP32 copies for the tridiagonalisation and back-transforms, FP64
+    // refinement buffers (all per matrix of the batch) and the Rayleigh-Ritz plan
+    void* A32 = nullptr;       // order x order   reduced matrix in FP32
+    void* W32 = nullptr;       // order x order   reflectors in FP32
+    void* tau32 = nullptr;     // order
+    float* Z32 = nullptr;      // order x order   tridiagonal eigenvectors in FP32
+    void* mY = nullptr;        // order x order   A X, then X y
+    void* mR = nullptr;        // order x order   residual, then the Ritz vectors y
+    void* mG = nullptr;        // order x order   X^H A X
+    void* mB = nullptr;        // order x order   X^H X
+    void* mP = nullptr;        // order x order   FP32 work
+    void* mP2 = nullptr;       // order x order   FP32 work
+    double* theta = nullptr;   // order           Ritz values
+    ks_plan* rr = nullptr;     // order-M plan of the Rayleigh-Ritz problem
+    int mixed_sweeps = 2;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     long graph_captures = 0, graph_replays = 0;
@@ -89,14 +105,13 @@ bool desc_valid(const ks_plan_desc* d) {
     long order = (long)d->n * (d->spin == KS_NONCOLLINEAR ? 2 : 1);
     if (order > 60000) return false;
     if (d->ld_h < order || d->ld_s < d->n) return false;
-    if (d->flags & ~(uint32_t)KS_PLAN_GRAPH) return false;
+    if (d->flags & ~(uint32_t)(KS_PLAN_GRAPH | KS_PLAN_AUTOTUNE)) return false;
     return true;
 }
 
 ks_status desc_supported(const ks_plan_desc* d) {
     if ((d->flags & KS_PLAN_GRAPH) && d->stream == nullptr) return KS_ERR_NOT_SUPPORTED;  // no capture there
     if (d->spin == KS_NONCOLLINEAR && d->dtype != KS_COMPLEX128) return KS_ERR_NOT_SUPPORTED;
-    if (d->precision != KS_FP64) return KS_ERR_NOT_SUPPORTED;
     if (d->batch > MAX_KW) return KS_ERR_NOT_SUPPORTED;
     return KS_OK;
 }
@@ -125,7 +140,7 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
     size_t oInfo = L.take(2 * sizeof(int));
     size_t oKwin = L.take(sizeof(int));
     // tridiagonalisation (per matrix of the batch)
-    size_t ntl = (order + HETRD_TILE - 1) / HETRD_TILE, nchl = (ntl + HETRD_SCH - 1) / HETRD_SCH;
+    size_t ntl = (order + HETRD_TILE - 1) / HETRD_TILE, nchl = (ntl + HETRD_SCH_MIN - 1) / HETRD_SCH_MIN;
     size_t hVW = order * 2 * nb, hX = order, hPQ = ntl * (1 + 2 * nb), hPR = ntl * nchl * HETRD_TILE;
     size_t hPC = ntl * ntl * HETRD_TILE, hPV = ntl * nchl, hPQv = 2 + 2 * nb;
     size_t oVW = L.take(B * hVW * es), oWV = L.take(B * hVW * es);
@@ -153,6 +168,26 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
     size_t oT1 = L.take((nm + 1) * sizeof(int)), oT2 = L.take((nm + 1) * sizeof(int));
     size_t oT3 = L.take((nm + 1) * sizeof(int));
     size_t oL1 = L.take(nl * sizeof(int)), oL2 = L.take(nl * sizeof(int));
+    // mixed precision (only when asked for)
+    const bool mixed = d->precision == KS_MIXED;
+    const size_t es32 = es / 2, mat = order * order;
+    size_t oA32 = 0, oW32 = 0, oTau32 = 0, oZ32 = 0, oMY = 0, oMR = 0, oMG = 0, oMB = 0, oMP = 0, oMP2 = 0;
+    size_t oTh = 0, oVWl = 0, oWVl = 0;
+    if (mixed) {
+        oA32 = L.take(B * mat * es32);
+        oW32 = L.take(B * mat * es32);
+        oTau32 = L.take(B * order * es32);
+        oZ32 = L.take(B * mat * 4);
+        oMY = L.take(B * mat * es);
+        oMR = L.take(B * mat * es);
+        oMG = L.take(B * mat * es);
+        oMB = L.take(B * mat * es);
+        oMP = L.take(B * mat * es32);
+        oMP2 = L.take(B * mat * es32);
+        oTh = L.take(B * order * 8);
+        oVWl = L.take(B * hVW * es32);
+        oWVl = L.take(B * hVW * es32);
+    }
     size_t total = L.off;
     if (!p) return total;
     char* b = p->base;
@@ -187,8 +222,23 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
         h.spcol = (long)hPC;
         h.spvav = (long)hPV;
         h.spq = (long)hPQv;
+        h.VWlo = mixed ? (void*)(b + oVWl) : nullptr;
+        h.WVlo = mixed ? (void*)(b + oWVl) : nullptr;
         h.prof = &p->prof;
     };
+    if (mixed) {
+        p->A32 = b + oA32;
+        p->W32 = b + oW32;
+        p->tau32 = b + oTau32;
+        p->Z32 = (float*)(b + oZ32);
+        p->mY = b + oMY;
+        p->mR = b + oMR;
+        p->mG = b + oMG;
+        p->mB = b + oMB;
+        p->mP = b + oMP;
+        p->mP2 = b + oMP2;
+        p->theta = (double*)(b + oTh);
+    }
     setH(p->hr, (double*)nullptr);
     setH(p->hc, (cplx*)nullptr);
     auto setB = [&](auto& w, auto* tag) {
@@ -263,6 +313,144 @@ KWeights make_weights(const ks_plan* p, const double* kw) {
 }
 
 template <typename T>
+BacktrWork<typename Lo<T>::type> lo_view(const BacktrWork<T>& w) {
+    using L = typename Lo<T>::type;
+    BacktrWork<L> v;
+    v.G = (L*)w.G;
+    v.Tf = (L*)w.Tf;
+    v.W1 = (L*)w.W1;
+    v.W2 = (L*)w.W2;
+    v.P = (L*)w.P;
+    v.pelems = w.pelems;
+    return v;
+}
+
+// C_sigma = Linv^H X_sigma per spin block for every matrix of the batch
+// (X: order x ncols, stride sX).
+template <typename T>
+void apply_linv_h(ks_plan* p, const T* Li, const T* X, long sX, int ncols, T* C) {
+    const int n = p->d.n, nsp = p->nsp, B = p->d.batch, ldh = p->d.ld_h, order = p->order;
+    const long sL = (long)n * n, sH = (long)order * ldh;
+    if (nsp == 1) {
+        gemm<T>(p->s, OP_C, OP_N, n, ncols, n, 1.0, Li, n, sL, X, ncols, sX, 0.0, C, ldh, sH, B, nullptr, 0,
+                UPLO_FULL, nullptr, TRI_A_UPPER);
+    } else {
+        for (int b = 0; b < B; ++b)
+            gemm<T>(p->s, OP_C, OP_N, n, ncols, n, 1.0, Li + b * sL, n, 0, X + b * sX, ncols, (long)n * ncols, 0.0,
+                    C + b * sH, ldh, (long)n * ldh, nsp, nullptr, 0, UPLO_FULL, nullptr, TRI_A_UPPER);
+    }
+}
+
+// The Rayleigh-Ritz plan of the mixed form: order m, same batch, type and
+// stream, FP64.  Created (or re-created for another m) outside any capture.
+ks_status ensure_rr_plan(ks_plan* p, int m) {
+    if (p->rr && p->rr->d.n == m) return KS_OK;
+    if (p->rr) {
+        ks_plan_destroy(p->rr);
+        p->rr = nullptr;
+    }
+    ks_plan_desc d{};
+    d.n = m;
+    d.batch = p->d.batch;
+    d.dtype = p->d.dtype;
+    d.spin = KS_COLLINEAR;
+    d.precision = KS_FP64;
+    d.ld_h = m;
+    d.ld_s = m;
+    d.stream = p->d.stream;
+    d.flags = 0;
+    return ks_plan_create(&d, &p->rr);
+}
+
+// Mixed-precision eigensolve after the Cholesky factor is in place:
+//   A (FP64, full) = Linv H Linv^H; its FP32 copy is tridiagonalised (trailing
+//   matrix in FP32, rank-2NB updates on the FP32 matrix cores, panels in FP64);
+//   divide and conquer in FP64 gives lam_hat and Z; the window vectors
+//   X = Q Z[:, window] come from the FP32 back-transform.  Refinement in FP64:
+//   mixed_sweeps correction sweeps X -= Q Z S(Z^T Q^H (A X - X lam_hat)) (the
+//   products with Q and Z in FP32), then Rayleigh-Ritz on span(X) with the
+//   plan's own FP64 solver.  Eigenvalues outside the window are lam_hat.
+template <typename T>
+ks_status gevd_mixed(ks_plan* p, const T* H, double* eps, T* C, int il, int iu) {
+    using L = typename Lo<T>::type;
+    hipStream_t s = p->s;
+    const int n = p->d.n, nsp = p->nsp, order = p->order, B = p->d.batch, ldh = p->d.ld_h;
+    const int M = iu - il + 1, c0 = il - 1;
+    const long sA = (long)order * order, sL = (long)n * n, sH = (long)order * ldh, sM = (long)order * M;
+    const long sMM = (long)M * M;
+    T* A = (T*)p->A;
+    T* W = (T*)p->W;
+    T* tau = (T*)p->tau;
+    T* Li = (T*)p->Li;
+    L* A32 = (L*)p->A32;
+    L* W32 = (L*)p->W32;
+    L* tau32 = (L*)p->tau32;
+    float* Z32 = p->Z32;
+    HetrdWork<T>& hw = *reinterpret_cast<HetrdWork<T>*>(is_cplx<T>::value ? (void*)&p->hc : (void*)&p->hr);
+    BacktrWork<T>& bw = *reinterpret_cast<BacktrWork<T>*>(is_cplx<T>::value ? (void*)&p->bc : (void*)&p->br);
+    BacktrWork<L> bl = lo_view(bw);
+    Prof& pf = p->prof;
+    if (!p->rr || p->rr->d.n != M) return KS_ERR_INVALID_ARG;  // prepared by ks_gevd
+    hipEvent_t e = pf.begin();
+    reduce_to_standard<T>(s, n, nsp, B, H, ldh, sH, Li, n, sL, A, W, p->info);
+    convert<T, L>(s, B, order, order, A, order, sA, A32, order, sA);
+    pf.end(KS_PHASE_REDUCE, e);
+    e = pf.begin();
+    hetrd<T, L>(s, order, A32, order, sA, B, p->dv, p->ev, tau, W, hw);
+    pf.end(KS_PHASE_TRIDIAG, e);
+    e = pf.begin();
+    stedc(s, p->tree, B, p->dv, p->ev, eps, p->Z, p->Z2, p->U, p->Qp, p->dc, p->info);
+    pf.end(KS_PHASE_DC, e);
+    e = pf.begin();
+    // FP32 copies of the reflectors and of Z, then X = Q Z[:, window] in FP32, widened into W
+    convert<T, L>(s, B, order, order, W, order, sA, W32, order, sA);
+    convert<T, L>(s, B, 1, order, tau, order, order, tau32, order, order);
+    convert<double, float>(s, B, order, order, p->Z, order, sA, Z32, order, sA);
+    L* P = (L*)p->mP;
+    load_z<L>(s, order, B, M, p->Z, c0, P, M, sM);
+    backtransform_q<L>(s, order, B, W32, tau32, M, P, M, sM, bl);
+    T* X = W;  // the FP64 reflectors are no longer needed
+    convert<L, T>(s, B, order, M, P, M, sM, X, M, sM);
+    pf.end(KS_PHASE_BACKTR, e);
+    e = pf.begin();
+    T* Y = (T*)p->mY;
+    T* R = (T*)p->mR;
+    const int wv = is_cplx<T>::value ? 2 : 1;  // a complex FP32 row of m entries is 2m floats
+    float* Pf = (float*)p->mP;
+    float* P2f = (float*)p->mP2;
+    for (int sw = 0; sw < p->mixed_sweeps; ++sw) {
+        gemm<T>(s, OP_N, OP_N, order, M, order, 1.0, A, order, sA, X, M, sM, 0.0, Y, M, sM, B);
+        residual<T>(s, B, order, M, Y, X, sM, eps, order, c0, R);
+        convert<T, L>(s, B, order, M, R, M, sM, P, M, sM);
+        backtransform_q<L>(s, order, B, W32, tau32, M, P, M, sM, bl, true);  // Q^H R
+        gemm<float>(s, OP_T, OP_N, order, wv * M, order, 1.0, Z32, order, sA, Pf, wv * M, wv * sM, 0.0, P2f,
+                    wv * M, wv * sM, B);  // Z^T Q^H R
+        correction_scale(s, B, order, M, wv, P2f, wv * sM, eps, order, c0, 1e-4);
+        gemm<float>(s, OP_N, OP_N, order, wv * M, order, 1.0, Z32, order, sA, P2f, wv * M, wv * sM, 0.0, Pf,
+                    wv * M, wv * sM, B);
+        backtransform_q<L>(s, order, B, W32, tau32, M, P, M, sM, bl);  // Q Z S(...)
+        sub_widened<T, L>(s, B, sM, X, P, sM);
+    }
+    // Rayleigh-Ritz: G = X^H A X, Bm = X^H X, G y = theta Bm y, X <- X y
+    T* G = (T*)p->mG;
+    T* Bm = (T*)p->mB;
+    gemm<T>(s, OP_N, OP_N, order, M, order, 1.0, A, order, sA, X, M, sM, 0.0, Y, M, sM, B);
+    gemm<T>(s, OP_C, OP_N, M, M, order, 1.0, X, M, sM, Y, M, sM, 0.0, G, M, sMM, B);
+    gemm<T>(s, OP_C, OP_N, M, M, order, 1.0, X, M, sM, X, M, sM, 0.0, Bm, M, sMM, B);
+    ks_status st = ks_gevd(p->rr, G, Bm, p->theta, R, 1, M, 0);
+    if (st != KS_OK) return st;
+    merge_info(s, p->rr->info, p->info);
+    gemm<T>(s, OP_N, OP_N, order, M, M, 1.0, X, M, sM, R, M, sMM, 0.0, Y, M, sM, B);
+    put_window(s, B, M, p->theta, M, eps, order, c0);
+    pf.end(KS_PHASE_REFINE, e);
+    e = pf.begin();
+    apply_linv_h<T>(p, Li, Y, sM, M, C);
+    pf.end(KS_PHASE_BACKTR, e);
+    if (hipPeekAtLastError() != hipSuccess) return KS_ERR_HIP;
+    return KS_OK;
+}
+
+template <typename T>
 ks_status gevd_impl(ks_plan* p, const T* H, const T* S, double* eps, T* C, int il, int iu,
                     uint32_t flags) {
     hipStream_t s = p->s;
@@ -284,6 +472,7 @@ ks_status gevd_impl(ks_plan* p, const T* H, const T* S, double* eps, T* C, int i
         pf.end(KS_PHASE_CHOLESKY, e);
         p->have_L = true;
     }
+    if (p->d.precision == KS_MIXED) return gevd_mixed<T>(p, H, eps, C, il, iu);
     // every step below takes the whole batch of k-points in each launch
     const int ncols = iu - il + 1;
     const long sA = (long)order * order, sL = (long)n * n, sH = (long)order * ldh;
@@ -291,7 +480,7 @@ ks_status gevd_impl(ks_plan* p, const T* H, const T* S, double* eps, T* C, int i
     reduce_to_standard<T>(s, n, nsp, B, H, ldh, sH, Li, n, sL, A, W, p->info);
     pf.end(KS_PHASE_REDUCE, e);
     e = pf.begin();
-    hetrd<T>(s, order, A, order, sA, B, p->dv, p->ev, tau, W, hw);
+    hetrd<T, T>(s, order, A, order, sA, B, p->dv, p->ev, tau, W, hw);
     pf.end(KS_PHASE_TRIDIAG, e);
     e = pf.begin();
     stedc(s, p->tree, B, p->dv, p->ev, eps, p->Z, p->Z2, p->U, p->Qp, p->dc, p->info);
@@ -300,14 +489,7 @@ ks_status gevd_impl(ks_plan* p, const T* H, const T* S, double* eps, T* C, int i
     // X = Q Z[:, il-1 : iu] in A (order x ncols per matrix), then C_sigma = Linv^H X_sigma per spin block
     load_z<T>(s, order, B, ncols, p->Z, il - 1, A, ncols, sA);
     backtransform_q<T>(s, order, B, W, tau, ncols, A, ncols, sA, bw);
-    if (nsp == 1) {
-        gemm<T>(s, OP_C, OP_N, n, ncols, n, 1.0, Li, n, sL, A, ncols, sA, 0.0, C, ldh, sH, B, nullptr, 0,
-                UPLO_FULL, nullptr, TRI_A_UPPER);
-    } else {
-        for (int b = 0; b < B; ++b)
-            gemm<T>(s, OP_C, OP_N, n, ncols, n, 1.0, Li + b * sL, n, 0, A + b * sA, ncols, (long)n * ncols, 0.0,
-                    C + b * sH, ldh, (long)n * ldh, nsp, nullptr, 0, UPLO_FULL, nullptr, TRI_A_UPPER);
-    }
+    apply_linv_h<T>(p, Li, A, sA, ncols, C);
     pf.end(KS_PHASE_BACKTR, e);
     if (hipPeekAtLastError() != hipSuccess) return KS_ERR_HIP;
     return KS_OK;
@@ -368,6 +550,26 @@ ks_status ks_plan_create(const ks_plan_desc* d, ks_plan** out) {
         delete p;
         return KS_ERR_HIP;
     }
+    p->tuning.tiles_per_workgroup = HETRD_SCH;
+    if (d->flags & KS_PLAN_AUTOTUNE) {
+        ks_tuning& tu = p->tuning;
+        const long sA = (long)p->order * p->order;
+        if (p->is_c)
+            tu.ncand = hetrd_tune<cplx>(p->s, p->order, (cplx*)p->A, p->order, sA, d->batch, p->dv, p->ev,
+                                        (cplx*)p->tau, p->hc, tu.cand, tu.ms, 3);
+        else
+            tu.ncand = hetrd_tune<double>(p->s, p->order, (double*)p->A, p->order, sA, d->batch, p->dv, p->ev,
+                                          (double*)p->tau, p->hr, tu.cand, tu.ms, 3);
+        int best = 0;
+        for (int c = 1; c < tu.ncand; ++c)
+            if (tu.ms[c] < tu.ms[best]) best = c;
+        if (tu.ncand > 0) tu.tiles_per_workgroup = tu.cand[best];
+        if (hipStreamSynchronize(p->s) != hipSuccess || tu.ncand == 0) {
+            ks_plan_destroy(p);
+            return KS_ERR_HIP;
+        }
+    }
+    p->hr.sch = p->hc.sch = p->tuning.tiles_per_workgroup;
     *out = p;
     return KS_OK;
 }
@@ -376,9 +578,16 @@ void ks_plan_destroy(ks_plan* p) {
     if (!p) return;
     (void)hipStreamSynchronize(p->s);
     graph_release(p);
+    if (p->rr) ks_plan_destroy(p->rr);
     if (p->base) (void)hipFree(p->base);
     if (p->adj) (void)hipFree(p->adj);
     delete p;
+}
+
+ks_status ks_plan_get_tuning(ks_plan* p, ks_tuning* out) {
+    if (!p || !out) return KS_ERR_INVALID_ARG;
+    *out = p->tuning;
+    return KS_OK;
 }
 
 ks_status ks_plan_get_graph_stats(ks_plan* p, int64_t* captures, int64_t* replays) {
@@ -395,6 +604,10 @@ ks_status ks_gevd(ks_plan* p, const void* H, const void* S, double* eps, void* C
     if (!(flags & KS_REUSE_S) && !S) return KS_ERR_INVALID_ARG;
     if ((flags & KS_REUSE_S) && !p->have_L) return KS_ERR_INVALID_ARG;
     if (!range_ok(p, il, iu)) return KS_ERR_INVALID_ARG;
+    if (p->d.precision == KS_MIXED) {
+        ks_status st = ensure_rr_plan(p, iu - il + 1);
+        if (st != KS_OK) return st;
+    }
     auto enqueue = [&]() -> ks_status {
         if (p->is_c)
             return gevd_impl<cplx>(p, (const cplx*)H, (const cplx*)S, eps, (cplx*)C, il, iu, flags);
@@ -558,11 +771,11 @@ void ks_internal_hetrd(ks_plan* p, void* A, double* d, double* e, const double* 
     int n = p->order;
     long sA = (long)n * n;
     if (p->is_c) {
-        hetrd<cplx>(p->s, n, (cplx*)A, n, sA, 1, d, e, (cplx*)p->tau, (cplx*)p->W, p->hc);
+        hetrd<cplx, cplx>(p->s, n, (cplx*)A, n, sA, 1, d, e, (cplx*)p->tau, (cplx*)p->W, p->hc);
         load_z<cplx>(p->s, n, 1, ncols, X, 0, (cplx*)Y, ncols, 0);
         backtransform_q<cplx>(p->s, n, 1, (cplx*)p->W, (cplx*)p->tau, ncols, (cplx*)Y, ncols, 0, p->bc);
     } else {
-        hetrd<double>(p->s, n, (double*)A, n, sA, 1, d, e, (double*)p->tau, (double*)p->W, p->hr);
+        hetrd<double, double>(p->s, n, (double*)A, n, sA, 1, d, e, (double*)p->tau, (double*)p->W, p->hr);
         load_z<double>(p->s, n, 1, ncols, X, 0, (double*)Y, ncols, 0);
         backtransform_q<double>(p->s, n, 1, (double*)p->W, (double*)p->tau, ncols, (double*)Y, ncols, 0, p->br);
     }

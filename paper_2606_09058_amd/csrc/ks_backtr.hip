@@ -27,9 +27,10 @@ __global__ void load_z_kernel(int n, int ncols, const double* Z, int c0, T* X, i
 // forming T: T^-1 = diag(1/tau) + strictly-upper(G) with G = V^H V, so W2 solves
 // the upper triangular system row by row from the bottom,
 // W2[i] = tau_i (W1[i] - sum_{l > i} G[i][l] W2[l])  (tau_i = 0 gives a zero row,
-// as the identity reflector contributes nothing).  One thread per column of W1;
-// the strict upper triangle of G is staged in LDS.
-template <typename T>
+// as the identity reflector contributes nothing).  ADJ: W2 = T^H W1 instead, with
+// (T^H)^-1 = diag(1/conj tau) + strictly-lower(G), solved from the top.  One
+// thread per column of W1; the strict triangle of G is staged in LDS.
+template <typename T, bool ADJ>
 __global__ __launch_bounds__(256) void apply_t_kernel(int jb, int ncols, const T* tau, long stau, const T* G,
                                                       const T* W1, T* W2) {
     constexpr int B = BACKTR_BT;
@@ -42,39 +43,58 @@ __global__ __launch_bounds__(256) void apply_t_kernel(int jb, int ncols, const T
     }
     __shared__ T sg[B * (B - 1) / 2];
     __shared__ T st[B];
+    // packed strict upper triangle of G: row i holds G[i][i+1 .. B-1]; for ADJ the
+    // same slots hold G[l][i] = conj(G[i][l]) read as the strict lower part
     for (int e = threadIdx.x; e < jb * jb; e += blockDim.x) {
         int i = e / jb, l = e % jb;
         if (l > i) sg[i * (2 * B - i - 1) / 2 + (l - i - 1)] = G[(long)i * jb + l];
     }
-    if (threadIdx.x < jb) st[threadIdx.x] = tau[threadIdx.x];
+    if (threadIdx.x < jb) st[threadIdx.x] = ADJ ? conj_(tau[threadIdx.x]) : tau[threadIdx.x];
     __syncthreads();
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncols) return;
     T w[B];
+    if constexpr (!ADJ) {
 #pragma unroll
-    for (int i = B - 1; i >= 0; --i) {
-        if (i < jb) {
-            T s = W1[(long)i * ncols + c];
-            const T* gi = sg + i * (2 * B - i - 1) / 2;
+        for (int i = B - 1; i >= 0; --i) {
+            if (i < jb) {
+                T s = W1[(long)i * ncols + c];
+                const T* gi = sg + i * (2 * B - i - 1) / 2;
 #pragma unroll
-            for (int l = i + 1; l < B; ++l)
-                if (l < jb) s -= gi[l - i - 1] * w[l];
-            w[i] = st[i] * s;
-            W2[(long)i * ncols + c] = w[i];
+                for (int l = i + 1; l < B; ++l)
+                    if (l < jb) s -= gi[l - i - 1] * w[l];
+                w[i] = st[i] * s;
+                W2[(long)i * ncols + c] = w[i];
+            }
+        }
+    } else {
+        // W2[i] = conj(tau_i) (W1[i] - sum_{l < i} conj(G[l][i]) W2[l])
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+            if (i < jb) {
+                T s = W1[(long)i * ncols + c];
+#pragma unroll
+                for (int l = 0; l < B; ++l)
+                    if (l < i) s -= conj_(sg[l * (2 * B - l - 1) / 2 + (i - l - 1)]) * w[l];
+                w[i] = st[i] * s;
+                W2[(long)i * ncols + c] = w[i];
+            }
         }
     }
 }
 
 template <typename T>
 void backtransform_q(hipStream_t s, int n, int batch, const T* Vall, const T* tau, int ncols, T* X, int ldx,
-                     long sX, BacktrWork<T>& w) {
+                     long sX, BacktrWork<T>& w, bool adjoint) {
     const int bt = BACKTR_BT;
     const int B = batch;
     const long sV = (long)n * n;
     int nref = n - 1;
     if (nref <= 0 || ncols <= 0) return;
     int nblk = cdiv(nref, bt);
-    for (int b = nblk - 1; b >= 0; --b) {
+    // Q X applies the blocks last to first; Q^H X = (H_{n-2}^H ... H_0^H) X applies them first to last
+    for (int q = 0; q < nblk; ++q) {
+        const int b = adjoint ? q : nblk - 1 - q;
         int b0 = b * bt;
         int jb = min(bt, nref - b0);
         int m = n - b0 - 1;
@@ -84,8 +104,12 @@ void backtransform_q(hipStream_t s, int n, int batch, const T* Vall, const T* ta
                        (long)jb * jb);
         gemm_splitk<T>(s, OP_C, OP_N, jb, ncols, m, 1.0, Vb, n, Xb, ldx, 0.0, w.W1, ncols, w.P, w.pelems, B, sV,
                        sX, (long)jb * ncols);
-        hipLaunchKernelGGL((apply_t_kernel<T>), dim3(cdiv(ncols, 256), B), dim3(256), 0, s, jb, ncols, tau + b0,
-                           (long)n, w.G, w.W1, w.W2);
+        if (adjoint)
+            hipLaunchKernelGGL((apply_t_kernel<T, true>), dim3(cdiv(ncols, 256), B), dim3(256), 0, s, jb, ncols,
+                               tau + b0, (long)n, w.G, w.W1, w.W2);
+        else
+            hipLaunchKernelGGL((apply_t_kernel<T, false>), dim3(cdiv(ncols, 256), B), dim3(256), 0, s, jb, ncols,
+                               tau + b0, (long)n, w.G, w.W1, w.W2);
         gemm<T>(s, OP_N, OP_N, m, ncols, jb, -1.0, Vb, n, sV, w.W2, ncols, (long)jb * ncols, 1.0, Xb, ldx, sX, B);
     }
 }
@@ -189,10 +213,12 @@ void fermi(hipStream_t s, int batch, int order, const double* eps, const KWeight
 
 #define KS_INST(T)                                                                                 \
     template void backtransform_q<T>(hipStream_t, int, int, const T*, const T*, int, T*, int, long,  \
-                                     BacktrWork<T>&);                                             \
+                                     BacktrWork<T>&, bool);                                       \
     template void load_z<T>(hipStream_t, int, int, int, const double*, int, T*, int, long);
 KS_INST(double)
 KS_INST(cplx)
+KS_INST(float)
+KS_INST(cplx32)
 #undef KS_INST
 
 }  // namespace ks

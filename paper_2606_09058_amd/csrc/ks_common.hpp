@@ -51,8 +51,50 @@ __host__ __device__ inline cplx inv_(cplx a) {
 }
 __host__ __device__ inline double inv_(double a) { return 1.0 / a; }
 
+// ---------------------------------------------------------------- single precision
+// Storage and arithmetic type of the mixed-precision trailing updates and
+// back-transform (FP32 on the matrix cores, FP32 accumulation).
+struct cplx32 {
+    float x, y;
+};
+__host__ __device__ inline cplx32 mk32(float r, float i) { cplx32 c; c.x = r; c.y = i; return c; }
+__host__ __device__ inline cplx32 operator+(cplx32 a, cplx32 b) { return mk32(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline cplx32 operator-(cplx32 a, cplx32 b) { return mk32(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline cplx32 operator-(cplx32 a) { return mk32(-a.x, -a.y); }
+__host__ __device__ inline cplx32 operator*(cplx32 a, cplx32 b) {
+    return mk32(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline cplx32 operator*(double s, cplx32 a) { return mk32((float)s * a.x, (float)s * a.y); }
+__host__ __device__ inline cplx32 operator*(cplx32 a, double s) { return mk32((float)s * a.x, (float)s * a.y); }
+__host__ __device__ inline cplx32& operator+=(cplx32& a, cplx32 b) { a.x += b.x; a.y += b.y; return a; }
+__host__ __device__ inline cplx32& operator-=(cplx32& a, cplx32 b) { a.x -= b.x; a.y -= b.y; return a; }
+__host__ __device__ inline float conj_(float a) { return a; }
+__host__ __device__ inline cplx32 conj_(cplx32 a) { return mk32(a.x, -a.y); }
+__host__ __device__ inline double re_(float a) { return a; }
+__host__ __device__ inline double re_(cplx32 a) { return a.x; }
+__host__ __device__ inline double im_(float) { return 0.0; }
+__host__ __device__ inline double im_(cplx32 a) { return a.y; }
+template <> __host__ __device__ inline float zero_<float>() { return 0.f; }
+template <> __host__ __device__ inline cplx32 zero_<cplx32>() { return mk32(0.f, 0.f); }
+template <> __host__ __device__ inline float from_re<float>(double r) { return (float)r; }
+template <> __host__ __device__ inline cplx32 from_re<cplx32>(double r) { return mk32((float)r, 0.f); }
+
+// FP64 <-> FP32 element conversions (round to nearest).
+__host__ __device__ inline float narrow(double a) { return (float)a; }
+__host__ __device__ inline cplx32 narrow(cplx a) { return mk32((float)a.x, (float)a.y); }
+__host__ __device__ inline double widen(float a) { return (double)a; }
+__host__ __device__ inline cplx widen(cplx32 a) { return mk((double)a.x, (double)a.y); }
+__host__ __device__ inline double widen(double a) { return a; }
+__host__ __device__ inline cplx widen(cplx a) { return a; }
+
+// The FP32 counterpart of an FP64 element type.
+template <typename T> struct Lo;
+template <> struct Lo<double> { using type = float; };
+template <> struct Lo<cplx> { using type = cplx32; };
+
 template <typename T> struct is_cplx { static constexpr bool value = false; };
 template <> struct is_cplx<cplx> { static constexpr bool value = true; };
+template <> struct is_cplx<cplx32> { static constexpr bool value = true; };
 
 // ---------------------------------------------------------------- wavefront
 constexpr int WAVE = 64;

@@ -1,4 +1,5 @@
-// ks_gemm.hip -- FP64 matrix-core (MFMA) GEMM for gfx950, real and complex.
+// ks_gemm.hip -- matrix-core (MFMA) GEMM for gfx950, real and complex, FP64
+// and (for the mixed-precision path) FP32 with FP32 accumulation.
 //
 // Every dense contraction of the eigensolver goes through this kernel: the
 // Cholesky trailing update, the triangular-solve updates of the reduction
@@ -10,9 +11,10 @@
 // LDS with a register prefetch of the next K step.  Each of the 4 waves owns
 // a 32 x 32 quadrant = 2 x 2 blocks of v_mfma_f64_16x16x4_f64.  Lane l of an
 // MFMA supplies A[l%16][l/16] and B[l/16][l%16] of the 16x4 / 4x16 operands
-// and receives D[l/16 + 4r][l%16] in accumulator register r.  A complex
-// product uses four real MFMAs (re*re - im*im, re*im + im*re) into separate
-// real and imaginary accumulators.
+// and receives D[l/16 + 4r][l%16] in accumulator register r.  The FP32 tile
+// uses v_mfma_f32_16x16x4_f32 with the same operand layout; its lane l receives
+// D[4 (l/16) + r][l%16].  A complex product uses four real MFMAs
+// (re*re - im*im, re*im + im*re) into separate real and imaginary accumulators.
 #include <algorithm>
 
 #include "ks_common.hpp"
@@ -20,11 +22,23 @@
 namespace ks {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int BM = 64, BN = 64, BK = 16, LPAD = 2;
 
 __device__ inline d4 mfma(double a, double b, d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline f4 mfma(float a, float b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Row (within a 16 x 16 block) of accumulator register r of a lane.
+template <typename T>
+__device__ inline int out_row(int lane, int r) {
+    if constexpr (sizeof(T) == 8 && !is_cplx<T>::value) return (lane >> 4) + 4 * r;  // f64 MFMA
+    else if constexpr (is_cplx<T>::value && sizeof(T) == 16) return (lane >> 4) + 4 * r;
+    else return 4 * (lane >> 4) + r;  // f32 MFMA
 }
 
 template <typename T, int OP>
@@ -47,7 +61,7 @@ __device__ inline void load_a(T (&r)[4], const T* A, int lda, int m, int K, int 
         for (int i = 0; i < 4; ++i) {
             bool ok = mm < m && kk + i < K;
             r[i] = ok ? ld_op<T, OPA>(A + (long)mm * lda + kk + i) : zero_<T>();
-            if (ks && ok) r[i] = r[i] * ks[kk + i];
+            if (ks && ok) r[i] = r[i] * ks[kk + i];  // (a narrowing multiply for FP32 types)
         }
     } else {
         int kk = k0 + (t >> 4), mm = m0 + (t & 15) * 4;
@@ -119,6 +133,14 @@ template <>
 struct Acc<cplx> {
     d4 re[2][2], im[2][2];
 };
+template <>
+struct Acc<float> {
+    f4 c[2][2];
+};
+template <>
+struct Acc<cplx32> {
+    f4 re[2][2], im[2][2];
+};
 
 __device__ inline void acc_zero(Acc<double>& a) {
 #pragma unroll
@@ -134,6 +156,72 @@ __device__ inline void acc_zero(Acc<cplx>& a) {
             a.re[i][j] = d4{0.0, 0.0, 0.0, 0.0};
             a.im[i][j] = d4{0.0, 0.0, 0.0, 0.0};
         }
+}
+
+__device__ inline void acc_zero(Acc<float>& a) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) a.c[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+}
+__device__ inline void acc_zero(Acc<cplx32>& a) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            a.re[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+            a.im[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+}
+
+// Real tile product (FP64 or FP32 MFMA, the same operand layout).
+template <typename R, typename V>
+__device__ inline void tile_mma_real(V (&c)[2][2], R (*sA)[BM + LPAD], R (*sB)[BN + LPAD]) {
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
+    int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+        int kr = ks * 4 + lk;
+        R a0 = sA[kr][wm * 32 + li], a1 = sA[kr][wm * 32 + 16 + li];
+        R b0 = sB[kr][wn * 32 + li], b1 = sB[kr][wn * 32 + 16 + li];
+        c[0][0] = mfma(a0, b0, c[0][0]);
+        c[0][1] = mfma(a0, b1, c[0][1]);
+        c[1][0] = mfma(a1, b0, c[1][0]);
+        c[1][1] = mfma(a1, b1, c[1][1]);
+    }
+}
+
+// Complex tile product: four real MFMAs per block.
+template <typename C, typename V>
+__device__ inline void tile_mma_cplx(V (&re)[2][2], V (&im)[2][2], C (*sA)[BM + LPAD], C (*sB)[BN + LPAD]) {
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
+    int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+        int kr = ks * 4 + lk;
+        C a[2] = {sA[kr][wm * 32 + li], sA[kr][wm * 32 + 16 + li]};
+        C b[2] = {sB[kr][wn * 32 + li], sB[kr][wn * 32 + 16 + li]};
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                re[i][j] = mfma(a[i].x, b[j].x, re[i][j]);
+                re[i][j] = mfma(-a[i].y, b[j].y, re[i][j]);
+                im[i][j] = mfma(a[i].x, b[j].y, im[i][j]);
+                im[i][j] = mfma(a[i].y, b[j].x, im[i][j]);
+            }
+    }
+}
+
+__device__ inline void tile_mma(Acc<float>& acc, float (*sA)[BM + LPAD], float (*sB)[BN + LPAD]) {
+    tile_mma_real<float, f4>(acc.c, sA, sB);
+}
+__device__ inline void tile_mma(Acc<cplx32>& acc, cplx32 (*sA)[BM + LPAD], cplx32 (*sB)[BN + LPAD]) {
+    tile_mma_cplx<cplx32, f4>(acc.re, acc.im, sA, sB);
+}
+__device__ inline float acc_get(const Acc<float>& a, int i, int j, int r) { return a.c[i][j][r]; }
+__device__ inline cplx32 acc_get(const Acc<cplx32>& a, int i, int j, int r) {
+    return mk32(a.re[i][j][r], a.im[i][j][r]);
 }
 
 __device__ inline void tile_mma(Acc<double>& acc, double (*sA)[BM + LPAD], double (*sB)[BN + LPAD]) {
@@ -208,7 +296,7 @@ __device__ inline void gemm_tile(int m, int n, int K, double alpha, const T* A, 
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                int row = m0 + wm * 32 + i * 16 + (lane >> 4) + 4 * r;
+                int row = m0 + wm * 32 + i * 16 + out_row<T>(lane, r);
                 int col = n0 + wn * 32 + j * 16 + (lane & 15);
                 if (row < m && col < n && (uplo == UPLO_FULL || col <= row)) {
                     T v = alpha * acc_get(acc, i, j, r);
@@ -270,6 +358,12 @@ template void gemm<double>(hipStream_t, Op, Op, int, int, int, double, const dou
 template void gemm<cplx>(hipStream_t, Op, Op, int, int, int, double, const cplx*, int, long,
                          const cplx*, int, long, double, cplx*, int, long, int, const double*, long,
                          Uplo, const int*, Tri);
+template void gemm<float>(hipStream_t, Op, Op, int, int, int, double, const float*, int, long,
+                          const float*, int, long, double, float*, int, long, int, const double*, long,
+                          Uplo, const int*, Tri);
+template void gemm<cplx32>(hipStream_t, Op, Op, int, int, int, double, const cplx32*, int, long,
+                           const cplx32*, int, long, double, cplx32*, int, long, int, const double*, long,
+                           Uplo, const int*, Tri);
 
 // ---------------------------------------------------------------- split K
 // Partial products over K chunks: P[b][z] = op(A_b)[:, Kz] op(B_b)[Kz, :] for
@@ -340,6 +434,10 @@ template void gemm_splitk<double>(hipStream_t, Op, Op, int, int, int, double, co
                                   int, double, double*, int, double*, long, int, long, long, long);
 template void gemm_splitk<cplx>(hipStream_t, Op, Op, int, int, int, double, const cplx*, int, const cplx*, int,
                                 double, cplx*, int, cplx*, long, int, long, long, long);
+template void gemm_splitk<float>(hipStream_t, Op, Op, int, int, int, double, const float*, int, const float*,
+                                 int, double, float*, int, float*, long, int, long, long, long);
+template void gemm_splitk<cplx32>(hipStream_t, Op, Op, int, int, int, double, const cplx32*, int,
+                                  const cplx32*, int, double, cplx32*, int, cplx32*, long, int, long, long, long);
 
 // ---------------------------------------------------------------- grouped
 __global__ __launch_bounds__(256) void gemm_grouped_dc_kernel(int nm, const int* lo, const int* hi,

@@ -50,8 +50,8 @@ __device__ inline cplx make_c<cplx>(double re, double im) { return mk(re, im); }
 // previous panel has been applied), so x = A[k.., k] and the per-workgroup
 // partial |x_{k+2..}|^2 is all the next reflector needs.  One wavefront per
 // 64 rows; partials laid out as below ([0] of each workgroup's record).
-template <typename T>
-__global__ __launch_bounds__(64) void colstart_kernel(int n, int k, int nb, const T* A, int lda, long sA,
+template <typename T, typename S>
+__global__ __launch_bounds__(64) void colstart_kernel(int n, int k, int nb, const S* A, int lda, long sA,
                                                       HetrdWork<T> hw) {
     const int z = blockIdx.z;
     A += z * sA;
@@ -61,7 +61,7 @@ __global__ __launch_bounds__(64) void colstart_kernel(int n, int k, int nb, cons
     int r = k + blockIdx.x * 64 + t;
     T c = zero_<T>();
     if (r < n) {
-        c = A[(long)r * lda + k];  // column k below the diagonal (lower storage)
+        c = widen(A[(long)r * lda + k]);  // column k below the diagonal (lower storage)
         if (r == k) c = from_re<T>(re_(c));
         x[r] = c;
     }
@@ -179,6 +179,7 @@ __device__ inline T rows_lane_sum(const T (&r)[8], int lane) {
 // Trailing Hermitian matrix-vector product y = A_trail v from the LOWER
 // triangle only.  The trailing matrix (rows/cols k+1 .. n-1) is cut into
 // 64 x 64 tiles; workgroup (c, I) takes tiles J = SCH c .. SCH c + SCH-1
+// (SCH, the tiles per workgroup, is a template parameter picked per plan)
 // (J <= I) of tile row I.  Each of its threads holds one column and R rows
 // of a tile in registers (R = 8 for real, 4 for complex data, so that a
 // thread keeps two tiles' worth in flight within 128 registers) (the next tile's loads are issued before the
@@ -191,7 +192,6 @@ __device__ inline T rows_lane_sum(const T (&r)[8], int lane) {
 // pvav, from which the next kernel gets the W-column correction without a
 // pass over w.
 constexpr int ST = HETRD_TILE;  // tile edge
-constexpr int SCH = HETRD_SCH;  // tiles per workgroup
 template <typename T>
 struct Sy {
     static constexpr int R = sizeof(T) == 8 ? 8 : 4;  // tile rows per thread
@@ -199,8 +199,8 @@ struct Sy {
     static constexpr int THREADS = 64 * NG;            // 512 or 1024
 };
 
-template <typename T>
-__global__ __launch_bounds__(Sy<T>::THREADS, 4) void symv_kernel(int n, int k, int j, int nb, const T* A, int lda,
+template <typename T, typename S, int SCH>
+__global__ __launch_bounds__(Sy<T>::THREADS, 4) void symv_kernel(int n, int k, int j, int nb, const S* A, int lda,
                                                           long sA, int nA, int nt, int nch, double* d,
                                                           double* e, T* taua, HetrdWork<T> hw) {
     constexpr int SY_R = Sy<T>::R, NG = Sy<T>::NG;
@@ -228,12 +228,12 @@ __global__ __launch_bounds__(Sy<T>::THREADS, 4) void symv_kernel(int n, int k, i
     const int o = k + 1;  // first trailing row / column
     const int col = t & 63, g = t >> 6;
     const int r0 = o + I * ST + g * SY_R;  // first row of this thread
-    T cur[SY_R], nxt[SY_R];
+    S cur[SY_R], nxt[SY_R];  // the tile rows as stored (FP64, or FP32 in the mixed form)
     {
         const int gc = o + J0 * ST + col;
 #pragma unroll
         for (int q = 0; q < SY_R; ++q)
-            cur[q] = (r0 + q < n && gc < n) ? A[(long)(r0 + q) * lda + gc] : zero_<T>();
+            cur[q] = (r0 + q < n && gc < n) ? A[(long)(r0 + q) * lda + gc] : zero_<S>();
     }
     T sc, tv;
     reflector<T>(k, nb, x, partA, nA, c == 0 && I == 0, d, e, taua, sc, tv);
@@ -259,23 +259,25 @@ __global__ __launch_bounds__(Sy<T>::THREADS, 4) void symv_kernel(int n, int k, i
             const int gc = o + (J + 1) * ST + col;
 #pragma unroll
             for (int q = 0; q < SY_R; ++q)
-                nxt[q] = (r0 + q < n && gc < n) ? A[(long)(r0 + q) * lda + gc] : zero_<T>();
+                nxt[q] = (r0 + q < n && gc < n) ? A[(long)(r0 + q) * lda + gc] : zero_<S>();
             vJn = vof(gc);
         }
         T cs = zero_<T>();
         if (J != I) {
 #pragma unroll
             for (int q = 0; q < SY_R; ++q) {
-                racc[q] += cur[q] * vJc;
-                cs += conj_(cur[q]) * vr[q];
+                const T a = widen(cur[q]);
+                racc[q] += a * vJc;
+                cs += conj_(a) * vr[q];
             }
         } else {
 #pragma unroll
             for (int q = 0; q < SY_R; ++q) {
                 const int rl = g * SY_R + q;
-                if (col <= rl) racc[q] += cur[q] * vJc;
-                if (col < rl) cs += conj_(cur[q]) * vr[q];
-                if (col == rl) vav += re_(cur[q]) * abs2_(vr[q]);
+                const T a = widen(cur[q]);
+                if (col <= rl) racc[q] += a * vJc;
+                if (col < rl) cs += conj_(a) * vr[q];
+                if (col == rl) vav += re_(a) * abs2_(vr[q]);
             }
         }
         vav += 2.0 * re_(conj_(vJc) * cs);
@@ -327,9 +329,9 @@ constexpr int WC_ROWS = 64;
 static_assert(WC_ROWS == ST, "a row block of wcol is a tile row of the symmetric product");
 static_assert(2 * HETRD_NB <= 64 && HETRD_NB % 4 == 0, "panel width");
 constexpr int WC_MAXU = HETRD_NB / 4;  // panel columns per wavefront
-template <typename T>
-__global__ __launch_bounds__(256) void wcol_kernel(int n, int k, int j, int nb, int next, const T* A, int lda,
-                                                   long sA, int nt, int nch, HetrdWork<T> hw) {
+template <typename T, typename S>
+__global__ __launch_bounds__(256) void wcol_kernel(int n, int k, int j, int nb, int next, const S* A, int lda,
+                                                   long sA, int nt, int nch, int sch, HetrdWork<T> hw) {
     __shared__ T sp[HETRD_NB], sq[HETRD_NB];          // p = W^H v, q = V^H v
     __shared__ T vk[HETRD_NB + 1], wk[HETRD_NB + 1];  // V and W on row k+1
     __shared__ T party[4][WC_ROWS], partc[4][WC_ROWS];
@@ -367,7 +369,7 @@ __global__ __launch_bounds__(256) void wcol_kernel(int n, int k, int j, int nb, 
     // y_r: row partials of tile row I, then column partials of the tiles below
     T y0 = zero_<T>(), y1 = zero_<T>();
     if (in) {
-        int nc = I / SCH + 1;
+        int nc = I / sch + 1;
         for (int c = pp; c < nc; c += 4) y0 += prow[((long)I * nch + c) * ST + lr];
         const T* pc = pcol + (long)I * nt * ST + lr;
         int I2 = I + 1 + pp;
@@ -421,7 +423,7 @@ __global__ __launch_bounds__(256) void wcol_kernel(int n, int k, int j, int nb, 
             WVc[(long)(nb + j) * n + r] = conj_(v);
             if (next) {
                 T cc = (partc[0][lr] + partc[1][lr]) + (partc[2][lr] + partc[3][lr]);
-                xn = A[(long)r * lda + k + 1] - cc - (v * conj_(wk[j]) + w);
+                xn = widen(A[(long)r * lda + k + 1]) - cc - (v * conj_(wk[j]) + w);
                 if (r == k + 1) xn = from_re<T>(re_(xn));
                 x[r] = xn;
             }
@@ -466,36 +468,64 @@ __global__ void store_panel_kernel(int n, int k0, int jb, const T* VWt, long sVW
     Vall[(long)r * n + k0 + i] = VWt[(long)i * n + r];
 }
 
-template <typename T>
-__global__ void last_diag_kernel(int n, const T* A, int lda, long sA, double* d) {
+template <typename S>
+__global__ void last_diag_kernel(int n, const S* A, int lda, long sA, double* d) {
     const int z = blockIdx.x;
     d[(long)z * n + n - 1] = re_(A[z * sA + (long)(n - 1) * lda + n - 1]);
 }
 
-template <typename T>
-void hetrd(hipStream_t s, int n, T* A, int lda, long sA, int batch, double* d, double* e, T* tau, T* Vall,
+// Launch the symmetric product of column k with sch tiles per workgroup.
+template <typename T, typename S>
+void symv_launch(hipStream_t s, int sch, int n, int k, int j, const S* A, int lda, long sA, int B, int nA,
+                 double* d, double* e, T* tau, const HetrdWork<T>& w) {
+    const int m = n - k - 1, nt = cdiv(m, ST), nch = cdiv(nt, sch), nb = HETRD_NB;
+    const dim3 grid(nch, nt, B), block(Sy<T>::THREADS);
+    if (sch == 2)
+        hipLaunchKernelGGL((symv_kernel<T, S, 2>), grid, block, 0, s, n, k, j, nb, A, lda, sA, nA, nt, nch, d, e,
+                           tau, w);
+    else if (sch == 8 && !is_cplx<T>::value)
+        hipLaunchKernelGGL((symv_kernel<T, S, 8>), grid, block, 0, s, n, k, j, nb, A, lda, sA, nA, nt, nch, d, e,
+                           tau, w);
+    else
+        hipLaunchKernelGGL((symv_kernel<T, S, 4>), grid, block, 0, s, n, k, j, nb, A, lda, sA, nA, nt, nch, d, e,
+                           tau, w);
+}
+
+// Panel buffers in the storage precision of the trailing matrix.
+template <typename T, typename S>
+__global__ void narrow_panel_kernel(long cnt, const T* src, long ssrc, S* dst, long sdst) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cnt) return;
+    dst[blockIdx.y * sdst + i] = narrow(src[blockIdx.y * ssrc + i]);
+}
+
+// S: storage type of the trailing matrix A (T, or FP32 in the mixed form, where
+// the rank-2NB trailing update runs on the FP32 matrix cores and everything
+// else, reflectors included, stays in FP64).
+template <typename T, typename S>
+void hetrd(hipStream_t s, int n, S* A, int lda, long sA, int batch, double* d, double* e, T* tau, T* Vall,
            HetrdWork<T>& w) {
+    constexpr bool lo = !std::is_same<T, S>::value;
     const int nb = HETRD_NB;
     const int B = batch;
     for (int k0 = 0; k0 < n - 1; k0 += nb) {
         int jb = min(nb, n - 1 - k0);
         fill_zero<T>(s, w.VW, w.sVW * B);
         fill_zero<T>(s, w.WV, w.sVW * B);
-        hipLaunchKernelGGL((colstart_kernel<T>), dim3(cdiv(n - k0, 64), 1, B), dim3(64), 0, s, n, k0, nb, A, lda,
+        hipLaunchKernelGGL((colstart_kernel<T, S>), dim3(cdiv(n - k0, 64), 1, B), dim3(64), 0, s, n, k0, nb, A, lda,
                            sA, w);
         for (int j = 0; j < jb; ++j) {
             int k = k0 + j;
             int m = n - k - 1;
-            int nt = cdiv(m, ST), nch = cdiv(nt, SCH);
+            int nt = cdiv(m, ST), nch = cdiv(nt, w.sch);
             int nA = cdiv(n - k, WC_ROWS);  // workgroups that wrote the partials of column k
             bool smp = w.prof && w.prof->sample();
             hipEvent_t e0 = smp ? w.prof->begin() : nullptr;
-            hipLaunchKernelGGL((symv_kernel<T>), dim3(nch, nt, B), dim3(Sy<T>::THREADS), 0, s, n, k, j, nb, A,
-                               lda, sA, nA, nt, nch, d, e, tau, w);
+            symv_launch<T, S>(s, w.sch, n, k, j, A, lda, sA, B, nA, d, e, tau, w);
             // algorithmic bytes of a Hermitian matrix-vector product: the lower triangle once
             if (smp) w.prof->end(PROF_HEMV, e0, (double)sizeof(T) * m * (m + 1) / 2.0 * B);
-            hipLaunchKernelGGL((wcol_kernel<T>), dim3(cdiv(m, WC_ROWS), 1, B), dim3(256), 0, s, n, k, j, nb,
-                               (int)(j + 1 < jb), A, lda, sA, nt, nch, w);
+            hipLaunchKernelGGL((wcol_kernel<T, S>), dim3(cdiv(m, WC_ROWS), 1, B), dim3(256), 0, s, n, k, j, nb,
+                               (int)(j + 1 < jb), A, lda, sA, nt, nch, w.sch, w);
         }
         long tot = (long)n * jb;
         hipLaunchKernelGGL((store_panel_kernel<T>), dim3(cdiv(tot, 256), 1, B), dim3(256), 0, s, n, k0, jb, w.VW,
@@ -503,17 +533,79 @@ void hetrd(hipStream_t s, int n, T* A, int lda, long sA, int batch, double* d, d
         int t0 = k0 + jb;
         if (t0 < n) {
             int mt = n - t0;
-            gemm<T>(s, OP_T, OP_N, mt, mt, 2 * nb, -1.0, w.VW + t0, n, w.sVW, w.WV + t0, n, w.sVW, 1.0,
-                    A + (long)t0 * lda + t0, lda, sA, B, nullptr, 0, UPLO_LOWER);
+            if constexpr (lo) {
+                S* VWs = (S*)w.VWlo;
+                S* WVs = (S*)w.WVlo;
+                const long cnt = w.sVW;
+                hipLaunchKernelGGL((narrow_panel_kernel<T, S>), dim3(cdiv(cnt, 256), B), dim3(256), 0, s, cnt, w.VW,
+                                   w.sVW, VWs, w.sVW);
+                hipLaunchKernelGGL((narrow_panel_kernel<T, S>), dim3(cdiv(cnt, 256), B), dim3(256), 0, s, cnt, w.WV,
+                                   w.sVW, WVs, w.sVW);
+                gemm<S>(s, OP_T, OP_N, mt, mt, 2 * nb, -1.0, VWs + t0, n, w.sVW, WVs + t0, n, w.sVW, 1.0,
+                        A + (long)t0 * lda + t0, lda, sA, B, nullptr, 0, UPLO_LOWER);
+            } else {
+                gemm<T>(s, OP_T, OP_N, mt, mt, 2 * nb, -1.0, w.VW + t0, n, w.sVW, w.WV + t0, n, w.sVW, 1.0,
+                        A + (long)t0 * lda + t0, lda, sA, B, nullptr, 0, UPLO_LOWER);
+            }
         }
     }
-    hipLaunchKernelGGL((last_diag_kernel<T>), dim3(B), dim3(1), 0, s, n, A, lda, sA, d);
+    hipLaunchKernelGGL((last_diag_kernel<S>), dim3(B), dim3(1), 0, s, n, A, lda, sA, d);
 }
 
-template void hetrd<double>(hipStream_t, int, double*, int, long, int, double*, double*, double*, double*,
-                            HetrdWork<double>&);
-template void hetrd<cplx>(hipStream_t, int, cplx*, int, long, int, double*, double*, cplx*, cplx*,
-                          HetrdWork<cplx>&);
+
+template <typename T>
+int hetrd_tune(hipStream_t s, int n, T* A, int lda, long sA, int batch, double* d, double* e, T* tau,
+               HetrdWork<T>& w, int* cand, double* ms, int reps) {
+    int nc = 0;
+    cand[nc++] = 2;
+    cand[nc++] = 4;
+    if (!is_cplx<T>::value) cand[nc++] = 8;
+    if (n < 2) {
+        for (int c = 0; c < nc; ++c) ms[c] = 0.0;
+        return nc;
+    }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return 0;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return 0;
+    }
+    // trailing sizes where the product is bandwidth-bound and where it is not
+    const int ks[4] = {0, n / 3, (2 * n) / 3, std::max(0, n - 1 - 4 * ST)};
+    for (int c = 0; c < nc; ++c) {
+        float tot = 0.f;
+        for (int q = 0; q < 4; ++q) {
+            const int k = std::min(ks[q], n - 2);
+            const int nA = cdiv(n - k, WC_ROWS);
+            symv_launch<T, T>(s, cand[c], n, k, 0, A, lda, sA, batch, nA, d, e, tau, w);  // warm
+            (void)hipEventRecord(e0, s);
+            for (int r = 0; r < reps; ++r)
+                symv_launch<T, T>(s, cand[c], n, k, 0, A, lda, sA, batch, nA, d, e, tau, w);
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            float t = 0.f;
+            (void)hipEventElapsedTime(&t, e0, e1);
+            tot += t;
+        }
+        ms[c] = tot;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return nc;
+}
+
+template void hetrd<double, double>(hipStream_t, int, double*, int, long, int, double*, double*, double*,
+                                    double*, HetrdWork<double>&);
+template void hetrd<cplx, cplx>(hipStream_t, int, cplx*, int, long, int, double*, double*, cplx*, cplx*,
+                                HetrdWork<cplx>&);
+template void hetrd<double, float>(hipStream_t, int, float*, int, long, int, double*, double*, double*,
+                                   double*, HetrdWork<double>&);
+template void hetrd<cplx, cplx32>(hipStream_t, int, cplx32*, int, long, int, double*, double*, cplx*, cplx*,
+                                  HetrdWork<cplx>&);
+template int hetrd_tune<double>(hipStream_t, int, double*, int, long, int, double*, double*, double*,
+                                HetrdWork<double>&, int*, double*, int);
+template int hetrd_tune<cplx>(hipStream_t, int, cplx*, int, long, int, double*, double*, cplx*,
+                              HetrdWork<cplx>&, int*, double*, int);
 template void fill_zero<double>(hipStream_t, double*, long);
 template void fill_zero<cplx>(hipStream_t, cplx*, long);
 template void fill_zero<int>(hipStream_t, int*, long);

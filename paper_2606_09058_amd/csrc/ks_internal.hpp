@@ -4,6 +4,7 @@
 
 #include <vector>
 #include <algorithm>
+#include <type_traits>
 
 #include "ks_common.hpp"
 
@@ -13,7 +14,8 @@ template <> __host__ __device__ inline int zero_<int>() { return 0; }
 
 constexpr int HETRD_NB = 32;   // panel width of the tridiagonalisation
 constexpr int HETRD_TILE = 64; // tile edge of the trailing symmetric product
-constexpr int HETRD_SCH = 4;   // tiles per workgroup of the trailing symmetric product
+constexpr int HETRD_SCH = 4;      // default tiles per workgroup of the trailing symmetric product
+constexpr int HETRD_SCH_MIN = 2;  // smallest candidate (sizes the partial buffers)
 constexpr int BACKTR_BT = 64;  // reflectors per compact-WY block of the back-transform
 constexpr int DC_LEAF = 32;    // largest divide-and-conquer leaf
 constexpr int MAX_KW = 64;     // k-point weights passed by value
@@ -72,12 +74,15 @@ struct HetrdWork {
     T* WV;          // 2NB x n   conj(W) then conj(V), transposed
     T* x;           // n         updated column
     T* partPQ;      // cdiv(n, 64) x (1 + 2NB) partial |x|^2, W^H x, V^H x
-    T* prow;        // nt x cdiv(nt, HETRD_SCH) x HETRD_TILE, nt = cdiv(n, HETRD_TILE): row partials
+    T* prow;        // nt x cdiv(nt, HETRD_SCH_MIN) x HETRD_TILE, nt = cdiv(n, HETRD_TILE): row partials
     T* pcol;        // nt x nt x HETRD_TILE                                           column partials
-    double* pvav;   // nt x cdiv(nt, HETRD_SCH) partial v^H A v
+    double* pvav;   // nt x cdiv(nt, HETRD_SCH_MIN) partial v^H A v
     T* pq;          // 2 + 2 NB: s, tau, W^H v, V^H v of the current column
+    void* VWlo = nullptr;  // mixed form: VW and WV in FP32 for the trailing update
+    void* WVlo = nullptr;
     // strides (elements) between the buffers of consecutive matrices of a batch
     long sVW = 0, sx = 0, spart = 0, sprow = 0, spcol = 0, spvav = 0, spq = 0;
+    int sch = HETRD_SCH;  // tiles per workgroup of the symmetric product (tuned per plan)
 };
 
 template <typename T>
@@ -149,9 +154,17 @@ void reduce_to_standard(hipStream_t s, int n, int nsp, int batch, const T* H, in
 template <typename T>
 void tri_inverse(hipStream_t s, int n, const T* L, int ldl, long sl, T* Linv, long si, int batch);
 
-template <typename T>
-void hetrd(hipStream_t s, int n, T* A, int lda, long sA, int batch, double* d, double* e, T* tau, T* Vall,
+template <typename T, typename S>
+void hetrd(hipStream_t s, int n, S* A, int lda, long sA, int batch, double* d, double* e, T* tau, T* Vall,
            HetrdWork<T>& w);
+
+// Tiles-per-workgroup candidates of the symmetric product for element type T,
+// and the time of `reps` launches of each at a few trailing sizes of an order-n
+// batch (the matrix contents do not matter for the timing).  Writes the
+// candidates to cand[] and times (ms) to ms[]; returns their number.
+template <typename T>
+int hetrd_tune(hipStream_t s, int n, T* A, int lda, long sA, int batch, double* d, double* e, T* tau,
+               HetrdWork<T>& w, int* cand, double* ms, int reps);
 
 // Divide and conquer for a batch of tridiagonals of order tr.n (d, e, lam:
 // stride n; Z, Z2, U, Qp: stride n^2; the work arrays of w: stride n, with
@@ -168,11 +181,11 @@ void dc_tree_host(int n, std::vector<int>& mlo, std::vector<int>& mmid, std::vec
 template <typename T>
 void load_z(hipStream_t s, int n, int batch, int ncols, const double* Z, int c0, T* X, int ldx, long sX);
 
-// X <- Q X for a batch: Q from the reflectors in Vall (n x n per matrix, the
-// tridiagonalisation's layout) and tau (n per matrix).
+// X <- Q X (or Q^H X with adjoint) for a batch: Q from the reflectors in Vall
+// (n x n per matrix, the tridiagonalisation's layout) and tau (n per matrix).
 template <typename T>
 void backtransform_q(hipStream_t s, int n, int batch, const T* Vall, const T* tau, int ncols, T* X, int ldx,
-                     long sX, BacktrWork<T>& w);
+                     long sX, BacktrWork<T>& w, bool adjoint = false);
 
 void fermi(hipStream_t s, int batch, int order, const double* eps, const KWeights& kw, double g,
            double ne, double kT, int il, int iu, double* occ, double* mu, double* eband, int* kwin,
@@ -183,6 +196,22 @@ void density_backward(hipStream_t s, int n, int nsp, int batch, const double* ep
                       const double* mu, double kT, double g, const KWeights& kw, const T* grad_rho,
                       const double* grad_eband, T* grad_H, T* grad_S, int lds, T* W1, T* W2, T* W3,
                       double* scal);
+
+// ---------------------------------------------------------------- mixed precision
+// Element kernels of the mixed-precision solve (ks_mixed.hip); every one takes
+// a batch of matrices (blockIdx.y) with the given element strides.
+template <typename Src, typename Dst>
+void convert(hipStream_t s, int batch, int rows, int cols, const Src* src, int lds, long ss, Dst* dst, int ldd,
+             long sd);
+template <typename T>
+void residual(hipStream_t s, int batch, int order, int m, const T* Y, const T* X, long sm, const double* lam,
+              long sl, int c0, T* R);
+void correction_scale(hipStream_t s, int batch, int order, int m, int w, float* P, long sp, const double* lam,
+                      long sl, int c0, double dmin);
+template <typename T, typename S>
+void sub_widened(hipStream_t s, int batch, long cnt, T* X, const S* D, long sm);
+void put_window(hipStream_t s, int batch, int m, const double* theta, long st, double* eps, long se, int c0);
+void merge_info(hipStream_t s, int* inner, int* outer);
 
 }  // namespace ks
 

@@ -17,6 +17,18 @@ __global__ void mfma_layout_kernel(double* out) {
     for (int r = 0; r < 4; ++r) out[l * 4 + r] = c[r];
 }
 
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__global__ void mfma_layout32_kernel(float* out) {
+    int l = threadIdx.x;
+    int ii = l % 16, kk = l / 16;
+    float a = (kk == 0) ? 100.f * ii : (kk == 1 ? 1.f : 0.f);
+    float b = (kk == 0) ? 1.f : (kk == 1 ? (float)ii : 0.f);
+    f4 c = {0.f, 0.f, 0.f, 0.f};
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    for (int r = 0; r < 4; ++r) out[l * 4 + r] = c[r];
+}
+
 static int32_t finish(hipStream_t s) {
     if (hipStreamSynchronize(s) != hipSuccess) return KS_ERR_HIP;
     if (hipGetLastError() != hipSuccess) return KS_ERR_HIP;
@@ -32,6 +44,13 @@ int32_t ks_test_mfma_layout(double* out, void* stream) {
     return finish(s);
 }
 
+int32_t ks_test_mfma_layout32(float* out, void* stream) {
+    if (!out) return KS_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(mfma_layout32_kernel, dim3(1), dim3(64), 0, s, out);
+    return finish(s);
+}
+
 int32_t ks_test_gemm(int32_t dtype, int32_t opa, int32_t opb, int32_t m, int32_t n, int32_t k,
                      double alpha, const void* A, int32_t lda, const void* B, int32_t ldb, double beta,
                      void* C, int32_t ldc, int32_t lower, void* stream) {
@@ -42,6 +61,12 @@ int32_t ks_test_gemm(int32_t dtype, int32_t opa, int32_t opb, int32_t m, int32_t
     if (dtype == 1)
         gemm<cplx>(s, (Op)opa, (Op)opb, m, n, k, alpha, (const cplx*)A, lda, 0, (const cplx*)B, ldb, 0,
                    beta, (cplx*)C, ldc, 0, 1, nullptr, 0, u);
+    else if (dtype == 2)
+        gemm<float>(s, (Op)opa, (Op)opb, m, n, k, alpha, (const float*)A, lda, 0, (const float*)B, ldb, 0,
+                    beta, (float*)C, ldc, 0, 1, nullptr, 0, u);
+    else if (dtype == 3)
+        gemm<cplx32>(s, (Op)opa, (Op)opb, m, n, k, alpha, (const cplx32*)A, lda, 0, (const cplx32*)B, ldb, 0,
+                     beta, (cplx32*)C, ldc, 0, 1, nullptr, 0, u);
     else
         gemm<double>(s, (Op)opa, (Op)opb, m, n, k, alpha, (const double*)A, lda, 0, (const double*)B, ldb,
                      0, beta, (double*)C, ldc, 0, 1, nullptr, 0, u);

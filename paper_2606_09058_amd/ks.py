@@ -19,6 +19,7 @@ KS_REAL64, KS_COMPLEX128 = 0, 1
 KS_COLLINEAR, KS_NONCOLLINEAR = 0, 1
 KS_FP64, KS_MIXED = 0, 1
 KS_PLAN_GRAPH = 1
+KS_PLAN_AUTOTUNE = 2
 KS_REUSE_S = 1
 
 STATUS = {
@@ -29,7 +30,7 @@ STATUS = {
 
 EXPORTS = ["ks_plan_create", "ks_plan_destroy", "ks_gevd", "ks_density", "ks_density_backward",
            "ks_plan_get_info", "ks_status_string", "ks_plan_workspace_bytes", "ks_plan_set_profiling",
-           "ks_plan_get_profile", "ks_plan_get_graph_stats"]
+           "ks_plan_get_profile", "ks_plan_get_graph_stats", "ks_plan_get_tuning"]
 
 
 class KSError(RuntimeError):
@@ -53,6 +54,12 @@ class Profile(ctypes.Structure):
     _fields_ = [("phase_ms", ctypes.c_double * 8), ("phase_calls", ctypes.c_int64 * 8),
                 ("hemv_ms", ctypes.c_double), ("hemv_launches", ctypes.c_int64),
                 ("hemv_bytes", ctypes.c_double)]
+
+
+class Tuning(ctypes.Structure):
+    """ks_tuning: the symmetric product's tiles per workgroup and the timings behind it."""
+    _fields_ = [("tiles_per_workgroup", ctypes.c_int32), ("ncand", ctypes.c_int32),
+                ("cand", ctypes.c_int32 * 4), ("ms", ctypes.c_double * 4)]
 
 
 _lib = None
@@ -89,6 +96,8 @@ def lib():
         L.ks_plan_get_profile.restype = I
         L.ks_plan_get_graph_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
         L.ks_plan_get_graph_stats.restype = I
+        L.ks_plan_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+        L.ks_plan_get_tuning.restype = I
         _lib = L
     return _lib
 
@@ -207,6 +216,13 @@ class Plan:
         pr = Profile()
         _check(lib().ks_plan_get_profile(self._h, ctypes.byref(pr)), "ks_plan_get_profile")
         return pr
+
+    def tuning(self):
+        """{"tiles_per_workgroup": t, "candidates": {cand: ms}} (timings only under KS_PLAN_AUTOTUNE)."""
+        tu = Tuning()
+        _check(lib().ks_plan_get_tuning(self._h, ctypes.byref(tu)), "ks_plan_get_tuning")
+        return {"tiles_per_workgroup": int(tu.tiles_per_workgroup),
+                "candidates": {int(tu.cand[i]): float(tu.ms[i]) for i in range(tu.ncand)}}
 
     def graph_stats(self):
         """(captures, replays) of ks_gevd under KS_PLAN_GRAPH."""

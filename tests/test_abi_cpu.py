@@ -64,8 +64,10 @@ def test_plan_create_rejects_bad_descriptors_without_device(L, bad):
 def test_plan_create_unsupported_combinations(L):
     h = ctypes.c_void_p()
     assert L.ks_plan_create(ctypes.byref(desc(spin=1, dtype=0)), ctypes.byref(h)) == 9
-    assert L.ks_plan_create(ctypes.byref(desc(prec=1)), ctypes.byref(h)) == 9
     assert L.ks_plan_create(ctypes.byref(desc(batch=65)), ctypes.byref(h)) == 9
+    # graph capture needs a stream of its own (the legacy default stream cannot be captured)
+    assert L.ks_plan_create(ctypes.byref(desc(flags=ks.KS_PLAN_GRAPH)), ctypes.byref(h)) == 9
+    assert not h.value
     assert L.ks_plan_create(ctypes.byref(desc()), None) == 1
     assert L.ks_plan_create(None, ctypes.byref(h)) == 1
 
@@ -79,6 +81,34 @@ def test_workspace_bytes_scale(L):
     # the 512-atom and 384-atom shaped problems fit easily in 288 GB
     assert L.ks_plan_workspace_bytes(ctypes.byref(desc(n=6656))) < 4e9
     assert L.ks_plan_workspace_bytes(ctypes.byref(desc(n=4992, spin=1, dtype=1))) < 1e10
+
+
+def test_workspace_bytes_grow_with_the_batch(L):
+    """Every per-matrix buffer is batched, so a batch of 16 needs about 16 times
+    the matrix storage of one plan (the cached factors were already per k)."""
+    b1 = L.ks_plan_workspace_bytes(ctypes.byref(desc(n=1300, dtype=1)))
+    b16 = L.ks_plan_workspace_bytes(ctypes.byref(desc(n=1300, dtype=1, batch=16)))
+    assert 12 < b16 / b1 < 17
+
+
+def test_mixed_precision_workspace(L):
+    """KS_MIXED adds FP32 copies of the reduced matrix, reflectors and tridiagonal
+    eigenvectors plus the FP64 refinement buffers, without changing the FP64 part."""
+    b64 = L.ks_plan_workspace_bytes(ctypes.byref(desc(n=1000)))
+    bmx = L.ks_plan_workspace_bytes(ctypes.byref(desc(n=1000, prec=ks.KS_MIXED)))
+    assert 1.5 < bmx / b64 < 3.5
+
+
+def test_plan_flags_accepted(L):
+    d = desc(flags=ks.KS_PLAN_GRAPH | ks.KS_PLAN_AUTOTUNE)
+    assert L.ks_plan_workspace_bytes(ctypes.byref(d)) > 0
+
+
+def test_tuning_and_graph_stats_reject_null(L):
+    t = ks.Tuning()
+    assert L.ks_plan_get_tuning(None, ctypes.byref(t)) == 1
+    c, r = ctypes.c_int64(), ctypes.c_int64()
+    assert L.ks_plan_get_graph_stats(None, ctypes.byref(c), ctypes.byref(r)) == 1
 
 
 def test_entry_points_reject_null_plan(L):

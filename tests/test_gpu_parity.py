@@ -171,6 +171,28 @@ def test_graph_replay_matches_eager_solves():
         assert np.array_equal(host(eps2), host(eps))
 
 
+@pytest.mark.parametrize("cplx", [False, True])
+def test_autotuned_plan_matches_oracle(cplx):
+    """KS_PLAN_AUTOTUNE times every tiles-per-workgroup candidate of the symmetric
+    product at plan creation and keeps the fastest; each candidate only regroups
+    partial sums, so the tuned plan and every forced candidate meet the oracle."""
+    announce("autotune", cplx)
+    p = I.toy(seed=31, natoms=24, norb=13, edge=14.0, n_electrons=120.0, kT=0.01, phases=cplx)
+    plan = ks.Plan(p.n, complex=cplx, stream=torch.cuda.Stream(), flags=ks.KS_PLAN_AUTOTUNE)
+    tu = plan.tuning()
+    assert tu["tiles_per_workgroup"] in tu["candidates"]
+    assert sorted(tu["candidates"]) == ([2, 4] if cplx else [2, 4, 8])
+    assert all(t > 0 for t in tu["candidates"].values())
+    assert tu["candidates"][tu["tiles_per_workgroup"]] == min(tu["candidates"].values())
+    with torch.cuda.stream(plan.stream):
+        H = dev(p.H)
+        S = dev(p.S.astype(p.H.dtype))
+        out = plan.solve(H, S, p.n_electrons, p.kT)
+        g = {k: host(v) for k, v in out.items()}
+    g["mu"], g["eband"] = float(g["mu"][0]), float(g["eband"][0])
+    compare(p, g, O.solve(p.H, p.S, p.n_electrons, p.kT))
+
+
 def test_window_and_reuse_of_S():
     """Eigenvectors il..iu only (the occupied window): same density; second call
     with KS_REUSE_S (cached Cholesky factor) gives identical results."""

@@ -30,6 +30,8 @@ def L():
     lib.ks_test_hetrd.restype = I32
     lib.ks_test_mfma_layout.argtypes = [V, V]
     lib.ks_test_mfma_layout.restype = I32
+    lib.ks_test_mfma_layout32.argtypes = [V, V]
+    lib.ks_test_mfma_layout32.restype = I32
     return lib
 
 
@@ -45,6 +47,19 @@ def test_mfma_f64_lane_layout(L):
     lane = np.arange(64)[:, None]
     r = np.arange(4)[None, :]
     expect = 100.0 * (lane // 16 + 4 * r) + lane % 16
+    assert np.array_equal(o, expect), o
+
+
+def test_mfma_f32_lane_layout(L):
+    """The FP32 MFMA returns rows 4 (lane / 16) + r in register r (the FP64 one
+    returns lane / 16 + 4 r); the FP32 GEMM's store depends on this."""
+    announce("mfma f32 layout")
+    out = torch.zeros(256, dtype=torch.float32, device="cuda")
+    assert L.ks_test_mfma_layout32(P(out), stream_handle()) == 0
+    o = host(out).reshape(64, 4)
+    lane = np.arange(64)[:, None]
+    r = np.arange(4)[None, :]
+    expect = 100.0 * (4 * (lane // 16) + r) + lane % 16
     assert np.array_equal(o, expect), o
 
 
@@ -75,6 +90,36 @@ def test_gemm_matches_numpy(L, cplx, opa, opb):
         got = host(Cd)
         scale = np.abs(A).max() * np.abs(B).max() * k + 1
         assert np.abs(got - ref).max() < 1e-13 * scale, (m, n, k)
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("opa,opb", [(0, 0), (0, 1), (0, 2), (1, 0), (2, 0)])
+def test_gemm_fp32_matches_numpy(L, cplx, opa, opb):
+    """FP32 matrix-core GEMM (FP32 accumulation) against a float64 product of the
+    same FP32-rounded operands; the bound is a few units of FP32 rounding per
+    accumulated term, far below what a wrong lane mapping would give."""
+    rng = np.random.default_rng(100 + opa * 3 + opb)
+    for (m, n, k) in GEMM_SHAPES:
+        announce("gemm fp32", cplx, opa, opb, m, n, k)
+        dt = np.complex64 if cplx else np.float32
+
+        def rnd(*s):
+            x = rng.normal(size=s)
+            return ((x + 1j * rng.normal(size=s)) if cplx else x).astype(dt)
+        A = rnd(m, k) if opa == 0 else rnd(k, m)
+        B = rnd(k, n) if opb == 0 else rnd(n, k)
+        C0 = rnd(m, n)
+        op = lambda X, o: X if o == 0 else (X.T if o == 1 else X.conj().T)  # noqa: E731
+        alpha, beta = -0.7, 0.3
+        wide = np.complex128 if cplx else np.float64
+        ref = alpha * op(A.astype(wide), opa) @ op(B.astype(wide), opb) + beta * C0.astype(wide)
+        Ad, Bd, Cd = dev(A), dev(B), dev(C0)
+        st = L.ks_test_gemm(3 if cplx else 2, opa, opb, m, n, k, alpha, P(Ad), A.shape[1], P(Bd),
+                            B.shape[1], beta, P(Cd), n, 0, stream_handle())
+        assert st == 0
+        got = host(Cd).astype(wide)
+        scale = np.abs(A).max() * np.abs(B).max() * k + 1
+        assert np.abs(got - ref).max() < 4e-7 * scale, (m, n, k)
 
 
 def test_gemm_lower_only(L):
