@@ -9,6 +9,7 @@ inputs already resident in HBM.  Prints ONE JSON line.
     python bench.py [--steps K] [--warmup W] [--workload supercell6656]
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -38,6 +39,30 @@ def nominal_flops(order, ncols, m_occ, cplx, n_s):
     density order^2 m_occ."""
     f = n_s ** 3 / 3.0 + order ** 3 + 4.0 * order ** 3 / 3.0 + 3.0 * order ** 2 * ncols + order ** 2 * m_occ
     return f * (4.0 if cplx else 1.0)
+
+
+def measured_traffic(workload):
+    """Per-launch memory traffic of symv_kernel from the committed counter summary
+    (profiles/symv_kernel_<workload>_traffic.txt: FETCH_SIZE + WRITE_SIZE runs,
+    each scaled by a plain copy of known size), or None if there is none for
+    this workload or the kernel source has changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "symv_kernel_%s_traffic.txt" % workload)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        line = line.strip()
+        if line and not line.startswith("#") and "=" in line:
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    src = os.path.join(ROOT, kv.get("source_file", "-"))
+    if not os.path.isfile(src):
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != kv.get("source_sha256"):
+        return None
+    return {"bytes": float(kv["traffic_bytes_per_launch_avg"]),
+            "over_algorithmic": float(kv["traffic_over_algorithmic"]),
+            "source": os.path.relpath(path, ROOT)}
 
 
 def cpu_baseline(p, n_sample):
@@ -136,8 +161,9 @@ def main():
     plan.check("warm steps")
 
     # cheap property checks of the last solve
+    SN = torch.block_diag(S, S) if p.nsp == 2 else S  # overlap of the spinor basis
     if p.batch == 1:
-        tr = float((rho * S.to(rho.dtype).T).sum().real.item())
+        tr = float((rho * SN.to(rho.dtype).T).sum().real.item())
     else:
         w = torch.tensor(p.weights, dtype=torch.float64, device="cuda")
         tr = float((w * (rho * S.to(rho.dtype).transpose(1, 2)).sum(dim=(1, 2)).real).sum().item())
@@ -146,6 +172,7 @@ def main():
     hemv_avg_us = 1e3 * prof.hemv_ms / max(1, prof.hemv_launches)
     hemv_gbs = prof.hemv_bytes / max(1e-12, prof.hemv_ms * 1e-3) / 1e9
     phases = phase_dict(prof, args.steps)
+    traffic = measured_traffic(args.workload)
     out = {
         "metric": "GEVD+density s/solve & TFLOP/s, N=6656 real, 2N=9984 cplx; mixed vs FP64",
         "value": ms / 1e3,
@@ -171,7 +198,10 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "symv_kernel (trailing Hermitian matrix-vector "
                                                "product of the tridiagonalisation)",
                      "achieved": hemv_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": hemv_gbs / PEAK_HBM_GBS, "traffic": None,
+                     "frac": hemv_gbs / PEAK_HBM_GBS,
+                     "traffic": traffic["bytes"] if traffic else None,
+                     "traffic_over_algorithmic": traffic["over_algorithmic"] if traffic else None,
+                     "traffic_source": traffic["source"] if traffic else None,
                      "avg_launch_us": hemv_avg_us, "sampled_launches": int(prof.hemv_launches),
                      "bytes_per_launch_avg": prof.hemv_bytes / max(1, prof.hemv_launches)},
         "checks": {"trace_rho_S_minus_Ne": tr - p.n_electrons, "mu": float(mu.item()),
@@ -203,8 +233,11 @@ def compare_precisions(p, H, S, eps_all, mu, steps, buffer_ha=0.4):
     iu = int((eps_all < float(mu.item()) + buffer_ha).sum(dim=-1).max().item())
     res = {"window": [1, iu], "buffer_ha": buffer_ha}
     outs = {}
-    for form, prec in (("fp64", ks.KS_FP64), ("mixed", ks.KS_MIXED)):
+    for form, prec, sweeps in (("fp64", ks.KS_FP64, None), ("mixed", ks.KS_MIXED, 2),
+                               ("mixed1", ks.KS_MIXED, 1)):
         plan = ks.Plan(p.n, batch=p.batch, complex=cplx, noncollinear=p.nsp == 2, precision=prec)
+        if sweeps is not None:
+            plan.set_refinement(sweeps)
         eps = torch.empty(plan._vshape(), dtype=torch.float64, device="cuda")
         C = torch.zeros(plan._mshape(), dtype=plan.mdtype, device="cuda")
         rho = torch.empty_like(C)
@@ -234,13 +267,15 @@ def compare_precisions(p, H, S, eps_all, mu, steps, buffer_ha=0.4):
         outs[form] = (eps.clone(), rho.clone(), float(eb.item()))
         del plan
     ef, rf, bf = outs["fp64"]
-    em, rm, bm = outs["mixed"]
-    res["speedup_mixed_vs_fp64"] = res["fp64_s_per_solve"] / res["mixed_s_per_solve"]
-    res["mixed_max_eig_err_window_vs_fp64"] = float((em[..., :iu] - ef[..., :iu]).abs().max().item())
-    res["mixed_max_eig_err_outside_vs_fp64"] = float((em[..., iu:] - ef[..., iu:]).abs().max().item()) \
-        if iu < p.order else 0.0
-    res["mixed_max_rho_err_vs_fp64"] = float((rm - rf).abs().max().item())
-    res["mixed_eband_err_vs_fp64"] = abs(bm - bf)
+    res["mixed_sweeps"] = {"mixed": 2, "mixed1": 1}
+    for form in ("mixed", "mixed1"):
+        em, rm, bm = outs[form]
+        res["speedup_%s_vs_fp64" % form] = res["fp64_s_per_solve"] / res[form + "_s_per_solve"]
+        res[form + "_max_eig_err_window_vs_fp64"] = float((em[..., :iu] - ef[..., :iu]).abs().max().item())
+        res[form + "_max_eig_err_outside_vs_fp64"] = float((em[..., iu:] - ef[..., iu:]).abs().max().item()) \
+            if iu < p.order else 0.0
+        res[form + "_max_rho_err_vs_fp64"] = float((rm - rf).abs().max().item())
+        res[form + "_eband_err_vs_fp64"] = abs(bm - bf)
     return res
 
 

@@ -191,6 +191,15 @@ typedef struct {
 } ks_tuning;
 ks_status ks_plan_get_tuning(ks_plan* plan, ks_tuning* out);
 
+/* KS_MIXED plans: the number of correction sweeps (0 .. 4, default 2) applied
+ * to the window's FP32 eigenvectors before the final FP64 Rayleigh-Ritz step.
+ * Each sweep shrinks the window subspace's components along the other
+ * eigenvectors by about u32 ||A|| / gap (u32 the FP32 unit roundoff, gap the
+ * distance from the window's eigenvalues to the rest of the spectrum), and
+ * the Rayleigh-Ritz eigenvalues carry the square of what is left.  Host-only;
+ * KS_ERR_INVALID_ARG outside the range, KS_ERR_NOT_SUPPORTED on an FP64 plan. */
+ks_status ks_plan_set_refinement(ks_plan* plan, int32_t sweeps);
+
 /* Graph use under KS_PLAN_GRAPH: how many argument sets were captured and how
  * many ks_gevd calls replayed a captured graph.  Host-only. */
 ks_status ks_plan_get_graph_stats(ks_plan* plan, int64_t* captures, int64_t* replays);

@@ -23,9 +23,11 @@ int32_t ks_test_gemm(int32_t dtype, int32_t opa, int32_t opb, int32_t m, int32_t
                      double alpha, const void* A, int32_t lda, const void* B, int32_t ldb, double beta,
                      void* C, int32_t ldc, int32_t lower, void* stream);
 
-/* In-place Cholesky of the n x n lower triangle of A (upper left untouched);
- * *info = failing 1-based column or 0. */
-int32_t ks_test_potrf(int32_t dtype, int32_t n, void* A, int32_t lda, int32_t* info, void* stream);
+/* In-place Cholesky of the n x n lower triangle of A (upper left untouched)
+ * and, if Linv is not NULL, the inverse factor into Linv (n x n, row stride n,
+ * zeros above the diagonal); *info = failing 1-based column or 0. */
+int32_t ks_test_potrf(int32_t dtype, int32_t n, void* A, int32_t lda, void* Linv, int32_t* info,
+                      void* stream);
 
 /* Eigen-decomposition of the symmetric tridiagonal (d[n], e[n-1]) by divide
  * and conquer: lam[n] ascending, Z[n][n] eigenvectors as columns. */

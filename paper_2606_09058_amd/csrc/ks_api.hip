@@ -63,7 +63,7 @@ struct ks_plan {
     // refinement buffers (all per matrix of the batch) and the Rayleigh-Ritz plan
     void* A32 = nullptr;       // order x order   reduced matrix in FP32
     void* W32 = nullptr;       // order x order   reflectors in FP32
-    void* tau32 = nullptr;     // order
+    void* Tall32 = nullptr;    // compact-WY factors of the back-transform in FP32
     float* Z32 = nullptr;      // order x order   tridiagonal eigenvectors in FP32
     void* mY = nullptr;        // order x order   A X, then X y
     void* mR = nullptr;        // order x order   residual, then the Ritz vectors y
@@ -150,7 +150,8 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
     size_t oPV = L.take(B * hPV * 8);
     size_t oPQv = L.take(B * hPQv * es);
     // back-transform
-    size_t oG = L.take(B * bt * bt * es), oT = L.take(bt * bt * es);
+    const size_t nblk_bt = order > 1 ? (order - 1 + bt - 1) / bt : 1;
+    size_t oG = L.take(B * bt * bt * es), oT = L.take(B * nblk_bt * bt * bt * es);
     size_t oW1 = L.take(B * bt * order * es), oW2 = L.take(B * bt * order * es);
     // split-K partial products of a BT x order product: as many K-chunks as the
     // GEMM cuts K = order into (at most max(16, order / 256)), for every matrix
@@ -171,12 +172,12 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
     // mixed precision (only when asked for)
     const bool mixed = d->precision == KS_MIXED;
     const size_t es32 = es / 2, mat = order * order;
-    size_t oA32 = 0, oW32 = 0, oTau32 = 0, oZ32 = 0, oMY = 0, oMR = 0, oMG = 0, oMB = 0, oMP = 0, oMP2 = 0;
+    size_t oA32 = 0, oW32 = 0, oT32 = 0, oZ32 = 0, oMY = 0, oMR = 0, oMG = 0, oMB = 0, oMP = 0, oMP2 = 0;
     size_t oTh = 0, oVWl = 0, oWVl = 0;
     if (mixed) {
         oA32 = L.take(B * mat * es32);
         oW32 = L.take(B * mat * es32);
-        oTau32 = L.take(B * order * es32);
+        oT32 = L.take(B * nblk_bt * bt * bt * es32);
         oZ32 = L.take(B * mat * 4);
         oMY = L.take(B * mat * es);
         oMR = L.take(B * mat * es);
@@ -229,7 +230,7 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
     if (mixed) {
         p->A32 = b + oA32;
         p->W32 = b + oW32;
-        p->tau32 = b + oTau32;
+        p->Tall32 = b + oT32;
         p->Z32 = (float*)(b + oZ32);
         p->mY = b + oMY;
         p->mR = b + oMR;
@@ -244,7 +245,8 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
     auto setB = [&](auto& w, auto* tag) {
         using T = std::remove_pointer_t<decltype(tag)>;
         w.G = (T*)(b + oG);
-        w.Tf = (T*)(b + oT);
+        w.Tall = (T*)(b + oT);
+        w.sTall = (long)(nblk_bt * bt * bt);
         w.W1 = (T*)(b + oW1);
         w.W2 = (T*)(b + oW2);
         w.P = (T*)(b + oSK);
@@ -317,7 +319,8 @@ BacktrWork<typename Lo<T>::type> lo_view(const BacktrWork<T>& w) {
     using L = typename Lo<T>::type;
     BacktrWork<L> v;
     v.G = (L*)w.G;
-    v.Tf = (L*)w.Tf;
+    v.Tall = nullptr;  // the FP32 factors have a buffer of their own
+    v.sTall = w.sTall;
     v.W1 = (L*)w.W1;
     v.W2 = (L*)w.W2;
     v.P = (L*)w.P;
@@ -384,11 +387,11 @@ ks_status gevd_mixed(ks_plan* p, const T* H, double* eps, T* C, int il, int iu) 
     T* Li = (T*)p->Li;
     L* A32 = (L*)p->A32;
     L* W32 = (L*)p->W32;
-    L* tau32 = (L*)p->tau32;
     float* Z32 = p->Z32;
     HetrdWork<T>& hw = *reinterpret_cast<HetrdWork<T>*>(is_cplx<T>::value ? (void*)&p->hc : (void*)&p->hr);
     BacktrWork<T>& bw = *reinterpret_cast<BacktrWork<T>*>(is_cplx<T>::value ? (void*)&p->bc : (void*)&p->br);
     BacktrWork<L> bl = lo_view(bw);
+    bl.Tall = (L*)p->Tall32;
     Prof& pf = p->prof;
     if (!p->rr || p->rr->d.n != M) return KS_ERR_INVALID_ARG;  // prepared by ks_gevd
     hipEvent_t e = pf.begin();
@@ -402,13 +405,15 @@ ks_status gevd_mixed(ks_plan* p, const T* H, double* eps, T* C, int il, int iu) 
     stedc(s, p->tree, B, p->dv, p->ev, eps, p->Z, p->Z2, p->U, p->Qp, p->dc, p->info);
     pf.end(KS_PHASE_DC, e);
     e = pf.begin();
-    // FP32 copies of the reflectors and of Z, then X = Q Z[:, window] in FP32, widened into W
+    // FP32 copies of the reflectors, their compact-WY factors and of Z, then
+    // X = Q Z[:, window] in FP32, widened into W
+    backtransform_prepare<T>(s, order, B, W, tau, bw);
+    convert<T, L>(s, B, 1, (int)bw.sTall, bw.Tall, (int)bw.sTall, bw.sTall, bl.Tall, (int)bw.sTall, bw.sTall);
     convert<T, L>(s, B, order, order, W, order, sA, W32, order, sA);
-    convert<T, L>(s, B, 1, order, tau, order, order, tau32, order, order);
     convert<double, float>(s, B, order, order, p->Z, order, sA, Z32, order, sA);
     L* P = (L*)p->mP;
     load_z<L>(s, order, B, M, p->Z, c0, P, M, sM);
-    backtransform_q<L>(s, order, B, W32, tau32, M, P, M, sM, bl);
+    backtransform_q<L>(s, order, B, W32, M, P, M, sM, bl);
     T* X = W;  // the FP64 reflectors are no longer needed
     convert<L, T>(s, B, order, M, P, M, sM, X, M, sM);
     pf.end(KS_PHASE_BACKTR, e);
@@ -422,13 +427,13 @@ ks_status gevd_mixed(ks_plan* p, const T* H, double* eps, T* C, int il, int iu) 
         gemm<T>(s, OP_N, OP_N, order, M, order, 1.0, A, order, sA, X, M, sM, 0.0, Y, M, sM, B);
         residual<T>(s, B, order, M, Y, X, sM, eps, order, c0, R);
         convert<T, L>(s, B, order, M, R, M, sM, P, M, sM);
-        backtransform_q<L>(s, order, B, W32, tau32, M, P, M, sM, bl, true);  // Q^H R
+        backtransform_q<L>(s, order, B, W32, M, P, M, sM, bl, true);  // Q^H R
         gemm<float>(s, OP_T, OP_N, order, wv * M, order, 1.0, Z32, order, sA, Pf, wv * M, wv * sM, 0.0, P2f,
                     wv * M, wv * sM, B);  // Z^T Q^H R
         correction_scale(s, B, order, M, wv, P2f, wv * sM, eps, order, c0, 1e-4);
         gemm<float>(s, OP_N, OP_N, order, wv * M, order, 1.0, Z32, order, sA, P2f, wv * M, wv * sM, 0.0, Pf,
                     wv * M, wv * sM, B);
-        backtransform_q<L>(s, order, B, W32, tau32, M, P, M, sM, bl);  // Q Z S(...)
+        backtransform_q<L>(s, order, B, W32, M, P, M, sM, bl);  // Q Z S(...)
         sub_widened<T, L>(s, B, sM, X, P, sM);
     }
     // Rayleigh-Ritz: G = X^H A X, Bm = X^H X, G y = theta Bm y, X <- X y
@@ -467,8 +472,9 @@ ks_status gevd_impl(ks_plan* p, const T* H, const T* S, double* eps, T* C, int i
     if (!(flags & KS_REUSE_S)) {
         hipEvent_t e = pf.begin();
         herm_complete<T>(s, n, S, lds, (long)n * lds, L, n, (long)n * n, B, p->info);
-        potrf<T>(s, n, L, n, (long)n * n, B, p->info);
-        tri_inverse<T>(s, n, L, n, (long)n * n, Li, (long)n * n, B);
+        // W (order^2 per matrix, free until the reduction) holds the inverse's intermediate
+        potrf_inv<T>(s, n, L, n, (long)n * n, Li, n, (long)n * n, (T*)p->W, (long)p->order * p->order, B,
+                     p->info);
         pf.end(KS_PHASE_CHOLESKY, e);
         p->have_L = true;
     }
@@ -488,7 +494,8 @@ ks_status gevd_impl(ks_plan* p, const T* H, const T* S, double* eps, T* C, int i
     e = pf.begin();
     // X = Q Z[:, il-1 : iu] in A (order x ncols per matrix), then C_sigma = Linv^H X_sigma per spin block
     load_z<T>(s, order, B, ncols, p->Z, il - 1, A, ncols, sA);
-    backtransform_q<T>(s, order, B, W, tau, ncols, A, ncols, sA, bw);
+    backtransform_prepare<T>(s, order, B, W, tau, bw);
+    backtransform_q<T>(s, order, B, W, ncols, A, ncols, sA, bw);
     apply_linv_h<T>(p, Li, A, sA, ncols, C);
     pf.end(KS_PHASE_BACKTR, e);
     if (hipPeekAtLastError() != hipSuccess) return KS_ERR_HIP;
@@ -582,6 +589,14 @@ void ks_plan_destroy(ks_plan* p) {
     if (p->base) (void)hipFree(p->base);
     if (p->adj) (void)hipFree(p->adj);
     delete p;
+}
+
+ks_status ks_plan_set_refinement(ks_plan* p, int32_t sweeps) {
+    if (!p || sweeps < 0 || sweeps > 4) return KS_ERR_INVALID_ARG;
+    if (p->d.precision != KS_MIXED) return KS_ERR_NOT_SUPPORTED;
+    if (p->mixed_sweeps != sweeps) graph_release(p);  // a captured sequence would keep the old count
+    p->mixed_sweeps = sweeps;
+    return KS_OK;
 }
 
 ks_status ks_plan_get_tuning(ks_plan* p, ks_tuning* out) {
@@ -773,10 +788,12 @@ void ks_internal_hetrd(ks_plan* p, void* A, double* d, double* e, const double* 
     if (p->is_c) {
         hetrd<cplx, cplx>(p->s, n, (cplx*)A, n, sA, 1, d, e, (cplx*)p->tau, (cplx*)p->W, p->hc);
         load_z<cplx>(p->s, n, 1, ncols, X, 0, (cplx*)Y, ncols, 0);
-        backtransform_q<cplx>(p->s, n, 1, (cplx*)p->W, (cplx*)p->tau, ncols, (cplx*)Y, ncols, 0, p->bc);
+        backtransform_prepare<cplx>(p->s, n, 1, (cplx*)p->W, (cplx*)p->tau, p->bc);
+        backtransform_q<cplx>(p->s, n, 1, (cplx*)p->W, ncols, (cplx*)Y, ncols, 0, p->bc);
     } else {
         hetrd<double, double>(p->s, n, (double*)A, n, sA, 1, d, e, (double*)p->tau, (double*)p->W, p->hr);
         load_z<double>(p->s, n, 1, ncols, X, 0, (double*)Y, ncols, 0);
-        backtransform_q<double>(p->s, n, 1, (double*)p->W, (double*)p->tau, ncols, (double*)Y, ncols, 0, p->br);
+        backtransform_prepare<double>(p->s, n, 1, (double*)p->W, (double*)p->tau, p->br);
+        backtransform_q<double>(p->s, n, 1, (double*)p->W, ncols, (double*)Y, ncols, 0, p->br);
     }
 }

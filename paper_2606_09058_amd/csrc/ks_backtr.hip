@@ -4,10 +4,11 @@
 // Fermi-Dirac occupations (Parts 3-4 of Sec. 3.1, Parts 4-5 of Sec. 3.2).
 //
 // Q = H_0 H_1 ... H_{n-2} is applied in blocks of BT reflectors in compact-WY
-// form, H_b ... H_{b+BT-1} = I - V T V^H (T upper triangular, built from
-// G = V^H V and tau), so each block is three MFMA GEMMs:
-// W1 = V^H X, W2 = T W1, X -= V W2.  A batch of matrices of one order shares
-// every launch (GEMM batch index, or blockIdx.y / z selecting the matrix).
+// form, H_b ... H_{b+BT-1} = I - V T V^H (T upper triangular, built once per
+// set of reflectors from G = V^H V and tau), so each block is three MFMA GEMMs:
+// W1 = V^H X, W2 = T W1 (T^H W1 for Q^H), X -= V W2.  A batch of matrices of one
+// order shares every launch (GEMM batch index, or blockIdx.y / z selecting the
+// matrix).
 #include "ks_internal.hpp"
 
 namespace ks {
@@ -23,69 +24,84 @@ __global__ void load_z_kernel(int n, int ncols, const double* Z, int c0, T* X, i
     X[(long)r * ldx + c] = from_re<T>(Z[(long)r * n + c0 + c]);
 }
 
-// W2 = T W1 for the compact-WY factor T of a block of reflectors, without
-// forming T: T^-1 = diag(1/tau) + strictly-upper(G) with G = V^H V, so W2 solves
-// the upper triangular system row by row from the bottom,
-// W2[i] = tau_i (W1[i] - sum_{l > i} G[i][l] W2[l])  (tau_i = 0 gives a zero row,
-// as the identity reflector contributes nothing).  ADJ: W2 = T^H W1 instead, with
-// (T^H)^-1 = diag(1/conj tau) + strictly-lower(G), solved from the top.  One
-// thread per column of W1; the strict triangle of G is staged in LDS.
-template <typename T, bool ADJ>
+// W2 = T W1 for the compact-WY factor T of a block of reflectors (applied to the
+// identity it forms T itself): T^-1 = diag(1/tau) + strictly-upper(G) with
+// G = V^H V, so W2 solves the upper triangular system row by row from the
+// bottom, W2[i] = tau_i (W1[i] - sum_{l > i} G[i][l] W2[l]) (tau_i = 0 gives a
+// zero row, as the identity reflector contributes nothing).  One thread per
+// column of W1; the strict upper triangle of G is staged in LDS.
+template <typename T>
 __global__ __launch_bounds__(256) void apply_t_kernel(int jb, int ncols, const T* tau, long stau, const T* G,
-                                                      const T* W1, T* W2) {
+                                                      const T* W1, T* W2, long sw1, long sw2) {
     constexpr int B = BACKTR_BT;
     {
         const int b = blockIdx.y;
         tau += b * stau;
         G += (long)b * jb * jb;
-        W1 += (long)b * jb * ncols;
-        W2 += (long)b * jb * ncols;
+        W1 += b * sw1;
+        W2 += b * sw2;
     }
     __shared__ T sg[B * (B - 1) / 2];
     __shared__ T st[B];
-    // packed strict upper triangle of G: row i holds G[i][i+1 .. B-1]; for ADJ the
-    // same slots hold G[l][i] = conj(G[i][l]) read as the strict lower part
     for (int e = threadIdx.x; e < jb * jb; e += blockDim.x) {
         int i = e / jb, l = e % jb;
         if (l > i) sg[i * (2 * B - i - 1) / 2 + (l - i - 1)] = G[(long)i * jb + l];
     }
-    if (threadIdx.x < jb) st[threadIdx.x] = ADJ ? conj_(tau[threadIdx.x]) : tau[threadIdx.x];
+    if (threadIdx.x < jb) st[threadIdx.x] = tau[threadIdx.x];
     __syncthreads();
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncols) return;
     T w[B];
-    if constexpr (!ADJ) {
 #pragma unroll
-        for (int i = B - 1; i >= 0; --i) {
-            if (i < jb) {
-                T s = W1[(long)i * ncols + c];
-                const T* gi = sg + i * (2 * B - i - 1) / 2;
+    for (int i = B - 1; i >= 0; --i) {
+        if (i < jb) {
+            T s = W1[(long)i * ncols + c];
+            const T* gi = sg + i * (2 * B - i - 1) / 2;
 #pragma unroll
-                for (int l = i + 1; l < B; ++l)
-                    if (l < jb) s -= gi[l - i - 1] * w[l];
-                w[i] = st[i] * s;
-                W2[(long)i * ncols + c] = w[i];
-            }
-        }
-    } else {
-        // W2[i] = conj(tau_i) (W1[i] - sum_{l < i} conj(G[l][i]) W2[l])
-#pragma unroll
-        for (int i = 0; i < B; ++i) {
-            if (i < jb) {
-                T s = W1[(long)i * ncols + c];
-#pragma unroll
-                for (int l = 0; l < B; ++l)
-                    if (l < i) s -= conj_(sg[l * (2 * B - l - 1) / 2 + (i - l - 1)]) * w[l];
-                w[i] = st[i] * s;
-                W2[(long)i * ncols + c] = w[i];
-            }
+            for (int l = i + 1; l < B; ++l)
+                if (l < jb) s -= gi[l - i - 1] * w[l];
+            w[i] = st[i] * s;
+            W2[(long)i * ncols + c] = w[i];
         }
     }
 }
 
 template <typename T>
-void backtransform_q(hipStream_t s, int n, int batch, const T* Vall, const T* tau, int ncols, T* X, int ldx,
-                     long sX, BacktrWork<T>& w, bool adjoint) {
+__global__ void identity_kernel(int m, T* X) {
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < m * m) X[e] = (e / m == e % m) ? from_re<T>(1.0) : zero_<T>();
+}
+
+// The compact-WY factors T_b (jb x jb, row-major, at Tall + b BT^2 per matrix)
+// of every block of BT reflectors: G = V_b^H V_b, then T_b = T I by back
+// substitution.
+template <typename T>
+void backtransform_prepare(hipStream_t s, int n, int batch, const T* Vall, const T* tau, BacktrWork<T>& w) {
+    const int bt = BACKTR_BT;
+    const int B = batch;
+    const long sV = (long)n * n;
+    const int nref = n - 1;
+    if (nref <= 0) return;
+    const int nblk = cdiv(nref, bt);
+    hipLaunchKernelGGL((identity_kernel<T>), dim3(cdiv(bt * bt, 256)), dim3(256), 0, s, bt, w.W1);
+    for (int b = 0; b < nblk; ++b) {
+        int b0 = b * bt;
+        int jb = min(bt, nref - b0);
+        int m = n - b0 - 1;
+        const T* Vb = Vall + (long)(b0 + 1) * n + b0;
+        gemm_splitk<T>(s, OP_C, OP_N, jb, jb, m, 1.0, Vb, n, Vb, n, 0.0, w.G, jb, w.P, w.pelems, B, sV, sV,
+                       (long)jb * jb);
+        if (jb < bt)  // a ragged last block: the identity of its own size
+            hipLaunchKernelGGL((identity_kernel<T>), dim3(cdiv(jb * jb, 256)), dim3(256), 0, s, jb, w.W2);
+        // T_b = T I (the identity is shared by the batch: matrix stride 0 through ld = jb)
+        hipLaunchKernelGGL((apply_t_kernel<T>), dim3(1, B), dim3(256), 0, s, jb, jb, tau + b0, (long)n,
+                           w.G, jb < bt ? w.W2 : w.W1, w.Tall + (long)b * bt * bt, (long)0, w.sTall);
+    }
+}
+
+template <typename T>
+void backtransform_q(hipStream_t s, int n, int batch, const T* Vall, int ncols, T* X, int ldx, long sX,
+                     BacktrWork<T>& w, bool adjoint) {
     const int bt = BACKTR_BT;
     const int B = batch;
     const long sV = (long)n * n;
@@ -99,17 +115,12 @@ void backtransform_q(hipStream_t s, int n, int batch, const T* Vall, const T* ta
         int jb = min(bt, nref - b0);
         int m = n - b0 - 1;
         const T* Vb = Vall + (long)(b0 + 1) * n + b0;
+        const T* Tb = w.Tall + (long)b * bt * bt;
         T* Xb = X + (long)(b0 + 1) * ldx;
-        gemm_splitk<T>(s, OP_C, OP_N, jb, jb, m, 1.0, Vb, n, Vb, n, 0.0, w.G, jb, w.P, w.pelems, B, sV, sV,
-                       (long)jb * jb);
         gemm_splitk<T>(s, OP_C, OP_N, jb, ncols, m, 1.0, Vb, n, Xb, ldx, 0.0, w.W1, ncols, w.P, w.pelems, B, sV,
                        sX, (long)jb * ncols);
-        if (adjoint)
-            hipLaunchKernelGGL((apply_t_kernel<T, true>), dim3(cdiv(ncols, 256), B), dim3(256), 0, s, jb, ncols,
-                               tau + b0, (long)n, w.G, w.W1, w.W2);
-        else
-            hipLaunchKernelGGL((apply_t_kernel<T, false>), dim3(cdiv(ncols, 256), B), dim3(256), 0, s, jb, ncols,
-                               tau + b0, (long)n, w.G, w.W1, w.W2);
+        gemm<T>(s, adjoint ? OP_C : OP_N, OP_N, jb, ncols, jb, 1.0, Tb, jb, w.sTall, w.W1, ncols, (long)jb * ncols,
+                0.0, w.W2, ncols, (long)jb * ncols, B);
         gemm<T>(s, OP_N, OP_N, m, ncols, jb, -1.0, Vb, n, sV, w.W2, ncols, (long)jb * ncols, 1.0, Xb, ldx, sX, B);
     }
 }
@@ -212,8 +223,9 @@ void fermi(hipStream_t s, int batch, int order, const double* eps, const KWeight
 }
 
 #define KS_INST(T)                                                                                 \
-    template void backtransform_q<T>(hipStream_t, int, int, const T*, const T*, int, T*, int, long,  \
+    template void backtransform_q<T>(hipStream_t, int, int, const T*, int, T*, int, long,            \
                                      BacktrWork<T>&, bool);                                       \
+    template void backtransform_prepare<T>(hipStream_t, int, int, const T*, const T*, BacktrWork<T>&); \
     template void load_z<T>(hipStream_t, int, int, int, const double*, int, T*, int, long);
 KS_INST(double)
 KS_INST(cplx)

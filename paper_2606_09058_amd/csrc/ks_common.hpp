@@ -157,7 +157,9 @@ enum Uplo { UPLO_FULL = 0, UPLO_LOWER = 1 };
 // Known-zero structure of an operand, used to shorten the K loop of a tile:
 // op(A) lower triangular (zero for k > m), op(B) upper triangular (zero for
 // k > n), op(A) upper triangular (zero for k < m).
-enum Tri { TRI_NONE = 0, TRI_A_LOWER = 1, TRI_B_UPPER = 2, TRI_A_UPPER = 3 };
+// Triangular operand of a GEMM (op applied): the tile loop skips the K range
+// where that operand is zero.
+enum Tri { TRI_NONE = 0, TRI_A_LOWER = 1, TRI_B_UPPER = 2, TRI_A_UPPER = 3, TRI_B_LOWER = 4 };
 
 // C = alpha op(A) op(B) (diag kscale between them if given) + beta C,
 // row-major, for `batch` problems with element strides sa, sb, sc.

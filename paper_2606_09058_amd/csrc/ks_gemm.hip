@@ -322,6 +322,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(int m, int n, int K, double a
     if (tri == TRI_A_LOWER) K = min(K, m0 + BM);
     if (tri == TRI_B_UPPER) K = min(K, n0 + BN);
     if (tri == TRI_A_UPPER) klo = (m0 / BK) * BK;
+    if (tri == TRI_B_LOWER) klo = (n0 / BK) * BK;
     gemm_tile<T, OPA, OPB>(m, n, K, alpha, A + b * sa, lda, B + b * sb, ldb, beta, C + b * sc, ldc,
                            kscale ? kscale + b * sk : nullptr, uplo, m0, n0, klo);
 }

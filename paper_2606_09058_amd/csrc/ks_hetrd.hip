@@ -336,6 +336,7 @@ __global__ __launch_bounds__(256) void wcol_kernel(int n, int k, int j, int nb, 
     __shared__ T vk[HETRD_NB + 1], wk[HETRD_NB + 1];  // V and W on row k+1
     __shared__ T party[4][WC_ROWS], partc[4][WC_ROWS];
     __shared__ T rowv[WC_ROWS], roww[WC_ROWS], rowx[WC_ROWS];
+    __shared__ T ys1[1];
     __shared__ double red[4];
     const int t = threadIdx.x, lr = t & 63, pp = t >> 6;
     const int I = blockIdx.x, z = blockIdx.z;
@@ -350,6 +351,19 @@ __global__ __launch_bounds__(256) void wcol_kernel(int n, int k, int j, int nb, 
     T* partA = hw.partPQ + z * hw.spart;
     const int r = k + 1 + I * WC_ROWS + lr;
     const bool in = r < n;
+    // loads that depend on nothing computed here are issued first
+    T xr = zero_<T>(), ar = zero_<T>();
+    if (pp == 0 && in) {
+        xr = x[r];
+        if (next) ar = widen(A[(long)r * lda + k + 1]);
+    }
+    if (pp == 1) {
+        // y_{k+1} (row 0 of tile row 0) for the W entry on row k+1
+        T ys = zero_<T>();
+        for (int I2 = 1 + lr; I2 < nt; I2 += 64) ys += pcol[(long)I2 * ST];
+        ys = wave_sum(ys);
+        if (lr == 0) ys1[0] = prow[0] + ys;
+    }
     const T sc = pq[0], tv = pq[1];
     if (t < j) {
         sp[t] = pq[2 + t];
@@ -382,7 +396,7 @@ __global__ __launch_bounds__(256) void wcol_kernel(int n, int k, int j, int nb, 
     // v^H A v from the product's partials (same order in every workgroup)
     double va = 0.0;
     for (int f = t; f < nt * nch; f += 256) va += pvav[f];
-    const double vAv = block_sum(va, red);  // its barriers also publish sp, sq, vk, wk
+    const double vAv = block_sum(va, red);  // its barriers also publish sp, sq, vk, wk, ys1
     double cr = 0.0;
     for (int i = 0; i < j; ++i) cr += re_(conj_(sq[i]) * sp[i]);
     const double alpha = -0.5 * abs2_(tv) * (vAv - 2.0 * cr);
@@ -398,13 +412,10 @@ __global__ __launch_bounds__(256) void wcol_kernel(int n, int k, int j, int nb, 
     party[pp][lr] = (y0 + y1) - cy;
     partc[pp][lr] = cx;
     if (pp == 0) {
-        // W on row k+1 (where v = 1); y_{k+1} is row 0 of tile row 0
-        T ys = zero_<T>();
-        for (int I2 = 1 + lr; I2 < nt; I2 += 64) ys += pcol[(long)I2 * ST];
-        ys = wave_sum(ys);
+        // W on row k+1 (where v = 1)
         T cs = lr < j ? vk[lr] * sp[lr] + wk[lr] * sq[lr] : zero_<T>();
         cs = wave_sum(cs);
-        T w1 = tv * ((prow[0] + ys) - cs) + from_re<T>(alpha);
+        T w1 = tv * (ys1[0] - cs) + from_re<T>(alpha);
         if (lr == 0) {
             wk[j] = w1;
             vk[j] = from_re<T>(1.0);
@@ -415,7 +426,7 @@ __global__ __launch_bounds__(256) void wcol_kernel(int n, int k, int j, int nb, 
         T v = zero_<T>(), w = zero_<T>(), xn = zero_<T>();
         if (in) {
             T y = (party[0][lr] + party[1][lr]) + (party[2][lr] + party[3][lr]);
-            v = (r == k + 1) ? from_re<T>(1.0) : sc * x[r];
+            v = (r == k + 1) ? from_re<T>(1.0) : sc * xr;
             w = (r == k + 1) ? wk[j] : tv * y + alpha * v;
             VWt[(long)j * n + r] = v;
             VWt[(long)(nb + j) * n + r] = w;
@@ -423,7 +434,7 @@ __global__ __launch_bounds__(256) void wcol_kernel(int n, int k, int j, int nb, 
             WVc[(long)(nb + j) * n + r] = conj_(v);
             if (next) {
                 T cc = (partc[0][lr] + partc[1][lr]) + (partc[2][lr] + partc[3][lr]);
-                xn = widen(A[(long)r * lda + k + 1]) - cc - (v * conj_(wk[j]) + w);
+                xn = ar - cc - (v * conj_(wk[j]) + w);
                 if (r == k + 1) xn = from_re<T>(re_(xn));
                 x[r] = xn;
             }

@@ -87,12 +87,13 @@ struct HetrdWork {
 
 template <typename T>
 struct BacktrWork {
-    T* G;         // BT x BT
-    T* Tf;        // BT x BT (spare)
-    T* W1;        // BT x n
-    T* W2;        // BT x n
+    T* G;         // BT x BT per matrix: V_b^H V_b
+    T* W1;        // BT x n per matrix
+    T* W2;        // BT x n per matrix
     T* P;         // split-K partial products
     long pelems;  // capacity of P in elements
+    T* Tall;      // cdiv(n-1, BT) x BT x BT per matrix: the compact-WY factors
+    long sTall;   // matrix stride of Tall
 };
 
 // Divide-and-conquer scratch; all position-indexed arrays have n entries and
@@ -134,12 +135,14 @@ struct DcTree {
 template <typename T>
 void fill_zero(hipStream_t s, T* p, long n);
 
+// Cholesky S = L L^H in place in L (lower) and L^-1 into Li (lower, zeros
+// above) for a batch (strides sl, si); work holds n^2/4 elements per matrix
+// (stride sw).  A failing pivot records its 1-based column in info.
 template <typename T>
-void potrf(hipStream_t s, int n, T* A, int lda, long sa, int batch, int* info);
+void potrf_inv(hipStream_t s, int n, T* L, int ldl, long sl, T* Li, int ldi, long si, T* work, long sw,
+               int batch, int* info);
 
-template <typename T>
-void trsm_left(hipStream_t s, bool conjt, int nl, int cols, const T* L, int ldl, long sl, T* B,
-               int ldb, long sb, int batch);
+
 
 template <typename T>
 void herm_complete(hipStream_t s, int n, const T* src, int lds, long ss, T* dst, int ldd, long sd,
@@ -151,8 +154,7 @@ template <typename T>
 void reduce_to_standard(hipStream_t s, int n, int nsp, int batch, const T* H, int ldh, long sH, const T* Linv,
                         int ldi, long sL, T* A, T* W, int* info);
 
-template <typename T>
-void tri_inverse(hipStream_t s, int n, const T* L, int ldl, long sl, T* Linv, long si, int batch);
+
 
 template <typename T, typename S>
 void hetrd(hipStream_t s, int n, S* A, int lda, long sA, int batch, double* d, double* e, T* tau, T* Vall,
@@ -181,11 +183,15 @@ void dc_tree_host(int n, std::vector<int>& mlo, std::vector<int>& mmid, std::vec
 template <typename T>
 void load_z(hipStream_t s, int n, int batch, int ncols, const double* Z, int c0, T* X, int ldx, long sX);
 
-// X <- Q X (or Q^H X with adjoint) for a batch: Q from the reflectors in Vall
-// (n x n per matrix, the tridiagonalisation's layout) and tau (n per matrix).
+// The compact-WY factors of every block of reflectors of a batch (Vall: n x n
+// per matrix, the tridiagonalisation's layout; tau: n per matrix) into w.Tall.
 template <typename T>
-void backtransform_q(hipStream_t s, int n, int batch, const T* Vall, const T* tau, int ncols, T* X, int ldx,
-                     long sX, BacktrWork<T>& w, bool adjoint = false);
+void backtransform_prepare(hipStream_t s, int n, int batch, const T* Vall, const T* tau, BacktrWork<T>& w);
+
+// X <- Q X (or Q^H X with adjoint) for a batch, with the factors prepared above.
+template <typename T>
+void backtransform_q(hipStream_t s, int n, int batch, const T* Vall, int ncols, T* X, int ldx, long sX,
+                     BacktrWork<T>& w, bool adjoint = false);
 
 void fermi(hipStream_t s, int batch, int order, const double* eps, const KWeights& kw, double g,
            double ne, double kT, int il, int iu, double* occ, double* mu, double* eband, int* kwin,

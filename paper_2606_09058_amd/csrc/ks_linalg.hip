@@ -1,207 +1,139 @@
 // ks_linalg.hip -- Cholesky factorisation of S, triangular solves, and the
 // reduction A = L^-1 H L^-H of the generalized problem to standard form.
 //
-// Cholesky and the triangular solves are recursive: the diagonal 32 x 32
-// blocks are factored/solved by LDS-resident single-workgroup kernels and
+// Cholesky is recursive and forms the inverse factor alongside: an
+// LDS-resident workgroup factors and inverts each 64 x 64 diagonal block and
 // everything else is an MFMA GEMM (ks_gemm.hip), so the O(n^3) work runs on
-// the matrix cores.  The inverse factor L^-1 is formed once per overlap (and
-// cached with L), so the reduction and the final back-substitution of every
-// solve are plain triangular-aware GEMMs.  The spinor form applies L^-1 to each
+// the matrix cores.  L^-1 is formed once per overlap and cached with L, so the
+// reduction and the final back-substitution of every solve are plain
+// triangular-aware GEMMs.  The spinor form applies L^-1 to each
 // spin block, i.e. (I2 (x) L)^-1 H (I2 (x) L)^-H, by treating the 2n x 2n
 // matrix as two n-row (then n-column) blocks: a batch of 2 with a block stride.
 #include "ks_internal.hpp"
 
 namespace ks {
 
-constexpr int TB = 32;  // leaf block of the recursive Cholesky / solves
-
-static int split_point(int n) {
-    int n1 = ((n / 2 + TB - 1) / TB) * TB;
-    if (n1 >= n) n1 = n - TB;
-    return n1;
-}
-
 // ---------------------------------------------------------------- Cholesky
-// Factor the n x n (n <= 32) lower block at A in place; column failures go to
-// info with the global 1-based column col0 + j + 1.
+// Recursive with explicit inverse: for S = [S11 S12; S21 S22],
+//   L11, inv11 from S11;  L21 = S21 inv11^H;  S22 -= L21 L21^H;
+//   L22, inv22 from S22;  inv21 = -inv22 L21 inv11,
+// down to 64 x 64 diagonal blocks that one workgroup factors and inverts in
+// LDS.  Every product is an MFMA GEMM with a large inner dimension, the
+// triangular operands skipping their zero half.
+constexpr int CB = 64;
+
+// Factor the nb x nb (nb <= CB) lower block at A in place and write its inverse
+// (lower, zero above) at D.  Column j of the factorisation and of the inverse
+// (right-looking forward substitution of L X = I) share one step with one
+// barrier: every thread reads the pivot itself; row i > j, entry c <= i takes
+//   c >  j:  S[i][c] -= S[i][j] conj(S[c][j]) / d_j      (factor)
+//   c <= j:  Y[i][c] -= S[i][j] Y[j][c] / d_j            (inverse)
+// with the columns of S and rows of Y left unscaled until the end
+// (L[i][j] = S[i][j] / sqrt(d_j), X[i][c] = Y[i][c] / sqrt(d_i)).  One wavefront
+// per row (rows j+1+w, j+5+w, ...), one lane per column: no index division.
+// A non-positive or non-finite pivot records the global 1-based column
+// col0 + j + 1 and continues with pivot 1.
 template <typename T>
-__global__ __launch_bounds__(64) void potrf_leaf_kernel(int n, T* A, int lda, long sa, int col0,
-                                                        int* info) {
-    __shared__ T L[TB][TB + 1];
-    __shared__ int bad;
+__global__ __launch_bounds__(256) void potrf_inv_leaf_kernel(int nb, T* A, int lda, long sa, T* D, int ldd,
+                                                             long sd, int col0, int* info) {
+    __shared__ T sL[CB][CB + 1];
+    __shared__ T sY[CB][CB + 1];
+    __shared__ double rl[CB];
     A += blockIdx.x * sa;
-    int t = threadIdx.x;
-    if (t == 0) bad = 0;
-    for (int e = t; e < n * n; e += 64) {
-        int i = e / n, j = e % n;
-        L[i][j] = (j <= i) ? A[(long)i * lda + j] : zero_<T>();
+    D += blockIdx.x * sd;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    for (int i = w; i < CB; i += 4) {
+        sL[i][lane] = (i < nb && lane <= i) ? A[(long)i * lda + lane] : zero_<T>();
+        sY[i][lane] = (i == lane) ? from_re<T>(1.0) : zero_<T>();
     }
     __syncthreads();
-    for (int j = 0; j < n; ++j) {
+    for (int j = 0; j < nb; ++j) {
+        const double d = re_(sL[j][j]);
+        const bool bad = !(d > 0.0) || !isfinite(d);
+        const double dj = bad ? 1.0 : d;
+        const double inv_d = 1.0 / dj;
         if (t == 0) {
-            double d = re_(L[j][j]);
-            for (int k = 0; k < j; ++k) d -= abs2_(L[j][k]);
-            if (!(d > 0.0) || !isfinite(d)) {
-                if (!bad) set_info(info, KS_ERR_NOT_POSDEF, col0 + j + 1);
-                bad = 1;
-                d = 1.0;
-            }
-            L[j][j] = from_re<T>(sqrt(d));
+            if (bad) set_info(info, KS_ERR_NOT_POSDEF, col0 + j + 1);
+            rl[j] = 1.0 / sqrt(dj);
         }
-        __syncthreads();
-        double ljj = re_(L[j][j]);
-        for (int i = j + 1 + t; i < n; i += 64) {
-            T s = L[i][j];
-            for (int k = 0; k < j; ++k) s -= L[i][k] * conj_(L[j][k]);
-            L[i][j] = s * (1.0 / ljj);
+        const int c = lane;
+        const T scj = conj_(sL[c][j]) * inv_d;  // factor part (c > j)
+        const T ycj = sY[j][c] * inv_d;          // inverse part (c <= j)
+        for (int i = j + 1 + w; i < nb; i += 4) {
+            const T sij = sL[i][j];
+            if (c > j && c <= i) sL[i][c] -= sij * scj;
+            else if (c <= j) sY[i][c] -= sij * ycj;
         }
         __syncthreads();
     }
-    for (int e = t; e < n * n; e += 64) {
-        int i = e / n, j = e % n;
-        if (j <= i) A[(long)i * lda + j] = L[i][j];
-    }
-}
-
-// X L^H = B for X (rows x nl, nl <= 32), in place in B; one thread per row.
-template <typename T>
-__global__ __launch_bounds__(256) void trsm_right_leaf_kernel(int rows, int nl, const T* L, int ldl,
-                                                              long sl, T* B, int ldb, long sb) {
-    __shared__ T sL[TB][TB + 1];
-    L += blockIdx.y * sl;
-    B += blockIdx.y * sb;
-    for (int e = threadIdx.x; e < nl * nl; e += blockDim.x) {
-        int i = e / nl, j = e % nl;
-        sL[i][j] = (j <= i) ? L[(long)i * ldl + j] : zero_<T>();
-    }
-    __syncthreads();
-    int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= rows) return;
-    T x[TB];
-    T* b = B + (long)r * ldb;
-#pragma unroll
-    for (int j = 0; j < TB; ++j) {
-        if (j < nl) {
-            T s = b[j];
-#pragma unroll
-            for (int i = 0; i < j; ++i) s -= x[i] * conj_(sL[j][i]);
-            x[j] = s * (1.0 / re_(sL[j][j]));
+    for (int i = w; i < nb; i += 4) {
+        const int c = lane;
+        if (c < nb) {
+            T lv = zero_<T>(), xv = zero_<T>();
+            if (c < i) lv = sL[i][c] * rl[c];
+            else if (c == i) lv = from_re<T>(1.0 / rl[i]);
+            if (c <= i) xv = sY[i][c] * rl[i];
+            if (c <= i) A[(long)i * lda + c] = lv;
+            D[(long)i * ldd + c] = xv;
         }
     }
-#pragma unroll
-    for (int j = 0; j < TB; ++j)
-        if (j < nl) b[j] = x[j];
 }
 
-// L X = B (conjt = 0) or L^H X = B (conjt = 1) for X (nl x cols, nl <= 32),
-// in place in B; one thread per column.
-template <typename T, int CONJT>
-__global__ __launch_bounds__(256) void trsm_left_leaf_kernel(int nl, int cols, const T* L, int ldl,
-                                                             long sl, T* B, int ldb, long sb) {
-    __shared__ T sL[TB][TB + 1];
-    L += blockIdx.y * sl;
-    B += blockIdx.y * sb;
-    for (int e = threadIdx.x; e < nl * nl; e += blockDim.x) {
-        int i = e / nl, j = e % nl;
-        sL[i][j] = (j <= i) ? L[(long)i * ldl + j] : zero_<T>();
-    }
-    __syncthreads();
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= cols) return;
-    T x[TB];
-    if constexpr (CONJT == 0) {
-#pragma unroll
-        for (int i = 0; i < TB; ++i) {
-            if (i < nl) {
-                T s = B[(long)i * ldb + c];
-#pragma unroll
-                for (int j = 0; j < i; ++j) s -= sL[i][j] * x[j];
-                x[i] = s * (1.0 / re_(sL[i][i]));
-            }
-        }
-    } else {
-#pragma unroll
-        for (int i = TB - 1; i >= 0; --i) {
-            if (i < nl) {
-                T s = B[(long)i * ldb + c];
-#pragma unroll
-                for (int j = i + 1; j < TB; ++j)
-                    if (j < nl) s -= conj_(sL[j][i]) * x[j];
-                x[i] = s * (1.0 / re_(sL[i][i]));
-            }
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < TB; ++i)
-        if (i < nl) B[(long)i * ldb + c] = x[i];
+// dst (rows x cols, ld ldd) = src (ld lds) for a batch.
+template <typename T>
+__global__ void copy_block_kernel(int rows, int cols, const T* src, int lds, long ss, T* dst, int ldd, long sd) {
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)rows * cols) return;
+    int r = (int)(e / cols), c = (int)(e % cols);
+    dst[blockIdx.y * sd + (long)r * ldd + c] = src[blockIdx.y * ss + (long)r * lds + c];
 }
 
 template <typename T>
-static void trsm_right_lh(hipStream_t s, int rows, int nl, const T* L, int ldl, long sl, T* B,
-                          int ldb, long sb, int batch) {
-    if (rows <= 0 || nl <= 0) return;
-    if (nl <= TB) {
-        dim3 grid(cdiv(rows, 256), batch);
-        hipLaunchKernelGGL((trsm_right_leaf_kernel<T>), grid, dim3(256), 0, s, rows, nl, L, ldl, sl,
-                           B, ldb, sb);
+static void potrf_inv_rec(hipStream_t s, int n, T* L, int ldl, long sl, T* Li, int ldi, long si, T* Tw, long st,
+                          int batch, int col0, int* info) {
+    if (n <= CB) {
+        hipLaunchKernelGGL((potrf_inv_leaf_kernel<T>), dim3(batch), dim3(256), 0, s, n, L, ldl, sl, Li, ldi, si,
+                           col0, info);
         return;
     }
-    int n1 = split_point(nl), n2 = nl - n1;
-    trsm_right_lh(s, rows, n1, L, ldl, sl, B, ldb, sb, batch);
-    gemm<T>(s, OP_N, OP_C, rows, n2, n1, -1.0, B, ldb, sb, L + (long)n1 * ldl, ldl, sl, 1.0, B + n1,
-            ldb, sb, batch);
-    trsm_right_lh(s, rows, n2, L + (long)n1 * ldl + n1, ldl, sl, B + n1, ldb, sb, batch);
+    int n1 = ((n / 2 + CB - 1) / CB) * CB;
+    if (n1 >= n) n1 = n - CB;
+    const int n2 = n - n1;
+    T* L21 = L + (long)n1 * ldl;
+    T* L22 = L21 + n1;
+    T* Li21 = Li + (long)n1 * ldi;
+    T* Li22 = Li21 + n1;
+    potrf_inv_rec(s, n1, L, ldl, sl, Li, ldi, si, Tw, st, batch, col0, info);
+    // L21 = S21 inv11^H (through Tw: a tile reads whole rows of S21)
+    gemm<T>(s, OP_N, OP_C, n2, n1, n1, 1.0, L21, ldl, sl, Li, ldi, si, 0.0, Tw, n1, st, batch, nullptr, 0,
+            UPLO_FULL, nullptr, TRI_B_UPPER);
+    long tot = (long)n2 * n1;
+    hipLaunchKernelGGL((copy_block_kernel<T>), dim3(cdiv(tot, 256), batch), dim3(256), 0, s, n2, n1, Tw, n1, st,
+                       L21, ldl, sl);
+    gemm<T>(s, OP_N, OP_C, n2, n2, n1, -1.0, L21, ldl, sl, L21, ldl, sl, 1.0, L22, ldl, sl, batch, nullptr, 0,
+            UPLO_LOWER);
+    potrf_inv_rec(s, n2, L22, ldl, sl, Li22, ldi, si, Tw, st, batch, col0 + n1, info);
+    // inv21 = -inv22 (L21 inv11)
+    gemm<T>(s, OP_N, OP_N, n2, n1, n1, 1.0, L21, ldl, sl, Li, ldi, si, 0.0, Tw, n1, st, batch, nullptr, 0,
+            UPLO_FULL, nullptr, TRI_B_LOWER);
+    gemm<T>(s, OP_N, OP_N, n2, n1, n2, -1.0, Li22, ldi, si, Tw, n1, st, 0.0, Li21, ldi, si, batch, nullptr, 0,
+            UPLO_FULL, nullptr, TRI_A_LOWER);
 }
 
 template <typename T>
-void trsm_left(hipStream_t s, bool conjt, int nl, int cols, const T* L, int ldl, long sl, T* B,
-               int ldb, long sb, int batch) {
-    if (cols <= 0 || nl <= 0) return;
-    if (nl <= TB) {
-        dim3 grid(cdiv(cols, 256), batch);
-        if (conjt)
-            hipLaunchKernelGGL((trsm_left_leaf_kernel<T, 1>), grid, dim3(256), 0, s, nl, cols, L, ldl,
-                               sl, B, ldb, sb);
-        else
-            hipLaunchKernelGGL((trsm_left_leaf_kernel<T, 0>), grid, dim3(256), 0, s, nl, cols, L, ldl,
-                               sl, B, ldb, sb);
-        return;
-    }
-    int n1 = split_point(nl), n2 = nl - n1;
-    const T* L21 = L + (long)n1 * ldl;
-    const T* L22 = L21 + n1;
-    T* B2 = B + (long)n1 * ldb;
-    if (!conjt) {
-        trsm_left(s, false, n1, cols, L, ldl, sl, B, ldb, sb, batch);
-        gemm<T>(s, OP_N, OP_N, n2, cols, n1, -1.0, L21, ldl, sl, B, ldb, sb, 1.0, B2, ldb, sb, batch);
-        trsm_left(s, false, n2, cols, L22, ldl, sl, B2, ldb, sb, batch);
-    } else {
-        trsm_left(s, true, n2, cols, L22, ldl, sl, B2, ldb, sb, batch);
-        gemm<T>(s, OP_C, OP_N, n1, cols, n2, -1.0, L21, ldl, sl, B2, ldb, sb, 1.0, B, ldb, sb, batch);
-        trsm_left(s, true, n1, cols, L, ldl, sl, B, ldb, sb, batch);
-    }
+__global__ void zero_upper_kernel(int n, T* X, int ldx, long sx) {
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)n * n) return;
+    int i = (int)(e / n), j = (int)(e % n);
+    if (j > i) X[blockIdx.y * sx + (long)i * ldx + j] = zero_<T>();
 }
 
 template <typename T>
-static void potrf_rec(hipStream_t s, int n, T* A, int lda, long sa, int batch, int col0, int* info) {
-    if (n <= TB) {
-        hipLaunchKernelGGL((potrf_leaf_kernel<T>), dim3(batch), dim3(64), 0, s, n, A, lda, sa, col0,
-                           info);
-        return;
-    }
-    int n1 = split_point(n), n2 = n - n1;
-    T* A21 = A + (long)n1 * lda;
-    T* A22 = A21 + n1;
-    potrf_rec(s, n1, A, lda, sa, batch, col0, info);
-    trsm_right_lh(s, n2, n1, A, lda, sa, A21, lda, sa, batch);
-    gemm<T>(s, OP_N, OP_C, n2, n2, n1, -1.0, A21, lda, sa, A21, lda, sa, 1.0, A22, lda, sa, batch,
-            nullptr, 0, UPLO_LOWER);
-    potrf_rec(s, n2, A22, lda, sa, batch, col0 + n1, info);
-}
-
-template <typename T>
-void potrf(hipStream_t s, int n, T* A, int lda, long sa, int batch, int* info) {
-    potrf_rec(s, n, A, lda, sa, batch, 0, info);
+void potrf_inv(hipStream_t s, int n, T* L, int ldl, long sl, T* Li, int ldi, long si, T* work, long sw,
+               int batch, int* info) {
+    long tot = (long)n * n;
+    hipLaunchKernelGGL((zero_upper_kernel<T>), dim3(cdiv(tot, 256), batch), dim3(256), 0, s, n, Li, ldi, si);
+    potrf_inv_rec<T>(s, n, L, ldl, sl, Li, ldi, si, work, sw, batch, 0, info);
 }
 
 // ---------------------------------------------------------------- copies
@@ -287,22 +219,6 @@ __global__ __launch_bounds__(256) void hermitize_kernel(int n, T* A, int lda) {
 
 // Explicit inverse of the lower triangular factor, Linv = L^-1 (solve L X = I);
 // the upper triangle of Linv comes out exactly zero.
-template <typename T>
-__global__ void set_identity_kernel(int n, T* X, long sx) {
-    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    X += blockIdx.y * sx;
-    if (e >= (long)n * n) return;
-    int i = (int)(e / n), j = (int)(e % n);
-    X[e] = (i == j) ? from_re<T>(1.0) : zero_<T>();
-}
-
-template <typename T>
-void tri_inverse(hipStream_t s, int n, const T* L, int ldl, long sl, T* Linv, long si, int batch) {
-    long tot = (long)n * n;
-    hipLaunchKernelGGL((set_identity_kernel<T>), dim3(cdiv(tot, 256), batch), dim3(256), 0, s, n, Linv, si);
-    trsm_left<T>(s, false, n, n, L, ldl, sl, Linv, n, si, batch);
-}
-
 // Reduction of H to A = (I (x) L)^-1 H (I (x) L)^-H with the explicit inverse:
 // two MFMA GEMMs whose triangular operand lets each tile skip the zero half of
 // its K range (~order^3 flops together for real input).  nsp spin blocks of n
@@ -335,12 +251,10 @@ void reduce_to_standard(hipStream_t s, int n, int nsp, int batch, const T* H, in
 }
 
 #define KS_INST(T)                                                                                 \
-    template void potrf<T>(hipStream_t, int, T*, int, long, int, int*);                            \
-    template void trsm_left<T>(hipStream_t, bool, int, int, const T*, int, long, T*, int, long, int); \
     template void herm_complete<T>(hipStream_t, int, const T*, int, long, T*, int, long, int, int*); \
     template void reduce_to_standard<T>(hipStream_t, int, int, int, const T*, int, long, const T*, int, \
                                         long, T*, T*, int*);                                        \
-    template void tri_inverse<T>(hipStream_t, int, const T*, int, long, T*, long, int);
+    template void potrf_inv<T>(hipStream_t, int, T*, int, long, T*, int, long, T*, long, int, int*);
 KS_INST(double)
 KS_INST(cplx)
 #undef KS_INST

@@ -73,18 +73,26 @@ int32_t ks_test_gemm(int32_t dtype, int32_t opa, int32_t opb, int32_t m, int32_t
     return finish(s);
 }
 
-int32_t ks_test_potrf(int32_t dtype, int32_t n, void* A, int32_t lda, int32_t* info, void* stream) {
+int32_t ks_test_potrf(int32_t dtype, int32_t n, void* A, int32_t lda, void* Linv, int32_t* info, void* stream) {
     if (!A || !info || n < 1 || lda < n) return KS_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
-    int* dinfo = nullptr;
-    if (hipMalloc((void**)&dinfo, 2 * sizeof(int)) != hipSuccess) return KS_ERR_ALLOC;
+    const size_t es = dtype == 1 ? 16 : 8;
+    const size_t nn = (size_t)n * n, nw = nn / 4 + 1;
+    char* buf = nullptr;
+    if (hipMalloc((void**)&buf, 256 + (nn + nw) * es) != hipSuccess) return KS_ERR_ALLOC;
+    int* dinfo = (int*)buf;
+    void* Li = buf + 256;
+    void* work = buf + 256 + nn * es;
     (void)hipMemsetAsync(dinfo, 0, 2 * sizeof(int), s);
-    if (dtype == 1) potrf<cplx>(s, n, (cplx*)A, lda, 0, 1, dinfo);
-    else potrf<double>(s, n, (double*)A, lda, 0, 1, dinfo);
+    if (dtype == 1)
+        potrf_inv<cplx>(s, n, (cplx*)A, lda, 0, (cplx*)Li, n, 0, (cplx*)work, 0, 1, dinfo);
+    else
+        potrf_inv<double>(s, n, (double*)A, lda, 0, (double*)Li, n, 0, (double*)work, 0, 1, dinfo);
+    if (Linv) (void)hipMemcpyAsync(Linv, Li, nn * es, hipMemcpyDeviceToDevice, s);
     int h[2] = {0, 0};
     int32_t st = finish(s);
     (void)hipMemcpy(h, dinfo, sizeof(h), hipMemcpyDeviceToHost);
-    (void)hipFree(dinfo);
+    (void)hipFree(buf);
     *info = h[0] ? h[1] : 0;
     return st;
 }

@@ -30,7 +30,7 @@ STATUS = {
 
 EXPORTS = ["ks_plan_create", "ks_plan_destroy", "ks_gevd", "ks_density", "ks_density_backward",
            "ks_plan_get_info", "ks_status_string", "ks_plan_workspace_bytes", "ks_plan_set_profiling",
-           "ks_plan_get_profile", "ks_plan_get_graph_stats", "ks_plan_get_tuning"]
+           "ks_plan_get_profile", "ks_plan_get_graph_stats", "ks_plan_get_tuning", "ks_plan_set_refinement"]
 
 
 class KSError(RuntimeError):
@@ -98,6 +98,8 @@ def lib():
         L.ks_plan_get_graph_stats.restype = I
         L.ks_plan_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
         L.ks_plan_get_tuning.restype = I
+        L.ks_plan_set_refinement.argtypes = [P, I]
+        L.ks_plan_set_refinement.restype = I
         _lib = L
     return _lib
 
@@ -216,6 +218,10 @@ class Plan:
         pr = Profile()
         _check(lib().ks_plan_get_profile(self._h, ctypes.byref(pr)), "ks_plan_get_profile")
         return pr
+
+    def set_refinement(self, sweeps):
+        """KS_MIXED: correction sweeps before the final Rayleigh-Ritz step."""
+        _check(lib().ks_plan_set_refinement(self._h, int(sweeps)), "ks_plan_set_refinement")
 
     def tuning(self):
         """{"tiles_per_workgroup": t, "candidates": {cand: ms}} (timings only under KS_PLAN_AUTOTUNE)."""

@@ -103,6 +103,33 @@ def test_mixed_kpoint_batch_vs_oracle():
     check(p, g, eps_o, rho_o, fr["mu"], iu)
 
 
+def test_mixed_refinement_sweeps_converge():
+    """Each correction sweep shrinks the window subspace error by ~u32 ||A|| / gap;
+    Rayleigh-Ritz eigenvalues carry its square.  Zero sweeps leave the FP32
+    subspace (eigenvalues off by ~1e-8 here); one sweep already meets the 1e-10 Ha
+    bar; the error does not grow with more sweeps."""
+    announce("mixed sweeps")
+    p = I.toy(seed=77, natoms=20, norb=13, edge=13.0, n_electrons=104.0, kT=0.01)
+    o = O.solve(p.H, p.S, p.n_electrons, p.kT)
+    iu = window_top(o["eps"], o["mu"])
+    errs = []
+    for sweeps in (0, 1, 2, 3):
+        plan = ks.Plan(p.n, precision=ks.KS_MIXED)
+        plan.set_refinement(sweeps)
+        H, S = dev(p.H), dev(p.S)
+        eps = torch.empty(p.order, dtype=torch.float64, device="cuda")
+        C = torch.zeros((p.order, p.order), dtype=torch.float64, device="cuda")
+        plan.gevd(H, S, eps, C, il=1, iu=iu)
+        plan.check("gevd")
+        errs.append(np.abs(host(eps)[:iu] - o["eps"][:iu]).max())
+    assert errs[1] < EPS_TOL and errs[2] < EPS_TOL and errs[3] < EPS_TOL, errs
+    assert errs[0] > errs[1], errs
+    with pytest.raises(ks.KSError):
+        ks.Plan(p.n).set_refinement(1)  # FP64 plans have nothing to refine
+    with pytest.raises(ks.KSError):
+        ks.Plan(p.n, precision=ks.KS_MIXED).set_refinement(5)
+
+
 def test_mixed_window_must_hold_the_occupied_states():
     """A window that ends below occupied states is flagged by ks_density, as in FP64."""
     announce("mixed window too small")

@@ -22,7 +22,7 @@ def L():
     V, I32, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
     lib.ks_test_gemm.argtypes = [I32, I32, I32, I32, I32, I32, D, V, I32, V, I32, D, V, I32, I32, V]
     lib.ks_test_gemm.restype = I32
-    lib.ks_test_potrf.argtypes = [I32, I32, V, I32, ctypes.POINTER(I32), V]
+    lib.ks_test_potrf.argtypes = [I32, I32, V, I32, V, ctypes.POINTER(I32), V]
     lib.ks_test_potrf.restype = I32
     lib.ks_test_stedc.argtypes = [I32, V, V, V, V, ctypes.POINTER(I32), V]
     lib.ks_test_stedc.restype = I32
@@ -139,19 +139,25 @@ def test_gemm_lower_only(L):
     assert np.array_equal(got[~low], C0[~low])
 
 
-@pytest.mark.parametrize("n", [1, 31, 32, 33, 100, 257])
+@pytest.mark.parametrize("n", [1, 31, 63, 64, 65, 100, 128, 257, 330])
 @pytest.mark.parametrize("cplx", [False, True])
 def test_potrf_matches_oracle(L, n, cplx):
+    """Blocked Cholesky (64-column blocks, ragged last block) against the oracle's
+    column algorithm, and the inverse factor: L^-1 L = I, zeros above the diagonal."""
     announce("potrf", n, cplx)
     rng = np.random.default_rng(n)
     S = I.random_spd(rng, n, cplx)
     A = dev(S)
+    Li = torch.full((n, n), 7.0, dtype=A.dtype, device="cuda")
     info = ctypes.c_int32(-1)
-    assert L.ks_test_potrf(int(cplx), n, P(A), n, ctypes.byref(info), stream_handle()) == 0
+    assert L.ks_test_potrf(int(cplx), n, P(A), n, P(Li), ctypes.byref(info), stream_handle()) == 0
     assert info.value == 0
     Lg = np.tril(host(A))
     Lo = O.cholesky(S)
     assert np.abs(Lg - Lo).max() < 1e-12 * np.abs(Lo).max()
+    Lih = host(Li)
+    assert np.array_equal(np.triu(Lih, 1), np.zeros((n, n)))
+    assert np.abs(Lih @ Lo - np.eye(n)).max() < 1e-11 * max(1.0, np.linalg.cond(Lo))
 
 
 def test_potrf_reports_failing_column(L):
@@ -165,7 +171,7 @@ def test_potrf_reports_failing_column(L):
     A = dev(S)
     info = ctypes.c_int32(-1)
     announce("potrf failure")
-    assert L.ks_test_potrf(0, n, P(A), n, ctypes.byref(info), stream_handle()) == 0
+    assert L.ks_test_potrf(0, n, P(A), n, None, ctypes.byref(info), stream_handle()) == 0
     assert info.value == col
 
 
