@@ -114,8 +114,9 @@ def main():
     cplx = np.iscomplexobj(p.H)
     stream = torch.cuda.Stream() if args.graph else torch.cuda.current_stream()
     torch.cuda.set_stream(stream)
+    # the plan times its symmetric-product tile shapes at creation (KS_PLAN_AUTOTUNE)
     plan = ks.Plan(p.n, batch=p.batch, complex=cplx, noncollinear=p.nsp == 2, stream=stream,
-                   flags=ks.KS_PLAN_GRAPH if args.graph else 0)
+                   flags=ks.KS_PLAN_AUTOTUNE | (ks.KS_PLAN_GRAPH if args.graph else 0))
     H = torch.from_numpy(p.H).cuda()
     S = torch.from_numpy(p.S.astype(p.H.dtype)).cuda()
     eps = torch.empty(plan._vshape(), dtype=torch.float64, device="cuda")
@@ -195,6 +196,8 @@ def main():
         "warm_s_per_solve": ms_warm / 1e3,
         "wall_s_timed": wall,
         "phases_ms": phases,
+        "tuning": {"tiles_per_workgroup": plan.tuning()["tiles_per_workgroup"],
+                   "candidates_ms": {str(k): v for k, v in plan.tuning()["candidates"].items()}},
         "roofline": {"bound": "hbm", "kernel": "symv_kernel (trailing Hermitian matrix-vector "
                                                "product of the tridiagonalisation)",
                      "achieved": hemv_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -235,7 +238,8 @@ def compare_precisions(p, H, S, eps_all, mu, steps, buffer_ha=0.4):
     outs = {}
     for form, prec, sweeps in (("fp64", ks.KS_FP64, None), ("mixed", ks.KS_MIXED, 2),
                                ("mixed1", ks.KS_MIXED, 1)):
-        plan = ks.Plan(p.n, batch=p.batch, complex=cplx, noncollinear=p.nsp == 2, precision=prec)
+        plan = ks.Plan(p.n, batch=p.batch, complex=cplx, noncollinear=p.nsp == 2, precision=prec,
+                       flags=ks.KS_PLAN_AUTOTUNE)
         if sweeps is not None:
             plan.set_refinement(sweeps)
         eps = torch.empty(plan._vshape(), dtype=torch.float64, device="cuda")

@@ -24,79 +24,67 @@ __global__ void load_z_kernel(int n, int ncols, const double* Z, int c0, T* X, i
     X[(long)r * ldx + c] = from_re<T>(Z[(long)r * n + c0 + c]);
 }
 
-// W2 = T W1 for the compact-WY factor T of a block of reflectors (applied to the
-// identity it forms T itself): T^-1 = diag(1/tau) + strictly-upper(G) with
-// G = V^H V, so W2 solves the upper triangular system row by row from the
-// bottom, W2[i] = tau_i (W1[i] - sum_{l > i} G[i][l] W2[l]) (tau_i = 0 gives a
-// zero row, as the identity reflector contributes nothing).  One thread per
-// column of W1; the strict upper triangle of G is staged in LDS.
+// T_b of every block at once (blockIdx.x = block, blockIdx.y = matrix): the back
+// substitution of apply_t_kernel applied to the identity, column c by thread c,
+// from G_b (ld BT) to T_b (jb x jb, ld jb).
 template <typename T>
-__global__ __launch_bounds__(256) void apply_t_kernel(int jb, int ncols, const T* tau, long stau, const T* G,
-                                                      const T* W1, T* W2, long sw1, long sw2) {
+__global__ __launch_bounds__(64) void t_factors_kernel(int n, const T* tau, const T* Gall, long sG, T* Tall,
+                                                       long sT) {
     constexpr int B = BACKTR_BT;
-    {
-        const int b = blockIdx.y;
-        tau += b * stau;
-        G += (long)b * jb * jb;
-        W1 += b * sw1;
-        W2 += b * sw2;
-    }
-    __shared__ T sg[B * (B - 1) / 2];
+    const int b = blockIdx.x, z = blockIdx.y;
+    const int b0 = b * B, jb = min(B, n - 1 - b0);
+    const T* G = Gall + z * sG + (long)b * B * B;  // may alias Tb (read fully first)
+    T* Tb = Tall + z * sT + (long)b * B * B;
+    tau += (long)z * n + b0;
+    __shared__ T sg[B][B + 1];
     __shared__ T st[B];
-    for (int e = threadIdx.x; e < jb * jb; e += blockDim.x) {
-        int i = e / jb, l = e % jb;
-        if (l > i) sg[i * (2 * B - i - 1) / 2 + (l - i - 1)] = G[(long)i * jb + l];
-    }
+    for (int e = threadIdx.x; e < jb * jb; e += blockDim.x) sg[e / jb][e % jb] = G[(long)(e / jb) * B + e % jb];
     if (threadIdx.x < jb) st[threadIdx.x] = tau[threadIdx.x];
-    __syncthreads();
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncols) return;
+    __syncthreads();  // all of G_b is in LDS before T_b overwrites it
+    const int c = threadIdx.x;
+    if (c >= jb) return;
     T w[B];
 #pragma unroll
     for (int i = B - 1; i >= 0; --i) {
         if (i < jb) {
-            T s = W1[(long)i * ncols + c];
-            const T* gi = sg + i * (2 * B - i - 1) / 2;
+            T acc = (i == c) ? from_re<T>(1.0) : zero_<T>();
 #pragma unroll
             for (int l = i + 1; l < B; ++l)
-                if (l < jb) s -= gi[l - i - 1] * w[l];
-            w[i] = st[i] * s;
-            W2[(long)i * ncols + c] = w[i];
+                if (l < jb) acc -= sg[i][l] * w[l];
+            w[i] = st[i] * acc;
+            Tb[(long)i * jb + c] = w[i];
         }
     }
 }
 
-template <typename T>
-__global__ void identity_kernel(int m, T* X) {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < m * m) X[e] = (e / m == e % m) ? from_re<T>(1.0) : zero_<T>();
-}
-
 // The compact-WY factors T_b (jb x jb, row-major, at Tall + b BT^2 per matrix)
-// of every block of BT reflectors: G = V_b^H V_b, then T_b = T I by back
-// substitution.
+// of every block of BT reflectors.  The reflector matrix is zero above each
+// block, so G_b = V_b^H V_b can run over all n rows: one split-K GEMM batched
+// over the full blocks (a ragged last block takes its own), then one launch
+// forms every T_b.
 template <typename T>
 void backtransform_prepare(hipStream_t s, int n, int batch, const T* Vall, const T* tau, BacktrWork<T>& w) {
     const int bt = BACKTR_BT;
-    const int B = batch;
-    const long sV = (long)n * n;
     const int nref = n - 1;
     if (nref <= 0) return;
-    const int nblk = cdiv(nref, bt);
-    hipLaunchKernelGGL((identity_kernel<T>), dim3(cdiv(bt * bt, 256)), dim3(256), 0, s, bt, w.W1);
-    for (int b = 0; b < nblk; ++b) {
-        int b0 = b * bt;
-        int jb = min(bt, nref - b0);
-        int m = n - b0 - 1;
-        const T* Vb = Vall + (long)(b0 + 1) * n + b0;
-        gemm_splitk<T>(s, OP_C, OP_N, jb, jb, m, 1.0, Vb, n, Vb, n, 0.0, w.G, jb, w.P, w.pelems, B, sV, sV,
-                       (long)jb * jb);
-        if (jb < bt)  // a ragged last block: the identity of its own size
-            hipLaunchKernelGGL((identity_kernel<T>), dim3(cdiv(jb * jb, 256)), dim3(256), 0, s, jb, w.W2);
-        // T_b = T I (the identity is shared by the batch: matrix stride 0 through ld = jb)
-        hipLaunchKernelGGL((apply_t_kernel<T>), dim3(1, B), dim3(256), 0, s, jb, jb, tau + b0, (long)n,
-                           w.G, jb < bt ? w.W2 : w.W1, w.Tall + (long)b * bt * bt, (long)0, w.sTall);
+    const int nblk = cdiv(nref, bt), nfull = nref / bt;
+    const long sV = (long)n * n;
+    for (int z = 0; z < batch; ++z) {
+        const T* V = Vall + z * sV;
+        // G_b is staged where T_b goes: each block of the next kernel reads its
+        // G_b into LDS before it writes T_b over it
+        T* Gz = w.Tall + z * w.sTall;
+        if (nfull > 0)
+            gemm_splitk<T>(s, OP_C, OP_N, bt, bt, n, 1.0, V, n, V, n, 0.0, Gz, bt, w.P, w.pelems, nfull, bt, bt,
+                           (long)bt * bt);
+        if (nblk > nfull) {
+            const int b0 = nfull * bt, jb = nref - b0;
+            gemm_splitk<T>(s, OP_C, OP_N, jb, jb, n, 1.0, V + b0, n, V + b0, n, 0.0, Gz + (long)nfull * bt * bt, bt,
+                           w.P, w.pelems);
+        }
     }
+    hipLaunchKernelGGL((t_factors_kernel<T>), dim3(nblk, batch), dim3(64), 0, s, n, tau, w.Tall, w.sTall, w.Tall,
+                       w.sTall);
 }
 
 template <typename T>

@@ -59,10 +59,24 @@ __global__ __launch_bounds__(256) void potrf_inv_leaf_kernel(int nb, T* A, int l
         const int c = lane;
         const T scj = conj_(sL[c][j]) * inv_d;  // factor part (c > j)
         const T ycj = sY[j][c] * inv_d;          // inverse part (c <= j)
-        for (int i = j + 1 + w; i < nb; i += 4) {
-            const T sij = sL[i][j];
-            if (c > j && c <= i) sL[i][c] -= sij * scj;
-            else if (c <= j) sY[i][c] -= sij * ycj;
+        // all reads of this step first (they cannot alias its writes), then the writes
+        constexpr int RPW = CB / 4;  // rows per wavefront
+        T sij[RPW], cur[RPW];
+#pragma unroll
+        for (int q = 0; q < RPW; ++q) {
+            const int i = j + 1 + w + 4 * q;
+            if (i < nb) {
+                sij[q] = sL[i][j];
+                cur[q] = (c > j) ? sL[i][c] : sY[i][c];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < RPW; ++q) {
+            const int i = j + 1 + w + 4 * q;
+            if (i < nb) {
+                if (c > j && c <= i) sL[i][c] = cur[q] - sij[q] * scj;
+                else if (c <= j) sY[i][c] = cur[q] - sij[q] * ycj;
+            }
         }
         __syncthreads();
     }
