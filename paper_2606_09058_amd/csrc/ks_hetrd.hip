@@ -235,14 +235,20 @@ __global__ __launch_bounds__(Sy<T>::THREADS, 4) void symv_kernel(int n, int k, i
         for (int q = 0; q < SY_R; ++q)
             cur[q] = (r0 + q < n && gc < n) ? A[(long)(r0 + q) * lda + gc] : zero_<S>();
     }
+    // the raw x entries of this workgroup's first tiles are loaded before the
+    // reflector's reduction, so their latency hides behind it
+    const int giI = o + I * ST + t, giJ = o + J0 * ST + col;
+    const T xI = (t < ST && giI < n) ? x[giI] : zero_<T>();
+    const T xJ = giJ < n ? x[giJ] : zero_<T>();
     T sc, tv;
     reflector<T>(k, nb, x, partA, nA, c == 0 && I == 0, d, e, taua, sc, tv);
     auto vof = [&](int gi) -> T {
         if (gi >= n) return zero_<T>();
         return (gi == o) ? from_re<T>(1.0) : sc * x[gi];
     };
-    if (t < ST) vI[t] = vof(o + I * ST + t);
-    T vJc = vof(o + J0 * ST + col);
+    auto vofx = [&](int gi, T xv) -> T { return gi >= n ? zero_<T>() : (gi == o ? from_re<T>(1.0) : sc * xv); };
+    if (t < ST) vI[t] = vofx(giI, xI);
+    T vJc = vofx(giJ, xJ);
     __syncthreads();
     T vr[SY_R], racc[SY_R];
 #pragma unroll
