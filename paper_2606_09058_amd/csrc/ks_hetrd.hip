@@ -587,12 +587,13 @@ int hetrd_tune(hipStream_t s, int n, T* A, int lda, long sA, int batch, double* 
         (void)hipEventDestroy(e0);
         return 0;
     }
-    // trailing sizes where the product is bandwidth-bound and where it is not
-    const int ks[4] = {0, n / 3, (2 * n) / 3, std::max(0, n - 1 - 4 * ST)};
+    // columns spread evenly over the tridiagonalisation, so that the sum
+    // estimates the whole solve's symmetric-product time
+    constexpr int NK = 8;
     for (int c = 0; c < nc; ++c) {
         float tot = 0.f;
-        for (int q = 0; q < 4; ++q) {
-            const int k = std::min(ks[q], n - 2);
+        for (int q = 0; q < NK; ++q) {
+            const int k = std::min((int)((long)q * (n - 1) / NK), n - 2);
             const int nA = cdiv(n - k, WC_ROWS);
             symv_launch<T, T>(s, cand[c], n, k, 0, A, lda, sA, batch, nA, d, e, tau, w);  // warm
             (void)hipEventRecord(e0, s);
