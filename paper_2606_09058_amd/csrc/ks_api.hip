@@ -145,7 +145,7 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
     size_t hPC = ntl * ntl * HETRD_TILE, hPV = ntl * nchl, hPQv = 2 + 2 * nb;
     size_t oVW = L.take(B * hVW * es), oWV = L.take(B * hVW * es);
     size_t oX = L.take(B * hX * es);
-    size_t oPQ = L.take(B * hPQ * es);
+    size_t oPQ = L.take(2 * B * hPQ * es);  // one partial buffer per column parity
     size_t oPR = L.take(B * hPR * es), oPC = L.take(B * hPC * es);
     size_t oPV = L.take(B * hPV * 8);
     size_t oPQv = L.take(B * hPQv * es);
@@ -216,6 +216,7 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
         h.pcol = (T*)(b + oPC);
         h.pvav = (double*)(b + oPV);
         h.pq = (T*)(b + oPQv);
+        h.sbuf = (long)(B * hPQ);
         h.sVW = (long)hVW;
         h.sx = (long)hX;
         h.spart = (long)hPQ;

@@ -7,15 +7,18 @@
 // read and kept up to date (row-major).  Panels of NB columns; a panel starts
 // with colstart (column k0 as the previous trailing update left it), then per
 // column k (panel column j) two launches:
-//   symv  (grid over 64 x 64 lower tiles) every workgroup reduces the column's
-//         partial |x|^2 and forms the reflector H_k = I - tau v v^H with
-//         H_k^H x = beta e_1 (beta real, so T is real for complex input); one
-//         workgroup also reduces the panel corrections p = W^H v, q = V^H v;
-//         then the tiles' share of y = A_trail v (the one pass over the
-//         trailing matrix, the memory-bound part, each lower tile read once)
-//         and of v^H A v;
-//   wcol  (grid over 64-row blocks) the final W column
-//         w = tau (y - V p - W q) + alpha v, and, inside the panel, the update
+//   symv  (grid over 64 x 64 lower tiles) the tiles' share of z = A_trail x
+//         with x the raw column (the one pass over the trailing matrix, the
+//         memory-bound part, each lower tile read once) and of x^H A x; one
+//         workgroup also reduces the raw panel products W^H x, V^H x.  It needs nothing
+//         reduced beforehand, so its tiles stream from the first instruction;
+//   wcol  (grid over 64-row blocks) the reflector H_k = I - tau v v^H with
+//         H_k^H x = beta e_1 (beta real, so T is real for complex input) from
+//         the partial |x|^2; with v = s x + c e_{k+1} (c = 1 - s x_{k+1}) the
+//         product is A v = s z + c a_1 (a_1 the trailing matrix's first
+//         column) and v^H A v follows from x^H A x, x^H a_1 = conj(z_{k+1})
+//         and a_11; then the final W column
+//         w = tau (A v - V p - W q) + alpha v, and, inside the panel, the update
 //         of column k+1 with the panel's reflectors and its partial sums
 //         |x|^2, W^H x, V^H x for the next reflector.
 // After the panel the lower triangle of the trailing matrix takes the rank-2NB
@@ -49,14 +52,15 @@ __device__ inline cplx make_c<cplx>(double re, double im) { return mk(re, im); }
 // Start of a panel: column k is already up to date (the trailing update of the
 // previous panel has been applied), so x = A[k.., k] and the per-workgroup
 // partial |x_{k+2..}|^2 is all the next reflector needs.  One wavefront per
-// 64 rows; partials laid out as below ([0] of each workgroup's record).
+// 64 rows; partials laid out as below ([0] of each workgroup's record), in the
+// buffer of column k's parity.
 template <typename T, typename S>
 __global__ __launch_bounds__(64) void colstart_kernel(int n, int k, int nb, const S* A, int lda, long sA,
                                                       HetrdWork<T> hw) {
     const int z = blockIdx.z;
     A += z * sA;
     T* x = hw.x + z * hw.sx;
-    T* partA = hw.partPQ + z * hw.spart;
+    T* partA = hw.partPQ + ((k & 1) ? hw.sbuf : 0) + z * hw.spart;
     int t = threadIdx.x;
     int r = k + blockIdx.x * 64 + t;
     T c = zero_<T>();
@@ -70,22 +74,18 @@ __global__ __launch_bounds__(64) void colstart_kernel(int n, int k, int nb, cons
     if (t == 0) partA[(long)blockIdx.x * (1 + 2 * nb)] = from_re<T>(a);
 }
 
-// The reflector of column k from the partials of the previous kernel: every
-// wavefront of every workgroup reduces the partial |x_{k+2..}|^2 in the same
-// order and forms H_k = I - tau v v^H with H_k^H x = beta e_1 itself, so no
-// barrier is needed.  Returns s = 1/(alpha - beta) (v = s x below row k+1) and
-// tau; the writer stores d[k], e[k], tau[k].
+// The reflector H_k = I - tau v v^H of column k with H_k^H x = beta e_1 from
+// alpha = x_{k+1} and the per-workgroup partials of |x_{k+2..}|^2, reduced by
+// one wavefront in a fixed order.  s = 1/(alpha - beta) gives v = s x below
+// row k+1 (v_{k+1} = 1); a zero column below the subdiagonal with real alpha
+// gives tau = 0 and s = 0.
 template <typename T>
-__device__ inline void reflector(int k, int nb, const T* x, const T* partA, int nA, bool writer, double* d,
-                                 double* e, T* taua, T& sc, T& tv) {
+__device__ inline void reflector(const T* partA, int nA, int ld, T alpha, T& sc, T& tv, double& beta) {
     const int lane = threadIdx.x & 63;
-    const int ld = 1 + 2 * nb;
     double a = 0.0;
     for (int b = lane; b < nA; b += 64) a += re_(partA[(long)b * ld]);
     const double xn2 = wave_sum(a);
-    const T alpha = x[k + 1];
     const double ar = re_(alpha), ai = im_(alpha);
-    double beta;
     if (xn2 == 0.0 && ai == 0.0) {
         tv = zero_<T>();
         beta = ar;
@@ -95,19 +95,15 @@ __device__ inline void reflector(int k, int nb, const T* x, const T* partA, int 
         tv = make_c<T>((beta - ar) / beta, -ai / beta);
         sc = inv_(alpha - from_re<T>(beta));
     }
-    if (writer && threadIdx.x == 0) {
-        d[k] = re_(x[k]);
-        e[k] = beta;
-        taua[k] = tv;
-    }
 }
 
-// The panel corrections p = W^H v and q = V^H v (v_{k+1} = 1, v = s x beyond),
-// reduced once per column by one workgroup of NW wavefronts and stored with s
-// and tau in pq: pq[0] = s, pq[1] = tau, pq[2 + i] = p_i, pq[2 + nb + i] = q_i.
+// The raw panel products W^H x and V^H x over rows k+2.. of column k, reduced
+// once per column by one workgroup of NW wavefronts from the partials of the
+// previous kernel: pq[2 + i] (W) and pq[2 + nb + i] (V), with pq[0] = x_{k+1}.
+// The reflector's scale and the row k+1 terms are applied by the next kernel.
 template <typename T, int NW>
-__device__ inline void panel_corrections(int n, int k, int j, int nb, const T* partA, int nA, const T* VWt,
-                                         T sc, T tv, T* pq, T (*part)[64]) {
+__device__ inline void panel_products(int k, int j, int nb, const T* x, const T* partA, int nA, T* pq,
+                                      T (*part)[64]) {
     static_assert(NW % 4 == 0, "wavefront count");
     const int t = threadIdx.x, lane = t & 63, g = t >> 6;
     const int ld = 1 + 2 * nb;
@@ -122,13 +118,10 @@ __device__ inline void panel_corrections(int n, int k, int j, int nb, const T* p
     if (t < nv) {
         T P = zero_<T>();
         for (int q = 0; q < NW; q += 4) P += (part[q][t] + part[q + 1][t]) + (part[q + 2][t] + part[q + 3][t]);
-        if (t < j) pq[2 + t] = conj_(VWt[(long)(nb + t) * n + k + 1]) + sc * P;
-        else pq[2 + nb + (t - j)] = conj_(VWt[(long)(t - j) * n + k + 1]) + sc * P;
+        if (t < j) pq[2 + t] = P;
+        else pq[2 + nb + (t - j)] = P;
     }
-    if (t == 0) {
-        pq[0] = sc;
-        pq[1] = tv;
-    }
+    if (t == 0) pq[0] = x[k + 1];
 }
 
 // Sum of r[0..R-1] over the 64 lanes for each of the R rows at once
@@ -176,21 +169,22 @@ __device__ inline T rows_lane_sum(const T (&r)[8], int lane) {
     return z;
 }
 
-// Trailing Hermitian matrix-vector product y = A_trail v from the LOWER
-// triangle only.  The trailing matrix (rows/cols k+1 .. n-1) is cut into
-// 64 x 64 tiles; workgroup (c, I) takes tiles J = SCH c .. SCH c + SCH-1
-// (SCH, the tiles per workgroup, is a template parameter picked per plan)
-// (J <= I) of tile row I.  Each of its threads holds one column and R rows
-// of a tile in registers (R = 8 for real, 4 for complex data, so that a
-// thread keeps two tiles' worth in flight within 128 registers) (the next tile's loads are issued before the
-// current one is used): the row sums A_IJ v_J stay in registers across the
+// Trailing Hermitian matrix-vector product z = A_trail x from the LOWER
+// triangle only, x the raw column k below its diagonal.  The trailing matrix
+// (rows/cols k+1 .. n-1) is cut into 64 x 64 tiles; workgroup (c, I) takes
+// tiles J = SCH c .. SCH c + SCH-1 (SCH, the tiles per workgroup, is a
+// template parameter picked per plan) (J <= I) of tile row I.  Each of its
+// threads holds one column and R rows of a tile in registers (R = 8 for real,
+// 4 for complex data, so that a thread keeps two tiles' worth in flight
+// within 128 registers; the next tile's loads are issued before the current
+// one is used): the row sums A_IJ x_J stay in registers across the
 // workgroup's tiles and are reduced over the lanes once at the end (into
-// prow); the column sums A_IJ^H v_I, one per tile, go to LDS and are reduced
-// over the row groups at the end (into pcol).  A diagonal tile is
-// expanded from its strict lower part.  Each workgroup also leaves its share
-// of v^H A v (2 Re v_I^H A_IJ v_J off the diagonal, v_I^H A_II v_I on it) in
-// pvav, from which the next kernel gets the W-column correction without a
-// pass over w.
+// prow); the column sums A_IJ^H x_I, one per tile, go to LDS and are reduced
+// over the row groups at the end (into pcol).  A diagonal tile is expanded
+// from its strict lower part.  Each workgroup also leaves its share of
+// x^H A x (2 Re x_I^H A_IJ x_J off the diagonal, x_I^H A_II x_I on it) in
+// pvav, from which the next kernel gets v^H A v and so the W-column
+// correction without a pass over w.
 constexpr int ST = HETRD_TILE;  // tile edge
 template <typename T>
 struct Sy {
@@ -201,8 +195,7 @@ struct Sy {
 
 template <typename T, typename S, int SCH>
 __global__ __launch_bounds__(Sy<T>::THREADS, 4) void symv_kernel(int n, int k, int j, int nb, const S* A, int lda,
-                                                          long sA, int nA, int nt, int nch, double* d,
-                                                          double* e, T* taua, HetrdWork<T> hw) {
+                                                          long sA, int nA, int nt, int nch, HetrdWork<T> hw) {
     constexpr int SY_R = Sy<T>::R, NG = Sy<T>::NG;
     __shared__ T vI[ST], yrow[ST];
     __shared__ T cred[SCH][NG][ST];
@@ -217,11 +210,7 @@ __global__ __launch_bounds__(Sy<T>::THREADS, 4) void symv_kernel(int n, int k, i
         return;
     }
     A += z * sA;
-    d += (long)z * n;
-    e += (long)z * n;
-    taua += (long)z * n;
     const T* x = hw.x + z * hw.sx;
-    const T* partA = hw.partPQ + z * hw.spart;
     T* prow = hw.prow + z * hw.sprow;
     T* pcol = hw.pcol + z * hw.spcol;
     const int ntile = min(J0 + SCH, I + 1) - J0;
@@ -235,20 +224,9 @@ __global__ __launch_bounds__(Sy<T>::THREADS, 4) void symv_kernel(int n, int k, i
         for (int q = 0; q < SY_R; ++q)
             cur[q] = (r0 + q < n && gc < n) ? A[(long)(r0 + q) * lda + gc] : zero_<S>();
     }
-    // the raw x entries of this workgroup's first tiles are loaded before the
-    // reflector's reduction, so their latency hides behind it
-    const int giI = o + I * ST + t, giJ = o + J0 * ST + col;
-    const T xI = (t < ST && giI < n) ? x[giI] : zero_<T>();
-    const T xJ = giJ < n ? x[giJ] : zero_<T>();
-    T sc, tv;
-    reflector<T>(k, nb, x, partA, nA, c == 0 && I == 0, d, e, taua, sc, tv);
-    auto vof = [&](int gi) -> T {
-        if (gi >= n) return zero_<T>();
-        return (gi == o) ? from_re<T>(1.0) : sc * x[gi];
-    };
-    auto vofx = [&](int gi, T xv) -> T { return gi >= n ? zero_<T>() : (gi == o ? from_re<T>(1.0) : sc * xv); };
-    if (t < ST) vI[t] = vofx(giI, xI);
-    T vJc = vofx(giJ, xJ);
+    auto xof = [&](int gi) -> T { return gi < n ? x[gi] : zero_<T>(); };
+    if (t < ST) vI[t] = xof(o + I * ST + t);
+    T vJc = xof(o + J0 * ST + col);
     __syncthreads();
     T vr[SY_R], racc[SY_R];
 #pragma unroll
@@ -266,7 +244,7 @@ __global__ __launch_bounds__(Sy<T>::THREADS, 4) void symv_kernel(int n, int k, i
 #pragma unroll
             for (int q = 0; q < SY_R; ++q)
                 nxt[q] = (r0 + q < n && gc < n) ? A[(long)(r0 + q) * lda + gc] : zero_<S>();
-            vJn = vof(gc);
+            vJn = xof(gc);
         }
         T cs = zero_<T>();
         if (J != I) {
@@ -306,30 +284,40 @@ __global__ __launch_bounds__(Sy<T>::THREADS, 4) void symv_kernel(int n, int k, i
             for (int q = 0; q < NG; q += 4)
                 cs += (cred[s][q][t] + cred[s][q + 1][t]) + (cred[s][q + 2][t] + cred[s][q + 3][t]);
             const int J = J0 + s;
-            if (J == I) ysum += cs;  // A_II^H v_I belongs to y_I as well
+            if (J == I) ysum += cs;  // A_II^H x_I belongs to z_I as well
             else pcol[((long)J * nt + I) * ST + t] = cs;
         }
         prow[((long)I * nch + c) * ST + t] = ysum;
     }
     if (t == 0) pvav[(long)I * nch + c] = vsum;
     if (c == 0 && I == 0)
-        panel_corrections<T, NG>(n, k, j, nb, partA, nA, hw.VW + z * hw.sVW, sc, tv, hw.pq + z * hw.spq, part);
+        panel_products<T, NG>(k, j, nb, x, hw.partPQ + ((k & 1) ? hw.sbuf : 0) + z * hw.spart, nA,
+                              hw.pq + z * hw.spq, part);
 }
 
-// Column k has just been reflected (panel column j).  One workgroup per 64
-// trailing rows r = k+1+64b+l, which is exactly tile row b of the symmetric
-// product, and four wavefronts that split every per-row sum four ways:
-//   * alpha = -|tau|^2 (v^H A v - 2 Re q^H p) / 2 from the product's v^H A v
-//     partials, with p = W^H v and q = V^H v, so w = tau (y - V p - W q) + alpha v
-//     is final at once (the usual w += alpha v with alpha = -tau w^H v / 2,
-//     since w^H v = conj(tau) v^H (A - V W^H - W V^H) v);
-//   * y_r from the tile partials, then w_r, stored with v_r in the panel;
+// Column k of the panel (panel column j) after its symmetric product.  One
+// workgroup per 64 trailing rows r = k+1+64b+l, which is exactly tile row b of
+// the product, and four wavefronts that split every per-row sum four ways:
+//   * the reflector (s, tau, beta) from alpha = x_{k+1} and the partial
+//     |x_{k+2..}|^2, by wavefront 0, while the others gather z_r;
+//   * A v = s z + c a_1 with c = 1 - s alpha (v = s x + c e_{k+1}) and
+//     v^H A v = |s|^2 x^H A x + 2 Re(conj(s) c x^H a_1) + |c|^2 a_11, where
+//     x^H a_1 = conj(z_{k+1}) since row k+1 of A is a_1^H;
+//   * p = W^H v and q = V^H v from the raw panel products (row k+1, where
+//     v = 1, added here), and alpha_w = -|tau|^2 (v^H A v - 2 Re q^H p) / 2, so
+//     w = tau (A v - V p - W q) + alpha_w v is final at once (the usual
+//     w += alpha_w v with alpha_w = -tau w^H v / 2, since
+//     w^H v = conj(tau) v^H (A - V W^H - W V^H) v);
+//   * w_r, stored with v_r in the panel;
 //   * unless column k closes the panel, column k+1 is brought up to date with
 //     the panel's j+1 reflectors, x_r = A[r][k+1] - V_r W_{k+1}^H - W_r V_{k+1}^H,
 //     and the workgroup's partials |x_{k+3..}|^2, W^H x and V^H x are written
-//     for the next reflector.
+//     for the next reflector, into the partial buffer of column k+1's parity
+//     (every workgroup reads all of column k's partials, so the two columns'
+//     partials cannot share one buffer).
 // Row k+1 of W (needed by every row for the update of column k+1) is
 // computed by every workgroup in the same order, so all of them agree.
+// Workgroup 0 stores d[k], e[k] = beta and tau[k].
 // Partials per workgroup: [0] |x|^2, [1+i] (W^H x)_i, [1+nb+i] (V^H x)_i.
 constexpr int WC_ROWS = 64;
 static_assert(WC_ROWS == ST, "a row block of wcol is a tile row of the symmetric product");
@@ -337,12 +325,13 @@ static_assert(2 * HETRD_NB <= 64 && HETRD_NB % 4 == 0, "panel width");
 constexpr int WC_MAXU = HETRD_NB / 4;  // panel columns per wavefront
 template <typename T, typename S>
 __global__ __launch_bounds__(256) void wcol_kernel(int n, int k, int j, int nb, int next, const S* A, int lda,
-                                                   long sA, int nt, int nch, int sch, HetrdWork<T> hw) {
+                                                   long sA, int nt, int nch, int sch, int nA, double* d,
+                                                   double* e, T* taua, HetrdWork<T> hw) {
     __shared__ T sp[HETRD_NB], sq[HETRD_NB];          // p = W^H v, q = V^H v
     __shared__ T vk[HETRD_NB + 1], wk[HETRD_NB + 1];  // V and W on row k+1
     __shared__ T party[4][WC_ROWS], partc[4][WC_ROWS];
     __shared__ T rowv[WC_ROWS], roww[WC_ROWS], rowx[WC_ROWS];
-    __shared__ T ys1[1];
+    __shared__ T ys1[1], refl[2];
     __shared__ double red[4];
     const int t = threadIdx.x, lr = t & 63, pp = t >> 6;
     const int I = blockIdx.x, z = blockIdx.z;
@@ -354,28 +343,23 @@ __global__ __launch_bounds__(256) void wcol_kernel(int n, int k, int j, int nb, 
     const double* pvav = hw.pvav + z * hw.spvav;
     T* VWt = hw.VW + z * hw.sVW;
     T* WVc = hw.WV + z * hw.sVW;
-    T* partA = hw.partPQ + z * hw.spart;
+    const long ldp = 1 + 2 * nb;
+    const T* partA = hw.partPQ + ((k & 1) ? hw.sbuf : 0) + z * hw.spart;
+    T* partN = hw.partPQ + ((k & 1) ? 0 : hw.sbuf) + z * hw.spart;
     const int r = k + 1 + I * WC_ROWS + lr;
     const bool in = r < n;
     // loads that depend on nothing computed here are issued first
     T xr = zero_<T>(), ar = zero_<T>();
     if (pp == 0 && in) {
         xr = x[r];
-        if (next) ar = widen(A[(long)r * lda + k + 1]);
+        ar = widen(A[(long)r * lda + k + 1]);  // a_1, and column k+1 before the panel's updates
     }
     if (pp == 1) {
-        // y_{k+1} (row 0 of tile row 0) for the W entry on row k+1
+        // z_{k+1} (row 0 of tile row 0) for the W entry on row k+1
         T ys = zero_<T>();
         for (int I2 = 1 + lr; I2 < nt; I2 += 64) ys += pcol[(long)I2 * ST];
         ys = wave_sum(ys);
         if (lr == 0) ys1[0] = prow[0] + ys;
-    }
-    const T sc = pq[0], tv = pq[1];
-    if (t < j) {
-        sp[t] = pq[2 + t];
-        sq[t] = pq[2 + nb + t];
-        vk[t] = VWt[(long)t * n + k + 1];
-        wk[t] = VWt[(long)(nb + t) * n + k + 1];
     }
     // this row's panel entries for columns i = pp, pp+4, ... < j
     T vr[WC_MAXU], wr[WC_MAXU];
@@ -386,7 +370,7 @@ __global__ __launch_bounds__(256) void wcol_kernel(int n, int k, int j, int nb, 
         vr[u] = ok ? VWt[(long)i * n + r] : zero_<T>();
         wr[u] = ok ? VWt[(long)(nb + i) * n + r] : zero_<T>();
     }
-    // y_r: row partials of tile row I, then column partials of the tiles below
+    // z_r: row partials of tile row I, then column partials of the tiles below
     T y0 = zero_<T>(), y1 = zero_<T>();
     if (in) {
         int nc = I / sch + 1;
@@ -399,13 +383,44 @@ __global__ __launch_bounds__(256) void wcol_kernel(int n, int k, int j, int nb, 
         }
         if (I2 < nt) y0 += pc[(long)I2 * ST];
     }
-    // v^H A v from the product's partials (same order in every workgroup)
+    // x^H A x from the product's partials (same order in every workgroup)
     double va = 0.0;
     for (int f = t; f < nt * nch; f += 256) va += pvav[f];
-    const double vAv = block_sum(va, red);  // its barriers also publish sp, sq, vk, wk, ys1
+    const T alpha = pq[0];
+    if (pp == 0) {
+        T sc, tv;
+        double beta;
+        reflector<T>(partA, nA, (int)ldp, alpha, sc, tv, beta);
+        if (lr == 0) {
+            refl[0] = sc;
+            refl[1] = tv;
+            if (I == 0) {
+                d[(long)z * n + k] = re_(x[k]);
+                e[(long)z * n + k] = beta;
+                taua[(long)z * n + k] = tv;
+            }
+        }
+        if (lr < j) {
+            const T vkt = VWt[(long)lr * n + k + 1], wkt = VWt[(long)(nb + lr) * n + k + 1];
+            vk[lr] = vkt;
+            wk[lr] = wkt;
+            sp[lr] = conj_(wkt) + sc * pq[2 + lr];
+            sq[lr] = conj_(vkt) + sc * pq[2 + nb + lr];
+        }
+    }
+    // one barrier for the sum; it also publishes refl, sp, sq, vk, wk, ys1
+    va = wave_sum(va);
+    if (lr == 0) red[pp] = va;
+    __syncthreads();
+    const double xAx = (red[0] + red[1]) + (red[2] + red[3]);
+    const T z1 = ys1[0];  // z_{k+1} = a_1^H x
+    const T sc = refl[0], tv = refl[1];
+    const T c1 = from_re<T>(1.0) - sc * alpha;  // v_{k+1} = s alpha + c1 = 1
+    const double a11 = re_(widen(A[(long)(k + 1) * lda + k + 1]));
+    const double vAv = abs2_(sc) * xAx + 2.0 * re_(conj_(sc) * c1 * conj_(z1)) + abs2_(c1) * a11;
     double cr = 0.0;
     for (int i = 0; i < j; ++i) cr += re_(conj_(sq[i]) * sp[i]);
-    const double alpha = -0.5 * abs2_(tv) * (vAv - 2.0 * cr);
+    const double alw = -0.5 * abs2_(tv) * (vAv - 2.0 * cr);
     T cy = zero_<T>(), cx = zero_<T>();
 #pragma unroll
     for (int u = 0; u < WC_MAXU; ++u) {
@@ -415,13 +430,13 @@ __global__ __launch_bounds__(256) void wcol_kernel(int n, int k, int j, int nb, 
             cx += vr[u] * conj_(wk[i]) + wr[u] * conj_(vk[i]);
         }
     }
-    party[pp][lr] = (y0 + y1) - cy;
+    party[pp][lr] = sc * (y0 + y1) - cy;
     partc[pp][lr] = cx;
     if (pp == 0) {
         // W on row k+1 (where v = 1)
         T cs = lr < j ? vk[lr] * sp[lr] + wk[lr] * sq[lr] : zero_<T>();
         cs = wave_sum(cs);
-        T w1 = tv * (ys1[0] - cs) + from_re<T>(alpha);
+        T w1 = tv * (sc * z1 + c1 * from_re<T>(a11) - cs) + from_re<T>(alw);
         if (lr == 0) {
             wk[j] = w1;
             vk[j] = from_re<T>(1.0);
@@ -431,9 +446,9 @@ __global__ __launch_bounds__(256) void wcol_kernel(int n, int k, int j, int nb, 
     if (pp == 0) {
         T v = zero_<T>(), w = zero_<T>(), xn = zero_<T>();
         if (in) {
-            T y = (party[0][lr] + party[1][lr]) + (party[2][lr] + party[3][lr]);
+            T y = (party[0][lr] + party[1][lr]) + (party[2][lr] + party[3][lr]) + c1 * ar;
             v = (r == k + 1) ? from_re<T>(1.0) : sc * xr;
-            w = (r == k + 1) ? wk[j] : tv * y + alpha * v;
+            w = (r == k + 1) ? wk[j] : tv * y + alw * v;
             VWt[(long)j * n + r] = v;
             VWt[(long)(nb + j) * n + r] = w;
             WVc[(long)j * n + r] = conj_(w);
@@ -453,7 +468,7 @@ __global__ __launch_bounds__(256) void wcol_kernel(int n, int k, int j, int nb, 
     __syncthreads();
     // partials for the next reflector over the panel columns 0 .. j
     const T xe = rowx[lr];
-    T* out = partA + (long)I * (1 + 2 * nb);
+    T* out = partN + (long)I * ldp;
     if (pp == 0) {
         double a = wave_sum(abs2_(xe));
         if (lr == 0) out[0] = from_re<T>(a);
@@ -494,18 +509,15 @@ __global__ void last_diag_kernel(int n, const S* A, int lda, long sA, double* d)
 // Launch the symmetric product of column k with sch tiles per workgroup.
 template <typename T, typename S>
 void symv_launch(hipStream_t s, int sch, int n, int k, int j, const S* A, int lda, long sA, int B, int nA,
-                 double* d, double* e, T* tau, const HetrdWork<T>& w) {
+                 const HetrdWork<T>& w) {
     const int m = n - k - 1, nt = cdiv(m, ST), nch = cdiv(nt, sch), nb = HETRD_NB;
     const dim3 grid(nch, nt, B), block(Sy<T>::THREADS);
     if (sch == 2)
-        hipLaunchKernelGGL((symv_kernel<T, S, 2>), grid, block, 0, s, n, k, j, nb, A, lda, sA, nA, nt, nch, d, e,
-                           tau, w);
+        hipLaunchKernelGGL((symv_kernel<T, S, 2>), grid, block, 0, s, n, k, j, nb, A, lda, sA, nA, nt, nch, w);
     else if (sch == 8 && !is_cplx<T>::value)
-        hipLaunchKernelGGL((symv_kernel<T, S, 8>), grid, block, 0, s, n, k, j, nb, A, lda, sA, nA, nt, nch, d, e,
-                           tau, w);
+        hipLaunchKernelGGL((symv_kernel<T, S, 8>), grid, block, 0, s, n, k, j, nb, A, lda, sA, nA, nt, nch, w);
     else
-        hipLaunchKernelGGL((symv_kernel<T, S, 4>), grid, block, 0, s, n, k, j, nb, A, lda, sA, nA, nt, nch, d, e,
-                           tau, w);
+        hipLaunchKernelGGL((symv_kernel<T, S, 4>), grid, block, 0, s, n, k, j, nb, A, lda, sA, nA, nt, nch, w);
 }
 
 // Panel buffers in the storage precision of the trailing matrix.
@@ -538,11 +550,11 @@ void hetrd(hipStream_t s, int n, S* A, int lda, long sA, int batch, double* d, d
             int nA = cdiv(n - k, WC_ROWS);  // workgroups that wrote the partials of column k
             bool smp = w.prof && w.prof->sample();
             hipEvent_t e0 = smp ? w.prof->begin() : nullptr;
-            symv_launch<T, S>(s, w.sch, n, k, j, A, lda, sA, B, nA, d, e, tau, w);
+            symv_launch<T, S>(s, w.sch, n, k, j, A, lda, sA, B, nA, w);
             // algorithmic bytes of a Hermitian matrix-vector product: the lower triangle once
             if (smp) w.prof->end(PROF_HEMV, e0, (double)sizeof(T) * m * (m + 1) / 2.0 * B);
             hipLaunchKernelGGL((wcol_kernel<T, S>), dim3(cdiv(m, WC_ROWS), 1, B), dim3(256), 0, s, n, k, j, nb,
-                               (int)(j + 1 < jb), A, lda, sA, nt, nch, w.sch, w);
+                               (int)(j + 1 < jb), A, lda, sA, nt, nch, w.sch, nA, d, e, tau, w);
         }
         long tot = (long)n * jb;
         hipLaunchKernelGGL((store_panel_kernel<T>), dim3(cdiv(tot, 256), 1, B), dim3(256), 0, s, n, k0, jb, w.VW,
@@ -595,10 +607,10 @@ int hetrd_tune(hipStream_t s, int n, T* A, int lda, long sA, int batch, double* 
         for (int q = 0; q < NK; ++q) {
             const int k = std::min((int)((long)q * (n - 1) / NK), n - 2);
             const int nA = cdiv(n - k, WC_ROWS);
-            symv_launch<T, T>(s, cand[c], n, k, 0, A, lda, sA, batch, nA, d, e, tau, w);  // warm
+            symv_launch<T, T>(s, cand[c], n, k, 0, A, lda, sA, batch, nA, w);  // warm
             (void)hipEventRecord(e0, s);
             for (int r = 0; r < reps; ++r)
-                symv_launch<T, T>(s, cand[c], n, k, 0, A, lda, sA, batch, nA, d, e, tau, w);
+                symv_launch<T, T>(s, cand[c], n, k, 0, A, lda, sA, batch, nA, w);
             (void)hipEventRecord(e1, s);
             (void)hipEventSynchronize(e1);
             float t = 0.f;

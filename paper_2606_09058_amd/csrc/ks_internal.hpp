@@ -73,15 +73,17 @@ struct HetrdWork {
     T* VW;          // 2NB x n   V then W of the current panel, transposed
     T* WV;          // 2NB x n   conj(W) then conj(V), transposed
     T* x;           // n         updated column
-    T* partPQ;      // cdiv(n, 64) x (1 + 2NB) partial |x|^2, W^H x, V^H x
+    T* partPQ;      // 2 x cdiv(n, 64) x (1 + 2NB) partial |x|^2, W^H x, V^H x; one buffer
+                    // per column parity, sbuf apart
     T* prow;        // nt x cdiv(nt, HETRD_SCH_MIN) x HETRD_TILE, nt = cdiv(n, HETRD_TILE): row partials
     T* pcol;        // nt x nt x HETRD_TILE                                           column partials
     double* pvav;   // nt x cdiv(nt, HETRD_SCH_MIN) partial v^H A v
-    T* pq;          // 2 + 2 NB: s, tau, W^H v, V^H v of the current column
+    T* pq;          // 2 + 2 NB: x_{k+1}, unused, raw W^H x, V^H x of the current column
     void* VWlo = nullptr;  // mixed form: VW and WV in FP32 for the trailing update
     void* WVlo = nullptr;
     // strides (elements) between the buffers of consecutive matrices of a batch
     long sVW = 0, sx = 0, spart = 0, sprow = 0, spcol = 0, spvav = 0, spq = 0;
+    long sbuf = 0;  // offset of the odd-column partial buffer
     int sch = HETRD_SCH;  // tiles per workgroup of the symmetric product (tuned per plan)
 };
 
