@@ -49,6 +49,25 @@ __device__ inline double make_c<double>(double re, double) { return re; }
 template <>
 __device__ inline cplx make_c<cplx>(double re, double im) { return mk(re, im); }
 
+// Sum of f(i) for i = i0, i0 + step, ... < cnt, U loads at a time: the loads of
+// a batch are all issued before the first is used, so a long sum costs
+// cnt / (U step) memory round trips instead of cnt / step.  Fixed order.
+template <int U, typename V, typename F>
+__device__ inline V batched_sum(int i0, int step, int cnt, F f) {
+    V acc = zero_<V>();
+    for (int b = i0; b < cnt; b += U * step) {
+        V v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = b + u * step;
+            v[u] = i < cnt ? f(i) : zero_<V>();
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc += v[u];
+    }
+    return acc;
+}
+
 // Start of a panel: column k is already up to date (the trailing update of the
 // previous panel has been applied), so x = A[k.., k] and the per-workgroup
 // partial |x_{k+2..}|^2 is all the next reflector needs.  One wavefront per
@@ -82,8 +101,7 @@ __global__ __launch_bounds__(64) void colstart_kernel(int n, int k, int nb, cons
 template <typename T>
 __device__ inline void reflector(const T* partA, int nA, int ld, T alpha, T& sc, T& tv, double& beta) {
     const int lane = threadIdx.x & 63;
-    double a = 0.0;
-    for (int b = lane; b < nA; b += 64) a += re_(partA[(long)b * ld]);
+    const double a = batched_sum<2, double>(lane, 64, nA, [&](int b) { return re_(partA[(long)b * ld]); });
     const double xn2 = wave_sum(a);
     const double ar = re_(alpha), ai = im_(alpha);
     if (xn2 == 0.0 && ai == 0.0) {
@@ -109,10 +127,8 @@ __device__ inline void panel_products(int k, int j, int nb, const T* x, const T*
     const int ld = 1 + 2 * nb;
     const int nv = 2 * j;
     if (lane < nv) {
-        int idx = lane < j ? 1 + lane : 1 + nb + (lane - j);
-        T a = zero_<T>();
-        for (int b = g; b < nA; b += NW) a += partA[(long)b * ld + idx];
-        part[g][lane] = a;
+        const int idx = lane < j ? 1 + lane : 1 + nb + (lane - j);
+        part[g][lane] = batched_sum<8, T>(g, NW, nA, [&](int b) { return partA[(long)b * ld + idx]; });
     }
     __syncthreads();
     if (t < nv) {
@@ -356,8 +372,7 @@ __global__ __launch_bounds__(256) void wcol_kernel(int n, int k, int j, int nb, 
     }
     if (pp == 1) {
         // z_{k+1} (row 0 of tile row 0) for the W entry on row k+1
-        T ys = zero_<T>();
-        for (int I2 = 1 + lr; I2 < nt; I2 += 64) ys += pcol[(long)I2 * ST];
+        T ys = batched_sum<2, T>(1 + lr, 64, nt, [&](int I2) { return pcol[(long)I2 * ST]; });
         ys = wave_sum(ys);
         if (lr == 0) ys1[0] = prow[0] + ys;
     }
@@ -370,22 +385,18 @@ __global__ __launch_bounds__(256) void wcol_kernel(int n, int k, int j, int nb, 
         vr[u] = ok ? VWt[(long)i * n + r] : zero_<T>();
         wr[u] = ok ? VWt[(long)(nb + i) * n + r] : zero_<T>();
     }
-    // z_r: row partials of tile row I, then column partials of the tiles below
-    T y0 = zero_<T>(), y1 = zero_<T>();
+    // z_r: row partials of tile row I (items 0 .. nc-1), then column partials
+    // of the tiles below (items nc ..), split over the four wavefronts
+    T zr = zero_<T>();
     if (in) {
-        int nc = I / sch + 1;
-        for (int c = pp; c < nc; c += 4) y0 += prow[((long)I * nch + c) * ST + lr];
-        const T* pc = pcol + (long)I * nt * ST + lr;
-        int I2 = I + 1 + pp;
-        for (; I2 + 4 < nt; I2 += 8) {
-            y0 += pc[(long)I2 * ST];
-            y1 += pc[(long)(I2 + 4) * ST];
-        }
-        if (I2 < nt) y0 += pc[(long)I2 * ST];
+        const int nc = I / sch + 1;
+        const T* pr = prow + (long)I * nch * ST + lr;
+        const T* pc = pcol + ((long)I * nt + I + 1 - nc) * ST + lr;
+        zr = batched_sum<8, T>(pp, 4, nc + nt - I - 1,
+                               [&](int f) { return f < nc ? pr[(long)f * ST] : pc[(long)f * ST]; });
     }
     // x^H A x from the product's partials (same order in every workgroup)
-    double va = 0.0;
-    for (int f = t; f < nt * nch; f += 256) va += pvav[f];
+    double va = batched_sum<8, double>(t, 256, nt * nch, [&](int f) { return pvav[f]; });
     const T alpha = pq[0];
     if (pp == 0) {
         T sc, tv;
@@ -430,7 +441,7 @@ __global__ __launch_bounds__(256) void wcol_kernel(int n, int k, int j, int nb, 
             cx += vr[u] * conj_(wk[i]) + wr[u] * conj_(vk[i]);
         }
     }
-    party[pp][lr] = sc * (y0 + y1) - cy;
+    party[pp][lr] = sc * zr - cy;
     partc[pp][lr] = cx;
     if (pp == 0) {
         // W on row k+1 (where v = 1)
