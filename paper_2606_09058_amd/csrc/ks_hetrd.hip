@@ -231,61 +231,84 @@ __global__ __launch_bounds__(Sy<T>::THREADS, 4) void symv_kernel(int n, int k, i
     T* pcol = hw.pcol + z * hw.spcol;
     const int ntile = min(J0 + SCH, I + 1) - J0;
     const int o = k + 1;  // first trailing row / column
-    const int col = t & 63, g = t >> 6;
+    // the row group is the wavefront index: uniform, so that the row addresses
+    // stay scalar and every load takes one 32-bit lane offset
+    const int col = t & 63, g = __builtin_amdgcn_readfirstlane(t >> 6);
     const int r0 = o + I * ST + g * SY_R;  // first row of this thread
-    S cur[SY_R], nxt[SY_R];  // the tile rows as stored (FP64, or FP32 in the mixed form)
-    {
-        const int gc = o + J0 * ST + col;
+    // Tiles s, s+1 and s+2 of the workgroup in a register ring of three slots
+    // (as stored: FP64, or FP32 in the mixed form): two tiles' loads stay in
+    // flight while one is used.  The tile loop is unrolled over SCH so that a
+    // tile's slot is fixed at compile time (moving a register whose load is in
+    // flight would wait for it), every load is unconditional (indices clamped
+    // into the matrix, the value replaced by zero outside it; a workgroup that
+    // reaches the diagonal re-reads its last tile in place of the tiles it does
+    // not have), so that each wait counts exactly the loads still needed, and
+    // x_I is read from LDS so that the ring fits the register budget.
+    S b[3][SY_R];
+    T xv[3];
+    auto xof = [&](int gi) -> T {
+        const T v = x[min(gi, n - 1)];
+        return gi < n ? v : zero_<T>();
+    };
+    auto load_tile = [&](int J, S(&bt)[SY_R]) {
+        const int gc = o + J * ST + col;
+        const unsigned off = (unsigned)min(gc, n - 1) * (unsigned)sizeof(S);
 #pragma unroll
-        for (int q = 0; q < SY_R; ++q)
-            cur[q] = (r0 + q < n && gc < n) ? A[(long)(r0 + q) * lda + gc] : zero_<S>();
+        for (int q = 0; q < SY_R; ++q) {
+            const char* row = (const char*)(A + (long)min(r0 + q, n - 1) * lda);
+            const S v = *(const S*)(row + off);
+            bt[q] = (r0 + q < n && gc < n) ? v : zero_<S>();
+        }
+    };
+    const int Jlast = J0 + ntile - 1;
+    // x_I is loaded first and stored to LDS after the tile loads are issued,
+    // so that the barrier waits for it alone
+    const T xI = xof(o + I * ST + (t & (ST - 1)));
+    load_tile(J0, b[0]);
+    xv[0] = xof(o + J0 * ST + col);
+    if constexpr (SCH > 1) {
+        load_tile(min(J0 + 1, Jlast), b[1]);
+        xv[1] = xof(o + (J0 + 1) * ST + col);
     }
-    auto xof = [&](int gi) -> T { return gi < n ? x[gi] : zero_<T>(); };
-    if (t < ST) vI[t] = xof(o + I * ST + t);
-    T vJc = xof(o + J0 * ST + col);
+    if (t < ST) vI[t] = xI;
     __syncthreads();
-    T vr[SY_R], racc[SY_R];
+    T racc[SY_R];
 #pragma unroll
-    for (int q = 0; q < SY_R; ++q) {
-        vr[q] = vI[g * SY_R + q];
-        racc[q] = zero_<T>();
-    }
+    for (int q = 0; q < SY_R; ++q) racc[q] = zero_<T>();
     double vav = 0.0;
-    for (int s = 0; s < ntile; ++s) {
+#pragma unroll
+    for (int s = 0; s < SCH; ++s) {
+        // x_I is re-read from LDS for every tile rather than kept in registers
+        asm volatile("" ::: "memory");
         const int J = J0 + s;
-        const bool more = s + 1 < ntile;
-        T vJn = zero_<T>();
-        if (more) {
-            const int gc = o + (J + 1) * ST + col;
-#pragma unroll
-            for (int q = 0; q < SY_R; ++q)
-                nxt[q] = (r0 + q < n && gc < n) ? A[(long)(r0 + q) * lda + gc] : zero_<S>();
-            vJn = xof(gc);
+        if (s + 2 < SCH) {  // constant once the loop is unrolled
+            load_tile(min(J + 2, Jlast), b[(s + 2) % 3]);
+            xv[(s + 2) % 3] = xof(o + (J + 2) * ST + col);
         }
-        T cs = zero_<T>();
-        if (J != I) {
+        if (s < ntile) {
+            const S(&bc)[SY_R] = b[s % 3];
+            const T xc = xv[s % 3];
+            T cs = zero_<T>();
+            if (J != I) {
 #pragma unroll
-            for (int q = 0; q < SY_R; ++q) {
-                const T a = widen(cur[q]);
-                racc[q] += a * vJc;
-                cs += conj_(a) * vr[q];
+                for (int q = 0; q < SY_R; ++q) {
+                    const T a = widen(bc[q]);
+                    racc[q] += a * xc;
+                    cs += conj_(a) * vI[g * SY_R + q];
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < SY_R; ++q) {
+                    const int rl = g * SY_R + q;
+                    const T a = widen(bc[q]);
+                    const T xq = vI[rl];
+                    if (col <= rl) racc[q] += a * xc;
+                    if (col < rl) cs += conj_(a) * xq;
+                    if (col == rl) vav += re_(a) * abs2_(xq);
+                }
             }
-        } else {
-#pragma unroll
-            for (int q = 0; q < SY_R; ++q) {
-                const int rl = g * SY_R + q;
-                const T a = widen(cur[q]);
-                if (col <= rl) racc[q] += a * vJc;
-                if (col < rl) cs += conj_(a) * vr[q];
-                if (col == rl) vav += re_(a) * abs2_(vr[q]);
-            }
-        }
-        vav += 2.0 * re_(conj_(vJc) * cs);
-        cred[s][g][col] = cs;
-        if (more) {
-#pragma unroll
-            for (int q = 0; q < SY_R; ++q) cur[q] = nxt[q];
-            vJc = vJn;
+            vav += 2.0 * re_(conj_(xc) * cs);
+            cred[s][g][col] = cs;
         }
     }
     const T rsum = rows_lane_sum<T>(racc, col);
