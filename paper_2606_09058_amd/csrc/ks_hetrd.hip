@@ -220,6 +220,14 @@ __global__ __launch_bounds__(Sy<T>::THREADS, 4) void symv_kernel(int n, int k, i
     const int c = blockIdx.x, I = blockIdx.y, z = blockIdx.z;
     const int J0 = c * SCH;
     const int t = threadIdx.x;
+    if (c == nch) {
+        // the extra workgroup column: workgroup (nch, 0) reduces the panel
+        // products from the start, alongside the tiles
+        if (I == 0)
+            panel_products<T, NG>(k, j, nb, hw.x + z * hw.sx,
+                                  hw.partPQ + ((k & 1) ? hw.sbuf : 0) + z * hw.spart, nA, hw.pq + z * hw.spq, part);
+        return;
+    }
     double* pvav = hw.pvav + z * hw.spvav;
     if (J0 > I) {
         if (t == 0) pvav[(long)I * nch + c] = 0.0;
@@ -329,21 +337,19 @@ __global__ __launch_bounds__(Sy<T>::THREADS, 4) void symv_kernel(int n, int k, i
         prow[((long)I * nch + c) * ST + t] = ysum;
     }
     if (t == 0) pvav[(long)I * nch + c] = vsum;
-    if (c == 0 && I == 0)
-        panel_products<T, NG>(k, j, nb, x, hw.partPQ + ((k & 1) ? hw.sbuf : 0) + z * hw.spart, nA,
-                              hw.pq + z * hw.spq, part);
 }
 
 // Column k of the panel (panel column j) after its symmetric product.  One
 // workgroup per 64 trailing rows r = k+1+64b+l, which is exactly tile row b of
-// the product, and four wavefronts that split every per-row sum four ways:
+// the product, and WC_NW wavefronts that split every gather so that each is a
+// single batch of loads:
 //   * the reflector (s, tau, beta) from alpha = x_{k+1} and the partial
-//     |x_{k+2..}|^2, by wavefront 0, while the others gather z_r;
+//     |x_{k+2..}|^2, with p = W^H v and q = V^H v from the raw panel products
+//     (row k+1, where v = 1, added here), by one wavefront;
 //   * A v = s z + c a_1 with c = 1 - s alpha (v = s x + c e_{k+1}) and
 //     v^H A v = |s|^2 x^H A x + 2 Re(conj(s) c x^H a_1) + |c|^2 a_11, where
 //     x^H a_1 = conj(z_{k+1}) since row k+1 of A is a_1^H;
-//   * p = W^H v and q = V^H v from the raw panel products (row k+1, where
-//     v = 1, added here), and alpha_w = -|tau|^2 (v^H A v - 2 Re q^H p) / 2, so
+//   * alpha_w = -|tau|^2 (v^H A v - 2 Re q^H p) / 2, so
 //     w = tau (A v - V p - W q) + alpha_w v is final at once (the usual
 //     w += alpha_w v with alpha_w = -tau w^H v / 2, since
 //     w^H v = conj(tau) v^H (A - V W^H - W V^H) v);
@@ -355,23 +361,30 @@ __global__ __launch_bounds__(Sy<T>::THREADS, 4) void symv_kernel(int n, int k, i
 //     (every workgroup reads all of column k's partials, so the two columns'
 //     partials cannot share one buffer).
 // Row k+1 of W (needed by every row for the update of column k+1) is
-// computed by every workgroup in the same order, so all of them agree.
+// computed by every thread in the same order, so all of them agree.
 // Workgroup 0 stores d[k], e[k] = beta and tau[k].
 // Partials per workgroup: [0] |x|^2, [1+i] (W^H x)_i, [1+nb+i] (V^H x)_i.
 constexpr int WC_ROWS = 64;
 static_assert(WC_ROWS == ST, "a row block of wcol is a tile row of the symmetric product");
-static_assert(2 * HETRD_NB <= 64 && HETRD_NB % 4 == 0, "panel width");
-constexpr int WC_MAXU = HETRD_NB / 4;  // panel columns per wavefront
+// wavefronts per workgroup: 16 for real data; 8 for complex, whose larger
+// per-thread state would not fit the register budget of 16
+template <typename T>
+struct Wc {
+    static constexpr int NW = is_cplx<T>::value ? 8 : 16;
+    static constexpr int MAXU = HETRD_NB / NW;  // panel columns per wavefront
+    static_assert(2 * HETRD_NB <= 64 && HETRD_NB % NW == 0 && NW % 4 == 0, "panel width");
+};
 template <typename T, typename S>
-__global__ __launch_bounds__(256) void wcol_kernel(int n, int k, int j, int nb, int next, const S* A, int lda,
-                                                   long sA, int nt, int nch, int sch, int nA, double* d,
-                                                   double* e, T* taua, HetrdWork<T> hw) {
-    __shared__ T sp[HETRD_NB], sq[HETRD_NB];          // p = W^H v, q = V^H v
-    __shared__ T vk[HETRD_NB + 1], wk[HETRD_NB + 1];  // V and W on row k+1
-    __shared__ T party[4][WC_ROWS], partc[4][WC_ROWS];
-    __shared__ T rowv[WC_ROWS], roww[WC_ROWS], rowx[WC_ROWS];
-    __shared__ T ys1[1], refl[2];
-    __shared__ double red[4];
+__global__ __launch_bounds__(64 * Wc<T>::NW) void wcol_kernel(int n, int k, int j, int nb, int next, const S* A,
+                                                          int lda, long sA, int nt, int nch, int sch, int nA,
+                                                          double* d, double* e, T* taua, HetrdWork<T> hw) {
+    constexpr int WC_NW = Wc<T>::NW, WC_MAXU = Wc<T>::MAXU;
+    __shared__ T sp[HETRD_NB], sq[HETRD_NB];  // p = W^H v, q = V^H v
+    __shared__ T vk[HETRD_NB], wk[HETRD_NB];  // V and W on row k+1
+    __shared__ T party[WC_NW][WC_ROWS], partc[WC_NW][WC_ROWS];
+    __shared__ T sh[5];  // s, tau, z_{k+1}, (V p + W q)_{k+1}, alpha
+    __shared__ double shd[2];  // a_11, Re q^H p
+    __shared__ double red[WC_NW];
     const int t = threadIdx.x, lr = t & 63, pp = t >> 6;
     const int I = blockIdx.x, z = blockIdx.z;
     A += z * sA;
@@ -387,78 +400,96 @@ __global__ __launch_bounds__(256) void wcol_kernel(int n, int k, int j, int nb, 
     T* partN = hw.partPQ + ((k & 1) ? 0 : hw.sbuf) + z * hw.spart;
     const int r = k + 1 + I * WC_ROWS + lr;
     const bool in = r < n;
-    // loads that depend on nothing computed here are issued first
+    // every thread: its row's x and a_1 entries (column k+1 before the panel's
+    // updates) and panel entries for columns i = pp, pp + WC_NW, ... < j
     T xr = zero_<T>(), ar = zero_<T>();
-    if (pp == 0 && in) {
+    if (in) {
         xr = x[r];
-        ar = widen(A[(long)r * lda + k + 1]);  // a_1, and column k+1 before the panel's updates
+        ar = widen(A[(long)r * lda + k + 1]);
     }
-    if (pp == 1) {
-        // z_{k+1} (row 0 of tile row 0) for the W entry on row k+1
-        T ys = batched_sum<2, T>(1 + lr, 64, nt, [&](int I2) { return pcol[(long)I2 * ST]; });
-        ys = wave_sum(ys);
-        if (lr == 0) ys1[0] = prow[0] + ys;
-    }
-    // this row's panel entries for columns i = pp, pp+4, ... < j
     T vr[WC_MAXU], wr[WC_MAXU];
 #pragma unroll
     for (int u = 0; u < WC_MAXU; ++u) {
-        int i = pp + 4 * u;
-        bool ok = in && i < j;
+        const int i = pp + WC_NW * u;
+        const bool ok = in && i < j;
         vr[u] = ok ? VWt[(long)i * n + r] : zero_<T>();
         wr[u] = ok ? VWt[(long)(nb + i) * n + r] : zero_<T>();
     }
+    if (pp == 1) {
+        // z_{k+1} (row 0 of tile row 0)
+        const T y0 = prow[0];
+        T ys = batched_sum<4, T>(1 + lr, 64, nt, [&](int I2) { return pcol[(long)I2 * ST]; });
+        ys = wave_sum(ys);
+        if (lr == 0) sh[2] = y0 + ys;
+    } else if (pp == 2) {
+        // the reflector and the panel products
+        // every load of this wavefront is issued before the reflector's reduction
+        const int lj = min(lr, nb - 1);
+        const T vkt = VWt[(long)lj * n + k + 1], wkt = VWt[(long)(nb + lj) * n + k + 1];
+        const T pw = pq[2 + lj], pv = pq[2 + nb + lj];
+        const T xk = x[k];
+        T sc, tv;
+        double beta;
+        const T alpha = pq[0];
+        reflector<T>(partA, nA, (int)ldp, alpha, sc, tv, beta);
+        T pl = zero_<T>(), ql = zero_<T>(), cs = zero_<T>();
+        double cr = 0.0;
+        if (lr < j) {
+            pl = conj_(wkt) + sc * pw;
+            ql = conj_(vkt) + sc * pv;
+            vk[lr] = vkt;
+            wk[lr] = wkt;
+            sp[lr] = pl;
+            sq[lr] = ql;
+            cs = vkt * pl + wkt * ql;
+            cr = re_(conj_(ql) * pl);
+        }
+        cs = wave_sum(cs);
+        cr = wave_sum(cr);
+        if (lr == 0) {
+            sh[0] = sc;
+            sh[1] = tv;
+            sh[3] = cs;
+            sh[4] = alpha;
+            shd[1] = cr;
+            if (I == 0) {
+                d[(long)z * n + k] = re_(xk);
+                e[(long)z * n + k] = beta;
+                taua[(long)z * n + k] = tv;
+            }
+        }
+    } else if (pp == 3 && lr == 0) {
+        shd[0] = re_(widen(A[(long)(k + 1) * lda + k + 1]));
+    }
     // z_r: row partials of tile row I (items 0 .. nc-1), then column partials
-    // of the tiles below (items nc ..), split over the four wavefronts
+    // of the tiles below (items nc ..), split over the wavefronts
     T zr = zero_<T>();
     if (in) {
         const int nc = I / sch + 1;
         const T* pr = prow + (long)I * nch * ST + lr;
         const T* pc = pcol + ((long)I * nt + I + 1 - nc) * ST + lr;
-        zr = batched_sum<8, T>(pp, 4, nc + nt - I - 1,
+        zr = batched_sum<8, T>(pp, WC_NW, nc + nt - I - 1,
                                [&](int f) { return f < nc ? pr[(long)f * ST] : pc[(long)f * ST]; });
     }
     // x^H A x from the product's partials (same order in every workgroup)
-    double va = batched_sum<8, double>(t, 256, nt * nch, [&](int f) { return pvav[f]; });
-    const T alpha = pq[0];
-    if (pp == 0) {
-        T sc, tv;
-        double beta;
-        reflector<T>(partA, nA, (int)ldp, alpha, sc, tv, beta);
-        if (lr == 0) {
-            refl[0] = sc;
-            refl[1] = tv;
-            if (I == 0) {
-                d[(long)z * n + k] = re_(x[k]);
-                e[(long)z * n + k] = beta;
-                taua[(long)z * n + k] = tv;
-            }
-        }
-        if (lr < j) {
-            const T vkt = VWt[(long)lr * n + k + 1], wkt = VWt[(long)(nb + lr) * n + k + 1];
-            vk[lr] = vkt;
-            wk[lr] = wkt;
-            sp[lr] = conj_(wkt) + sc * pq[2 + lr];
-            sq[lr] = conj_(vkt) + sc * pq[2 + nb + lr];
-        }
-    }
-    // one barrier for the sum; it also publishes refl, sp, sq, vk, wk, ys1
+    double va = batched_sum<4, double>(t, 64 * WC_NW, nt * nch, [&](int f) { return pvav[f]; });
     va = wave_sum(va);
     if (lr == 0) red[pp] = va;
-    __syncthreads();
-    const double xAx = (red[0] + red[1]) + (red[2] + red[3]);
-    const T z1 = ys1[0];  // z_{k+1} = a_1^H x
-    const T sc = refl[0], tv = refl[1];
+    __syncthreads();  // publishes sh, shd, sp, sq, vk, wk, red
+    double xAx = 0.0;
+#pragma unroll
+    for (int q = 0; q < WC_NW; q += 4) xAx += (red[q] + red[q + 1]) + (red[q + 2] + red[q + 3]);
+    const T sc = sh[0], tv = sh[1], z1 = sh[2], alpha = sh[4];
     const T c1 = from_re<T>(1.0) - sc * alpha;  // v_{k+1} = s alpha + c1 = 1
-    const double a11 = re_(widen(A[(long)(k + 1) * lda + k + 1]));
+    const double a11 = shd[0];
     const double vAv = abs2_(sc) * xAx + 2.0 * re_(conj_(sc) * c1 * conj_(z1)) + abs2_(c1) * a11;
-    double cr = 0.0;
-    for (int i = 0; i < j; ++i) cr += re_(conj_(sq[i]) * sp[i]);
-    const double alw = -0.5 * abs2_(tv) * (vAv - 2.0 * cr);
+    const double alw = -0.5 * abs2_(tv) * (vAv - 2.0 * shd[1]);
+    // W on row k+1 (where v = 1)
+    const T w1 = tv * (sc * z1 + c1 * from_re<T>(a11) - sh[3]) + from_re<T>(alw);
     T cy = zero_<T>(), cx = zero_<T>();
 #pragma unroll
     for (int u = 0; u < WC_MAXU; ++u) {
-        int i = pp + 4 * u;
+        const int i = pp + WC_NW * u;
         if (i < j) {
             cy += vr[u] * sp[i] + wr[u] * sq[i];
             cx += vr[u] * conj_(wk[i]) + wr[u] * conj_(vk[i]);
@@ -466,60 +497,54 @@ __global__ __launch_bounds__(256) void wcol_kernel(int n, int k, int j, int nb, 
     }
     party[pp][lr] = sc * zr - cy;
     partc[pp][lr] = cx;
-    if (pp == 0) {
-        // W on row k+1 (where v = 1)
-        T cs = lr < j ? vk[lr] * sp[lr] + wk[lr] * sq[lr] : zero_<T>();
-        cs = wave_sum(cs);
-        T w1 = tv * (sc * z1 + c1 * from_re<T>(a11) - cs) + from_re<T>(alw);
-        if (lr == 0) {
-            wk[j] = w1;
-            vk[j] = from_re<T>(1.0);
-        }
-    }
     __syncthreads();
-    if (pp == 0) {
-        T v = zero_<T>(), w = zero_<T>(), xn = zero_<T>();
-        if (in) {
-            T y = (party[0][lr] + party[1][lr]) + (party[2][lr] + party[3][lr]) + c1 * ar;
-            v = (r == k + 1) ? from_re<T>(1.0) : sc * xr;
-            w = (r == k + 1) ? wk[j] : tv * y + alw * v;
+    // every wavefront forms its lanes' rows (the same values in each)
+    T v = zero_<T>(), w = zero_<T>(), xn = zero_<T>();
+    if (in) {
+        T y = zero_<T>(), cc = zero_<T>();
+#pragma unroll
+        for (int q = 0; q < WC_NW; q += 4) {
+            y += (party[q][lr] + party[q + 1][lr]) + (party[q + 2][lr] + party[q + 3][lr]);
+            cc += (partc[q][lr] + partc[q + 1][lr]) + (partc[q + 2][lr] + partc[q + 3][lr]);
+        }
+        y += c1 * ar;
+        v = (r == k + 1) ? from_re<T>(1.0) : sc * xr;
+        w = (r == k + 1) ? w1 : tv * y + alw * v;
+        xn = ar - cc - (v * conj_(w1) + w);
+        if (r == k + 1) xn = from_re<T>(re_(xn));
+        if (pp == 0) {
             VWt[(long)j * n + r] = v;
             VWt[(long)(nb + j) * n + r] = w;
             WVc[(long)j * n + r] = conj_(w);
             WVc[(long)(nb + j) * n + r] = conj_(v);
-            if (next) {
-                T cc = (partc[0][lr] + partc[1][lr]) + (partc[2][lr] + partc[3][lr]);
-                xn = ar - cc - (v * conj_(wk[j]) + w);
-                if (r == k + 1) xn = from_re<T>(re_(xn));
-                x[r] = xn;
-            }
+            if (next) x[r] = xn;
         }
-        rowv[lr] = v;
-        roww[lr] = w;
-        rowx[lr] = (r >= k + 3) ? xn : zero_<T>();
     }
     if (!next) return;
-    __syncthreads();
-    // partials for the next reflector over the panel columns 0 .. j
-    const T xe = rowx[lr];
+    // partials for the next reflector over the panel columns 0 .. j: this
+    // wavefront's columns i = pp + WC_NW u, the W and V products of all of them
+    // reduced over the 64 rows at once (reduce-scatter; lane (64 / (2 WC_MAXU)) q
+    // ends with product q)
+    const T xe = (r >= k + 3) ? xn : zero_<T>();
     T* out = partN + (long)I * ldp;
-    if (pp == 0) {
-        double a = wave_sum(abs2_(xe));
+    if (pp == 1) {
+        const double a = wave_sum(abs2_(xe));
         if (lr == 0) out[0] = from_re<T>(a);
     }
+    T prod[2 * WC_MAXU];
 #pragma unroll
     for (int u = 0; u < WC_MAXU; ++u) {
-        int i = pp + 4 * u;  // wave-uniform; j < HETRD_NB, so i = j is reached
-        if (i <= j) {
-            T vi = (i == j) ? rowv[lr] : vr[u];
-            T wi = (i == j) ? roww[lr] : wr[u];
-            T pw = wave_sum(conj_(wi) * xe);
-            T pv = wave_sum(conj_(vi) * xe);
-            if (lr == 0) {
-                out[1 + i] = pw;
-                out[1 + nb + i] = pv;
-            }
-        }
+        const int i = pp + WC_NW * u;
+        const T vi = (i == j) ? v : vr[u];
+        const T wi = (i == j) ? w : wr[u];
+        prod[2 * u] = (i <= j) ? conj_(wi) * xe : zero_<T>();
+        prod[2 * u + 1] = (i <= j) ? conj_(vi) * xe : zero_<T>();
+    }
+    const T ps = rows_lane_sum<T>(prod, lr);
+    constexpr int LPQ = 64 / (2 * WC_MAXU);
+    if (lr % LPQ == 0) {
+        const int q = lr / LPQ, i = pp + WC_NW * (q >> 1);
+        if (i <= j) out[(q & 1) ? 1 + nb + i : 1 + i] = ps;
     }
 }
 
@@ -545,7 +570,8 @@ template <typename T, typename S>
 void symv_launch(hipStream_t s, int sch, int n, int k, int j, const S* A, int lda, long sA, int B, int nA,
                  const HetrdWork<T>& w) {
     const int m = n - k - 1, nt = cdiv(m, ST), nch = cdiv(nt, sch), nb = HETRD_NB;
-    const dim3 grid(nch, nt, B), block(Sy<T>::THREADS);
+    // one workgroup column beyond the tiles' for the panel products
+    const dim3 grid(nch + 1, nt, B), block(Sy<T>::THREADS);
     if (sch == 2)
         hipLaunchKernelGGL((symv_kernel<T, S, 2>), grid, block, 0, s, n, k, j, nb, A, lda, sA, nA, nt, nch, w);
     else if (sch == 8 && !is_cplx<T>::value)
@@ -587,7 +613,7 @@ void hetrd(hipStream_t s, int n, S* A, int lda, long sA, int batch, double* d, d
             symv_launch<T, S>(s, w.sch, n, k, j, A, lda, sA, B, nA, w);
             // algorithmic bytes of a Hermitian matrix-vector product: the lower triangle once
             if (smp) w.prof->end(PROF_HEMV, e0, (double)sizeof(T) * m * (m + 1) / 2.0 * B);
-            hipLaunchKernelGGL((wcol_kernel<T, S>), dim3(cdiv(m, WC_ROWS), 1, B), dim3(256), 0, s, n, k, j, nb,
+            hipLaunchKernelGGL((wcol_kernel<T, S>), dim3(cdiv(m, WC_ROWS), 1, B), dim3(64 * Wc<T>::NW), 0, s, n, k, j, nb,
                                (int)(j + 1 < jb), A, lda, sA, nt, nch, w.sch, nA, d, e, tau, w);
         }
         long tot = (long)n * jb;
