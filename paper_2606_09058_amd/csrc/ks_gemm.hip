@@ -16,6 +16,7 @@
 // D[4 (l/16) + r][l%16].  A complex product uses four real MFMAs
 // (re*re - im*im, re*im + im*re) into separate real and imaginary accumulators.
 #include <algorithm>
+#include <type_traits>
 
 #include "ks_common.hpp"
 
@@ -327,10 +328,203 @@ __global__ __launch_bounds__(256) void gemm_kernel(int m, int n, int K, double a
                            kscale ? kscale + b * sk : nullptr, uplo, m0, n0, klo);
 }
 
+// ---------------------------------------------------------------- large tiles
+// Large tiles only where they pay: enough k steps to amortise the tile's
+// prologue and epilogue, and enough tiles to keep two workgroups on every CU
+// (measured: rank-64 updates and 6656 x 1414 x 6656 FP64 products run faster
+// on 64 x 64 tiles).
+constexpr long BIG_MIN_TILES = 512;
+constexpr int BIG_MIN_K = 256;
+// Output tiles of BM x BN (128 x 128; 64 x 64 for FP64 complex) with one
+// wave tile of BM/2 x BN/2 per wavefront (2 x 2 wavefronts), so that each k
+// step feeds (BM/32)(BN/32) MFMA blocks per wavefront per operand fragment
+// pair: half the L2 traffic per flop of the 64 x 64 tile.  The LDS stages are
+// double-buffered (one barrier per k step) and each thread prefetches its
+// share of the next stage into registers while the current one is used.
+template <typename T>
+struct Big;
+// accumulator vector of one 16 x 16 MFMA block, and a complex value from its parts
+template <typename T>
+struct AccVec {
+    using type = d4;
+};
+template <>
+struct AccVec<float> {
+    using type = f4;
+};
+template <>
+struct AccVec<cplx32> {
+    using type = f4;
+};
+__device__ inline cplx from_parts(double re, double im, const cplx*) { return mk(re, im); }
+__device__ inline cplx32 from_parts(float re, float im, const cplx32*) { return mk32(re, im); }
+template <>
+struct Big<double> {
+    static constexpr int BM = 128, BN = 128, BK = 16;
+};
+template <>
+struct Big<float> {
+    static constexpr int BM = 128, BN = 128, BK = 32;
+};
+template <>
+struct Big<cplx> {
+    static constexpr int BM = 64, BN = 64, BK = 16;  // (two workgroups per CU fit in LDS)
+};
+template <>
+struct Big<cplx32> {
+    static constexpr int BM = 128, BN = 128, BK = 16;
+};
+
+// Load an R x C block of memory (row stride ld, C contiguous) starting at
+// (r0, c0), zero outside rows < nr and columns < nc; every thread takes one
+// contiguous run of R C / 256 elements.
+template <typename T, int R, int C, int OP>
+__device__ inline void big_load(T (&v)[R * C / 256], const T* P, int ld, int nr, int nc, int r0, int c0,
+                                int t) {
+    constexpr int E = R * C / 256, TPR = C / E;
+    static_assert(E * 256 == R * C && TPR * E == C && 256 / TPR == R, "block shape");
+    const int rr = r0 + t / TPR, cc = c0 + (t % TPR) * E;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        const bool ok = rr < nr && cc + i < nc;
+        v[i] = ok ? ld_op<T, OP>(P + (long)rr * ld + cc + i) : zero_<T>();
+    }
+}
+
+template <typename T, int OPA, int OPB>
+__global__ __launch_bounds__(256, 2) void gemm_big_kernel(int m, int n, int K, double alpha, const T* A, int lda,
+                                                       long sa, const T* B, int ldb, long sb, double beta, T* C,
+                                                       int ldc, long sc, int uplo, const int* kdev, int tri) {
+    constexpr int BM = Big<T>::BM, BN = Big<T>::BN, BKb = Big<T>::BK;
+    constexpr int WM = BM / 2, WN = BN / 2, MI = WM / 16, NI = WN / 16;
+    constexpr int EA = BM * BKb / 256, EB = BN * BKb / 256;
+    __shared__ T sA[2][BKb][BM + LPAD];
+    __shared__ T sB[2][BKb][BN + LPAD];
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    if (uplo == UPLO_LOWER && m0 + BM - 1 < n0) return;  // tile strictly above the diagonal
+    const long b = blockIdx.z;
+    A += b * sa;
+    B += b * sb;
+    C += b * sc;
+    if (kdev) K = min(K, *kdev);
+    int klo = 0;
+    if (tri == TRI_A_LOWER) K = min(K, m0 + BM);
+    if (tri == TRI_B_UPPER) K = min(K, n0 + BN);
+    if (tri == TRI_A_UPPER) klo = (m0 / BKb) * BKb;
+    if (tri == TRI_B_LOWER) klo = (n0 / BKb) * BKb;
+    const int t = threadIdx.x;
+    T ra[EA], rb[EB];
+    // op(A) tile BM x BK: A is m x K (OP_N) or K x m; op(B) tile BK x BN: B is K x n (OP_N) or n x K
+    auto load = [&](int k0) {
+        if constexpr (OPA == OP_N) big_load<T, BM, BKb, OPA>(ra, A, lda, m, K, m0, k0, t);
+        else big_load<T, BKb, BM, OPA>(ra, A, lda, K, m, k0, m0, t);
+        if constexpr (OPB == OP_N) big_load<T, BKb, BN, OPB>(rb, B, ldb, K, n, k0, n0, t);
+        else big_load<T, BN, BKb, OPB>(rb, B, ldb, n, K, n0, k0, t);
+    };
+    auto store = [&](int buf) {
+        if constexpr (OPA == OP_N) {
+            constexpr int TPR = BKb / EA;
+            const int mm = t / TPR, kk = (t % TPR) * EA;
+#pragma unroll
+            for (int i = 0; i < EA; ++i) sA[buf][kk + i][mm] = ra[i];
+        } else {
+            constexpr int TPR = BM / EA;
+            const int kk = t / TPR, mm = (t % TPR) * EA;
+#pragma unroll
+            for (int i = 0; i < EA; ++i) sA[buf][kk][mm + i] = ra[i];
+        }
+        if constexpr (OPB == OP_N) {
+            constexpr int TPR = BN / EB;
+            const int kk = t / TPR, nn = (t % TPR) * EB;
+#pragma unroll
+            for (int i = 0; i < EB; ++i) sB[buf][kk][nn + i] = rb[i];
+        } else {
+            constexpr int TPR = BKb / EB;
+            const int nn = t / TPR, kk = (t % TPR) * EB;
+#pragma unroll
+            for (int i = 0; i < EB; ++i) sB[buf][kk + i][nn] = rb[i];
+        }
+    };
+    const int lane = t & 63, w = t >> 6, wm = w >> 1, wn = w & 1;
+    const int li = lane & 15, lk = lane >> 4;
+    using V = typename AccVec<T>::type;
+    V cre[MI][NI], cim[is_cplx<T>::value ? MI : 1][is_cplx<T>::value ? NI : 1];
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NI; ++j) {
+            cre[i][j] = V{};
+            if constexpr (is_cplx<T>::value) cim[i][j] = V{};
+        }
+    if (K > klo) {
+        load(klo);
+        store(0);
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int k0 = klo; k0 < K; k0 += BKb) {
+        const bool more = k0 + BKb < K;
+        if (more) load(k0 + BKb);
+#pragma unroll
+        for (int ks = 0; ks < BKb / 4; ++ks) {
+            const int kr = ks * 4 + lk;
+            T a[MI], bb[NI];
+#pragma unroll
+            for (int i = 0; i < MI; ++i) a[i] = sA[cur][kr][wm * WM + 16 * i + li];
+#pragma unroll
+            for (int j = 0; j < NI; ++j) bb[j] = sB[cur][kr][wn * WN + 16 * j + li];
+#pragma unroll
+            for (int i = 0; i < MI; ++i)
+#pragma unroll
+                for (int j = 0; j < NI; ++j) {
+                    if constexpr (is_cplx<T>::value) {
+                        cre[i][j] = mfma(a[i].x, bb[j].x, cre[i][j]);
+                        cre[i][j] = mfma(-a[i].y, bb[j].y, cre[i][j]);
+                        cim[i][j] = mfma(a[i].x, bb[j].y, cim[i][j]);
+                        cim[i][j] = mfma(a[i].y, bb[j].x, cim[i][j]);
+                    } else {
+                        cre[i][j] = mfma(a[i], bb[j], cre[i][j]);
+                    }
+                }
+        }
+        if (more) store(cur ^ 1);
+        __syncthreads();
+        cur ^= 1;
+    }
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NI; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wm * WM + i * 16 + out_row<T>(lane, r);
+                const int col = n0 + wn * WN + j * 16 + li;
+                if (row < m && col < n && (uplo == UPLO_FULL || col <= row)) {
+                    T v;
+                    if constexpr (is_cplx<T>::value) v = from_parts(cre[i][j][r], cim[i][j][r], (const T*)nullptr);
+                    else v = cre[i][j][r];
+                    v = alpha * v;
+                    T* pc = C + (long)row * ldc + col;
+                    if (beta != 0.0) v += beta * (*pc);
+                    *pc = v;
+                }
+            }
+}
+
 template <typename T, int OPA, int OPB>
 static void launch(hipStream_t s, int m, int n, int k, double alpha, const T* A, int lda, long sa,
                    const T* B, int ldb, long sb, double beta, T* C, int ldc, long sc, int batch,
                    const double* kscale, long sk, Uplo uplo, const int* kdev, Tri tri) {
+    constexpr int BBM = Big<T>::BM, BBN = Big<T>::BN;
+    const long big_tiles = (long)cdiv(m, BBM) * cdiv(n, BBN) * batch / (uplo == UPLO_LOWER ? 2 : 1);
+    // FP32 gains from large tiles at one round of workgroups, FP64 from two
+    const long min_tiles = (sizeof(T) == 4 || std::is_same<T, cplx32>::value) ? BIG_MIN_TILES : 2 * BIG_MIN_TILES;
+    if (!kscale && k >= BIG_MIN_K && big_tiles >= min_tiles) {
+        dim3 grid(cdiv(n, BBN), cdiv(m, BBM), batch);
+        hipLaunchKernelGGL((gemm_big_kernel<T, OPA, OPB>), grid, dim3(256), 0, s, m, n, k, alpha, A, lda, sa, B,
+                           ldb, sb, beta, C, ldc, sc, (int)uplo, kdev, (int)tri);
+        return;
+    }
     dim3 grid(cdiv(n, BN), cdiv(m, BM), batch);
     hipLaunchKernelGGL((gemm_kernel<T, OPA, OPB>), grid, dim3(256), 0, s, m, n, k, alpha, A, lda, sa,
                        B, ldb, sb, beta, C, ldc, sc, kscale, sk, (int)uplo, kdev, (int)tri);

@@ -63,7 +63,10 @@ def test_mfma_f32_lane_layout(L):
     assert np.array_equal(o, expect), o
 
 
-GEMM_SHAPES = [(1, 1, 1), (64, 64, 16), (65, 130, 17), (200, 77, 300), (5, 300, 64), (130, 1, 2)]
+# the last shape has enough output tiles and k steps for the large-tile kernel
+# in every precision (ragged in m, n and k for every tile and k-step size)
+GEMM_SHAPES = [(1, 1, 1), (64, 64, 16), (65, 130, 17), (200, 77, 300), (5, 300, 64), (130, 1, 2),
+               (4100, 4099, 270)]
 
 
 @pytest.mark.parametrize("cplx", [False, True])
@@ -122,15 +125,16 @@ def test_gemm_fp32_matches_numpy(L, cplx, opa, opb):
         assert np.abs(got - ref).max() < 4e-7 * scale, (m, n, k)
 
 
-def test_gemm_lower_only(L):
+@pytest.mark.parametrize("m,k", [(150, 40), (5800, 260)])
+def test_gemm_lower_only(L, m, k):
+    """Only the lower triangle is written; the second shape takes the large-tile kernel."""
     rng = np.random.default_rng(5)
-    m = 150
-    A = rng.normal(size=(m, 40))
+    A = rng.normal(size=(m, k))
     C0 = rng.normal(size=(m, m))
     Cd = dev(C0)
     Ad = dev(A)
     announce("gemm lower")
-    assert L.ks_test_gemm(0, 0, 1, m, m, 40, 1.0, P(Ad), 40, P(Ad), 40, 1.0, P(Cd), m, 1,
+    assert L.ks_test_gemm(0, 0, 1, m, m, k, 1.0, P(Ad), k, P(Ad), k, 1.0, P(Cd), m, 1,
                           stream_handle()) == 0
     got = host(Cd)
     ref = C0 + A @ A.T
