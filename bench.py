@@ -197,7 +197,8 @@ def main():
         "wall_s_timed": wall,
         "phases_ms": phases,
         "tuning": {"tiles_per_workgroup": plan.tuning()["tiles_per_workgroup"],
-                   "candidates_ms": {str(k): v for k, v in plan.tuning()["candidates"].items()}},
+                   "candidates_ms": {str(k): v for k, v in plan.tuning()["candidates"].items()},
+                   "segments": plan.tuning()["segments"]},
         "roofline": {"bound": "hbm", "kernel": "symv_kernel (trailing Hermitian matrix-vector "
                                                "product of the tridiagonalisation)",
                      "achieved": hemv_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",

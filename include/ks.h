@@ -182,12 +182,22 @@ ks_status ks_plan_set_profiling(ks_plan* plan, int32_t enable, int32_t stride);
 ks_status ks_plan_get_profile(ks_plan* plan, ks_profile* out);
 
 /* The tile shape in use and, under KS_PLAN_AUTOTUNE, what was measured:
- * ms[i] is the time of the timing launches with cand[i] tiles per workgroup. */
+ * ms[i] is the time of the timing launches with cand[i] tiles per workgroup
+ * summed over the sampled columns, and tiles_per_workgroup the candidate with
+ * the least total.  The tridiagonalisation uses, for columns k from
+ * seg_first[i] up to seg_first[i+1] - 1 (the last segment up to the end), the
+ * candidate seg_tiles[i] that was fastest at the column sampled in that
+ * segment; without autotuning nseg = 1 and every column uses
+ * tiles_per_workgroup. */
+#define KS_TUNE_SEGMENTS 8
 typedef struct {
     int32_t tiles_per_workgroup;
     int32_t ncand;
     int32_t cand[4];
     double  ms[4];
+    int32_t nseg;
+    int32_t seg_first[KS_TUNE_SEGMENTS];
+    int32_t seg_tiles[KS_TUNE_SEGMENTS];
 } ks_tuning;
 ks_status ks_plan_get_tuning(ks_plan* plan, ks_tuning* out);
 

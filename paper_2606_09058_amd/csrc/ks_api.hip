@@ -559,25 +559,34 @@ ks_status ks_plan_create(const ks_plan_desc* d, ks_plan** out) {
         return KS_ERR_HIP;
     }
     p->tuning.tiles_per_workgroup = HETRD_SCH;
+    p->tuning.nseg = 1;
+    p->tuning.seg_first[0] = 0;
+    p->tuning.seg_tiles[0] = HETRD_SCH;
     if (d->flags & KS_PLAN_AUTOTUNE) {
         ks_tuning& tu = p->tuning;
         const long sA = (long)p->order * p->order;
         if (p->is_c)
             tu.ncand = hetrd_tune<cplx>(p->s, p->order, (cplx*)p->A, p->order, sA, d->batch, p->dv, p->ev,
-                                        (cplx*)p->tau, p->hc, tu.cand, tu.ms, 3);
+                                        (cplx*)p->tau, p->hc, tu.cand, tu.ms, 3, tu.seg_first, tu.seg_tiles);
         else
             tu.ncand = hetrd_tune<double>(p->s, p->order, (double*)p->A, p->order, sA, d->batch, p->dv, p->ev,
-                                          (double*)p->tau, p->hr, tu.cand, tu.ms, 3);
+                                          (double*)p->tau, p->hr, tu.cand, tu.ms, 3, tu.seg_first, tu.seg_tiles);
         int best = 0;
         for (int c = 1; c < tu.ncand; ++c)
             if (tu.ms[c] < tu.ms[best]) best = c;
         if (tu.ncand > 0) tu.tiles_per_workgroup = tu.cand[best];
+        tu.nseg = KS_TUNE_SEGMENTS;
         if (hipStreamSynchronize(p->s) != hipSuccess || tu.ncand == 0) {
             ks_plan_destroy(p);
             return KS_ERR_HIP;
         }
     }
     p->hr.sch = p->hc.sch = p->tuning.tiles_per_workgroup;
+    p->hr.nseg = p->hc.nseg = p->tuning.nseg;
+    for (int i = 0; i < p->tuning.nseg; ++i) {
+        p->hr.seg_first[i] = p->hc.seg_first[i] = p->tuning.seg_first[i];
+        p->hr.seg_sch[i] = p->hc.seg_sch[i] = p->tuning.seg_tiles[i];
+    }
     *out = p;
     return KS_OK;
 }

@@ -574,7 +574,7 @@ void symv_launch(hipStream_t s, int sch, int n, int k, int j, const S* A, int ld
     const dim3 grid(nch + 1, nt, B), block(Sy<T>::THREADS);
     if (sch == 2)
         hipLaunchKernelGGL((symv_kernel<T, S, 2>), grid, block, 0, s, n, k, j, nb, A, lda, sA, nA, nt, nch, w);
-    else if (sch == 8 && !is_cplx<T>::value)
+    else if (sch == 8)
         hipLaunchKernelGGL((symv_kernel<T, S, 8>), grid, block, 0, s, n, k, j, nb, A, lda, sA, nA, nt, nch, w);
     else
         hipLaunchKernelGGL((symv_kernel<T, S, 4>), grid, block, 0, s, n, k, j, nb, A, lda, sA, nA, nt, nch, w);
@@ -606,15 +606,16 @@ void hetrd(hipStream_t s, int n, S* A, int lda, long sA, int batch, double* d, d
         for (int j = 0; j < jb; ++j) {
             int k = k0 + j;
             int m = n - k - 1;
-            int nt = cdiv(m, ST), nch = cdiv(nt, w.sch);
+            const int sch = w.sch_for(k);
+            int nt = cdiv(m, ST), nch = cdiv(nt, sch);
             int nA = cdiv(n - k, WC_ROWS);  // workgroups that wrote the partials of column k
             bool smp = w.prof && w.prof->sample();
             hipEvent_t e0 = smp ? w.prof->begin() : nullptr;
-            symv_launch<T, S>(s, w.sch, n, k, j, A, lda, sA, B, nA, w);
+            symv_launch<T, S>(s, sch, n, k, j, A, lda, sA, B, nA, w);
             // algorithmic bytes of a Hermitian matrix-vector product: the lower triangle once
             if (smp) w.prof->end(PROF_HEMV, e0, (double)sizeof(T) * m * (m + 1) / 2.0 * B);
             hipLaunchKernelGGL((wcol_kernel<T, S>), dim3(cdiv(m, WC_ROWS), 1, B), dim3(64 * Wc<T>::NW), 0, s, n, k, j, nb,
-                               (int)(j + 1 < jb), A, lda, sA, nt, nch, w.sch, nA, d, e, tau, w);
+                               (int)(j + 1 < jb), A, lda, sA, nt, nch, sch, nA, d, e, tau, w);
         }
         long tot = (long)n * jb;
         hipLaunchKernelGGL((store_panel_kernel<T>), dim3(cdiv(tot, 256), 1, B), dim3(256), 0, s, n, k0, jb, w.VW,
@@ -642,13 +643,24 @@ void hetrd(hipStream_t s, int n, S* A, int lda, long sA, int batch, double* d, d
 }
 
 
+// Time the symmetric product with each candidate tile count at NK columns
+// spread evenly over the tridiagonalisation: ms[c] is candidate c's total
+// (which estimates the whole solve's product time), and segment q of the
+// columns (around sample q) takes the candidate fastest at that sample.
 template <typename T>
 int hetrd_tune(hipStream_t s, int n, T* A, int lda, long sA, int batch, double* d, double* e, T* tau,
-               HetrdWork<T>& w, int* cand, double* ms, int reps) {
+               HetrdWork<T>& w, int* cand, double* ms, int reps, int* seg_first, int* seg_tiles) {
     int nc = 0;
     cand[nc++] = 2;
     cand[nc++] = 4;
-    if (!is_cplx<T>::value) cand[nc++] = 8;
+    cand[nc++] = 8;
+    constexpr int NK = KS_TUNE_SEGMENTS;
+    int ks_[NK];
+    for (int q = 0; q < NK; ++q) {
+        ks_[q] = std::max(0, std::min((int)((long)q * (n - 1) / NK), n - 2));
+        seg_first[q] = q == 0 ? 0 : (ks_[q - 1] + ks_[q] + 1) / 2;
+        seg_tiles[q] = HETRD_SCH;
+    }
     if (n < 2) {
         for (int c = 0; c < nc; ++c) ms[c] = 0.0;
         return nc;
@@ -659,13 +671,11 @@ int hetrd_tune(hipStream_t s, int n, T* A, int lda, long sA, int batch, double* 
         (void)hipEventDestroy(e0);
         return 0;
     }
-    // columns spread evenly over the tridiagonalisation, so that the sum
-    // estimates the whole solve's symmetric-product time
-    constexpr int NK = 8;
+    float per[4][NK];
     for (int c = 0; c < nc; ++c) {
         float tot = 0.f;
         for (int q = 0; q < NK; ++q) {
-            const int k = std::min((int)((long)q * (n - 1) / NK), n - 2);
+            const int k = ks_[q];
             const int nA = cdiv(n - k, WC_ROWS);
             symv_launch<T, T>(s, cand[c], n, k, 0, A, lda, sA, batch, nA, w);  // warm
             (void)hipEventRecord(e0, s);
@@ -675,9 +685,16 @@ int hetrd_tune(hipStream_t s, int n, T* A, int lda, long sA, int batch, double* 
             (void)hipEventSynchronize(e1);
             float t = 0.f;
             (void)hipEventElapsedTime(&t, e0, e1);
+            per[c][q] = t;
             tot += t;
         }
         ms[c] = tot;
+    }
+    for (int q = 0; q < NK; ++q) {
+        int best = 0;
+        for (int c = 1; c < nc; ++c)
+            if (per[c][q] < per[best][q]) best = c;
+        seg_tiles[q] = cand[best];
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -693,9 +710,9 @@ template void hetrd<double, float>(hipStream_t, int, float*, int, long, int, dou
 template void hetrd<cplx, cplx32>(hipStream_t, int, cplx32*, int, long, int, double*, double*, cplx*, cplx*,
                                   HetrdWork<cplx>&);
 template int hetrd_tune<double>(hipStream_t, int, double*, int, long, int, double*, double*, double*,
-                                HetrdWork<double>&, int*, double*, int);
+                                HetrdWork<double>&, int*, double*, int, int*, int*);
 template int hetrd_tune<cplx>(hipStream_t, int, cplx*, int, long, int, double*, double*, cplx*,
-                              HetrdWork<cplx>&, int*, double*, int);
+                              HetrdWork<cplx>&, int*, double*, int, int*, int*);
 template void fill_zero<double>(hipStream_t, double*, long);
 template void fill_zero<cplx>(hipStream_t, cplx*, long);
 template void fill_zero<int>(hipStream_t, int*, long);

@@ -85,6 +85,16 @@ struct HetrdWork {
     long sVW = 0, sx = 0, spart = 0, sprow = 0, spcol = 0, spvav = 0, spq = 0;
     long sbuf = 0;  // offset of the odd-column partial buffer
     int sch = HETRD_SCH;  // tiles per workgroup of the symmetric product (tuned per plan)
+    // tuned per column segment: columns from seg_first[i] use seg_sch[i]
+    int nseg = 0;
+    int seg_first[KS_TUNE_SEGMENTS] = {};
+    int seg_sch[KS_TUNE_SEGMENTS] = {};
+    int sch_for(int k) const {
+        int v = sch;
+        for (int i = 0; i < nseg; ++i)
+            if (k >= seg_first[i]) v = seg_sch[i];
+        return v;
+    }
 };
 
 template <typename T>
@@ -168,7 +178,7 @@ void hetrd(hipStream_t s, int n, S* A, int lda, long sA, int batch, double* d, d
 // candidates to cand[] and times (ms) to ms[]; returns their number.
 template <typename T>
 int hetrd_tune(hipStream_t s, int n, T* A, int lda, long sA, int batch, double* d, double* e, T* tau,
-               HetrdWork<T>& w, int* cand, double* ms, int reps);
+               HetrdWork<T>& w, int* cand, double* ms, int reps, int* seg_first, int* seg_tiles);
 
 // Divide and conquer for a batch of tridiagonals of order tr.n (d, e, lam:
 // stride n; Z, Z2, U, Qp: stride n^2; the work arrays of w: stride n, with

@@ -59,7 +59,8 @@ class Profile(ctypes.Structure):
 class Tuning(ctypes.Structure):
     """ks_tuning: the symmetric product's tiles per workgroup and the timings behind it."""
     _fields_ = [("tiles_per_workgroup", ctypes.c_int32), ("ncand", ctypes.c_int32),
-                ("cand", ctypes.c_int32 * 4), ("ms", ctypes.c_double * 4)]
+                ("cand", ctypes.c_int32 * 4), ("ms", ctypes.c_double * 4), ("nseg", ctypes.c_int32),
+                ("seg_first", ctypes.c_int32 * 8), ("seg_tiles", ctypes.c_int32 * 8)]
 
 
 _lib = None
@@ -228,7 +229,8 @@ class Plan:
         tu = Tuning()
         _check(lib().ks_plan_get_tuning(self._h, ctypes.byref(tu)), "ks_plan_get_tuning")
         return {"tiles_per_workgroup": int(tu.tiles_per_workgroup),
-                "candidates": {int(tu.cand[i]): float(tu.ms[i]) for i in range(tu.ncand)}}
+                "candidates": {int(tu.cand[i]): float(tu.ms[i]) for i in range(tu.ncand)},
+                "segments": [(int(tu.seg_first[i]), int(tu.seg_tiles[i])) for i in range(tu.nseg)]}
 
     def graph_stats(self):
         """(captures, replays) of ks_gevd under KS_PLAN_GRAPH."""

@@ -181,9 +181,13 @@ def test_autotuned_plan_matches_oracle(cplx):
     plan = ks.Plan(p.n, complex=cplx, stream=torch.cuda.Stream(), flags=ks.KS_PLAN_AUTOTUNE)
     tu = plan.tuning()
     assert tu["tiles_per_workgroup"] in tu["candidates"]
-    assert sorted(tu["candidates"]) == ([2, 4] if cplx else [2, 4, 8])
+    assert sorted(tu["candidates"]) == [2, 4, 8]
     assert all(t > 0 for t in tu["candidates"].values())
     assert tu["candidates"][tu["tiles_per_workgroup"]] == min(tu["candidates"].values())
+    seg = tu["segments"]
+    assert len(seg) == 8 and seg[0][0] == 0
+    assert all(a[0] < b[0] for a, b in zip(seg, seg[1:])), seg
+    assert all(t in tu["candidates"] for _, t in seg), seg
     with torch.cuda.stream(plan.stream):
         H = dev(p.H)
         S = dev(p.S.astype(p.H.dtype))
