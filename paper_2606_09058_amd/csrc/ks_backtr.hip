@@ -24,67 +24,92 @@ __global__ void load_z_kernel(int n, int ncols, const double* Z, int c0, T* X, i
     X[(long)r * ldx + c] = from_re<T>(Z[(long)r * n + c0 + c]);
 }
 
-// T_b of every block at once (blockIdx.x = block, blockIdx.y = matrix): the back
-// substitution of apply_t_kernel applied to the identity, column c by thread c,
-// from G_b (ld BT) to T_b (jb x jb, ld jb).
+// The triangular factors of the two halves of every block at once
+// (blockIdx.x = 2 block + half, blockIdx.y = matrix): T_h solves
+// (diag(1/tau) + striu(G_hh)) T_h = I for the half's reflectors, by back
+// substitution on the identity, column c by thread c.  G_b (= V_b^H V_b) and
+// T_b share storage (leading dimension BT): each half reads its diagonal
+// block of G into LDS before writing T_h over it, and the second half also
+// zeroes the block below the first (T_b is upper triangular); the block above
+// the second half still holds V_1^H V_2 for the coupling term.
+constexpr int TF_HALF = BACKTR_BT / 2;
 template <typename T>
-__global__ __launch_bounds__(64) void t_factors_kernel(int n, const T* tau, const T* Gall, long sG, T* Tall,
-                                                       long sT) {
-    constexpr int B = BACKTR_BT;
-    const int b = blockIdx.x, z = blockIdx.y;
-    const int b0 = b * B, jb = min(B, n - 1 - b0);
-    const T* G = Gall + z * sG + (long)b * B * B;  // may alias Tb (read fully first)
+__global__ __launch_bounds__(TF_HALF) void t_factors_kernel(int n, const T* tau, T* Tall, long sT) {
+    constexpr int B = BACKTR_BT, H = TF_HALF;
+    const int b = blockIdx.x >> 1, h = blockIdx.x & 1, z = blockIdx.y;
+    const int b0 = b * B, jb = min(B, n - 1 - b0), o = h * H, jh = min(H, jb - o);
+    if (jh <= 0) return;
     T* Tb = Tall + z * sT + (long)b * B * B;
-    tau += (long)z * n + b0;
-    __shared__ T sg[B][B + 1];
-    __shared__ T st[B];
-    for (int e = threadIdx.x; e < jb * jb; e += blockDim.x) sg[e / jb][e % jb] = G[(long)(e / jb) * B + e % jb];
-    if (threadIdx.x < jb) st[threadIdx.x] = tau[threadIdx.x];
-    __syncthreads();  // all of G_b is in LDS before T_b overwrites it
+    T* Th = Tb + (long)o * B + o;
+    tau += (long)z * n + b0 + o;
+    __shared__ T sg[H][H + 1];
+    __shared__ T st[H];
+    for (int e = threadIdx.x; e < jh * jh; e += blockDim.x) sg[e / jh][e % jh] = Th[(long)(e / jh) * B + e % jh];
+    if (threadIdx.x < jh) st[threadIdx.x] = tau[threadIdx.x];
+    __syncthreads();  // the half's block of G is in LDS before T_h overwrites it
     const int c = threadIdx.x;
-    if (c >= jb) return;
-    T w[B];
+    if (h == 1)
+        for (int i = 0; i < jh; ++i) Tb[(long)(o + i) * B + c] = zero_<T>();  // below the first half
+    if (c >= jh) return;
+    T w[H];
 #pragma unroll
-    for (int i = B - 1; i >= 0; --i) {
-        if (i < jb) {
+    for (int i = H - 1; i >= 0; --i) {
+        if (i < jh) {
             T acc = (i == c) ? from_re<T>(1.0) : zero_<T>();
 #pragma unroll
-            for (int l = i + 1; l < B; ++l)
-                if (l < jb) acc -= sg[i][l] * w[l];
+            for (int l = i + 1; l < H; ++l)
+                if (l < jh) acc -= sg[i][l] * w[l];
             w[i] = st[i] * acc;
-            Tb[(long)i * jb + c] = w[i];
+            Th[(long)i * B + c] = w[i];
         }
     }
 }
 
-// The compact-WY factors T_b (jb x jb, row-major, at Tall + b BT^2 per matrix)
-// of every block of BT reflectors.  The reflector matrix is zero above each
-// block, so G_b = V_b^H V_b can run over all n rows: one split-K GEMM batched
-// over the full blocks (a ragged last block takes its own), then one launch
-// forms every T_b.
+// The compact-WY factors T_b (jb x jb, row-major with leading dimension BT, at
+// Tall + b BT^2 per matrix) of every block of BT reflectors.  The reflector
+// matrix is zero above each block, so G_b = V_b^H V_b can run over all n rows:
+// one split-K GEMM batched over the full blocks (a ragged last block takes its
+// own).  One launch forms the triangular factors of both halves of every
+// block; the coupling T_12 = -T_1 (V_1^H V_2) T_2 of the two halves (the
+// product of the two halves' compact-WY forms) takes two batched GEMMs.
 template <typename T>
 void backtransform_prepare(hipStream_t s, int n, int batch, const T* Vall, const T* tau, BacktrWork<T>& w) {
-    const int bt = BACKTR_BT;
+    const int bt = BACKTR_BT, hb = TF_HALF;
     const int nref = n - 1;
     if (nref <= 0) return;
     const int nblk = cdiv(nref, bt), nfull = nref / bt;
-    const long sV = (long)n * n;
+    const long sV = (long)n * n, bb = (long)bt * bt;
     for (int z = 0; z < batch; ++z) {
         const T* V = Vall + z * sV;
-        // G_b is staged where T_b goes: each block of the next kernel reads its
-        // G_b into LDS before it writes T_b over it
+        // G_b is staged where T_b goes
         T* Gz = w.Tall + z * w.sTall;
         if (nfull > 0)
-            gemm_splitk<T>(s, OP_C, OP_N, bt, bt, n, 1.0, V, n, V, n, 0.0, Gz, bt, w.P, w.pelems, nfull, bt, bt,
-                           (long)bt * bt);
+            gemm_splitk<T>(s, OP_C, OP_N, bt, bt, n, 1.0, V, n, V, n, 0.0, Gz, bt, w.P, w.pelems, nfull, bt, bt, bb);
         if (nblk > nfull) {
             const int b0 = nfull * bt, jb = nref - b0;
-            gemm_splitk<T>(s, OP_C, OP_N, jb, jb, n, 1.0, V + b0, n, V + b0, n, 0.0, Gz + (long)nfull * bt * bt, bt,
+            gemm_splitk<T>(s, OP_C, OP_N, jb, jb, n, 1.0, V + b0, n, V + b0, n, 0.0, Gz + (long)nfull * bb, bt,
                            w.P, w.pelems);
         }
     }
-    hipLaunchKernelGGL((t_factors_kernel<T>), dim3(nblk, batch), dim3(64), 0, s, n, tau, w.Tall, w.sTall, w.Tall,
-                       w.sTall);
+    hipLaunchKernelGGL((t_factors_kernel<T>), dim3(2 * nblk, batch), dim3(TF_HALF), 0, s, n, tau, w.Tall, w.sTall);
+    // coupling of the halves: Y = G_12 T_2 (in W1), then T_12 = -T_1 Y over G_12
+    const long sy = (long)hb * hb;
+    for (int z = 0; z < batch; ++z) {
+        T* Tz = w.Tall + z * w.sTall;
+        if (nfull > 0) {
+            gemm<T>(s, OP_N, OP_N, hb, hb, hb, 1.0, Tz + hb, bt, bb, Tz + (long)hb * bt + hb, bt, bb, 0.0, w.W1, hb,
+                    sy, nfull);
+            gemm<T>(s, OP_N, OP_N, hb, hb, hb, -1.0, Tz, bt, bb, w.W1, hb, sy, 0.0, Tz + hb, bt, bb, nfull);
+        }
+        const int jb = nref - nfull * bt;
+        if (nblk > nfull && jb > hb) {
+            T* Tl = Tz + (long)nfull * bb;
+            const int j2 = jb - hb;
+            gemm<T>(s, OP_N, OP_N, hb, j2, j2, 1.0, Tl + hb, bt, 0, Tl + (long)hb * bt + hb, bt, 0, 0.0, w.W1, j2, 0,
+                    1);
+            gemm<T>(s, OP_N, OP_N, hb, j2, hb, -1.0, Tl, bt, 0, w.W1, j2, 0, 0.0, Tl + hb, bt, 0, 1);
+        }
+    }
 }
 
 template <typename T>
@@ -107,7 +132,7 @@ void backtransform_q(hipStream_t s, int n, int batch, const T* Vall, int ncols, 
         T* Xb = X + (long)(b0 + 1) * ldx;
         gemm_splitk<T>(s, OP_C, OP_N, jb, ncols, m, 1.0, Vb, n, Xb, ldx, 0.0, w.W1, ncols, w.P, w.pelems, B, sV,
                        sX, (long)jb * ncols);
-        gemm<T>(s, adjoint ? OP_C : OP_N, OP_N, jb, ncols, jb, 1.0, Tb, jb, w.sTall, w.W1, ncols, (long)jb * ncols,
+        gemm<T>(s, adjoint ? OP_C : OP_N, OP_N, jb, ncols, jb, 1.0, Tb, bt, w.sTall, w.W1, ncols, (long)jb * ncols,
                 0.0, w.W2, ncols, (long)jb * ncols, B);
         gemm<T>(s, OP_N, OP_N, m, ncols, jb, -1.0, Vb, n, sV, w.W2, ncols, (long)jb * ncols, 1.0, Xb, ldx, sX, B);
     }

@@ -16,7 +16,7 @@ constexpr int HETRD_NB = 32;   // panel width of the tridiagonalisation
 constexpr int HETRD_TILE = 64; // tile edge of the trailing symmetric product
 constexpr int HETRD_SCH = 4;      // default tiles per workgroup of the trailing symmetric product
 constexpr int HETRD_SCH_MIN = 2;  // smallest candidate (sizes the partial buffers)
-constexpr int BACKTR_BT = 64;  // reflectors per compact-WY block of the back-transform
+constexpr int BACKTR_BT = 128;  // reflectors per compact-WY block of the back-transform
 constexpr int DC_LEAF = 32;    // largest divide-and-conquer leaf
 constexpr int MAX_KW = 64;     // k-point weights passed by value
 
