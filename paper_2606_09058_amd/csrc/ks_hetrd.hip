@@ -185,6 +185,35 @@ __device__ inline T rows_lane_sum(const T (&r)[8], int lane) {
     return z;
 }
 
+template <typename T>
+__device__ inline T rows_lane_sum(const T (&r)[16], int lane) {
+    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
+    T w[8], u[4], v[2];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        T send = b5 ? r[i] : r[i + 8];
+        T keep = b5 ? r[i + 8] : r[i];
+        w[i] = keep + shfl_xor_(send, 32);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        T send = b4 ? w[i] : w[i + 4];
+        T keep = b4 ? w[i + 4] : w[i];
+        u[i] = keep + shfl_xor_(send, 16);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        T send = b3 ? u[i] : u[i + 2];
+        T keep = b3 ? u[i + 2] : u[i];
+        v[i] = keep + shfl_xor_(send, 8);
+    }
+    T send = b2 ? v[0] : v[1];
+    T z = (b2 ? v[1] : v[0]) + shfl_xor_(send, 4);
+    z += shfl_xor_(z, 2);
+    z += shfl_xor_(z, 1);
+    return z;
+}
+
 // Trailing Hermitian matrix-vector product z = A_trail x from the LOWER
 // triangle only, x the raw column k below its diagonal.  The trailing matrix
 // (rows/cols k+1 .. n-1) is cut into 64 x 64 tiles; workgroup (c, I) takes
@@ -202,17 +231,21 @@ __device__ inline T rows_lane_sum(const T (&r)[8], int lane) {
 // pvav, from which the next kernel gets v^H A v and so the W-column
 // correction without a pass over w.
 constexpr int ST = HETRD_TILE;  // tile edge
-template <typename T>
+template <typename T, typename S>
 struct Sy {
     static constexpr int R = sizeof(T) == 8 ? 8 : 4;  // tile rows per thread
     static constexpr int NG = ST / R;                  // row groups = wavefronts
     static constexpr int THREADS = 64 * NG;            // 512 or 1024
+    // slots of the register ring of tiles: three (two tiles in flight) for an
+    // FP64 trailing matrix, five (four in flight: the same bytes and
+    // registers) when it is stored in FP32
+    static constexpr int NSLOT = sizeof(S) < sizeof(T) ? 5 : 3;
 };
 
 template <typename T, typename S, int SCH>
-__global__ __launch_bounds__(Sy<T>::THREADS, 4) void symv_kernel(int n, int k, int j, int nb, const S* A, int lda,
+__global__ __launch_bounds__((Sy<T, S>::THREADS), 4) void symv_kernel(int n, int k, int j, int nb, const S* A, int lda,
                                                           long sA, int nA, int nt, int nch, HetrdWork<T> hw) {
-    constexpr int SY_R = Sy<T>::R, NG = Sy<T>::NG;
+    constexpr int SY_R = Sy<T, S>::R, NG = Sy<T, S>::NG;
     __shared__ T vI[ST], yrow[ST];
     __shared__ T cred[SCH][NG][ST];
     __shared__ T part[NG][64];
@@ -243,17 +276,18 @@ __global__ __launch_bounds__(Sy<T>::THREADS, 4) void symv_kernel(int n, int k, i
     // stay scalar and every load takes one 32-bit lane offset
     const int col = t & 63, g = __builtin_amdgcn_readfirstlane(t >> 6);
     const int r0 = o + I * ST + g * SY_R;  // first row of this thread
-    // Tiles s, s+1 and s+2 of the workgroup in a register ring of three slots
-    // (as stored: FP64, or FP32 in the mixed form): two tiles' loads stay in
-    // flight while one is used.  The tile loop is unrolled over SCH so that a
+    // The workgroup's tiles pass through a register ring of NSLOT slots (as
+    // stored: FP64, or FP32 in the mixed form): NSLOT - 1 tiles' loads stay
+    // in flight while one is used.  The tile loop is unrolled over SCH so that a
     // tile's slot is fixed at compile time (moving a register whose load is in
     // flight would wait for it), every load is unconditional (indices clamped
     // into the matrix, the value replaced by zero outside it; a workgroup that
     // reaches the diagonal re-reads its last tile in place of the tiles it does
     // not have), so that each wait counts exactly the loads still needed, and
     // x_I is read from LDS so that the ring fits the register budget.
-    S b[3][SY_R];
-    T xv[3];
+    constexpr int NSLOT = Sy<T, S>::NSLOT, PD = NSLOT - 1;
+    S b[NSLOT][SY_R];
+    T xv[NSLOT];
     auto xof = [&](int gi) -> T {
         const T v = x[min(gi, n - 1)];
         return gi < n ? v : zero_<T>();
@@ -272,11 +306,12 @@ __global__ __launch_bounds__(Sy<T>::THREADS, 4) void symv_kernel(int n, int k, i
     // x_I is loaded first and stored to LDS after the tile loads are issued,
     // so that the barrier waits for it alone
     const T xI = xof(o + I * ST + (t & (ST - 1)));
-    load_tile(J0, b[0]);
-    xv[0] = xof(o + J0 * ST + col);
-    if constexpr (SCH > 1) {
-        load_tile(min(J0 + 1, Jlast), b[1]);
-        xv[1] = xof(o + (J0 + 1) * ST + col);
+#pragma unroll
+    for (int p = 0; p < PD; ++p) {
+        if (p < SCH) {
+            load_tile(min(J0 + p, Jlast), b[p]);
+            xv[p] = xof(o + (J0 + p) * ST + col);
+        }
     }
     if (t < ST) vI[t] = xI;
     __syncthreads();
@@ -289,13 +324,13 @@ __global__ __launch_bounds__(Sy<T>::THREADS, 4) void symv_kernel(int n, int k, i
         // x_I is re-read from LDS for every tile rather than kept in registers
         asm volatile("" ::: "memory");
         const int J = J0 + s;
-        if (s + 2 < SCH) {  // constant once the loop is unrolled
-            load_tile(min(J + 2, Jlast), b[(s + 2) % 3]);
-            xv[(s + 2) % 3] = xof(o + (J + 2) * ST + col);
+        if (s + PD < SCH) {  // constant once the loop is unrolled
+            load_tile(min(J + PD, Jlast), b[(s + PD) % NSLOT]);
+            xv[(s + PD) % NSLOT] = xof(o + (J + PD) * ST + col);
         }
         if (s < ntile) {
-            const S(&bc)[SY_R] = b[s % 3];
-            const T xc = xv[s % 3];
+            const S(&bc)[SY_R] = b[s % NSLOT];
+            const T xc = xv[s % NSLOT];
             T cs = zero_<T>();
             if (J != I) {
 #pragma unroll
@@ -571,7 +606,7 @@ void symv_launch(hipStream_t s, int sch, int n, int k, int j, const S* A, int ld
                  const HetrdWork<T>& w) {
     const int m = n - k - 1, nt = cdiv(m, ST), nch = cdiv(nt, sch), nb = HETRD_NB;
     // one workgroup column beyond the tiles' for the panel products
-    const dim3 grid(nch + 1, nt, B), block(Sy<T>::THREADS);
+    const dim3 grid(nch + 1, nt, B), block(Sy<T, S>::THREADS);
     if (sch == 2)
         hipLaunchKernelGGL((symv_kernel<T, S, 2>), grid, block, 0, s, n, k, j, nb, A, lda, sA, nA, nt, nch, w);
     else if (sch == 8)
