@@ -358,18 +358,22 @@ __global__ __launch_bounds__((Sy<T, S>::THREADS), 4) void symv_kernel(int n, int
     constexpr int LPR = 64 / SY_R;  // lanes per row after the reduction
     if (col % LPR == 0) yrow[g * SY_R + col / LPR] = rsum;
     const double vsum = block_sum(vav, redd);  // its barriers also publish yrow and cred
-    if (t < ST) {
-        T ysum = yrow[t];
-        for (int s = 0; s < ntile; ++s) {
-            T cs = zero_<T>();
+    // wavefront g reduces the column sums of tile g (SCH <= NG); the last tile
+    // is the diagonal one when the workgroup reaches it, whose column sums
+    // belong to z_I as well, and its wavefront also stores the row sums
+    static_assert(SCH <= NG, "one wavefront per tile");
+    if (g < ntile) {
+        const int s = g, J = J0 + s;
+        T cs = zero_<T>();
 #pragma unroll
-            for (int q = 0; q < NG; q += 4)
-                cs += (cred[s][q][t] + cred[s][q + 1][t]) + (cred[s][q + 2][t] + cred[s][q + 3][t]);
-            const int J = J0 + s;
-            if (J == I) ysum += cs;  // A_II^H x_I belongs to z_I as well
-            else pcol[((long)J * nt + I) * ST + t] = cs;
+        for (int q = 0; q < NG; q += 4)
+            cs += (cred[s][q][col] + cred[s][q + 1][col]) + (cred[s][q + 2][col] + cred[s][q + 3][col]);
+        if (J == I) {
+            prow[((long)I * nch + c) * ST + col] = yrow[col] + cs;
+        } else {
+            pcol[((long)J * nt + I) * ST + col] = cs;
+            if (s == ntile - 1) prow[((long)I * nch + c) * ST + col] = yrow[col];
         }
-        prow[((long)I * nch + c) * ST + t] = ysum;
     }
     if (t == 0) pvav[(long)I * nch + c] = vsum;
 }
