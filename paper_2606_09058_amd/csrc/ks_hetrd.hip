@@ -357,7 +357,9 @@ __global__ __launch_bounds__((Sy<T, S>::THREADS), 4) void symv_kernel(int n, int
     const T rsum = rows_lane_sum<T>(racc, col);
     constexpr int LPR = 64 / SY_R;  // lanes per row after the reduction
     if (col % LPR == 0) yrow[g * SY_R + col / LPR] = rsum;
-    const double vsum = block_sum(vav, redd);  // its barriers also publish yrow and cred
+    vav = wave_sum(vav);
+    if (col == 0) redd[g] = vav;
+    __syncthreads();  // publishes yrow, cred and the x^H A x partials
     // wavefront g reduces the column sums of tile g (SCH <= NG); the last tile
     // is the diagonal one when the workgroup reaches it, whose column sums
     // belong to z_I as well, and its wavefront also stores the row sums
@@ -375,7 +377,11 @@ __global__ __launch_bounds__((Sy<T, S>::THREADS), 4) void symv_kernel(int n, int
             if (s == ntile - 1) prow[((long)I * nch + c) * ST + col] = yrow[col];
         }
     }
-    if (t == 0) pvav[(long)I * nch + c] = vsum;
+    if (t == 0) {
+        double vsum = 0.0;
+        for (int q = 0; q < NG; ++q) vsum += redd[q];
+        pvav[(long)I * nch + c] = vsum;
+    }
 }
 
 // Column k of the panel (panel column j) after its symmetric product.  One
