@@ -248,6 +248,7 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
         w.G = (T*)(b + oG);
         w.Tall = (T*)(b + oT);
         w.sTall = (long)(nblk_bt * bt * bt);
+        w.bt = backtr_block((int)order);
         w.W1 = (T*)(b + oW1);
         w.W2 = (T*)(b + oW2);
         w.P = (T*)(b + oSK);
@@ -322,6 +323,7 @@ BacktrWork<typename Lo<T>::type> lo_view(const BacktrWork<T>& w) {
     v.G = (L*)w.G;
     v.Tall = nullptr;  // the FP32 factors have a buffer of their own
     v.sTall = w.sTall;
+    v.bt = w.bt;
     v.W1 = (L*)w.W1;
     v.W2 = (L*)w.W2;
     v.P = (L*)w.P;

@@ -24,20 +24,22 @@ __global__ void load_z_kernel(int n, int ncols, const double* Z, int c0, T* X, i
     X[(long)r * ldx + c] = from_re<T>(Z[(long)r * n + c0 + c]);
 }
 
-// The triangular factors of the two halves of every block at once
-// (blockIdx.x = 2 block + half, blockIdx.y = matrix): T_h solves
-// (diag(1/tau) + striu(G_hh)) T_h = I for the half's reflectors, by back
+// The triangular factors of the BACKTR_SUB-reflector sub-blocks ("quarters"
+// of a 256-reflector block) of every block at once (blockIdx.x = block x
+// sub-blocks per block + sub-block, blockIdx.y = matrix): T_q solves
+// (diag(1/tau) + striu(G_qq)) T_q = I for the quarter's reflectors, by back
 // substitution on the identity, column c by thread c.  G_b (= V_b^H V_b) and
-// T_b share storage (leading dimension BT): each half reads its diagonal
-// block of G into LDS before writing T_h over it, and the second half also
-// zeroes the block below the first (T_b is upper triangular); the block above
-// the second half still holds V_1^H V_2 for the coupling term.
-constexpr int TF_HALF = BACKTR_BT / 2;
+// T_b share storage (leading dimension BT): each quarter reads its diagonal
+// block of G into LDS before writing T_q over it, and zeroes the blocks to its
+// left (T_b is upper triangular); the blocks above the diagonal still hold
+// V_p^H V_q for the coupling terms.
+constexpr int TF_Q = BACKTR_SUB;
 template <typename T>
-__global__ __launch_bounds__(TF_HALF) void t_factors_kernel(int n, const T* tau, T* Tall, long sT) {
-    constexpr int B = BACKTR_BT, H = TF_HALF;
-    const int b = blockIdx.x >> 1, h = blockIdx.x & 1, z = blockIdx.y;
-    const int b0 = b * B, jb = min(B, n - 1 - b0), o = h * H, jh = min(H, jb - o);
+__global__ __launch_bounds__(TF_Q) void t_factors_kernel(int n, int B, const T* tau, T* Tall, long sT) {
+    constexpr int H = TF_Q;
+    const int nq = B / H;
+    const int b = blockIdx.x / nq, qd = blockIdx.x % nq, z = blockIdx.y;
+    const int b0 = b * B, jb = min(B, n - 1 - b0), o = qd * H, jh = min(H, jb - o);
     if (jh <= 0) return;
     T* Tb = Tall + z * sT + (long)b * B * B;
     T* Th = Tb + (long)o * B + o;
@@ -46,10 +48,10 @@ __global__ __launch_bounds__(TF_HALF) void t_factors_kernel(int n, const T* tau,
     __shared__ T st[H];
     for (int e = threadIdx.x; e < jh * jh; e += blockDim.x) sg[e / jh][e % jh] = Th[(long)(e / jh) * B + e % jh];
     if (threadIdx.x < jh) st[threadIdx.x] = tau[threadIdx.x];
-    __syncthreads();  // the half's block of G is in LDS before T_h overwrites it
+    __syncthreads();  // the quarter's block of G is in LDS before T_q overwrites it
     const int c = threadIdx.x;
-    if (h == 1)
-        for (int i = 0; i < jh; ++i) Tb[(long)(o + i) * B + c] = zero_<T>();  // below the first half
+    for (int i = 0; i < jh; ++i)
+        for (int cc = c; cc < o; cc += H) Tb[(long)(o + i) * B + cc] = zero_<T>();  // left of the quarter
     if (c >= jh) return;
     T w[H];
 #pragma unroll
@@ -69,12 +71,13 @@ __global__ __launch_bounds__(TF_HALF) void t_factors_kernel(int n, const T* tau,
 // Tall + b BT^2 per matrix) of every block of BT reflectors.  The reflector
 // matrix is zero above each block, so G_b = V_b^H V_b can run over all n rows:
 // one split-K GEMM batched over the full blocks (a ragged last block takes its
-// own).  One launch forms the triangular factors of both halves of every
-// block; the coupling T_12 = -T_1 (V_1^H V_2) T_2 of the two halves (the
-// product of the two halves' compact-WY forms) takes two batched GEMMs.
+// own).  One launch forms the triangular factors of the quarters of every
+// block; then pairs of neighbouring factors are joined, quarters into halves
+// and halves into the block, by the coupling T_12 = -T_1 (V_1^H V_2) T_2 (the
+// product of two compact-WY forms), two batched GEMMs per pair position.
 template <typename T>
 void backtransform_prepare(hipStream_t s, int n, int batch, const T* Vall, const T* tau, BacktrWork<T>& w) {
-    const int bt = BACKTR_BT, hb = TF_HALF;
+    const int bt = w.bt;
     const int nref = n - 1;
     if (nref <= 0) return;
     const int nblk = cdiv(nref, bt), nfull = nref / bt;
@@ -91,23 +94,30 @@ void backtransform_prepare(hipStream_t s, int n, int batch, const T* Vall, const
                            w.P, w.pelems);
         }
     }
-    hipLaunchKernelGGL((t_factors_kernel<T>), dim3(2 * nblk, batch), dim3(TF_HALF), 0, s, n, tau, w.Tall, w.sTall);
-    // coupling of the halves: Y = G_12 T_2 (in W1), then T_12 = -T_1 Y over G_12
-    const long sy = (long)hb * hb;
+    hipLaunchKernelGGL((t_factors_kernel<T>), dim3((bt / TF_Q) * nblk, batch), dim3(TF_Q), 0, s, n, bt, tau, w.Tall,
+                       w.sTall);
+    // join pairs: Y = G_12 T_2 (in W1), then T_12 = -T_1 Y over G_12
+    const int jl = nref - nfull * bt;  // order of a ragged last block (0 if none)
     for (int z = 0; z < batch; ++z) {
         T* Tz = w.Tall + z * w.sTall;
-        if (nfull > 0) {
-            gemm<T>(s, OP_N, OP_N, hb, hb, hb, 1.0, Tz + hb, bt, bb, Tz + (long)hb * bt + hb, bt, bb, 0.0, w.W1, hb,
-                    sy, nfull);
-            gemm<T>(s, OP_N, OP_N, hb, hb, hb, -1.0, Tz, bt, bb, w.W1, hb, sy, 0.0, Tz + hb, bt, bb, nfull);
-        }
-        const int jb = nref - nfull * bt;
-        if (nblk > nfull && jb > hb) {
-            T* Tl = Tz + (long)nfull * bb;
-            const int j2 = jb - hb;
-            gemm<T>(s, OP_N, OP_N, hb, j2, j2, 1.0, Tl + hb, bt, 0, Tl + (long)hb * bt + hb, bt, 0, 0.0, w.W1, j2, 0,
-                    1);
-            gemm<T>(s, OP_N, OP_N, hb, j2, hb, -1.0, Tl, bt, 0, w.W1, j2, 0, 0.0, Tl + hb, bt, 0, 1);
+        for (int hb = TF_Q; hb < bt; hb *= 2) {
+            for (int po = 0; po < bt; po += 2 * hb) {
+                T* T1 = Tz + (long)po * bt + po;
+                T* G12 = T1 + hb;
+                T* T2 = T1 + (long)hb * bt + hb;
+                if (nfull > 0) {
+                    gemm<T>(s, OP_N, OP_N, hb, hb, hb, 1.0, G12, bt, bb, T2, bt, bb, 0.0, w.W1, hb, (long)hb * hb,
+                            nfull);
+                    gemm<T>(s, OP_N, OP_N, hb, hb, hb, -1.0, T1, bt, bb, w.W1, hb, (long)hb * hb, 0.0, G12, bt, bb,
+                            nfull);
+                }
+                const int h2 = std::min(hb, jl - po - hb);  // the ragged block's second factor of this pair
+                if (nblk > nfull && h2 > 0) {
+                    const long lo = (long)nfull * bb;
+                    gemm<T>(s, OP_N, OP_N, hb, h2, h2, 1.0, G12 + lo, bt, 0, T2 + lo, bt, 0, 0.0, w.W1, h2, 0, 1);
+                    gemm<T>(s, OP_N, OP_N, hb, h2, hb, -1.0, T1 + lo, bt, 0, w.W1, h2, 0, 0.0, G12 + lo, bt, 0, 1);
+                }
+            }
         }
     }
 }
@@ -115,7 +125,7 @@ void backtransform_prepare(hipStream_t s, int n, int batch, const T* Vall, const
 template <typename T>
 void backtransform_q(hipStream_t s, int n, int batch, const T* Vall, int ncols, T* X, int ldx, long sX,
                      BacktrWork<T>& w, bool adjoint) {
-    const int bt = BACKTR_BT;
+    const int bt = w.bt;
     const int B = batch;
     const long sV = (long)n * n;
     int nref = n - 1;

@@ -16,7 +16,12 @@ constexpr int HETRD_NB = 32;   // panel width of the tridiagonalisation
 constexpr int HETRD_TILE = 64; // tile edge of the trailing symmetric product
 constexpr int HETRD_SCH = 4;      // default tiles per workgroup of the trailing symmetric product
 constexpr int HETRD_SCH_MIN = 2;  // smallest candidate (sizes the partial buffers)
-constexpr int BACKTR_BT = 128;  // reflectors per compact-WY block of the back-transform
+constexpr int BACKTR_BT = 256;  // largest number of reflectors per compact-WY block of the back-transform
+constexpr int BACKTR_SUB = 64;  // reflectors per triangular factor solved directly (a power of two)
+// reflectors per compact-WY block for a given order: 256 from order 4096 up
+// (rank-256 updates run on the large-tile GEMM), 128 below (smaller orders
+// pay more for the larger factors than they gain)
+inline int backtr_block(int order) { return order >= 4096 ? 256 : 128; }
 constexpr int DC_LEAF = 32;    // largest divide-and-conquer leaf
 constexpr int MAX_KW = 64;     // k-point weights passed by value
 
@@ -106,6 +111,7 @@ struct BacktrWork {
     long pelems;  // capacity of P in elements
     T* Tall;      // cdiv(n-1, BT) x BT x BT per matrix: the compact-WY factors
     long sTall;   // matrix stride of Tall
+    int bt = BACKTR_BT;  // reflectors per block for this plan's order (a multiple of BACKTR_SUB)
 };
 
 // Divide-and-conquer scratch; all position-indexed arrays have n entries and

@@ -276,3 +276,23 @@ def test_hetrd_similarity(L, n, cplx):
     wT, _, _ = O.jacobi(T)
     wA, _, _ = O.jacobi(A)
     assert np.abs(wT - wA).max() < 1e-12 * n
+
+
+def test_hetrd_similarity_order_4100(L):
+    """Order 4100 takes 256-reflector compact-WY blocks in the back-transform
+    (16 full blocks and a ragged one of 3) and the large-tile GEMMs: Q unitary
+    and Q T Q^H = A (which fix eig(T) = eig(A))."""
+    n = 4100
+    announce("hetrd", n)
+    rng = np.random.default_rng(11)
+    A = I.random_hermitian(rng, n, False)
+    Ad = dev(A)
+    d = torch.zeros(n, dtype=torch.float64, device="cuda")
+    e = torch.zeros(n, dtype=torch.float64, device="cuda")
+    X = dev(np.eye(n))
+    Y = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    assert L.ks_test_hetrd(0, n, P(Ad), P(d), P(e), P(X), n, P(Y), stream_handle()) == 0
+    dh, eh, Q = host(d), host(e)[:n - 1], host(Y)
+    T = tridiag(dh, eh)
+    assert np.abs(Q.T @ Q - np.eye(n)).max() < 1e-12
+    assert np.abs(Q @ T @ Q.T - A).max() < 1e-12 * max(1.0, np.abs(A).max()) * n
