@@ -486,7 +486,8 @@ ks_status gevd_impl(ks_plan* p, const T* H, const T* S, double* eps, T* C, int i
     const int ncols = iu - il + 1;
     const long sA = (long)order * order, sL = (long)n * n, sH = (long)order * ldh;
     hipEvent_t e = pf.begin();
-    reduce_to_standard<T>(s, n, nsp, B, H, ldh, sH, Li, n, sL, A, W, p->info);
+    // only the lower triangle: the tridiagonalisation reads nothing else
+    reduce_to_standard<T>(s, n, nsp, B, H, ldh, sH, Li, n, sL, A, W, p->info, true);
     pf.end(KS_PHASE_REDUCE, e);
     e = pf.begin();
     hetrd<T, T>(s, order, A, order, sA, B, p->dv, p->ev, tau, W, hw);

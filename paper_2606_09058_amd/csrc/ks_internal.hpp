@@ -167,10 +167,12 @@ void herm_complete(hipStream_t s, int n, const T* src, int lds, long ss, T* dst,
                    int batch, int* info);
 
 // A = (I (x) Linv) H (I (x) Linv)^H for a batch (H: row stride ldh, matrix
-// stride sH; Linv: n x n, stride sL; A, W: order x order, consecutive).
+// stride sH; Linv: n x n, stride sL; A, W: order x order, consecutive).  With
+// lower_only only the lower triangle of A is formed (all the tridiagonalisation
+// reads), which halves the second product.
 template <typename T>
 void reduce_to_standard(hipStream_t s, int n, int nsp, int batch, const T* H, int ldh, long sH, const T* Linv,
-                        int ldi, long sL, T* A, T* W, int* info);
+                        int ldi, long sL, T* A, T* W, int* info, bool lower_only = false);
 
 
 

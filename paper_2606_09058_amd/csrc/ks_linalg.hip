@@ -239,16 +239,17 @@ __global__ __launch_bounds__(256) void hermitize_kernel(int n, T* A, int lda) {
 // rows; order = nsp * n.  Only the lower triangle of A is used afterwards.
 template <typename T>
 void reduce_to_standard(hipStream_t s, int n, int nsp, int batch, const T* H, int ldh, long sH, const T* Linv,
-                        int ldi, long sL, T* A, T* W, int* info) {
+                        int ldi, long sL, T* A, T* W, int* info, bool lower_only) {
     const int order = n * nsp;
     const long sA = (long)order * order;
+    const Uplo up = lower_only ? UPLO_LOWER : UPLO_FULL;
     herm_complete<T>(s, order, H, ldh, sH, A, order, sA, batch, info);
     if (nsp == 1) {
         // W = Linv A, A = W Linv^H for every matrix of the batch
         gemm<T>(s, OP_N, OP_N, n, n, n, 1.0, Linv, ldi, sL, A, order, sA, 0.0, W, order, sA, batch, nullptr, 0,
                 UPLO_FULL, nullptr, TRI_A_LOWER);
-        gemm<T>(s, OP_N, OP_C, n, n, n, 1.0, W, order, sA, Linv, ldi, sL, 0.0, A, order, sA, batch, nullptr, 0,
-                UPLO_FULL, nullptr, TRI_B_UPPER);
+        gemm<T>(s, OP_N, OP_C, n, n, n, 1.0, W, order, sA, Linv, ldi, sL, 0.0, A, order, sA, batch, nullptr, 0, up,
+                nullptr, TRI_B_UPPER);
         return;
     }
     for (int b = 0; b < batch; ++b) {
@@ -259,15 +260,24 @@ void reduce_to_standard(hipStream_t s, int n, int nsp, int batch, const T* H, in
         gemm<T>(s, OP_N, OP_N, n, order, n, 1.0, Lb, ldi, 0, Ab, order, (long)n * order, 0.0, Wb, order,
                 (long)n * order, nsp, nullptr, 0, UPLO_FULL, nullptr, TRI_A_LOWER);
         // A = W (I (x) Linv)^H : spin column-block r of A is column-block r of W times Linv^H
-        gemm<T>(s, OP_N, OP_C, order, n, n, 1.0, Wb, order, n, Lb, ldi, 0, 0.0, Ab, order, n, nsp, nullptr, 0,
-                UPLO_FULL, nullptr, TRI_B_UPPER);
+        if (!lower_only) {
+            gemm<T>(s, OP_N, OP_C, order, n, n, 1.0, Wb, order, n, Lb, ldi, 0, 0.0, Ab, order, n, nsp, nullptr, 0,
+                    UPLO_FULL, nullptr, TRI_B_UPPER);
+        } else {
+            // lower triangle: column-block 0 over all rows, column-block 1 over its own rows only
+            gemm<T>(s, OP_N, OP_C, order, n, n, 1.0, Wb, order, 0, Lb, ldi, 0, 0.0, Ab, order, 0, 1, nullptr, 0,
+                    UPLO_LOWER, nullptr, TRI_B_UPPER);
+            const long d = (long)n * order + n;
+            gemm<T>(s, OP_N, OP_C, n, n, n, 1.0, Wb + d, order, 0, Lb, ldi, 0, 0.0, Ab + d, order, 0, 1, nullptr, 0,
+                    UPLO_LOWER, nullptr, TRI_B_UPPER);
+        }
     }
 }
 
 #define KS_INST(T)                                                                                 \
     template void herm_complete<T>(hipStream_t, int, const T*, int, long, T*, int, long, int, int*); \
     template void reduce_to_standard<T>(hipStream_t, int, int, int, const T*, int, long, const T*, int, \
-                                        long, T*, T*, int*);                                        \
+                                        long, T*, T*, int*, bool);                                  \
     template void potrf_inv<T>(hipStream_t, int, T*, int, long, T*, int, long, T*, long, int, int*);
 KS_INST(double)
 KS_INST(cplx)
