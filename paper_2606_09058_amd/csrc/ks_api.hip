@@ -694,14 +694,18 @@ ks_status ks_density(ks_plan* p, const double* eps, const void* C, int32_t il, i
     hipEvent_t e = p->prof.begin();
     fermi(s, p->d.batch, order, eps, kw, g, ne, kT, il, iu, f, mu, eband, p->kwin, p->info);
     long mat = (long)order * ldh;
-    // rho = C diag(f) C^H over the window columns that carry occupation (count on the device)
-    if (p->is_c)
+    // rho = C diag(f) C^H over the window columns that carry occupation (count
+    // on the device): the lower triangle, then the upper one as its mirror
+    if (p->is_c) {
         gemm<cplx>(s, OP_N, OP_C, order, order, ncols, 1.0, (const cplx*)C, ldh, mat, (const cplx*)C, ldh,
-                   mat, 0.0, (cplx*)rho, ldh, mat, p->d.batch, f + il - 1, order, UPLO_FULL, p->kwin);
-    else
+                   mat, 0.0, (cplx*)rho, ldh, mat, p->d.batch, f + il - 1, order, UPLO_LOWER, p->kwin);
+        mirror_lower<cplx>(s, order, (cplx*)rho, ldh, mat, p->d.batch);
+    } else {
         gemm<double>(s, OP_N, OP_T, order, order, ncols, 1.0, (const double*)C, ldh, mat,
                      (const double*)C, ldh, mat, 0.0, (double*)rho, ldh, mat, p->d.batch, f + il - 1,
-                     order, UPLO_FULL, p->kwin);
+                     order, UPLO_LOWER, p->kwin);
+        mirror_lower<double>(s, order, (double*)rho, ldh, mat, p->d.batch);
+    }
     p->prof.end(KS_PHASE_DENSITY, e);
     if (hipPeekAtLastError() != hipSuccess) return KS_ERR_HIP;
     return KS_OK;

@@ -166,6 +166,11 @@ template <typename T>
 void herm_complete(hipStream_t s, int n, const T* src, int lds, long ss, T* dst, int ldd, long sd,
                    int batch, int* info);
 
+// X[i][j] = conj(X[j][i]) for j > i (the upper triangle from the lower one),
+// in place, for a batch of n x n matrices.
+template <typename T>
+void mirror_lower(hipStream_t s, int n, T* X, int ldx, long sx, int batch);
+
 // A = (I (x) Linv) H (I (x) Linv)^H for a batch (H: row stride ldh, matrix
 // stride sH; Linv: n x n, stride sL; A, W: order x order, consecutive).  With
 // lower_only only the lower triangle of A is formed (all the tridiagonalisation

@@ -194,6 +194,35 @@ void herm_complete(hipStream_t s, int n, const T* src, int lds, long ss, T* dst,
                        info);
 }
 
+// The strictly upper triangle of each n x n matrix X (row stride ldx, matrix
+// stride sx) from its lower one, in place: X[i][j] = conj(X[j][i]) for j > i.
+// One workgroup per 32 x 32 tile on or above the diagonal; it reads only the
+// lower triangle and writes only the strictly upper one.
+template <typename T>
+__global__ __launch_bounds__(256) void mirror_lower_kernel(int n, T* X, int ldx, long sx) {
+    __shared__ T tile[32][33];
+    const int bi = blockIdx.y * 32, bj = blockIdx.x * 32;
+    if (bj < bi) return;
+    X += blockIdx.z * sx;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    for (int r = ty; r < 32; r += 8) {
+        const int i = bj + r, j = bi + tx;  // the mirrored tile, lower part only
+        tile[r][tx] = (i < n && j < n && j <= i) ? X[(long)i * ldx + j] : zero_<T>();
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int i = bi + r, j = bj + tx;
+        if (i < n && j < n && j > i) X[(long)i * ldx + j] = conj_(tile[tx][r]);
+    }
+}
+
+template <typename T>
+void mirror_lower(hipStream_t s, int n, T* X, int ldx, long sx, int batch) {
+    if (n <= 0 || batch <= 0) return;
+    dim3 grid(cdiv(n, 32), cdiv(n, 32), batch);
+    hipLaunchKernelGGL((mirror_lower_kernel<T>), grid, dim3(256), 0, s, n, X, ldx, sx);
+}
+
 // dst (cols x rows) = src^H (src rows x cols).
 template <typename T>
 __global__ __launch_bounds__(256) void conj_transpose_kernel(int rows, int cols, const T* src,
@@ -278,7 +307,8 @@ void reduce_to_standard(hipStream_t s, int n, int nsp, int batch, const T* H, in
     template void herm_complete<T>(hipStream_t, int, const T*, int, long, T*, int, long, int, int*); \
     template void reduce_to_standard<T>(hipStream_t, int, int, int, const T*, int, long, const T*, int, \
                                         long, T*, T*, int*, bool);                                  \
-    template void potrf_inv<T>(hipStream_t, int, T*, int, long, T*, int, long, T*, long, int, int*);
+    template void potrf_inv<T>(hipStream_t, int, T*, int, long, T*, int, long, T*, long, int, int*);    \
+    template void mirror_lower<T>(hipStream_t, int, T*, int, long, int);
 KS_INST(double)
 KS_INST(cplx)
 #undef KS_INST
