@@ -398,7 +398,10 @@ ks_status gevd_mixed(ks_plan* p, const T* H, double* eps, T* C, int il, int iu) 
     Prof& pf = p->prof;
     if (!p->rr || p->rr->d.n != M) return KS_ERR_INVALID_ARG;  // prepared by ks_gevd
     hipEvent_t e = pf.begin();
-    reduce_to_standard<T>(s, n, nsp, B, H, ldh, sH, Li, n, sL, A, W, p->info);
+    // the lower triangle, then the upper one as its mirror (the residuals take
+    // products with the whole matrix)
+    reduce_to_standard<T>(s, n, nsp, B, H, ldh, sH, Li, n, sL, A, W, p->info, true);
+    mirror_lower<T>(s, order, A, order, sA, B);
     convert<T, L>(s, B, order, order, A, order, sA, A32, order, sA);
     pf.end(KS_PHASE_REDUCE, e);
     e = pf.begin();
