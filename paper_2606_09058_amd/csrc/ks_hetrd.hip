@@ -593,7 +593,9 @@ __global__ __launch_bounds__(64 * Wc<T>::NW) void wcol_kernel(int n, int k, int 
     }
 }
 
-// Copy the panel's reflectors into columns k0 .. k0+jb-1 of Vall (n x n).
+// Copy the panel's reflectors into columns k0 .. k0+jb-1 of Vall (n x n), with
+// the zeros above each reflector's first entry (row k0+i+1, where it is 1):
+// the panel buffer holds only the rows its column kernels wrote.
 template <typename T>
 __global__ void store_panel_kernel(int n, int k0, int jb, const T* VWt, long sVW, T* Vall) {
     VWt += blockIdx.z * sVW;
@@ -601,7 +603,7 @@ __global__ void store_panel_kernel(int n, int k0, int jb, const T* VWt, long sVW
     long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (long)n * jb) return;
     int i = (int)(e / n), r = (int)(e % n);
-    Vall[(long)r * n + k0 + i] = VWt[(long)i * n + r];
+    Vall[(long)r * n + k0 + i] = r > k0 + i ? VWt[(long)i * n + r] : zero_<T>();
 }
 
 template <typename S>
@@ -644,8 +646,13 @@ void hetrd(hipStream_t s, int n, S* A, int lda, long sA, int batch, double* d, d
     const int B = batch;
     for (int k0 = 0; k0 < n - 1; k0 += nb) {
         int jb = min(nb, n - 1 - k0);
-        fill_zero<T>(s, w.VW, w.sVW * B);
-        fill_zero<T>(s, w.WV, w.sVW * B);
+        // The column kernels write every panel row the trailing update and the
+        // next columns read (rows k+1.. of column k); only a short last panel
+        // leaves panel columns unwritten that its update would read.
+        if (jb < nb) {
+            fill_zero<T>(s, w.VW, w.sVW * B);
+            fill_zero<T>(s, w.WV, w.sVW * B);
+        }
         hipLaunchKernelGGL((colstart_kernel<T, S>), dim3(cdiv(n - k0, 64), 1, B), dim3(64), 0, s, n, k0, nb, A, lda,
                            sA, w);
         for (int j = 0; j < jb; ++j) {
