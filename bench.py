@@ -170,6 +170,28 @@ def main():
         tr = float((w * (rho * S.to(rho.dtype).transpose(1, 2)).sum(dim=(1, 2)).real).sum().item())
     m_occ = int((occ > 2e-15 * p.g).sum(dim=-1).max().item())
     flops = p.batch * nominal_flops(p.order, p.order, m_occ, cplx, p.n)
+
+    # energy-density matrix E = C diag(f eps) C^H of the last solve, over the
+    # columns that carry occupation (outside the timed steps: not part of `value`)
+    edm = torch.empty_like(rho)
+    with torch.cuda.stream(stream):
+        plan.energy_density(eps, C, occ, edm, il=1, iu=max(1, m_occ))
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        plan.energy_density(eps, C, occ, edm, il=1, iu=max(1, m_occ))
+    e1.record(stream)
+    torch.cuda.synchronize()
+    plan.check("energy density")
+    ms_edm = e0.elapsed_time(e1) / args.steps
+    SNe = torch.block_diag(S, S) if p.nsp == 2 else S
+    if p.batch == 1:
+        edm_tr = float((edm * SNe.to(edm.dtype).T).sum().real.item())
+    else:
+        wk = torch.tensor(p.weights, dtype=torch.float64, device="cuda")
+        edm_tr = float((wk * (edm * S.to(edm.dtype).transpose(1, 2)).sum(dim=(1, 2)).real).sum().item())
+    # lower triangle of an order x order x m_occ product (x4 for complex)
+    edm_flops = p.batch * (4.0 if cplx else 1.0) * p.order * p.order * m_occ
     hemv_avg_us = 1e3 * prof.hemv_ms / max(1, prof.hemv_launches)
     hemv_gbs = prof.hemv_bytes / max(1e-12, prof.hemv_ms * 1e-3) / 1e9
     phases = phase_dict(prof, args.steps)
@@ -209,7 +231,10 @@ def main():
                      "avg_launch_us": hemv_avg_us, "sampled_launches": int(prof.hemv_launches),
                      "bytes_per_launch_avg": prof.hemv_bytes / max(1, prof.hemv_launches)},
         "checks": {"trace_rho_S_minus_Ne": tr - p.n_electrons, "mu": float(mu.item()),
-                   "eband": float(eband.item())},
+                   "eband": float(eband.item()),
+                   "trace_edm_S_minus_eband": edm_tr - float(eband.item())},
+        "energy_density": {"ms": ms_edm, "columns": m_occ,
+                           "tflops": edm_flops / (ms_edm * 1e-3) / 1e12},
     }
     if p.batch > 1:
         out["ms_per_kpoint"] = ms / p.batch

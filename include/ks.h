@@ -142,6 +142,18 @@ ks_status ks_density(ks_plan* plan, const double* eps, const void* C, int32_t il
                      double n_electrons, double kT, const double* kweights, void* rho,
                      double* mu, double* eband, double* occ);
 
+/* Energy-density matrix E_k = C_k diag(f_k eps_k) C_k^H (paper Sec. 3.1, the
+ * Part 4 quantity needed for forces; with H C = S C eps it equals
+ * S^-1 H rho, and tr(E S) = E_band per k).  Not positive semi-definite, so it
+ * is a scaled product rather than a square-root factorisation.
+ *   eps  [batch][order] eigenvalues, C as for ks_density (window il .. iu)
+ *   occ  DEVICE [batch][order] occupations f_ik (from ks_density)
+ *   edm  [batch][order][ld_h] output, both triangles (exactly Hermitian)
+ * Argument errors (null pointers, window outside 1..order) return before any
+ * device work; the call is asynchronous on the plan's stream. */
+ks_status ks_energy_density(ks_plan* plan, const double* eps, const void* C, int32_t il, int32_t iu,
+                            const double* occ, void* edm);
+
 /* Adjoint of (rho, E_band) with respect to (H, S): given dL/drho (grad_rho,
  * full, may be NULL for zero) and dL/dE_band (grad_eband, DEVICE scalar or
  * NULL for zero), writes grad_H [batch][order][ld_h] and grad_S [batch][n][ld_s]

@@ -15,6 +15,7 @@ and follows the paper's definitions:
 * ``fermi``         -- occupations and the chemical potential by bisection on
                        the electron count (Part 3 of Sec. 3.1),
 * ``density``       -- rho = C f C^H (Sec. 2 density matrix, conjugated),
+* ``energy_density``-- E = C diag(f eps) C^H (the energy-density matrix),
 * ``adjoint``       -- dense gradients of L(rho, E_band) w.r.t. H and S,
 * ``cholesky``, ``solve_lower``, ``solve_lower_h``, ``jacobi`` -- the steps.
 """
@@ -218,6 +219,13 @@ def density(C, w):
     _set(0, order)
     lib().ko_density(order, ncols, int(dt == np.complex128), _ptr(C), ncols, _ptr(w), _ptr(rho))
     return rho
+
+
+def energy_density(C, occ, eps):
+    """Energy-density matrix E = C diag(f eps) C^H over the columns of C (the
+    Part 4 quantity of Sec. 3.1 used for forces): the density-matrix sum with
+    weights f_i eps_i."""
+    return density(C, np.asarray(occ, dtype=np.float64) * np.asarray(eps, dtype=np.float64))
 
 
 def adjoint(eps, C, mu, kT, g, Gbar=None, ebar=0.0, nsp=1, wk=None):

@@ -33,6 +33,7 @@ struct ks_plan {
     double* U = nullptr;
     double* Qp = nullptr;
     double* occ = nullptr;     // batch x order
+    double* fe = nullptr;      // batch x order: f eps, the energy-density weights
     int* info = nullptr;       // [2]
     int* kwin = nullptr;       // occupied-window width found by the Fermi kernel
     Prof prof;
@@ -137,6 +138,7 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
     size_t oZ = L.take(B * order * order * 8), oZ2 = L.take(B * order * order * 8);
     size_t oU = L.take(B * order * order * 8), oQp = L.take(B * order * order * 8);
     size_t oOcc = L.take(B * order * 8);
+    size_t oFe = L.take(B * order * 8);  // occupation x eigenvalue weights of the energy-density matrix
     size_t oInfo = L.take(2 * sizeof(int));
     size_t oKwin = L.take(sizeof(int));
     // tridiagonalisation (per matrix of the batch)
@@ -204,6 +206,7 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
     p->U = (double*)(b + oU);
     p->Qp = (double*)(b + oQp);
     p->occ = (double*)(b + oOcc);
+    p->fe = (double*)(b + oFe);
     p->info = (int*)(b + oInfo);
     p->kwin = (int*)(b + oKwin);
     auto setH = [&](auto& h, auto* tag) {
@@ -710,6 +713,37 @@ ks_status ks_density(ks_plan* p, const double* eps, const void* C, int32_t il, i
         mirror_lower<double>(s, order, (double*)rho, ldh, mat, p->d.batch);
     }
     p->prof.end(KS_PHASE_DENSITY, e);
+    if (hipPeekAtLastError() != hipSuccess) return KS_ERR_HIP;
+    return KS_OK;
+}
+
+// f_ik eps_ik for the window columns of every matrix of the batch.
+__global__ void edm_weights_kernel(int order, int c0, int ncols, const double* occ, const double* eps, double* fe) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ncols) return;
+    const long o = (long)blockIdx.y * order + c0 + i;
+    fe[o] = occ[o] * eps[o];
+}
+
+ks_status ks_energy_density(ks_plan* p, const double* eps, const void* C, int32_t il, int32_t iu,
+                            const double* occ, void* edm) {
+    if (!p || !eps || !C || !occ || !edm) return KS_ERR_INVALID_ARG;
+    if (!range_ok(p, il, iu)) return KS_ERR_INVALID_ARG;
+    hipStream_t s = p->s;
+    const int order = p->order, ldh = p->d.ld_h, ncols = iu - il + 1, c0 = il - 1;
+    const long mat = (long)order * ldh;
+    hipLaunchKernelGGL(edm_weights_kernel, dim3(cdiv(ncols, 256), p->d.batch), dim3(256), 0, s, order, c0, ncols,
+                       occ, eps, p->fe);
+    // E = C diag(f eps) C^H: the lower triangle, then the upper one as its mirror
+    if (p->is_c) {
+        gemm<cplx>(s, OP_N, OP_C, order, order, ncols, 1.0, (const cplx*)C, ldh, mat, (const cplx*)C, ldh, mat,
+                   0.0, (cplx*)edm, ldh, mat, p->d.batch, p->fe + c0, order, UPLO_LOWER);
+        mirror_lower<cplx>(s, order, (cplx*)edm, ldh, mat, p->d.batch);
+    } else {
+        gemm<double>(s, OP_N, OP_T, order, order, ncols, 1.0, (const double*)C, ldh, mat, (const double*)C, ldh,
+                     mat, 0.0, (double*)edm, ldh, mat, p->d.batch, p->fe + c0, order, UPLO_LOWER);
+        mirror_lower<double>(s, order, (double*)edm, ldh, mat, p->d.batch);
+    }
     if (hipPeekAtLastError() != hipSuccess) return KS_ERR_HIP;
     return KS_OK;
 }

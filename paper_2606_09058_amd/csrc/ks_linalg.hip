@@ -195,9 +195,10 @@ void herm_complete(hipStream_t s, int n, const T* src, int lds, long ss, T* dst,
 }
 
 // The strictly upper triangle of each n x n matrix X (row stride ldx, matrix
-// stride sx) from its lower one, in place: X[i][j] = conj(X[j][i]) for j > i.
-// One workgroup per 32 x 32 tile on or above the diagonal; it reads only the
-// lower triangle and writes only the strictly upper one.
+// stride sx) from its lower one, in place: X[i][j] = conj(X[j][i]) for j > i,
+// and the diagonal made real, so that X is exactly Hermitian.  One workgroup
+// per 32 x 32 tile on or above the diagonal; each element is read once (into
+// LDS) before the tile writes it.
 template <typename T>
 __global__ __launch_bounds__(256) void mirror_lower_kernel(int n, T* X, int ldx, long sx) {
     __shared__ T tile[32][33];
@@ -213,6 +214,7 @@ __global__ __launch_bounds__(256) void mirror_lower_kernel(int n, T* X, int ldx,
     for (int r = ty; r < 32; r += 8) {
         const int i = bi + r, j = bj + tx;
         if (i < n && j < n && j > i) X[(long)i * ldx + j] = conj_(tile[tx][r]);
+        if (i < n && j == i) X[(long)i * ldx + j] = from_re<T>(re_(tile[tx][r]));  // real diagonal
     }
 }
 

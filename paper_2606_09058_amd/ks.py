@@ -28,7 +28,7 @@ STATUS = {
     8: "KS_ERR_HIP", 9: "KS_ERR_NOT_SUPPORTED",
 }
 
-EXPORTS = ["ks_plan_create", "ks_plan_destroy", "ks_gevd", "ks_density", "ks_density_backward",
+EXPORTS = ["ks_plan_create", "ks_plan_destroy", "ks_gevd", "ks_density", "ks_energy_density", "ks_density_backward",
            "ks_plan_get_info", "ks_status_string", "ks_plan_workspace_bytes", "ks_plan_set_profiling",
            "ks_plan_get_profile", "ks_plan_get_graph_stats", "ks_plan_get_tuning", "ks_plan_set_refinement"]
 
@@ -83,6 +83,8 @@ def lib():
         L.ks_gevd.restype = I
         L.ks_density.argtypes = [P, P, P, I, I, D, D, P, P, P, P, P]
         L.ks_density.restype = I
+        L.ks_energy_density.argtypes = [P, P, P, I, I, P, P]
+        L.ks_energy_density.restype = I
         L.ks_density_backward.argtypes = [P, P, P, P, P, D, P, P, P, P]
         L.ks_density_backward.restype = I
         L.ks_plan_get_info.argtypes = [P, ctypes.POINTER(I)]
@@ -196,6 +198,16 @@ class Plan:
         st = lib().ks_density(self._h, _ptr(eps), _ptr(C), int(il), int(iu), float(n_electrons),
                               float(kT), kw, _ptr(rho), _ptr(mu), _ptr(eband), _ptr(occ))
         _check(st, "ks_density")
+
+    def energy_density(self, eps, C, occ, edm, il=1, iu=None):
+        """ks_energy_density: edm = C diag(occ eps) C^H over the window il..iu (device tensors)."""
+        iu = self.order if iu is None else iu
+        _need(eps, "eps", torch.float64, self._vshape())
+        _need(C, "C", self.mdtype, self._mshape())
+        _need(occ, "occ", torch.float64, self._vshape())
+        _need(edm, "edm", self.mdtype, self._mshape())
+        st = lib().ks_energy_density(self._h, _ptr(eps), _ptr(C), int(il), int(iu), _ptr(occ), _ptr(edm))
+        _check(st, "ks_energy_density")
 
     def density_backward(self, eps, C, mu, occ, kT, grad_rho, grad_eband, grad_H, grad_S):
         _need(eps, "eps", torch.float64, self._vshape())

@@ -78,6 +78,34 @@ def test_noncollinear_vs_oracle(natoms):
     compare(p, g, o)
 
 
+@pytest.mark.parametrize("kind", ["real", "complex", "noncollinear", "window"])
+def test_energy_density_vs_oracle(kind):
+    """ks_energy_density (E = C diag(f eps) C^H) against the oracle's, and the
+    identity S E = H rho on the GPU's own results; the window case takes the
+    occupied columns only."""
+    announce("energy density", kind)
+    if kind == "noncollinear":
+        p = I.noncollinear(seed=5, nx=5, ny=1, nz=1, lam_max=0.2)
+    else:
+        p = I.toy(seed=23, natoms=14, norb=13, edge=12.0, n_electrons=110.0, kT=0.01, phases=kind != "real")
+    o = O.solve(p.H, p.S, p.n_electrons, p.kT, nsp=p.nsp)
+    il, iu = 1, p.order
+    if kind == "window":
+        iu = int((o["occ"] > p.g * 1e-15).sum()) + 5
+    plan = ks.Plan(p.n, complex=np.iscomplexobj(p.H), noncollinear=p.nsp == 2)
+    out = plan.solve(dev(p.H), dev(p.S.astype(p.H.dtype)), p.n_electrons, p.kT, il=il, iu=iu)
+    edm = torch.empty_like(out["rho"])
+    plan.energy_density(out["eps"], out["C"], out["occ"], edm, il=il, iu=iu)
+    plan.check("energy density")
+    E = host(edm)
+    Eo = O.energy_density(o["C"], o["occ"], o["eps"])
+    scale = max(1.0, np.abs(o["eps"]).max())
+    assert np.abs(E - Eo).max() < RHO_TOL * scale
+    SN = np.kron(np.eye(p.nsp), p.S) if p.nsp == 2 else p.S
+    assert np.abs(SN @ E - p.H @ host(out["rho"])).max() < 1e-9 * scale
+    assert np.array_equal(E, E.conj().T)
+
+
 def test_kpoint_batch_common_mu():
     announce("kpoint batch")
     p = I.kpoint_batch(natoms=6, norb=13, kgrid=(2, 2, 1))

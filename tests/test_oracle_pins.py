@@ -332,6 +332,33 @@ def test_density_convention_is_conjugate_of_paper_n():
     assert np.abs(rho - n_paper.conj()).max() < 1e-14
 
 
+@pytest.mark.parametrize("cplx,nsp", [(False, 1), (True, 1), (True, 2)])
+def test_energy_density_pins(cplx, nsp):
+    """E = C diag(f eps) C^H: with H C = S C eps, S E = H rho exactly; tr(E S_NC) =
+    E_band; and an explicit sum of outer products on a small input (the oracle's
+    definition retyped would not pin it; these three fix a dropped weight, a
+    transposed operand or a lost conjugate)."""
+    if nsp == 2:
+        p = I.noncollinear(seed=4, nx=3, ny=1, nz=1, lam_max=0.2)
+    else:
+        p = I.toy(seed=17, natoms=5, norb=7, n_electrons=24.0, phases=cplx)
+    r = O.solve(p.H, p.S, p.n_electrons, p.kT, nsp=nsp)
+    E = O.energy_density(r["C"], r["occ"], r["eps"])
+    SN = np.kron(np.eye(nsp), p.S) if nsp == 2 else p.S
+    scale = max(1.0, np.abs(r["eps"]).max())
+    assert np.abs(SN @ E - p.H @ r["rho"]).max() < 1e-10 * scale
+    assert abs(np.trace(E @ SN).real - r["eband"]) < 1e-10 * scale
+    assert np.abs(E - E.conj().T).max() < 1e-12 * scale
+    # explicit sum on the first few columns
+    C, f, e = r["C"][:, :5], r["occ"][:5], r["eps"][:5]
+    brute = np.zeros((C.shape[0], C.shape[0]), C.dtype)
+    for i in range(5):
+        for a in range(C.shape[0]):
+            for b in range(C.shape[0]):
+                brute[a, b] += f[i] * e[i] * C[a, i] * np.conj(C[b, i])
+    assert np.abs(O.energy_density(C, f, e) - brute).max() < 1e-13 * scale
+
+
 def test_noncollinear_zero_spin_coupling_matches_two_collinear_solves():
     """B = 0: the spinor problem splits into two collinear problems sharing one mu
     (g = 1 each); with H_aa = H_bb, rho_aa = rho_bb = rho_col(g=2)/2."""
@@ -429,7 +456,7 @@ def test_free_energy_gradient_is_rho_and_minus_edm(cplx, nsp):
     r = O.solve(H, S, ne, kT, nsp=nsp)
     rng = np.random.default_rng(13)
     n = S.shape[0]
-    edm = O.density(r["C"], r["occ"] * r["eps"])
+    edm = O.energy_density(r["C"], r["occ"], r["eps"])
     edm_s = sum(edm[b * n:(b + 1) * n, b * n:(b + 1) * n] for b in range(nsp))
     h = 1e-6
     for _ in range(4):
