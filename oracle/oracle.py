@@ -16,6 +16,7 @@ and follows the paper's definitions:
                        the electron count (Part 3 of Sec. 3.1),
 * ``density``       -- rho = C f C^H (Sec. 2 density matrix, conjugated),
 * ``energy_density``-- E = C diag(f eps) C^H (the energy-density matrix),
+* ``bloch_sum``     -- X(k) = sum_R X_R exp(i k.R) (the Bloch sums of Sec. 2),
 * ``adjoint``       -- dense gradients of L(rho, E_band) w.r.t. H and S,
 * ``cholesky``, ``solve_lower``, ``solve_lower_h``, ``jacobi`` -- the steps.
 """
@@ -219,6 +220,14 @@ def density(C, w):
     _set(0, order)
     lib().ko_density(order, ncols, int(dt == np.complex128), _ptr(C), ncols, _ptr(w), _ptr(rho))
     return rho
+
+
+def bloch_sum(XR, R, kvec):
+    """Bloch sums X(k) = sum_R X_R exp(i k.R) (Sec. 2, the Bloch-sum equations for
+    H(k) and S(k)): XR (nR, n, n), R (nR, 3), kvec (nk, 3) -> (nk, n, n) complex."""
+    XR = np.asarray(XR, dtype=np.float64)
+    ph = np.exp(1j * (np.asarray(kvec, dtype=np.float64) @ np.asarray(R, dtype=np.float64).T))  # (nk, nR)
+    return np.einsum("kr,rij->kij", ph, XR)
 
 
 def energy_density(C, occ, eps):

@@ -234,6 +234,44 @@ def noncollinear(seed=0, nx=8, ny=8, nz=6, norb=13, spacing=4.0, jitter=0.2, cut
                    "noncollinear", dict(natoms=natoms, norb=norb, sigma=sigma, seed=seed))
 
 
+def kpoint_realspace(seed=0, natoms=100, norb=13, density=1.0 / 64.0, min_dist=2.0, kgrid=(4, 2, 2)):
+    """The real-space blocks behind ``kpoint_batch`` (same seed, same numbers):
+    dict(HR, SR: (27, n, n) real, R: (27, 3) lattice vectors, k: (nk, 3)), with
+    S_0 carrying the unit diagonal and without the overlap shift sigma."""
+    rng = np.random.default_rng(seed)
+    edge = (natoms / density) ** (1.0 / 3.0)
+    box = np.full(3, edge)
+    pos = np.zeros((natoms, 3))
+    cnt = 0
+    while cnt < natoms:
+        p = rng.uniform(0.0, edge, size=3)
+        if cnt:
+            d = pos[:cnt] - p
+            d -= box * np.round(d / box)
+            if np.sqrt((d * d).sum(-1)).min() < min_dist:
+                continue
+        pos[cnt] = p
+        cnt += 1
+    n = natoms * norb
+    A = _sym_from_upper(n, _upper_values(rng, n, "normal", 0.3), rng.uniform(-1.0, 1.0, size=n))
+    U = _sym_from_upper(n, _upper_values(rng, n, "uniform"), rng.uniform(0.0, 1.0, size=n))
+    Rs = [np.array([a, b, c], dtype=np.float64) * edge
+          for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)]
+    ks = [2.0 * np.pi * np.array([i / kgrid[0], j / kgrid[1], l / kgrid[2]]) / edge
+          for i in range(kgrid[0]) for j in range(kgrid[1]) for l in range(kgrid[2])]
+    HR = np.zeros((len(Rs), n, n))
+    SR = np.zeros((len(Rs), n, n))
+    for r, R in enumerate(Rs):
+        dv = pos[None, :, :] + R - pos[:, None, :]          # t_j + R - t_i
+        dat = np.sqrt((dv * dv).sum(-1))
+        d = _orbital_distances(dat, norb)
+        HR[r] = A * np.exp(-d / 2.0)
+        SR[r] = 0.4 * U * np.exp(-d)
+        if not R.any():
+            SR[r][np.diag_indices(n)] = 1.0
+    return dict(HR=HR, SR=SR, R=np.array(Rs), k=np.array(ks))
+
+
 def kpoint_batch(seed=0, natoms=100, norb=13, density=1.0 / 64.0, min_dist=2.0,
                  kgrid=(4, 2, 2), electrons_per_atom=4.0, kT=0.01):
     """Bloch-summed k-point problems (paper Sec. 2, the Bloch-sum equations):

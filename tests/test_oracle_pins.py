@@ -359,6 +359,26 @@ def test_energy_density_pins(cplx, nsp):
     assert np.abs(O.energy_density(C, f, e) - brute).max() < 1e-13 * scale
 
 
+def test_bloch_sum_pins():
+    """X(k) = sum_R X_R exp(i k.R): the Gamma point is the plain sum; one lattice
+    vector gives X_R times its phase; real X_R give X(-k) = conj(X(k)); a set of R
+    closed under negation with X_-R = X_R^T gives Hermitian X(k); and the
+    generator's own H(k) (a separate plain sum) is reproduced."""
+    rs = I.kpoint_realspace(seed=3, natoms=5, norb=4, kgrid=(2, 2, 1))
+    HR, R, k = rs["HR"], rs["R"], rs["k"]
+    g = O.bloch_sum(HR, R, np.zeros((1, 3)))[0]
+    assert np.abs(g - HR.sum(0)).max() < 1e-13
+    one = O.bloch_sum(HR[5:6], R[5:6], k)
+    for q in range(len(k)):
+        assert np.abs(one[q] - HR[5] * np.exp(1j * k[q] @ R[5])).max() < 1e-14
+    Xp = O.bloch_sum(HR, R, k)
+    Xm = O.bloch_sum(HR, R, -k)
+    assert np.abs(Xm - Xp.conj()).max() < 1e-12
+    assert np.abs(Xp - Xp.conj().transpose(0, 2, 1)).max() < 1e-12
+    p = I.kpoint_batch(seed=3, natoms=5, norb=4, kgrid=(2, 2, 1))
+    assert np.abs(0.5 * (Xp + Xp.conj().transpose(0, 2, 1)) - p.H).max() < 1e-13
+
+
 def test_noncollinear_zero_spin_coupling_matches_two_collinear_solves():
     """B = 0: the spinor problem splits into two collinear problems sharing one mu
     (g = 1 each); with H_aa = H_bb, rho_aa = rho_bb = rho_col(g=2)/2."""
