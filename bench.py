@@ -238,6 +238,8 @@ def main():
     }
     if p.batch > 1:
         out["ms_per_kpoint"] = ms / p.batch
+    if args.workload == "kpoints16x1300":
+        out["bloch_sum"] = bloch_sum_timing(plan, p, stream, args.steps)
     if not args.no_mixed:
         out["precision_comparison"] = compare_precisions(p, H, S, eps, mu, args.steps)
     if not args.no_cpu_baseline:
@@ -248,6 +250,41 @@ def main():
 def phase_dict(prof, steps):
     names = ["cholesky", "reduce", "tridiag", "dc", "backtransform", "density", "adjoint", "refine"]
     return {nm: prof.phase_ms[i] / steps for i, nm in enumerate(names)}
+
+
+def bloch_sum_timing(plan, p, stream, steps):
+    """ks_bloch_sum of H(k) and S(k) for every k-point from the workload's 27
+    real-space blocks (outside the timed solve steps).  GB/s counts the
+    algorithmic bytes: the real blocks read once, the complex k-point matrices
+    written once."""
+    import torch
+    from paper_2606_09058_amd import inputs as I
+    rs = I.kpoint_realspace()
+    n, nk, nR = p.n, p.batch, rs["R"].shape[0]
+    R = torch.from_numpy(rs["R"]).cuda()
+    kv = torch.from_numpy(rs["k"]).cuda()
+    HR = torch.from_numpy(rs["HR"]).cuda()
+    SR = torch.from_numpy(rs["SR"]).cuda()
+    Hk = torch.empty((nk, n, n), dtype=torch.complex128, device="cuda")
+    Sk = torch.empty_like(Hk)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        plan.bloch_sum(R, kv, HR, Hk)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        plan.bloch_sum(R, kv, HR, Hk)
+        plan.bloch_sum(R, kv, SR, Sk)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    plan.check("bloch sum")
+    ms = e0.elapsed_time(e1) / (2 * steps)
+    nbytes = nR * n * n * 8 + nk * n * n * 16
+    dH = float((Hk - torch.from_numpy(p.H).cuda()).abs().max().item())
+    return {"ms_per_matrix_set": ms, "lattice_vectors": nR, "kpoints": nk, "GB_per_s": nbytes / (ms * 1e-3) / 1e9,
+            "max_abs_diff_vs_generator_H": dH}
 
 
 def compare_precisions(p, H, S, eps_all, mu, steps, buffer_ha=0.4):

@@ -154,6 +154,21 @@ ks_status ks_density(ks_plan* plan, const double* eps, const void* C, int32_t il
 ks_status ks_energy_density(ks_plan* plan, const double* eps, const void* C, int32_t il, int32_t iu,
                             const double* occ, void* edm);
 
+/* Bloch sums X(k) = sum_R X_R exp(i k.R) for every k-point of a plan (paper
+ * Sec. 2, the Bloch-sum equations for H(k) and S(k)); complex collinear plans
+ * only (KS_ERR_NOT_SUPPORTED otherwise).
+ *   nR    number of lattice vectors, 1 <= nR <= 64
+ *   R     DEVICE [nR][3] lattice vectors (Bohr)
+ *   kvec  DEVICE [batch][3] k-points (1/Bohr)
+ *   XR    DEVICE [nR][n][ld_r] real blocks X_R (row-major), ld_r >= n
+ *   Xk    DEVICE [batch][n][ld_k] complex128 output, ld_k >= n
+ * Only the lower triangle is summed; the upper one is written as its conjugate
+ * transpose and the diagonal as its real part, which is X(k) itself when the
+ * set of R is closed under negation with X_-R = X_R^T (then X(k) is
+ * Hermitian).  Argument errors return before any device work. */
+ks_status ks_bloch_sum(ks_plan* plan, int32_t nR, const double* R, const double* kvec, const double* XR,
+                       int32_t ld_r, void* Xk, int32_t ld_k);
+
 /* Adjoint of (rho, E_band) with respect to (H, S): given dL/drho (grad_rho,
  * full, may be NULL for zero) and dL/dE_band (grad_eband, DEVICE scalar or
  * NULL for zero), writes grad_H [batch][order][ld_h] and grad_S [batch][n][ld_s]

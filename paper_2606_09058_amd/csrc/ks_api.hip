@@ -717,6 +717,56 @@ ks_status ks_density(ks_plan* p, const double* eps, const void* C, int32_t il, i
     return KS_OK;
 }
 
+// Bloch sums of the lower triangle: thread (i, j) of row block blockIdx.y
+// accumulates X_R[i][j] exp(i k.R) over R for up to BS_KC k-points at once
+// (blockIdx.z selects the chunk), the phases formed once per workgroup in LDS.
+constexpr int BS_KC = 16;
+constexpr int BS_MAXR = 64;
+__global__ __launch_bounds__(256) void bloch_sum_kernel(int n, int nk, int nR, const double* R, const double* kvec,
+                                                        const double* XR, int ld_r, cplx* Xk, int ld_k) {
+    __shared__ double pc[BS_KC][BS_MAXR], ps[BS_KC][BS_MAXR];
+    const int k0 = blockIdx.z * BS_KC, kc = min(BS_KC, nk - k0);
+    for (int e = threadIdx.x; e < kc * nR; e += blockDim.x) {
+        const int q = e / nR, r = e % nR;
+        const double* kv = kvec + 3L * (k0 + q);
+        const double* rv = R + 3L * r;
+        double sn, cs;
+        sincos(kv[0] * rv[0] + kv[1] * rv[1] + kv[2] * rv[2], &sn, &cs);
+        pc[q][r] = cs;
+        ps[q][r] = sn;
+    }
+    __syncthreads();
+    const int i = blockIdx.y, j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j > i || j >= n) return;
+    double re[BS_KC], im[BS_KC];
+#pragma unroll
+    for (int q = 0; q < BS_KC; ++q) re[q] = im[q] = 0.0;
+    for (int r = 0; r < nR; ++r) {
+        const double x = XR[((long)r * n + i) * ld_r + j];
+#pragma unroll
+        for (int q = 0; q < BS_KC; ++q) {
+            re[q] += x * pc[q][r];
+            im[q] += x * ps[q][r];
+        }
+    }
+    for (int q = 0; q < kc; ++q) Xk[((long)(k0 + q) * n + i) * ld_k + j] = mk(re[q], im[q]);
+}
+
+ks_status ks_bloch_sum(ks_plan* p, int32_t nR, const double* R, const double* kvec, const double* XR,
+                       int32_t ld_r, void* Xk, int32_t ld_k) {
+    if (!p || !R || !kvec || !XR || !Xk || nR < 1) return KS_ERR_INVALID_ARG;
+    const int n = p->d.n, nk = p->d.batch;
+    if (ld_r < n || ld_k < n) return KS_ERR_INVALID_ARG;
+    if (!p->is_c || p->nsp != 1) return KS_ERR_NOT_SUPPORTED;
+    if (nR > BS_MAXR) return KS_ERR_INVALID_ARG;
+    hipStream_t s = p->s;
+    hipLaunchKernelGGL(bloch_sum_kernel, dim3(cdiv(n, 256), n, cdiv(nk, BS_KC)), dim3(256), 0, s, n, nk, nR, R,
+                       kvec, XR, ld_r, (cplx*)Xk, ld_k);
+    mirror_lower<cplx>(s, n, (cplx*)Xk, ld_k, (long)n * ld_k, nk);
+    if (hipPeekAtLastError() != hipSuccess) return KS_ERR_HIP;
+    return KS_OK;
+}
+
 // f_ik eps_ik for the window columns of every matrix of the batch.
 __global__ void edm_weights_kernel(int order, int c0, int ncols, const double* occ, const double* eps, double* fe) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;

@@ -28,7 +28,8 @@ STATUS = {
     8: "KS_ERR_HIP", 9: "KS_ERR_NOT_SUPPORTED",
 }
 
-EXPORTS = ["ks_plan_create", "ks_plan_destroy", "ks_gevd", "ks_density", "ks_energy_density", "ks_density_backward",
+EXPORTS = ["ks_plan_create", "ks_plan_destroy", "ks_gevd", "ks_density", "ks_energy_density", "ks_bloch_sum",
+           "ks_density_backward",
            "ks_plan_get_info", "ks_status_string", "ks_plan_workspace_bytes", "ks_plan_set_profiling",
            "ks_plan_get_profile", "ks_plan_get_graph_stats", "ks_plan_get_tuning", "ks_plan_set_refinement"]
 
@@ -85,6 +86,8 @@ def lib():
         L.ks_density.restype = I
         L.ks_energy_density.argtypes = [P, P, P, I, I, P, P]
         L.ks_energy_density.restype = I
+        L.ks_bloch_sum.argtypes = [P, I, P, P, P, I, P, I]
+        L.ks_bloch_sum.restype = I
         L.ks_density_backward.argtypes = [P, P, P, P, P, D, P, P, P, P]
         L.ks_density_backward.restype = I
         L.ks_plan_get_info.argtypes = [P, ctypes.POINTER(I)]
@@ -208,6 +211,17 @@ class Plan:
         _need(edm, "edm", self.mdtype, self._mshape())
         st = lib().ks_energy_density(self._h, _ptr(eps), _ptr(C), int(il), int(iu), _ptr(occ), _ptr(edm))
         _check(st, "ks_energy_density")
+
+    def bloch_sum(self, R, kvec, XR, Xk):
+        """ks_bloch_sum: Xk[q] = sum_r XR[r] exp(i kvec[q].R[r]) (device tensors; XR real
+        (nR, n, n), Xk complex (batch, n, n) or (n, n) for one k-point)."""
+        nR = int(R.shape[0])
+        _need(R, "R", torch.float64, (nR, 3))
+        _need(kvec, "kvec", torch.float64, (self.batch, 3))
+        _need(XR, "XR", torch.float64, (nR, self.n, self.n))
+        _need(Xk, "Xk", torch.complex128, self._mshape())
+        st = lib().ks_bloch_sum(self._h, nR, _ptr(R), _ptr(kvec), _ptr(XR), self.n, _ptr(Xk), self.n)
+        _check(st, "ks_bloch_sum")
 
     def density_backward(self, eps, C, mu, occ, kT, grad_rho, grad_eband, grad_H, grad_S):
         _need(eps, "eps", torch.float64, self._vshape())

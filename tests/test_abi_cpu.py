@@ -117,6 +117,7 @@ def test_entry_points_reject_null_plan(L):
     assert L.ks_gevd(None, None, None, None, None, 1, 1, 0) == 1
     assert L.ks_density(None, None, None, 1, 1, 1.0, 0.01, None, None, None, None, None) == 1
     assert L.ks_energy_density(None, None, None, 1, 1, None, None) == 1
+    assert L.ks_bloch_sum(None, 1, None, None, None, 1, None, 1) == 1
     assert L.ks_density_backward(None, None, None, None, None, 0.01, None, None, None, None) == 1
     v = ctypes.c_int32(0)
     assert L.ks_plan_get_info(None, ctypes.byref(v)) == 1

@@ -106,6 +106,33 @@ def test_energy_density_vs_oracle(kind):
     assert np.array_equal(E, E.conj().T)
 
 
+def test_bloch_sum_vs_oracle():
+    """ks_bloch_sum for 18 k-points (two passes of the 16-k-point chunk) against
+    the oracle's Bloch sum, for H and S; the output is exactly Hermitian and
+    matches the k-point generator's H(k); real and spinor plans are refused."""
+    announce("bloch sum")
+    kg = (3, 3, 2)
+    rs = I.kpoint_realspace(seed=8, natoms=6, norb=13, kgrid=kg)
+    n, nk = rs["HR"].shape[1], len(rs["k"])
+    plan = ks.Plan(n, batch=nk, complex=True)
+    R, kv = dev(rs["R"]), dev(rs["k"])
+    for X in (rs["HR"], rs["SR"]):
+        out = torch.empty((nk, n, n), dtype=torch.complex128, device="cuda")
+        plan.bloch_sum(R, kv, dev(X), out)
+        plan.check("bloch sum")
+        g = host(out)
+        o = O.bloch_sum(X, rs["R"], rs["k"])
+        assert np.abs(g - o).max() < 1e-13 * np.abs(X).sum(0).max()
+        assert np.array_equal(g, g.conj().transpose(0, 2, 1))
+    p = I.kpoint_batch(seed=8, natoms=6, norb=13, kgrid=kg)
+    plan.bloch_sum(R, kv, dev(rs["HR"]), out)
+    assert np.abs(host(out) - p.H).max() < 1e-13
+    for bad in (ks.Plan(n, batch=nk), ks.Plan(n, batch=nk, complex=True, noncollinear=True)):
+        with pytest.raises(ks.KSError):
+            bad.bloch_sum(R, kv, dev(rs["HR"]), torch.empty(bad._mshape(), dtype=torch.complex128,
+                                                               device="cuda"))
+
+
 def test_kpoint_batch_common_mu():
     announce("kpoint batch")
     p = I.kpoint_batch(natoms=6, norb=13, kgrid=(2, 2, 1))
