@@ -717,14 +717,25 @@ ks_status ks_density(ks_plan* p, const double* eps, const void* C, int32_t il, i
     return KS_OK;
 }
 
-// Bloch sums of the lower triangle: thread (i, j) of row block blockIdx.y
-// accumulates X_R[i][j] exp(i k.R) over R for up to BS_KC k-points at once
-// (blockIdx.z selects the chunk), the phases formed once per workgroup in LDS.
+// Bloch sums over 32x32 tiles of the lower triangle: the workgroup of tile
+// (I, J), I >= J, accumulates X_R[i][j] exp(i k.R) over R for up to BS_KC
+// k-points at once (blockIdx.z selects the chunk; the phases of the chunk are
+// formed once per workgroup in LDS), writes its tile, and writes the mirrored
+// tile X[j][i] = conj(X[i][j]) through an LDS transpose, so that both
+// triangles leave in coalesced rows and every X_R entry is read once per chunk.
 constexpr int BS_KC = 16;
 constexpr int BS_MAXR = 64;
-__global__ __launch_bounds__(256) void bloch_sum_kernel(int n, int nk, int nR, const double* R, const double* kvec,
-                                                        const double* XR, int ld_r, cplx* Xk, int ld_k) {
+constexpr int BS_T = 32;
+__global__ __launch_bounds__(BS_T * BS_T) void bloch_sum_kernel(int n, int nk, int nR, const double* R,
+                                                                const double* kvec, const double* XR, int ld_r,
+                                                                cplx* Xk, int ld_k) {
     __shared__ double pc[BS_KC][BS_MAXR], ps[BS_KC][BS_MAXR];
+    __shared__ cplx tr[2][BS_T][BS_T + 1];
+    const int t = blockIdx.x;
+    int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    while (I * (I + 1) / 2 > t) --I;
+    const int J = t - I * (I + 1) / 2;
     const int k0 = blockIdx.z * BS_KC, kc = min(BS_KC, nk - k0);
     for (int e = threadIdx.x; e < kc * nR; e += blockDim.x) {
         const int q = e / nR, r = e % nR;
@@ -736,20 +747,51 @@ __global__ __launch_bounds__(256) void bloch_sum_kernel(int n, int nk, int nR, c
         ps[q][r] = sn;
     }
     __syncthreads();
-    const int i = blockIdx.y, j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j > i || j >= n) return;
+    const int tx = threadIdx.x % BS_T, ty = threadIdx.x / BS_T;
+    const int i = I * BS_T + ty, j = J * BS_T + tx;
+    const bool in = i < n && j < n && (I > J || tx <= ty);
     double re[BS_KC], im[BS_KC];
 #pragma unroll
     for (int q = 0; q < BS_KC; ++q) re[q] = im[q] = 0.0;
-    for (int r = 0; r < nR; ++r) {
-        const double x = XR[((long)r * n + i) * ld_r + j];
+    if (in) {
+        const double* x = XR + (long)i * ld_r + j;
+        const long sr = (long)n * ld_r;
+        int r = 0;
+        for (; r + 4 <= nR; r += 4) {
+            double xv[4];
 #pragma unroll
-        for (int q = 0; q < BS_KC; ++q) {
-            re[q] += x * pc[q][r];
-            im[q] += x * ps[q][r];
+            for (int u = 0; u < 4; ++u) xv[u] = x[(r + u) * sr];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int q = 0; q < BS_KC; ++q) {
+                    re[q] += xv[u] * pc[q][r + u];
+                    im[q] += xv[u] * ps[q][r + u];
+                }
+        }
+        for (; r < nR; ++r) {
+            const double xv = x[r * sr];
+#pragma unroll
+            for (int q = 0; q < BS_KC; ++q) {
+                re[q] += xv * pc[q][r];
+                im[q] += xv * ps[q][r];
+            }
         }
     }
-    for (int q = 0; q < kc; ++q) Xk[((long)(k0 + q) * n + i) * ld_k + j] = mk(re[q], im[q]);
+    // the mirrored entry this thread writes: row J*32+ty, column I*32+tx
+    const int mi = J * BS_T + ty, mj = I * BS_T + tx;
+    const bool min_ = mi < n && mj < n && (I > J || tx > ty);
+#pragma unroll
+    for (int q = 0; q < BS_KC; ++q) {
+        if (q < kc) {
+            cplx* o = Xk + (long)(k0 + q) * n * ld_k;
+            const cplx v = mk(re[q], i == j ? 0.0 : im[q]);
+            if (in) o[(long)i * ld_k + j] = v;
+            tr[q & 1][ty][tx] = v;
+            __syncthreads();
+            if (min_) o[(long)mi * ld_k + mj] = conj_(tr[q & 1][tx][ty]);
+        }
+    }
 }
 
 ks_status ks_bloch_sum(ks_plan* p, int32_t nR, const double* R, const double* kvec, const double* XR,
@@ -760,9 +802,9 @@ ks_status ks_bloch_sum(ks_plan* p, int32_t nR, const double* R, const double* kv
     if (!p->is_c || p->nsp != 1) return KS_ERR_NOT_SUPPORTED;
     if (nR > BS_MAXR) return KS_ERR_INVALID_ARG;
     hipStream_t s = p->s;
-    hipLaunchKernelGGL(bloch_sum_kernel, dim3(cdiv(n, 256), n, cdiv(nk, BS_KC)), dim3(256), 0, s, n, nk, nR, R,
-                       kvec, XR, ld_r, (cplx*)Xk, ld_k);
-    mirror_lower<cplx>(s, n, (cplx*)Xk, ld_k, (long)n * ld_k, nk);
+    const int nt = cdiv(n, BS_T);
+    hipLaunchKernelGGL(bloch_sum_kernel, dim3(nt * (nt + 1) / 2, 1, cdiv(nk, BS_KC)), dim3(BS_T * BS_T), 0, s, n, nk,
+                       nR, R, kvec, XR, ld_r, (cplx*)Xk, ld_k);
     if (hipPeekAtLastError() != hipSuccess) return KS_ERR_HIP;
     return KS_OK;
 }
