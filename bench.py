@@ -95,6 +95,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the FP64-vs-mixed comparison on the occupied window")
+    ap.add_argument("--no-lowdin", action="store_true", help="skip the Loewdin-route comparison")
     ap.add_argument("--graph", action="store_true", help="plan with KS_PLAN_GRAPH (capture once, replay)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -240,6 +241,8 @@ def main():
         out["ms_per_kpoint"] = ms / p.batch
     if args.workload == "kpoints16x1300":
         out["bloch_sum"] = bloch_sum_timing(plan, p, stream, args.steps)
+    if not args.no_lowdin:
+        out["lowdin_route"] = lowdin_timing(p, H, S, eps, rho, stream, args.steps)
     if not args.no_mixed:
         out["precision_comparison"] = compare_precisions(p, H, S, eps, mu, args.steps)
     if not args.no_cpu_baseline:
@@ -285,6 +288,53 @@ def bloch_sum_timing(plan, p, stream, steps):
     dH = float((Hk - torch.from_numpy(p.H).cuda()).abs().max().item())
     return {"ms_per_matrix_set": ms, "lattice_vectors": nR, "kpoints": nk, "GB_per_s": nbytes / (ms * 1e-3) / 1e9,
             "max_abs_diff_vs_generator_H": dH}
+
+
+def lowdin_timing(p, H, S, eps_ref, rho_ref, stream, steps):
+    """The paper's own route (KS_PLAN_LOWDIN: eigen-decomposition of S, V = U s^-1/2,
+    H' = V^H H V, C = V C') on the same input, all eigenvectors, outside the
+    timed steps: first-cycle solves (S decomposed) and later-cycle solves (V
+    reused), with the phase times and the differences from the Cholesky route."""
+    import numpy as np
+    import torch
+    from paper_2606_09058_amd import ks
+    plan = ks.Plan(p.n, batch=p.batch, complex=np.iscomplexobj(p.H), noncollinear=p.nsp == 2, stream=stream,
+                   flags=ks.KS_PLAN_AUTOTUNE | ks.KS_PLAN_LOWDIN)
+    eps = torch.empty_like(eps_ref)
+    C = torch.empty_like(rho_ref)
+    rho = torch.empty_like(rho_ref)
+    mu = torch.empty(1, dtype=torch.float64, device="cuda")
+    eband = torch.empty(1, dtype=torch.float64, device="cuda")
+
+    def step(reuse):
+        plan.gevd(H, S, eps, C, reuse_s=reuse)
+        plan.density(eps, C, p.n_electrons, p.kT, rho, mu, eband, kweights=p.weights)
+
+    with torch.cuda.stream(stream):
+        step(False)
+    torch.cuda.synchronize()
+    plan.check("lowdin warm-up")
+    res = {}
+    for name, reuse in (("first_cycle", False), ("later_cycles", True)):
+        plan.get_profile()
+        plan.set_profiling(True, 1 << 30)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            step(reuse)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        prof = plan.get_profile()
+        plan.set_profiling(False)
+        plan.check("lowdin " + name)
+        ph = phase_dict(prof, steps)
+        ph["overlap_eig_and_V"] = ph.pop("cholesky")
+        res[name] = {"s_per_solve": e0.elapsed_time(e1) / steps / 1e3,
+                     "phases_ms": {k: v for k, v in ph.items() if v > 0}}
+    res["max_abs_eps_diff_vs_cholesky"] = float((eps - eps_ref).abs().max().item())
+    res["max_abs_rho_diff_vs_cholesky"] = float((rho - rho_ref).abs().max().item())
+    return res
 
 
 def compare_precisions(p, H, S, eps_all, mu, steps, buffer_ha=0.4):

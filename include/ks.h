@@ -82,7 +82,20 @@ enum { KS_PLAN_GRAPH = 1u,
         * plan's own order and batch, and keep the fastest (synchronous, a few
         * milliseconds; without the flag a fixed default is used).  The choice
         * changes only the grouping of partial sums, not the algorithm. */
-       KS_PLAN_AUTOTUNE = 2u };
+       KS_PLAN_AUTOTUNE = 2u,
+       /* KS_PLAN_LOWDIN: ks_gevd takes the paper's own route (Sec. 3.1 Parts
+        * 2-1..2-5, Sec. 3.2 Parts 3-1..3-6) instead of the Cholesky one:
+        * U^H S U = s by the same Hermitian eigensolver (tridiagonalisation,
+        * divide and conquer, back-transform) on S, V = U s^-1/2,
+        * H' = V_NC^H H V_NC with V_NC = diag(V, V), H' C' = C' eps, C = V_NC C'.
+        * KS_REUSE_S keeps V (cycles 2 onwards skip Parts 2-1 and 2-2).  A
+        * non-positive eigenvalue of S gives KS_ERR_NOT_POSDEF with info = the
+        * number of eigenvalues <= 0.  Spinor plans hold a second, collinear
+        * plan of order n for the eigenproblem of S (its workspace is included
+        * in ks_plan_workspace_bytes).  Not with KS_MIXED (KS_ERR_NOT_SUPPORTED).
+        * Results equal the Cholesky route's up to rounding: eps, rho and the
+        * occupied subspace do not depend on the S-orthonormal basis. */
+       KS_PLAN_LOWDIN = 4u };
 enum { KS_REUSE_S = 1u };                            /* ks_gevd flags                */
 
 typedef struct ks_plan ks_plan; /* opaque: workspace, cached Cholesky factor, info */
@@ -121,7 +134,8 @@ void ks_plan_destroy(ks_plan* plan);
  *   flags   KS_REUSE_S: S is unchanged since the last call on this plan, reuse
  *           its cached Cholesky factor (the self-consistent cycle after the
  *           first, paper Sec. 5, cycles 2 onwards reuse the overlap work).
- * Device failures: KS_ERR_NOT_POSDEF (info = failing column, 1-based),
+ * Device failures: KS_ERR_NOT_POSDEF (info = failing column, 1-based; under
+ * KS_PLAN_LOWDIN the number of eigenvalues of S that are <= 0),
  * KS_ERR_NONFINITE, KS_ERR_NO_CONVERGENCE via ks_plan_get_info. */
 ks_status ks_gevd(ks_plan* plan, const void* H, const void* S, double* eps, void* C,
                   int32_t il, int32_t iu, uint32_t flags);

@@ -74,6 +74,11 @@ struct ks_plan {
     void* mP2 = nullptr;       // order x order   FP32 work
     double* theta = nullptr;   // order           Ritz values
     ks_plan* rr = nullptr;     // order-M plan of the Rayleigh-Ritz problem
+    // KS_PLAN_LOWDIN: V = U s^-1/2 lives in L (batch x n x n); sev holds the
+    // eigenvalues s of S; spinor plans solve the order-n eigenproblem of S on
+    // the collinear plan ov (collinear plans use their own buffers)
+    double* sev = nullptr;     // batch x n
+    ks_plan* ov = nullptr;
     int mixed_sweeps = 2;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -106,7 +111,7 @@ bool desc_valid(const ks_plan_desc* d) {
     long order = (long)d->n * (d->spin == KS_NONCOLLINEAR ? 2 : 1);
     if (order > 60000) return false;
     if (d->ld_h < order || d->ld_s < d->n) return false;
-    if (d->flags & ~(uint32_t)(KS_PLAN_GRAPH | KS_PLAN_AUTOTUNE)) return false;
+    if (d->flags & ~(uint32_t)(KS_PLAN_GRAPH | KS_PLAN_AUTOTUNE | KS_PLAN_LOWDIN)) return false;
     return true;
 }
 
@@ -114,7 +119,24 @@ ks_status desc_supported(const ks_plan_desc* d) {
     if ((d->flags & KS_PLAN_GRAPH) && d->stream == nullptr) return KS_ERR_NOT_SUPPORTED;  // no capture there
     if (d->spin == KS_NONCOLLINEAR && d->dtype != KS_COMPLEX128) return KS_ERR_NOT_SUPPORTED;
     if (d->batch > MAX_KW) return KS_ERR_NOT_SUPPORTED;
+    if ((d->flags & KS_PLAN_LOWDIN) && d->precision == KS_MIXED) return KS_ERR_NOT_SUPPORTED;
     return KS_OK;
+}
+
+// The order-n collinear plan on which a spinor KS_PLAN_LOWDIN plan solves the
+// eigenproblem of S (same batch, type, stream and tuning request).
+ks_plan_desc lowdin_overlap_desc(const ks_plan_desc* d) {
+    ks_plan_desc c{};
+    c.n = d->n;
+    c.batch = d->batch;
+    c.dtype = d->dtype;
+    c.spin = KS_COLLINEAR;
+    c.precision = KS_FP64;
+    c.ld_h = d->n;
+    c.ld_s = d->n;
+    c.stream = d->stream;
+    c.flags = d->flags & KS_PLAN_AUTOTUNE;
+    return c;
 }
 
 // Lays out (or, with plan == nullptr, only measures) the workspace.
@@ -191,10 +213,12 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
         oVWl = L.take(B * hVW * es32);
         oWVl = L.take(B * hVW * es32);
     }
+    const size_t oSev = (d->flags & KS_PLAN_LOWDIN) ? L.take(B * n * 8) : 0;
     size_t total = L.off;
     if (!p) return total;
     char* b = p->base;
     p->L = b + oL;
+    if (d->flags & KS_PLAN_LOWDIN) p->sev = (double*)(b + oSev);
     p->Li = b + oLi;
     p->A = b + oA;
     p->W = b + oW;
@@ -464,6 +488,91 @@ ks_status gevd_mixed(ks_plan* p, const T* H, double* eps, T* C, int il, int iu) 
     return KS_OK;
 }
 
+// V = U s^-1/2 (Part 2-2 / 3-2): column j of the eigenvectors of S scaled by
+// 1/sqrt(s_j), for every matrix of the batch.  s ascends, so the number of
+// non-positive s_j is the index of the last one; that count is the detail of
+// KS_ERR_NOT_POSDEF.
+template <typename T>
+__global__ void lowdin_v_kernel(int n, const T* U, const double* sv, T* V, int* info) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
+    if (j >= n) return;
+    const long b = blockIdx.z;
+    const double* sb = sv + b * n;
+    const double sj = sb[j];
+    const long o = b * n * n + (long)i * n + j;
+    if (!(sj > 0.0)) {  // flagged; the column is zeroed so that the rest of the solve stays finite
+        if (i == 0 && (j == n - 1 || sb[j + 1] > 0.0)) set_info(info, KS_ERR_NOT_POSDEF, j + 1);
+        V[o] = zero_<T>();
+        return;
+    }
+    V[o] = U[o] * (1.0 / sqrt(sj));
+}
+
+// Loewdin route (Sec. 3.1 Parts 2-1..2-5; Sec. 3.2 Parts 3-1..3-6): eigenvectors
+// U and eigenvalues s of S (Hermitian eigensolve of order n: the same
+// tridiagonalisation, divide and conquer and back-transform as the main solve,
+// on plan q); V = U s^-1/2; H' = V_NC^H H V_NC with V_NC = diag(V, V);
+// H' C' = C' eps; C = V_NC C'.  Under KS_REUSE_S the V of the previous call is
+// kept (the paper's SCF cycles 2 onwards skip Parts 2-1 and 2-2).
+template <typename T>
+ks_status gevd_lowdin(ks_plan* p, const T* H, const T* S, double* eps, T* C, int il, int iu, uint32_t flags) {
+    hipStream_t s = p->s;
+    const int n = p->d.n, nsp = p->nsp, order = p->order, B = p->d.batch, ldh = p->d.ld_h, lds = p->d.ld_s;
+    const long sA = (long)order * order, sV = (long)n * n, sH = (long)order * ldh;
+    T* A = (T*)p->A;
+    T* W = (T*)p->W;
+    T* V = (T*)p->L;
+    Prof& pf = p->prof;
+    if (!(flags & KS_REUSE_S)) {
+        hipEvent_t e = pf.begin();
+        ks_plan* q = p->ov ? p->ov : p;  // an order-n plan
+        T* Aq = (T*)q->A;
+        T* Wq = (T*)q->W;
+        HetrdWork<T>& qh = *reinterpret_cast<HetrdWork<T>*>(is_cplx<T>::value ? (void*)&q->hc : (void*)&q->hr);
+        BacktrWork<T>& qb = *reinterpret_cast<BacktrWork<T>*>(is_cplx<T>::value ? (void*)&q->bc : (void*)&q->br);
+        herm_complete<T>(s, n, S, lds, (long)n * lds, Aq, n, sV, B, p->info);
+        hetrd<T, T>(s, n, Aq, n, sV, B, q->dv, q->ev, (T*)q->tau, Wq, qh);
+        stedc(s, q->tree, B, q->dv, q->ev, p->sev, q->Z, q->Z2, q->U, q->Qp, q->dc, p->info);
+        load_z<T>(s, n, B, n, q->Z, 0, Aq, n, sV);
+        backtransform_prepare<T>(s, n, B, Wq, (T*)q->tau, qb);
+        backtransform_q<T>(s, n, B, Wq, n, Aq, n, sV, qb);
+        hipLaunchKernelGGL(lowdin_v_kernel<T>, dim3(cdiv(n, 256), n, B), dim3(256), 0, s, n, (const T*)Aq,
+                           (const double*)p->sev, V, p->info);
+        pf.end(KS_PHASE_CHOLESKY, e);
+        p->have_L = true;
+    }
+    const int ncols = iu - il + 1;
+    hipEvent_t e = pf.begin();
+    // H' = V_NC^H (H V_NC): the full H in A, W = A V_NC, then the lower triangle
+    // of H' (the part the tridiagonalisation reads) into A
+    herm_complete<T>(s, order, H, ldh, sH, A, order, sA, B, p->info);
+    for (int b = 0; b < nsp; ++b)
+        gemm<T>(s, OP_N, OP_N, order, n, n, 1.0, A + b * n, order, sA, V, n, sV, 0.0, W + b * n, order, sA, B);
+    for (int b = 0; b < nsp; ++b)
+        gemm<T>(s, OP_C, OP_N, n, order, n, 1.0, V, n, sV, W + (long)b * n * order, order, sA, 0.0,
+                A + (long)b * n * order, order, sA, B, nullptr, 0, b == 0 ? UPLO_LOWER : UPLO_FULL);
+    pf.end(KS_PHASE_REDUCE, e);
+    e = pf.begin();
+    hetrd<T, T>(s, order, A, order, sA, B, p->dv, p->ev, (T*)p->tau, W,
+                *reinterpret_cast<HetrdWork<T>*>(is_cplx<T>::value ? (void*)&p->hc : (void*)&p->hr));
+    pf.end(KS_PHASE_TRIDIAG, e);
+    e = pf.begin();
+    stedc(s, p->tree, B, p->dv, p->ev, eps, p->Z, p->Z2, p->U, p->Qp, p->dc, p->info);
+    pf.end(KS_PHASE_DC, e);
+    e = pf.begin();
+    BacktrWork<T>& bw = *reinterpret_cast<BacktrWork<T>*>(is_cplx<T>::value ? (void*)&p->bc : (void*)&p->br);
+    load_z<T>(s, order, B, ncols, p->Z, il - 1, A, ncols, sA);
+    backtransform_prepare<T>(s, order, B, W, (T*)p->tau, bw);
+    backtransform_q<T>(s, order, B, W, ncols, A, ncols, sA, bw);
+    // C_sigma = V C'_sigma per spin block
+    for (int b = 0; b < nsp; ++b)
+        gemm<T>(s, OP_N, OP_N, n, ncols, n, 1.0, V, n, sV, A + (long)b * n * ncols, ncols, sA, 0.0,
+                C + (long)b * n * ldh, ldh, sH, B);
+    pf.end(KS_PHASE_BACKTR, e);
+    if (hipPeekAtLastError() != hipSuccess) return KS_ERR_HIP;
+    return KS_OK;
+}
+
 template <typename T>
 ks_status gevd_impl(ks_plan* p, const T* H, const T* S, double* eps, T* C, int il, int iu,
                     uint32_t flags) {
@@ -478,6 +587,7 @@ ks_status gevd_impl(ks_plan* p, const T* H, const T* S, double* eps, T* C, int i
     BacktrWork<T>& bw = *reinterpret_cast<BacktrWork<T>*>(is_cplx<T>::value ? (void*)&p->bc : (void*)&p->br);
     Prof& pf = p->prof;
     T* Li = (T*)p->Li;
+    if (p->d.flags & KS_PLAN_LOWDIN) return gevd_lowdin<T>(p, H, S, eps, C, il, iu, flags);
     if (!(flags & KS_REUSE_S)) {
         hipEvent_t e = pf.begin();
         herm_complete<T>(s, n, S, lds, (long)n * lds, L, n, (long)n * n, B, p->info);
@@ -534,7 +644,12 @@ const char* ks_status_string(ks_status st) {
 
 uint64_t ks_plan_workspace_bytes(const ks_plan_desc* d) {
     if (!desc_valid(d)) return 0;
-    return (uint64_t)layout(d, nullptr);
+    uint64_t bytes = layout(d, nullptr);
+    if ((d->flags & KS_PLAN_LOWDIN) && d->spin == KS_NONCOLLINEAR) {
+        ks_plan_desc c = lowdin_overlap_desc(d);
+        bytes += layout(&c, nullptr);
+    }
+    return bytes;
 }
 
 ks_status ks_plan_create(const ks_plan_desc* d, ks_plan** out) {
@@ -566,6 +681,14 @@ ks_status ks_plan_create(const ks_plan_desc* d, ks_plan** out) {
         (void)hipFree(p->base);
         delete p;
         return KS_ERR_HIP;
+    }
+    if ((d->flags & KS_PLAN_LOWDIN) && p->nsp == 2) {
+        ks_plan_desc c = lowdin_overlap_desc(d);
+        ks_status st = ks_plan_create(&c, &p->ov);
+        if (st != KS_OK) {
+            ks_plan_destroy(p);
+            return st;
+        }
     }
     p->tuning.tiles_per_workgroup = HETRD_SCH;
     p->tuning.nseg = 1;
@@ -605,6 +728,7 @@ void ks_plan_destroy(ks_plan* p) {
     (void)hipStreamSynchronize(p->s);
     graph_release(p);
     if (p->rr) ks_plan_destroy(p->rr);
+    if (p->ov) ks_plan_destroy(p->ov);
     if (p->base) (void)hipFree(p->base);
     if (p->adj) (void)hipFree(p->adj);
     delete p;

@@ -67,6 +67,8 @@ def test_plan_create_unsupported_combinations(L):
     assert L.ks_plan_create(ctypes.byref(desc(batch=65)), ctypes.byref(h)) == 9
     # graph capture needs a stream of its own (the legacy default stream cannot be captured)
     assert L.ks_plan_create(ctypes.byref(desc(flags=ks.KS_PLAN_GRAPH)), ctypes.byref(h)) == 9
+    # the Loewdin route is FP64 only
+    assert L.ks_plan_create(ctypes.byref(desc(prec=ks.KS_MIXED, flags=ks.KS_PLAN_LOWDIN)), ctypes.byref(h)) == 9
     assert not h.value
     assert L.ks_plan_create(ctypes.byref(desc()), None) == 1
     assert L.ks_plan_create(None, ctypes.byref(h)) == 1
@@ -101,8 +103,23 @@ def test_mixed_precision_workspace(L):
     assert 1.5 < bmx / b64 < 3.5
 
 
+def test_lowdin_workspace(L):
+    """KS_PLAN_LOWDIN keeps V in the Cholesky factor's slot and adds the
+    eigenvalues of S; a spinor plan adds a collinear order-n plan for the
+    eigenproblem of S."""
+    b = L.ks_plan_workspace_bytes(ctypes.byref(desc(n=1000)))
+    bl = L.ks_plan_workspace_bytes(ctypes.byref(desc(n=1000, flags=ks.KS_PLAN_LOWDIN)))
+    assert 0 < bl - b <= 1000 * 8 + 256
+    bn = L.ks_plan_workspace_bytes(ctypes.byref(desc(n=500, spin=1, dtype=1)))
+    bc = L.ks_plan_workspace_bytes(ctypes.byref(desc(n=500, dtype=1)))
+    bnl = L.ks_plan_workspace_bytes(ctypes.byref(desc(n=500, spin=1, dtype=1, flags=ks.KS_PLAN_LOWDIN)))
+    assert 0 < bnl - bn - bc <= 500 * 8 + 256
+
+
 def test_plan_flags_accepted(L):
     d = desc(flags=ks.KS_PLAN_GRAPH | ks.KS_PLAN_AUTOTUNE)
+    assert L.ks_plan_workspace_bytes(ctypes.byref(d)) > 0
+    d = desc(flags=ks.KS_PLAN_GRAPH | ks.KS_PLAN_AUTOTUNE | ks.KS_PLAN_LOWDIN)
     assert L.ks_plan_workspace_bytes(ctypes.byref(d)) > 0
 
 
