@@ -30,11 +30,13 @@ constexpr int CB = 64;
 //   c <= j:  Y[i][c] -= S[i][j] Y[j][c] / d_j            (inverse)
 // with the columns of S and rows of Y left unscaled until the end
 // (L[i][j] = S[i][j] / sqrt(d_j), X[i][c] = Y[i][c] / sqrt(d_i)).  One wavefront
-// per row (rows j+1+w, j+5+w, ...), one lane per column: no index division.
+// per row (rows j+1+w, j+1+w+LW, ... for LW = 16 wavefronts), one lane per
+// column: no index division, four rows per thread and step.
 // A non-positive or non-finite pivot records the global 1-based column
 // col0 + j + 1 and continues with pivot 1.
+constexpr int LW = 16;  // wavefronts of the leaf kernel
 template <typename T>
-__global__ __launch_bounds__(256) void potrf_inv_leaf_kernel(int nb, T* A, int lda, long sa, T* D, int ldd,
+__global__ __launch_bounds__(64 * LW) void potrf_inv_leaf_kernel(int nb, T* A, int lda, long sa, T* D, int ldd,
                                                              long sd, int col0, int* info) {
     __shared__ T sL[CB][CB + 1];
     __shared__ T sY[CB][CB + 1];
@@ -42,7 +44,7 @@ __global__ __launch_bounds__(256) void potrf_inv_leaf_kernel(int nb, T* A, int l
     A += blockIdx.x * sa;
     D += blockIdx.x * sd;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    for (int i = w; i < CB; i += 4) {
+    for (int i = w; i < CB; i += LW) {
         sL[i][lane] = (i < nb && lane <= i) ? A[(long)i * lda + lane] : zero_<T>();
         sY[i][lane] = (i == lane) ? from_re<T>(1.0) : zero_<T>();
     }
@@ -60,11 +62,11 @@ __global__ __launch_bounds__(256) void potrf_inv_leaf_kernel(int nb, T* A, int l
         const T scj = conj_(sL[c][j]) * inv_d;  // factor part (c > j)
         const T ycj = sY[j][c] * inv_d;          // inverse part (c <= j)
         // all reads of this step first (they cannot alias its writes), then the writes
-        constexpr int RPW = CB / 4;  // rows per wavefront
+        constexpr int RPW = CB / LW;  // rows per wavefront
         T sij[RPW], cur[RPW];
 #pragma unroll
         for (int q = 0; q < RPW; ++q) {
-            const int i = j + 1 + w + 4 * q;
+            const int i = j + 1 + w + LW * q;
             if (i < nb) {
                 sij[q] = sL[i][j];
                 cur[q] = (c > j) ? sL[i][c] : sY[i][c];
@@ -72,7 +74,7 @@ __global__ __launch_bounds__(256) void potrf_inv_leaf_kernel(int nb, T* A, int l
         }
 #pragma unroll
         for (int q = 0; q < RPW; ++q) {
-            const int i = j + 1 + w + 4 * q;
+            const int i = j + 1 + w + LW * q;
             if (i < nb) {
                 if (c > j && c <= i) sL[i][c] = cur[q] - sij[q] * scj;
                 else if (c <= j) sY[i][c] = cur[q] - sij[q] * ycj;
@@ -80,7 +82,7 @@ __global__ __launch_bounds__(256) void potrf_inv_leaf_kernel(int nb, T* A, int l
         }
         __syncthreads();
     }
-    for (int i = w; i < nb; i += 4) {
+    for (int i = w; i < nb; i += LW) {
         const int c = lane;
         if (c < nb) {
             T lv = zero_<T>(), xv = zero_<T>();
@@ -106,7 +108,7 @@ template <typename T>
 static void potrf_inv_rec(hipStream_t s, int n, T* L, int ldl, long sl, T* Li, int ldi, long si, T* Tw, long st,
                           int batch, int col0, int* info) {
     if (n <= CB) {
-        hipLaunchKernelGGL((potrf_inv_leaf_kernel<T>), dim3(batch), dim3(256), 0, s, n, L, ldl, sl, Li, ldi, si,
+        hipLaunchKernelGGL((potrf_inv_leaf_kernel<T>), dim3(batch), dim3(64 * LW), 0, s, n, L, ldl, sl, Li, ldi, si,
                            col0, info);
         return;
     }
