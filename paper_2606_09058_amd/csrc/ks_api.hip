@@ -699,10 +699,10 @@ ks_status ks_plan_create(const ks_plan_desc* d, ks_plan** out) {
         const long sA = (long)p->order * p->order;
         if (p->is_c)
             tu.ncand = hetrd_tune<cplx>(p->s, p->order, (cplx*)p->A, p->order, sA, d->batch, p->dv, p->ev,
-                                        (cplx*)p->tau, p->hc, tu.cand, tu.ms, 3, tu.seg_first, tu.seg_tiles);
+                                        (cplx*)p->tau, p->hc, tu.cand, tu.ms, 8, tu.seg_first, tu.seg_tiles);
         else
             tu.ncand = hetrd_tune<double>(p->s, p->order, (double*)p->A, p->order, sA, d->batch, p->dv, p->ev,
-                                          (double*)p->tau, p->hr, tu.cand, tu.ms, 3, tu.seg_first, tu.seg_tiles);
+                                          (double*)p->tau, p->hr, tu.cand, tu.ms, 8, tu.seg_first, tu.seg_tiles);
         int best = 0;
         for (int c = 1; c < tu.ncand; ++c)
             if (tu.ms[c] < tu.ms[best]) best = c;

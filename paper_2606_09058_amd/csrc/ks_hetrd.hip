@@ -723,23 +723,32 @@ int hetrd_tune(hipStream_t s, int n, T* A, int lda, long sA, int batch, double* 
         (void)hipEventDestroy(e0);
         return 0;
     }
+    // every (candidate, segment) pair is timed in TUNE_ROUNDS interleaved
+    // rounds of `reps` launches and keeps its fastest round, so that a slow
+    // round (clock ramp, another process) does not decide the choice
+    constexpr int TUNE_ROUNDS = 3;
     float per[4][NK];
+    for (int c = 0; c < nc; ++c)
+        for (int q = 0; q < NK; ++q) per[c][q] = 3.0e38f;
+    for (int round = 0; round < TUNE_ROUNDS; ++round)
+        for (int q = 0; q < NK; ++q)
+            for (int c0 = 0; c0 < nc; ++c0) {
+                const int c = (c0 + round) % nc;
+                const int k = ks_[q];
+                const int nA = cdiv(n - k, WC_ROWS);
+                symv_launch<T, T>(s, cand[c], n, k, 0, A, lda, sA, batch, nA, w);  // warm
+                (void)hipEventRecord(e0, s);
+                for (int r = 0; r < reps; ++r)
+                    symv_launch<T, T>(s, cand[c], n, k, 0, A, lda, sA, batch, nA, w);
+                (void)hipEventRecord(e1, s);
+                (void)hipEventSynchronize(e1);
+                float t = 0.f;
+                (void)hipEventElapsedTime(&t, e0, e1);
+                per[c][q] = std::min(per[c][q], t);
+            }
     for (int c = 0; c < nc; ++c) {
         float tot = 0.f;
-        for (int q = 0; q < NK; ++q) {
-            const int k = ks_[q];
-            const int nA = cdiv(n - k, WC_ROWS);
-            symv_launch<T, T>(s, cand[c], n, k, 0, A, lda, sA, batch, nA, w);  // warm
-            (void)hipEventRecord(e0, s);
-            for (int r = 0; r < reps; ++r)
-                symv_launch<T, T>(s, cand[c], n, k, 0, A, lda, sA, batch, nA, w);
-            (void)hipEventRecord(e1, s);
-            (void)hipEventSynchronize(e1);
-            float t = 0.f;
-            (void)hipEventElapsedTime(&t, e0, e1);
-            per[c][q] = t;
-            tot += t;
-        }
+        for (int q = 0; q < NK; ++q) tot += per[c][q];
         ms[c] = tot;
     }
     for (int q = 0; q < NK; ++q) {
