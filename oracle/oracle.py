@@ -12,6 +12,9 @@ and follows the paper's definitions:
                        Sec. 3.2) by Cholesky + cyclic Jacobi,
 * ``gevd_lowdin``   -- the same problem by the Loewdin route of Sec. 3.1
                        (Parts 2-1..2-5) / Sec. 3.2 (Parts 3-1..3-6),
+* ``gevd_canonical``-- the Loewdin route with the eigenvectors of S whose
+                       eigenvalue is at most tau * max(s) left out (canonical
+                       orthogonalisation of an overcomplete basis),
 * ``fermi``         -- occupations and the chemical potential by bisection on
                        the electron count (Part 3 of Sec. 3.1),
 * ``density``       -- rho = C f C^H (Sec. 2 density matrix, conjugated),
@@ -191,6 +194,33 @@ def gevd(H, S, nsp=1, nthreads=0, route="cholesky"):
 
 def gevd_lowdin(H, S, nsp=1, nthreads=0):
     return gevd(H, S, nsp=nsp, nthreads=nthreads, route="lowdin")
+
+
+def gevd_canonical(H, S, tau, nsp=1, nthreads=0):
+    """The Loewdin route (Sec. 3.1 Parts 2-1..2-5, Sec. 3.2 Parts 3-1..3-6) on
+    the eigenvectors of S that are kept: U^H S U = s (ascending), keep the
+    columns with s_j > tau * max(s), V = U_keep s_keep^-1/2, V_NC = diag(V, V),
+    H' = V_NC^H H V_NC, H' C' = C' eps, C = V_NC C'.  With tau = 0 every s_j
+    must be positive.  H and S in full storage.
+
+    Returns (eps ascending (nsp*m,), C (order, nsp*m), m = number kept)."""
+    dt = np.complex128 if (np.iscomplexobj(H) or np.iscomplexobj(S)) else np.float64
+    H = _c(H, dt)
+    S = _c(S, dt)
+    n = S.shape[0]
+    assert H.shape == (nsp * n, nsp * n)
+    s, U, _ = jacobi(S, nthreads=nthreads)
+    if not s[-1] > 0.0:
+        raise OracleError("S has no positive eigenvalue")
+    keep = s > tau * s[-1]
+    if tau == 0.0 and not keep.all():
+        raise OracleError("S not positive definite: %d eigenvalues <= 0" % int((~keep).sum()))
+    V = U[:, keep] / np.sqrt(s[keep])
+    VN = np.kron(np.eye(nsp), V)
+    Hp = VN.conj().T @ H @ VN
+    Hp = 0.5 * (Hp + Hp.conj().T)
+    eps, Cp, _ = jacobi(Hp, nthreads=nthreads)
+    return eps, VN @ Cp, int(keep.sum())
 
 
 def fermi(eps, ne, kT, g, wk=None):

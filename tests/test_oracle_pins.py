@@ -238,6 +238,54 @@ def test_gevd_invariants_and_lowdin_route(cplx, nsp):
     assert np.abs(O.density(C, occ) - O.density(C2, occ)).max() < 1e-10
 
 
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("nsp", [1, 2])
+def test_canonical_route_keeps_everything_for_a_definite_overlap(cplx, nsp):
+    """With no eigenvalue of S under the cutoff the canonical route is the
+    Loewdin route: the same eigenvalues and density as the Cholesky route."""
+    rng = np.random.default_rng(31)
+    n = 20
+    cp = cplx or nsp == 2
+    H = herm(rng, n * nsp, cp)
+    S = spd(rng, n, cp)
+    eps, C = O.gevd(H, S, nsp=nsp)
+    e2, C2, m = O.gevd_canonical(H, S, 1e-12, nsp=nsp)
+    assert m == n
+    assert np.abs(eps - e2).max() < 1e-11
+    occ = np.where(np.arange(n * nsp) < n // 2, 1.0, 0.0)
+    assert np.abs(O.density(C, occ) - O.density(C2, occ)).max() < 1e-10
+    with pytest.raises(O.OracleError):
+        O.gevd_canonical(H, -S, 0.0, nsp=nsp)
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("nsp", [1, 2])
+def test_canonical_route_on_an_overcomplete_basis(cplx, nsp):
+    """n basis functions spanning only m < n dimensions: chi = B phi with phi
+    orthonormal, S = B B^H (rank m), H = B_NC h B_NC^H.  On span(B) the
+    problem is h z = eps z (with c = B G^-1 z, G = B^H B), so the route must
+    keep m eigenvectors of S per spin block, return eig(h) (LAPACK), and give
+    rho = B_NC G_NC^-1 (Z f Z^H) G_NC^-1 B_NC^H."""
+    rng = np.random.default_rng(32)
+    n, m = 26, 19
+    cp = cplx or nsp == 2
+    B = rng.normal(size=(n, m)) + (1j * rng.normal(size=(n, m)) if cp else 0)
+    h = herm(rng, m * nsp, cp)
+    BN = np.kron(np.eye(nsp), B)
+    S = B @ B.conj().T
+    H = BN @ h @ BN.conj().T
+    eps, C, keep = O.gevd_canonical(H, S, 1e-10, nsp=nsp)
+    assert keep == m
+    w, Z = np.linalg.eigh(h)
+    assert np.abs(eps - w).max() < 1e-9 * max(1.0, np.abs(w).max())
+    SN = np.kron(np.eye(nsp), S)
+    assert np.abs(C.conj().T @ SN @ C - np.eye(m * nsp)).max() < 1e-9
+    f = np.where(np.arange(m * nsp) < (m * nsp) // 3, 1.0, 0.0)
+    GNi = np.linalg.inv(BN.conj().T @ BN)
+    ref = BN @ GNi @ (Z * f) @ Z.conj().T @ GNi @ BN.conj().T
+    assert np.abs(O.density(C, f) - ref).max() < 1e-9 * max(1.0, np.abs(ref).max())
+
+
 def test_gevd_reads_lower_triangle_only():
     rng = np.random.default_rng(8)
     H = herm(rng, 12, True)
