@@ -251,6 +251,26 @@ ks_status ks_plan_get_tuning(ks_plan* plan, ks_tuning* out);
  * KS_ERR_INVALID_ARG outside the range, KS_ERR_NOT_SUPPORTED on an FP64 plan. */
 ks_status ks_plan_set_refinement(ks_plan* plan, int32_t sweeps);
 
+/* KS_PLAN_LOWDIN plans: canonical orthogonalisation of an overcomplete basis
+ * (the Loewdin route with the eigenvectors of S whose eigenvalue s_j is at
+ * most tau * max(s) left out, so that H' is solved on the span of the rest).
+ * 0 <= tau < 1; tau = 0 (the default) keeps every s_j and requires all of
+ * them positive, as in the paper.  With tau > 0 the dropped directions stay
+ * in the fixed-order solve as placeholders: per matrix, the last
+ * nsp * (n - nkeep) eigenvalues all equal sigma = 2 |H'|_F + 1 (above every
+ * kept one), their eigenvectors are zero and their occupation is zero; the
+ * caller reads nkeep with ks_plan_get_overlap_rank.  Takes effect at the next
+ * ks_gevd that decomposes S (not under KS_REUSE_S).  Host-only;
+ * KS_ERR_INVALID_ARG outside the range, KS_ERR_NOT_SUPPORTED on a plan
+ * without KS_PLAN_LOWDIN. */
+ks_status ks_plan_set_overlap_cutoff(ks_plan* plan, double tau);
+
+/* KS_PLAN_LOWDIN plans: the number of eigenvectors of S kept by the last
+ * decomposition of S, per k-point, into the HOST array nkeep[batch]
+ * (synchronizes the plan's stream).  KS_ERR_INVALID_ARG before S has been
+ * decomposed or for NULL, KS_ERR_NOT_SUPPORTED without KS_PLAN_LOWDIN. */
+ks_status ks_plan_get_overlap_rank(ks_plan* plan, int32_t* nkeep);
+
 /* Graph use under KS_PLAN_GRAPH: how many argument sets were captured and how
  * many ks_gevd calls replayed a captured graph.  Host-only. */
 ks_status ks_plan_get_graph_stats(ks_plan* plan, int64_t* captures, int64_t* replays);

@@ -78,6 +78,9 @@ struct ks_plan {
     // eigenvalues s of S; spinor plans solve the order-n eigenproblem of S on
     // the collinear plan ov (collinear plans use their own buffers)
     double* sev = nullptr;     // batch x n
+    int* nkeep = nullptr;      // batch: eigenvectors of S kept
+    double* fpart = nullptr;   // batch x row blocks: |H'|_F^2 partials
+    double ov_tau = 0.0;       // cutoff tau of ks_plan_set_overlap_cutoff
     ks_plan* ov = nullptr;
     int mixed_sweeps = 2;
     hipGraph_t graph = nullptr;
@@ -213,12 +216,19 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
         oVWl = L.take(B * hVW * es32);
         oWVl = L.take(B * hVW * es32);
     }
-    const size_t oSev = (d->flags & KS_PLAN_LOWDIN) ? L.take(B * n * 8) : 0;
+    const bool lw = (d->flags & KS_PLAN_LOWDIN) != 0;
+    const size_t oSev = lw ? L.take(B * n * 8) : 0;
+    const size_t oNkeep = lw ? L.take(B * sizeof(int)) : 0;
+    const size_t oFpart = lw ? L.take(B * ((order + 63) / 64) * 8) : 0;
     size_t total = L.off;
     if (!p) return total;
     char* b = p->base;
     p->L = b + oL;
-    if (d->flags & KS_PLAN_LOWDIN) p->sev = (double*)(b + oSev);
+    if (lw) {
+        p->sev = (double*)(b + oSev);
+        p->nkeep = (int*)(b + oNkeep);
+        p->fpart = (double*)(b + oFpart);
+    }
     p->Li = b + oLi;
     p->A = b + oA;
     p->W = b + oW;
@@ -488,24 +498,71 @@ ks_status gevd_mixed(ks_plan* p, const T* H, double* eps, T* C, int il, int iu) 
     return KS_OK;
 }
 
-// V = U s^-1/2 (Part 2-2 / 3-2): column j of the eigenvectors of S scaled by
-// 1/sqrt(s_j), for every matrix of the batch.  s ascends, so the number of
-// non-positive s_j is the index of the last one; that count is the detail of
-// KS_ERR_NOT_POSDEF.
+// V = U s^-1/2 (Part 2-2 / 3-2) with the columns in descending order of s:
+// column j of V is eigenvector n-1-j of S scaled by 1/sqrt(s), or zero when
+// s <= tau * max(s) (canonical orthogonalisation drops it), so that the kept
+// columns come first; nkeep gets their number.  With tau = 0 a non-positive
+// s is a failure, KS_ERR_NOT_POSDEF with detail = the number of s_j <= 0
+// (s ascends, so that is the index of the last one); with tau > 0 only a
+// non-positive max(s) is.
 template <typename T>
-__global__ void lowdin_v_kernel(int n, const T* U, const double* sv, T* V, int* info) {
+__global__ void lowdin_v_kernel(int n, const T* U, const double* sv, double tau, T* V, int* nkeep, int* info) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
     if (j >= n) return;
     const long b = blockIdx.z;
     const double* sb = sv + b * n;
-    const double sj = sb[j];
-    const long o = b * n * n + (long)i * n + j;
-    if (!(sj > 0.0)) {  // flagged; the column is zeroed so that the rest of the solve stays finite
-        if (i == 0 && (j == n - 1 || sb[j + 1] > 0.0)) set_info(info, KS_ERR_NOT_POSDEF, j + 1);
-        V[o] = zero_<T>();
-        return;
+    const double smax = sb[n - 1], thr = tau * smax;
+    const int src = n - 1 - j;
+    const double sj = sb[src];
+    const bool keep = sj > thr && smax > 0.0;
+    if (i == 0) {
+        // src is the smallest kept eigenvalue: the kept count is n - src
+        if (keep && (src == 0 || !(sb[src - 1] > thr))) nkeep[b] = n - src;
+        if (!(smax > 0.0) && j == 0) {
+            nkeep[b] = 0;
+            set_info(info, KS_ERR_NOT_POSDEF, n);
+        } else if (tau == 0.0 && !(sj > 0.0) && (src == n - 1 || sb[src + 1] > 0.0)) {
+            set_info(info, KS_ERR_NOT_POSDEF, src + 1);
+        }
     }
-    V[o] = U[o] * (1.0 / sqrt(sj));
+    const long o = b * n * n + (long)i * n;
+    V[o + j] = keep ? U[o + src] * (1.0 / sqrt(sj)) : zero_<T>();
+}
+
+// |H'|_F^2 of the lower triangle (off-diagonal entries twice), one partial per
+// 64-row block and matrix, summed in a fixed order.
+template <typename T>
+__global__ __launch_bounds__(256) void frob_lower_kernel(int order, const T* A, long sA, double* part) {
+    __shared__ double red[4];
+    const int r0 = blockIdx.x * 64, z = blockIdx.y;
+    A += z * sA;
+    double acc = 0.0;
+    for (int r = r0; r < min(r0 + 64, order); ++r)
+        for (int c = threadIdx.x; c <= r; c += blockDim.x) acc += (c < r ? 2.0 : 1.0) * abs2_(A[(long)r * order + c]);
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) part[(long)z * gridDim.x + blockIdx.x] = acc;
+}
+
+// The dropped directions of H' (zero rows and columns) get a diagonal
+// placeholder sigma = 2 |H'|_F + 1, above every kept eigenvalue, so that they
+// sort last with zero eigenvectors C = V_NC e_j and zero occupation.
+template <typename T>
+__global__ __launch_bounds__(256) void lowdin_sigma_kernel(int n, int nsp, int order, T* A, long sA,
+                                                           const double* part, int nblk, const int* nkeep) {
+    __shared__ double sig;
+    const int z = blockIdx.x;
+    if (threadIdx.x == 0) {
+        double f = 0.0;
+        for (int q = 0; q < nblk; ++q) f += part[(long)z * nblk + q];
+        sig = 2.0 * sqrt(f) + 1.0;
+    }
+    __syncthreads();
+    const int nk = nkeep[z], nd = n - nk;
+    A += z * sA;
+    for (int e = threadIdx.x; e < nsp * nd; e += blockDim.x) {
+        const int r = (e / nd) * n + nk + e % nd;
+        A[(long)r * order + r] = from_re<T>(sig);
+    }
 }
 
 // Loewdin route (Sec. 3.1 Parts 2-1..2-5; Sec. 3.2 Parts 3-1..3-6): eigenvectors
@@ -537,7 +594,7 @@ ks_status gevd_lowdin(ks_plan* p, const T* H, const T* S, double* eps, T* C, int
         backtransform_prepare<T>(s, n, B, Wq, (T*)q->tau, qb);
         backtransform_q<T>(s, n, B, Wq, n, Aq, n, sV, qb);
         hipLaunchKernelGGL(lowdin_v_kernel<T>, dim3(cdiv(n, 256), n, B), dim3(256), 0, s, n, (const T*)Aq,
-                           (const double*)p->sev, V, p->info);
+                           (const double*)p->sev, p->ov_tau, V, p->nkeep, p->info);
         pf.end(KS_PHASE_CHOLESKY, e);
         p->have_L = true;
     }
@@ -551,6 +608,12 @@ ks_status gevd_lowdin(ks_plan* p, const T* H, const T* S, double* eps, T* C, int
     for (int b = 0; b < nsp; ++b)
         gemm<T>(s, OP_C, OP_N, n, order, n, 1.0, V, n, sV, W + (long)b * n * order, order, sA, 0.0,
                 A + (long)b * n * order, order, sA, B, nullptr, 0, b == 0 ? UPLO_LOWER : UPLO_FULL);
+    if (p->ov_tau > 0.0) {
+        const int nblk = cdiv(order, 64);
+        hipLaunchKernelGGL(frob_lower_kernel<T>, dim3(nblk, B), dim3(256), 0, s, order, (const T*)A, sA, p->fpart);
+        hipLaunchKernelGGL(lowdin_sigma_kernel<T>, dim3(B), dim3(256), 0, s, n, nsp, order, A, sA,
+                           (const double*)p->fpart, nblk, (const int*)p->nkeep);
+    }
     pf.end(KS_PHASE_REDUCE, e);
     e = pf.begin();
     hetrd<T, T>(s, order, A, order, sA, B, p->dv, p->ev, (T*)p->tau, W,
@@ -732,6 +795,24 @@ void ks_plan_destroy(ks_plan* p) {
     if (p->base) (void)hipFree(p->base);
     if (p->adj) (void)hipFree(p->adj);
     delete p;
+}
+
+ks_status ks_plan_set_overlap_cutoff(ks_plan* p, double tau) {
+    if (!p || !(tau >= 0.0 && tau < 1.0)) return KS_ERR_INVALID_ARG;
+    if (!(p->d.flags & KS_PLAN_LOWDIN)) return KS_ERR_NOT_SUPPORTED;
+    if (p->ov_tau != tau) graph_release(p);  // a captured sequence would keep the old cutoff
+    p->ov_tau = tau;
+    return KS_OK;
+}
+
+ks_status ks_plan_get_overlap_rank(ks_plan* p, int32_t* nkeep) {
+    if (!p || !nkeep) return KS_ERR_INVALID_ARG;
+    if (!(p->d.flags & KS_PLAN_LOWDIN)) return KS_ERR_NOT_SUPPORTED;
+    if (!p->have_L) return KS_ERR_INVALID_ARG;
+    if (hipStreamSynchronize(p->s) != hipSuccess) return KS_ERR_HIP;
+    if (hipMemcpy(nkeep, p->nkeep, sizeof(int) * p->d.batch, hipMemcpyDeviceToHost) != hipSuccess)
+        return KS_ERR_HIP;
+    return KS_OK;
 }
 
 ks_status ks_plan_set_refinement(ks_plan* p, int32_t sweeps) {

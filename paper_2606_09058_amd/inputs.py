@@ -361,6 +361,37 @@ def random_spd(rng, n, cplx, cond=COND_S):
     return S
 
 
+def overcomplete(seed=0, n=90, ms=(70,), nsp=1, cplx=False, kT=0.01):
+    """An overcomplete basis: n functions chi = B phi spanning m < n dimensions
+    (phi orthonormal, B n x m Gaussian), so S = B B^H has rank m, and
+    H = B_NC h B_NC^H with h a random Hermitian matrix of order nsp m (B_NC =
+    diag(B, B) for the spinor form).  One k-point per entry of ms; electrons
+    g nsp m / 3 per k-point (g = 2 collinear, 1 spinor).  meta holds B and h
+    per k-point for closed-form checks."""
+    rng = np.random.default_rng(seed)
+    cp = cplx or nsp == 2
+    Hs, Ss, Bs, hs = [], [], [], []
+    for m in ms:
+        B = rng.normal(size=(n, m))
+        if cp:
+            B = B + 1j * rng.normal(size=(n, m))
+        h = random_hermitian(rng, nsp * m, cp)
+        BN = np.kron(np.eye(nsp), B)
+        S = B @ B.conj().T
+        H = BN @ h @ BN.conj().T
+        Hs.append(0.5 * (H + H.conj().T))
+        Ss.append(0.5 * (S + S.conj().T))
+        Bs.append(B)
+        hs.append(h)
+    g = 2.0 if nsp == 1 else 1.0
+    ne = float(sum(round(g * nsp * m / 3.0) for m in ms)) / len(ms)
+    one = len(ms) == 1
+    p = Problem(Hs[0] if one else np.array(Hs), Ss[0] if one else np.array(Ss), ne, kT, nsp=nsp,
+                weights=None if one else np.full(len(ms), 1.0 / len(ms)), name="overcomplete")
+    p.meta = {"B": Bs, "h": hs, "m": list(ms)}
+    return p
+
+
 # Named workloads: the five configurations and small stand-ins of the same kind.
 def workload(name: str, seed: int = 0) -> Problem:
     if name == "toy64":

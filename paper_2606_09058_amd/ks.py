@@ -32,7 +32,8 @@ STATUS = {
 EXPORTS = ["ks_plan_create", "ks_plan_destroy", "ks_gevd", "ks_density", "ks_energy_density", "ks_bloch_sum",
            "ks_density_backward",
            "ks_plan_get_info", "ks_status_string", "ks_plan_workspace_bytes", "ks_plan_set_profiling",
-           "ks_plan_get_profile", "ks_plan_get_graph_stats", "ks_plan_get_tuning", "ks_plan_set_refinement"]
+           "ks_plan_get_profile", "ks_plan_get_graph_stats", "ks_plan_get_tuning", "ks_plan_set_refinement",
+           "ks_plan_set_overlap_cutoff", "ks_plan_get_overlap_rank"]
 
 
 class KSError(RuntimeError):
@@ -89,6 +90,10 @@ def lib():
         L.ks_energy_density.restype = I
         L.ks_bloch_sum.argtypes = [P, I, P, P, P, I, P, I]
         L.ks_bloch_sum.restype = I
+        L.ks_plan_set_overlap_cutoff.argtypes = [P, D]
+        L.ks_plan_set_overlap_cutoff.restype = I
+        L.ks_plan_get_overlap_rank.argtypes = [P, P]
+        L.ks_plan_get_overlap_rank.restype = I
         L.ks_density_backward.argtypes = [P, P, P, P, P, D, P, P, P, P]
         L.ks_density_backward.restype = I
         L.ks_plan_get_info.argtypes = [P, ctypes.POINTER(I)]
@@ -238,6 +243,16 @@ class Plan:
         st = lib().ks_density_backward(self._h, _ptr(eps), _ptr(C), _ptr(mu), _ptr(occ), float(kT),
                                        _ptr(grad_rho), _ptr(grad_eband), _ptr(grad_H), _ptr(grad_S))
         _check(st, "ks_density_backward")
+
+    def set_overlap_cutoff(self, tau):
+        """KS_PLAN_LOWDIN: drop the eigenvectors of S with s <= tau * max(s)."""
+        _check(lib().ks_plan_set_overlap_cutoff(self._h, float(tau)), "ks_plan_set_overlap_cutoff")
+
+    def overlap_rank(self):
+        """KS_PLAN_LOWDIN: eigenvectors of S kept per k-point by the last decomposition."""
+        v = (ctypes.c_int32 * self.batch)()
+        _check(lib().ks_plan_get_overlap_rank(self._h, v), "ks_plan_get_overlap_rank")
+        return [int(x) for x in v]
 
     def set_profiling(self, enable, stride=1):
         _check(lib().ks_plan_set_profiling(self._h, int(bool(enable)), int(stride)), "ks_plan_set_profiling")

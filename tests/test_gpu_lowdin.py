@@ -187,3 +187,71 @@ def test_lowdin_graph_replay_matches_eager():
             assert np.array_equal(host(C), host(C2)), rep
         gplan.check("graph")
         assert gplan.graph_stats()[1] >= 1
+
+
+@pytest.mark.parametrize("kind", ["real", "complex", "noncollinear", "batch"])
+def test_overlap_cutoff_on_an_overcomplete_basis(kind):
+    """Canonical orthogonalisation (ks_plan_set_overlap_cutoff): an n-function
+    basis spanning m < n dimensions.  The kept count must be m per k-point, the
+    kept eigenvalues the oracle's canonical route and eig(h) (the closed form),
+    the placeholders equal, above every kept eigenvalue, with zero
+    eigenvectors; rho the oracle's and tr(rho S) = N_e."""
+    announce("lowdin overlap cutoff", kind)
+    tau = 1e-10
+    if kind == "real":
+        p = I.overcomplete(seed=1, n=90, ms=(70,))
+    elif kind == "complex":
+        p = I.overcomplete(seed=2, n=100, ms=(77,), cplx=True)
+    elif kind == "noncollinear":
+        p = I.overcomplete(seed=3, n=50, ms=(41,), nsp=2)
+    else:
+        p = I.overcomplete(seed=4, n=80, ms=(60, 70))
+    plan = lowdin_plan(p)
+    plan.set_overlap_cutoff(tau)
+    g = run(plan, p)
+    assert plan.overlap_rank() == list(p.meta["m"])
+    eps = g["eps"].reshape(p.batch, p.order)
+    C = g["C"].reshape(p.batch, p.order, p.order)
+    rho = g["rho"].reshape(p.batch, p.order, p.order)
+    Hs = p.H.reshape(p.batch, p.order, p.order)
+    Ss = p.S.reshape(p.batch, p.n, p.n)
+    es_pad = np.full((p.batch, p.order), 1.0e6)  # dropped states: never occupied
+    Cos = []
+    for k in range(p.batch):
+        mk = p.nsp * p.meta["m"][k]
+        e_o, C_o, m_o = O.gevd_canonical(Hs[k], Ss[k], tau, nsp=p.nsp)
+        assert m_o == p.meta["m"][k]
+        scale = max(1.0, np.abs(e_o).max())
+        assert np.abs(eps[k, :mk] - e_o).max() < 1e-9 * scale
+        assert np.abs(eps[k, :mk] - np.linalg.eigvalsh(p.meta["h"][k])).max() < 1e-9 * scale
+        ph = eps[k, mk:]
+        assert ph.size == p.order - mk and np.all(ph > eps[k, :mk].max())
+        assert np.abs(ph - ph[0]).max() <= 1e-9 * abs(ph[0])
+        assert np.abs(C[k][:, mk:]).max() < 1e-9
+        es_pad[k, :mk] = e_o
+        Cos.append(C_o)
+    fr = O.fermi(es_pad, p.n_electrons, p.kT, p.g, wk=p.weights)
+    occ = np.atleast_2d(fr["occ"])
+    for k in range(p.batch):
+        mk = p.nsp * p.meta["m"][k]
+        rho_o = O.density(Cos[k], occ[k, :mk])
+        assert np.abs(rho[k] - rho_o).max() < RHO_TOL * max(1.0, np.abs(rho_o).max())
+    SN = [np.kron(np.eye(p.nsp), Ss[k]) if p.nsp == 2 else Ss[k] for k in range(p.batch)]
+    w = [1.0] if p.batch == 1 else list(p.weights)
+    tr = sum(w[k] * np.trace(rho[k] @ SN[k]).real for k in range(p.batch))
+    assert abs(tr - p.n_electrons) < 1e-8 * p.n_electrons
+
+
+def test_overlap_cutoff_arguments():
+    announce("lowdin cutoff arguments")
+    p = I.toy(seed=2, natoms=3, norb=8)
+    plan = lowdin_plan(p)
+    with pytest.raises(ks.KSError):
+        plan.set_overlap_cutoff(1.5)
+    with pytest.raises(ks.KSError):
+        plan.overlap_rank()  # S not decomposed yet
+    run(plan, p)
+    assert plan.overlap_rank() == [p.n]
+    chol = ks.Plan(p.n)
+    with pytest.raises(ks.KSError):
+        chol.set_overlap_cutoff(1e-8)
