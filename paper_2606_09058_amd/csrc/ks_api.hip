@@ -81,6 +81,7 @@ struct ks_plan {
     int* nkeep = nullptr;      // batch: eigenvectors of S kept
     double* fpart = nullptr;   // batch x row blocks: |H'|_F^2 partials
     double ov_tau = 0.0;       // cutoff tau of ks_plan_set_overlap_cutoff
+    double v_tau = 0.0;        // the cutoff the V in use was formed with
     ks_plan* ov = nullptr;
     int mixed_sweeps = 2;
     hipGraph_t graph = nullptr;
@@ -595,6 +596,7 @@ ks_status gevd_lowdin(ks_plan* p, const T* H, const T* S, double* eps, T* C, int
         backtransform_q<T>(s, n, B, Wq, n, Aq, n, sV, qb);
         hipLaunchKernelGGL(lowdin_v_kernel<T>, dim3(cdiv(n, 256), n, B), dim3(256), 0, s, n, (const T*)Aq,
                            (const double*)p->sev, p->ov_tau, V, p->nkeep, p->info);
+        p->v_tau = p->ov_tau;
         pf.end(KS_PHASE_CHOLESKY, e);
         p->have_L = true;
     }
@@ -608,7 +610,7 @@ ks_status gevd_lowdin(ks_plan* p, const T* H, const T* S, double* eps, T* C, int
     for (int b = 0; b < nsp; ++b)
         gemm<T>(s, OP_C, OP_N, n, order, n, 1.0, V, n, sV, W + (long)b * n * order, order, sA, 0.0,
                 A + (long)b * n * order, order, sA, B, nullptr, 0, b == 0 ? UPLO_LOWER : UPLO_FULL);
-    if (p->ov_tau > 0.0) {
+    if (p->v_tau > 0.0) {  // V has dropped (zero) columns: give them their placeholder
         const int nblk = cdiv(order, 64);
         hipLaunchKernelGGL(frob_lower_kernel<T>, dim3(nblk, B), dim3(256), 0, s, order, (const T*)A, sA, p->fpart);
         hipLaunchKernelGGL(lowdin_sigma_kernel<T>, dim3(B), dim3(256), 0, s, n, nsp, order, A, sA,

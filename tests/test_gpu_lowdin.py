@@ -255,3 +255,30 @@ def test_overlap_cutoff_arguments():
     chol = ks.Plan(p.n)
     with pytest.raises(ks.KSError):
         chol.set_overlap_cutoff(1e-8)
+
+
+def test_overlap_cutoff_kept_with_the_reused_v():
+    """V formed with a cutoff and reused (KS_REUSE_S) after the cutoff is reset:
+    the reused V keeps its dropped columns, so the new H must still get the
+    placeholders (the cutoff in force when V was formed decides), and the kept
+    eigenvalues are eig(h') for the new h'."""
+    announce("lowdin cutoff with reused V")
+    tau = 1e-10
+    p = I.overcomplete(seed=6, n=70, ms=(52,), cplx=True)
+    plan = lowdin_plan(p)
+    plan.set_overlap_cutoff(tau)
+    run(plan, p)
+    plan.set_overlap_cutoff(0.0)
+    B = p.meta["B"][0]
+    h2 = p.meta["h"][0] + 0.1 * np.eye(52)
+    H2 = B @ h2 @ B.conj().T
+    q = I.Problem(0.5 * (H2 + H2.conj().T), p.S, p.n_electrons, p.kT)
+    g = run(plan, q, reuse_s=True)
+    m = 52
+    e_o, C_o, m_o = O.gevd_canonical(q.H, q.S, tau)
+    assert m_o == m and plan.overlap_rank() == [m]
+    scale = max(1.0, np.abs(e_o).max())
+    assert np.abs(g["eps"][:m] - e_o).max() < 1e-9 * scale
+    assert np.abs(g["eps"][:m] - np.linalg.eigvalsh(h2)).max() < 1e-9 * scale
+    assert np.all(g["eps"][m:] > g["eps"][:m].max())
+    assert abs(np.trace(g["rho"] @ q.S).real - q.n_electrons) < 1e-8 * q.n_electrons
