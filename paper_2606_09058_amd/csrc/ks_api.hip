@@ -148,7 +148,7 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
     int nsp = d->spin == KS_NONCOLLINEAR ? 2 : 1;
     size_t n = d->n, order = n * nsp, B = d->batch;
     size_t es = d->dtype == KS_COMPLEX128 ? 16 : 8;
-    size_t nb = HETRD_NB, bt = BACKTR_BT;
+    size_t nb = HETRD_NB, bt = backtr_block((int)order);
     std::vector<int> mlo, mmid, mhi, llo, lhi, mk;
     int depth = 0;
     dc_tree_host((int)order, mlo, mmid, mhi, llo, lhi, depth, mk);

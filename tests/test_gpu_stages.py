@@ -278,11 +278,12 @@ def test_hetrd_similarity(L, n, cplx):
     assert np.abs(wT - wA).max() < 1e-12 * n
 
 
-def test_hetrd_similarity_order_4100(L):
-    """Order 4100 takes 256-reflector compact-WY blocks in the back-transform
-    (16 full blocks and a ragged one of 3) and the large-tile GEMMs: Q unitary
-    and Q T Q^H = A (which fix eig(T) = eig(A))."""
-    n = 4100
+@pytest.mark.parametrize("n", [4100, 6150])
+def test_hetrd_similarity_large_orders(L, n):
+    """Orders 4100 and 6150 take 256-reflector compact-WY blocks in the
+    back-transform (16 full blocks and a ragged one of 3; 24 and a ragged one
+    of 5) and the large-tile GEMMs: Q unitary and Q T Q^H = A (which fix
+    eig(T) = eig(A))."""
     announce("hetrd", n)
     rng = np.random.default_rng(11)
     A = I.random_hermitian(rng, n, False)
