@@ -17,8 +17,13 @@
  * Route: Cholesky S = L L^H; A = L^-1 H L^-H (spinor form: with L applied to
  * each spin block, i.e. (I2 (x) L)); blocked Householder tridiagonalisation
  * A = Q T Q^H; divide-and-conquer eigensolver of T; back-transform
- * C = L^-H Q Z.  Everything runs in HIP kernels on the device, asynchronously
- * on the plan's stream; the host only validates arguments and enqueues.
+ * C = L^-H Q Z.  Plans created with KS_PLAN_LOWDIN take the paper's own route
+ * instead (eigen-decomposition of S, V = U s^-1/2, H' = V^H H V, C = V C'),
+ * optionally dropping the near-null directions of an overcomplete basis.
+ * Further entry points form the energy-density matrix C diag(f eps) C^H and
+ * the Bloch sums H(k), S(k) of real-space blocks for a batch of k-points.
+ * Everything runs in HIP kernels on the device, asynchronously on the plan's
+ * stream; the host only validates arguments and enqueues.
  *
  * Conventions shared by all entry points
  *   - Matrices are row-major with a row stride ("leading dimension") in

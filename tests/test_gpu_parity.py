@@ -133,6 +133,34 @@ def test_bloch_sum_vs_oracle():
                                                                device="cuda"))
 
 
+def test_bloch_sum_edge_sizes():
+    """The largest lattice-vector count (64) with a ragged order (37, not a
+    multiple of the 32-row tile) and one k-point against the oracle; 65
+    lattice vectors and a short output stride are refused before any work."""
+    announce("bloch sum edges")
+    rng = np.random.default_rng(9)
+    n, nR = 37, 64
+    R = rng.integers(-3, 4, size=(nR, 3)).astype(np.float64) * 7.0
+    k = rng.uniform(-0.5, 0.5, size=(1, 3))
+    XR = rng.normal(size=(nR, n, n))
+    plan = ks.Plan(n, batch=1, complex=True)
+    out = torch.empty((n, n), dtype=torch.complex128, device="cuda")
+    plan.bloch_sum(dev(R), dev(k), dev(XR), out)
+    plan.check("bloch sum edges")
+    o = O.bloch_sum(XR, R, k)[0]
+    lo = np.tril(o)
+    # the lower triangle is the sum itself; the upper one is its mirror
+    assert np.abs(np.tril(host(out)) - lo + np.diag(1j * np.diag(o).imag)).max() < 1e-12 * np.abs(XR).sum(0).max()
+    g = host(out)
+    assert np.array_equal(g, g.conj().T)
+    R65 = np.zeros((65, 3))
+    with pytest.raises(ks.KSError):
+        plan.bloch_sum(dev(R65), dev(k), dev(np.zeros((65, n, n))), out)
+    L = ks.lib()
+    assert L.ks_bloch_sum(plan._h, nR, dev(R).data_ptr(), dev(k).data_ptr(), dev(XR).data_ptr(), n,
+                          out.data_ptr(), n - 1) == 1
+
+
 def test_kpoint_batch_common_mu():
     announce("kpoint batch")
     p = I.kpoint_batch(natoms=6, norb=13, kgrid=(2, 2, 1))
