@@ -265,7 +265,9 @@ ks_status ks_plan_set_refinement(ks_plan* plan, int32_t sweeps);
  * nsp * (n - nkeep) eigenvalues all equal sigma = 2 |H'|_F + 1 (above every
  * kept one), their eigenvectors are zero and their occupation is zero; the
  * caller reads nkeep with ks_plan_get_overlap_rank.  Takes effect at the next
- * ks_gevd that decomposes S (not under KS_REUSE_S).  Host-only;
+ * ks_gevd that decomposes S (not under KS_REUSE_S).  While the V in use was
+ * formed with tau > 0, ks_density_backward returns KS_ERR_NOT_SUPPORTED (its
+ * formulas assume a complete S-orthonormal eigenbasis).  Host-only;
  * KS_ERR_INVALID_ARG outside the range, KS_ERR_NOT_SUPPORTED on a plan
  * without KS_PLAN_LOWDIN. */
 ks_status ks_plan_set_overlap_cutoff(ks_plan* plan, double tau);

@@ -1052,6 +1052,9 @@ ks_status ks_density_backward(ks_plan* p, const double* eps, const void* C, cons
                               const double* grad_eband, void* grad_H, void* grad_S) {
     if (!p || !eps || !C || !mu || !occ || !grad_H || !grad_S) return KS_ERR_INVALID_ARG;
     if (!(kT > 0.0) || !isfinite(kT)) return KS_ERR_INVALID_ARG;
+    // the gradient formulas use the completeness of the eigenvectors in the
+    // S metric, which a basis reduced by the overlap cutoff does not have
+    if (p->v_tau > 0.0) return KS_ERR_NOT_SUPPORTED;
     int order = p->order, B = p->d.batch;
     if (!p->adj) {
         size_t m = (size_t)order * order * p->es;

@@ -282,3 +282,10 @@ def test_overlap_cutoff_kept_with_the_reused_v():
     assert np.abs(g["eps"][:m] - np.linalg.eigvalsh(h2)).max() < 1e-9 * scale
     assert np.all(g["eps"][m:] > g["eps"][:m].max())
     assert abs(np.trace(g["rho"] @ q.S).real - q.n_electrons) < 1e-8 * q.n_electrons
+    # the adjoint needs a complete eigenbasis: refused while V has dropped columns
+    n = p.n
+    z = torch.zeros((n, n), dtype=torch.complex128, device="cuda")
+    eps_t = dev(g["eps"])
+    with pytest.raises(ks.KSError):
+        plan.density_backward(eps_t, dev(g["C"]), dev(g["mu"]), dev(g["occ"]), p.kT, dev(g["rho"]) * 0, None,
+                              z.clone(), z.clone())
