@@ -170,7 +170,7 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
     // tridiagonalisation (per matrix of the batch)
     size_t ntl = (order + HETRD_TILE - 1) / HETRD_TILE, nchl = (ntl + HETRD_SCH_MIN - 1) / HETRD_SCH_MIN;
     size_t hVW = order * 2 * nb, hX = order, hPQ = ntl * (1 + 2 * nb), hPR = ntl * nchl * HETRD_TILE;
-    size_t hPC = ntl * ntl * HETRD_TILE, hPV = ntl * nchl, hPQv = 2 + 2 * nb;
+    size_t hPC = ntl * ntl * HETRD_TILE, hPV = ntl * nchl, hPQv = 5 + 2 * nb;
     size_t oVW = L.take(B * hVW * es), oWV = L.take(B * hVW * es);
     size_t oX = L.take(B * hX * es);
     size_t oPQ = L.take(2 * B * hPQ * es);  // one partial buffer per column parity

@@ -118,7 +118,12 @@ __device__ inline void reflector(const T* partA, int nA, int ld, T alpha, T& sc,
 // The raw panel products W^H x and V^H x over rows k+2.. of column k, reduced
 // once per column by one workgroup of NW wavefronts from the partials of the
 // previous kernel: pq[2 + i] (W) and pq[2 + nb + i] (V), with pq[0] = x_{k+1}.
-// The reflector's scale and the row k+1 terms are applied by the next kernel.
+// For real data its last wavefront also forms the reflector of column k from
+// alpha = x_{k+1} and the partial norms, into pq[2 + 2nb .. 4 + 2nb] =
+// (s, tau, beta), off the column kernel's critical path (measured: 3 ms of
+// 147 at N = 6656; complex data keep it in the column kernel, where the
+// longer panel workgroup of their product kernel cost more than it saved).  The reflector's scale and the row
+// k+1 terms are applied by the next kernel.
 template <typename T, int NW>
 __device__ inline void panel_products(int k, int j, int nb, const T* x, const T* partA, int nA, T* pq,
                                       T (*part)[64]) {
@@ -130,6 +135,20 @@ __device__ inline void panel_products(int k, int j, int nb, const T* x, const T*
         const int idx = lane < j ? 1 + lane : 1 + nb + (lane - j);
         part[g][lane] = batched_sum<8, T>(g, NW, nA, [&](int b) { return partA[(long)b * ld + idx]; });
     }
+    if (g == NW - 1) {  // alongside the partial sums of the other wavefronts
+        const T alpha = x[k + 1];
+        if constexpr (!is_cplx<T>::value) {
+            T sc, tv;
+            double beta;
+            reflector<T>(partA, nA, ld, alpha, sc, tv, beta);
+            if (lane == 0) {
+                pq[2 + 2 * nb] = sc;
+                pq[3 + 2 * nb] = tv;
+                pq[4 + 2 * nb] = from_re<T>(beta);
+            }
+        }
+        if (lane == 0) pq[0] = alpha;
+    }
     __syncthreads();
     if (t < nv) {
         T P = zero_<T>();
@@ -137,7 +156,6 @@ __device__ inline void panel_products(int k, int j, int nb, const T* x, const T*
         if (t < j) pq[2 + t] = P;
         else pq[2 + nb + (t - j)] = P;
     }
-    if (t == 0) pq[0] = x[k + 1];
 }
 
 // Sum of r[0..R-1] over the 64 lanes for each of the R rows at once
@@ -388,8 +406,9 @@ __global__ __launch_bounds__((Sy<T, S>::THREADS), 4) void symv_kernel(int n, int
 // workgroup per 64 trailing rows r = k+1+64b+l, which is exactly tile row b of
 // the product, and WC_NW wavefronts that split every gather so that each is a
 // single batch of loads:
-//   * the reflector (s, tau, beta) from alpha = x_{k+1} and the partial
-//     |x_{k+2..}|^2, with p = W^H v and q = V^H v from the raw panel products
+//   * the reflector (s, tau, beta), for real data formed by the product
+//     kernel's panel workgroup, for complex data here from alpha = x_{k+1}
+//     and the partial |x_{k+2..}|^2, with p = W^H v and q = V^H v from the raw panel products
 //     (row k+1, where v = 1, added here), by one wavefront;
 //   * A v = s z + c a_1 with c = 1 - s alpha (v = s x + c e_{k+1}) and
 //     v^H A v = |s|^2 x^H A x + 2 Re(conj(s) c x^H a_1) + |c|^2 a_11, where
@@ -473,10 +492,16 @@ __global__ __launch_bounds__(64 * Wc<T>::NW) void wcol_kernel(int n, int k, int 
         const T vkt = VWt[(long)lj * n + k + 1], wkt = VWt[(long)(nb + lj) * n + k + 1];
         const T pw = pq[2 + lj], pv = pq[2 + nb + lj];
         const T xk = x[k];
+        const T alpha = pq[0];
         T sc, tv;
         double beta;
-        const T alpha = pq[0];
-        reflector<T>(partA, nA, (int)ldp, alpha, sc, tv, beta);
+        if constexpr (is_cplx<T>::value) {
+            reflector<T>(partA, nA, (int)ldp, alpha, sc, tv, beta);
+        } else {  // formed by the product kernel's panel workgroup
+            sc = pq[2 + 2 * nb];
+            tv = pq[3 + 2 * nb];
+            beta = re_(pq[4 + 2 * nb]);
+        }
         T pl = zero_<T>(), ql = zero_<T>(), cs = zero_<T>();
         double cr = 0.0;
         if (lr < j) {

@@ -83,7 +83,8 @@ struct HetrdWork {
     T* prow;        // nt x cdiv(nt, HETRD_SCH_MIN) x HETRD_TILE, nt = cdiv(n, HETRD_TILE): row partials
     T* pcol;        // nt x nt x HETRD_TILE                                           column partials
     double* pvav;   // nt x cdiv(nt, HETRD_SCH_MIN) partial v^H A v
-    T* pq;          // 2 + 2 NB: x_{k+1}, unused, raw W^H x, V^H x of the current column
+    T* pq;          // 5 + 2 NB: x_{k+1}, unused, raw W^H x, V^H x of the current column,
+                    // then the reflector's s, tau and beta
     void* VWlo = nullptr;  // mixed form: VW and WV in FP32 for the trailing update
     void* WVlo = nullptr;
     // strides (elements) between the buffers of consecutive matrices of a batch
