@@ -91,7 +91,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="supercell6656", choices=sorted(WORKLOADS))
     ap.add_argument("--stride", type=int, default=16, help="sample every n-th matrix-vector launch")
-    ap.add_argument("--cpu-sample", type=int, default=1300)
+    ap.add_argument("--cpu-sample", type=int, default=1700)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the FP64-vs-mixed comparison on the occupied window")
