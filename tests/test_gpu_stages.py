@@ -143,6 +143,29 @@ def test_gemm_lower_only(L, m, k):
     assert np.array_equal(got[~low], C0[~low])
 
 
+@pytest.mark.parametrize("fp32", [False, True])
+@pytest.mark.parametrize("m,n,k", [(150, 150, 64), (1000, 1000, 37), (67, 200, 1), (4100, 4100, 64)])
+def test_gemm_rank_update_lower(L, m, n, k, fp32):
+    """C = C - A^T B on the lower triangle with k <= 64 (the trailing-update form,
+    A and B stored k x m, k x n): ragged tiles, a partial last k step, and the
+    upper triangle left untouched."""
+    announce("gemm rank update", m, n, k, fp32)
+    rng = np.random.default_rng(m + k)
+    dt = np.float32 if fp32 else np.float64
+    A = rng.normal(size=(k, m)).astype(dt)
+    B = rng.normal(size=(k, n)).astype(dt)
+    C0 = rng.normal(size=(m, n)).astype(dt)
+    Cd = dev(C0)
+    assert L.ks_test_gemm(2 if fp32 else 0, 1, 0, m, n, k, -1.0, P(dev(A)), m, P(dev(B)), n, 1.0, P(Cd), n, 1,
+                          stream_handle()) == 0
+    got = host(Cd).astype(np.float64)
+    ref = C0.astype(np.float64) - A.astype(np.float64).T @ B.astype(np.float64)
+    low = np.tril(np.ones((m, n), bool))
+    tol = (4e-7 if fp32 else 1e-13) * (k + 1) * 16
+    assert np.abs(got[low] - ref[low]).max() < tol
+    assert np.array_equal(got[~low], C0.astype(np.float64)[~low])
+
+
 @pytest.mark.parametrize("n", [1, 31, 63, 64, 65, 100, 128, 257, 330])
 @pytest.mark.parametrize("cplx", [False, True])
 def test_potrf_matches_oracle(L, n, cplx):
