@@ -26,6 +26,8 @@
 // The panel buffers are stored transposed (NB columns of length n each) so
 // that the per-row corrections read them coalesced, and the GEMM reads them
 // as (V W)^T and conj(W V).  All reductions are fixed-order (deterministic).
+#include <hip/hip_ext.h>
+
 #include "ks_internal.hpp"
 
 namespace ks {
@@ -637,13 +639,27 @@ __global__ void last_diag_kernel(int n, const S* A, int lda, long sA, double* d)
     d[(long)z * n + n - 1] = re_(A[z * sA + (long)(n - 1) * lda + n - 1]);
 }
 
-// Launch the symmetric product of column k with sch tiles per workgroup.
+// Launch the symmetric product of column k with sch tiles per workgroup.  With
+// events, the launch itself records them at the kernel's start and end (so
+// the sampled duration is the kernel's own, without the gap before it).
 template <typename T, typename S>
 void symv_launch(hipStream_t s, int sch, int n, int k, int j, const S* A, int lda, long sA, int B, int nA,
-                 const HetrdWork<T>& w) {
+                 const HetrdWork<T>& w, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
     const int m = n - k - 1, nt = cdiv(m, ST), nch = cdiv(nt, sch), nb = HETRD_NB;
     // one workgroup column beyond the tiles' for the panel products
     const dim3 grid(nch + 1, nt, B), block(Sy<T, S>::THREADS);
+    if (ev0) {
+        if (sch == 2)
+            hipExtLaunchKernelGGL((symv_kernel<T, S, 2>), grid, block, 0, s, ev0, ev1, 0, n, k, j, nb, A, lda, sA,
+                                  nA, nt, nch, w);
+        else if (sch == 8)
+            hipExtLaunchKernelGGL((symv_kernel<T, S, 8>), grid, block, 0, s, ev0, ev1, 0, n, k, j, nb, A, lda, sA,
+                                  nA, nt, nch, w);
+        else
+            hipExtLaunchKernelGGL((symv_kernel<T, S, 4>), grid, block, 0, s, ev0, ev1, 0, n, k, j, nb, A, lda, sA,
+                                  nA, nt, nch, w);
+        return;
+    }
     if (sch == 2)
         hipLaunchKernelGGL((symv_kernel<T, S, 2>), grid, block, 0, s, n, k, j, nb, A, lda, sA, nA, nt, nch, w);
     else if (sch == 8)
@@ -686,11 +702,13 @@ void hetrd(hipStream_t s, int n, S* A, int lda, long sA, int batch, double* d, d
             const int sch = w.sch_for(k);
             int nt = cdiv(m, ST), nch = cdiv(nt, sch);
             int nA = cdiv(n - k, WC_ROWS);  // workgroups that wrote the partials of column k
-            bool smp = w.prof && w.prof->sample();
-            hipEvent_t e0 = smp ? w.prof->begin() : nullptr;
-            symv_launch<T, S>(s, sch, n, k, j, A, lda, sA, B, nA, w);
-            // algorithmic bytes of a Hermitian matrix-vector product: the lower triangle once
-            if (smp) w.prof->end(PROF_HEMV, e0, (double)sizeof(T) * m * (m + 1) / 2.0 * B);
+            const bool smp = w.prof && w.prof->sample();
+            hipEvent_t e0 = smp ? w.prof->take() : nullptr;
+            hipEvent_t e1 = smp ? w.prof->take() : nullptr;
+            symv_launch<T, S>(s, sch, n, k, j, A, lda, sA, B, nA, w, e0, e1);
+            // algorithmic bytes of a Hermitian matrix-vector product: the lower
+            // triangle once, in the storage precision
+            if (smp) w.prof->push(PROF_HEMV, e0, e1, (double)sizeof(S) * m * (m + 1) / 2.0 * B);
             hipLaunchKernelGGL((wcol_kernel<T, S>), dim3(cdiv(m, WC_ROWS), 1, B), dim3(64 * Wc<T>::NW), 0, s, n, k, j, nb,
                                (int)(j + 1 < jb), A, lda, sA, nt, nch, sch, nA, d, e, tau, w);
         }

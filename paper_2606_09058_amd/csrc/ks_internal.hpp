@@ -56,6 +56,20 @@ struct Prof {
         return e;
     }
     hipEvent_t begin() { return on ? rec_event() : nullptr; }
+    // an unrecorded event, for a launch that records it itself
+    hipEvent_t take() {
+        hipEvent_t e = nullptr;
+        if (!pool.empty()) {
+            e = pool.back();
+            pool.pop_back();
+        } else if (hipEventCreate(&e) != hipSuccess) {
+            return nullptr;
+        }
+        return e;
+    }
+    void push(int tag, hipEvent_t a, hipEvent_t b, double bytes) {
+        if (a && b) recs.push_back({tag, a, b, bytes});
+    }
     void end(int tag, hipEvent_t a, double bytes = 0.0) {
         if (!on || !a) return;
         hipEvent_t b = rec_event();
