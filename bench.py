@@ -101,7 +101,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: a single matrix of this solve does not shard, and "
-              "k-point sharding across GPUs is not part of this build (--gpus 1)", file=sys.stderr)
+              "k-point sharding across GPUs is not implemented here (--gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
