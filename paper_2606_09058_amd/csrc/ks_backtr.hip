@@ -47,7 +47,7 @@ __global__ __launch_bounds__(TF_Q) void t_factors_kernel(int n, int B, const T* 
     __shared__ T sg[H][H + 1];
     __shared__ T st[H];
     for (int e = threadIdx.x; e < jh * jh; e += blockDim.x) sg[e / jh][e % jh] = Th[(long)(e / jh) * B + e % jh];
-    if (threadIdx.x < jh) st[threadIdx.x] = tau[threadIdx.x];
+    if ((int)threadIdx.x < jh) st[threadIdx.x] = tau[threadIdx.x];
     __syncthreads();  // the quarter's block of G is in LDS before T_q overwrites it
     const int c = threadIdx.x;
     for (int i = 0; i < jh; ++i)
