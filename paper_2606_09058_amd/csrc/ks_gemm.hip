@@ -500,8 +500,25 @@ __global__ __launch_bounds__(256, 2) void gemm_big_kernel(int m, int n, int K, d
         __syncthreads();
         cur ^= 1;
     }
+    // With beta != 0, one row of blocks at a time: its C values are all
+    // requested before any of them is written back (a read of C placed after a
+    // write to C would wait for the memory once per element, since the
+    // compiler cannot tell that the addresses differ).
+    const bool acc_c = beta != 0.0;
 #pragma unroll
-    for (int i = 0; i < MI; ++i)
+    for (int i = 0; i < MI; ++i) {
+        T cv[NI][4];
+        if (acc_c) {
+#pragma unroll
+            for (int j = 0; j < NI; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = m0 + wm * WM + i * 16 + out_row<T>(lane, r);
+                    const int col = n0 + wn * WN + j * 16 + li;
+                    const bool ok = row < m && col < n && (uplo == UPLO_FULL || col <= row);
+                    cv[j][r] = ok ? C[(long)row * ldc + col] : zero_<T>();
+                }
+        }
 #pragma unroll
         for (int j = 0; j < NI; ++j)
 #pragma unroll
@@ -517,11 +534,11 @@ __global__ __launch_bounds__(256, 2) void gemm_big_kernel(int m, int n, int K, d
                         v = cre[i][j][r];
                     }
                     v = alpha * v;
-                    T* pc = C + (long)row * ldc + col;
-                    if (beta != 0.0) v += beta * (*pc);
-                    *pc = v;
+                    if (acc_c) v += beta * cv[j][r];
+                    C[(long)row * ldc + col] = v;
                 }
             }
+    }
 }
 
 template <typename T, int OPA, int OPB>
