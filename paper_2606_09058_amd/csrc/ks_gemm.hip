@@ -296,8 +296,25 @@ __device__ inline void gemm_tile(int m, int n, int K, double alpha, const T* A, 
         tile_mma(acc, sA, sB);
     }
     int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
+    // with beta != 0 a row of blocks' C values are all requested before any is
+    // written back (see the large-tile kernel); complex tiles read C in place,
+    // which keeps their register budget
+    const bool acc_c = beta != 0.0;
+    constexpr bool pre = !is_cplx<T>::value;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2; ++i) {
+        T cv[2][4];
+        if (pre && acc_c) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = m0 + wm * 32 + i * 16 + out_row<T>(lane, r);
+                    const int col = n0 + wn * 32 + j * 16 + (lane & 15);
+                    const bool ok = row < m && col < n && (uplo == UPLO_FULL || col <= row);
+                    cv[j][r] = ok ? C[(long)row * ldc + col] : zero_<T>();
+                }
+        }
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -307,10 +324,11 @@ __device__ inline void gemm_tile(int m, int n, int K, double alpha, const T* A, 
                 if (row < m && col < n && (uplo == UPLO_FULL || col <= row)) {
                     T v = alpha * acc_get(acc, i, j, r);
                     T* pc = C + (long)row * ldc + col;
-                    if (beta != 0.0) v += beta * (*pc);
+                    if (acc_c) v += beta * (pre ? cv[j][r] : *pc);
                     *pc = v;
                 }
             }
+    }
 }
 
 template <typename T, int OPA, int OPB>
