@@ -562,26 +562,40 @@ __global__ __launch_bounds__(256) void dc_gather_kernel(int n, int nm, const int
 }
 
 // Final order: value of merged column c is x_c (c < K) or the deflated value;
-// stable rank sort; lam[lo + rank] = value, src[lo + rank] = c.
+// stable rank sort; lam[lo + rank] = value, src[lo + rank] = c.  The values
+// every thread compares against pass through LDS in chunks, formed once per
+// workgroup instead of gathered from memory by every thread.
+constexpr int RANK_CHUNK = 2048;
 __global__ __launch_bounds__(256) void dc_rank_kernel(int n, int nm, const int* mlo, const int* mhi, DcWork w) {
+    __shared__ double sv[RANK_CHUNK];
     const int G = blockIdx.y, g = G % nm;
     w = dc_slice(w, G / nm, n);
-    int lo = mlo[g], hi = mhi[g];
-    int K0 = hi - lo, K = w.kk[G];
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= K0) return;
+    const int lo = mlo[g], hi = mhi[g];
+    const int K0 = hi - lo, K = w.kk[G];
+    if ((int)(blockIdx.x * blockDim.x) >= K0) return;  // the whole workgroup: no barrier is skipped
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool act = c < K0;
     const double* d = w.dnd + lo;
     auto val = [&](int q) -> double {
         return (q < K) ? d[w.orig[lo + q]] + w.tau[lo + q] : w.dfval[lo + q - K];
     };
-    double v = val(c);
+    const double v = act ? val(c) : 0.0;
     int rk = 0;
-    for (int q = 0; q < K0; ++q) {
-        double u = val(q);
-        rk += (u < v) || (u == v && q < c);
+    for (int q0 = 0; q0 < K0; q0 += RANK_CHUNK) {
+        const int cnt = min(RANK_CHUNK, K0 - q0);
+        __syncthreads();  // the previous chunk has been read
+        for (int e = threadIdx.x; e < cnt; e += blockDim.x) sv[e] = val(q0 + e);
+        __syncthreads();
+        if (act)
+            for (int e = 0; e < cnt; ++e) {
+                const double u = sv[e];
+                rk += (u < v) || (u == v && q0 + e < c);
+            }
     }
-    w.fval[lo + rk] = v;
-    w.fsrc[lo + rk] = c;
+    if (act) {
+        w.fval[lo + rk] = v;
+        w.fsrc[lo + rk] = c;
+    }
 }
 
 __global__ __launch_bounds__(256) void dc_permute_kernel(int n, int nm, const int* mlo, const int* mhi,
