@@ -208,12 +208,16 @@ __global__ __launch_bounds__(64) void dc_leaf_kernel(int n, const int* leaf_lo, 
 }
 
 // ---------------------------------------------------------------- merges
-// One workgroup per merge: form (D, z), merge-sort, deflate.
+// One workgroup per merge: form (D, z), merge-sort, deflate.  With use_lds the
+// launch provides K0 doubles of dynamic LDS and the two sorted lists are
+// staged there for the merge's binary searches.
+constexpr int DEFLATE_LDS_MAX = 8192;  // 64 KB of dynamic LDS
 __global__ __launch_bounds__(256) void dc_deflate_kernel(int n, int nm, const int* mlo, const int* mmid,
                                                          const int* mhi, const double* e,
                                                          const double* lam, const double* Z,
-                                                         DcWork w) {
+                                                         DcWork w, int use_lds) {
     __shared__ double sd[64], sz[64];
+    extern __shared__ double slam[];
     const int G = blockIdx.x, g = G % nm, bm = G / nm;
     w = dc_slice(w, bm, n);
     e += (long)bm * n;
@@ -227,8 +231,13 @@ __global__ __launch_bounds__(256) void dc_deflate_kernel(int n, int nm, const in
     double sg = (b >= 0.0) ? 1.0 : -1.0;
     const double rs2 = 0.70710678118654752440;
     double dmax = 0.0, zmax = 0.0;
+    if (use_lds) {
+        for (int c = t; c < K0; c += blockDim.x) slam[c] = lam[lo + c];
+        __syncthreads();
+    }
+    const double* L = use_lds ? (const double*)slam : lam + lo;  // L[q] = lam[lo + q]
     for (int c = t; c < K0; c += blockDim.x) {
-        double D = lam[lo + c];
+        double D = L[c];
         double z = (c < n1) ? Z[(long)(mid - 1) * n + lo + c] : sg * Z[(long)mid * n + lo + c];
         z *= rs2;
         // rank in the merged order (ties: first list first)
@@ -237,7 +246,7 @@ __global__ __launch_bounds__(256) void dc_deflate_kernel(int n, int nm, const in
             int a = 0, bb = K0 - n1;  // count of second-list entries < D
             while (a < bb) {
                 int h = (a + bb) >> 1;
-                if (lam[mid + h] < D) a = h + 1;
+                if (L[n1 + h] < D) a = h + 1;
                 else bb = h;
             }
             rank = c + a;
@@ -245,7 +254,7 @@ __global__ __launch_bounds__(256) void dc_deflate_kernel(int n, int nm, const in
             int a = 0, bb = n1;  // count of first-list entries <= D
             while (a < bb) {
                 int h = (a + bb) >> 1;
-                if (lam[lo + h] <= D) a = h + 1;
+                if (L[h] <= D) a = h + 1;
                 else bb = h;
             }
             rank = (c - n1) + a;
@@ -630,7 +639,9 @@ void stedc(hipStream_t s, const DcTree& tr, int batch, const double* d, const do
         const int* mmid = tr.d_mmid + off;
         const int* mhi = tr.d_mhi + off;
         const int mk = tr.max_k0[l];
-        hipLaunchKernelGGL(dc_deflate_kernel, dim3(NG), dim3(256), 0, s, n, nm, mlo, mmid, mhi, e, lam, Z, w);
+        const int dl = mk <= DEFLATE_LDS_MAX ? 1 : 0;
+        hipLaunchKernelGGL(dc_deflate_kernel, dim3(NG), dim3(256), dl ? (size_t)mk * sizeof(double) : 0, s, n, nm,
+                           mlo, mmid, mhi, e, lam, Z, w, dl);
         hipLaunchKernelGGL(dc_rotate_kernel, dim3(cdiv(mk, 256), NG), dim3(256), 0, s, n, nm, mlo, mhi, w, Z);
         hipLaunchKernelGGL(dc_secular_kernel, dim3(cdiv(mk, 4), NG), dim3(256), 0, s, n, nm, mlo, w, info);
         hipLaunchKernelGGL(dc_zhat_kernel, dim3(cdiv(mk, 4), NG), dim3(256), 0, s, n, nm, mlo, w);
