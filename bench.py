@@ -7,6 +7,11 @@ by bisection, occupations, band energy, density matrix) for one matrix, with
 inputs already resident in HBM.  Prints ONE JSON line.
 
     python bench.py [--steps K] [--warmup W] [--workload supercell6656]
+
+With --counter-workload it instead runs the short fixed workload that the
+memory-traffic counters are taken on (one rocprofv3 --pmc run per counter):
+a plain 1 GiB device fill and copy, whose counter readings give each
+counter's scale, then one FP64 ks_gevd (all eigenvectors) of --workload.
 """
 import argparse
 import hashlib
@@ -84,6 +89,32 @@ def cpu_baseline(p, n_sample):
                       "(%.0f electrons) took %.2f s; scaled by (%d/%d)^3" % (ns, ns, ne, dt, p.order, ns)}
 
 
+COPY_BYTES = 1 << 30
+
+
+def counter_workload(p):
+    """A plain copy of known size (the fill writes 1 GiB, the copy reads 1 GiB and
+    writes 1 GiB), then one FP64 solve whose kernels the counters measure."""
+    import numpy as np
+    import torch
+    from paper_2606_09058_amd import ks
+    x = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1.0)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    print("copy_bytes", COPY_BYTES, flush=True)
+    del x, y
+    plan = ks.Plan(p.n, batch=p.batch, complex=np.iscomplexobj(p.H), noncollinear=p.nsp == 2)
+    H = torch.from_numpy(p.H).cuda()
+    S = torch.from_numpy(p.S.astype(p.H.dtype)).cuda()
+    eps = torch.empty(plan._vshape(), dtype=torch.float64, device="cuda")
+    C = torch.empty(plan._mshape(), dtype=plan.mdtype, device="cuda")
+    plan.gevd(H, S, eps, C)
+    plan.check("counter workload")
+    print("solved", p.name, "order", p.order, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +128,8 @@ def main():
                     help="skip the FP64-vs-mixed comparison on the occupied window")
     ap.add_argument("--no-lowdin", action="store_true", help="skip the Loewdin-route comparison")
     ap.add_argument("--graph", action="store_true", help="plan with KS_PLAN_GRAPH (capture once, replay)")
+    ap.add_argument("--counter-workload", action="store_true",
+                    help="run the fixed workload of the rocprofv3 memory-counter runs and exit")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -112,6 +145,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     p = I.workload(args.workload)
+    if args.counter_workload:
+        counter_workload(p)
+        return
     cplx = np.iscomplexobj(p.H)
     stream = torch.cuda.Stream() if args.graph else torch.cuda.current_stream()
     torch.cuda.set_stream(stream)

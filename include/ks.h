@@ -111,7 +111,7 @@ typedef struct {
                         /* the solve takes all of them in one launch               */
     int32_t dtype;      /* KS_REAL64 or KS_COMPLEX128; noncollinear needs complex  */
     int32_t spin;       /* KS_COLLINEAR (g = 2) or KS_NONCOLLINEAR (g = 1)         */
-    int32_t precision;  /* KS_FP64 (KS_MIXED is reserved)                          */
+    int32_t precision;  /* KS_FP64 or KS_MIXED (FP32 trailing updates, refined)    */
     int32_t ld_h;       /* row stride of H, C, rho, grad_H; >= order               */
     int32_t ld_s;       /* row stride of S, grad_S; >= n                           */
     void*   stream;     /* hipStream_t every call is enqueued on (NULL = default)  */
@@ -193,7 +193,9 @@ ks_status ks_bloch_sum(ks_plan* plan, int32_t nR, const double* R, const double*
  * NULL for zero), writes grad_H [batch][order][ld_h] and grad_S [batch][n][ld_s]
  * such that dL = sum_k Re tr(grad_H^H dH) + Re tr(grad_S^H dS).  Needs ALL
  * eigenvectors (C from ks_gevd with il = 1, iu = order) and mu, occ from
- * ks_density; it keeps no state from the forward calls.  Spinor form: grad_S
+ * ks_density.  The k weights w_k (which enter E_band and the common mu) are
+ * those of the last ks_density call on this plan (uniform 1/batch before the
+ * first); nothing else is kept from the forward calls.  Spinor form: grad_S
  * is the sum of the two diagonal spin blocks of the gradient of diag(S, S). */
 ks_status ks_density_backward(ks_plan* plan, const double* eps, const void* C, const double* mu,
                               const double* occ, double kT, const void* grad_rho,

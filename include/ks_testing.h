@@ -40,6 +40,14 @@ int32_t ks_test_stedc(int32_t n, const double* d, const double* e, double* lam, 
 int32_t ks_test_hetrd(int32_t dtype, int32_t n, void* A, double* d, double* e, const double* X,
                       int32_t ncols, void* Y, void* stream);
 
+/* Iteration caps of the divide-and-conquer eigensolver for every later call in
+ * this process: Jacobi sweeps of the leaves (default 40) and iterations of the
+ * secular-equation solver (default 120); a value <= 0 restores the default.
+ * A step that reaches its cap records KS_ERR_NO_CONVERGENCE in the plan's info
+ * word and finishes normally (its outputs are then undefined).  Host-only; it
+ * lets a test drive that failure path with ordinary inputs. */
+int32_t ks_test_set_iteration_caps(int32_t leaf_sweeps, int32_t secular_iters);
+
 /* One v_mfma_f64_16x16x4_f64 where lane l feeds A[l%16][l/16] and B[l/16][l%16]
  * with A[i][0] = 100 i, A[i][1] = 1, B[0][j] = 1, B[1][j] = j (other k zero), so
  * D[i][j] = 100 i + j; out[lane * 4 + r] = accumulator register r of each lane. */

@@ -84,6 +84,9 @@ struct ks_plan {
     double v_tau = 0.0;        // the cutoff the V in use was formed with
     ks_plan* ov = nullptr;
     int mixed_sweeps = 2;
+    // k weights of the last ks_density call (uniform until then); the adjoint's
+    // chemical-potential and band-energy terms use the same weights
+    KWeights kw_last{};
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     long graph_captures = 0, graph_replays = 0;
@@ -742,6 +745,7 @@ ks_status ks_plan_create(const ks_plan_desc* d, ks_plan** out) {
     }
     p->bytes = bytes;
     layout(d, p);
+    p->kw_last = make_weights(p, nullptr);
     if (hipMemset(p->info, 0, 2 * sizeof(int)) != hipSuccess) {
         (void)hipFree(p->base);
         delete p;
@@ -901,6 +905,7 @@ ks_status ks_density(ks_plan* p, const double* eps, const void* C, int32_t il, i
             if (!(kweights[b] >= 0.0) || !isfinite(kweights[b])) return KS_ERR_INVALID_ARG;
     }
     KWeights kw = make_weights(p, kweights);
+    p->kw_last = kw;
     double* f = occ ? occ : p->occ;
     hipStream_t s = p->s;
     int order = p->order, ldh = p->d.ld_h, ncols = iu - il + 1;
@@ -1070,7 +1075,7 @@ ks_status ks_density_backward(ks_plan* p, const double* eps, const void* C, cons
         p->ascal = (double*)(p->adj + 3 * mm);
     }
     double g = p->nsp == 2 ? 1.0 : 2.0;
-    KWeights kw = make_weights(p, nullptr);
+    const KWeights kw = p->kw_last;
     hipEvent_t e = p->prof.begin();
     if (p->is_c)
         density_backward<cplx>(p->s, p->d.n, p->nsp, B, eps, (const cplx*)C, p->d.ld_h, mu, kT, g, kw,

@@ -214,6 +214,10 @@ int hetrd_tune(hipStream_t s, int n, T* A, int lda, long sA, int batch, double* 
 void stedc(hipStream_t s, const DcTree& tr, int batch, const double* d, const double* e, double* lam,
            double* Z, double* Z2, double* U, double* Qp, DcWork& w, int* info);
 
+// Test hook: iteration caps of the leaf Jacobi and the secular solver (<= 0
+// restores the defaults, 40 sweeps and 120 iterations).
+void stedc_set_caps(int leaf_sweeps, int secular_iters);
+
 void dc_tree_host(int n, std::vector<int>& mlo, std::vector<int>& mmid, std::vector<int>& mhi,
                   std::vector<int>& leaf_lo, std::vector<int>& leaf_hi, int& depth,
                   std::vector<int>& max_k0);

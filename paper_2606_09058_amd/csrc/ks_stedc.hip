@@ -84,7 +84,7 @@ __global__ void dc_init_kernel(int n, const double* d, const double* e, const in
 // Parallel cyclic Jacobi on the dense leaf (size <= DC_LEAF) in LDS.
 __global__ __launch_bounds__(64) void dc_leaf_kernel(int n, const int* leaf_lo, const int* leaf_hi,
                                                      const double* dw, const double* e, double* lam,
-                                                     double* Z, int* info) {
+                                                     double* Z, int* info, int max_sweeps) {
     constexpr int L = DC_LEAF;
     __shared__ double A[L][L + 1];
     __shared__ double VT[L][L + 1];
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(64) void dc_leaf_kernel(int n, const int* leaf_lo, 
     int m = s + (s & 1);
     int np = m / 2;
     int sweep = 0;
-    for (; sweep < 40 && s > 1; ++sweep) {
+    for (; sweep < max_sweeps && s > 1; ++sweep) {
         if (t == 0) any_rot = 0;
         __syncthreads();
         for (int r = 0; r < m - 1; ++r) {
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(64) void dc_leaf_kernel(int n, const int* leaf_lo, 
         }
         if (!any_rot) break;
     }
-    if (sweep >= 40 && t == 0) set_info(info, KS_ERR_NO_CONVERGENCE, 1);
+    if (sweep >= max_sweeps && s > 1 && t == 0) set_info(info, KS_ERR_NO_CONVERGENCE, 1);
     // stable ascending rank sort of the diagonal
     if (t < s) w[t] = A[t][t];
     __syncthreads();
@@ -373,7 +373,8 @@ __global__ __launch_bounds__(256) void dc_rotate_kernel(int n, int nm, const int
 }
 
 // Secular equation: one wavefront per root.
-__global__ __launch_bounds__(256) void dc_secular_kernel(int n, int nm, const int* mlo, DcWork w, int* info) {
+__global__ __launch_bounds__(256) void dc_secular_kernel(int n, int nm, const int* mlo, DcWork w, int* info,
+                                                         int max_iter) {
     const int G = blockIdx.y, g = G % nm;
     w = dc_slice(w, G / nm, n);
     int lo = mlo[g];
@@ -418,7 +419,7 @@ __global__ __launch_bounds__(256) void dc_secular_kernel(int n, int nm, const in
     double dor = d[o];
     double tau = 0.5 * (blo + bhi);
     bool conv = false;
-    for (int it = 0; it < 120; ++it) {
+    for (int it = 0; it < max_iter; ++it) {
         double psi = 0.0, phi = 0.0, dpsi = 0.0, dphi = 0.0, eabs = 0.0;
         for (int i = lane; i < K; i += 64) {
             double del = (d[i] - dor) - tau;
@@ -475,7 +476,7 @@ __global__ __launch_bounds__(256) void dc_secular_kernel(int n, int nm, const in
             double c = f - rho * S1 / D1;
             tn = (c > 0.0) ? tau + D1 + rho * S1 / c : 0.5 * (blo + bhi);
         }
-        if (!(tn > blo && tn < bhi) || it >= 60) tn = 0.5 * (blo + bhi);
+        if (!(tn > blo && tn < bhi) || it >= max_iter / 2) tn = 0.5 * (blo + bhi);
         tau = tn;
     }
     if (lane == 0) {
@@ -624,6 +625,20 @@ __global__ __launch_bounds__(256) void dc_permute_kernel(int n, int nm, const in
     if (r == lo) lam[lo + p] = w.fval[lo + p];
 }
 
+// Iteration caps of the leaf Jacobi sweeps and of the secular-equation
+// iterations.  A step that reaches its cap records KS_ERR_NO_CONVERGENCE and
+// still finishes normally.  The defaults are far above what any input needs
+// (quadratic convergence); a test hook lowers them to exercise that path.
+namespace {
+int g_leaf_sweeps = 40;
+int g_secular_iters = 120;
+}  // namespace
+
+void stedc_set_caps(int leaf_sweeps, int secular_iters) {
+    g_leaf_sweeps = leaf_sweeps > 0 ? leaf_sweeps : 40;
+    g_secular_iters = secular_iters > 0 ? secular_iters : 120;
+}
+
 void stedc(hipStream_t s, const DcTree& tr, int batch, const double* d, const double* e, double* lam,
            double* Z, double* Z2, double* U, double* Qp, DcWork& w, int* info) {
     const int n = tr.n, B = batch;
@@ -631,7 +646,7 @@ void stedc(hipStream_t s, const DcTree& tr, int batch, const double* d, const do
     hipLaunchKernelGGL(dc_init_kernel, dim3(cdiv(n, 256), B), dim3(256), 0, s, n, d, e, tr.d_leaf_lo, tr.nleaf,
                        w.dw);
     hipLaunchKernelGGL(dc_leaf_kernel, dim3(tr.nleaf, B), dim3(64), 0, s, n, tr.d_leaf_lo, tr.d_leaf_hi,
-                       (const double*)w.dw, e, lam, Z, info);
+                       (const double*)w.dw, e, lam, Z, info, g_leaf_sweeps);
     for (int l = tr.depth - 1; l >= 0; --l) {
         const int nm = 1 << l, NG = nm * B;
         const int off = nm - 1;
@@ -643,7 +658,8 @@ void stedc(hipStream_t s, const DcTree& tr, int batch, const double* d, const do
         hipLaunchKernelGGL(dc_deflate_kernel, dim3(NG), dim3(256), dl ? (size_t)mk * sizeof(double) : 0, s, n, nm,
                            mlo, mmid, mhi, e, lam, Z, w, dl);
         hipLaunchKernelGGL(dc_rotate_kernel, dim3(cdiv(mk, 256), NG), dim3(256), 0, s, n, nm, mlo, mhi, w, Z);
-        hipLaunchKernelGGL(dc_secular_kernel, dim3(cdiv(mk, 4), NG), dim3(256), 0, s, n, nm, mlo, w, info);
+        hipLaunchKernelGGL(dc_secular_kernel, dim3(cdiv(mk, 4), NG), dim3(256), 0, s, n, nm, mlo, w, info,
+                           g_secular_iters);
         hipLaunchKernelGGL(dc_zhat_kernel, dim3(cdiv(mk, 4), NG), dim3(256), 0, s, n, nm, mlo, w);
         hipLaunchKernelGGL(dc_colnorm_kernel, dim3(cdiv(mk, 4), NG), dim3(256), 0, s, n, nm, mlo, w);
         hipLaunchKernelGGL(dc_ugen_kernel, dim3(cdiv(mk, 256), mk, NG), dim3(256), 0, s, n, nm, mlo, w, U);

@@ -127,4 +127,9 @@ int32_t ks_test_hetrd(int32_t dtype, int32_t n, void* A, double* d, double* e, c
     return s2;
 }
 
+int32_t ks_test_set_iteration_caps(int32_t leaf_sweeps, int32_t secular_iters) {
+    ks::stedc_set_caps(leaf_sweeps, secular_iters);
+    return KS_OK;
+}
+
 }  // extern "C"

@@ -392,6 +392,64 @@ def overcomplete(seed=0, n=90, ms=(70,), nsp=1, cplx=False, kT=0.01):
     return p
 
 
+def known_spectrum_spinor(seed=0, n=4992, rank=64, lo=-28.8, hi=21.3, n_electrons=1536.0, kT=0.01,
+                          offdiag=0.45, close_pairs=48, ties=16, close_gap=1e-7):
+    """A spinor problem of order 2n with a spectrum fixed by construction, for
+    full-size checks that need no eigensolver on the host.
+
+    Lambda: 2n values drawn uniformly in [lo, hi] (the range of the 384-atom
+    noncollinear workload), with ``close_pairs`` pairs moved to within
+    ``close_gap`` Ha of each other and ``ties`` exact duplicates, sorted.
+    U: 2n x rank with orthonormal columns (QR of a complex Gaussian matrix);
+    Q = I - 2 U U^H is unitary, so A = Q diag(Lambda) Q has eigenvalues Lambda
+    and eigenvectors Q e_i; it is formed as
+    diag(Lambda) + [U, Lambda U] M [U, Lambda U]^H with M = [[4 U^H Lambda U, -2 I],
+    [-2 I, 0]].  L0: unit lower bidiagonal, complex subdiagonal of modulus <=
+    ``offdiag``; S = L0 L0^H (n x n) and H = B A B^H with B = diag(L0, L0), so
+    H C = diag(S, S) C eps has eps = Lambda and C = B^-H Q.
+
+    Returns a Problem (nsp = 2) whose meta holds Lambda, U and the subdiagonal
+    of L0."""
+    rng = np.random.default_rng(seed)
+    order = 2 * n
+    lam = np.sort(rng.uniform(lo, hi, size=order))
+    pos = rng.choice(order - 1, size=close_pairs + ties, replace=False)
+    for q, i in enumerate(pos):
+        lam[i + 1] = lam[i] + (close_gap * rng.uniform(0.1, 1.0) if q < close_pairs else 0.0)
+    lam = np.sort(lam)
+    G = rng.normal(size=(order, rank)) + 1j * rng.normal(size=(order, rank))
+    U, _ = np.linalg.qr(G)
+    LU = lam[:, None] * U
+    M11 = 4.0 * (U.conj().T @ LU)
+    P = np.concatenate([U, LU], axis=1)
+    M = np.zeros((2 * rank, 2 * rank), np.complex128)
+    M[:rank, :rank] = M11
+    M[:rank, rank:] = -2.0 * np.eye(rank)
+    M[rank:, :rank] = -2.0 * np.eye(rank)
+    A = (P @ M) @ P.conj().T
+    A[np.diag_indices(order)] += lam
+    a = offdiag * rng.uniform(0.0, 1.0, size=n - 1) * np.exp(2j * np.pi * rng.uniform(size=n - 1))
+    # B A B^H with B = diag(L0, L0): row i of B X is X_i + a_{i-1} X_{i-1} within a spin block
+    BA = A.copy()
+    for b in range(2):
+        o = b * n
+        BA[o + 1:o + n] += a[:, None] * A[o:o + n - 1]
+    H = BA.copy()
+    for b in range(2):
+        o = b * n
+        H[:, o + 1:o + n] += BA[:, o:o + n - 1] * a.conj()[None, :]
+    # Hermitian up to rounding (only the lower triangle is read by the solver);
+    # the diagonal is made exactly real
+    H[np.diag_indices(order)] = H[np.diag_indices(order)].real
+    S = np.zeros((n, n), np.complex128)
+    S[np.diag_indices(n)] = 1.0
+    S[np.arange(1, n), np.arange(1, n)] += np.abs(a) ** 2
+    S[np.arange(1, n), np.arange(n - 1)] = a
+    S[np.arange(n - 1), np.arange(1, n)] = a.conj()
+    return Problem(H, S, float(n_electrons), float(kT), 2, None, "known_spectrum_spinor",
+                   dict(lam=lam, U=U, a=a, seed=seed))
+
+
 # Named workloads: the five configurations and small stand-ins of the same kind.
 def workload(name: str, seed: int = 0) -> Problem:
     if name == "toy64":
@@ -400,6 +458,9 @@ def workload(name: str, seed: int = 0) -> Problem:
         return supercell(seed)
     if name == "noncollinear9984":
         return noncollinear(seed)
+    if name == "noncollinear4160":
+        # 160 atoms on a perturbed 8 x 5 x 4 lattice: order 4160 complex spinor, 640 electrons
+        return noncollinear(seed, nx=8, ny=5, nz=4)
     if name == "kpoints16x1300":
         return kpoint_batch(seed)
     if name == "diff2048":

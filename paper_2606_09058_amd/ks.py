@@ -322,16 +322,48 @@ class Plan:
         return dict(eps=eps, C=C, rho=rho, mu=mu, eband=eband, occ=occ)
 
 
+# Plans of KSDensity, one per (order, element type, spin form, device, stream):
+# a self-consistent loop that calls KSDensity every cycle reuses the plan's
+# workspace instead of allocating it again, and the Cholesky factor of S while
+# S is the same tensor, unmodified (same object, same version counter; the
+# plan keeps a reference to it, so its memory cannot be reused meanwhile).
+_PLANS = {}
+
+
+def clear_plan_cache():
+    """Destroy the plans KSDensity keeps (frees their device workspace)."""
+    for plan, _ in _PLANS.values():
+        plan.close()
+    _PLANS.clear()
+
+
+def _density_plan(n, cplx, noncollinear, device):
+    stream = torch.cuda.current_stream(device)
+    key = (int(n), bool(cplx), bool(noncollinear), device.index, stream.cuda_stream)
+    ent = _PLANS.get(key)
+    if ent is None:
+        ent = [Plan(n, complex=cplx, noncollinear=noncollinear, stream=stream), None]
+        _PLANS[key] = ent
+    return ent
+
+
 class KSDensity(torch.autograd.Function):
     """(H, S) -> (rho, E_band) through ks_gevd + ks_density; backward through
     ks_density_backward.  Gradients are the Hermitian matrices grad_H, grad_S with
-    dL = Re tr(grad_H^H dH) + Re tr(grad_S^H dS) (torch's convention for real L)."""
+    dL = Re tr(grad_H^H dH) + Re tr(grad_S^H dS) (torch's convention for real L).
+    The plan is cached per shape, type, device and stream, and KS_REUSE_S is
+    passed while S is the same unmodified tensor as in the previous call."""
 
     @staticmethod
     def forward(ctx, H, S, n_electrons, kT, noncollinear=False):
         n = S.shape[-1]
-        plan = Plan(n, complex=H.is_complex(), noncollinear=noncollinear)
-        out = plan.solve(H.contiguous(), S.contiguous(), n_electrons, kT)
+        ent = _density_plan(n, H.is_complex(), noncollinear, H.device)
+        plan = ent[0]
+        Sc = S.contiguous()
+        last = ent[1]
+        reuse = last is not None and last[0] is Sc and last[1] == Sc._version
+        out = plan.solve(H.contiguous(), None if reuse else Sc, n_electrons, kT, reuse_s=reuse)
+        ent[1] = (Sc, Sc._version)
         ctx.plan = plan
         ctx.kT = float(kT)
         ctx.save_for_backward(out["eps"], out["C"], out["mu"], out["occ"])

@@ -88,11 +88,74 @@ def test_noncollinear9984_full_size():
     assert orth < 1e-11, orth
     assert abs(tr - p.n_electrons) < 1e-10 * p.n_electrons
     assert herm < 1e-13 and comm < 1e-12
+    assert np.all(np.diff(host(out["eps"])) >= 0)
     g = golden("noncollinear9984")
     if g is not None:
         assert g["inputs_sha256"] == p.digest()
         check_against_golden(g, host(out["eps"])[None], out["mu"].item(), out["eband"].item(),
                              [host(out["rho"])], p.order)
+
+
+def test_noncollinear4160_against_oracle():
+    """The spinor workload on a 160-atom lattice (order 4160 complex: 256-reflector
+    back-transform blocks, large-tile complex GEMMs and divide-and-conquer merges
+    above 2048) against the oracle's stored eigenvalues, mu, E_band and sampled
+    density entries."""
+    announce("noncollinear4160 vs oracle")
+    p = I.workload("noncollinear4160")
+    g = golden("noncollinear4160")
+    assert g is not None and g["inputs_sha256"] == p.digest()
+    plan, H, S, out = gpu_solve(p)
+    res, orth, tr, herm, comm = properties(H, S, out, 2)
+    assert res < 1e-12 and orth < 1e-11 and herm < 1e-13 and comm < 1e-12
+    assert abs(tr - p.n_electrons) < 1e-10 * p.n_electrons
+    check_against_golden(g, host(out["eps"])[None], out["mu"].item(), out["eband"].item(),
+                         [host(out["rho"])], p.order)
+
+
+def _known_rows(p, rows):
+    """Rows of C = B^-H Q for known_spectrum_spinor: row l (spin block b, local
+    index i) is conj(y)^T Q with y = L0^-1 e_i in block b (forward substitution
+    on the bidiagonal) and Q = I - 2 U U^H."""
+    n, order = p.n, p.order
+    a = p.meta["a"]
+    U = p.meta["U"]
+    out = np.zeros((len(rows), order), np.complex128)
+    for r, l in enumerate(rows):
+        b, i = divmod(int(l), n)
+        y = np.zeros(order, np.complex128)
+        y[b * n + i] = 1.0
+        y[b * n + i + 1:b * n + n] = np.cumprod(-a[i:])
+        yc = y.conj()
+        out[r] = yc - 2.0 * (yc @ U) @ U.conj().T
+    return out
+
+
+def test_known_spectrum_spinor9984():
+    """Order 9984 complex spinor problem with a spectrum fixed by construction
+    (H = B Q Lambda Q B^H, S = L0 L0^H, B = diag(L0, L0); close pairs 1e-7 Ha
+    apart and exact ties): every eigenvalue within 1e-10 Ha of Lambda, mu and
+    E_band from the oracle's bisection on Lambda, and a 64 x 64 block of rho
+    against C = B^-H Q of the construction, element by element."""
+    from oracle import oracle as O
+    announce("known spectrum 9984")
+    p = I.known_spectrum_spinor(seed=0)
+    lam = p.meta["lam"]
+    plan, H, S, out = gpu_solve(p)
+    plan.check("known spectrum solve")
+    eps = host(out["eps"])
+    assert np.all(np.diff(eps) >= 0)
+    assert np.abs(eps - lam).max() < 1e-10
+    fr = O.fermi(lam, p.n_electrons, p.kT, p.g)
+    assert abs(out["mu"].item() - fr["mu"]) < 1e-9
+    assert abs(out["eband"].item() - fr["eband"]) < 1e-9 * max(1.0, abs(fr["eband"]))
+    rng = np.random.default_rng(7)
+    R = np.sort(rng.choice(p.order, 64, replace=False))
+    M = np.sort(rng.choice(p.order, 64, replace=False))
+    CR, CM = _known_rows(p, R), _known_rows(p, M)
+    ref = (CR * fr["occ"]) @ CM.conj().T
+    rho = out["rho"][torch.as_tensor(R, device="cuda")][:, torch.as_tensor(M, device="cuda")]
+    assert np.abs(host(rho) - ref).max() < 1e-9
 
 
 def test_kpoints16x1300_full_size():

@@ -137,3 +137,42 @@ def test_mixed_window_must_hold_the_occupied_states():
     plan = ks.Plan(p.n, precision=ks.KS_MIXED)
     with pytest.raises(ks.KSError):
         plan.solve(dev(p.H), dev(p.S), p.n_electrons, p.kT, il=1, iu=8)
+
+
+def test_mixed_kpoints16x1300_full_size():
+    """The batched k-point workload at full size (16 x 1300 complex) in KS_MIXED,
+    window every state below the stored mu + 0.4 Ha: per-k-point window
+    eigenvalues, mu, E_band and the sampled density entries against the
+    oracle's stored values; the window residual and C^H S C = I on the device."""
+    import json
+    import os
+    announce("mixed kpoints16x1300 full size")
+    p = I.workload("kpoints16x1300")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "kpoints16x1300.json")
+    gd = json.load(open(path))
+    assert gd["inputs_sha256"] == p.digest()
+    eps_o = np.array(gd["eps"]).reshape(p.batch, p.order)
+    iu = window_top(eps_o, gd["mu"])
+    plan = ks.Plan(p.n, batch=p.batch, complex=True, precision=ks.KS_MIXED)
+    H = dev(p.H)
+    S = dev(p.S)
+    out = plan.solve(H, S, p.n_electrons, p.kT, il=1, iu=iu, kweights=p.weights)
+    eps = host(out["eps"])
+    assert np.abs(eps[:, :iu] - eps_o[:, :iu]).max() < EPS_TOL
+    assert abs(out["mu"].item() - gd["mu"]) < 1e-9
+    assert abs(out["eband"].item() - gd["eband"]) < 1e-9 * max(1.0, abs(gd["eband"]))
+    idx = np.array(gd["rho_idx"])
+    ii = torch.as_tensor(idx[:, 0], device="cuda")
+    jj = torch.as_tensor(idx[:, 1], device="cuda")
+    for k in range(p.batch):
+        ref = np.array(gd["rho_samples"][k])
+        ref = ref[:, 0] + 1j * ref[:, 1]
+        got = host(out["rho"][k][ii, jj])
+        assert np.abs(got - ref).max() < RHO_TOL
+        Ck = out["C"][k][:, :iu]
+        ek = out["eps"][k][:iu].to(torch.complex128)
+        R = H[k] @ Ck - (S[k] @ Ck) * ek[None, :]
+        res = (torch.linalg.norm(R) / (torch.linalg.norm(H[k]) * torch.linalg.norm(Ck))).item()
+        G = Ck.conj().T @ S[k] @ Ck
+        orth = (G - torch.eye(iu, dtype=G.dtype, device="cuda")).abs().max().item()
+        assert res < RES_TOL and orth < ORTH_TOL, (k, res, orth)

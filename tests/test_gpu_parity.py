@@ -3,6 +3,7 @@ oracle on seeded NAO-shaped inputs, edge cases and device-side failures.
 
 Tolerances (FP64): eigenvalues 1e-10 Ha, residual ||HC - SC eps|| / (||H|| ||C||)
 1e-12, |C^H S C - I| 1e-11, density 1e-9, mu and E_band 1e-9."""
+import ctypes
 import json
 import os
 
@@ -442,3 +443,92 @@ def _loss(H, S, p, W):
     with torch.no_grad():
         rho, eb = ks.KSDensity.apply(dev(H), dev(S), p.n_electrons, p.kT)
         return float(((W * rho).real.sum() + 0.5 * eb.sum()).item())
+
+
+def test_adjoint_weighted_kpoint_batch():
+    """Batched backward with non-uniform k weights: the weights of the forward
+    ks_density call enter the common-mu coupling and the band-energy terms."""
+    announce("adjoint weighted batch")
+    ps = [I.toy(seed=s, natoms=6, norb=8, edge=9.0, n_electrons=24.0, kT=0.03, phases=True) for s in (31, 32)]
+    H = np.stack([p.H for p in ps])
+    S = np.stack([p.S for p in ps])
+    wk = np.array([0.3, 0.7])
+    ne, kT, ebar = 24.0, 0.03, 0.4
+    n = ps[0].n
+    plan = ks.Plan(n, batch=2, complex=True)
+    out = plan.solve(dev(H), dev(S), ne, kT, kweights=wk)
+    rng = np.random.default_rng(5)
+    W = rng.normal(size=(2, n, n)).astype(np.complex128)
+    gH = torch.zeros((2, n, n), dtype=torch.complex128, device="cuda")
+    gS = torch.zeros((2, n, n), dtype=torch.complex128, device="cuda")
+    ge = torch.tensor([ebar], dtype=torch.float64, device="cuda")
+    plan.density_backward(out["eps"], out["C"], out["mu"], out["occ"], kT, dev(W), ge, gH, gS)
+    plan.check("weighted backward")
+    eo, Co = zip(*[O.gevd(H[k], S[k]) for k in range(2)])
+    fr = O.fermi(np.stack(eo), ne, kT, 2.0, wk=wk)
+    assert abs(float(host(out["mu"])[0]) - fr["mu"]) < MU_TOL
+    Hb, Sb = O.adjoint(np.stack(eo), np.stack(Co), fr["mu"], kT, 2.0, Gbar=W, ebar=ebar, wk=wk)
+    assert np.abs(host(gH) - Hb).max() < 1e-8 * max(1.0, np.abs(Hb).max())
+    assert np.abs(host(gS) - Sb).max() < 1e-8 * max(1.0, np.abs(Sb).max())
+    plan.close()
+
+
+def test_no_convergence_flagged():
+    """Iteration caps lowered through the test hook: the divide-and-conquer leaf
+    sweeps and secular iterations stop early, record KS_ERR_NO_CONVERGENCE, and
+    every kernel still finishes (the caps are restored afterwards)."""
+    announce("no convergence")
+    L = ks.lib()
+    L.ks_test_set_iteration_caps.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    L.ks_test_set_iteration_caps.restype = ctypes.c_int32
+    p = I.toy(seed=4, natoms=8, norb=8)
+    try:
+        for caps in [(1, 120), (40, 1)]:
+            assert L.ks_test_set_iteration_caps(*caps) == 0
+            _, plan = solve_gpu(p, check=False)
+            st, info = plan.get_info()
+            assert st == 3 and info == -3, (caps, st, info)
+            plan.close()
+    finally:
+        L.ks_test_set_iteration_caps(0, 0)
+    g, plan = solve_gpu(p)
+    plan.close()
+
+
+def test_alloc_failure_reported():
+    """A descriptor whose workspace exceeds the device memory: KS_ERR_ALLOC from
+    ks_plan_create, before any allocation, and no plan."""
+    announce("alloc failure")
+    L = ks.lib()
+    d = ks.PlanDesc(20000, 64, ks.KS_REAL64, ks.KS_COLLINEAR, ks.KS_FP64, 20000, 20000, None, 0)
+    need = L.ks_plan_workspace_bytes(ctypes.byref(d))
+    free, total = torch.cuda.mem_get_info()
+    assert need > total
+    h = ctypes.c_void_p()
+    assert L.ks_plan_create(ctypes.byref(d), ctypes.byref(h)) == 7
+    assert not h.value
+    with pytest.raises(ks.KSError) as ex:
+        ks.Plan(20000, batch=64)
+    assert ex.value.status == 7
+
+
+def test_ksdensity_reuses_plan_and_overlap_factor():
+    """KSDensity keeps one plan per shape and stream and passes KS_REUSE_S while S
+    is the same unmodified tensor; an in-place change of S (new version) or a new
+    S tensor factors again.  Every call matches the oracle."""
+    announce("KSDensity cache")
+    ks.clear_plan_cache()
+    p = I.toy(seed=13, natoms=5, norb=8, n_electrons=16.0, kT=0.02, phases=True)
+    S = dev(p.S)
+    for H in (p.H, p.H + 0.05 * np.diag(np.arange(p.order))):
+        rho, eb = ks.KSDensity.apply(dev(H), S, p.n_electrons, p.kT)
+        o = O.solve(H, p.S, p.n_electrons, p.kT)
+        assert np.abs(host(rho) - o["rho"]).max() < RHO_TOL
+    assert len(ks._PLANS) == 1
+    S2 = p.S * 1.1
+    S.mul_(1.1)  # in place: the cached factor is stale
+    rho, eb = ks.KSDensity.apply(dev(p.H), S, p.n_electrons, p.kT)
+    o = O.solve(p.H, S2, p.n_electrons, p.kT)
+    assert np.abs(host(rho) - o["rho"]).max() < RHO_TOL
+    ks.clear_plan_cache()
+    assert not ks._PLANS

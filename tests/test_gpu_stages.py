@@ -320,3 +320,30 @@ def test_hetrd_similarity_large_orders(L, n):
     T = tridiag(dh, eh)
     assert np.abs(Q.T @ Q - np.eye(n)).max() < 1e-12
     assert np.abs(Q @ T @ Q.T - A).max() < 1e-12 * max(1.0, np.abs(A).max()) * n
+
+
+@pytest.mark.parametrize("n", [4100, 6150])
+def test_hetrd_similarity_large_orders_complex(L, n):
+    """Complex Hermitian orders 4100 and 6150: the complex symmetric product and
+    column kernels over many panels, 256-reflector complex compact-WY blocks with
+    a ragged last block and the complex large-tile GEMMs.  Q unitary and
+    Q T Q^H = A (which fix eig(T) = eig(A)), checked with FP64 products on the
+    device."""
+    announce("hetrd complex", n)
+    rng = np.random.default_rng(n + 3)
+    A = I.random_hermitian(rng, n, True)
+    Ad = dev(A)
+    A0 = Ad.clone()
+    d = torch.zeros(n, dtype=torch.float64, device="cuda")
+    e = torch.zeros(n, dtype=torch.float64, device="cuda")
+    X = dev(np.eye(n))
+    Y = torch.zeros((n, n), dtype=torch.complex128, device="cuda")
+    assert L.ks_test_hetrd(1, n, P(Ad), P(d), P(e), P(X), n, P(Y), stream_handle()) == 0
+    torch.cuda.synchronize()
+    T = torch.diag(d.to(torch.complex128)) + torch.diag(e[:n - 1].to(torch.complex128), 1) + \
+        torch.diag(e[:n - 1].to(torch.complex128), -1)
+    Yh = Y.conj().T.contiguous()
+    err_u = ((Yh @ Y) - torch.eye(n, dtype=torch.complex128, device="cuda")).abs().max().item()
+    err_s = ((Y @ T) @ Yh - A0).abs().max().item()
+    assert err_u < 1e-12, err_u
+    assert err_s < 1e-12 * max(1.0, A0.abs().max().item()) * n, err_s

@@ -560,3 +560,60 @@ def test_adjoint_one_by_one_closed_form():
     Hb, Sb = O.adjoint(r["eps"], r["C"], r["mu"], 0.1, 2.0, Gbar=np.array([[1.0]]))
     assert abs(Hb[0, 0]) < 1e-12
     assert abs(Sb[0, 0] - (-1.2 / 1.7 ** 2)) < 1e-12
+
+
+def _forward_k(Hs, Ss, ne, kT, wk, Ws, wE):
+    """Weighted k-point loss L = sum_k Re sum W_k rho_k + wE E_band, one mu over k."""
+    eps, Cs = zip(*[O.gevd(H, S) for H, S in zip(Hs, Ss)])
+    fr = O.fermi(np.stack(eps), ne, kT, 2.0, wk=wk)
+    occ = np.atleast_2d(fr["occ"])
+    L = wE * fr["eband"]
+    for k in range(len(Hs)):
+        L += np.sum(Ws[k] * O.density(Cs[k], occ[k])).real
+    return L, np.stack(eps), np.stack(Cs), fr
+
+
+def test_adjoint_weighted_kpoints_central_differences():
+    """Two k-points with weights (0.3, 0.7) and one common mu: the batched adjoint
+    (the mu coupling a_k = w_k sum Gt_ii f' / sum w f' and the weighted E_band
+    terms) equals central differences of the weighted loss along random
+    Hermitian directions of both k-points' H and S."""
+    rng = np.random.default_rng(21)
+    n, nk = 6, 2
+    Hs = [herm(rng, n, True) * 0.5 for _ in range(nk)]
+    Ss = [spd(rng, n, True) / n for _ in range(nk)]
+    wk = np.array([0.3, 0.7])
+    ne, kT, wE = 5.0, 0.25, 0.6
+    Ws = [rng.normal(size=(n, n)) for _ in range(nk)]
+    _, eps, Cs, fr = _forward_k(Hs, Ss, ne, kT, wk, Ws, wE)
+    Hb, Sb = O.adjoint(eps, Cs, fr["mu"], kT, 2.0, Gbar=np.stack(Ws).astype(np.complex128), ebar=wE,
+                       wk=wk)
+    h = 1e-6
+    for t in range(4):
+        dH = [herm(rng, n, True) for _ in range(nk)]
+        dS = [herm(rng, n, True) * 0.1 for _ in range(nk)]
+        lp = _forward_k([H + h * d for H, d in zip(Hs, dH)], [S + h * d for S, d in zip(Ss, dS)],
+                        ne, kT, wk, Ws, wE)[0]
+        lm = _forward_k([H - h * d for H, d in zip(Hs, dH)], [S - h * d for S, d in zip(Ss, dS)],
+                        ne, kT, wk, Ws, wE)[0]
+        fd = (lp - lm) / (2 * h)
+        an = sum(np.sum(Hb[k].conj() * dH[k]).real + np.sum(Sb[k].conj() * dS[k]).real for k in range(nk))
+        assert abs(fd - an) < 1e-6 * max(1.0, abs(fd)), (t, fd, an)
+    # with equal weights the mu coupling differs: the weights are not a no-op
+    Hb2, _ = O.adjoint(eps, Cs, fr["mu"], kT, 2.0, Gbar=np.stack(Ws).astype(np.complex128), ebar=wE)
+    assert np.abs(Hb2 - Hb).max() > 1e-3
+
+
+def test_known_spectrum_construction_matches_oracle():
+    """The known-spectrum spinor construction that the full-size GPU test uses:
+    at a small order the oracle finds exactly Lambda, and rho built from the
+    construction's C = B^-H Q rows equals the oracle's rho."""
+    from tests.test_gpu_fullsize import _known_rows
+    p = I.known_spectrum_spinor(seed=3, n=40, rank=8, lo=-3.0, hi=2.0, n_electrons=30.0, kT=0.05,
+                                close_pairs=3, ties=2)
+    Hh = np.tril(p.H) + np.tril(p.H, -1).conj().T
+    r = O.solve(Hh, p.S, p.n_electrons, p.kT, nsp=2)
+    assert np.abs(r["eps"] - p.meta["lam"]).max() < 1e-12
+    C = _known_rows(p, np.arange(p.order))
+    rho = (C * r["occ"]) @ C.conj().T
+    assert np.abs(rho - r["rho"]).max() < 1e-11
