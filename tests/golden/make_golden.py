@@ -38,6 +38,13 @@ def sample_idx(order, seed=2):
     return rng.integers(0, order, size=(NSAMPLE, 2))
 
 
+def host_cpu():
+    for line in open("/proc/cpuinfo"):
+        if line.startswith("model name"):
+            return line.split(":", 1)[1].strip()
+    return "unknown"
+
+
 def one_k(H, S, nsp, nthreads):
     t = time.time()
     eps, C = O.gevd(H, S, nsp=nsp, nthreads=nthreads)
@@ -46,7 +53,7 @@ def one_k(H, S, nsp, nthreads):
 
 def run(name, nthreads=0):
     p = I.workload(name)
-    out = dict(workload=name, inputs_sha256=p.digest(), n_electrons=p.n_electrons, kT=p.kT,
+    out = dict(workload=name, inputs_sha256=p.digest(), n_electrons=p.n_electrons, kT=p.kT, host_cpu=host_cpu(),
                g=p.g, nsp=p.nsp, order=p.order, batch=p.batch, oracle_threads=O.max_threads()
                if nthreads <= 0 else nthreads)
     Hs = p.H if p.batch > 1 else p.H[None]
