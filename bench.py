@@ -1,12 +1,18 @@
 #!/usr/bin/env python3
 """Benchmark of the generalized Kohn-Sham eigensolve + density build on one MI355X.
 
-One step = ks_gevd (Cholesky of S, reduction, Householder tridiagonalisation,
-divide and conquer, back-transform; all eigenvectors) + ks_density (Fermi level
-by bisection, occupations, band energy, density matrix) for one matrix, with
-inputs already resident in HBM.  Prints ONE JSON line.
+One step = ks_gevd (Cholesky of S, reduction, tridiagonalisation, divide and
+conquer, back-transform; all eigenvectors) + ks_density (Fermi level by
+bisection, occupations, band energy, density matrix) for one matrix (or one
+batch of k-points), with inputs already resident in HBM.  Prints ONE JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--workload supercell6656]
+    python bench.py [--steps K] [--warmup W] [--workload supercell6656] [--route twostage]
+
+`value` is the main workload's seconds per solve on the chosen tridiagonalisation
+route; the line also carries the other route, and (unless --no-configs) the
+other two sizes of the metric: the 2N = 9984 spinor problem and the 16 x 1300
+k-point batch (both routes, FP64 vs mixed on the occupied window, graph vs
+eager launches for the batch), at reduced step counts stated in the line.
 
 With --counter-workload it instead runs the short fixed workload that the
 memory-traffic counters are taken on (one rocprofv3 --pmc run per counter):
@@ -16,6 +22,7 @@ counter's scale, then one FP64 ks_gevd (all eigenvectors) of --workload.
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -35,13 +42,17 @@ WORKLOADS = {
     "kpoints16x1300": "16 k-points x N=1300 complex Hermitian (100-atom cell, 27 lattice vectors), "
                       "400 electrons, kT=0.01 Ha, one common Fermi level, all k in each launch",
 }
+# tridiagonalisation routes: one-stage Householder, or dense -> band -> tridiagonal
+ROUTE_FLAGS = {"onestage": 0, "twostage": 8}
+DEFAULT_ROUTE = "onestage"
 
 
 def nominal_flops(order, ncols, m_occ, cplx, n_s):
     """LAPACK-style nominal counts of the steps performed (real; complex x4):
     Cholesky n^3/3 (n = order of S), reduction order^3, tridiagonalisation
     4 order^3/3, back-transform 2 order^2 ncols + triangular solve order^2 ncols,
-    density order^2 m_occ."""
+    density order^2 m_occ.  The same count for both routes (the two-stage
+    route performs more flops than it is credited with)."""
     f = n_s ** 3 / 3.0 + order ** 3 + 4.0 * order ** 3 / 3.0 + 3.0 * order ** 2 * ncols + order ** 2 * m_occ
     return f * (4.0 if cplx else 1.0)
 
@@ -70,23 +81,53 @@ def measured_traffic(workload):
             "source": os.path.relpath(path, ROOT)}
 
 
-def cpu_baseline(p, n_sample):
-    """The oracle as it stands, on the leading n_sample x n_sample principal block of
-    the same workload (electron count scaled), scaled by (order / n_sample)^3."""
+def host_cpu():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(p, sizes):
+    """The oracle as it stands (Cholesky + cyclic Jacobi + back-substitution +
+    Fermi bisection + density) timed on leading principal blocks of the same
+    workload (electron count scaled) at several sizes; the time is extrapolated
+    to the full order with the exponent fitted to those sizes (cyclic Jacobi
+    needs more sweeps as the order grows, so the exponent exceeds 3).  The line
+    also quotes the stored full-size oracle run of the same workload, if the
+    fixture records one."""
     import numpy as np
     from oracle import oracle as O
-    ns = min(n_sample, p.n)
-    H = np.ascontiguousarray(p.H[:ns, :ns])
-    S = np.ascontiguousarray(p.S[:ns, :ns])
-    ne = p.n_electrons * ns / p.n
-    t0 = time.perf_counter()
-    O.solve(H, S, ne, p.kT, nsp=1)
-    dt = time.perf_counter() - t0
-    scale = (p.order / ns) ** 3
-    return {"value": dt * scale, "unit": "s/solve", "cores": O.max_threads(), "kind": "oracle",
-            "sample": "oracle (Cholesky + cyclic Jacobi + back-substitution + Fermi bisection + "
-                      "density) on the leading %dx%d principal block of the same workload "
-                      "(%.0f electrons) took %.2f s; scaled by (%d/%d)^3" % (ns, ns, ne, dt, p.order, ns)}
+    pts = []
+    for ns in sizes:
+        ns = min(ns, p.n)
+        H = np.ascontiguousarray(p.H[:ns, :ns])
+        S = np.ascontiguousarray(p.S[:ns, :ns])
+        t0 = time.perf_counter()
+        O.solve(H, S, p.n_electrons * ns / p.n, p.kT, nsp=1)
+        pts.append((ns, time.perf_counter() - t0))
+    x = np.log([a for a, _ in pts])
+    y = np.log([b for _, b in pts])
+    slope, icpt = np.polyfit(x, y, 1)
+    est = math.exp(icpt + slope * math.log(p.order))
+    out = {"value": est, "unit": "s/solve", "cores": O.max_threads(), "kind": "oracle",
+           "host_cpu": host_cpu(),
+           "sample": "oracle on leading principal blocks of the same workload: " +
+                     ", ".join("%d: %.2f s" % (a, b) for a, b in pts) +
+                     "; time ~ order^%.2f fitted, extrapolated to order %d" % (slope, p.order),
+           "fitted_exponent": slope}
+    gpath = os.path.join(ROOT, "tests", "golden", p.name + ".json")
+    if os.path.exists(gpath):
+        g = json.load(open(gpath))
+        if g.get("gevd_seconds"):
+            out["full_size_oracle_run"] = {
+                "gevd_seconds": float(sum(g["gevd_seconds"])), "threads": g.get("oracle_threads"),
+                "host_cpu": g.get("host_cpu", "not recorded (the fixture predates the field)"),
+                "source": os.path.relpath(gpath, ROOT)}
+    return out
 
 
 COPY_BYTES = 1 << 30
@@ -115,18 +156,121 @@ def counter_workload(p):
     print("solved", p.name, "order", p.order, flush=True)
 
 
+def phase_dict(prof, steps):
+    names = ["cholesky", "reduce", "tridiag", "dc", "backtransform", "density", "adjoint", "refine"]
+    return {nm: prof.phase_ms[i] / steps for i, nm in enumerate(names)}
+
+
+def time_route(p, H, S, route, steps, warmup, stride, stream, graph=False, warm=True, tag=""):
+    """W warm-up and K timed solves (gevd, all eigenvectors, + density) on one
+    plan of the given route; events on the plan's stream.  Returns the timings,
+    the sampled symmetric-product launches (one-stage route), the phase times
+    and the last solve's outputs."""
+    import numpy as np
+    import torch
+    from paper_2606_09058_amd import ks
+    flags = ks.KS_PLAN_AUTOTUNE | ROUTE_FLAGS[route] | (ks.KS_PLAN_GRAPH if graph else 0)
+    with torch.cuda.stream(stream):
+        plan = ks.Plan(p.n, batch=p.batch, complex=np.iscomplexobj(p.H), noncollinear=p.nsp == 2, stream=stream,
+                       flags=flags)
+        eps = torch.empty(plan._vshape(), dtype=torch.float64, device="cuda")
+        C = torch.empty(plan._mshape(), dtype=plan.mdtype, device="cuda")
+        rho = torch.empty_like(C)
+        mu = torch.empty(1, dtype=torch.float64, device="cuda")
+        eband = torch.empty(1, dtype=torch.float64, device="cuda")
+        occ = torch.empty(plan._vshape(), dtype=torch.float64, device="cuda")
+
+    def step(reuse=False):
+        plan.gevd(H, S, eps, C, reuse_s=reuse)
+        plan.density(eps, C, p.n_electrons, p.kT, rho, mu, eband, occ=occ, kweights=p.weights)
+
+    for _ in range(warmup):
+        step()
+    plan.check(tag + route + " warm-up")
+    plan.get_profile()  # clear
+    plan.set_profiling(True, stride)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / steps
+    prof = plan.get_profile()
+    plan.set_profiling(False)
+    plan.check(tag + route + " timed steps")
+    ms_warm = None
+    if warm:
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            step(reuse=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_warm = e0.elapsed_time(e1) / steps
+        plan.check(tag + route + " warm steps")
+    return dict(plan=plan, eps=eps, C=C, rho=rho, mu=mu, eband=eband, occ=occ, ms=ms, ms_warm=ms_warm,
+                prof=prof, wall=wall, phases=phase_dict(prof, steps))
+
+
+def symv_roofline(prof, traffic):
+    hemv_avg_us = 1e3 * prof.hemv_ms / max(1, prof.hemv_launches)
+    hemv_gbs = prof.hemv_bytes / max(1e-12, prof.hemv_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": "symv_kernel (trailing Hermitian matrix-vector product of the "
+                                      "one-stage tridiagonalisation)",
+            "achieved": hemv_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": hemv_gbs / PEAK_HBM_GBS,
+            "traffic": traffic["bytes"] if traffic else None,
+            "traffic_over_algorithmic": traffic["over_algorithmic"] if traffic else None,
+            "traffic_source": traffic["source"] if traffic else None,
+            "avg_launch_us": hemv_avg_us, "sampled_launches": int(prof.hemv_launches),
+            "bytes_per_launch_avg": prof.hemv_bytes / max(1, prof.hemv_launches)}
+
+
+def occupied_count(occ, p):
+    return int((occ > 2e-15 * p.g).sum(dim=-1).max().item())
+
+
+def trace_check(p, rho, S):
+    import torch
+    SN = torch.block_diag(S, S) if p.nsp == 2 else S
+    if p.batch == 1:
+        return float((rho * SN.to(rho.dtype).T).sum().real.item())
+    w = torch.tensor(p.weights, dtype=torch.float64, device="cuda")
+    return float((w * (rho * S.to(rho.dtype).transpose(1, 2)).sum(dim=(1, 2)).real).sum().item())
+
+
+def route_summary(r, ref, p, flops):
+    out = {"s_per_solve": r["ms"] / 1e3, "tflops": flops / (r["ms"] * 1e-3) / 1e12,
+           "phases_ms": {k: v for k, v in r["phases"].items() if v > 0}}
+    if r["ms_warm"] is not None:
+        out["warm_s_per_solve"] = r["ms_warm"] / 1e3
+    if ref is not None:
+        out["max_abs_eps_diff_vs_main"] = float((r["eps"] - ref["eps"]).abs().max().item())
+        out["max_abs_rho_diff_vs_main"] = float((r["rho"] - ref["rho"]).abs().max().item())
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="supercell6656", choices=sorted(WORKLOADS))
+    ap.add_argument("--route", default=DEFAULT_ROUTE, choices=sorted(ROUTE_FLAGS),
+                    help="tridiagonalisation route of the main measurement")
     ap.add_argument("--stride", type=int, default=16, help="sample every n-th matrix-vector launch")
-    ap.add_argument("--cpu-sample", type=int, default=1700)
+    ap.add_argument("--cpu-sizes", default="850,1200,1700",
+                    help="orders of the oracle samples behind cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the FP64-vs-mixed comparison on the occupied window")
     ap.add_argument("--no-lowdin", action="store_true", help="skip the Loewdin-route comparison")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other sizes of the metric (2N = 9984 spinor, 16 x 1300 k-points)")
     ap.add_argument("--graph", action="store_true", help="plan with KS_PLAN_GRAPH (capture once, replay)")
     ap.add_argument("--counter-workload", action="store_true",
                     help="run the fixed workload of the rocprofv3 memory-counter runs and exit")
@@ -140,7 +284,6 @@ def main():
     import numpy as np
     import torch
     from paper_2606_09058_amd import inputs as I
-    from paper_2606_09058_amd import ks
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
@@ -151,61 +294,13 @@ def main():
     cplx = np.iscomplexobj(p.H)
     stream = torch.cuda.Stream() if args.graph else torch.cuda.current_stream()
     torch.cuda.set_stream(stream)
-    # the plan times its symmetric-product tile shapes at creation (KS_PLAN_AUTOTUNE)
-    plan = ks.Plan(p.n, batch=p.batch, complex=cplx, noncollinear=p.nsp == 2, stream=stream,
-                   flags=ks.KS_PLAN_AUTOTUNE | (ks.KS_PLAN_GRAPH if args.graph else 0))
     H = torch.from_numpy(p.H).cuda()
     S = torch.from_numpy(p.S.astype(p.H.dtype)).cuda()
-    eps = torch.empty(plan._vshape(), dtype=torch.float64, device="cuda")
-    C = torch.empty(plan._mshape(), dtype=plan.mdtype, device="cuda")
-    rho = torch.empty_like(C)
-    mu = torch.empty(1, dtype=torch.float64, device="cuda")
-    eband = torch.empty(1, dtype=torch.float64, device="cuda")
-    occ = torch.empty(plan._vshape(), dtype=torch.float64, device="cuda")
-
-    def step(reuse=False):
-        plan.gevd(H, S, eps, C, reuse_s=reuse)
-        plan.density(eps, C, p.n_electrons, p.kT, rho, mu, eband, occ=occ, kweights=p.weights)
-
-    for _ in range(args.warmup):
-        step()
-    plan.check("warmup")
-    plan.get_profile()  # clear
-    plan.set_profiling(True, args.stride)
-
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        step()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1) / args.steps
-    prof = plan.get_profile()
-    plan.set_profiling(False)
-    plan.check("timed steps")
-
-    # warm solves (cached Cholesky factor), the analogue of SCF cycles 2 onwards
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.steps):
-        step(reuse=True)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms_warm = e0.elapsed_time(e1) / args.steps
-    plan.check("warm steps")
-
-    # cheap property checks of the last solve
-    SN = torch.block_diag(S, S) if p.nsp == 2 else S  # overlap of the spinor basis
-    if p.batch == 1:
-        tr = float((rho * SN.to(rho.dtype).T).sum().real.item())
-    else:
-        w = torch.tensor(p.weights, dtype=torch.float64, device="cuda")
-        tr = float((w * (rho * S.to(rho.dtype).transpose(1, 2)).sum(dim=(1, 2)).real).sum().item())
-    m_occ = int((occ > 2e-15 * p.g).sum(dim=-1).max().item())
+    r = time_route(p, H, S, args.route, args.steps, args.warmup, args.stride, stream, graph=args.graph)
+    plan, eps, C, rho, mu, eband, occ = (r[k] for k in ("plan", "eps", "C", "rho", "mu", "eband", "occ"))
+    ms = r["ms"]
+    tr = trace_check(p, rho, S)
+    m_occ = occupied_count(occ, p)
     flops = p.batch * nominal_flops(p.order, p.order, m_occ, cplx, p.n)
 
     # energy-density matrix E = C diag(f eps) C^H of the last solve, over the
@@ -214,6 +309,8 @@ def main():
     with torch.cuda.stream(stream):
         plan.energy_density(eps, C, occ, edm, il=1, iu=max(1, m_occ))
     torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(args.steps):
         plan.energy_density(eps, C, occ, edm, il=1, iu=max(1, m_occ))
@@ -221,18 +318,9 @@ def main():
     torch.cuda.synchronize()
     plan.check("energy density")
     ms_edm = e0.elapsed_time(e1) / args.steps
-    SNe = torch.block_diag(S, S) if p.nsp == 2 else S
-    if p.batch == 1:
-        edm_tr = float((edm * SNe.to(edm.dtype).T).sum().real.item())
-    else:
-        wk = torch.tensor(p.weights, dtype=torch.float64, device="cuda")
-        edm_tr = float((wk * (edm * S.to(edm.dtype).transpose(1, 2)).sum(dim=(1, 2)).real).sum().item())
-    # lower triangle of an order x order x m_occ product (x4 for complex)
+    edm_tr = trace_check(p, edm, S)
     edm_flops = p.batch * (4.0 if cplx else 1.0) * p.order * p.order * m_occ
-    hemv_avg_us = 1e3 * prof.hemv_ms / max(1, prof.hemv_launches)
-    hemv_gbs = prof.hemv_bytes / max(1e-12, prof.hemv_ms * 1e-3) / 1e9
-    phases = phase_dict(prof, args.steps)
-    traffic = measured_traffic(args.workload)
+    tu = plan.tuning()
     out = {
         "metric": "GEVD+density s/solve & TFLOP/s, N=6656 real, 2N=9984 cplx; mixed vs FP64",
         "value": ms / 1e3,
@@ -247,32 +335,30 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": args.workload + ": " + WORKLOADS[args.workload], "form": "fp64",
-                   "order": p.order, "batch": p.batch, "electrons": p.n_electrons, "kT": p.kT,
-                   "eigenvectors": p.order, "occupied_window": m_occ, "graph": bool(args.graph)},
+                   "route": args.route, "order": p.order, "batch": p.batch, "electrons": p.n_electrons,
+                   "kT": p.kT, "eigenvectors": p.order, "occupied_window": m_occ, "graph": bool(args.graph)},
         "tflops": flops / (ms * 1e-3) / 1e12,
         "tflops_frac_fp64_peak": flops / (ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
         "nominal_flops": flops,
-        "warm_s_per_solve": ms_warm / 1e3,
-        "wall_s_timed": wall,
-        "phases_ms": phases,
-        "tuning": {"tiles_per_workgroup": plan.tuning()["tiles_per_workgroup"],
-                   "candidates_ms": {str(k): v for k, v in plan.tuning()["candidates"].items()},
-                   "segments": plan.tuning()["segments"]},
-        "roofline": {"bound": "hbm", "kernel": "symv_kernel (trailing Hermitian matrix-vector "
-                                               "product of the tridiagonalisation)",
-                     "achieved": hemv_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": hemv_gbs / PEAK_HBM_GBS,
-                     "traffic": traffic["bytes"] if traffic else None,
-                     "traffic_over_algorithmic": traffic["over_algorithmic"] if traffic else None,
-                     "traffic_source": traffic["source"] if traffic else None,
-                     "avg_launch_us": hemv_avg_us, "sampled_launches": int(prof.hemv_launches),
-                     "bytes_per_launch_avg": prof.hemv_bytes / max(1, prof.hemv_launches)},
+        "warm_s_per_solve": r["ms_warm"] / 1e3,
+        "wall_s_timed": r["wall"],
+        "phases_ms": r["phases"],
+        "tuning": {"tiles_per_workgroup": tu["tiles_per_workgroup"],
+                   "candidates_ms": {str(k): v for k, v in tu["candidates"].items()},
+                   "segments": tu["segments"]},
         "checks": {"trace_rho_S_minus_Ne": tr - p.n_electrons, "mu": float(mu.item()),
-                   "eband": float(eband.item()),
-                   "trace_edm_S_minus_eband": edm_tr - float(eband.item())},
-        "energy_density": {"ms": ms_edm, "columns": m_occ,
-                           "tflops": edm_flops / (ms_edm * 1e-3) / 1e12},
+                   "eband": float(eband.item()), "trace_edm_S_minus_eband": edm_tr - float(eband.item())},
+        "energy_density": {"ms": ms_edm, "columns": m_occ, "tflops": edm_flops / (ms_edm * 1e-3) / 1e12},
     }
+    # the other tridiagonalisation route on the same input (fewer steps)
+    other = "twostage" if args.route == "onestage" else "onestage"
+    r2 = time_route(p, H, S, other, max(2, args.steps // 4), 1, args.stride, stream, warm=False)
+    out["routes"] = {args.route: route_summary(r, None, p, flops), other: route_summary(r2, r, p, flops)}
+    out["routes"][other]["steps"] = max(2, args.steps // 4)
+    sy = r if args.route == "onestage" else r2
+    out["roofline"] = symv_roofline(sy["prof"], measured_traffic(args.workload))
+    out["roofline"]["route"] = "onestage"
+    del r2
     if p.batch > 1:
         out["ms_per_kpoint"] = ms / p.batch
     if args.workload == "kpoints16x1300":
@@ -282,13 +368,56 @@ def main():
     if not args.no_mixed:
         out["precision_comparison"] = compare_precisions(p, H, S, eps, mu, args.steps)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p, args.cpu_sample)
+        out["cpu_baseline"] = cpu_baseline(p, [int(x) for x in args.cpu_sizes.split(",")])
+    del plan, r, H, S, C, rho, edm
+    torch.cuda.empty_cache()
+    if not args.no_configs:
+        out["configs"] = {}
+        for name in ("supercell6656", "noncollinear9984", "kpoints16x1300"):
+            if name != args.workload:
+                out["configs"][name] = other_config(name, stream, args.stride)
+                torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 
 
-def phase_dict(prof, steps):
-    names = ["cholesky", "reduce", "tridiag", "dc", "backtransform", "density", "adjoint", "refine"]
-    return {nm: prof.phase_ms[i] / steps for i, nm in enumerate(names)}
+def other_config(name, stream, stride, steps=3):
+    """Another size of the metric at reduced steps: both routes (all
+    eigenvectors), the one-stage symmetric product's roofline, FP64 vs mixed on
+    the occupied window, and for a k-point batch graph-replayed vs eager launches."""
+    import numpy as np
+    import torch
+    from paper_2606_09058_amd import inputs as I
+    p = I.workload(name)
+    cplx = np.iscomplexobj(p.H)
+    H = torch.from_numpy(p.H).cuda()
+    S = torch.from_numpy(p.S.astype(p.H.dtype)).cuda()
+    res = {"workload": name + ": " + WORKLOADS[name], "steps": steps, "warmup": 1, "order": p.order,
+           "batch": p.batch}
+    runs = {}
+    for route in ("onestage", "twostage"):
+        runs[route] = time_route(p, H, S, route, steps, 1, stride, stream, warm=route == "onestage", tag=name + " ")
+    ref = runs["onestage"]
+    m_occ = occupied_count(ref["occ"], p)
+    flops = p.batch * nominal_flops(p.order, p.order, m_occ, cplx, p.n)
+    res["nominal_flops"] = flops
+    res["occupied_window"] = m_occ
+    res["routes"] = {rt: route_summary(runs[rt], None if rt == "onestage" else ref, p, flops) for rt in runs}
+    res["trace_rho_S_minus_Ne"] = trace_check(p, ref["rho"], S) - p.n_electrons
+    res["roofline"] = symv_roofline(ref["prof"], measured_traffic(name))
+    if p.batch > 1:
+        res["ms_per_kpoint"] = {rt: runs[rt]["ms"] / p.batch for rt in runs}
+    mu = ref["mu"]
+    eps = ref["eps"]
+    del runs, ref
+    torch.cuda.empty_cache()
+    if p.batch > 1:
+        g = time_route(p, H, S, "onestage", steps, 1, stride, stream, graph=True, warm=False, tag=name + " graph ")
+        res["graph_s_per_batch"] = g["ms"] / 1e3
+        res["graph_ms_per_kpoint"] = g["ms"] / p.batch
+        res["graph_replays"] = g["plan"].graph_stats()[1]
+        del g
+    res["precision_comparison"] = compare_precisions(p, H, S, eps, mu, 2)
+    return res
 
 
 def bloch_sum_timing(plan, p, stream, steps):
@@ -383,12 +512,12 @@ def compare_precisions(p, H, S, eps_all, mu, steps, buffer_ha=0.4):
     from paper_2606_09058_amd import ks
     cplx = torch.is_complex(H)
     iu = int((eps_all < float(mu.item()) + buffer_ha).sum(dim=-1).max().item())
-    res = {"window": [1, iu], "buffer_ha": buffer_ha}
+    res = {"window": [1, iu], "buffer_ha": buffer_ha, "steps": steps}
     outs = {}
-    for form, prec, sweeps in (("fp64", ks.KS_FP64, None), ("mixed", ks.KS_MIXED, 2),
-                               ("mixed1", ks.KS_MIXED, 1)):
+    for form, prec, sweeps, flags in (("fp64", ks.KS_FP64, None, 0), ("fp64_twostage", ks.KS_FP64, None, 8),
+                                      ("mixed", ks.KS_MIXED, 2, 0), ("mixed1", ks.KS_MIXED, 1, 0)):
         plan = ks.Plan(p.n, batch=p.batch, complex=cplx, noncollinear=p.nsp == 2, precision=prec,
-                       flags=ks.KS_PLAN_AUTOTUNE)
+                       flags=ks.KS_PLAN_AUTOTUNE | flags)
         if sweeps is not None:
             plan.set_refinement(sweeps)
         eps = torch.empty(plan._vshape(), dtype=torch.float64, device="cuda")
@@ -416,17 +545,23 @@ def compare_precisions(p, H, S, eps_all, mu, steps, buffer_ha=0.4):
         plan.set_profiling(False)
         plan.check(form + " window steps")
         res[form + "_s_per_solve"] = e0.elapsed_time(e1) / steps / 1e3
-        res[form + "_phases_ms"] = phase_dict(prof, steps)
+        res[form + "_phases_ms"] = {k: v for k, v in phase_dict(prof, steps).items() if v > 0}
         outs[form] = (eps.clone(), rho.clone(), float(eb.item()))
-        del plan
+        del plan, C, rho
+        torch.cuda.empty_cache()
     ef, rf, bf = outs["fp64"]
     res["mixed_sweeps"] = {"mixed": 2, "mixed1": 1}
-    for form in ("mixed", "mixed1"):
+    best = min(res["fp64_s_per_solve"], res["fp64_twostage_s_per_solve"])
+    res["fastest_fp64_s_per_solve"] = best
+    for form in ("fp64_twostage", "mixed", "mixed1"):
         em, rm, bm = outs[form]
-        res["speedup_%s_vs_fp64" % form] = res["fp64_s_per_solve"] / res[form + "_s_per_solve"]
+        if form != "fp64_twostage":
+            res["speedup_%s_vs_fp64" % form] = res["fp64_s_per_solve"] / res[form + "_s_per_solve"]
+            res["speedup_%s_vs_fastest_fp64" % form] = best / res[form + "_s_per_solve"]
         res[form + "_max_eig_err_window_vs_fp64"] = float((em[..., :iu] - ef[..., :iu]).abs().max().item())
-        res[form + "_max_eig_err_outside_vs_fp64"] = float((em[..., iu:] - ef[..., iu:]).abs().max().item()) \
-            if iu < p.order else 0.0
+        if form != "fp64_twostage":
+            res[form + "_max_eig_err_outside_vs_fp64"] = float((em[..., iu:] - ef[..., iu:]).abs().max().item()) \
+                if iu < p.order else 0.0
         res[form + "_max_rho_err_vs_fp64"] = float((rm - rf).abs().max().item())
         res[form + "_eband_err_vs_fp64"] = abs(bm - bf)
     return res

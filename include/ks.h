@@ -100,7 +100,23 @@ enum { KS_PLAN_GRAPH = 1u,
         * in ks_plan_workspace_bytes).  Not with KS_MIXED (KS_ERR_NOT_SUPPORTED).
         * Results equal the Cholesky route's up to rounding: eps, rho and the
         * occupied subspace do not depend on the S-orthonormal basis. */
-       KS_PLAN_LOWDIN = 4u };
+       KS_PLAN_LOWDIN = 4u,
+       /* KS_PLAN_TWOSTAGE: the reduced matrix is brought to tridiagonal form in
+        * two stages (the two-stage scheme of the paper's CPU solver, Sec. 4, in
+        * place of the one-stage Householder reduction whose bandwidth-bound
+        * matrix-vector products Sec. 6 names as the limit): panels of 32 columns
+        * are factored by Householder QR and the trailing matrix takes two-sided
+        * rank-64 updates on the matrix cores, leaving a band of half-bandwidth
+        * 32; bulge chasing then reduces the band to tridiagonal form, and the
+        * eigenvectors take the chasing reflectors in blocks of 32 sweeps before
+        * the panel reflectors.  Same outputs as the one-stage route up to
+        * rounding.  FP64 only (with KS_MIXED: KS_ERR_NOT_SUPPORTED); the Loewdin
+        * route uses it for H' (the eigen-decomposition of S stays one-stage).
+        * Its kernels wait for each other across workgroups, so a plan asks for
+        * at most one workgroup per compute unit per waiting launch; a wait that
+        * never completes gives up after seconds with KS_ERR_NO_CONVERGENCE
+        * (info -1 in the band reduction, -2 in the bulge chasing). */
+       KS_PLAN_TWOSTAGE = 8u };
 enum { KS_REUSE_S = 1u };                            /* ks_gevd flags                */
 
 typedef struct ks_plan ks_plan; /* opaque: workspace, cached Cholesky factor, info */

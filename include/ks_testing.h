@@ -40,6 +40,17 @@ int32_t ks_test_stedc(int32_t n, const double* d, const double* e, double* lam, 
 int32_t ks_test_hetrd(int32_t dtype, int32_t n, void* A, double* d, double* e, const double* X,
                       int32_t ncols, void* Y, void* stream);
 
+/* The same with the two-stage reduction (KS_PLAN_TWOSTAGE): A = Q T Q^H with
+ * Q = Q1 Q2 (panel reflectors, then bulge-chasing reflectors), Y = Q X. */
+int32_t ks_test_hetrd2(int32_t dtype, int32_t n, void* A, double* d, double* e, const double* X,
+                       int32_t ncols, void* Y, void* stream);
+
+/* The first stage alone: A (full storage, overwritten) becomes B = Q1^H A Q1,
+ * Hermitian with half-bandwidth 32 (its lower triangle is written: the band,
+ * zeros below it; the upper triangle is left undefined), and Y = Q1 X for the
+ * n x ncols real X (row stride n), Y of the dtype with row stride ncols. */
+int32_t ks_test_he2hb(int32_t dtype, int32_t n, void* A, const double* X, int32_t ncols, void* Y, void* stream);
+
 /* Iteration caps of the divide-and-conquer eigensolver for every later call in
  * this process: Jacobi sweeps of the leaves (default 40) and iterations of the
  * secular-equation solver (default 120); a value <= 0 restores the default.

@@ -41,6 +41,8 @@ struct ks_plan {
     HetrdWork<cplx> hc;
     BacktrWork<double> br;
     BacktrWork<cplx> bc;
+    BandWork<double> bandr;    // KS_PLAN_TWOSTAGE buffers
+    BandWork<cplx> bandc;
     DcWork dc;
     DcTree tree;
     bool have_L = false;
@@ -118,7 +120,7 @@ bool desc_valid(const ks_plan_desc* d) {
     long order = (long)d->n * (d->spin == KS_NONCOLLINEAR ? 2 : 1);
     if (order > 60000) return false;
     if (d->ld_h < order || d->ld_s < d->n) return false;
-    if (d->flags & ~(uint32_t)(KS_PLAN_GRAPH | KS_PLAN_AUTOTUNE | KS_PLAN_LOWDIN)) return false;
+    if (d->flags & ~(uint32_t)(KS_PLAN_GRAPH | KS_PLAN_AUTOTUNE | KS_PLAN_LOWDIN | KS_PLAN_TWOSTAGE)) return false;
     return true;
 }
 
@@ -127,6 +129,7 @@ ks_status desc_supported(const ks_plan_desc* d) {
     if (d->spin == KS_NONCOLLINEAR && d->dtype != KS_COMPLEX128) return KS_ERR_NOT_SUPPORTED;
     if (d->batch > MAX_KW) return KS_ERR_NOT_SUPPORTED;
     if ((d->flags & KS_PLAN_LOWDIN) && d->precision == KS_MIXED) return KS_ERR_NOT_SUPPORTED;
+    if ((d->flags & KS_PLAN_TWOSTAGE) && d->precision == KS_MIXED) return KS_ERR_NOT_SUPPORTED;
     return KS_OK;
 }
 
@@ -220,6 +223,31 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
         oVWl = L.take(B * hVW * es32);
         oWVl = L.take(B * hVW * es32);
     }
+    // two-stage reduction (only when asked for)
+    const bool two = (d->flags & KS_PLAN_TWOSTAGE) != 0;
+    const size_t tm = order > 1 ? (size_t)s2_steps((int)order, 0) : 1;       // steps of the longest sweep
+    const size_t jg = order > 1 ? (order - 1 + Q2_NB - 1) / Q2_NB : 1;       // groups of sweeps
+    const size_t pmax = (order + (es == 16 ? 256 : 512) - 1) / (es == 16 ? 256 : 512);
+    const size_t npan = (order + KB - 1) / KB;
+    constexpr size_t GMAX = 64;  // bulge-chasing workgroups per matrix
+    size_t oBX = 0, oB3 = 0, oBT = 0, oBM = 0, oBN = 0, oRec = 0, oCnt = 0, oGp = 0, oAb = 0, oVpk = 0, oTaupk = 0;
+    size_t oTpk = 0, oBW1 = 0, oBW2 = 0;
+    if (two) {
+        oBX = L.take(B * order * KB * es);
+        oB3 = L.take(B * order * 3 * KB * es);
+        oBT = L.take(B * KB * KB * es);
+        oBM = L.take(B * KB * KB * es);
+        oBN = L.take(B * KB * KB * es);
+        oRec = L.take(B * 2 * pmax * 2 * KB * es);
+        oCnt = L.take(B * npan * sizeof(int));
+        oGp = L.take(B * GMAX * sizeof(int));
+        oAb = L.take(sizeof(int));
+        oVpk = L.take(B * jg * tm * Q2_GL * Q2_NB * es);
+        oTaupk = L.take(B * jg * tm * Q2_NB * es);
+        oTpk = L.take(B * jg * tm * Q2_NB * Q2_NB * es);
+        oBW1 = L.take(B * jg * Q2_NB * order * es);
+        oBW2 = L.take(B * jg * Q2_NB * order * es);
+    }
     const bool lw = (d->flags & KS_PLAN_LOWDIN) != 0;
     const size_t oSev = lw ? L.take(B * n * 8) : 0;
     const size_t oNkeep = lw ? L.take(B * sizeof(int)) : 0;
@@ -297,6 +325,38 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
     };
     setB(p->br, (double*)nullptr);
     setB(p->bc, (cplx*)nullptr);
+    auto setBand = [&](auto& w, auto* tag) {
+        using T = std::remove_pointer_t<decltype(tag)>;
+        if (!two) return;
+        w.X = (T*)(b + oBX);
+        w.sX = (long)(order * KB);
+        w.buf3 = (T*)(b + oB3);
+        w.sbuf = (long)(order * 3 * KB);
+        w.Tf = (T*)(b + oBT);
+        w.sTf = (long)(KB * KB);
+        w.M = (T*)(b + oBM);
+        w.N = (T*)(b + oBN);
+        w.rec = (T*)(b + oRec);
+        w.srec = (long)(2 * pmax * 2 * KB);
+        w.cnt = (int*)(b + oCnt);
+        w.scnt = (long)npan;
+        w.gprog = (int*)(b + oGp);
+        w.sgp = (long)GMAX;
+        w.abort_ = (int*)(b + oAb);
+        w.Vpk = (T*)(b + oVpk);
+        w.sVpk = (long)(jg * tm * Q2_GL * Q2_NB);
+        w.taupk = (T*)(b + oTaupk);
+        w.staupk = (long)(jg * tm * Q2_NB);
+        w.Tpk = (T*)(b + oTpk);
+        w.sTpk = (long)(jg * tm * Q2_NB * Q2_NB);
+        w.W1 = (T*)(b + oBW1);
+        w.W2 = (T*)(b + oBW2);
+        w.sW = (long)(jg * Q2_NB * order);
+        w.P = (T*)(b + oSK);
+        w.pelems = (long)pel;
+    };
+    setBand(p->bandr, (double*)nullptr);
+    setBand(p->bandc, (cplx*)nullptr);
     DcWork& w = p->dc;
     w.dw = (double*)(b + oDd[0]);
     w.ds = (double*)(b + oDd[1]);
@@ -407,6 +467,47 @@ ks_status ensure_rr_plan(ks_plan* p, int m) {
     d.stream = p->d.stream;
     d.flags = 0;
     return ks_plan_create(&d, &p->rr);
+}
+
+template <typename T>
+HetrdWork<T>& hetrd_work(ks_plan* p) {
+    return *reinterpret_cast<HetrdWork<T>*>(is_cplx<T>::value ? (void*)&p->hc : (void*)&p->hr);
+}
+template <typename T>
+BacktrWork<T>& backtr_work(ks_plan* p) {
+    return *reinterpret_cast<BacktrWork<T>*>(is_cplx<T>::value ? (void*)&p->bc : (void*)&p->br);
+}
+template <typename T>
+BandWork<T>& band_work(ks_plan* p) {
+    return *reinterpret_cast<BandWork<T>*>(is_cplx<T>::value ? (void*)&p->bandc : (void*)&p->bandr);
+}
+
+// A (order x order per matrix, lower triangle read) = Q T Q^H into (dv, ev),
+// the reflectors of Q in W and tau: one-stage Householder, or with
+// KS_PLAN_TWOSTAGE dense -> band -> tridiagonal (the stage-1 reflectors in W
+// and tau, the stage-2 ones in the band buffers).
+template <typename T>
+void tridiagonalize(ks_plan* p, T* A, T* W, T* tau) {
+    const int order = p->order, B = p->d.batch;
+    const long sA = (long)order * order;
+    if (p->d.flags & KS_PLAN_TWOSTAGE) {
+        he2hb<T>(p->s, order, A, order, sA, B, W, tau, band_work<T>(p), p->info);
+        hb2st<T>(p->s, order, A, order, sA, B, p->dv, p->ev, band_work<T>(p), p->info);
+    } else {
+        hetrd<T, T>(p->s, order, A, order, sA, B, p->dv, p->ev, tau, W, hetrd_work<T>(p));
+    }
+}
+
+// X = Q Z[:, c0 : c0 + ncols] (order x ncols per matrix, matrix stride
+// order^2) for the Q that tridiagonalize() left in W and tau.
+template <typename T>
+void back_q(ks_plan* p, const T* W, const T* tau, int c0, int ncols, T* X) {
+    const int order = p->order, B = p->d.batch;
+    const long sA = (long)order * order;
+    load_z<T>(p->s, order, B, ncols, p->Z, c0, X, ncols, sA);
+    if (p->d.flags & KS_PLAN_TWOSTAGE) q2_apply<T>(p->s, order, B, ncols, X, ncols, sA, band_work<T>(p));
+    backtransform_prepare<T>(p->s, order, B, W, tau, backtr_work<T>(p));
+    backtransform_q<T>(p->s, order, B, W, ncols, X, ncols, sA, backtr_work<T>(p));
 }
 
 // Mixed-precision eigensolve after the Cholesky factor is in place:
@@ -621,17 +722,13 @@ ks_status gevd_lowdin(ks_plan* p, const T* H, const T* S, double* eps, T* C, int
     }
     pf.end(KS_PHASE_REDUCE, e);
     e = pf.begin();
-    hetrd<T, T>(s, order, A, order, sA, B, p->dv, p->ev, (T*)p->tau, W,
-                *reinterpret_cast<HetrdWork<T>*>(is_cplx<T>::value ? (void*)&p->hc : (void*)&p->hr));
+    tridiagonalize<T>(p, A, W, (T*)p->tau);
     pf.end(KS_PHASE_TRIDIAG, e);
     e = pf.begin();
     stedc(s, p->tree, B, p->dv, p->ev, eps, p->Z, p->Z2, p->U, p->Qp, p->dc, p->info);
     pf.end(KS_PHASE_DC, e);
     e = pf.begin();
-    BacktrWork<T>& bw = *reinterpret_cast<BacktrWork<T>*>(is_cplx<T>::value ? (void*)&p->bc : (void*)&p->br);
-    load_z<T>(s, order, B, ncols, p->Z, il - 1, A, ncols, sA);
-    backtransform_prepare<T>(s, order, B, W, (T*)p->tau, bw);
-    backtransform_q<T>(s, order, B, W, ncols, A, ncols, sA, bw);
+    back_q<T>(p, W, (const T*)p->tau, il - 1, ncols, A);
     // C_sigma = V C'_sigma per spin block
     for (int b = 0; b < nsp; ++b)
         gemm<T>(s, OP_N, OP_N, n, ncols, n, 1.0, V, n, sV, A + (long)b * n * ncols, ncols, sA, 0.0,
@@ -651,8 +748,6 @@ ks_status gevd_impl(ks_plan* p, const T* H, const T* S, double* eps, T* C, int i
     T* A = (T*)p->A;
     T* W = (T*)p->W;
     T* tau = (T*)p->tau;
-    HetrdWork<T>& hw = *reinterpret_cast<HetrdWork<T>*>(is_cplx<T>::value ? (void*)&p->hc : (void*)&p->hr);
-    BacktrWork<T>& bw = *reinterpret_cast<BacktrWork<T>*>(is_cplx<T>::value ? (void*)&p->bc : (void*)&p->br);
     Prof& pf = p->prof;
     T* Li = (T*)p->Li;
     if (p->d.flags & KS_PLAN_LOWDIN) return gevd_lowdin<T>(p, H, S, eps, C, il, iu, flags);
@@ -674,16 +769,14 @@ ks_status gevd_impl(ks_plan* p, const T* H, const T* S, double* eps, T* C, int i
     reduce_to_standard<T>(s, n, nsp, B, H, ldh, sH, Li, n, sL, A, W, p->info, true);
     pf.end(KS_PHASE_REDUCE, e);
     e = pf.begin();
-    hetrd<T, T>(s, order, A, order, sA, B, p->dv, p->ev, tau, W, hw);
+    tridiagonalize<T>(p, A, W, tau);
     pf.end(KS_PHASE_TRIDIAG, e);
     e = pf.begin();
     stedc(s, p->tree, B, p->dv, p->ev, eps, p->Z, p->Z2, p->U, p->Qp, p->dc, p->info);
     pf.end(KS_PHASE_DC, e);
     e = pf.begin();
     // X = Q Z[:, il-1 : iu] in A (order x ncols per matrix), then C_sigma = Linv^H X_sigma per spin block
-    load_z<T>(s, order, B, ncols, p->Z, il - 1, A, ncols, sA);
-    backtransform_prepare<T>(s, order, B, W, tau, bw);
-    backtransform_q<T>(s, order, B, W, ncols, A, ncols, sA, bw);
+    back_q<T>(p, W, tau, il - 1, ncols, A);
     apply_linv_h<T>(p, Li, A, sA, ncols, C);
     pf.end(KS_PHASE_BACKTR, e);
     if (hipPeekAtLastError() != hipSuccess) return KS_ERR_HIP;
@@ -745,6 +838,22 @@ ks_status ks_plan_create(const ks_plan_desc* d, ks_plan** out) {
     }
     p->bytes = bytes;
     layout(d, p);
+    if (d->flags & KS_PLAN_TWOSTAGE) {
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1) {
+            (void)hipFree(p->base);
+            delete p;
+            return KS_ERR_HIP;
+        }
+        p->bandr.ncu = p->bandc.ncu = ncu;
+        // the panel factorisation's workgroups of one matrix must all be resident together
+        if (cdiv(p->order, p->is_c ? 256 : 512) > ncu) {
+            (void)hipFree(p->base);
+            delete p;
+            return KS_ERR_NOT_SUPPORTED;
+        }
+    }
     p->kw_last = make_weights(p, nullptr);
     if (hipMemset(p->info, 0, 2 * sizeof(int)) != hipSuccess) {
         (void)hipFree(p->base);
@@ -1139,6 +1248,22 @@ ks_status ks_plan_get_info(ks_plan* p, int32_t* info) {
 }  // extern "C"
 
 // Internal stage drivers used by the test hooks (ks_testhooks.hip).
+void ks_internal_he2hb(ks_plan* p, void* A, const double* X, int ncols, void* Y) {
+    int n = p->order;
+    long sA = (long)n * n;
+    if (p->is_c) {
+        he2hb<cplx>(p->s, n, (cplx*)A, n, sA, 1, (cplx*)p->W, (cplx*)p->tau, p->bandc, p->info);
+        load_z<cplx>(p->s, n, 1, ncols, X, 0, (cplx*)Y, ncols, 0);
+        backtransform_prepare<cplx>(p->s, n, 1, (cplx*)p->W, (cplx*)p->tau, p->bc);
+        backtransform_q<cplx>(p->s, n, 1, (cplx*)p->W, ncols, (cplx*)Y, ncols, 0, p->bc);
+    } else {
+        he2hb<double>(p->s, n, (double*)A, n, sA, 1, (double*)p->W, (double*)p->tau, p->bandr, p->info);
+        load_z<double>(p->s, n, 1, ncols, X, 0, (double*)Y, ncols, 0);
+        backtransform_prepare<double>(p->s, n, 1, (double*)p->W, (double*)p->tau, p->br);
+        backtransform_q<double>(p->s, n, 1, (double*)p->W, ncols, (double*)Y, ncols, 0, p->br);
+    }
+}
+
 void ks_internal_stedc(ks_plan* p, const double* d, const double* e, double* lam, double* Z) {
     stedc(p->s, p->tree, 1, d, e, lam, Z, p->Z2, p->U, p->Qp, p->dc, p->info);
 }
@@ -1146,6 +1271,26 @@ void ks_internal_stedc(ks_plan* p, const double* d, const double* e, double* lam
 void ks_internal_hetrd(ks_plan* p, void* A, double* d, double* e, const double* X, int ncols, void* Y) {
     int n = p->order;
     long sA = (long)n * n;
+    if (p->d.flags & KS_PLAN_TWOSTAGE) {
+        if (p->is_c) {
+            BandWork<cplx>& w = p->bandc;
+            he2hb<cplx>(p->s, n, (cplx*)A, n, sA, 1, (cplx*)p->W, (cplx*)p->tau, w, p->info);
+            hb2st<cplx>(p->s, n, (cplx*)A, n, sA, 1, d, e, w, p->info);
+            load_z<cplx>(p->s, n, 1, ncols, X, 0, (cplx*)Y, ncols, 0);
+            q2_apply<cplx>(p->s, n, 1, ncols, (cplx*)Y, ncols, 0, w);
+            backtransform_prepare<cplx>(p->s, n, 1, (cplx*)p->W, (cplx*)p->tau, p->bc);
+            backtransform_q<cplx>(p->s, n, 1, (cplx*)p->W, ncols, (cplx*)Y, ncols, 0, p->bc);
+        } else {
+            BandWork<double>& w = p->bandr;
+            he2hb<double>(p->s, n, (double*)A, n, sA, 1, (double*)p->W, (double*)p->tau, w, p->info);
+            hb2st<double>(p->s, n, (double*)A, n, sA, 1, d, e, w, p->info);
+            load_z<double>(p->s, n, 1, ncols, X, 0, (double*)Y, ncols, 0);
+            q2_apply<double>(p->s, n, 1, ncols, (double*)Y, ncols, 0, w);
+            backtransform_prepare<double>(p->s, n, 1, (double*)p->W, (double*)p->tau, p->br);
+            backtransform_q<double>(p->s, n, 1, (double*)p->W, ncols, (double*)Y, ncols, 0, p->br);
+        }
+        return;
+    }
     if (p->is_c) {
         hetrd<cplx, cplx>(p->s, n, (cplx*)A, n, sA, 1, d, e, (cplx*)p->tau, (cplx*)p->W, p->hc);
         load_z<cplx>(p->s, n, 1, ncols, X, 0, (cplx*)Y, ncols, 0);

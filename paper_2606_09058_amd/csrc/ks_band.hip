@@ -1,0 +1,549 @@
+// ks_band.hip -- two-stage reduction of the reduced Hermitian matrix to real
+// symmetric tridiagonal form, the alternative to the one-stage Householder
+// tridiagonalisation of ks_hetrd.hip.  The paper attributes the limited
+// speed-up of its eigen-solve to the one-stage reduction's bandwidth-bound
+// matrix-vector products (Sec. 6), and its CPU runs use a two-stage solver
+// (Sec. 4).  Here the dense matrix is first reduced to a band of half-bandwidth
+// KB with matrix-core updates (stage 1), then the band is chased to tridiagonal
+// form (stage 2); the eigenvectors take the stage-2 reflectors (q2_apply) and
+// then the stage-1 ones (the compact-WY back-transform of ks_backtr.hip).
+//
+// Stage 1, panel k0 (columns k0 .. k0+KB-1, rows k0+KB .. n-1 below the band):
+//   * QR of the m x KB panel by Householder reflectors H_j = I - tau_j v_j v_j^H
+//     (H_j^H x = beta e_1, beta real), in one launch whose workgroups each hold
+//     up to R panel rows in LDS.  Per column j each workgroup forms, over its
+//     rows below row j, the products conj(x_i) P[i][c] of the raw column x with
+//     every panel column (the norm for c = j, the reflector's application for
+//     c > j, the triangular factor's V^H v_j for c < j) and row j itself; the
+//     partials of all workgroups are summed in a fixed order by every workgroup
+//     after an arrival counter shows all of them written, so one exchange per
+//     column suffices and every workgroup forms the same reflector.
+//   * The two-sided update A22 <- Q^H A22 Q with Q = I - V T V^H (T from the
+//     forward recurrence of the compact-WY form): X = A22 V T,
+//     W = X - V (T^H V^H X) / 2, A22 -= V W^H + W V^H, all on the matrix cores;
+//     A22 is kept full (both triangles) so that A22 V is a plain product.
+// Stage 2, sweep s (s = 0 .. n-2) annihilates column s below the subdiagonal
+// and chases the bulge down the band in tasks of KB rows: task 0 forms the
+// reflector of column s and applies it to the first diagonal block; task t
+// applies the previous reflector from the right to the block below (which
+// fills it), annihilates that block's first column with a new reflector
+// applied from the left, and applies the new reflector to the next diagonal
+// block from both sides.  Task (s, t) may start once sweep s-1 has finished
+// task t+1 (the blocks they touch are then disjoint).  One wavefront runs one
+// sweep; the Q wavefronts of a workgroup take consecutive sweeps and hand
+// progress to each other through LDS, consecutive workgroups through a
+// progress word in global memory (agent-scope release / acquire), so that only
+// one sweep in Q crosses compute units.
+#include "ks_internal.hpp"
+
+namespace ks {
+
+template <typename T>
+__device__ inline T mkc(double re, double im);
+template <>
+__device__ inline double mkc<double>(double re, double) { return re; }
+template <>
+__device__ inline cplx mkc<cplx>(double re, double im) { return mk(re, im); }
+
+// Householder scalars from alpha (the entry kept) and the squared norm of the
+// entries below it: tau, s = 1/(alpha - beta) (v = s x below the first entry)
+// and beta, with beta real.  A zero column below a real alpha gives tau = 0.
+template <typename T>
+__device__ inline void house(T alpha, double xn2, T& tv, T& sc, double& beta) {
+    const double ar = re_(alpha), ai = im_(alpha);
+    if (xn2 == 0.0 && ai == 0.0) {
+        tv = zero_<T>();
+        sc = zero_<T>();
+        beta = ar;
+    } else {
+        beta = -copysign(sqrt(ar * ar + ai * ai + xn2), ar);
+        tv = mkc<T>((beta - ar) / beta, -ai / beta);
+        sc = inv_(alpha - from_re<T>(beta));
+    }
+}
+
+// Sum of f(g), g = 0 .. cnt-1, in index order, eight loads in flight at a time.
+template <typename V, typename F>
+__device__ inline V batched_sum8(int cnt, F f) {
+    V acc = zero_<V>();
+    for (int b = 0; b < cnt; b += 8) {
+        V v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = b + u < cnt ? f(b + u) : zero_<V>();
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    return acc;
+}
+
+// Bounded waits: a wait gives up after this many polls (a few seconds), records
+// the failure and raises the abort word, which every other wait also watches.
+// Polls of LDS take ~0.1 us, polls of global memory ~1-2 us.
+constexpr long WAIT_POLLS = 1L << 24;
+constexpr long WAIT_POLLS_GLOBAL = 1L << 21;
+
+// ---------------------------------------------------------------- stage 1
+template <typename T>
+struct Pn {
+    static constexpr int R = is_cplx<T>::value ? 256 : 512;  // panel rows per workgroup (128 KB of LDS)
+};
+constexpr int PN_THREADS = 512;
+constexpr int PN_RG = PN_THREADS / KB;  // row groups of the partial sums
+
+template <typename T>
+__global__ __launch_bounds__(PN_THREADS) void panel_qr_kernel(int n, int k0, int P, int zoff, T* A, int lda, long sA,
+                                                              T* Vall, T* tau, BandWork<T> bw, int* info) {
+    constexpr int R = Pn<T>::R;
+    __shared__ T pt[R][KB];          // this workgroup's panel rows
+    __shared__ T red[PN_RG][KB];
+    __shared__ T tot[2 * KB];        // summed partials of column j, then row j
+    __shared__ T Tl[KB][KB + 1];     // compact-WY factor (workgroup 0)
+    __shared__ T taus[KB];
+    __shared__ int go;
+    const int wg = blockIdx.x, z = zoff + blockIdx.z, t = threadIdx.x;
+    A += z * sA;
+    Vall += z * (long)n * n;
+    tau += (long)z * n;
+    T* rec = bw.rec + z * bw.srec;
+    int* cnt = bw.cnt + z * bw.scnt + k0 / KB;
+    const int m = n - k0 - KB;
+    const int nr = min(KB, m);  // reflectors of this panel
+    const int i0 = wg * R;      // first panel row held here
+    const int nl = min(R, m - i0);
+    for (int e = t; e < R * KB; e += PN_THREADS) {
+        const int li = e / KB, c = e % KB;
+        pt[li][c] = li < nl ? A[(long)(k0 + KB + i0 + li) * lda + k0 + c] : zero_<T>();
+    }
+    if (wg == 0)
+        for (int e = t; e < KB * (KB + 1); e += PN_THREADS) Tl[e / (KB + 1)][e % (KB + 1)] = zero_<T>();
+    __syncthreads();
+    const int rg = t / KB, c = t % KB;
+    for (int j = 0; j < nr; ++j) {
+        // partials over this workgroup's rows below row j: s_c = sum conj(x_i) P[i][c]
+        T sacc = zero_<T>();
+        for (int li = rg; li < nl; li += PN_RG)
+            if (i0 + li > j) sacc += conj_(pt[li][j]) * pt[li][c];
+        red[rg][c] = sacc;
+        __syncthreads();
+        const int par = j & 1;
+        T* myrec = rec + ((long)par * P + wg) * (2 * KB);
+        if (t < KB) {
+            T sum = zero_<T>();
+#pragma unroll
+            for (int g = 0; g < PN_RG; g += 4) sum += (red[g][t] + red[g + 1][t]) + (red[g + 2][t] + red[g + 3][t]);
+            myrec[t] = sum;
+        } else if (t < 2 * KB) {
+            const int lj = j - i0;
+            myrec[t] = (lj >= 0 && lj < nl) ? pt[lj][t - KB] : zero_<T>();
+        }
+        __syncthreads();
+        if (t == 0) {
+            __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            const int want = P * (j + 1);
+            long polls = 0;
+            int ok = 1;
+            while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < want) {
+                if ((++polls & 255) == 0 &&
+                    (polls > WAIT_POLLS_GLOBAL || __hip_atomic_load(bw.abort_, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            if (!ok) {
+                atomicExch(bw.abort_, 1);
+                set_info(info, KS_ERR_NO_CONVERGENCE, -1);
+            }
+            go = ok;
+        }
+        __syncthreads();
+        if (!go) return;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (t < 2 * KB) {
+            const T* r0 = rec + (long)par * P * (2 * KB) + t;
+            tot[t] = batched_sum8<T>(P, [&](int g) { return r0[(long)g * 2 * KB]; });
+        }
+        __syncthreads();
+        // the reflector (the same in every workgroup)
+        const T alpha = tot[KB + j];
+        T tv, sc;
+        double beta;
+        house<T>(alpha, re_(tot[j]), tv, sc, beta);
+        // columns c > j of rows i >= j: P[i][c] -= v_i g_c with g_c = conj(tau) (v^H P[:, c]),
+        // v^H P[:, c] = P[j][c] + conj(s) s_c
+        if (c > j) {
+            const T gc = conj_(tv) * (tot[KB + c] + conj_(sc) * tot[c]);
+            for (int li = rg; li < nl; li += PN_RG) {
+                const int i = i0 + li;
+                if (i == j) pt[li][c] -= gc;
+                else if (i > j) pt[li][c] -= sc * pt[li][j] * gc;
+            }
+        }
+        // column j of the triangular factor: T[l][j] = -tau sum_q T[l][q] vd_q
+        // (q = l .. j-1), vd_q = v_q^H v_j = conj(P[j][q]) + s conj(s_q)
+        if (wg == 0 && t < KB) {
+            if (t < j) {
+                T acc = zero_<T>();
+                for (int q = t; q < j; ++q) acc += Tl[t][q] * (conj_(tot[KB + q]) + sc * conj_(tot[q]));
+                Tl[t][j] = -(tv * acc);
+            } else if (t == j) {
+                Tl[j][j] = tv;
+                taus[j] = tv;
+            }
+        }
+        __syncthreads();
+        if (c == j) {
+            for (int li = rg; li < nl; li += PN_RG) {
+                const int i = i0 + li;
+                if (i == j) pt[li][j] = from_re<T>(beta);
+                else if (i > j) pt[li][j] = sc * pt[li][j];
+            }
+        }
+        __syncthreads();
+    }
+    // R into the band (zeros below it), the reflectors into Vall (unit entry
+    // explicit, zeros above) and into both V columns of the update buffer
+    T* b3 = bw.buf3 + z * bw.sbuf;
+    for (int e = t; e < R * KB; e += PN_THREADS) {
+        const int li = e / KB, cc = e % KB;
+        if (li >= nl) continue;
+        const int i = i0 + li;
+        const T pv = pt[li][cc];
+        const long row = k0 + KB + i;
+        A[row * lda + k0 + cc] = (i <= cc) ? pv : zero_<T>();
+        const T vv = cc < nr ? (i > cc ? pv : (i == cc ? from_re<T>(1.0) : zero_<T>())) : zero_<T>();
+        Vall[row * n + k0 + cc] = vv;
+        b3[(long)i * 3 * KB + cc] = vv;
+        b3[(long)i * 3 * KB + 2 * KB + cc] = vv;
+    }
+    if (wg == 0) {
+        if (t < KB) tau[k0 + t] = t < nr ? taus[t] : zero_<T>();
+        T* Tf = bw.Tf + z * bw.sTf;
+        for (int e = t; e < KB * KB; e += PN_THREADS) Tf[e] = Tl[e / KB][e % KB];
+    }
+}
+
+template <typename T>
+void he2hb(hipStream_t s, int n, T* A, int lda, long sA, int batch, T* Vall, T* tau, BandWork<T>& w, int* info) {
+    const long sV = (long)n * n;
+    // the trailing products read the full matrix
+    mirror_lower<T>(s, n, A, lda, sA, batch);
+    fill_zero<T>(s, Vall, sV * batch);
+    fill_zero<T>(s, tau, (long)n * batch);
+    fill_zero<int>(s, w.cnt, w.scnt * batch);
+    fill_zero<int>(s, w.abort_, 1);
+    constexpr int R = Pn<T>::R;
+    for (int k0 = 0;; k0 += KB) {
+        const int m = n - k0 - KB;
+        if (m <= 0) break;
+        const int P = cdiv(m, R);
+        // all workgroups of one launch wait for each other: a chunk of the batch
+        // per launch keeps them resident together (one workgroup per compute unit)
+        const int zc = std::max(1, std::min(batch, w.ncu / P));
+        for (int z0 = 0; z0 < batch; z0 += zc)
+            hipLaunchKernelGGL(panel_qr_kernel<T>, dim3(P, 1, std::min(zc, batch - z0)), dim3(PN_THREADS), 0, s, n, k0,
+                               P, z0, A, lda, sA, Vall, tau, w, info);
+        const int t0 = k0 + KB;
+        T* A22 = A + (long)t0 * lda + t0;
+        T* b3 = w.buf3;
+        const long kk = (long)KB * KB;
+        // X = A22 V; X T into the second third of buf3
+        gemm_splitk<T>(s, OP_N, OP_N, m, KB, m, 1.0, A22, lda, b3, 3 * KB, 0.0, w.X, KB, w.P, w.pelems, batch, sA,
+                       w.sbuf, w.sX);
+        gemm<T>(s, OP_N, OP_N, m, KB, KB, 1.0, w.X, KB, w.sX, w.Tf, KB, w.sTf, 0.0, b3 + KB, 3 * KB, w.sbuf, batch);
+        // M = V^H X T, N = T^H M, W = X T - V N / 2 in place
+        gemm_splitk<T>(s, OP_C, OP_N, KB, KB, m, 1.0, b3, 3 * KB, b3 + KB, 3 * KB, 0.0, w.M, KB, w.P, w.pelems, batch,
+                       w.sbuf, w.sbuf, kk);
+        gemm<T>(s, OP_C, OP_N, KB, KB, KB, 1.0, w.Tf, KB, w.sTf, w.M, KB, kk, 0.0, w.N, KB, kk, batch);
+        gemm<T>(s, OP_N, OP_N, m, KB, KB, -0.5, b3, 3 * KB, w.sbuf, w.N, KB, kk, 1.0, b3 + KB, 3 * KB, w.sbuf, batch);
+        // A22 -= [V W] [W V]^H = V W^H + W V^H
+        gemm<T>(s, OP_N, OP_C, m, m, 2 * KB, -1.0, b3, 3 * KB, w.sbuf, b3 + KB, 3 * KB, w.sbuf, 1.0, A22, lda, sA,
+                batch);
+    }
+}
+
+// ---------------------------------------------------------------- stage 2
+template <typename T>
+struct S2 {
+    static constexpr int Q = is_cplx<T>::value ? 8 : 16;  // sweeps (wavefronts) per workgroup
+};
+
+// LDS written by some lanes of a wavefront is read by others: keep the
+// compiler from reordering across this point and wait for the LDS operations.
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline double shfl_(double v, int src) { return __shfl(v, src, WAVE); }
+__device__ inline cplx shfl_(cplx v, int src) { return mk(__shfl(v.x, src, WAVE), __shfl(v.y, src, WAVE)); }
+
+// Reflector of a column held by the lanes of the first half (lane r holds row
+// r, the second half holds zero): every lane gets tau, beta and its row's v_r
+// (v_0 = 1).
+template <typename T>
+__device__ inline void wave_reflector(T x, int r, int h, T& tv, T& vr, double& beta) {
+    const T xr = shfl_(x, r);
+    const T alpha = shfl_(x, 0);
+    const double xn2 = wave_sum((h == 0 && r >= 1) ? abs2_(x) : 0.0);
+    T sc;
+    house<T>(alpha, xn2, tv, sc, beta);
+    vr = (r == 0) ? from_re<T>(1.0) : sc * xr;
+}
+
+template <typename T>
+__global__ __launch_bounds__(64 * S2<T>::Q) void bulge_kernel(int n, int G, int zoff, T* A, int lda, long sA,
+                                                             double* e, BandWork<T> bw, int* info) {
+    constexpr int Q = S2<T>::Q;
+    constexpr int HC = KB / 2;  // columns per lane: lanes r and r + 32 hold the two halves of row r
+    __shared__ T tile[Q][KB][KB + 1];
+    __shared__ T vsh[Q][KB], wsh[Q][KB], ush[Q][KB], vpv[Q][KB];
+    __shared__ int lp[Q];  // progress of each wavefront's current sweep (key, below)
+    const int g = blockIdx.x, z = zoff + blockIdx.z;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = lane & (KB - 1), h = lane >> 5, cb = h * HC;
+    A += z * sA;
+    e += (long)z * n;
+    int* gp = bw.gprog + z * bw.sgp;
+    T* Vpk = bw.Vpk + z * bw.sVpk;
+    T* taupk = bw.taupk + z * bw.staupk;
+    const int ns = n - 1, Tmax = s2_steps(n, 0);
+    // progress key of sweep s with `done` tasks finished: s (Tmax + 1) + done + 1,
+    // increasing along every wavefront's work (0 = nothing yet)
+    const int K = Tmax + 1;
+    if (lane == 0) lp[w] = 0;
+    __syncthreads();
+    T (*tl)[KB + 1] = tile[w];
+    for (int round = 0;; ++round) {
+        const int s = (round * G + g) * Q + w;
+        if (s >= ns) break;
+        const int Ts = s2_steps(n, s);
+        T tprev = zero_<T>();
+        for (int t = 0; t < Ts; ++t) {
+            if (s > 0) {
+                // sweep s-1 must have finished task t+1 (or all of its tasks)
+                const int thr = (s - 1) * K + min(t + 2, s2_steps(n, s - 1)) + 1;
+                int ok = 1;
+                if (lane == 0) {
+                    long polls = 0;
+                    if (w > 0) {
+                        while (__hip_atomic_load(&lp[w - 1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < thr) {
+                            if ((++polls & 1023) == 0 &&
+                                (polls > WAIT_POLLS ||
+                                 __hip_atomic_load(bw.abort_, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                                ok = 0;
+                                break;
+                            }
+                            __builtin_amdgcn_s_sleep(1);
+                        }
+                    } else {
+                        const int pg = g == 0 ? G - 1 : g - 1;
+                        while (__hip_atomic_load(&gp[pg], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < thr) {
+                            if ((++polls & 63) == 0 &&
+                                (polls > WAIT_POLLS_GLOBAL ||
+                                 __hip_atomic_load(bw.abort_, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                                ok = 0;
+                                break;
+                            }
+                            __builtin_amdgcn_s_sleep(1);
+                        }
+                    }
+                    if (!ok) {
+                        atomicExch(bw.abort_, 1);
+                        set_info(info, KS_ERR_NO_CONVERGENCE, -2);
+                    }
+                }
+                ok = __shfl(ok, 0, WAVE);
+                if (!ok) return;
+                if (w == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
+            const int R0 = s + 1 + t * KB;  // first row of block t
+            const int Lr = min(KB, n - R0);
+            T tv, vr;
+            double beta;
+            if (t == 0) {
+                // column s below the subdiagonal
+                const T x = (h == 0 && r < Lr) ? A[(long)(R0 + r) * lda + s] : zero_<T>();
+                wave_reflector<T>(x, r, h, tv, vr, beta);
+                if (h == 0 && r < Lr) A[(long)(R0 + r) * lda + s] = (r == 0) ? from_re<T>(beta) : zero_<T>();
+                if (lane == 0) e[s] = beta;
+            } else {
+                // block t below the previous diagonal block (columns P0 .. P0+KB-1):
+                // B <- B H_prev, then a reflector annihilating B's first column, B <- H^H B
+                const int P0 = R0 - KB;
+                T bv[HC];
+#pragma unroll
+                for (int k = 0; k < HC; ++k) bv[k] = (r < Lr) ? A[(long)(R0 + r) * lda + P0 + cb + k] : zero_<T>();
+                T y = zero_<T>();
+#pragma unroll
+                for (int k = 0; k < HC; ++k) y += bv[k] * vpv[w][cb + k];
+                y += shfl_xor_(y, 32);
+                const T ty = tprev * y;
+#pragma unroll
+                for (int k = 0; k < HC; ++k) bv[k] -= ty * conj_(vpv[w][cb + k]);
+                wave_reflector<T>(h == 0 ? bv[0] : zero_<T>(), r, h, tv, vr, beta);
+                // u_c = sum_r conj(v_r) B[r][c], through the wavefront's LDS tile
+#pragma unroll
+                for (int k = 0; k < HC; ++k) tl[r][cb + k] = conj_(vr) * bv[k];
+                wave_lds_sync();
+                if (lane < KB) {
+                    T u = zero_<T>();
+                    for (int q = 0; q < KB; ++q) u += tl[q][lane];
+                    ush[w][lane] = u;
+                }
+                wave_lds_sync();
+                const T tvr = conj_(tv) * vr;
+#pragma unroll
+                for (int k = 0; k < HC; ++k) bv[k] -= tvr * ush[w][cb + k];
+                if (h == 0) bv[0] = (r == 0) ? from_re<T>(beta) : zero_<T>();
+                if (r < Lr)
+#pragma unroll
+                    for (int k = 0; k < HC; ++k) A[(long)(R0 + r) * lda + P0 + cb + k] = bv[k];
+                wave_lds_sync();
+            }
+            // diagonal block t: D <- H^H D H with w = tau D v - (|tau|^2 v^H D v / 2) v,
+            // D -= v w^H + w v^H (lower triangle stored; mirrored in LDS)
+#pragma unroll
+            for (int k = 0; k < HC; ++k) {
+                const int c = cb + k;
+                if (c <= r && r < Lr) tl[r][c] = A[(long)(R0 + r) * lda + R0 + c];
+            }
+            if (h == 0) vsh[w][r] = vr;
+            wave_lds_sync();
+            T dv[HC];
+#pragma unroll
+            for (int k = 0; k < HC; ++k) {
+                const int c = cb + k;
+                dv[k] = (r < Lr && c < Lr) ? (c <= r ? tl[r][c] : conj_(tl[c][r])) : zero_<T>();
+            }
+            T p = zero_<T>();
+#pragma unroll
+            for (int k = 0; k < HC; ++k) p += dv[k] * vsh[w][cb + k];
+            p += shfl_xor_(p, 32);
+            const T w0 = tv * p;
+            const T kv = wave_sum(h == 0 ? conj_(vr) * w0 : zero_<T>());
+            const double alw = -0.5 * re_(conj_(tv) * kv);
+            const T wr = w0 + alw * vr;
+            if (h == 0) wsh[w][r] = wr;
+            wave_lds_sync();
+#pragma unroll
+            for (int k = 0; k < HC; ++k) {
+                const int c = cb + k;
+                dv[k] -= vr * conj_(wsh[w][c]) + wr * conj_(vsh[w][c]);
+                if (c <= r && r < Lr)
+                    A[(long)(R0 + r) * lda + R0 + c] = (c == r) ? from_re<T>(re_(dv[k])) : dv[k];
+            }
+            // the reflector: kept for the next task, and stored in its group's
+            // column (group j = s / Q2_NB at step t, column s % Q2_NB, from row s % Q2_NB)
+            if (h == 0) vpv[w][r] = vr;
+            tprev = tv;
+            {
+                const int j = s / Q2_NB, q = s % Q2_NB;
+                T* vg = Vpk + ((long)j * Tmax + t) * Q2_GL * Q2_NB;
+                if (h == 0 && r < Lr) vg[(long)(q + r) * Q2_NB + q] = vr;
+                if (lane == 0) taupk[((long)j * Tmax + t) * Q2_NB + q] = tv;
+            }
+            wave_lds_sync();
+            const int key = s * K + t + 2;  // t + 1 tasks done
+            if (lane == 0) {
+                __hip_atomic_store(&lp[w], key, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (w == Q - 1) __hip_atomic_store(&gp[g], key, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    }
+}
+
+template <typename T>
+__global__ void band_diag_kernel(int n, const T* A, int lda, long sA, double* d) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, z = blockIdx.y;
+    if (i < n) d[(long)z * n + i] = re_(A[z * sA + (long)i * lda + i]);
+}
+
+template <typename T>
+void hb2st(hipStream_t s, int n, T* A, int lda, long sA, int batch, double* d, double* e, BandWork<T>& w,
+           int* info) {
+    const int ns = n - 1;
+    if (ns > 0) {
+        constexpr int Q = S2<T>::Q;
+        const int Tmax = s2_steps(n, 0);
+        fill_zero<T>(s, w.Vpk, w.sVpk * batch);
+        fill_zero<T>(s, w.taupk, w.staupk * batch);
+        fill_zero<int>(s, w.gprog, w.sgp * batch);
+        // about Tmax / 2 sweeps are in flight at once (each starts two tasks
+        // after its predecessor and lasts up to Tmax tasks)
+        int G = std::min(cdiv(ns, Q), cdiv(Tmax, 2 * Q) + 2);
+        G = std::max(1, std::min(G, std::min((int)w.sgp, w.ncu)));
+        const int zc = std::max(1, std::min(batch, w.ncu / G));
+        for (int z0 = 0; z0 < batch; z0 += zc)
+            hipLaunchKernelGGL(bulge_kernel<T>, dim3(G, 1, std::min(zc, batch - z0)), dim3(64 * Q), 0, s, n, G, z0, A,
+                               lda, sA, e, w, info);
+    }
+    hipLaunchKernelGGL(band_diag_kernel<T>, dim3(cdiv(n, 256), batch), dim3(256), 0, s, n, (const T*)A, lda, sA, d);
+}
+
+// ---------------------------------------------------------------- stage-2 back-transform
+// The compact-WY factor of every group (j, t): the reflectors of sweeps
+// j Q2_NB .. j Q2_NB + Q2_NB - 1 at step t, column q starting at row q of the
+// group's Q2_GL x Q2_NB matrix V (zeros elsewhere; missing reflectors are zero
+// with tau = 0).  T solves the forward recurrence T[q][q] = tau_q,
+// T[0:q, q] = -tau_q T[0:q, 0:q] (V^H V)[0:q, q].
+template <typename T>
+__global__ __launch_bounds__(256) void q2_tfactor_kernel(int n, int Tmax, BandWork<T> bw) {
+    const int j = blockIdx.x, t = blockIdx.y, z = blockIdx.z;
+    if (t >= s2_steps(n, j * Q2_NB)) return;
+    const long grp = (long)j * Tmax + t;
+    const T* V = bw.Vpk + z * bw.sVpk + grp * Q2_GL * Q2_NB;
+    const T* tau = bw.taupk + z * bw.staupk + grp * Q2_NB;
+    T* Tg = bw.Tpk + z * bw.sTpk + grp * Q2_NB * Q2_NB;
+    __shared__ T sv[Q2_GL][Q2_NB + 1];
+    __shared__ T sg[Q2_NB][Q2_NB + 1];
+    __shared__ T st[Q2_NB][Q2_NB + 1];
+    __shared__ T stau[Q2_NB];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < Q2_GL * Q2_NB; e += 256) sv[e / Q2_NB][e % Q2_NB] = V[e];
+    for (int e = tid; e < Q2_NB * (Q2_NB + 1); e += 256) st[e / (Q2_NB + 1)][e % (Q2_NB + 1)] = zero_<T>();
+    if (tid < Q2_NB) stau[tid] = tau[tid];
+    __syncthreads();
+    for (int e = tid; e < Q2_NB * Q2_NB; e += 256) {
+        const int a = e / Q2_NB, b = e % Q2_NB;
+        T acc = zero_<T>();
+        if (a < b)
+            for (int rr = 0; rr < Q2_GL; ++rr) acc += conj_(sv[rr][a]) * sv[rr][b];
+        sg[a][b] = acc;
+    }
+    __syncthreads();
+    for (int q = 0; q < Q2_NB; ++q) {
+        if (tid < q) {
+            T acc = zero_<T>();
+            for (int l = tid; l < q; ++l) acc += st[tid][l] * sg[l][q];
+            st[tid][q] = -(stau[q] * acc);
+        } else if (tid == q) {
+            st[q][q] = stau[q];
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < Q2_NB * Q2_NB; e += 256) Tg[e] = st[e / Q2_NB][e % Q2_NB];
+}
+
+// X <- Q2 X: the groups in the order (j descending, t ascending) that the
+// reflectors' overlaps require, level by level: group (j, t) at level
+// t + 3 (J - 1 - j); the groups of one level touch disjoint rows.
+template <typename T>
+void q2_apply(hipStream_t s, int n, int batch, int ncols, T* X, int ldx, long sX, BandWork<T>& w) {
+    const int ns = n - 1;
+    if (ns <= 0 || ncols <= 0) return;
+    const int J = cdiv(ns, Q2_NB), Tmax = s2_steps(n, 0);
+    hipLaunchKernelGGL(q2_tfactor_kernel<T>, dim3(J, Tmax, batch), dim3(256), 0, s, n, Tmax, w);
+    const int nlev = Tmax + 3 * (J - 1);
+    for (int lv = 0; lv < nlev; ++lv) q2_level<T>(s, n, batch, lv, ncols, X, ldx, sX, w);
+}
+
+template void he2hb<double>(hipStream_t, int, double*, int, long, int, double*, double*, BandWork<double>&, int*);
+template void he2hb<cplx>(hipStream_t, int, cplx*, int, long, int, cplx*, cplx*, BandWork<cplx>&, int*);
+template void hb2st<double>(hipStream_t, int, double*, int, long, int, double*, double*, BandWork<double>&, int*);
+template void hb2st<cplx>(hipStream_t, int, cplx*, int, long, int, double*, double*, BandWork<cplx>&, int*);
+template void q2_apply<double>(hipStream_t, int, int, int, double*, int, long, BandWork<double>&);
+template void q2_apply<cplx>(hipStream_t, int, int, int, cplx*, int, long, BandWork<cplx>&);
+
+}  // namespace ks

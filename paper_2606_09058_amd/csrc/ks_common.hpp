@@ -143,6 +143,18 @@ __device__ inline void set_info(int* info, int code, int detail) {
     if (atomicCAS(info, 0, code) == 0) info[1] = detail;
 }
 
+// ---------------------------------------------------------------- two-stage reduction
+// Half-bandwidth of the band form between the two stages, and the grouping of
+// the bulge-chasing reflectors for the blocked back-transform: Q2_NB
+// consecutive sweeps at one step form one compact-WY block whose reflectors,
+// each shifted down a row from the previous, fit a Q2_GL x Q2_NB matrix.
+constexpr int KB = 32;
+constexpr int Q2_NB = 32;
+constexpr int Q2_GL = KB + Q2_NB - 1;
+// Steps (tasks) of bulge-chasing sweep s of an order-n band: one per KB rows
+// below the subdiagonal entry it starts from.
+__host__ __device__ inline int s2_steps(int n, int s) { return (n - 1 - s + KB - 1) / KB; }
+
 // ---------------------------------------------------------------- host side
 #define KS_HIP(x)                                   \
     do {                                            \

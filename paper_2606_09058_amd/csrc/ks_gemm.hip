@@ -18,7 +18,7 @@
 #include <algorithm>
 #include <type_traits>
 
-#include "ks_common.hpp"
+#include "ks_internal.hpp"
 
 namespace ks {
 
@@ -350,6 +350,46 @@ __global__ __launch_bounds__(256) void gemm_kernel(int m, int n, int K, double a
     gemm_tile<T, OPA, OPB>(m, n, K, alpha, A + b * sa, lda, B + b * sb, ldb, beta, C + b * sc, ldc,
                            kscale ? kscale + b * sk : nullptr, uplo, m0, n0, klo);
 }
+
+// ---------------------------------------------------------------- two-stage back-transform
+// One level of X <- Q2 X (bulge-chasing reflectors, ks_band.hip): workgroup
+// (j, c) applies group (j, t), t = level - 3 (J - 1 - j), to the 64 columns of
+// X from c * 64 on: rows r0 = j Q2_NB + 1 + t KB .. r0 + L - 1 (L <= Q2_GL),
+// W1 = V^H X, W2 = T W1, X -= V W2, three tile products through the group's
+// scratch rows of W1 and W2.  Groups that do not exist at this level leave.
+template <typename T>
+__global__ __launch_bounds__(256) void q2_group_kernel(int n, int J, int Tmax, int level, int ncols, T* X, int ldx,
+                                                       long sX, const T* Vpk, long sVpk, const T* Tpk, long sTpk,
+                                                       T* W1, T* W2, long sW) {
+    const int j = blockIdx.x, z = blockIdx.z;
+    const int t = level - 3 * (J - 1 - j);
+    const int s0 = j * Q2_NB;
+    if (t < 0 || t >= s2_steps(n, s0)) return;
+    const int r0 = s0 + 1 + t * KB;
+    const int L = min(Q2_GL, n - r0);
+    const int c0 = blockIdx.y * BN;
+    const long grp = (long)j * Tmax + t;
+    const T* V = Vpk + z * sVpk + grp * Q2_GL * Q2_NB;
+    const T* Tg = Tpk + z * sTpk + grp * Q2_NB * Q2_NB;
+    T* Xg = X + z * sX + (long)r0 * ldx;
+    T* w1 = W1 + z * sW + (long)j * Q2_NB * ncols;
+    T* w2 = W2 + z * sW + (long)j * Q2_NB * ncols;
+    gemm_tile<T, OP_C, OP_N>(Q2_NB, ncols, L, 1.0, V, Q2_NB, Xg, ldx, 0.0, w1, ncols, nullptr, UPLO_FULL, 0, c0);
+    __syncthreads();
+    gemm_tile<T, OP_N, OP_N>(Q2_NB, ncols, Q2_NB, 1.0, Tg, Q2_NB, w1, ncols, 0.0, w2, ncols, nullptr, UPLO_FULL, 0,
+                             c0);
+    __syncthreads();
+    gemm_tile<T, OP_N, OP_N>(L, ncols, Q2_NB, -1.0, V, Q2_NB, w2, ncols, 1.0, Xg, ldx, nullptr, UPLO_FULL, 0, c0);
+}
+
+template <typename T>
+void q2_level(hipStream_t s, int n, int batch, int level, int ncols, T* X, int ldx, long sX, const BandWork<T>& w) {
+    const int J = cdiv(n - 1, Q2_NB), Tmax = s2_steps(n, 0);
+    hipLaunchKernelGGL((q2_group_kernel<T>), dim3(J, cdiv(ncols, BN), batch), dim3(256), 0, s, n, J, Tmax, level,
+                       ncols, X, ldx, sX, (const T*)w.Vpk, w.sVpk, (const T*)w.Tpk, w.sTpk, w.W1, w.W2, w.sW);
+}
+template void q2_level<double>(hipStream_t, int, int, int, int, double*, int, long, const BandWork<double>&);
+template void q2_level<cplx>(hipStream_t, int, int, int, int, cplx*, int, long, const BandWork<cplx>&);
 
 // ---------------------------------------------------------------- large tiles
 // Large tiles only where they pay: enough k steps to amortise the tile's

@@ -129,6 +129,26 @@ struct BacktrWork {
     int bt = BACKTR_BT;  // reflectors per block for this plan's order (a multiple of BACKTR_SUB)
 };
 
+// Buffers of the two-stage reduction (ks_band.hip) for one element type; every
+// pointer holds `batch` consecutive per-matrix buffers of the given stride.
+template <typename T>
+struct BandWork {
+    T* X = nullptr;      long sX = 0;     // order x KB: A22 V of a panel
+    T* buf3 = nullptr;   long sbuf = 0;   // order x 3KB: [V | X T, then W | V] of a panel
+    T* Tf = nullptr;     long sTf = 0;    // KB x KB: compact-WY factor of a panel
+    T* M = nullptr;      T* N = nullptr;  // KB x KB each (stride KB^2): V^H X T, T^H V^H X T
+    T* rec = nullptr;    long srec = 0;   // 2 x pmax x 2KB: per-workgroup partial sums of a panel column
+    int* cnt = nullptr;  long scnt = 0;   // one arrival counter per panel
+    int* gprog = nullptr; long sgp = 0;   // bulge chasing: progress of each workgroup's last sweep
+    int* abort_ = nullptr;                // set by a wait that gave up: every wait then leaves
+    T* Vpk = nullptr;    long sVpk = 0;   // J x Tmax x Q2_GL x Q2_NB: bulge-chasing reflectors per group
+    T* taupk = nullptr;  long staupk = 0; // J x Tmax x Q2_NB
+    T* Tpk = nullptr;    long sTpk = 0;   // J x Tmax x Q2_NB x Q2_NB: compact-WY factors of the groups
+    T* W1 = nullptr;     T* W2 = nullptr; long sW = 0;  // J Q2_NB x order: group products
+    T* P = nullptr;      long pelems = 0; // split-K partial products (shared with the back-transform)
+    int ncu = 1;                          // compute units: every workgroup of a waiting kernel must be resident
+};
+
 // Divide-and-conquer scratch; all position-indexed arrays have n entries and
 // each merge uses the slice [lo, hi) of its rows.
 struct DcWork {
@@ -208,6 +228,29 @@ template <typename T>
 int hetrd_tune(hipStream_t s, int n, T* A, int lda, long sA, int batch, double* d, double* e, T* tau,
                HetrdWork<T>& w, int* cand, double* ms, int reps, int* seg_first, int* seg_tiles);
 
+// Two-stage reduction of a batch of Hermitian matrices (A: order n, row
+// stride lda, matrix stride sA; the lower triangle is read) to real symmetric
+// tridiagonal form: he2hb reduces A to a band of half-bandwidth KB (panel QR
+// + two-sided rank-2KB updates on the matrix cores) and leaves the panel
+// reflectors in Vall (n x n per matrix, reflector c in column c from row c+KB
+// on, zeros elsewhere) with tau; hb2st chases the band to tridiagonal form
+// (d, e: stride n) and keeps its reflectors grouped for q2_apply, which forms
+// X <- Q2 X for the n x ncols blocks of X.  A wait that gives up (a resident
+// workgroup never arrived) records KS_ERR_NO_CONVERGENCE with detail -1
+// (stage 1) or -2 (stage 2) and every kernel still ends.
+template <typename T>
+void he2hb(hipStream_t s, int n, T* A, int lda, long sA, int batch, T* Vall, T* tau, BandWork<T>& w, int* info);
+template <typename T>
+void hb2st(hipStream_t s, int n, T* A, int lda, long sA, int batch, double* d, double* e, BandWork<T>& w,
+           int* info);
+template <typename T>
+void q2_apply(hipStream_t s, int n, int batch, int ncols, T* X, int ldx, long sX, BandWork<T>& w);
+// One level of the blocked application of the bulge-chasing reflectors
+// (ks_gemm.hip): every group (j, t) with t = level - 3 (J - 1 - j) is applied to
+// its rows of X, all of X's columns, by three MFMA tile products per 64 columns.
+template <typename T>
+void q2_level(hipStream_t s, int n, int batch, int level, int ncols, T* X, int ldx, long sX, const BandWork<T>& w);
+
 // Divide and conquer for a batch of tridiagonals of order tr.n (d, e, lam:
 // stride n; Z, Z2, U, Qp: stride n^2; the work arrays of w: stride n, with
 // kk, nrot, rho holding batch x (merges of the widest level)).
@@ -268,3 +311,4 @@ void merge_info(hipStream_t s, int* inner, int* outer);
 // Stage drivers behind the test hooks (defined in ks_api.hip).
 void ks_internal_stedc(ks_plan* p, const double* d, const double* e, double* lam, double* Z);
 void ks_internal_hetrd(ks_plan* p, void* A, double* d, double* e, const double* X, int ncols, void* Y);
+void ks_internal_he2hb(ks_plan* p, void* A, const double* X, int ncols, void* Y);

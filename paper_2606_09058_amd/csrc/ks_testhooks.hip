@@ -127,6 +127,35 @@ int32_t ks_test_hetrd(int32_t dtype, int32_t n, void* A, double* d, double* e, c
     return s2;
 }
 
+int32_t ks_test_hetrd2(int32_t dtype, int32_t n, void* A, double* d, double* e, const double* X,
+                       int32_t ncols, void* Y, void* stream) {
+    if (!A || !d || !e || !X || !Y || n < 1 || ncols < 1) return KS_ERR_INVALID_ARG;
+    ks_plan_desc desc = {n, 1, dtype == 1 ? KS_COMPLEX128 : KS_REAL64, KS_COLLINEAR, KS_FP64, n, n, stream,
+                         KS_PLAN_TWOSTAGE};
+    ks_plan* p = nullptr;
+    ks_status st = ks_plan_create(&desc, &p);
+    if (st != KS_OK) return st;
+    ks_internal_hetrd(p, A, d, e, X, ncols, Y);
+    int32_t inf = 0;
+    ks_status s2 = ks_plan_get_info(p, &inf);
+    ks_plan_destroy(p);
+    return s2;
+}
+
+int32_t ks_test_he2hb(int32_t dtype, int32_t n, void* A, const double* X, int32_t ncols, void* Y, void* stream) {
+    if (!A || !X || !Y || n < 1 || ncols < 1) return KS_ERR_INVALID_ARG;
+    ks_plan_desc desc = {n, 1, dtype == 1 ? KS_COMPLEX128 : KS_REAL64, KS_COLLINEAR, KS_FP64, n, n, stream,
+                         KS_PLAN_TWOSTAGE};
+    ks_plan* p = nullptr;
+    ks_status st = ks_plan_create(&desc, &p);
+    if (st != KS_OK) return st;
+    ks_internal_he2hb(p, A, X, ncols, Y);
+    int32_t inf = 0;
+    ks_status s2 = ks_plan_get_info(p, &inf);
+    ks_plan_destroy(p);
+    return s2;
+}
+
 int32_t ks_test_set_iteration_caps(int32_t leaf_sweeps, int32_t secular_iters) {
     ks::stedc_set_caps(leaf_sweeps, secular_iters);
     return KS_OK;

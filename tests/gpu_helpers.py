@@ -27,9 +27,9 @@ def stream_handle():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def solve_gpu(p, il=1, iu=None, check=True):
+def solve_gpu(p, il=1, iu=None, check=True, flags=0):
     """Run ks_gevd + ks_density on a Problem; returns numpy results and the plan."""
-    plan = ks.Plan(p.n, batch=p.batch, complex=np.iscomplexobj(p.H), noncollinear=p.nsp == 2)
+    plan = ks.Plan(p.n, batch=p.batch, complex=np.iscomplexobj(p.H), noncollinear=p.nsp == 2, flags=flags)
     H = dev(p.H)
     S = dev(p.S.astype(p.H.dtype))
     out = plan.solve(H, S, p.n_electrons, p.kT, il=il, iu=iu, kweights=p.weights, check=check)

@@ -51,7 +51,7 @@ def desc(n=100, batch=1, dtype=0, spin=0, prec=0, ldh=None, lds=None, flags=0):
 
 @pytest.mark.parametrize("bad", [
     dict(n=0), dict(batch=0), dict(dtype=2), dict(spin=3), dict(prec=7), dict(ldh=99),
-    dict(lds=50), dict(flags=8), dict(n=40000, spin=1, dtype=1),
+    dict(lds=50), dict(flags=16), dict(n=40000, spin=1, dtype=1),
 ])
 def test_plan_create_rejects_bad_descriptors_without_device(L, bad):
     h = ctypes.c_void_p()
@@ -69,6 +69,8 @@ def test_plan_create_unsupported_combinations(L):
     assert L.ks_plan_create(ctypes.byref(desc(flags=ks.KS_PLAN_GRAPH)), ctypes.byref(h)) == 9
     # the Loewdin route is FP64 only
     assert L.ks_plan_create(ctypes.byref(desc(prec=ks.KS_MIXED, flags=ks.KS_PLAN_LOWDIN)), ctypes.byref(h)) == 9
+    # so is the two-stage reduction
+    assert L.ks_plan_create(ctypes.byref(desc(prec=ks.KS_MIXED, flags=ks.KS_PLAN_TWOSTAGE)), ctypes.byref(h)) == 9
     assert not h.value
     assert L.ks_plan_create(ctypes.byref(desc()), None) == 1
     assert L.ks_plan_create(None, ctypes.byref(h)) == 1
@@ -121,6 +123,20 @@ def test_plan_flags_accepted(L):
     assert L.ks_plan_workspace_bytes(ctypes.byref(d)) > 0
     d = desc(flags=ks.KS_PLAN_GRAPH | ks.KS_PLAN_AUTOTUNE | ks.KS_PLAN_LOWDIN)
     assert L.ks_plan_workspace_bytes(ctypes.byref(d)) > 0
+    d = desc(flags=ks.KS_PLAN_GRAPH | ks.KS_PLAN_AUTOTUNE | ks.KS_PLAN_LOWDIN | ks.KS_PLAN_TWOSTAGE)
+    assert L.ks_plan_workspace_bytes(ctypes.byref(d)) > 0
+
+
+def test_twostage_workspace(L):
+    """KS_PLAN_TWOSTAGE adds the bulge-chasing reflectors grouped in blocks of 32
+    sweeps (63 x 32 per group, about 2 order^2 elements), their triangular
+    factors (order^2) and the two group-product buffers (2 order^2): about
+    5 order^2 elements on top of the one-stage plan."""
+    for n, dt, es in ((2000, 0, 8), (1500, 1, 16)):
+        b = L.ks_plan_workspace_bytes(ctypes.byref(desc(n=n, dtype=dt)))
+        b2 = L.ks_plan_workspace_bytes(ctypes.byref(desc(n=n, dtype=dt, flags=ks.KS_PLAN_TWOSTAGE)))
+        extra = (b2 - b) / (es * n * n)
+        assert 4.5 < extra < 6.0, extra
 
 
 def test_tuning_and_graph_stats_reject_null(L):

@@ -25,8 +25,12 @@ def golden(name):
     return json.load(open(path)) if os.path.exists(path) else None
 
 
-def gpu_solve(p):
-    plan = ks.Plan(p.n, batch=p.batch, complex=np.iscomplexobj(p.H), noncollinear=p.nsp == 2)
+# one-stage Householder tridiagonalisation, and the two-stage reduction
+ROUTES = [pytest.param(0, id="onestage"), pytest.param(ks.KS_PLAN_TWOSTAGE, id="twostage")]
+
+
+def gpu_solve(p, flags=0):
+    plan = ks.Plan(p.n, batch=p.batch, complex=np.iscomplexobj(p.H), noncollinear=p.nsp == 2, flags=flags)
     H = dev(p.H)
     S = dev(p.S.astype(p.H.dtype))
     out = plan.solve(H, S, p.n_electrons, p.kT, kweights=p.weights)
@@ -61,10 +65,11 @@ def check_against_golden(g, eps, mu, eband, rho_list, order):
         assert np.abs(got - ref).max() < 1e-9
 
 
-def test_supercell6656_full_size():
-    announce("supercell6656 full size")
+@pytest.mark.parametrize("flags", ROUTES)
+def test_supercell6656_full_size(flags):
+    announce("supercell6656 full size", flags)
     p = I.workload("supercell6656")
-    plan, H, S, out = gpu_solve(p)
+    plan, H, S, out = gpu_solve(p, flags)
     res, orth, tr, herm, comm = properties(H, S, out, 1)
     assert res < 1e-12, res
     assert orth < 1e-11, orth
@@ -79,10 +84,11 @@ def test_supercell6656_full_size():
                              p.order)
 
 
-def test_noncollinear9984_full_size():
-    announce("noncollinear9984 full size")
+@pytest.mark.parametrize("flags", ROUTES)
+def test_noncollinear9984_full_size(flags):
+    announce("noncollinear9984 full size", flags)
     p = I.workload("noncollinear9984")
-    plan, H, S, out = gpu_solve(p)
+    plan, H, S, out = gpu_solve(p, flags)
     res, orth, tr, herm, comm = properties(H, S, out, 2)
     assert res < 1e-12, res
     assert orth < 1e-11, orth
@@ -96,16 +102,17 @@ def test_noncollinear9984_full_size():
                              [host(out["rho"])], p.order)
 
 
-def test_noncollinear4160_against_oracle():
+@pytest.mark.parametrize("flags", ROUTES)
+def test_noncollinear4160_against_oracle(flags):
     """The spinor workload on a 160-atom lattice (order 4160 complex: 256-reflector
     back-transform blocks, large-tile complex GEMMs and divide-and-conquer merges
     above 2048) against the oracle's stored eigenvalues, mu, E_band and sampled
     density entries."""
-    announce("noncollinear4160 vs oracle")
+    announce("noncollinear4160 vs oracle", flags)
     p = I.workload("noncollinear4160")
     g = golden("noncollinear4160")
     assert g is not None and g["inputs_sha256"] == p.digest()
-    plan, H, S, out = gpu_solve(p)
+    plan, H, S, out = gpu_solve(p, flags)
     res, orth, tr, herm, comm = properties(H, S, out, 2)
     assert res < 1e-12 and orth < 1e-11 and herm < 1e-13 and comm < 1e-12
     assert abs(tr - p.n_electrons) < 1e-10 * p.n_electrons
@@ -131,17 +138,18 @@ def _known_rows(p, rows):
     return out
 
 
-def test_known_spectrum_spinor9984():
+@pytest.mark.parametrize("flags", ROUTES)
+def test_known_spectrum_spinor9984(flags):
     """Order 9984 complex spinor problem with a spectrum fixed by construction
     (H = B Q Lambda Q B^H, S = L0 L0^H, B = diag(L0, L0); close pairs 1e-7 Ha
     apart and exact ties): every eigenvalue within 1e-10 Ha of Lambda, mu and
     E_band from the oracle's bisection on Lambda, and a 64 x 64 block of rho
     against C = B^-H Q of the construction, element by element."""
     from oracle import oracle as O
-    announce("known spectrum 9984")
+    announce("known spectrum 9984", flags)
     p = I.known_spectrum_spinor(seed=0)
     lam = p.meta["lam"]
-    plan, H, S, out = gpu_solve(p)
+    plan, H, S, out = gpu_solve(p, flags)
     plan.check("known spectrum solve")
     eps = host(out["eps"])
     assert np.all(np.diff(eps) >= 0)
@@ -158,11 +166,12 @@ def test_known_spectrum_spinor9984():
     assert np.abs(host(rho) - ref).max() < 1e-9
 
 
-def test_kpoints16x1300_full_size():
-    announce("kpoints16x1300 full size")
+@pytest.mark.parametrize("flags", ROUTES)
+def test_kpoints16x1300_full_size(flags):
+    announce("kpoints16x1300 full size", flags)
     p = I.workload("kpoints16x1300")
     g = golden("kpoints16x1300")
-    plan, H, S, out = gpu_solve(p)
+    plan, H, S, out = gpu_solve(p, flags)
     for k in range(p.batch):
         sub = {key: out[key][k] for key in ("eps", "C", "rho")}
         res, orth, tr, herm, comm = properties(H[k], S[k], sub, 1)
