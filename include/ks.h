@@ -177,6 +177,29 @@ ks_status ks_density(ks_plan* plan, const double* eps, const void* C, int32_t il
                      double n_electrons, double kT, const double* kweights, void* rho,
                      double* mu, double* eband, double* occ);
 
+/* ks_density for callers that cannot allocate device memory (code under graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation with the same kernels, so the same results bit for bit, but it
+ * takes the descriptor the eigenvectors were computed under instead of a plan
+ * and allocates nothing.  Its scratch (the occupied-window count, and the
+ * occupations and the failure word when occ / info are NULL) is a static
+ * device array of 1 MiB per GPU, held until the process ends.
+ *   desc     n, batch, dtype, spin, ld_h, stream as for the plan (precision,
+ *            ld_s and flags are not used)
+ *   info     device int32[2] or NULL: info[0] = ks_status of a failure found on
+ *            the device (KS_ERR_WINDOW), 0 if none; info[1] = its detail.  The
+ *            call clears it first.  With NULL the word lives in the scratch and
+ *            cannot be read back.
+ *   other arguments as for ks_density.
+ * KS_ERR_ALLOC, before any device work, if occ is NULL and batch * order
+ * exceeds 131008 (the occupations would not fit the scratch); argument errors
+ * as for ks_density.  All calls on one GPU share its scratch: calls that overlap
+ * in time on one GPU (two streams, two host threads) race and must not be
+ * issued; consecutive calls on one stream are safe. */
+ks_status ks_density_noalloc(const ks_plan_desc* desc, const double* eps, const void* C, int32_t il, int32_t iu,
+                             double n_electrons, double kT, const double* kweights, void* rho, double* mu,
+                             double* eband, double* occ, int32_t* info);
+
 /* Energy-density matrix E_k = C_k diag(f_k eps_k) C_k^H (paper Sec. 3.1, the
  * Part 4 quantity needed for forces; with H C = S C eps it equals
  * S^-1 H rho, and tr(E S) = E_band per k).  Not positive semi-definite, so it
