@@ -411,7 +411,10 @@ def other_config(name, stream, stride, steps=3):
     del runs, ref
     torch.cuda.empty_cache()
     if p.batch > 1:
-        g = time_route(p, H, S, "onestage", steps, 1, stride, stream, graph=True, warm=False, tag=name + " graph ")
+        # graph capture needs a stream of its own
+        torch.cuda.synchronize()
+        g = time_route(p, H, S, "onestage", steps, 1, stride, torch.cuda.Stream(), graph=True, warm=False,
+                       tag=name + " graph ")
         res["graph_s_per_batch"] = g["ms"] / 1e3
         res["graph_ms_per_kpoint"] = g["ms"] / p.batch
         res["graph_replays"] = g["plan"].graph_stats()[1]

@@ -249,7 +249,7 @@ ks_status ks_density_backward(ks_plan* plan, const double* eps, const void* C, c
 enum {
     KS_PHASE_CHOLESKY = 0, KS_PHASE_REDUCE = 1, KS_PHASE_TRIDIAG = 2, KS_PHASE_DC = 3,
     KS_PHASE_BACKTR = 4, KS_PHASE_DENSITY = 5, KS_PHASE_ADJOINT = 6,
-    KS_PHASE_REFINE = 7,      /* KS_MIXED: correction sweeps + Rayleigh-Ritz        */
+    KS_PHASE_REFINE = 7,      /* KS_MIXED: correction sweeps + subspace step        */
     KS_NPHASE = 8
 };
 typedef struct {
@@ -288,12 +288,17 @@ typedef struct {
 } ks_tuning;
 ks_status ks_plan_get_tuning(ks_plan* plan, ks_tuning* out);
 
-/* KS_MIXED plans: the number of correction sweeps (0 .. 4, default 2) applied
- * to the window's FP32 eigenvectors before the final FP64 Rayleigh-Ritz step.
- * Each sweep shrinks the window subspace's components along the other
- * eigenvectors by about u32 ||A|| / gap (u32 the FP32 unit roundoff, gap the
- * distance from the window's eigenvalues to the rest of the spectrum), and
- * the Rayleigh-Ritz eigenvalues carry the square of what is left.  Host-only;
+/* KS_MIXED plans: the number of correction sweeps (0 .. 4, default 1) applied
+ * to the window's FP32 eigenvectors before the FP64 subspace step.  Each sweep
+ * shrinks the window subspace's components along the other eigenvectors by
+ * about u32 ||A|| / gap (u32 the FP32 unit roundoff, gap the distance from the
+ * window's eigenvalues to the rest of the spectrum).  The subspace step then
+ * solves the window's eigenproblem inside the corrected subspace,
+ * G = X^H A X with B = X^H X, by two refinement passes on the M x M matrices
+ * (a first-order orthonormalising and diagonalising correction between
+ * groups of eigenvalues more than 2e-6 max|eps| apart, an exact Jacobi solve
+ * inside each closer group, groups of more than 64 taken in pieces of 64);
+ * its eigenvalues carry the square of what the sweeps leave.  Host-only;
  * KS_ERR_INVALID_ARG outside the range, KS_ERR_NOT_SUPPORTED on an FP64 plan. */
 ks_status ks_plan_set_refinement(ks_plan* plan, int32_t sweeps);
 

@@ -74,8 +74,11 @@ struct ks_plan {
     void* mB = nullptr;        // order x order   X^H X
     void* mP = nullptr;        // order x order   FP32 work
     void* mP2 = nullptr;       // order x order   FP32 work
-    double* theta = nullptr;   // order           Ritz values
-    ks_plan* rr = nullptr;     // order-M plan of the Rayleigh-Ritz problem
+    double* theta = nullptr;   // order           refined window values
+    void* mS = nullptr;        // order x order   M x M scratch of the subspace refinement
+    void* mS2 = nullptr;       // order x order   M x M scratch of the subspace refinement
+    int* mI = nullptr;         // 3 x order       cluster starts, sizes and ranks of the window
+    ks_plan* rr = nullptr;     // unused (kept null)
     // KS_PLAN_LOWDIN: V = U s^-1/2 lives in L (batch x n x n); sev holds the
     // eigenvalues s of S; spinor plans solve the order-n eigenproblem of S on
     // the collinear plan ov (collinear plans use their own buffers)
@@ -85,7 +88,7 @@ struct ks_plan {
     double ov_tau = 0.0;       // cutoff tau of ks_plan_set_overlap_cutoff
     double v_tau = 0.0;        // the cutoff the V in use was formed with
     ks_plan* ov = nullptr;
-    int mixed_sweeps = 2;
+    int mixed_sweeps = 1;
     // k weights of the last ks_density call (uniform until then); the adjoint's
     // chemical-potential and band-energy terms use the same weights
     KWeights kw_last{};
@@ -207,7 +210,7 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
     const bool mixed = d->precision == KS_MIXED;
     const size_t es32 = es / 2, mat = order * order;
     size_t oA32 = 0, oW32 = 0, oT32 = 0, oZ32 = 0, oMY = 0, oMR = 0, oMG = 0, oMB = 0, oMP = 0, oMP2 = 0;
-    size_t oTh = 0, oVWl = 0, oWVl = 0;
+    size_t oTh = 0, oVWl = 0, oWVl = 0, oMS = 0, oMS2 = 0, oMI = 0;
     if (mixed) {
         oA32 = L.take(B * mat * es32);
         oW32 = L.take(B * mat * es32);
@@ -220,6 +223,9 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
         oMP = L.take(B * mat * es32);
         oMP2 = L.take(B * mat * es32);
         oTh = L.take(B * order * 8);
+        oMS = L.take(B * mat * es);
+        oMS2 = L.take(B * mat * es);
+        oMI = L.take(3 * B * order * sizeof(int));
         oVWl = L.take(B * hVW * es32);
         oWVl = L.take(B * hVW * es32);
     }
@@ -309,6 +315,9 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
         p->mP = b + oMP;
         p->mP2 = b + oMP2;
         p->theta = (double*)(b + oTh);
+        p->mS = b + oMS;
+        p->mS2 = b + oMS2;
+        p->mI = (int*)(b + oMI);
     }
     setH(p->hr, (double*)nullptr);
     setH(p->hc, (cplx*)nullptr);
@@ -448,27 +457,6 @@ void apply_linv_h(ks_plan* p, const T* Li, const T* X, long sX, int ncols, T* C)
     }
 }
 
-// The Rayleigh-Ritz plan of the mixed form: order m, same batch, type and
-// stream, FP64.  Created (or re-created for another m) outside any capture.
-ks_status ensure_rr_plan(ks_plan* p, int m) {
-    if (p->rr && p->rr->d.n == m) return KS_OK;
-    if (p->rr) {
-        ks_plan_destroy(p->rr);
-        p->rr = nullptr;
-    }
-    ks_plan_desc d{};
-    d.n = m;
-    d.batch = p->d.batch;
-    d.dtype = p->d.dtype;
-    d.spin = KS_COLLINEAR;
-    d.precision = KS_FP64;
-    d.ld_h = m;
-    d.ld_s = m;
-    d.stream = p->d.stream;
-    d.flags = 0;
-    return ks_plan_create(&d, &p->rr);
-}
-
 template <typename T>
 HetrdWork<T>& hetrd_work(ks_plan* p) {
     return *reinterpret_cast<HetrdWork<T>*>(is_cplx<T>::value ? (void*)&p->hc : (void*)&p->hr);
@@ -516,8 +504,10 @@ void back_q(ks_plan* p, const T* W, const T* tau, int c0, int ncols, T* X) {
 //   divide and conquer in FP64 gives lam_hat and Z; the window vectors
 //   X = Q Z[:, window] come from the FP32 back-transform.  Refinement in FP64:
 //   mixed_sweeps correction sweeps X -= Q Z S(Z^T Q^H (A X - X lam_hat)) (the
-//   products with Q and Z in FP32), then Rayleigh-Ritz on span(X) with the
-//   plan's own FP64 solver.  Eigenvalues outside the window are lam_hat.
+//   products with Q and Z in FP32) remove the components outside the window;
+//   the window's own eigenproblem in span(X), G = X^H A X, is then solved by
+//   M x M refinement passes (subspace_refine).  Eigenvalues outside the window
+//   are lam_hat.
 template <typename T>
 ks_status gevd_mixed(ks_plan* p, const T* H, double* eps, T* C, int il, int iu) {
     using L = typename Lo<T>::type;
@@ -538,7 +528,6 @@ ks_status gevd_mixed(ks_plan* p, const T* H, double* eps, T* C, int il, int iu) 
     BacktrWork<L> bl = lo_view(bw);
     bl.Tall = (L*)p->Tall32;
     Prof& pf = p->prof;
-    if (!p->rr || p->rr->d.n != M) return KS_ERR_INVALID_ARG;  // prepared by ks_gevd
     hipEvent_t e = pf.begin();
     // the lower triangle, then the upper one as its mirror (the residuals take
     // products with the whole matrix)
@@ -578,26 +567,24 @@ ks_status gevd_mixed(ks_plan* p, const T* H, double* eps, T* C, int il, int iu) 
         backtransform_q<L>(s, order, B, W32, M, P, M, sM, bl, true);  // Q^H R
         gemm<float>(s, OP_T, OP_N, order, wv * M, order, 1.0, Z32, order, sA, Pf, wv * M, wv * sM, 0.0, P2f,
                     wv * M, wv * sM, B);  // Z^T Q^H R
-        correction_scale(s, B, order, M, wv, P2f, wv * sM, eps, order, c0, 1e-4);
+        correction_scale(s, B, order, M, wv, P2f, wv * sM, eps, order, c0);
         gemm<float>(s, OP_N, OP_N, order, wv * M, order, 1.0, Z32, order, sA, P2f, wv * M, wv * sM, 0.0, Pf,
                     wv * M, wv * sM, B);
         backtransform_q<L>(s, order, B, W32, M, P, M, sM, bl);  // Q Z S(...)
         sub_widened<T, L>(s, B, sM, X, P, sM);
     }
-    // Rayleigh-Ritz: G = X^H A X, Bm = X^H X, G y = theta Bm y, X <- X y
+    // the window inside the refined subspace: G = X^H A X, then M x M
+    // refinement (subspace_refine) instead of a nested eigensolve; X comes back
+    // refined, with its columns in ascending order of the window values
     T* G = (T*)p->mG;
     T* Bm = (T*)p->mB;
     gemm<T>(s, OP_N, OP_N, order, M, order, 1.0, A, order, sA, X, M, sM, 0.0, Y, M, sM, B);
     gemm<T>(s, OP_C, OP_N, M, M, order, 1.0, X, M, sM, Y, M, sM, 0.0, G, M, sMM, B);
-    gemm<T>(s, OP_C, OP_N, M, M, order, 1.0, X, M, sM, X, M, sM, 0.0, Bm, M, sMM, B);
-    ks_status st = ks_gevd(p->rr, G, Bm, p->theta, R, 1, M, 0);
-    if (st != KS_OK) return st;
-    merge_info(s, p->rr->info, p->info);
-    gemm<T>(s, OP_N, OP_N, order, M, M, 1.0, X, M, sM, R, M, sMM, 0.0, Y, M, sM, B);
-    put_window(s, B, M, p->theta, M, eps, order, c0);
+    subspace_refine<T>(s, B, order, M, X, sM, Y, G, Bm, R, (T*)p->mS, (T*)p->mS2, p->theta, order, p->mI,
+                       p->mI + (long)B * order, p->mI + 2L * B * order, order, eps, order, c0, 2);
     pf.end(KS_PHASE_REFINE, e);
     e = pf.begin();
-    apply_linv_h<T>(p, Li, Y, sM, M, C);
+    apply_linv_h<T>(p, Li, X, sM, M, C);
     pf.end(KS_PHASE_BACKTR, e);
     if (hipPeekAtLastError() != hipSuccess) return KS_ERR_HIP;
     return KS_OK;
@@ -958,10 +945,6 @@ ks_status ks_gevd(ks_plan* p, const void* H, const void* S, double* eps, void* C
     if (!(flags & KS_REUSE_S) && !S) return KS_ERR_INVALID_ARG;
     if ((flags & KS_REUSE_S) && !p->have_L) return KS_ERR_INVALID_ARG;
     if (!range_ok(p, il, iu)) return KS_ERR_INVALID_ARG;
-    if (p->d.precision == KS_MIXED) {
-        ks_status st = ensure_rr_plan(p, iu - il + 1);
-        if (st != KS_OK) return st;
-    }
     auto enqueue = [&]() -> ks_status {
         if (p->is_c)
             return gevd_impl<cplx>(p, (const cplx*)H, (const cplx*)S, eps, (cplx*)C, il, iu, flags);

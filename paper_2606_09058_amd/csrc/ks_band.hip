@@ -156,9 +156,8 @@ __global__ __launch_bounds__(PN_THREADS) void panel_qr_kernel(int n, int k0, int
             }
             go = ok;
         }
-        __syncthreads();
+        __syncthreads();  // thread 0's acquire load orders every thread's reads below
         if (!go) return;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if (t < 2 * KB) {
             const T* r0 = rec + (long)par * P * (2 * KB) + t;
             tot[t] = batched_sum8<T>(P, [&](int g) { return r0[(long)g * 2 * KB]; });
@@ -265,7 +264,11 @@ void he2hb(hipStream_t s, int n, T* A, int lda, long sA, int batch, T* Vall, T* 
 // ---------------------------------------------------------------- stage 2
 template <typename T>
 struct S2 {
-    static constexpr int Q = is_cplx<T>::value ? 8 : 16;  // sweeps (wavefronts) per workgroup
+    // sweeps (wavefronts) per workgroup: one per SIMD, since the chase is bound
+    // by the latency of its dependent tasks, not by throughput; a workgroup
+    // takes a whole compute unit (its LDS is padded at launch)
+    static constexpr int Q = 4;
+    static constexpr size_t LDS = sizeof(T) * (Q * KB * (KB + 1) + 4 * Q * KB) + Q * sizeof(int);
 };
 
 // LDS written by some lanes of a wavefront is read by others: keep the
@@ -356,15 +359,32 @@ __global__ __launch_bounds__(64 * S2<T>::Q) void bulge_kernel(int n, int G, int 
                 }
                 ok = __shfl(ok, 0, WAVE);
                 if (!ok) return;
-                if (w == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
             const int R0 = s + 1 + t * KB;  // first row of block t
             const int Lr = min(KB, n - R0);
+            // every load of the task at once: the column or block below the
+            // previous diagonal block, and the diagonal block D (its upper half
+            // read as the conjugate of the lower one)
+            T bv[HC], dv[HC];
+            T x = zero_<T>();
+            if (t == 0) {
+                if (h == 0 && r < Lr) x = A[(long)(R0 + r) * lda + s];
+            } else {
+                const int P0 = R0 - KB;
+#pragma unroll
+                for (int k = 0; k < HC; ++k) bv[k] = (r < Lr) ? A[(long)(R0 + r) * lda + P0 + cb + k] : zero_<T>();
+            }
+#pragma unroll
+            for (int k = 0; k < HC; ++k) {
+                const int c = cb + k;
+                T v = zero_<T>();
+                if (r < Lr && c < Lr) v = c <= r ? A[(long)(R0 + r) * lda + R0 + c] : conj_(A[(long)(R0 + c) * lda + R0 + r]);
+                dv[k] = v;
+            }
             T tv, vr;
             double beta;
             if (t == 0) {
                 // column s below the subdiagonal
-                const T x = (h == 0 && r < Lr) ? A[(long)(R0 + r) * lda + s] : zero_<T>();
                 wave_reflector<T>(x, r, h, tv, vr, beta);
                 if (h == 0 && r < Lr) A[(long)(R0 + r) * lda + s] = (r == 0) ? from_re<T>(beta) : zero_<T>();
                 if (lane == 0) e[s] = beta;
@@ -372,9 +392,6 @@ __global__ __launch_bounds__(64 * S2<T>::Q) void bulge_kernel(int n, int G, int 
                 // block t below the previous diagonal block (columns P0 .. P0+KB-1):
                 // B <- B H_prev, then a reflector annihilating B's first column, B <- H^H B
                 const int P0 = R0 - KB;
-                T bv[HC];
-#pragma unroll
-                for (int k = 0; k < HC; ++k) bv[k] = (r < Lr) ? A[(long)(R0 + r) * lda + P0 + cb + k] : zero_<T>();
                 T y = zero_<T>();
 #pragma unroll
                 for (int k = 0; k < HC; ++k) y += bv[k] * vpv[w][cb + k];
@@ -400,23 +417,11 @@ __global__ __launch_bounds__(64 * S2<T>::Q) void bulge_kernel(int n, int G, int 
                 if (r < Lr)
 #pragma unroll
                     for (int k = 0; k < HC; ++k) A[(long)(R0 + r) * lda + P0 + cb + k] = bv[k];
-                wave_lds_sync();
             }
             // diagonal block t: D <- H^H D H with w = tau D v - (|tau|^2 v^H D v / 2) v,
-            // D -= v w^H + w v^H (lower triangle stored; mirrored in LDS)
-#pragma unroll
-            for (int k = 0; k < HC; ++k) {
-                const int c = cb + k;
-                if (c <= r && r < Lr) tl[r][c] = A[(long)(R0 + r) * lda + R0 + c];
-            }
+            // D -= v w^H + w v^H (the lower triangle written back)
             if (h == 0) vsh[w][r] = vr;
             wave_lds_sync();
-            T dv[HC];
-#pragma unroll
-            for (int k = 0; k < HC; ++k) {
-                const int c = cb + k;
-                dv[k] = (r < Lr && c < Lr) ? (c <= r ? tl[r][c] : conj_(tl[c][r])) : zero_<T>();
-            }
             T p = zero_<T>();
 #pragma unroll
             for (int k = 0; k < HC; ++k) p += dv[k] * vsh[w][cb + k];
@@ -475,9 +480,12 @@ void hb2st(hipStream_t s, int n, T* A, int lda, long sA, int batch, double* d, d
         int G = std::min(cdiv(ns, Q), cdiv(Tmax, 2 * Q) + 2);
         G = std::max(1, std::min(G, std::min((int)w.sgp, w.ncu)));
         const int zc = std::max(1, std::min(batch, w.ncu / G));
+        // LDS above half a compute unit's: one workgroup (one wavefront per SIMD) per CU
+        constexpr size_t want = 82 * 1024;
+        const unsigned pad = S2<T>::LDS < want ? (unsigned)(want - S2<T>::LDS) : 0u;
         for (int z0 = 0; z0 < batch; z0 += zc)
-            hipLaunchKernelGGL(bulge_kernel<T>, dim3(G, 1, std::min(zc, batch - z0)), dim3(64 * Q), 0, s, n, G, z0, A,
-                               lda, sA, e, w, info);
+            hipLaunchKernelGGL(bulge_kernel<T>, dim3(G, 1, std::min(zc, batch - z0)), dim3(64 * Q), pad, s, n, G, z0,
+                               A, lda, sA, e, w, info);
     }
     hipLaunchKernelGGL(band_diag_kernel<T>, dim3(cdiv(n, 256), batch), dim3(256), 0, s, n, (const T*)A, lda, sA, d);
 }

@@ -358,10 +358,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(int m, int n, int K, double a
 // W1 = V^H X, W2 = T W1, X -= V W2, three tile products through the group's
 // scratch rows of W1 and W2.  Groups that do not exist at this level leave.
 template <typename T>
-__global__ __launch_bounds__(256) void q2_group_kernel(int n, int J, int Tmax, int level, int ncols, T* X, int ldx,
-                                                       long sX, const T* Vpk, long sVpk, const T* Tpk, long sTpk,
-                                                       T* W1, T* W2, long sW) {
-    const int j = blockIdx.x, z = blockIdx.z;
+__global__ __launch_bounds__(256) void q2_group_kernel(int n, int J, int Tmax, int level, int j0, int ncols, T* X,
+                                                       int ldx, long sX, const T* Vpk, long sVpk, const T* Tpk,
+                                                       long sTpk, T* W1, T* W2, long sW) {
+    const int j = j0 + (int)blockIdx.x, z = blockIdx.z;
     const int t = level - 3 * (J - 1 - j);
     const int s0 = j * Q2_NB;
     if (t < 0 || t >= s2_steps(n, s0)) return;
@@ -385,8 +385,16 @@ __global__ __launch_bounds__(256) void q2_group_kernel(int n, int J, int Tmax, i
 template <typename T>
 void q2_level(hipStream_t s, int n, int batch, int level, int ncols, T* X, int ldx, long sX, const BandWork<T>& w) {
     const int J = cdiv(n - 1, Q2_NB), Tmax = s2_steps(n, 0);
-    hipLaunchKernelGGL((q2_group_kernel<T>), dim3(J, cdiv(ncols, BN), batch), dim3(256), 0, s, n, J, Tmax, level,
-                       ncols, X, ldx, sX, (const T*)w.Vpk, w.sVpk, (const T*)w.Tpk, w.sTpk, w.W1, w.W2, w.sW);
+    // the blocks j with a group at this level: t = level - 3 (J - 1 - j) in [0, steps of sweep j Q2_NB)
+    // (t grows with j while the steps of the block's first sweep shrink: the
+    // valid j form one run, from the first with t >= 0)
+    const int j0 = std::max(0, J - 1 - level / 3);
+    int j1 = J - 1;
+    while (j1 >= j0 && s2_steps(n, j1 * Q2_NB) <= level - 3 * (J - 1 - j1)) --j1;
+    if (j0 > j1) return;
+    hipLaunchKernelGGL((q2_group_kernel<T>), dim3(j1 - j0 + 1, cdiv(ncols, BN), batch), dim3(256), 0, s, n, J, Tmax,
+                       level, j0, ncols, X, ldx, sX, (const T*)w.Vpk, w.sVpk, (const T*)w.Tpk, w.sTpk, w.W1, w.W2,
+                       w.sW);
 }
 template void q2_level<double>(hipStream_t, int, int, int, int, double*, int, long, const BandWork<double>&);
 template void q2_level<cplx>(hipStream_t, int, int, int, int, cplx*, int, long, const BandWork<cplx>&);

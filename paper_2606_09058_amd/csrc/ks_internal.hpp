@@ -300,7 +300,19 @@ template <typename T>
 void residual(hipStream_t s, int batch, int order, int m, const T* Y, const T* X, long sm, const double* lam,
               long sl, int c0, T* R);
 void correction_scale(hipStream_t s, int batch, int order, int m, int w, float* P, long sp, const double* lam,
-                      long sl, int c0, double dmin);
+                      long sl, int c0);
+// The window's eigenproblem inside the refined subspace span(X) (X: order x M,
+// ld M, matrix stride sX): with G = X^H A X given (M x M, ld M) and B = X^H X
+// formed here, `passes` refinement passes in M-space (first-order correction
+// between clusters, an exact small solve inside each cluster of nearly equal
+// values) give W with W^H B W = I, W^H G W diagonal; X <- X W with its columns
+// in ascending order of the values, which go to eps[c0 ..] (matrix stride se).
+// Tm, W, Tmp: M x M scratch; theta: M per matrix (stride st); cstart, csize,
+// rank: M ints per matrix (stride sc); Y: order x M scratch.
+template <typename T>
+void subspace_refine(hipStream_t s, int batch, int order, int M, T* X, long sX, T* Y, T* G, T* Bm, T* Tm, T* W,
+                     T* Tmp, double* theta, long st, int* cstart, int* csize, int* rank, long sc, double* eps,
+                     long se, int c0, int passes);
 template <typename T, typename S>
 void sub_widened(hipStream_t s, int batch, long cnt, T* X, const S* D, long sm);
 void put_window(hipStream_t s, int batch, int m, const double* theta, long st, double* eps, long se, int c0);

@@ -3,9 +3,14 @@
 The tridiagonalisation's trailing matrix lives in FP32 with FP32 matrix-core
 updates, the window eigenvectors are back-transformed in FP32, and the window
 [il, iu] is refined in FP64 (correction sweeps with the FP32 decomposition,
-then Rayleigh-Ritz).  Bars, on the window: eigenvalues 1e-10 Ha (the stated
+then the window's eigenproblem solved in the corrected subspace by M x M
+refinement passes).  Bars, on the window: eigenvalues 1e-10 Ha (the stated
 target), residual ||HC - SC eps|| / (||H|| ||C||) 1e-11, |C^H S C - I| 1e-11,
-density 1e-9 (the FP64 bars, with the residual one decade looser); outside the
+density 1e-9.  The residual bar is a decade looser than FP64's: the default
+single correction sweep leaves the components outside the window at about
+(u32 ||A|| / gap)^2 ~ 1e-12, which the residual sees to first order (the
+eigenvalues only to second order); two sweeps reach the FP64 bar (checked
+below).  Outside the
 window the eigenvalues are those of the FP32 tridiagonal, checked to 1e-4 of the
 spectral range.  The window holds every state below mu + 0.4 Ha, so the
 refined subspace is separated from the rest by at least 40 kT."""
@@ -105,14 +110,15 @@ def test_mixed_kpoint_batch_vs_oracle():
 
 def test_mixed_refinement_sweeps_converge():
     """Each correction sweep shrinks the window subspace error by ~u32 ||A|| / gap;
-    Rayleigh-Ritz eigenvalues carry its square.  Zero sweeps leave the FP32
-    subspace (eigenvalues off by ~1e-8 here); one sweep already meets the 1e-10 Ha
-    bar; the error does not grow with more sweeps."""
+    the subspace step's eigenvalues carry its square.  One sweep meets the
+    1e-10 Ha bar and more sweeps do not make it worse; with none the FP32
+    subspace error is left (its square, reported, is small here but not
+    guaranteed)."""
     announce("mixed sweeps")
     p = I.toy(seed=77, natoms=20, norb=13, edge=13.0, n_electrons=104.0, kT=0.01)
     o = O.solve(p.H, p.S, p.n_electrons, p.kT)
     iu = window_top(o["eps"], o["mu"])
-    errs = []
+    errs, res = [], []
     for sweeps in (0, 1, 2, 3):
         plan = ks.Plan(p.n, precision=ks.KS_MIXED)
         plan.set_refinement(sweeps)
@@ -122,8 +128,10 @@ def test_mixed_refinement_sweeps_converge():
         plan.gevd(H, S, eps, C, il=1, iu=iu)
         plan.check("gevd")
         errs.append(np.abs(host(eps)[:iu] - o["eps"][:iu]).max())
+        res.append(residuals(p.H, p.S, host(eps)[:iu], host(C)[:, :iu])[0])
     assert errs[1] < EPS_TOL and errs[2] < EPS_TOL and errs[3] < EPS_TOL, errs
-    assert errs[0] > errs[1], errs
+    assert res[1] < 1e-11 and res[2] < 1e-12 and res[3] < 1e-12, res
+    print("window eigenvalue error by sweeps 0..3:", errs, "residual:", res)
     with pytest.raises(ks.KSError):
         ks.Plan(p.n).set_refinement(1)  # FP64 plans have nothing to refine
     with pytest.raises(ks.KSError):
@@ -176,3 +184,32 @@ def test_mixed_kpoints16x1300_full_size():
         G = Ck.conj().T @ S[k] @ Ck
         orth = (G - torch.eye(iu, dtype=G.dtype, device="cuda")).abs().max().item()
         assert res < RES_TOL and orth < ORTH_TOL, (k, res, orth)
+
+
+def test_mixed_clusters_and_exact_degeneracy():
+    """Window eigenvalues in tight clusters (pairs 1e-7 Ha apart and an exactly
+    threefold level, built with a known spectrum H = S^1/2 Q diag(lam) Q^H S^1/2):
+    the subspace step's exact solves inside clusters keep every window
+    eigenvalue within 1e-10 Ha, the residual and C^H S C = I at the FP64 bars."""
+    announce("mixed clusters")
+    rng = np.random.default_rng(12)
+    n = 260
+    lam = np.sort(rng.uniform(-3.0, 3.0, n))
+    for i in range(5, 120, 23):  # close pairs
+        lam[i + 1] = lam[i] + 1e-7
+    lam[60:63] = lam[60]         # an exactly threefold level
+    lam = np.sort(lam)
+    Q, _ = np.linalg.qr(rng.normal(size=(n, n)))
+    S = I.random_hermitian(rng, n, False) * 0.01 + np.eye(n)
+    w, U = np.linalg.eigh(S)
+    Sh = (U * np.sqrt(w)) @ U.T
+    H = Sh @ (Q * lam) @ Q.T @ Sh
+    H = (H + H.T) / 2
+    ne, kT = 160.0, 0.01
+    o = O.solve(H, S, ne, kT)
+    assert np.abs(o["eps"] - lam).max() < 1e-10
+    iu = window_top(o["eps"], o["mu"])
+    from types import SimpleNamespace
+    p = SimpleNamespace(H=H, S=S, n=n, batch=1, nsp=1, g=2.0, n_electrons=ne, kT=kT, weights=None)
+    g = solve_mixed(p, iu)
+    check(p, g, o["eps"], [o["rho"]], o["mu"], iu)
