@@ -284,6 +284,7 @@ def main():
     import numpy as np
     import torch
     from paper_2606_09058_amd import inputs as I
+    from paper_2606_09058_amd import ks
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
@@ -345,7 +346,14 @@ def main():
         "phases_ms": r["phases"],
         "tuning": {"tiles_per_workgroup": tu["tiles_per_workgroup"],
                    "candidates_ms": {str(k): v for k, v in tu["candidates"].items()},
-                   "segments": tu["segments"]},
+                   "segments": tu["segments"],
+                   "backtr_block": tu["backtr_block"],
+                   "gemm_big_min_k": ("never" if tu["gemm_big_min_k"] == ks.KS_TUNE_NEVER
+                                      else tu["gemm_big_min_k"]),
+                   "backtr_ms": {"bt%d_%s" % (b, "never" if g == ks.KS_TUNE_NEVER else "k%d" % g): v
+                                 for (b, g), v in tu["backtr_ms"].items()},
+                   "dc_leaf": tu["dc_leaf"],
+                   "dc_ms": {str(k): v for k, v in tu["dc_ms"].items()}},
         "checks": {"trace_rho_S_minus_Ne": tr - p.n_electrons, "mu": float(mu.item()),
                    "eband": float(eband.item()), "trace_edm_S_minus_eband": edm_tr - float(eband.item())},
         "energy_density": {"ms": ms_edm, "columns": m_occ, "tflops": edm_flops / (ms_edm * 1e-3) / 1e12},

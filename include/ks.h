@@ -268,15 +268,33 @@ ks_status ks_plan_set_profiling(ks_plan* plan, int32_t enable, int32_t stride);
  * read, and clear it. */
 ks_status ks_plan_get_profile(ks_plan* plan, ks_profile* out);
 
-/* The tile shape in use and, under KS_PLAN_AUTOTUNE, what was measured:
- * ms[i] is the time of the timing launches with cand[i] tiles per workgroup
- * summed over the sampled columns, and tiles_per_workgroup the candidate with
- * the least total.  The tridiagonalisation uses, for columns k from
- * seg_first[i] up to seg_first[i+1] - 1 (the last segment up to the end), the
- * candidate seg_tiles[i] that was fastest at the column sampled in that
- * segment; without autotuning nseg = 1 and every column uses
- * tiles_per_workgroup. */
+/* The tuning knobs of a plan and, under KS_PLAN_AUTOTUNE, what was measured
+ * at plan creation on the plan's own buffers and shapes.
+ *
+ * Symmetric product of the one-stage tridiagonalisation: ms[i] is the time of
+ * the timing launches with cand[i] tiles per workgroup summed over the sampled
+ * columns, and tiles_per_workgroup the candidate with the least total.  The
+ * tridiagonalisation uses, for columns k from seg_first[i] up to
+ * seg_first[i+1] - 1 (the last segment up to the end), the candidate
+ * seg_tiles[i] that was fastest at the column sampled in that segment.
+ *
+ * Back-transform and GEMM tiles: backtr_block is the number of reflectors per
+ * compact-WY block of the back-transform (128 or 256) and gemm_big_min_k the
+ * smallest inner dimension for which a large product takes the 128 x 128
+ * tiles (KS_TUNE_NEVER: never, 64 x 64 tiles only).  backtr_ms[b][g] is the
+ * time of one back-transform of all eigenvectors with backtr_block = 128 << b
+ * and gemm_big_min_k = 256 (g = 0) or KS_TUNE_NEVER (g = 1).
+ *
+ * Divide and conquer: dc_leaf is the largest leaf of the tear tree (16 or 32),
+ * dc_ms[l] the time of one solve of a synthetic tridiagonal of the plan's
+ * order with dc_leaf = 16 << l.
+ *
+ * Without autotuning nseg = 1, every column uses tiles_per_workgroup, the
+ * other knobs take their defaults (backtr_block 256 from order 4096 up, 128
+ * below; gemm_big_min_k 256; dc_leaf 32) and the times are 0.  from_cache is
+ * 1 when the knobs were set by ks_plan_set_tuning, 0 otherwise. */
 #define KS_TUNE_SEGMENTS 8
+#define KS_TUNE_NEVER 0x7fffffff
 typedef struct {
     int32_t tiles_per_workgroup;
     int32_t ncand;
@@ -285,8 +303,26 @@ typedef struct {
     int32_t nseg;
     int32_t seg_first[KS_TUNE_SEGMENTS];
     int32_t seg_tiles[KS_TUNE_SEGMENTS];
+    int32_t backtr_block;
+    int32_t gemm_big_min_k;
+    double  backtr_ms[2][2];
+    int32_t dc_leaf;
+    double  dc_ms[2];
+    int32_t from_cache;
 } ks_tuning;
 ks_status ks_plan_get_tuning(ks_plan* plan, ks_tuning* out);
+
+/* Set a plan's knobs from a ks_tuning filled by ks_plan_get_tuning on a plan
+ * of the same descriptor (for instance one kept in a tuning cache), without
+ * timing anything.  Only the knobs are read: tiles_per_workgroup, nseg,
+ * seg_first, seg_tiles, backtr_block, gemm_big_min_k and dc_leaf; the measured
+ * times are copied for reporting.  KS_ERR_INVALID_ARG (plan unchanged) if a
+ * knob is outside its candidates (tiles 2, 4 or 8; 1 <= nseg <=
+ * KS_TUNE_SEGMENTS with seg_first[0] = 0 and increasing; backtr_block 128 or
+ * 256; gemm_big_min_k >= 16 or KS_TUNE_NEVER; dc_leaf 16 or 32).  Host-side
+ * except for re-uploading the divide-and-conquer tree (synchronous); a
+ * captured graph of the plan is dropped and captured again on the next call. */
+ks_status ks_plan_set_tuning(ks_plan* plan, const ks_tuning* t);
 
 /* KS_MIXED plans: the number of correction sweeps (0 .. 4, default 1) applied
  * to the window's FP32 eigenvectors before the FP64 subspace step.  Each sweep

@@ -152,15 +152,49 @@ ks_plan_desc lowdin_overlap_desc(const ks_plan_desc* d) {
     return c;
 }
 
+// Compact-WY blocks of bt reflectors (128 or 256; the buffers hold 256).
+template <typename T>
+void set_backtr_block(BacktrWork<T>& w, int order, int bt) {
+    const long nblk = order > 1 ? (order - 1 + bt - 1) / bt : 1;
+    w.bt = bt;
+    w.sTall = nblk * bt * bt;
+}
+
+// Tear tree with leaves of at most `leaf` rows (DC_LEAF_MIN .. DC_LEAF; the
+// arrays hold the tree of the smallest), uploaded synchronously: at plan
+// creation and from ks_plan_set_tuning only.
+ks_status set_dc_leaf(ks_plan* p, int leaf) {
+    std::vector<int> mlo, mmid, mhi, llo, lhi, mk;
+    int depth = 0;
+    dc_tree_host(p->order, leaf, mlo, mmid, mhi, llo, lhi, depth, mk);
+    DcTree& t = p->tree;
+    t.depth = depth;
+    t.nleaf = (int)llo.size();
+    t.nmerge_total = (int)mlo.size();
+    t.max_k0 = mk;
+    const size_t nm = mlo.size(), nl = llo.size();
+    if (nm && (hipMemcpy(t.d_mlo, mlo.data(), nm * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+               hipMemcpy(t.d_mmid, mmid.data(), nm * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+               hipMemcpy(t.d_mhi, mhi.data(), nm * sizeof(int), hipMemcpyHostToDevice) != hipSuccess))
+        return KS_ERR_HIP;
+    if (hipMemcpy(t.d_leaf_lo, llo.data(), nl * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(t.d_leaf_hi, lhi.data(), nl * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+        return KS_ERR_HIP;
+    p->tuning.dc_leaf = leaf;
+    return KS_OK;
+}
+
 // Lays out (or, with plan == nullptr, only measures) the workspace.
 size_t layout(const ks_plan_desc* d, ks_plan* p) {
     int nsp = d->spin == KS_NONCOLLINEAR ? 2 : 1;
     size_t n = d->n, order = n * nsp, B = d->batch;
     size_t es = d->dtype == KS_COMPLEX128 ? 16 : 8;
-    size_t nb = HETRD_NB, bt = backtr_block((int)order);
+    // back-transform buffers for the largest block the autotuner may choose,
+    // and divide-and-conquer tree arrays for the smallest leaf
+    size_t nb = HETRD_NB, bt = BACKTR_BT;
     std::vector<int> mlo, mmid, mhi, llo, lhi, mk;
     int depth = 0;
-    dc_tree_host((int)order, mlo, mmid, mhi, llo, lhi, depth, mk);
+    dc_tree_host((int)order, DC_LEAF_MIN, mlo, mmid, mhi, llo, lhi, depth, mk);
     size_t nm = mlo.size(), nl = llo.size();
     size_t maxm = depth > 0 ? ((size_t)1 << (depth - 1)) : 1;
     Layout L;
@@ -232,12 +266,13 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
     // two-stage reduction (only when asked for)
     const bool two = (d->flags & KS_PLAN_TWOSTAGE) != 0;
     const size_t tm = order > 1 ? (size_t)s2_steps((int)order, 0) : 1;       // steps of the longest sweep
-    const size_t jg = order > 1 ? (order - 1 + Q2_NB - 1) / Q2_NB : 1;       // groups of sweeps
+    const size_t q2nb = (size_t)q2_nb(es == 16);                           // sweeps per group
+    const size_t jg = order > 1 ? (order - 1 + q2nb - 1) / q2nb : 1;           // groups of sweeps
     const size_t pmax = (order + (es == 16 ? 256 : 512) - 1) / (es == 16 ? 256 : 512);
     const size_t npan = (order + KB - 1) / KB;
     constexpr size_t GMAX = 64;  // bulge-chasing workgroups per matrix
     size_t oBX = 0, oB3 = 0, oBT = 0, oBM = 0, oBN = 0, oRec = 0, oCnt = 0, oGp = 0, oAb = 0, oVpk = 0, oTaupk = 0;
-    size_t oTpk = 0, oBW1 = 0, oBW2 = 0;
+    size_t oQ2p = 0;
     if (two) {
         oBX = L.take(B * order * KB * es);
         oB3 = L.take(B * order * 3 * KB * es);
@@ -248,11 +283,10 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
         oCnt = L.take(B * npan * sizeof(int));
         oGp = L.take(B * GMAX * sizeof(int));
         oAb = L.take(sizeof(int));
-        oVpk = L.take(B * jg * tm * Q2_GL * Q2_NB * es);
-        oTaupk = L.take(B * jg * tm * Q2_NB * es);
-        oTpk = L.take(B * jg * tm * Q2_NB * Q2_NB * es);
-        oBW1 = L.take(B * jg * Q2_NB * order * es);
-        oBW2 = L.take(B * jg * Q2_NB * order * es);
+        oVpk = L.take(B * jg * tm * q2nb * KB * es);
+        oTaupk = L.take(B * jg * tm * q2nb * es);
+        const size_t q2w = (size_t)q2_passes(es == 16);
+        oQ2p = L.take(B * ((jg + q2w - 1) / q2w) * ((order + 63) / 64) * sizeof(int));
     }
     const bool lw = (d->flags & KS_PLAN_LOWDIN) != 0;
     const size_t oSev = lw ? L.take(B * n * 8) : 0;
@@ -325,8 +359,7 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
         using T = std::remove_pointer_t<decltype(tag)>;
         w.G = (T*)(b + oG);
         w.Tall = (T*)(b + oT);
-        w.sTall = (long)(nblk_bt * bt * bt);
-        w.bt = backtr_block((int)order);
+        set_backtr_block(w, (int)order, backtr_block((int)order));
         w.W1 = (T*)(b + oW1);
         w.W2 = (T*)(b + oW2);
         w.P = (T*)(b + oSK);
@@ -353,14 +386,10 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
         w.sgp = (long)GMAX;
         w.abort_ = (int*)(b + oAb);
         w.Vpk = (T*)(b + oVpk);
-        w.sVpk = (long)(jg * tm * Q2_GL * Q2_NB);
+        w.sVpk = (long)(jg * tm * q2nb * KB);
         w.taupk = (T*)(b + oTaupk);
-        w.staupk = (long)(jg * tm * Q2_NB);
-        w.Tpk = (T*)(b + oTpk);
-        w.sTpk = (long)(jg * tm * Q2_NB * Q2_NB);
-        w.W1 = (T*)(b + oBW1);
-        w.W2 = (T*)(b + oBW2);
-        w.sW = (long)(jg * Q2_NB * order);
+        w.staupk = (long)(jg * tm * q2nb);
+        w.q2prog = (int*)(b + oQ2p);
         w.P = (T*)(b + oSK);
         w.pelems = (long)pel;
     };
@@ -389,24 +418,13 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
     w.rho = (double*)(b + oRho);
     DcTree& t = p->tree;
     t.n = (int)order;
-    t.depth = depth;
-    t.nleaf = (int)nl;
-    t.nmerge_total = (int)nm;
-    t.max_k0 = mk;
     t.d_mlo = (int*)(b + oT1);
     t.d_mmid = (int*)(b + oT2);
     t.d_mhi = (int*)(b + oT3);
     t.d_mid_all = t.d_mmid;
     t.d_leaf_lo = (int*)(b + oL1);
     t.d_leaf_hi = (int*)(b + oL2);
-    // upload the tree (small, synchronous, at plan creation only)
-    if (nm) {
-        (void)hipMemcpy(t.d_mlo, mlo.data(), nm * sizeof(int), hipMemcpyHostToDevice);
-        (void)hipMemcpy(t.d_mmid, mmid.data(), nm * sizeof(int), hipMemcpyHostToDevice);
-        (void)hipMemcpy(t.d_mhi, mhi.data(), nm * sizeof(int), hipMemcpyHostToDevice);
-    }
-    (void)hipMemcpy(t.d_leaf_lo, llo.data(), nl * sizeof(int), hipMemcpyHostToDevice);
-    (void)hipMemcpy(t.d_leaf_hi, lhi.data(), nl * sizeof(int), hipMemcpyHostToDevice);
+    set_dc_leaf(p, DC_LEAF);
     return total;
 }
 
@@ -493,7 +511,7 @@ void back_q(ks_plan* p, const T* W, const T* tau, int c0, int ncols, T* X) {
     const int order = p->order, B = p->d.batch;
     const long sA = (long)order * order;
     load_z<T>(p->s, order, B, ncols, p->Z, c0, X, ncols, sA);
-    if (p->d.flags & KS_PLAN_TWOSTAGE) q2_apply<T>(p->s, order, B, ncols, X, ncols, sA, band_work<T>(p));
+    if (p->d.flags & KS_PLAN_TWOSTAGE) q2_apply<T>(p->s, order, B, ncols, X, ncols, sA, band_work<T>(p), p->info);
     backtransform_prepare<T>(p->s, order, B, W, tau, backtr_work<T>(p));
     backtransform_q<T>(p->s, order, B, W, ncols, X, ncols, sA, backtr_work<T>(p));
 }
@@ -772,6 +790,125 @@ ks_status gevd_impl(ks_plan* p, const T* H, const T* S, double* eps, T* C, int i
 
 }  // namespace
 
+namespace {
+
+// The plan's knobs into its work descriptors.
+void apply_tuning(ks_plan* p) {
+    const ks_tuning& tu = p->tuning;
+    p->hr.sch = p->hc.sch = tu.tiles_per_workgroup;
+    p->hr.nseg = p->hc.nseg = tu.nseg;
+    for (int i = 0; i < tu.nseg; ++i) {
+        p->hr.seg_first[i] = p->hc.seg_first[i] = tu.seg_first[i];
+        p->hr.seg_sch[i] = p->hc.seg_sch[i] = tu.seg_tiles[i];
+    }
+    set_backtr_block(p->br, p->order, tu.backtr_block);
+    set_backtr_block(p->bc, p->order, tu.backtr_block);
+}
+
+// Milliseconds of `rounds` runs of f after one untimed run, the least.
+template <typename F>
+float time_min(hipStream_t s, int rounds, F f) {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -1.f;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return -1.f;
+    }
+    f();
+    float best = 3.0e38f;
+    for (int r = 0; r < rounds; ++r) {
+        (void)hipEventRecord(e0, s);
+        f();
+        (void)hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) {
+            best = -1.f;
+            break;
+        }
+        float t = 0.f;
+        (void)hipEventElapsedTime(&t, e0, e1);
+        best = std::min(best, t);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return best;
+}
+
+// Back-transform block and large-GEMM threshold: one back-transform of all
+// eigenvectors (the plan's own shapes and buffers, zero reflectors: the
+// products' time does not depend on the values) per candidate pair.
+template <typename T>
+ks_status tune_backtr(ks_plan* p) {
+    ks_tuning& tu = p->tuning;
+    const int order = p->order, B = p->d.batch;
+    const long sA = (long)order * order;
+    BacktrWork<T>& w = backtr_work<T>(p);
+    T* V = (T*)p->W;
+    T* tau = (T*)p->tau;
+    T* X = (T*)p->A;
+    fill_zero<T>(p->s, V, sA * B);
+    fill_zero<T>(p->s, tau, (long)order * B);
+    fill_zero<T>(p->s, X, sA * B);
+    float best = 3.0e38f;
+    for (int bi = 0; bi < 2; ++bi)
+        for (int gi = 0; gi < 2; ++gi) {
+            const int bt = 128 << bi, gk = gi ? KS_TUNE_NEVER : 256;
+            set_backtr_block(w, order, bt);
+            GemmPolicy gp(gk);
+            const float t = time_min(p->s, 2, [&]() {
+                backtransform_prepare<T>(p->s, order, B, V, tau, w);
+                backtransform_q<T>(p->s, order, B, V, order, X, order, sA, w);
+            });
+            if (t < 0.f) return KS_ERR_HIP;
+            tu.backtr_ms[bi][gi] = t;
+            if (t < best) {
+                best = t;
+                tu.backtr_block = bt;
+                tu.gemm_big_min_k = gk;
+            }
+        }
+    return KS_OK;
+}
+
+__global__ void synth_tridiag_kernel(int n, long total, double* d, double* e) {
+    const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int k = (int)(i % n);
+    d[i] = 2.0 * cos(0.731 * k) + (double)k / n;
+    e[i] = 0.5 + 0.25 * sin(1.37 * k);
+}
+
+// Divide-and-conquer leaf: one solve of a fixed tridiagonal of the plan's
+// order (smooth, non-degenerate entries) per candidate.
+ks_status tune_dc(ks_plan* p) {
+    const int order = p->order, B = p->d.batch;
+    const long tot = (long)order * B;
+    hipLaunchKernelGGL(synth_tridiag_kernel, dim3((unsigned)cdiv(tot, 256)), dim3(256), 0, p->s, order, tot, p->dv,
+                       p->ev);
+    float best = 3.0e38f;
+    int leaf_best = DC_LEAF;
+    for (int li = 0; li < 2; ++li) {
+        const int leaf = DC_LEAF_MIN << li;
+        if (hipStreamSynchronize(p->s) != hipSuccess) return KS_ERR_HIP;
+        ks_status st = set_dc_leaf(p, leaf);
+        if (st != KS_OK) return st;
+        const float t = time_min(p->s, 2, [&]() {
+            stedc(p->s, p->tree, B, p->dv, p->ev, p->occ, p->Z, p->Z2, p->U, p->Qp, p->dc, p->info);
+        });
+        if (t < 0.f) return KS_ERR_HIP;
+        p->tuning.dc_ms[li] = t;
+        if (t < best) {
+            best = t;
+            leaf_best = leaf;
+        }
+    }
+    ks_status st = set_dc_leaf(p, leaf_best);
+    if (st != KS_OK) return st;
+    if (hipMemset(p->info, 0, 2 * sizeof(int)) != hipSuccess) return KS_ERR_HIP;
+    return KS_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* ks_status_string(ks_status st) {
@@ -859,6 +996,8 @@ ks_status ks_plan_create(const ks_plan_desc* d, ks_plan** out) {
     p->tuning.nseg = 1;
     p->tuning.seg_first[0] = 0;
     p->tuning.seg_tiles[0] = HETRD_SCH;
+    p->tuning.backtr_block = backtr_block(p->order);
+    p->tuning.gemm_big_min_k = 256;
     if (d->flags & KS_PLAN_AUTOTUNE) {
         ks_tuning& tu = p->tuning;
         const long sA = (long)p->order * p->order;
@@ -877,13 +1016,14 @@ ks_status ks_plan_create(const ks_plan_desc* d, ks_plan** out) {
             ks_plan_destroy(p);
             return KS_ERR_HIP;
         }
+        ks_status st = p->is_c ? tune_backtr<cplx>(p) : tune_backtr<double>(p);
+        if (st == KS_OK) st = tune_dc(p);
+        if (st != KS_OK) {
+            ks_plan_destroy(p);
+            return st;
+        }
     }
-    p->hr.sch = p->hc.sch = p->tuning.tiles_per_workgroup;
-    p->hr.nseg = p->hc.nseg = p->tuning.nseg;
-    for (int i = 0; i < p->tuning.nseg; ++i) {
-        p->hr.seg_first[i] = p->hc.seg_first[i] = p->tuning.seg_first[i];
-        p->hr.seg_sch[i] = p->hc.seg_sch[i] = p->tuning.seg_tiles[i];
-    }
+    apply_tuning(p);
     *out = p;
     return KS_OK;
 }
@@ -931,6 +1071,29 @@ ks_status ks_plan_get_tuning(ks_plan* p, ks_tuning* out) {
     return KS_OK;
 }
 
+ks_status ks_plan_set_tuning(ks_plan* p, const ks_tuning* t) {
+    if (!p || !t) return KS_ERR_INVALID_ARG;
+    auto tiles_ok = [](int v) { return v == 2 || v == 4 || v == 8; };
+    if (!tiles_ok(t->tiles_per_workgroup)) return KS_ERR_INVALID_ARG;
+    if (t->nseg < 1 || t->nseg > KS_TUNE_SEGMENTS || t->seg_first[0] != 0) return KS_ERR_INVALID_ARG;
+    for (int i = 0; i < t->nseg; ++i) {
+        if (!tiles_ok(t->seg_tiles[i])) return KS_ERR_INVALID_ARG;
+        if (i > 0 && t->seg_first[i] <= t->seg_first[i - 1]) return KS_ERR_INVALID_ARG;
+    }
+    if (t->backtr_block != 128 && t->backtr_block != 256) return KS_ERR_INVALID_ARG;
+    if (t->gemm_big_min_k < 16) return KS_ERR_INVALID_ARG;
+    if (t->dc_leaf != DC_LEAF_MIN && t->dc_leaf != DC_LEAF) return KS_ERR_INVALID_ARG;
+    // work in flight may use the tree and the block layout
+    if (hipStreamSynchronize(p->s) != hipSuccess) return KS_ERR_HIP;
+    ks_status st = set_dc_leaf(p, t->dc_leaf);
+    if (st != KS_OK) return st;
+    p->tuning = *t;
+    p->tuning.from_cache = 1;
+    apply_tuning(p);
+    graph_release(p);
+    return KS_OK;
+}
+
 ks_status ks_plan_get_graph_stats(ks_plan* p, int64_t* captures, int64_t* replays) {
     if (!p || !captures || !replays) return KS_ERR_INVALID_ARG;
     *captures = p->graph_captures;
@@ -941,6 +1104,7 @@ ks_status ks_plan_get_graph_stats(ks_plan* p, int64_t* captures, int64_t* replay
 ks_status ks_gevd(ks_plan* p, const void* H, const void* S, double* eps, void* C, int32_t il,
                   int32_t iu, uint32_t flags) {
     if (!p || !H || !eps || !C) return KS_ERR_INVALID_ARG;
+    GemmPolicy gpol(p->tuning.gemm_big_min_k);  // the plan's large-tile threshold for its launches
     if (flags & ~(uint32_t)KS_REUSE_S) return KS_ERR_INVALID_ARG;
     if (!(flags & KS_REUSE_S) && !S) return KS_ERR_INVALID_ARG;
     if ((flags & KS_REUSE_S) && !p->have_L) return KS_ERR_INVALID_ARG;
@@ -988,6 +1152,7 @@ ks_status ks_density(ks_plan* p, const double* eps, const void* C, int32_t il, i
                      double ne, double kT, const double* kweights, void* rho, double* mu,
                      double* eband, double* occ) {
     if (!p || !eps || !C || !rho || !mu || !eband) return KS_ERR_INVALID_ARG;
+    GemmPolicy gpol(p->tuning.gemm_big_min_k);  // the plan's large-tile threshold for its launches
     if (!range_ok(p, il, iu)) return KS_ERR_INVALID_ARG;
     if (!(kT > 0.0) || !isfinite(kT)) return KS_ERR_INVALID_ARG;
     double g = p->nsp == 2 ? 1.0 : 2.0;
@@ -1124,6 +1289,7 @@ __global__ void edm_weights_kernel(int order, int c0, int ncols, const double* o
 ks_status ks_energy_density(ks_plan* p, const double* eps, const void* C, int32_t il, int32_t iu,
                             const double* occ, void* edm) {
     if (!p || !eps || !C || !occ || !edm) return KS_ERR_INVALID_ARG;
+    GemmPolicy gpol(p->tuning.gemm_big_min_k);  // the plan's large-tile threshold for its launches
     if (!range_ok(p, il, iu)) return KS_ERR_INVALID_ARG;
     hipStream_t s = p->s;
     const int order = p->order, ldh = p->d.ld_h, ncols = iu - il + 1, c0 = il - 1;
@@ -1148,6 +1314,7 @@ ks_status ks_density_backward(ks_plan* p, const double* eps, const void* C, cons
                               const double* occ, double kT, const void* grad_rho,
                               const double* grad_eband, void* grad_H, void* grad_S) {
     if (!p || !eps || !C || !mu || !occ || !grad_H || !grad_S) return KS_ERR_INVALID_ARG;
+    GemmPolicy gpol(p->tuning.gemm_big_min_k);  // the plan's large-tile threshold for its launches
     if (!(kT > 0.0) || !isfinite(kT)) return KS_ERR_INVALID_ARG;
     // the gradient formulas use the completeness of the eigenvectors in the
     // S metric, which a basis reduced by the overlap cutoff does not have
@@ -1260,7 +1427,7 @@ void ks_internal_hetrd(ks_plan* p, void* A, double* d, double* e, const double* 
             he2hb<cplx>(p->s, n, (cplx*)A, n, sA, 1, (cplx*)p->W, (cplx*)p->tau, w, p->info);
             hb2st<cplx>(p->s, n, (cplx*)A, n, sA, 1, d, e, w, p->info);
             load_z<cplx>(p->s, n, 1, ncols, X, 0, (cplx*)Y, ncols, 0);
-            q2_apply<cplx>(p->s, n, 1, ncols, (cplx*)Y, ncols, 0, w);
+            q2_apply<cplx>(p->s, n, 1, ncols, (cplx*)Y, ncols, 0, w, p->info);
             backtransform_prepare<cplx>(p->s, n, 1, (cplx*)p->W, (cplx*)p->tau, p->bc);
             backtransform_q<cplx>(p->s, n, 1, (cplx*)p->W, ncols, (cplx*)Y, ncols, 0, p->bc);
         } else {
@@ -1268,7 +1435,7 @@ void ks_internal_hetrd(ks_plan* p, void* A, double* d, double* e, const double* 
             he2hb<double>(p->s, n, (double*)A, n, sA, 1, (double*)p->W, (double*)p->tau, w, p->info);
             hb2st<double>(p->s, n, (double*)A, n, sA, 1, d, e, w, p->info);
             load_z<double>(p->s, n, 1, ncols, X, 0, (double*)Y, ncols, 0);
-            q2_apply<double>(p->s, n, 1, ncols, (double*)Y, ncols, 0, w);
+            q2_apply<double>(p->s, n, 1, ncols, (double*)Y, ncols, 0, w, p->info);
             backtransform_prepare<double>(p->s, n, 1, (double*)p->W, (double*)p->tau, p->br);
             backtransform_q<double>(p->s, n, 1, (double*)p->W, ncols, (double*)Y, ncols, 0, p->br);
         }

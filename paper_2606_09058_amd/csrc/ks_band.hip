@@ -36,6 +36,8 @@
 // one sweep in Q crosses compute units.
 #include "ks_internal.hpp"
 
+#include <utility>
+
 namespace ks {
 
 template <typename T>
@@ -127,42 +129,53 @@ __global__ __launch_bounds__(PN_THREADS) void panel_qr_kernel(int n, int k0, int
         __syncthreads();
         const int par = j & 1;
         T* myrec = rec + ((long)par * P + wg) * (2 * KB);
-        if (t < KB) {
-            T sum = zero_<T>();
-#pragma unroll
-            for (int g = 0; g < PN_RG; g += 4) sum += (red[g][t] + red[g + 1][t]) + (red[g + 2][t] + red[g + 3][t]);
-            myrec[t] = sum;
-        } else if (t < 2 * KB) {
-            const int lj = j - i0;
-            myrec[t] = (lj >= 0 && lj < nl) ? pt[lj][t - KB] : zero_<T>();
-        }
-        __syncthreads();
-        if (t == 0) {
-            __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            const int want = P * (j + 1);
-            long polls = 0;
-            int ok = 1;
-            while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < want) {
-                if ((++polls & 255) == 0 &&
-                    (polls > WAIT_POLLS_GLOBAL || __hip_atomic_load(bw.abort_, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
-                    ok = 0;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-            }
-            if (!ok) {
-                atomicExch(bw.abort_, 1);
-                set_info(info, KS_ERR_NO_CONVERGENCE, -1);
-            }
-            go = ok;
-        }
-        __syncthreads();  // thread 0's acquire load orders every thread's reads below
-        if (!go) return;
         if (t < 2 * KB) {
-            const T* r0 = rec + (long)par * P * (2 * KB) + t;
-            tot[t] = batched_sum8<T>(P, [&](int g) { return r0[(long)g * 2 * KB]; });
+            T v;
+            if (t < KB) {
+                v = zero_<T>();
+#pragma unroll
+                for (int g = 0; g < PN_RG; g += 4) v += (red[g][t] + red[g + 1][t]) + (red[g + 2][t] + red[g + 3][t]);
+            } else {
+                const int lj = j - i0;
+                v = (lj >= 0 && lj < nl) ? pt[lj][t - KB] : zero_<T>();
+            }
+            // a single workgroup's record is the total itself (the exchange
+            // would give 0 + v, which is exact)
+            if (P > 1) myrec[t] = v;
+            else tot[t] = v;
         }
         __syncthreads();
+        if (P > 1) {
+            if (t == 0) {
+                __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                const int want = P * (j + 1);
+                long polls = 0;
+                int ok = 1;
+                // plain polls; one acquire once the count is reached
+                while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want) {
+                    if ((++polls & 255) == 0 &&
+                        (polls > WAIT_POLLS_GLOBAL ||
+                         __hip_atomic_load(bw.abort_, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                        ok = 0;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                if (!ok) {
+                    atomicExch(bw.abort_, 1);
+                    set_info(info, KS_ERR_NO_CONVERGENCE, -1);
+                }
+                go = ok;
+            }
+            __syncthreads();  // thread 0's acquire orders every thread's reads below
+            if (!go) return;
+            if (t < 2 * KB) {
+                const T* r0 = rec + (long)par * P * (2 * KB) + t;
+                tot[t] = batched_sum8<T>(P, [&](int g) { return r0[(long)g * 2 * KB]; });
+            }
+            __syncthreads();
+        }
         // the reflector (the same in every workgroup)
         const T alpha = tot[KB + j];
         T tv, sc;
@@ -178,28 +191,32 @@ __global__ __launch_bounds__(PN_THREADS) void panel_qr_kernel(int n, int k0, int
                 else if (i > j) pt[li][c] -= sc * pt[li][j] * gc;
             }
         }
-        // column j of the triangular factor: T[l][j] = -tau sum_q T[l][q] vd_q
-        // (q = l .. j-1), vd_q = v_q^H v_j = conj(P[j][q]) + s conj(s_q)
-        if (wg == 0 && t < KB) {
-            if (t < j) {
-                T acc = zero_<T>();
-                for (int q = t; q < j; ++q) acc += Tl[t][q] * (conj_(tot[KB + q]) + sc * conj_(tot[q]));
-                Tl[t][j] = -(tv * acc);
-            } else if (t == j) {
-                Tl[j][j] = tv;
-                taus[j] = tv;
-            }
+        // inner products with the earlier reflectors for the triangular factor,
+        // vd_q = v_q^H v_j = conj(P[j][q]) + s conj(s_q), kept in the strictly
+        // lower part of Tl (Tl[j][q]); the factor itself is formed after the loop
+        if (wg == 0) {
+            if (t < j) Tl[j][t] = conj_(tot[KB + t]) + sc * conj_(tot[t]);
+            else if (t == j) taus[j] = tv;
         }
         __syncthreads();
-        if (c == j) {
-            for (int li = rg; li < nl; li += PN_RG) {
-                const int i = i0 + li;
-                if (i == j) pt[li][j] = from_re<T>(beta);
-                else if (i > j) pt[li][j] = sc * pt[li][j];
-            }
+        for (int li = t; li < nl; li += PN_THREADS) {
+            const int i = i0 + li;
+            if (i == j) pt[li][j] = from_re<T>(beta);
+            else if (i > j) pt[li][j] = sc * pt[li][j];
         }
         __syncthreads();
     }
+    // upper triangular factor by rows, T[l][j] = -tau_j sum_q T[l][q] vd_q(j)
+    // (q = l .. j-1); row l only reads its own entries and the stored products
+    if (wg == 0 && t < nr) {
+        Tl[t][t] = taus[t];
+        for (int j = t + 1; j < nr; ++j) {
+            T acc = zero_<T>();
+            for (int q = t; q < j; ++q) acc += Tl[t][q] * Tl[j][q];
+            Tl[t][j] = -(taus[j] * acc);
+        }
+    }
+    __syncthreads();
     // R into the band (zeros below it), the reflectors into Vall (unit entry
     // explicit, zeros above) and into both V columns of the update buffer
     T* b3 = bw.buf3 + z * bw.sbuf;
@@ -218,7 +235,10 @@ __global__ __launch_bounds__(PN_THREADS) void panel_qr_kernel(int n, int k0, int
     if (wg == 0) {
         if (t < KB) tau[k0 + t] = t < nr ? taus[t] : zero_<T>();
         T* Tf = bw.Tf + z * bw.sTf;
-        for (int e = t; e < KB * KB; e += PN_THREADS) Tf[e] = Tl[e / KB][e % KB];
+        for (int e = t; e < KB * KB; e += PN_THREADS) {
+            const int l = e / KB, jj = e % KB;
+            Tf[e] = (l <= jj && jj < nr) ? Tl[l][jj] : zero_<T>();
+        }
     }
 }
 
@@ -265,8 +285,9 @@ void he2hb(hipStream_t s, int n, T* A, int lda, long sA, int batch, T* Vall, T* 
 template <typename T>
 struct S2 {
     // sweeps (wavefronts) per workgroup: one per SIMD, since the chase is bound
-    // by the latency of its dependent tasks, not by throughput; a workgroup
-    // takes a whole compute unit (its LDS is padded at launch)
+    // by the latency of its dependent tasks, not by throughput (eight, two per
+    // SIMD, ran the chase at half the speed); a workgroup takes a whole compute
+    // unit (its LDS is padded at launch)
     static constexpr int Q = 4;
     static constexpr size_t LDS = sizeof(T) * (Q * KB * (KB + 1) + 4 * Q * KB) + Q * sizeof(int);
 };
@@ -439,15 +460,16 @@ __global__ __launch_bounds__(64 * S2<T>::Q) void bulge_kernel(int n, int G, int 
                 if (c <= r && r < Lr)
                     A[(long)(R0 + r) * lda + R0 + c] = (c == r) ? from_re<T>(re_(dv[k])) : dv[k];
             }
-            // the reflector: kept for the next task, and stored in its group's
-            // column (group j = s / Q2_NB at step t, column s % Q2_NB, from row s % Q2_NB)
+            // the reflector: kept for the next task, and stored for the
+            // back-transform as reflector s % NB of group (s / NB, t)
             if (h == 0) vpv[w][r] = vr;
             tprev = tv;
             {
-                const int j = s / Q2_NB, q = s % Q2_NB;
-                T* vg = Vpk + ((long)j * Tmax + t) * Q2_GL * Q2_NB;
-                if (h == 0 && r < Lr) vg[(long)(q + r) * Q2_NB + q] = vr;
-                if (lane == 0) taupk[((long)j * Tmax + t) * Q2_NB + q] = tv;
+                constexpr int NB = Q2NB<T>::v;
+                const int j = s / NB, q = s % NB;
+                T* vg = Vpk + ((long)j * Tmax + t) * NB * KB;
+                if (h == 0 && r < Lr) vg[q * KB + r] = vr;
+                if (lane == 0) taupk[((long)j * Tmax + t) * NB + q] = tv;
             }
             wave_lds_sync();
             const int key = s * K + t + 2;  // t + 1 tasks done
@@ -491,67 +513,257 @@ void hb2st(hipStream_t s, int n, T* A, int lda, long sA, int batch, double* d, d
 }
 
 // ---------------------------------------------------------------- stage-2 back-transform
-// The compact-WY factor of every group (j, t): the reflectors of sweeps
-// j Q2_NB .. j Q2_NB + Q2_NB - 1 at step t, column q starting at row q of the
-// group's Q2_GL x Q2_NB matrix V (zeros elsewhere; missing reflectors are zero
-// with tau = 0).  T solves the forward recurrence T[q][q] = tau_q,
-// T[0:q, q] = -tau_q T[0:q, 0:q] (V^H V)[0:q, q].
+// X <- Q2 X with Q2 the product of the stage-2 reflectors in the order the
+// chase formed them (sweep by sweep, step by step), so the last one formed acts
+// first.  Reflectors on disjoint rows commute; the application goes by groups
+// (j, t), the reflectors of sweeps NB j .. NB j + NB - 1 at step t (NB = Q2NB):
+// rows r0 = NB j + 1 + 32 t .. r0 + NB + 30, reflector q on rows r0 + q ..
+// r0 + q + 31, taken q = NB - 1 down to 0.  Pass j applies its groups
+// t = 0, 1, ... in order (each overlaps the next only through reflectors of
+// later sweeps), after pass j + 1: group t of pass j brings in the rows
+// r0 + NB .. r0 + NB + 31, which pass j + 1 has finished once it has applied
+// its own group t (they are the top 32 rows of that group, never touched
+// again), and keeps the rows r0 .. r0 + NB - 1 from its previous group (for
+// t = 0 they are rows no later pass touches).
+//
+// One lane per column of X: each lane keeps the KB + NB rows of its column's
+// window in registers, so a reflector's inner product is the lane's own sum
+// and no lane exchanges anything; the window moves down 32 rows per group (the
+// top 32 stored, 32 new ones loaded).  A workgroup takes W consecutive passes
+// of one 64-column slice, one wavefront each, handing progress on through LDS;
+// the next W passes of the slice follow in another workgroup, through the
+// progress word of the pass block in global memory (one word per block and
+// slice, written by the block's last wavefront only: a word shared by the
+// blocks would let a block's own later progress answer its wait).  Items (pass block, matrix, slice) go to the
+// resident workgroups in order, so the earliest unfinished item never waits
+// for a later one.
 template <typename T>
-__global__ __launch_bounds__(256) void q2_tfactor_kernel(int n, int Tmax, BandWork<T> bw) {
-    const int j = blockIdx.x, t = blockIdx.y, z = blockIdx.z;
-    if (t >= s2_steps(n, j * Q2_NB)) return;
-    const long grp = (long)j * Tmax + t;
-    const T* V = bw.Vpk + z * bw.sVpk + grp * Q2_GL * Q2_NB;
-    const T* tau = bw.taupk + z * bw.staupk + grp * Q2_NB;
-    T* Tg = bw.Tpk + z * bw.sTpk + grp * Q2_NB * Q2_NB;
-    __shared__ T sv[Q2_GL][Q2_NB + 1];
-    __shared__ T sg[Q2_NB][Q2_NB + 1];
-    __shared__ T st[Q2_NB][Q2_NB + 1];
-    __shared__ T stau[Q2_NB];
-    const int tid = threadIdx.x;
-    for (int e = tid; e < Q2_GL * Q2_NB; e += 256) sv[e / Q2_NB][e % Q2_NB] = V[e];
-    for (int e = tid; e < Q2_NB * (Q2_NB + 1); e += 256) st[e / (Q2_NB + 1)][e % (Q2_NB + 1)] = zero_<T>();
-    if (tid < Q2_NB) stau[tid] = tau[tid];
-    __syncthreads();
-    for (int e = tid; e < Q2_NB * Q2_NB; e += 256) {
-        const int a = e / Q2_NB, b = e % Q2_NB;
-        T acc = zero_<T>();
-        if (a < b)
-            for (int rr = 0; rr < Q2_GL; ++rr) acc += conj_(sv[rr][a]) * sv[rr][b];
-        sg[a][b] = acc;
-    }
-    __syncthreads();
-    for (int q = 0; q < Q2_NB; ++q) {
-        if (tid < q) {
-            T acc = zero_<T>();
-            for (int l = tid; l < q; ++l) acc += st[tid][l] * sg[l][q];
-            st[tid][q] = -(stau[q] * acc);
-        } else if (tid == q) {
-            st[q][q] = stau[q];
-        }
-        __syncthreads();
-    }
-    for (int e = tid; e < Q2_NB * Q2_NB; e += 256) Tg[e] = st[e / Q2_NB][e % Q2_NB];
+struct Q2S {
+    // passes per workgroup (q2_passes): the window takes 128 registers per lane
+    // for real data (64 rows), 192 for complex (48 rows)
+    static constexpr int W = is_cplx<T>::value ? 4 : 8;
+};
+constexpr int Q2_COLS = 64;  // columns per item, one per lane
+
+// Between the workgroups of the stage-2 back-transform, rows go through
+// memory without cache maintenance: the producing wavefront writes them
+// through (agent-scope relaxed atomic stores) and waits for the stores to
+// complete before it raises the progress word; the consumer polls the word and
+// reads the rows with coherent (agent-scope relaxed atomic) loads.  No
+// agent-scope release / acquire, whose L2 write-back and invalidation would
+// stall every workgroup on the XCD.
+__device__ __forceinline__ double load_coherent(const double* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ cplx load_coherent(const cplx* p) {
+    return mk(__hip_atomic_load(&p->x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+              __hip_atomic_load(&p->y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+// A store that goes through to memory (an agent-scope relaxed atomic store).
+__device__ __forceinline__ void store_through(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_through(cplx* p, cplx v) {
+    __hip_atomic_store(&p->x, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&p->y, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// X <- Q2 X: the groups in the order (j descending, t ascending) that the
-// reflectors' overlaps require, level by level: group (j, t) at level
-// t + 3 (J - 1 - j); the groups of one level touch disjoint rows.
+// One reflector of a group on the lane's window: x[Q .. Q+31] -= v (tau v^H x),
+// the coefficients read from LDS (broadcast).
+template <int Q, int WR, typename T>
+__device__ __forceinline__ void q2_reflect(T (&x)[WR], const T* vq, const T* tq) {
+    T d0 = zero_<T>(), d1 = zero_<T>(), d2 = zero_<T>(), d3 = zero_<T>();
+#pragma unroll
+    for (int r = 0; r < KB; r += 4) {
+        d0 += conj_(vq[r]) * x[Q + r];
+        d1 += conj_(vq[r + 1]) * x[Q + r + 1];
+        d2 += conj_(vq[r + 2]) * x[Q + r + 2];
+        d3 += conj_(vq[r + 3]) * x[Q + r + 3];
+    }
+    const T d = tq[0] * ((d0 + d1) + (d2 + d3));
+#pragma unroll
+    for (int r = 0; r < KB; ++r) x[Q + r] -= vq[r] * d;
+}
+
+// The group's reflectors q = NB - 1 down to 0 (each index a constant, so that
+// the window stays in registers).
+template <typename T, int WR, int... Is>
+__device__ __forceinline__ void q2_reflect_all(T (&x)[WR], const T* vb, const T* tb,
+                                               std::integer_sequence<int, Is...>) {
+    constexpr int NB = (int)sizeof...(Is);
+    (q2_reflect<NB - 1 - Is, WR, T>(x, vb + (NB - 1 - Is) * KB, tb + (NB - 1 - Is)), ...);
+}
+
 template <typename T>
-void q2_apply(hipStream_t s, int n, int batch, int ncols, T* X, int ldx, long sX, BandWork<T>& w) {
+__global__ __launch_bounds__(64 * Q2S<T>::W) void q2_stream_kernel(int n, int J, int Tmax, int ncols, int batch,
+                                                                   int G, T* X, int ldx, long sX,
+                                                                   const T* __restrict__ Vpk, long sVpk,
+                                                                   const T* __restrict__ taupk, long staupk,
+                                                                   int* prog, int* abort_, int* info) {
+    constexpr int W = Q2S<T>::W;
+    constexpr int NB = Q2NB<T>::v;
+    constexpr int WR = KB + NB;  // window rows (the group's KB + NB - 1, and one more)
+    __shared__ T vs[W][NB][KB];
+    __shared__ T ts[W][NB];
+    __shared__ int lp[W];  // groups finished by each wavefront's pass
+    __shared__ int stop;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int nsl = (ncols + Q2_COLS - 1) / Q2_COLS;
+    const long per_b = (long)batch * nsl;
+    const long nitems = (long)((J + W - 1) / W) * per_b;
+    for (long it = blockIdx.x; it < nitems; it += G) {
+        __syncthreads();  // every wavefront is done with the previous item
+        if (threadIdx.x == 0) stop = __hip_atomic_load(abort_, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (threadIdx.x < W) lp[threadIdx.x] = 0;
+        __syncthreads();
+        if (stop) break;
+        const int b = (int)(it / per_b);
+        const int z = (int)((it % per_b) / nsl), c = (int)(it % nsl);
+        const int j = J - 1 - b * W - w;
+        if (j < 0) continue;
+        const int col = c * Q2_COLS + lane;
+        const bool cv = col < ncols;
+        T* Xc = X + z * sX + (cv ? col : 0);
+        const T* Vz = Vpk + z * sVpk;
+        const T* tz = taupk + z * staupk;
+        int* pg = prog + it;  // this item's progress; item it - per_b is the previous block
+        const int Ts = s2_steps(n, j * NB);
+        const int Tp = j + 1 < J ? s2_steps(n, (j + 1) * NB) : 0;  // groups of pass j + 1
+        // Rows past the matrix are read as its last row: their coefficients
+        // are zero, so they change nothing and are never stored; lanes past
+        // the last column read column 0 and store nothing.
+        T x[WR];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) x[k] = Xc[(long)min(j * NB + 1 + k, n - 1) * ldx];
+        for (int t = 0; t < Ts; ++t) {
+            const int r0 = j * NB + 1 + t * KB;
+            if (Tp > 0) {
+                const int need = min(t + 1, Tp);
+                int ok = 1;
+                if (lane == 0) {
+                    long polls = 0;
+                    if (w > 0) {
+                        while (__hip_atomic_load(&lp[w - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < need) {
+                            if ((++polls & 1023) == 0 &&
+                                (polls > WAIT_POLLS ||
+                                 __hip_atomic_load(abort_, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                                ok = 0;
+                                break;
+                            }
+                            __builtin_amdgcn_s_sleep(1);
+                        }
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                    } else {
+                        // the previous block's rows were written through to memory and are
+                        // read below with coherent loads: no cache invalidation needed
+                        const int* pp = pg - per_b;
+                        while (__hip_atomic_load(pp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                            if ((++polls & 63) == 0 &&
+                                (polls > WAIT_POLLS_GLOBAL ||
+                                 __hip_atomic_load(abort_, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                                ok = 0;
+                                break;
+                            }
+                            __builtin_amdgcn_s_sleep(1);
+                        }
+                        asm volatile("" ::: "memory");
+                    }
+                    if (!ok) {
+                        atomicExch(abort_, 1);
+                        set_info(info, KS_ERR_NO_CONVERGENCE, -3);
+                    }
+                }
+                ok = __shfl(ok, 0, WAVE);
+                if (!ok) break;
+            }
+            // the window's 32 new rows (coherent loads where another workgroup wrote them)
+            if (w == 0 && b > 0) {
+#pragma unroll
+                for (int k = NB; k < WR; ++k) x[k] = load_coherent(Xc + (long)min(r0 + k, n - 1) * ldx);
+            } else if (r0 + WR <= n) {
+                const T* pl = Xc + (long)(r0 + NB) * ldx;
+#pragma unroll
+                for (int k = NB; k < WR; ++k) {
+                    x[k] = *pl;
+                    pl += ldx;
+                }
+            } else {
+#pragma unroll
+                for (int k = NB; k < WR; ++k) x[k] = Xc[(long)min(r0 + k, n - 1) * ldx];
+            }
+            // the group's reflectors (reflector q contiguous, v_0 = 1, zeros past the matrix)
+            const long grp = (long)j * Tmax + t;
+            const T* Vg = Vz + grp * NB * KB;
+            wave_lds_sync();
+#pragma unroll
+            for (int e = 0; e < NB * KB / 64; ++e) (&vs[w][0][0])[e * 64 + lane] = Vg[e * 64 + lane];
+            if (lane < NB) ts[w][lane] = tz[grp * NB + lane];
+            wave_lds_sync();
+            // an offset the compiler cannot see through, so that the coefficient
+            // addresses are formed here rather than hoisted out of the group loop
+            int vo = 0;
+            asm volatile("" : "+v"(vo));
+            q2_reflect_all<T, WR>(x, &vs[w][0][0] + vo, &ts[w][0] + vo, std::make_integer_sequence<int, NB>{});
+            // the top 32 rows are final for this pass (all of the window after the last group)
+            // (the last pass of the block writes its rows through to memory, for
+            // the next block's workgroup)
+            if (cv) {
+                T* ps = Xc + (long)r0 * ldx;
+                const int kend = t == Ts - 1 ? min(WR, n - r0) : min(KB, n - r0);
+                const bool wt = w == W - 1;
+                if (kend == KB && !wt) {
+#pragma unroll
+                    for (int k = 0; k < KB; ++k) {
+                        *ps = x[k];
+                        ps += ldx;
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < WR; ++k) {
+                        if (k < kend) {
+                            if (wt) store_through(ps, x[k]);
+                            else *ps = x[k];
+                        }
+                        ps += ldx;
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < NB; ++k) x[k] = x[k + KB];
+            wave_lds_sync();
+            if (w == W - 1) {
+                // the written-through stores complete before the progress word
+                asm volatile("" ::: "memory");
+                __builtin_amdgcn_s_waitcnt(0);
+                asm volatile("" ::: "memory");
+            }
+            if (lane == 0) {
+                __hip_atomic_store(&lp[w], t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (w == W - 1) __hip_atomic_store(pg, t + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    }
+}
+
+template <typename T>
+void q2_apply(hipStream_t s, int n, int batch, int ncols, T* X, int ldx, long sX, BandWork<T>& w, int* info) {
     const int ns = n - 1;
     if (ns <= 0 || ncols <= 0) return;
-    const int J = cdiv(ns, Q2_NB), Tmax = s2_steps(n, 0);
-    hipLaunchKernelGGL(q2_tfactor_kernel<T>, dim3(J, Tmax, batch), dim3(256), 0, s, n, Tmax, w);
-    const int nlev = Tmax + 3 * (J - 1);
-    for (int lv = 0; lv < nlev; ++lv) q2_level<T>(s, n, batch, lv, ncols, X, ldx, sX, w);
+    const int J = cdiv(ns, Q2NB<T>::v), Tmax = s2_steps(n, 0);
+    const int nsl = cdiv(ncols, Q2_COLS);
+    const long nitems = (long)cdiv(J, Q2S<T>::W) * batch * nsl;
+    fill_zero<int>(s, w.q2prog, nitems);
+    // every workgroup resident (one per compute unit at most, by registers)
+    const int G = (int)std::max(1L, std::min(nitems, (long)w.ncu));
+    hipLaunchKernelGGL(q2_stream_kernel<T>, dim3(G), dim3(64 * Q2S<T>::W), 0, s, n, J, Tmax, ncols, batch, G, X,
+                       ldx, sX, (const T*)w.Vpk, w.sVpk, (const T*)w.taupk, w.staupk, w.q2prog, w.abort_, info);
 }
 
 template void he2hb<double>(hipStream_t, int, double*, int, long, int, double*, double*, BandWork<double>&, int*);
 template void he2hb<cplx>(hipStream_t, int, cplx*, int, long, int, cplx*, cplx*, BandWork<cplx>&, int*);
 template void hb2st<double>(hipStream_t, int, double*, int, long, int, double*, double*, BandWork<double>&, int*);
 template void hb2st<cplx>(hipStream_t, int, cplx*, int, long, int, double*, double*, BandWork<cplx>&, int*);
-template void q2_apply<double>(hipStream_t, int, int, int, double*, int, long, BandWork<double>&);
-template void q2_apply<cplx>(hipStream_t, int, int, int, cplx*, int, long, BandWork<cplx>&);
+template void q2_apply<double>(hipStream_t, int, int, int, double*, int, long, BandWork<double>&, int*);
+template void q2_apply<cplx>(hipStream_t, int, int, int, cplx*, int, long, BandWork<cplx>&, int*);
 
 }  // namespace ks

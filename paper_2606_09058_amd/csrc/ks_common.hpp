@@ -145,12 +145,25 @@ __device__ inline void set_info(int* info, int code, int detail) {
 
 // ---------------------------------------------------------------- two-stage reduction
 // Half-bandwidth of the band form between the two stages, and the grouping of
-// the bulge-chasing reflectors for the blocked back-transform: Q2_NB
-// consecutive sweeps at one step form one compact-WY block whose reflectors,
-// each shifted down a row from the previous, fit a Q2_GL x Q2_NB matrix.
+// the bulge-chasing reflectors for the back-transform: the reflectors of NB
+// consecutive sweeps at one step form a group, each shifted down a row from
+// the previous (KB + NB - 1 rows in all).  The back-transform keeps a group's
+// rows of one column in a lane's registers: NB = 32 for real data, 16 for
+// complex (48 complex rows are 192 registers).
 constexpr int KB = 32;
-constexpr int Q2_NB = 32;
-constexpr int Q2_GL = KB + Q2_NB - 1;
+template <typename T>
+struct Q2NB {
+    static constexpr int v = 32;
+};
+template <>
+struct Q2NB<cplx> {
+    static constexpr int v = 16;
+};
+inline int q2_nb(bool complex_data) { return complex_data ? 16 : 32; }
+// Passes (wavefronts) per workgroup of the stage-2 back-transform: two per
+// SIMD for real data; one for complex, whose window and coefficients need the
+// accumulation registers as well.
+inline int q2_passes(bool complex_data) { return complex_data ? 4 : 8; }
 // Steps (tasks) of bulge-chasing sweep s of an order-n band: one per KB rows
 // below the subdiagonal entry it starts from.
 __host__ __device__ inline int s2_steps(int n, int s) { return (n - 1 - s + KB - 1) / KB; }

@@ -351,53 +351,6 @@ __global__ __launch_bounds__(256) void gemm_kernel(int m, int n, int K, double a
                            kscale ? kscale + b * sk : nullptr, uplo, m0, n0, klo);
 }
 
-// ---------------------------------------------------------------- two-stage back-transform
-// One level of X <- Q2 X (bulge-chasing reflectors, ks_band.hip): workgroup
-// (j, c) applies group (j, t), t = level - 3 (J - 1 - j), to the 64 columns of
-// X from c * 64 on: rows r0 = j Q2_NB + 1 + t KB .. r0 + L - 1 (L <= Q2_GL),
-// W1 = V^H X, W2 = T W1, X -= V W2, three tile products through the group's
-// scratch rows of W1 and W2.  Groups that do not exist at this level leave.
-template <typename T>
-__global__ __launch_bounds__(256) void q2_group_kernel(int n, int J, int Tmax, int level, int j0, int ncols, T* X,
-                                                       int ldx, long sX, const T* Vpk, long sVpk, const T* Tpk,
-                                                       long sTpk, T* W1, T* W2, long sW) {
-    const int j = j0 + (int)blockIdx.x, z = blockIdx.z;
-    const int t = level - 3 * (J - 1 - j);
-    const int s0 = j * Q2_NB;
-    if (t < 0 || t >= s2_steps(n, s0)) return;
-    const int r0 = s0 + 1 + t * KB;
-    const int L = min(Q2_GL, n - r0);
-    const int c0 = blockIdx.y * BN;
-    const long grp = (long)j * Tmax + t;
-    const T* V = Vpk + z * sVpk + grp * Q2_GL * Q2_NB;
-    const T* Tg = Tpk + z * sTpk + grp * Q2_NB * Q2_NB;
-    T* Xg = X + z * sX + (long)r0 * ldx;
-    T* w1 = W1 + z * sW + (long)j * Q2_NB * ncols;
-    T* w2 = W2 + z * sW + (long)j * Q2_NB * ncols;
-    gemm_tile<T, OP_C, OP_N>(Q2_NB, ncols, L, 1.0, V, Q2_NB, Xg, ldx, 0.0, w1, ncols, nullptr, UPLO_FULL, 0, c0);
-    __syncthreads();
-    gemm_tile<T, OP_N, OP_N>(Q2_NB, ncols, Q2_NB, 1.0, Tg, Q2_NB, w1, ncols, 0.0, w2, ncols, nullptr, UPLO_FULL, 0,
-                             c0);
-    __syncthreads();
-    gemm_tile<T, OP_N, OP_N>(L, ncols, Q2_NB, -1.0, V, Q2_NB, w2, ncols, 1.0, Xg, ldx, nullptr, UPLO_FULL, 0, c0);
-}
-
-template <typename T>
-void q2_level(hipStream_t s, int n, int batch, int level, int ncols, T* X, int ldx, long sX, const BandWork<T>& w) {
-    const int J = cdiv(n - 1, Q2_NB), Tmax = s2_steps(n, 0);
-    // the blocks j with a group at this level: t = level - 3 (J - 1 - j) in [0, steps of sweep j Q2_NB)
-    // (t grows with j while the steps of the block's first sweep shrink: the
-    // valid j form one run, from the first with t >= 0)
-    const int j0 = std::max(0, J - 1 - level / 3);
-    int j1 = J - 1;
-    while (j1 >= j0 && s2_steps(n, j1 * Q2_NB) <= level - 3 * (J - 1 - j1)) --j1;
-    if (j0 > j1) return;
-    hipLaunchKernelGGL((q2_group_kernel<T>), dim3(j1 - j0 + 1, cdiv(ncols, BN), batch), dim3(256), 0, s, n, J, Tmax,
-                       level, j0, ncols, X, ldx, sX, (const T*)w.Vpk, w.sVpk, (const T*)w.Tpk, w.sTpk, w.W1, w.W2,
-                       w.sW);
-}
-template void q2_level<double>(hipStream_t, int, int, int, int, double*, int, long, const BandWork<double>&);
-template void q2_level<cplx>(hipStream_t, int, int, int, int, cplx*, int, long, const BandWork<cplx>&);
 
 // ---------------------------------------------------------------- large tiles
 // Large tiles only where they pay: enough k steps to amortise the tile's
@@ -406,6 +359,12 @@ template void q2_level<cplx>(hipStream_t, int, int, int, int, cplx*, int, long, 
 // on 64 x 64 tiles).
 constexpr long BIG_MIN_TILES = 512;
 constexpr int BIG_MIN_K = 256;
+// The smallest k for the large tiles, set per plan call (the autotuner's
+// knob) on the calling thread: launches are enqueued by the thread that calls
+// the entry point, so a plan's setting holds for exactly its own launches.
+static thread_local int g_big_min_k = BIG_MIN_K;
+void gemm_set_big_min_k(int k) { g_big_min_k = k; }
+int gemm_big_min_k() { return g_big_min_k; }
 // Output tiles of BM x BN (128 x 128; 64 x 64 for FP64 complex) with one
 // wave tile of BM/2 x BN/2 per wavefront (2 x 2 wavefronts), so that each k
 // step feeds (BM/32)(BN/32) MFMA blocks per wavefront per operand fragment
@@ -615,7 +574,7 @@ static void launch(hipStream_t s, int m, int n, int k, double alpha, const T* A,
     const long big_tiles = (long)cdiv(m, BBM) * cdiv(n, BBN) * batch / (uplo == UPLO_LOWER ? 2 : 1);
     // FP32 gains from large tiles at one round of workgroups, FP64 from two
     const long min_tiles = (sizeof(T) == 4 || std::is_same<T, cplx32>::value) ? BIG_MIN_TILES : 2 * BIG_MIN_TILES;
-    if (!kscale && k >= BIG_MIN_K && big_tiles >= min_tiles) {
+    if (!kscale && k >= g_big_min_k && big_tiles >= min_tiles) {
         dim3 grid(cdiv(n, BBN), cdiv(m, BBM), batch);
         hipLaunchKernelGGL((gemm_big_kernel<T, OPA, OPB>), grid, dim3(256), 0, s, m, n, k, alpha, A, lda, sa, B,
                            ldb, sb, beta, C, ldc, sc, (int)uplo, kdev, (int)tri);

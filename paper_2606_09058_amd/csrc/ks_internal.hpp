@@ -22,6 +22,17 @@ constexpr int BACKTR_SUB = 64;  // reflectors per triangular factor solved direc
 // (rank-256 updates run on the large-tile GEMM), 128 below (smaller orders
 // pay more for the larger factors than they gain)
 inline int backtr_block(int order) { return order >= 4096 ? 256 : 128; }
+constexpr int DC_LEAF_MIN = 16;  // smallest leaf the autotuner tries (the workspace fits its tree)
+
+// Large GEMM tiles from this inner dimension on (KS_TUNE_NEVER: never), for
+// the launches the calling thread enqueues; GemmPolicy sets it for a scope.
+void gemm_set_big_min_k(int k);
+int gemm_big_min_k();
+struct GemmPolicy {
+    int prev;
+    explicit GemmPolicy(int k) : prev(gemm_big_min_k()) { gemm_set_big_min_k(k); }
+    ~GemmPolicy() { gemm_set_big_min_k(prev); }
+};
 constexpr int DC_LEAF = 32;    // largest divide-and-conquer leaf
 constexpr int MAX_KW = 64;     // k-point weights passed by value
 
@@ -141,10 +152,9 @@ struct BandWork {
     int* cnt = nullptr;  long scnt = 0;   // one arrival counter per panel
     int* gprog = nullptr; long sgp = 0;   // bulge chasing: progress of each workgroup's last sweep
     int* abort_ = nullptr;                // set by a wait that gave up: every wait then leaves
-    T* Vpk = nullptr;    long sVpk = 0;   // J x Tmax x Q2_GL x Q2_NB: bulge-chasing reflectors per group
+    T* Vpk = nullptr;    long sVpk = 0;   // J x Tmax x Q2_NB x KB: bulge-chasing reflectors per group
     T* taupk = nullptr;  long staupk = 0; // J x Tmax x Q2_NB
-    T* Tpk = nullptr;    long sTpk = 0;   // J x Tmax x Q2_NB x Q2_NB: compact-WY factors of the groups
-    T* W1 = nullptr;     T* W2 = nullptr; long sW = 0;  // J Q2_NB x order: group products
+    int* q2prog = nullptr;                // stage-2 back-transform: progress per (pass block, matrix, 64-column slice)
     T* P = nullptr;      long pelems = 0; // split-K partial products (shared with the back-transform)
     int ncu = 1;                          // compute units: every workgroup of a waiting kernel must be resident
 };
@@ -237,19 +247,15 @@ int hetrd_tune(hipStream_t s, int n, T* A, int lda, long sA, int batch, double* 
 // (d, e: stride n) and keeps its reflectors grouped for q2_apply, which forms
 // X <- Q2 X for the n x ncols blocks of X.  A wait that gives up (a resident
 // workgroup never arrived) records KS_ERR_NO_CONVERGENCE with detail -1
-// (stage 1) or -2 (stage 2) and every kernel still ends.
+// (stage 1), -2 (stage 2) or -3 (stage-2 back-transform) and every kernel
+// still ends.
 template <typename T>
 void he2hb(hipStream_t s, int n, T* A, int lda, long sA, int batch, T* Vall, T* tau, BandWork<T>& w, int* info);
 template <typename T>
 void hb2st(hipStream_t s, int n, T* A, int lda, long sA, int batch, double* d, double* e, BandWork<T>& w,
            int* info);
 template <typename T>
-void q2_apply(hipStream_t s, int n, int batch, int ncols, T* X, int ldx, long sX, BandWork<T>& w);
-// One level of the blocked application of the bulge-chasing reflectors
-// (ks_gemm.hip): every group (j, t) with t = level - 3 (J - 1 - j) is applied to
-// its rows of X, all of X's columns, by three MFMA tile products per 64 columns.
-template <typename T>
-void q2_level(hipStream_t s, int n, int batch, int level, int ncols, T* X, int ldx, long sX, const BandWork<T>& w);
+void q2_apply(hipStream_t s, int n, int batch, int ncols, T* X, int ldx, long sX, BandWork<T>& w, int* info);
 
 // Divide and conquer for a batch of tridiagonals of order tr.n (d, e, lam:
 // stride n; Z, Z2, U, Qp: stride n^2; the work arrays of w: stride n, with
@@ -261,7 +267,7 @@ void stedc(hipStream_t s, const DcTree& tr, int batch, const double* d, const do
 // restores the defaults, 40 sweeps and 120 iterations).
 void stedc_set_caps(int leaf_sweeps, int secular_iters);
 
-void dc_tree_host(int n, std::vector<int>& mlo, std::vector<int>& mmid, std::vector<int>& mhi,
+void dc_tree_host(int n, int leaf, std::vector<int>& mlo, std::vector<int>& mmid, std::vector<int>& mhi,
                   std::vector<int>& leaf_lo, std::vector<int>& leaf_hi, int& depth,
                   std::vector<int>& max_k0);
 

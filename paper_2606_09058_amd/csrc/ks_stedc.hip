@@ -672,12 +672,14 @@ void stedc(hipStream_t s, const DcTree& tr, int batch, const double* d, const do
     }
 }
 
-// Host: the tear tree for order n (depth = smallest with ceil(n / 2^depth) <= DC_LEAF).
-void dc_tree_host(int n, std::vector<int>& mlo, std::vector<int>& mmid, std::vector<int>& mhi,
+// Host: the tear tree for order n (depth = smallest with ceil(n / 2^depth) <= leaf,
+// leaf <= DC_LEAF).
+void dc_tree_host(int n, int leaf, std::vector<int>& mlo, std::vector<int>& mmid, std::vector<int>& mhi,
                   std::vector<int>& leaf_lo, std::vector<int>& leaf_hi, int& depth,
                   std::vector<int>& max_k0) {
+    leaf = std::max(2, std::min(leaf, DC_LEAF));
     depth = 0;
-    while ((n + (1 << depth) - 1) / (1 << depth) > DC_LEAF) ++depth;
+    while ((n + (1 << depth) - 1) / (1 << depth) > leaf) ++depth;
     // nodes level by level: level l has 2^l nodes, stored at offset 2^l - 1
     std::vector<int> lo{0}, hi{n};
     mlo.clear();

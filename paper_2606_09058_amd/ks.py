@@ -12,6 +12,8 @@ import os
 
 import torch
 
+from . import tune_cache as tune_cache_mod
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libks.so")
 
@@ -33,7 +35,7 @@ STATUS = {
 EXPORTS = ["ks_plan_create", "ks_plan_destroy", "ks_gevd", "ks_density", "ks_energy_density", "ks_bloch_sum",
            "ks_density_backward",
            "ks_plan_get_info", "ks_status_string", "ks_plan_workspace_bytes", "ks_plan_set_profiling",
-           "ks_plan_get_profile", "ks_plan_get_graph_stats", "ks_plan_get_tuning", "ks_plan_set_refinement",
+           "ks_plan_get_profile", "ks_plan_get_graph_stats", "ks_plan_get_tuning", "ks_plan_set_tuning", "ks_plan_set_refinement",
            "ks_plan_set_overlap_cutoff", "ks_plan_get_overlap_rank"]
 
 
@@ -61,10 +63,16 @@ class Profile(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    """ks_tuning: the symmetric product's tiles per workgroup and the timings behind it."""
+    """ks_tuning: the plan's knobs and, under KS_PLAN_AUTOTUNE, the timings behind them."""
     _fields_ = [("tiles_per_workgroup", ctypes.c_int32), ("ncand", ctypes.c_int32),
                 ("cand", ctypes.c_int32 * 4), ("ms", ctypes.c_double * 4), ("nseg", ctypes.c_int32),
-                ("seg_first", ctypes.c_int32 * 8), ("seg_tiles", ctypes.c_int32 * 8)]
+                ("seg_first", ctypes.c_int32 * 8), ("seg_tiles", ctypes.c_int32 * 8),
+                ("backtr_block", ctypes.c_int32), ("gemm_big_min_k", ctypes.c_int32),
+                ("backtr_ms", (ctypes.c_double * 2) * 2), ("dc_leaf", ctypes.c_int32),
+                ("dc_ms", ctypes.c_double * 2), ("from_cache", ctypes.c_int32)]
+
+
+KS_TUNE_NEVER = 0x7FFFFFFF
 
 
 _lib = None
@@ -111,6 +119,8 @@ def lib():
         L.ks_plan_get_graph_stats.restype = I
         L.ks_plan_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
         L.ks_plan_get_tuning.restype = I
+        L.ks_plan_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+        L.ks_plan_set_tuning.restype = I
         L.ks_plan_set_refinement.argtypes = [P, I]
         L.ks_plan_set_refinement.restype = I
         _lib = L
@@ -150,7 +160,11 @@ class Plan:
     """Owns a ks_plan: workspace for `batch` problems of `n` orbitals per spin block."""
 
     def __init__(self, n, batch=1, complex=False, noncollinear=False, precision=KS_FP64, stream=None,
-                 ld_h=None, ld_s=None, flags=0):
+                 ld_h=None, ld_s=None, flags=0, tune_cache=None):
+        """tune_cache: path of a tuning-cache JSON file.  With KS_PLAN_AUTOTUNE in
+        flags, a plan whose key is in the cache takes the stored knobs without
+        timing anything (tuning()["from_cache"] is then True); otherwise it is
+        tuned and its knobs are added to the cache."""
         self.n = int(n)
         self.batch = int(batch)
         self.nsp = 2 if noncollinear else 1
@@ -167,7 +181,28 @@ class Plan:
                              int(ld_h or self.order), int(ld_s or self.n), ctypes.c_void_p(handle),
                              int(flags))
         self._h = ctypes.c_void_p()
+        entry, key = None, None
+        if tune_cache is not None and (flags & KS_PLAN_AUTOTUNE):
+            key = self.tune_key(flags)
+            entry = tune_cache_mod.lookup(tune_cache, key)
+            if entry is not None:
+                self.desc.flags = int(flags) & ~KS_PLAN_AUTOTUNE
         _check(lib().ks_plan_create(ctypes.byref(self.desc), ctypes.byref(self._h)), "ks_plan_create")
+        self.desc.flags = int(flags)
+        if entry is not None:
+            self.set_tuning(entry)
+        elif key is not None:
+            tune_cache_mod.store(tune_cache, key, self.tuning_knobs())
+
+    def tune_key(self, flags=None):
+        """The tuning-cache key of this plan's shape on the current device."""
+        flags = self.desc.flags if flags is None else flags
+        props = torch.cuda.get_device_properties(torch.cuda.current_device())
+        arch = "%s-%dcu" % (props.gcnArchName.split(":")[0], props.multi_processor_count)
+        route = "twostage" if flags & KS_PLAN_TWOSTAGE else ("lowdin" if flags & KS_PLAN_LOWDIN else "onestage")
+        return tune_cache_mod.cache_key(arch, "gevd", "complex128" if self.complex else "real64", self.order,
+                                        self.batch, "noncollinear" if self.nsp == 2 else "collinear",
+                                        "mixed" if self.desc.precision == KS_MIXED else "fp64", route)
 
     # shapes --------------------------------------------------------------------------------
     def _mshape(self):
@@ -268,12 +303,45 @@ class Plan:
         _check(lib().ks_plan_set_refinement(self._h, int(sweeps)), "ks_plan_set_refinement")
 
     def tuning(self):
-        """{"tiles_per_workgroup": t, "candidates": {cand: ms}} (timings only under KS_PLAN_AUTOTUNE)."""
+        """The plan's knobs and (under KS_PLAN_AUTOTUNE) the timings behind them:
+        tiles_per_workgroup, candidates {tiles: ms}, segments [(first column, tiles)],
+        backtr_block, gemm_big_min_k (KS_TUNE_NEVER: 64 x 64 tiles only),
+        backtr_ms {(block, big_min_k): ms}, dc_leaf, dc_ms {leaf: ms}, from_cache."""
         tu = Tuning()
         _check(lib().ks_plan_get_tuning(self._h, ctypes.byref(tu)), "ks_plan_get_tuning")
         return {"tiles_per_workgroup": int(tu.tiles_per_workgroup),
                 "candidates": {int(tu.cand[i]): float(tu.ms[i]) for i in range(tu.ncand)},
-                "segments": [(int(tu.seg_first[i]), int(tu.seg_tiles[i])) for i in range(tu.nseg)]}
+                "segments": [(int(tu.seg_first[i]), int(tu.seg_tiles[i])) for i in range(tu.nseg)],
+                "backtr_block": int(tu.backtr_block), "gemm_big_min_k": int(tu.gemm_big_min_k),
+                "backtr_ms": {(128 << b, KS_TUNE_NEVER if g else 256): float(tu.backtr_ms[b][g])
+                              for b in range(2) for g in range(2)},
+                "dc_leaf": int(tu.dc_leaf), "dc_ms": {16 << i: float(tu.dc_ms[i]) for i in range(2)},
+                "from_cache": bool(tu.from_cache)}
+
+    def tuning_knobs(self):
+        """The knobs alone, as a tuning-cache entry."""
+        tu = Tuning()
+        _check(lib().ks_plan_get_tuning(self._h, ctypes.byref(tu)), "ks_plan_get_tuning")
+        return {"tiles_per_workgroup": int(tu.tiles_per_workgroup), "nseg": int(tu.nseg),
+                "seg_first": [int(tu.seg_first[i]) for i in range(tu.nseg)],
+                "seg_tiles": [int(tu.seg_tiles[i]) for i in range(tu.nseg)],
+                "backtr_block": int(tu.backtr_block), "gemm_big_min_k": int(tu.gemm_big_min_k),
+                "dc_leaf": int(tu.dc_leaf)}
+
+    def set_tuning(self, knobs):
+        """Set the knobs from a tuning-cache entry (ks_plan_set_tuning)."""
+        tu = Tuning()
+        tu.tiles_per_workgroup = int(knobs["tiles_per_workgroup"])
+        tu.nseg = int(knobs["nseg"])
+        if not 1 <= tu.nseg <= 8 or len(knobs["seg_first"]) != tu.nseg or len(knobs["seg_tiles"]) != tu.nseg:
+            raise ValueError("bad segment list in tuning entry")
+        for i in range(tu.nseg):
+            tu.seg_first[i] = int(knobs["seg_first"][i])
+            tu.seg_tiles[i] = int(knobs["seg_tiles"][i])
+        tu.backtr_block = int(knobs["backtr_block"])
+        tu.gemm_big_min_k = int(knobs["gemm_big_min_k"])
+        tu.dc_leaf = int(knobs["dc_leaf"])
+        _check(lib().ks_plan_set_tuning(self._h, ctypes.byref(tu)), "ks_plan_set_tuning")
 
     def graph_stats(self):
         """(captures, replays) of ks_gevd under KS_PLAN_GRAPH."""
