@@ -108,14 +108,17 @@ enum { KS_PLAN_GRAPH = 1u,
         * are factored by Householder QR and the trailing matrix takes two-sided
         * rank-64 updates on the matrix cores, leaving a band of half-bandwidth
         * 32; bulge chasing then reduces the band to tridiagonal form, and the
-        * eigenvectors take the chasing reflectors in blocks of 32 sweeps before
-        * the panel reflectors.  Same outputs as the one-stage route up to
-        * rounding.  FP64 only (with KS_MIXED: KS_ERR_NOT_SUPPORTED); the Loewdin
-        * route uses it for H' (the eigen-decomposition of S stays one-stage).
-        * Its kernels wait for each other across workgroups, so a plan asks for
-        * at most one workgroup per compute unit per waiting launch; a wait that
-        * never completes gives up after seconds with KS_ERR_NO_CONVERGENCE
-        * (info -1 in the band reduction, -2 in the bulge chasing). */
+        * eigenvectors take the chasing reflectors (in groups of 32 sweeps, 16
+        * for complex data) before the panel reflectors.  Same outputs as the
+        * one-stage route up to rounding.  FP64 only (with KS_MIXED:
+        * KS_ERR_NOT_SUPPORTED); the Loewdin route uses it for H' (the
+        * eigen-decomposition of S stays one-stage).  Its kernels wait for each
+        * other across workgroups, so a plan asks for at most one workgroup per
+        * compute unit per waiting launch (orders up to 512 times the compute
+        * units, 256 times for complex data, else KS_ERR_NOT_SUPPORTED); a wait
+        * that never completes gives up after seconds with KS_ERR_NO_CONVERGENCE
+        * (info -1 in the band reduction, -2 in the bulge chasing, -3 in the
+        * chasing reflectors' back-transform). */
        KS_PLAN_TWOSTAGE = 8u };
 enum { KS_REUSE_S = 1u };                            /* ks_gevd flags                */
 

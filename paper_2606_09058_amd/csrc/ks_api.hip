@@ -268,7 +268,8 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
     const size_t tm = order > 1 ? (size_t)s2_steps((int)order, 0) : 1;       // steps of the longest sweep
     const size_t q2nb = (size_t)q2_nb(es == 16);                           // sweeps per group
     const size_t jg = order > 1 ? (order - 1 + q2nb - 1) / q2nb : 1;           // groups of sweeps
-    const size_t pmax = (order + (es == 16 ? 256 : 512) - 1) / (es == 16 ? 256 : 512);
+    const size_t prow = (size_t)panel_rows(es == 16);
+    const size_t pmax = (order + prow - 1) / prow;
     const size_t npan = (order + KB - 1) / KB;
     constexpr size_t GMAX = 64;  // bulge-chasing workgroups per matrix
     size_t oBX = 0, oB3 = 0, oBT = 0, oBM = 0, oBN = 0, oRec = 0, oCnt = 0, oGp = 0, oAb = 0, oVpk = 0, oTaupk = 0;
@@ -972,7 +973,7 @@ ks_status ks_plan_create(const ks_plan_desc* d, ks_plan** out) {
         }
         p->bandr.ncu = p->bandc.ncu = ncu;
         // the panel factorisation's workgroups of one matrix must all be resident together
-        if (cdiv(p->order, p->is_c ? 256 : 512) > ncu) {
+        if (cdiv(p->order, panel_rows(p->is_c)) > ncu) {
             (void)hipFree(p->base);
             delete p;
             return KS_ERR_NOT_SUPPORTED;

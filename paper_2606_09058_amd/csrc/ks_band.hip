@@ -85,20 +85,30 @@ constexpr long WAIT_POLLS = 1L << 24;
 constexpr long WAIT_POLLS_GLOBAL = 1L << 21;
 
 // ---------------------------------------------------------------- stage 1
+// A workgroup's panel rows live in registers: thread (rg, c) holds column c of
+// rows rg, rg + PN_RG, ... (NI of them); only the pivot column of each step
+// goes through LDS, once, for every thread of its row group.
 template <typename T>
 struct Pn {
-    static constexpr int R = is_cplx<T>::value ? 256 : 512;  // panel rows per workgroup (128 KB of LDS)
+    static constexpr int R = panel_rows(is_cplx<T>::value);  // rows per workgroup
 };
 constexpr int PN_THREADS = 512;
-constexpr int PN_RG = PN_THREADS / KB;  // row groups of the partial sums
+constexpr int PN_RG = PN_THREADS / KB;  // row groups
+
+// c ? a : b by value, field by field (a select between aggregates through
+// their addresses would keep a register array in memory)
+__device__ inline double pick(bool c, double a, double b) { return c ? a : b; }
+__device__ inline cplx pick(bool c, cplx a, cplx b) { return mk(c ? a.x : b.x, c ? a.y : b.y); }
 
 template <typename T>
 __global__ __launch_bounds__(PN_THREADS) void panel_qr_kernel(int n, int k0, int P, int zoff, T* A, int lda, long sA,
                                                               T* Vall, T* tau, BandWork<T> bw, int* info) {
     constexpr int R = Pn<T>::R;
-    __shared__ T pt[R][KB];          // this workgroup's panel rows
+    constexpr int NI = R / PN_RG;   // rows per thread
+    __shared__ T xs[R];              // the pivot column (raw) of this workgroup's rows
     __shared__ T red[PN_RG][KB];
     __shared__ T tot[2 * KB];        // summed partials of column j, then row j
+    __shared__ T rowj[KB];           // row j of the panel (when it is one of this workgroup's rows)
     __shared__ T Tl[KB][KB + 1];     // compact-WY factor (workgroup 0)
     __shared__ T taus[KB];
     __shared__ int go;
@@ -112,20 +122,40 @@ __global__ __launch_bounds__(PN_THREADS) void panel_qr_kernel(int n, int k0, int
     const int nr = min(KB, m);  // reflectors of this panel
     const int i0 = wg * R;      // first panel row held here
     const int nl = min(R, m - i0);
-    for (int e = t; e < R * KB; e += PN_THREADS) {
-        const int li = e / KB, c = e % KB;
-        pt[li][c] = li < nl ? A[(long)(k0 + KB + i0 + li) * lda + k0 + c] : zero_<T>();
+    const int rg = t / KB, c = t % KB;
+    T pr[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int li = rg + PN_RG * i;
+        const T a = A[(long)(k0 + KB + i0 + min(li, nl - 1)) * lda + k0 + c];
+        pr[i] = pick(li < nl, a, zero_<T>());
     }
     if (wg == 0)
         for (int e = t; e < KB * (KB + 1); e += PN_THREADS) Tl[e / (KB + 1)][e % (KB + 1)] = zero_<T>();
-    __syncthreads();
-    const int rg = t / KB, c = t % KB;
     for (int j = 0; j < nr; ++j) {
+        const int lj = j - i0;  // row j's index in this workgroup (if 0 <= lj < nl)
+        // the pivot column to LDS, and row j (its owners: row group lj % PN_RG, slot lj / PN_RG)
+        if (c == j) {
+#pragma unroll
+            for (int i = 0; i < NI; ++i) xs[rg + PN_RG * i] = pr[i];
+        }
+        if (lj >= 0 && lj < nl && rg == lj % PN_RG) {
+            const int ij = lj / PN_RG;
+            T v = zero_<T>();
+#pragma unroll
+            for (int i = 0; i < NI; ++i) v = pick(i == ij, pr[i], v);
+            rowj[c] = v;
+        }
+        __syncthreads();
         // partials over this workgroup's rows below row j: s_c = sum conj(x_i) P[i][c]
-        T sacc = zero_<T>();
-        for (int li = rg; li < nl; li += PN_RG)
-            if (i0 + li > j) sacc += conj_(pt[li][j]) * pt[li][c];
-        red[rg][c] = sacc;
+        T s0 = zero_<T>(), s1 = zero_<T>();
+#pragma unroll
+        for (int i = 0; i < NI; i += 2) {
+            const int li = rg + PN_RG * i;
+            if (i0 + li > j && li < nl) s0 += conj_(xs[li]) * pr[i];
+            if (i0 + li + PN_RG > j && li + PN_RG < nl) s1 += conj_(xs[li + PN_RG]) * pr[i + 1];
+        }
+        red[rg][c] = s0 + s1;
         __syncthreads();
         const int par = j & 1;
         T* myrec = rec + ((long)par * P + wg) * (2 * KB);
@@ -136,8 +166,7 @@ __global__ __launch_bounds__(PN_THREADS) void panel_qr_kernel(int n, int k0, int
 #pragma unroll
                 for (int g = 0; g < PN_RG; g += 4) v += (red[g][t] + red[g + 1][t]) + (red[g + 2][t] + red[g + 3][t]);
             } else {
-                const int lj = j - i0;
-                v = (lj >= 0 && lj < nl) ? pt[lj][t - KB] : zero_<T>();
+                v = (lj >= 0 && lj < nl) ? rowj[t - KB] : zero_<T>();
             }
             // a single workgroup's record is the total itself (the exchange
             // would give 0 + v, which is exact)
@@ -182,13 +211,22 @@ __global__ __launch_bounds__(PN_THREADS) void panel_qr_kernel(int n, int k0, int
         double beta;
         house<T>(alpha, re_(tot[j]), tv, sc, beta);
         // columns c > j of rows i >= j: P[i][c] -= v_i g_c with g_c = conj(tau) (v^H P[:, c]),
-        // v^H P[:, c] = P[j][c] + conj(s) s_c
+        // v^H P[:, c] = P[j][c] + conj(s) s_c; column j itself becomes v (beta on row j)
         if (c > j) {
             const T gc = conj_(tv) * (tot[KB + c] + conj_(sc) * tot[c]);
-            for (int li = rg; li < nl; li += PN_RG) {
-                const int i = i0 + li;
-                if (i == j) pt[li][c] -= gc;
-                else if (i > j) pt[li][c] -= sc * pt[li][j] * gc;
+            const T sg = sc * gc;
+#pragma unroll
+            for (int i = 0; i < NI; ++i) {
+                const int gi = i0 + rg + PN_RG * i;
+                if (gi == j) pr[i] -= gc;
+                else if (gi > j) pr[i] -= xs[rg + PN_RG * i] * sg;
+            }
+        } else if (c == j) {
+#pragma unroll
+            for (int i = 0; i < NI; ++i) {
+                const int gi = i0 + rg + PN_RG * i;
+                if (gi == j) pr[i] = from_re<T>(beta);
+                else if (gi > j) pr[i] = sc * pr[i];
             }
         }
         // inner products with the earlier reflectors for the triangular factor,
@@ -198,13 +236,7 @@ __global__ __launch_bounds__(PN_THREADS) void panel_qr_kernel(int n, int k0, int
             if (t < j) Tl[j][t] = conj_(tot[KB + t]) + sc * conj_(tot[t]);
             else if (t == j) taus[j] = tv;
         }
-        __syncthreads();
-        for (int li = t; li < nl; li += PN_THREADS) {
-            const int i = i0 + li;
-            if (i == j) pt[li][j] = from_re<T>(beta);
-            else if (i > j) pt[li][j] = sc * pt[li][j];
-        }
-        __syncthreads();
+        __syncthreads();  // xs, rowj and tot are rewritten by the next column
     }
     // upper triangular factor by rows, T[l][j] = -tau_j sum_q T[l][q] vd_q(j)
     // (q = l .. j-1); row l only reads its own entries and the stored products
@@ -220,17 +252,18 @@ __global__ __launch_bounds__(PN_THREADS) void panel_qr_kernel(int n, int k0, int
     // R into the band (zeros below it), the reflectors into Vall (unit entry
     // explicit, zeros above) and into both V columns of the update buffer
     T* b3 = bw.buf3 + z * bw.sbuf;
-    for (int e = t; e < R * KB; e += PN_THREADS) {
-        const int li = e / KB, cc = e % KB;
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int li = rg + PN_RG * i;
         if (li >= nl) continue;
-        const int i = i0 + li;
-        const T pv = pt[li][cc];
-        const long row = k0 + KB + i;
-        A[row * lda + k0 + cc] = (i <= cc) ? pv : zero_<T>();
-        const T vv = cc < nr ? (i > cc ? pv : (i == cc ? from_re<T>(1.0) : zero_<T>())) : zero_<T>();
-        Vall[row * n + k0 + cc] = vv;
-        b3[(long)i * 3 * KB + cc] = vv;
-        b3[(long)i * 3 * KB + 2 * KB + cc] = vv;
+        const int gi = i0 + li;
+        const T pv = pr[i];
+        const long row = k0 + KB + gi;
+        A[row * lda + k0 + c] = (gi <= c) ? pv : zero_<T>();
+        const T vv = c < nr ? (gi > c ? pv : (gi == c ? from_re<T>(1.0) : zero_<T>())) : zero_<T>();
+        Vall[row * n + k0 + c] = vv;
+        b3[(long)gi * 3 * KB + c] = vv;
+        b3[(long)gi * 3 * KB + 2 * KB + c] = vv;
     }
     if (wg == 0) {
         if (t < KB) tau[k0 + t] = t < nr ? taus[t] : zero_<T>();
@@ -537,6 +570,8 @@ void hb2st(hipStream_t s, int n, T* A, int lda, long sA, int batch, double* d, d
 // blocks would let a block's own later progress answer its wait).  Items (pass block, matrix, slice) go to the
 // resident workgroups in order, so the earliest unfinished item never waits
 // for a later one.
+typedef __attribute__((address_space(3))) char* LdsPtr;
+
 template <typename T>
 struct Q2S {
     // passes per workgroup (q2_passes): the window takes 128 registers per lane
@@ -603,8 +638,10 @@ __global__ __launch_bounds__(64 * Q2S<T>::W) void q2_stream_kernel(int n, int J,
     constexpr int W = Q2S<T>::W;
     constexpr int NB = Q2NB<T>::v;
     constexpr int WR = KB + NB;  // window rows (the group's KB + NB - 1, and one more)
-    __shared__ T vs[W][NB][KB];
-    __shared__ T ts[W][NB];
+    // the coefficients of a wavefront's current group and of its next one,
+    // which direct global -> LDS loads bring in while the current one is applied
+    __shared__ T vs[2][W][NB][KB];
+    __shared__ T ts[2][W][NB];
     __shared__ int lp[W];  // groups finished by each wavefront's pass
     __shared__ int stop;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -632,6 +669,21 @@ __global__ __launch_bounds__(64 * Q2S<T>::W) void q2_stream_kernel(int n, int J,
         // Rows past the matrix are read as its last row: their coefficients
         // are zero, so they change nothing and are never stored; lanes past
         // the last column read column 0 and store nothing.
+        // stage group t's coefficients (NB x KB values, then NB taus, both
+        // contiguous) into buffer t & 1 of this wavefront: 16 bytes per lane
+        // per load for the coefficients, 4 for the taus
+        auto stage = [&](int t) {
+            const long grp = (long)j * Tmax + t;
+            const char* src = (const char*)(Vz + grp * NB * KB);
+            LdsPtr dst = (LdsPtr)(void*)&vs[t & 1][w][0][0];
+#pragma unroll
+            for (int i = 0; i < (int)(NB * KB * sizeof(T)) / 1024; ++i)
+                __builtin_amdgcn_global_load_lds((const void*)(src + i * 1024 + lane * 16), dst + i * 1024, 16, 0, 0);
+            static_assert(NB * sizeof(T) == 256, "taus: 4 bytes per lane");
+            __builtin_amdgcn_global_load_lds((const void*)((const char*)(tz + grp * NB) + lane * 4),
+                                             (LdsPtr)(void*)&ts[t & 1][w][0], 4, 0, 0);
+        };
+        stage(0);
         T x[WR];
 #pragma unroll
         for (int k = 0; k < NB; ++k) x[k] = Xc[(long)min(j * NB + 1 + k, n - 1) * ldx];
@@ -691,19 +743,19 @@ __global__ __launch_bounds__(64 * Q2S<T>::W) void q2_stream_kernel(int n, int J,
 #pragma unroll
                 for (int k = NB; k < WR; ++k) x[k] = Xc[(long)min(r0 + k, n - 1) * ldx];
             }
-            // the group's reflectors (reflector q contiguous, v_0 = 1, zeros past the matrix)
-            const long grp = (long)j * Tmax + t;
-            const T* Vg = Vz + grp * NB * KB;
-            wave_lds_sync();
-#pragma unroll
-            for (int e = 0; e < NB * KB / 64; ++e) (&vs[w][0][0])[e * 64 + lane] = Vg[e * 64 + lane];
-            if (lane < NB) ts[w][lane] = tz[grp * NB + lane];
-            wave_lds_sync();
+            // this group's coefficients (staged during the previous group) and the
+            // new rows have arrived; the next group's coefficients go to the other
+            // buffer, whose reads (the previous group's) are done
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_s_waitcnt(0);
+            asm volatile("" ::: "memory");
+            if (t + 1 < Ts) stage(t + 1);
             // an offset the compiler cannot see through, so that the coefficient
             // addresses are formed here rather than hoisted out of the group loop
             int vo = 0;
             asm volatile("" : "+v"(vo));
-            q2_reflect_all<T, WR>(x, &vs[w][0][0] + vo, &ts[w][0] + vo, std::make_integer_sequence<int, NB>{});
+            q2_reflect_all<T, WR>(x, &vs[t & 1][w][0][0] + vo, &ts[t & 1][w][0] + vo,
+                                  std::make_integer_sequence<int, NB>{});
             // the top 32 rows are final for this pass (all of the window after the last group)
             // (the last pass of the block writes its rows through to memory, for
             // the next block's workgroup)

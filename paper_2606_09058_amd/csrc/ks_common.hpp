@@ -160,6 +160,10 @@ struct Q2NB<cplx> {
     static constexpr int v = 16;
 };
 inline int q2_nb(bool complex_data) { return complex_data ? 16 : 32; }
+// Panel rows per workgroup of the stage-1 panel QR (held in registers: 32 per
+// thread of 512 for real data, 16 for complex; twice as many rows, in half as
+// many workgroups, made the two-stage reduction slower, 190 -> 223 ms at order 6656).
+__host__ __device__ constexpr int panel_rows(bool complex_data) { return complex_data ? 256 : 512; }
 // Passes (wavefronts) per workgroup of the stage-2 back-transform: two per
 // SIMD for real data; one for complex, whose window and coefficients need the
 // accumulation registers as well.
