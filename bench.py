@@ -91,6 +91,11 @@ def host_cpu():
     return "unknown"
 
 
+def progress(msg):
+    """One line per finished part of the run, on stderr (the JSON line stays alone on stdout)."""
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
 def cpu_baseline(p, sizes):
     """The oracle as it stands (Cholesky + cyclic Jacobi + back-substitution +
     Fermi bisection + density) timed on leading principal blocks of the same
@@ -360,6 +365,7 @@ def main():
     }
     # the other tridiagonalisation route on the same input (fewer steps)
     other = "twostage" if args.route == "onestage" else "onestage"
+    progress("%s route timed (%.3f s/solve); %s route" % (args.route, ms / 1e3, other))
     r2 = time_route(p, H, S, other, max(2, args.steps // 4), 1, args.stride, stream, warm=False)
     out["routes"] = {args.route: route_summary(r, None, p, flops), other: route_summary(r2, r, p, flops)}
     out["routes"][other]["steps"] = max(2, args.steps // 4)
@@ -372,10 +378,13 @@ def main():
     if args.workload == "kpoints16x1300":
         out["bloch_sum"] = bloch_sum_timing(plan, p, stream, args.steps)
     if not args.no_lowdin:
+        progress("Loewdin route")
         out["lowdin_route"] = lowdin_timing(p, H, S, eps, rho, stream, args.steps)
     if not args.no_mixed:
+        progress("FP64 vs mixed on the occupied window")
         out["precision_comparison"] = compare_precisions(p, H, S, eps, mu, args.steps)
     if not args.no_cpu_baseline:
+        progress("oracle on the host")
         out["cpu_baseline"] = cpu_baseline(p, [int(x) for x in args.cpu_sizes.split(",")])
     del plan, r, H, S, C, rho, edm
     torch.cuda.empty_cache()
@@ -383,6 +392,7 @@ def main():
         out["configs"] = {}
         for name in ("supercell6656", "noncollinear9984", "kpoints16x1300"):
             if name != args.workload:
+                progress("workload " + name)
                 out["configs"][name] = other_config(name, stream, args.stride)
                 torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
