@@ -97,8 +97,6 @@ constexpr int PN_RG = PN_THREADS / KB;  // row groups
 
 // c ? a : b by value, field by field (a select between aggregates through
 // their addresses would keep a register array in memory)
-__device__ inline double pick(bool c, double a, double b) { return c ? a : b; }
-__device__ inline cplx pick(bool c, cplx a, cplx b) { return mk(c ? a.x : b.x, c ? a.y : b.y); }
 
 template <typename T>
 __global__ __launch_bounds__(PN_THREADS) void panel_qr_kernel(int n, int k0, int P, int zoff, T* A, int lda, long sA,

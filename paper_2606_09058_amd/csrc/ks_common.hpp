@@ -107,6 +107,10 @@ __device__ inline double wave_sum(double v) {
 __device__ inline cplx wave_sum(cplx v) { return mk(wave_sum(v.x), wave_sum(v.y)); }
 __device__ inline double shfl_xor_(double v, int m) { return __shfl_xor(v, m, WAVE); }
 __device__ inline cplx shfl_xor_(cplx v, int m) { return mk(__shfl_xor(v.x, m, WAVE), __shfl_xor(v.y, m, WAVE)); }
+// Select field by field: a ternary on the whole struct keeps an array of it
+// out of registers.
+__device__ inline double pick(bool c, double a, double b) { return c ? a : b; }
+__device__ inline cplx pick(bool c, cplx a, cplx b) { return mk(c ? a.x : b.x, c ? a.y : b.y); }
 __device__ inline double wave_prod(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v *= __shfl_xor(v, o, WAVE);

@@ -70,6 +70,31 @@ __device__ inline V batched_sum(int i0, int step, int cnt, F f) {
     return acc;
 }
 
+// Origin of the tiling of column k's trailing matrix (rows and columns k+1 ..
+// n-1): k+1 rounded down to a 128-byte boundary of a stored row, so that the
+// row segment a workgroup reads starts on a cache line and no line is shared
+// by two workgroups (their L2s may be on different XCDs); the rows and columns
+// below k+1 inside the first tiles are masked.  The column kernels use the
+// same row blocks, so the partials of column k come in
+// cdiv(n - tile_origin(k - 1), 64) blocks.
+template <typename S>
+__host__ __device__ constexpr int tile_origin(int k) {
+    return (k + 1) & ~(int)(128 / sizeof(S) - 1);
+}
+template <typename S>
+__host__ __device__ constexpr int partial_blocks(int n, int k) {
+    return (n - tile_origin<S>(k - 1) + HETRD_TILE - 1) / HETRD_TILE;
+}
+
+// Workgroups (c, I) of the symmetric product with tiles (sch c .. ) on or
+// below the diagonal, I = 0 .. nt-1, c = 0 .. I / sch, numbered row by row:
+// the first index of tile row I (each of its workgroups leaves one x^H A x
+// partial there).
+__host__ __device__ inline int tri_index(int I, int sch) {
+    const int q = I / sch;
+    return I + sch * q * (q - 1) / 2 + q * (I - q * sch);
+}
+
 // Start of a panel: column k is already up to date (the trailing update of the
 // previous panel has been applied), so x = A[k.., k] and the per-workgroup
 // partial |x_{k+2..}|^2 is all the next reflector needs.  One wavefront per
@@ -83,9 +108,9 @@ __global__ __launch_bounds__(64) void colstart_kernel(int n, int k, int nb, cons
     T* x = hw.x + z * hw.sx;
     T* partA = hw.partPQ + ((k & 1) ? hw.sbuf : 0) + z * hw.spart;
     int t = threadIdx.x;
-    int r = k + blockIdx.x * 64 + t;
+    int r = tile_origin<S>(k - 1) + blockIdx.x * 64 + t;
     T c = zero_<T>();
-    if (r < n) {
+    if (r >= k && r < n) {
         c = widen(A[(long)r * lda + k]);  // column k below the diagonal (lower storage)
         if (r == k) c = from_re<T>(re_(c));
         x[r] = c;
@@ -169,12 +194,12 @@ __device__ inline T rows_lane_sum(const T (&r)[4], int lane) {
     T w[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-        T send = b5 ? r[i] : r[i + 2];
-        T keep = b5 ? r[i + 2] : r[i];
+        T send = pick(b5, r[i], r[i + 2]);
+        T keep = pick(b5, r[i + 2], r[i]);
         w[i] = keep + shfl_xor_(send, 32);
     }
-    T send = b4 ? w[0] : w[1];
-    T z = (b4 ? w[1] : w[0]) + shfl_xor_(send, 16);
+    T send = pick(b4, w[0], w[1]);
+    T z = pick(b4, w[1], w[0]) + shfl_xor_(send, 16);
     z += shfl_xor_(z, 8);
     z += shfl_xor_(z, 4);
     z += shfl_xor_(z, 2);
@@ -187,18 +212,18 @@ __device__ inline T rows_lane_sum(const T (&r)[8], int lane) {
     T w[4], u[2];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        T send = b5 ? r[i] : r[i + 4];
-        T keep = b5 ? r[i + 4] : r[i];
+        T send = pick(b5, r[i], r[i + 4]);
+        T keep = pick(b5, r[i + 4], r[i]);
         w[i] = keep + shfl_xor_(send, 32);
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-        T send = b4 ? w[i] : w[i + 2];
-        T keep = b4 ? w[i + 2] : w[i];
+        T send = pick(b4, w[i], w[i + 2]);
+        T keep = pick(b4, w[i + 2], w[i]);
         u[i] = keep + shfl_xor_(send, 16);
     }
-    T send = b3 ? u[0] : u[1];
-    T z = (b3 ? u[1] : u[0]) + shfl_xor_(send, 8);
+    T send = pick(b3, u[0], u[1]);
+    T z = pick(b3, u[1], u[0]) + shfl_xor_(send, 8);
     z += shfl_xor_(z, 4);
     z += shfl_xor_(z, 2);
     z += shfl_xor_(z, 1);
@@ -211,24 +236,24 @@ __device__ inline T rows_lane_sum(const T (&r)[16], int lane) {
     T w[8], u[4], v[2];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        T send = b5 ? r[i] : r[i + 8];
-        T keep = b5 ? r[i + 8] : r[i];
+        T send = pick(b5, r[i], r[i + 8]);
+        T keep = pick(b5, r[i + 8], r[i]);
         w[i] = keep + shfl_xor_(send, 32);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        T send = b4 ? w[i] : w[i + 4];
-        T keep = b4 ? w[i + 4] : w[i];
+        T send = pick(b4, w[i], w[i + 4]);
+        T keep = pick(b4, w[i + 4], w[i]);
         u[i] = keep + shfl_xor_(send, 16);
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-        T send = b3 ? u[i] : u[i + 2];
-        T keep = b3 ? u[i + 2] : u[i];
+        T send = pick(b3, u[i], u[i + 2]);
+        T keep = pick(b3, u[i + 2], u[i]);
         v[i] = keep + shfl_xor_(send, 8);
     }
-    T send = b2 ? v[0] : v[1];
-    T z = (b2 ? v[1] : v[0]) + shfl_xor_(send, 4);
+    T send = pick(b2, v[0], v[1]);
+    T z = pick(b2, v[1], v[0]) + shfl_xor_(send, 4);
     z += shfl_xor_(z, 2);
     z += shfl_xor_(z, 1);
     return z;
@@ -248,24 +273,37 @@ __device__ inline T rows_lane_sum(const T (&r)[16], int lane) {
 // over the row groups at the end (into pcol).  A diagonal tile is expanded
 // from its strict lower part.  Each workgroup also leaves its share of
 // x^H A x (2 Re x_I^H A_IJ x_J off the diagonal, x_I^H A_II x_I on it) in
-// pvav, from which the next kernel gets v^H A v and so the W-column
+// pvav (at tri_index(I, SCH) + c: the workgroups above the diagonal leave
+// nothing), from which the next kernel gets v^H A v and so the W-column
 // correction without a pass over w.
 constexpr int ST = HETRD_TILE;  // tile edge
+
 template <typename T, typename S>
 struct Sy {
-    static constexpr int R = sizeof(T) == 8 ? 8 : 4;  // tile rows per thread
-    static constexpr int NG = ST / R;                  // row groups = wavefronts
-    static constexpr int THREADS = 64 * NG;            // 512 or 1024
-    // slots of the register ring of tiles: three (two tiles in flight) for an
-    // FP64 trailing matrix, five (four in flight: the same bytes and
-    // registers) when it is stored in FP32
+    static constexpr int R = 8;             // tile rows per thread
+    static constexpr int NG = ST / R;       // row groups = wavefronts
+    static constexpr int THREADS = 64 * NG; // 512
+    // rows per load step: the thread's whole share of a tile for real data,
+    // half of it for complex data, so that a step's values and products fit
+    // beside the steps in flight within 128 registers (two workgroups per CU:
+    // one's loads cover the other's final reductions)
+    static constexpr int RS = is_cplx<T>::value ? 4 : 8;
+    static constexpr int NSUB = R / RS;  // steps per tile
+    // complex data reduce each step's row sums over the lanes at once (one
+    // accumulator per lane and step of a tile instead of one per row); real
+    // data keep a row's sum in registers across the tiles and reduce it once
+    // at the end (per-step reductions measured 15-25% slower there)
+    static constexpr bool LSTEP = is_cplx<T>::value;
+    // slots of the register ring of steps: three (two steps in flight) with
+    // FP64 storage, five (four in flight: the same bytes and registers) when
+    // the trailing matrix is stored in FP32
     static constexpr int NSLOT = sizeof(S) < sizeof(T) ? 5 : 3;
 };
 
 template <typename T, typename S, int SCH>
 __global__ __launch_bounds__((Sy<T, S>::THREADS), 4) void symv_kernel(int n, int k, int j, int nb, const S* A, int lda,
                                                           long sA, int nA, int nt, int nch, HetrdWork<T> hw) {
-    constexpr int SY_R = Sy<T, S>::R, NG = Sy<T, S>::NG;
+    constexpr int SY_R = Sy<T, S>::R, NG = Sy<T, S>::NG, RS = Sy<T, S>::RS, NSUB = Sy<T, S>::NSUB;
     __shared__ T vI[ST], yrow[ST];
     __shared__ T cred[SCH][NG][ST];
     __shared__ T part[NG][64];
@@ -282,101 +320,121 @@ __global__ __launch_bounds__((Sy<T, S>::THREADS), 4) void symv_kernel(int n, int
         return;
     }
     double* pvav = hw.pvav + z * hw.spvav;
-    if (J0 > I) {
-        if (t == 0) pvav[(long)I * nch + c] = 0.0;
-        return;
-    }
+    if (J0 > I) return;
     A += z * sA;
     const T* x = hw.x + z * hw.sx;
     T* prow = hw.prow + z * hw.sprow;
     T* pcol = hw.pcol + z * hw.spcol;
     const int ntile = min(J0 + SCH, I + 1) - J0;
-    const int o = k + 1;  // first trailing row / column
+    const int o = k + 1;                   // first trailing row / column
+    const int oa = tile_origin<S>(k);      // first row / column of the tiles
     // the row group is the wavefront index: uniform, so that the row addresses
     // stay scalar and every load takes one 32-bit lane offset
     const int col = t & 63, g = __builtin_amdgcn_readfirstlane(t >> 6);
-    const int r0 = o + I * ST + g * SY_R;  // first row of this thread
-    // The workgroup's tiles pass through a register ring of NSLOT slots (as
-    // stored: FP64, or FP32 in the mixed form): NSLOT - 1 tiles' loads stay
-    // in flight while one is used.  The tile loop is unrolled over SCH so that a
-    // tile's slot is fixed at compile time (moving a register whose load is in
-    // flight would wait for it), every load is unconditional (indices clamped
-    // into the matrix, the value replaced by zero outside it; a workgroup that
-    // reaches the diagonal re-reads its last tile in place of the tiles it does
-    // not have), so that each wait counts exactly the loads still needed, and
-    // x_I is read from LDS so that the ring fits the register budget.
-    constexpr int NSLOT = Sy<T, S>::NSLOT, PD = NSLOT - 1;
-    S b[NSLOT][SY_R];
-    T xv[NSLOT];
+    const int r0 = oa + I * ST + g * SY_R;  // first row of this thread
+    // The workgroup's tiles pass, RS rows per thread at a time (a step),
+    // through a register ring of NSLOT slots (as stored: FP64, or FP32 in the
+    // mixed form): NSLOT - 1 steps' loads stay in flight while one is used.
+    // The step loop is unrolled so that a step's slot is fixed at compile time
+    // (moving a register whose load is in flight would wait for it), every
+    // load is unconditional (indices clamped into the matrix, the value
+    // replaced by zero outside it; a workgroup that reaches the diagonal
+    // re-reads its last tile in place of the tiles it does not have), so that
+    // each wait counts exactly the loads still needed.
+    constexpr int NSLOT = Sy<T, S>::NSLOT, PD = NSLOT - 1, NSTEP = SCH * NSUB;
+    S b[NSLOT][RS];
+    T xv[NSLOT];  // x on the thread's column of the tiles in use or in flight
     auto xof = [&](int gi) -> T {
         const T v = x[min(gi, n - 1)];
-        return gi < n ? v : zero_<T>();
+        return (gi >= o && gi < n) ? v : zero_<T>();
     };
-    auto load_tile = [&](int J, S(&bt)[SY_R]) {
-        const int gc = o + J * ST + col;
+    auto load_step = [&](int J, int hs, S(&bt)[RS]) {
+        const int gc = oa + J * ST + col;
+        const bool cin = gc >= o && gc < n;
         const unsigned off = (unsigned)min(gc, n - 1) * (unsigned)sizeof(S);
 #pragma unroll
-        for (int q = 0; q < SY_R; ++q) {
-            const char* row = (const char*)(A + (long)min(r0 + q, n - 1) * lda);
+        for (int q = 0; q < RS; ++q) {
+            const int r = r0 + hs * RS + q;
+            const char* row = (const char*)(A + (long)min(r, n - 1) * lda);
             const S v = *(const S*)(row + off);
-            bt[q] = (r0 + q < n && gc < n) ? v : zero_<S>();
+            bt[q] = (cin && r >= o && r < n) ? v : zero_<S>();
         }
     };
     const int Jlast = J0 + ntile - 1;
-    // x_I is loaded first and stored to LDS after the tile loads are issued,
-    // so that the barrier waits for it alone
-    const T xI = xof(o + I * ST + (t & (ST - 1)));
+    // x_I is loaded first and stored to LDS after the first steps' loads are
+    // issued, so that the barrier waits for it alone (a wait counts the loads
+    // in the order they were issued)
+    const T xI = xof(oa + I * ST + (t & (ST - 1)));
+    // (the loads of a step are issued by code written out at both places: a
+    // helper taking the step as an argument kept the ring out of registers
+    // until after unrolling and cost 14-38 registers)
 #pragma unroll
-    for (int p = 0; p < PD; ++p) {
-        if (p < SCH) {
-            load_tile(min(J0 + p, Jlast), b[p]);
-            xv[p] = xof(o + (J0 + p) * ST + col);
+    for (int h = 0; h < PD; ++h) {
+        if (h < NSTEP) {
+            load_step(min(J0 + h / NSUB, Jlast), h % NSUB, b[h % NSLOT]);
+            if (h % NSUB == 0) xv[(h / NSUB) % NSLOT] = xof(oa + (J0 + h / NSUB) * ST + col);
         }
     }
     if (t < ST) vI[t] = xI;
     __syncthreads();
-    T racc[SY_R];
+    // with LSTEP the row sums of each step are reduced over the lanes at once
+    // (lanes LPR q .. LPR q + LPR - 1 end with row q of the step), so one
+    // accumulator per lane and step of a tile carries them across the tiles;
+    // otherwise one accumulator per row of the thread
+    constexpr bool LSTEP = Sy<T, S>::LSTEP;
+    constexpr int LPR = 64 / (LSTEP ? RS : SY_R), NACC = LSTEP ? NSUB : SY_R;
+    T racc[NACC];
 #pragma unroll
-    for (int q = 0; q < SY_R; ++q) racc[q] = zero_<T>();
+    for (int q = 0; q < NACC; ++q) racc[q] = zero_<T>();
     double vav = 0.0;
+    T cs = zero_<T>();  // column sums of the current tile
 #pragma unroll
-    for (int s = 0; s < SCH; ++s) {
-        // x_I is re-read from LDS for every tile rather than kept in registers
+    for (int h = 0; h < NSTEP; ++h) {
+        const int s = h / NSUB, hs = h % NSUB, J = J0 + s;
+        // x_I is re-read from LDS at every step rather than kept in registers
         asm volatile("" ::: "memory");
-        const int J = J0 + s;
-        if (s + PD < SCH) {  // constant once the loop is unrolled
-            load_tile(min(J + PD, Jlast), b[(s + PD) % NSLOT]);
-            xv[(s + PD) % NSLOT] = xof(o + (J + PD) * ST + col);
+        if (h + PD < NSTEP) {  // constant once the loop is unrolled
+            const int h2 = h + PD, s2 = h2 / NSUB;
+            load_step(min(J0 + s2, Jlast), h2 % NSUB, b[h2 % NSLOT]);
+            if (h2 % NSUB == 0) xv[s2 % NSLOT] = xof(oa + (J0 + s2) * ST + col);
         }
         if (s < ntile) {
-            const S(&bc)[SY_R] = b[s % NSLOT];
+            const S(&bc)[RS] = b[h % NSLOT];
             const T xc = xv[s % NSLOT];
-            T cs = zero_<T>();
-            if (J != I) {
+            if (hs == 0) cs = zero_<T>();
+            T rp[RS];
 #pragma unroll
-                for (int q = 0; q < SY_R; ++q) {
-                    const T a = widen(bc[q]);
-                    racc[q] += a * xc;
-                    cs += conj_(a) * vI[g * SY_R + q];
-                }
-            } else {
-#pragma unroll
-                for (int q = 0; q < SY_R; ++q) {
-                    const int rl = g * SY_R + q;
-                    const T a = widen(bc[q]);
-                    const T xq = vI[rl];
-                    if (col <= rl) racc[q] += a * xc;
+            for (int q = 0; q < RS; ++q) {
+                const int rl = g * SY_R + hs * RS + q;
+                const T a = widen(bc[q]);
+                const T xq = vI[rl];
+                if (J != I) {
+                    if constexpr (LSTEP) rp[q] = a * xc;
+                    else racc[hs * RS + q] += a * xc;
+                    cs += conj_(a) * xq;
+                } else {
+                    if constexpr (LSTEP) rp[q] = pick(col <= rl, a * xc, zero_<T>());
+                    else if (col <= rl) racc[hs * RS + q] += a * xc;
                     if (col < rl) cs += conj_(a) * xq;
                     if (col == rl) vav += re_(a) * abs2_(xq);
                 }
             }
-            vav += 2.0 * re_(conj_(xc) * cs);
-            cred[s][g][col] = cs;
+            if constexpr (LSTEP) racc[hs] += rows_lane_sum<T>(rp, col);
+            if (hs == NSUB - 1) {
+                vav += 2.0 * re_(conj_(xc) * cs);
+                cred[s][g][col] = cs;
+            }
         }
     }
-    const T rsum = rows_lane_sum<T>(racc, col);
-    constexpr int LPR = 64 / SY_R;  // lanes per row after the reduction
-    if (col % LPR == 0) yrow[g * SY_R + col / LPR] = rsum;
+    if constexpr (LSTEP) {
+        if (col % LPR == 0) {
+#pragma unroll
+            for (int hs = 0; hs < NSUB; ++hs) yrow[g * SY_R + hs * RS + col / LPR] = racc[hs];
+        }
+    } else {
+        const T rsum = rows_lane_sum<T>(racc, col);
+        if (col % LPR == 0) yrow[g * SY_R + col / LPR] = rsum;
+    }
     vav = wave_sum(vav);
     if (col == 0) redd[g] = vav;
     __syncthreads();  // publishes yrow, cred and the x^H A x partials
@@ -400,7 +458,7 @@ __global__ __launch_bounds__((Sy<T, S>::THREADS), 4) void symv_kernel(int n, int
     if (t == 0) {
         double vsum = 0.0;
         for (int q = 0; q < NG; ++q) vsum += redd[q];
-        pvav[(long)I * nch + c] = vsum;
+        pvav[tri_index(I, SCH) + c] = vsum;
     }
 }
 
@@ -438,6 +496,10 @@ template <typename T>
 struct Wc {
     static constexpr int NW = is_cplx<T>::value ? 8 : 16;
     static constexpr int MAXU = HETRD_NB / NW;  // panel columns per wavefront
+    // loads in flight per lane in the reduction of z's partials: the whole
+    // reduction is one round of loads up to 16 (real) or 32 (complex) per
+    // lane, i.e. up to 256 tile rows of partials
+    static constexpr int ZU = is_cplx<T>::value ? 32 : 16;
     static_assert(2 * HETRD_NB <= 64 && HETRD_NB % NW == 0 && NW % 4 == 0, "panel width");
 };
 template <typename T, typename S>
@@ -464,8 +526,9 @@ __global__ __launch_bounds__(64 * Wc<T>::NW) void wcol_kernel(int n, int k, int 
     const long ldp = 1 + 2 * nb;
     const T* partA = hw.partPQ + ((k & 1) ? hw.sbuf : 0) + z * hw.spart;
     T* partN = hw.partPQ + ((k & 1) ? 0 : hw.sbuf) + z * hw.spart;
-    const int r = k + 1 + I * WC_ROWS + lr;
-    const bool in = r < n;
+    const int oa = tile_origin<S>(k);  // first row of the row blocks (a tile row each)
+    const int r = oa + I * WC_ROWS + lr;
+    const bool in = r > k && r < n;
     // every thread: its row's x and a_1 entries (column k+1 before the panel's
     // updates) and panel entries for columns i = pp, pp + WC_NW, ... < j
     T xr = zero_<T>(), ar = zero_<T>();
@@ -482,9 +545,10 @@ __global__ __launch_bounds__(64 * Wc<T>::NW) void wcol_kernel(int n, int k, int 
         wr[u] = ok ? VWt[(long)(nb + i) * n + r] : zero_<T>();
     }
     if (pp == 1) {
-        // z_{k+1} (row 0 of tile row 0)
-        const T y0 = prow[0];
-        T ys = batched_sum<4, T>(1 + lr, 64, nt, [&](int I2) { return pcol[(long)I2 * ST]; });
+        // z_{k+1} (row k+1 - oa of tile row 0)
+        const int lk = k + 1 - oa;
+        const T y0 = prow[lk];
+        T ys = batched_sum<4, T>(1 + lr, 64, nt, [&](int I2) { return pcol[(long)I2 * ST + lk]; });
         ys = wave_sum(ys);
         if (lr == 0) sh[2] = y0 + ys;
     } else if (pp == 2) {
@@ -540,11 +604,11 @@ __global__ __launch_bounds__(64 * Wc<T>::NW) void wcol_kernel(int n, int k, int 
         const int nc = I / sch + 1;
         const T* pr = prow + (long)I * nch * ST + lr;
         const T* pc = pcol + ((long)I * nt + I + 1 - nc) * ST + lr;
-        zr = batched_sum<8, T>(pp, WC_NW, nc + nt - I - 1,
+        zr = batched_sum<Wc<T>::ZU, T>(pp, WC_NW, nc + nt - I - 1,
                                [&](int f) { return f < nc ? pr[(long)f * ST] : pc[(long)f * ST]; });
     }
     // x^H A x from the product's partials (same order in every workgroup)
-    double va = batched_sum<4, double>(t, 64 * WC_NW, nt * nch, [&](int f) { return pvav[f]; });
+    double va = batched_sum<4, double>(t, 64 * WC_NW, tri_index(nt, sch), [&](int f) { return pvav[f]; });
     va = wave_sum(va);
     if (lr == 0) red[pp] = va;
     __syncthreads();  // publishes sh, shd, sp, sq, vk, wk, red
@@ -645,7 +709,7 @@ __global__ void last_diag_kernel(int n, const S* A, int lda, long sA, double* d)
 template <typename T, typename S>
 void symv_launch(hipStream_t s, int sch, int n, int k, int j, const S* A, int lda, long sA, int B, int nA,
                  const HetrdWork<T>& w, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
-    const int m = n - k - 1, nt = cdiv(m, ST), nch = cdiv(nt, sch), nb = HETRD_NB;
+    const int nt = cdiv(n - tile_origin<S>(k), ST), nch = cdiv(nt, sch), nb = HETRD_NB;
     // one workgroup column beyond the tiles' for the panel products
     const dim3 grid(nch + 1, nt, B), block(Sy<T, S>::THREADS);
     if (ev0) {
@@ -694,14 +758,14 @@ void hetrd(hipStream_t s, int n, S* A, int lda, long sA, int batch, double* d, d
             fill_zero<T>(s, w.VW, w.sVW * B);
             fill_zero<T>(s, w.WV, w.sVW * B);
         }
-        hipLaunchKernelGGL((colstart_kernel<T, S>), dim3(cdiv(n - k0, 64), 1, B), dim3(64), 0, s, n, k0, nb, A, lda,
-                           sA, w);
+        hipLaunchKernelGGL((colstart_kernel<T, S>), dim3(partial_blocks<S>(n, k0), 1, B), dim3(64), 0, s, n, k0, nb,
+                           A, lda, sA, w);
         for (int j = 0; j < jb; ++j) {
             int k = k0 + j;
             int m = n - k - 1;
             const int sch = w.sch_for(k);
-            int nt = cdiv(m, ST), nch = cdiv(nt, sch);
-            int nA = cdiv(n - k, WC_ROWS);  // workgroups that wrote the partials of column k
+            int nt = cdiv(n - tile_origin<S>(k), ST), nch = cdiv(nt, sch);
+            int nA = partial_blocks<S>(n, k);  // workgroups that wrote the partials of column k
             const bool smp = w.prof && w.prof->sample();
             hipEvent_t e0 = smp ? w.prof->take() : nullptr;
             hipEvent_t e1 = smp ? w.prof->take() : nullptr;
@@ -709,7 +773,7 @@ void hetrd(hipStream_t s, int n, S* A, int lda, long sA, int batch, double* d, d
             // algorithmic bytes of a Hermitian matrix-vector product: the lower
             // triangle once, in the storage precision
             if (smp) w.prof->push(PROF_HEMV, e0, e1, (double)sizeof(S) * m * (m + 1) / 2.0 * B);
-            hipLaunchKernelGGL((wcol_kernel<T, S>), dim3(cdiv(m, WC_ROWS), 1, B), dim3(64 * Wc<T>::NW), 0, s, n, k, j, nb,
+            hipLaunchKernelGGL((wcol_kernel<T, S>), dim3(nt, 1, B), dim3(64 * Wc<T>::NW), 0, s, n, k, j, nb,
                                (int)(j + 1 < jb), A, lda, sA, nt, nch, sch, nA, d, e, tau, w);
         }
         long tot = (long)n * jb;
@@ -778,7 +842,7 @@ int hetrd_tune(hipStream_t s, int n, T* A, int lda, long sA, int batch, double* 
             for (int c0 = 0; c0 < nc; ++c0) {
                 const int c = (c0 + round) % nc;
                 const int k = ks_[q];
-                const int nA = cdiv(n - k, WC_ROWS);
+                const int nA = partial_blocks<T>(n, k);
                 symv_launch<T, T>(s, cand[c], n, k, 0, A, lda, sA, batch, nA, w);  // warm
                 (void)hipEventRecord(e0, s);
                 for (int r = 0; r < reps; ++r)

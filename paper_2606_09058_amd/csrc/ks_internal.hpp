@@ -107,7 +107,7 @@ struct HetrdWork {
                     // per column parity, sbuf apart
     T* prow;        // nt x cdiv(nt, HETRD_SCH_MIN) x HETRD_TILE, nt = cdiv(n, HETRD_TILE): row partials
     T* pcol;        // nt x nt x HETRD_TILE                                           column partials
-    double* pvav;   // nt x cdiv(nt, HETRD_SCH_MIN) partial v^H A v
+    double* pvav;   // partial x^H A x of the product's workgroups (at most nt x cdiv(nt, HETRD_SCH_MIN))
     T* pq;          // 5 + 2 NB: x_{k+1}, unused, raw W^H x, V^H x of the current column,
                     // then the reflector's s, tau and beta
     void* VWlo = nullptr;  // mixed form: VW and WV in FP32 for the trailing update
