@@ -13,6 +13,9 @@ route; the line also carries the other route, and (unless --no-configs) the
 other two sizes of the metric: the 2N = 9984 spinor problem and the 16 x 1300
 k-point batch (both routes, FP64 vs mixed on the occupied window, graph vs
 eager launches for the batch), at reduced step counts stated in the line.
+A complex workload whose overlap is real (the spinor workload, at the Gamma
+point) is solved with KS_PLAN_REAL_OVERLAP (the factor of S in real
+arithmetic); the line also times the complex-factor route on it.
 
 With --counter-workload it instead runs the short fixed workload that the
 memory-traffic counters are taken on (one rocprofv3 --pmc run per counter):
@@ -44,6 +47,17 @@ WORKLOADS = {
 }
 # tridiagonalisation routes: one-stage Householder, or dense -> band -> tridiagonal
 ROUTE_FLAGS = {"onestage": 0, "twostage": 8}
+# complex workloads whose overlap is real (the spinor workloads at the Gamma
+# point) are solved with KS_PLAN_REAL_OVERLAP unless --complex-overlap; the
+# line also times the complex-factor route for comparison
+REAL_OVERLAP = {"use": True}
+
+
+def overlap_flags(p):
+    """KS_PLAN_REAL_OVERLAP (16) for a complex problem with a real S."""
+    import numpy as np
+    real_s = np.iscomplexobj(p.H) and not np.any(np.imag(p.S))
+    return 16 if (real_s and REAL_OVERLAP["use"]) else 0
 DEFAULT_ROUTE = "onestage"
 
 
@@ -151,7 +165,8 @@ def counter_workload(p):
     torch.cuda.synchronize()
     print("copy_bytes", COPY_BYTES, flush=True)
     del x, y
-    plan = ks.Plan(p.n, batch=p.batch, complex=np.iscomplexobj(p.H), noncollinear=p.nsp == 2)
+    plan = ks.Plan(p.n, batch=p.batch, complex=np.iscomplexobj(p.H), noncollinear=p.nsp == 2,
+                   flags=overlap_flags(p))
     H = torch.from_numpy(p.H).cuda()
     S = torch.from_numpy(p.S.astype(p.H.dtype)).cuda()
     eps = torch.empty(plan._vshape(), dtype=torch.float64, device="cuda")
@@ -166,7 +181,7 @@ def phase_dict(prof, steps):
     return {nm: prof.phase_ms[i] / steps for i, nm in enumerate(names)}
 
 
-def time_route(p, H, S, route, steps, warmup, stride, stream, graph=False, warm=True, tag=""):
+def time_route(p, H, S, route, steps, warmup, stride, stream, graph=False, warm=True, tag="", overlap=None):
     """W warm-up and K timed solves (gevd, all eigenvectors, + density) on one
     plan of the given route; events on the plan's stream.  Returns the timings,
     the sampled symmetric-product launches (one-stage route), the phase times
@@ -175,6 +190,7 @@ def time_route(p, H, S, route, steps, warmup, stride, stream, graph=False, warm=
     import torch
     from paper_2606_09058_amd import ks
     flags = ks.KS_PLAN_AUTOTUNE | ROUTE_FLAGS[route] | (ks.KS_PLAN_GRAPH if graph else 0)
+    flags |= overlap_flags(p) if overlap is None else overlap
     with torch.cuda.stream(stream):
         plan = ks.Plan(p.n, batch=p.batch, complex=np.iscomplexobj(p.H), noncollinear=p.nsp == 2, stream=stream,
                        flags=flags)
@@ -277,9 +293,12 @@ def main():
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the other sizes of the metric (2N = 9984 spinor, 16 x 1300 k-points)")
     ap.add_argument("--graph", action="store_true", help="plan with KS_PLAN_GRAPH (capture once, replay)")
+    ap.add_argument("--complex-overlap", action="store_true",
+                    help="factor a real overlap of a complex problem in complex arithmetic too")
     ap.add_argument("--counter-workload", action="store_true",
                     help="run the fixed workload of the rocprofv3 memory-counter runs and exit")
     args = ap.parse_args()
+    REAL_OVERLAP["use"] = not args.complex_overlap
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: a single matrix of this solve does not shard, and "
@@ -342,7 +361,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload + ": " + WORKLOADS[args.workload], "form": "fp64",
                    "route": args.route, "order": p.order, "batch": p.batch, "electrons": p.n_electrons,
-                   "kT": p.kT, "eigenvectors": p.order, "occupied_window": m_occ, "graph": bool(args.graph)},
+                   "kT": p.kT, "eigenvectors": p.order, "occupied_window": m_occ, "graph": bool(args.graph),
+                   "overlap": "real" if overlap_flags(p) else "as given"},
         "tflops": flops / (ms * 1e-3) / 1e12,
         "tflops_frac_fp64_peak": flops / (ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
         "nominal_flops": flops,
@@ -369,6 +389,13 @@ def main():
     r2 = time_route(p, H, S, other, max(2, args.steps // 4), 1, args.stride, stream, warm=False)
     out["routes"] = {args.route: route_summary(r, None, p, flops), other: route_summary(r2, r, p, flops)}
     out["routes"][other]["steps"] = max(2, args.steps // 4)
+    if overlap_flags(p):
+        progress("complex-factor route")
+        r3 = time_route(p, H, S, "onestage", max(2, args.steps // 4), 1, args.stride, stream, warm=False,
+                        overlap=0)
+        out["routes"]["onestage_complex_factor"] = route_summary(r3, r, p, flops)
+        out["routes"]["onestage_complex_factor"]["steps"] = max(2, args.steps // 4)
+        del r3
     sy = r if args.route == "onestage" else r2
     out["roofline"] = symv_roofline(sy["prof"], measured_traffic(args.workload))
     out["roofline"]["route"] = "onestage"
@@ -414,6 +441,10 @@ def other_config(name, stream, stride, steps=3):
     runs = {}
     for route in ("onestage", "twostage"):
         runs[route] = time_route(p, H, S, route, steps, 1, stride, stream, warm=route == "onestage", tag=name + " ")
+    if overlap_flags(p):
+        runs["onestage_complex_factor"] = time_route(p, H, S, "onestage", 2, 1, stride, stream, warm=False,
+                                                     tag=name + " complex factor ", overlap=0)
+        res["overlap"] = "real"
     ref = runs["onestage"]
     m_occ = occupied_count(ref["occ"], p)
     flops = p.batch * nominal_flops(p.order, p.order, m_occ, cplx, p.n)
@@ -538,7 +569,7 @@ def compare_precisions(p, H, S, eps_all, mu, steps, buffer_ha=0.4):
     for form, prec, sweeps, flags in (("fp64", ks.KS_FP64, None, 0), ("fp64_twostage", ks.KS_FP64, None, 8),
                                       ("mixed", ks.KS_MIXED, 2, 0), ("mixed1", ks.KS_MIXED, 1, 0)):
         plan = ks.Plan(p.n, batch=p.batch, complex=cplx, noncollinear=p.nsp == 2, precision=prec,
-                       flags=ks.KS_PLAN_AUTOTUNE | flags)
+                       flags=ks.KS_PLAN_AUTOTUNE | flags | overlap_flags(p))
         if sweeps is not None:
             plan.set_refinement(sweeps)
         eps = torch.empty(plan._vshape(), dtype=torch.float64, device="cuda")

@@ -116,10 +116,23 @@ enum { KS_PLAN_GRAPH = 1u,
         * other across workgroups, so a plan asks for at most one workgroup per
         * compute unit per waiting launch (orders up to 512 times the compute
         * units, 256 times for complex data, else KS_ERR_NOT_SUPPORTED); a wait
-        * that never completes gives up after seconds with KS_ERR_NO_CONVERGENCE
-        * (info -1 in the band reduction, -2 in the bulge chasing, -3 in the
-        * chasing reflectors' back-transform). */
-       KS_PLAN_TWOSTAGE = 8u };
+        * that never completes (in the band reduction, the bulge chasing or the
+        * chasing reflectors' back-transform) gives up after seconds with
+        * KS_ERR_NO_CONVERGENCE. */
+       KS_PLAN_TWOSTAGE = 8u,
+       /* KS_PLAN_REAL_OVERLAP: on a KS_COMPLEX128 plan, S (still passed in
+        * complex storage) is real, as the overlap of real orbitals at the
+        * Gamma point is, also in the spinor form diag(S, S) of Sec. 3.2 whose
+        * H carries the complex spin-orbit blocks.  The Cholesky factor and its
+        * inverse are then formed in real arithmetic, and the products with
+        * them (the reduction L^-1 H L^-H, the Cholesky form of Sec. 3.1 Part
+        * 2-3, and C = L^-H X, Part 2-5) take the complex matrices as real ones of twice the
+        * columns: two real products per complex one instead of three.  An
+        * imaginary part other than zero in the lower triangle of S (diagonal
+        * included) gives KS_ERR_INVALID_ARG with info = its 1-based row.  No
+        * effect on KS_REAL64 plans; the Loewdin route ignores it.  Results
+        * equal the complex route's up to rounding. */
+       KS_PLAN_REAL_OVERLAP = 16u };
 enum { KS_REUSE_S = 1u };                            /* ks_gevd flags                */
 
 typedef struct ks_plan ks_plan; /* opaque: workspace, cached Cholesky factor, info */
@@ -160,7 +173,9 @@ void ks_plan_destroy(ks_plan* plan);
  *           first, paper Sec. 5, cycles 2 onwards reuse the overlap work).
  * Device failures: KS_ERR_NOT_POSDEF (info = failing column, 1-based; under
  * KS_PLAN_LOWDIN the number of eigenvalues of S that are <= 0),
- * KS_ERR_NONFINITE, KS_ERR_NO_CONVERGENCE via ks_plan_get_info. */
+ * KS_ERR_NONFINITE, KS_ERR_NO_CONVERGENCE, and under KS_PLAN_REAL_OVERLAP
+ * KS_ERR_INVALID_ARG (info = row of an imaginary entry of S) via
+ * ks_plan_get_info. */
 ks_status ks_gevd(ks_plan* plan, const void* H, const void* S, double* eps, void* C,
                   int32_t il, int32_t iu, uint32_t flags);
 
@@ -369,8 +384,10 @@ ks_status ks_plan_get_graph_stats(ks_plan* plan, int64_t* captures, int64_t* rep
 
 /* Synchronize the plan's stream and read its info word: 0 if no device failure
  * was recorded since the last call, else the failing Cholesky column (>0) for
- * KS_ERR_NOT_POSDEF, or -status for other device failures.  Clears the word.
- * Returns KS_OK or the status of the recorded failure. */
+ * KS_ERR_NOT_POSDEF, the row (>0) of an imaginary overlap entry for
+ * KS_ERR_INVALID_ARG under KS_PLAN_REAL_OVERLAP, or -status for other device
+ * failures.  Clears the word.  Returns KS_OK or the status of the recorded
+ * failure. */
 ks_status ks_plan_get_info(ks_plan* plan, int32_t* info);
 
 /* Static, never NULL. */

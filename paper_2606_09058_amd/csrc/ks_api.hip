@@ -123,7 +123,9 @@ bool desc_valid(const ks_plan_desc* d) {
     long order = (long)d->n * (d->spin == KS_NONCOLLINEAR ? 2 : 1);
     if (order > 60000) return false;
     if (d->ld_h < order || d->ld_s < d->n) return false;
-    if (d->flags & ~(uint32_t)(KS_PLAN_GRAPH | KS_PLAN_AUTOTUNE | KS_PLAN_LOWDIN | KS_PLAN_TWOSTAGE)) return false;
+    if (d->flags & ~(uint32_t)(KS_PLAN_GRAPH | KS_PLAN_AUTOTUNE | KS_PLAN_LOWDIN | KS_PLAN_TWOSTAGE |
+                               KS_PLAN_REAL_OVERLAP))
+        return false;
     return true;
 }
 
@@ -466,6 +468,17 @@ template <typename T>
 void apply_linv_h(ks_plan* p, const T* Li, const T* X, long sX, int ncols, T* C) {
     const int n = p->d.n, nsp = p->nsp, B = p->d.batch, ldh = p->d.ld_h, order = p->order;
     const long sL = (long)n * n, sH = (long)order * ldh;
+    if constexpr (is_cplx<T>::value) {
+        if (p->d.flags & KS_PLAN_REAL_OVERLAP) {
+            // real Linv: X and C as real matrices of interleaved (re, im) columns
+            const double* Lr = (const double*)Li;
+            for (int b = 0; b < B; ++b)
+                gemm<double>(p->s, OP_T, OP_N, n, 2 * ncols, n, 1.0, Lr + b * sL, n, 0,
+                             (const double*)(X + b * sX), 2 * ncols, 2L * n * ncols, 0.0, (double*)(C + b * sH),
+                             2 * ldh, 2L * n * ldh, nsp, nullptr, 0, UPLO_FULL, nullptr, TRI_A_UPPER);
+            return;
+        }
+    }
     if (nsp == 1) {
         gemm<T>(p->s, OP_C, OP_N, n, ncols, n, 1.0, Li, n, sL, X, ncols, sX, 0.0, C, ldh, sH, B, nullptr, 0,
                 UPLO_FULL, nullptr, TRI_A_UPPER);
@@ -474,6 +487,42 @@ void apply_linv_h(ks_plan* p, const T* Li, const T* X, long sX, int ncols, T* C)
             gemm<T>(p->s, OP_C, OP_N, n, ncols, n, 1.0, Li + b * sL, n, 0, X + b * sX, ncols, (long)n * ncols, 0.0,
                     C + b * sH, ldh, (long)n * ldh, nsp, nullptr, 0, UPLO_FULL, nullptr, TRI_A_UPPER);
     }
+}
+
+// The Cholesky factor of S and its inverse into the plan (L, Li); with
+// KS_PLAN_REAL_OVERLAP on a complex plan both are real matrices (n x n
+// doubles per matrix) in the same buffers.
+template <typename T>
+void factor_overlap(ks_plan* p, const T* S) {
+    const int n = p->d.n, B = p->d.batch, lds = p->d.ld_s;
+    const long sL = (long)n * n, sw = (long)p->order * p->order;
+    if constexpr (is_cplx<T>::value) {
+        if (p->d.flags & KS_PLAN_REAL_OVERLAP) {
+            real_sym_complete(p->s, n, S, lds, (long)n * lds, (double*)p->L, n, sL, B, p->info);
+            // W (order^2 complex per matrix, free until the reduction) holds the inverse's intermediate
+            potrf_inv<double>(p->s, n, (double*)p->L, n, sL, (double*)p->Li, n, sL, (double*)p->W, 2 * sw, B,
+                              p->info);
+            return;
+        }
+    }
+    herm_complete<T>(p->s, n, S, lds, (long)n * lds, (T*)p->L, n, sL, B, p->info);
+    potrf_inv<T>(p->s, n, (T*)p->L, n, sL, (T*)p->Li, n, sL, (T*)p->W, sw, B, p->info);
+}
+
+// A = (I (x) Linv) H (I (x) Linv)^H with the plan's factor (lower triangle
+// only with lower_only).
+template <typename T>
+void reduce_h(ks_plan* p, const T* H, T* A, T* W, bool lower_only) {
+    const int n = p->d.n, nsp = p->nsp, B = p->d.batch, ldh = p->d.ld_h;
+    const long sL = (long)n * n, sH = (long)p->order * ldh;
+    if constexpr (is_cplx<T>::value) {
+        if (p->d.flags & KS_PLAN_REAL_OVERLAP) {
+            reduce_to_standard_real(p->s, n, nsp, B, H, ldh, sH, (const double*)p->Li, n, sL, A, W, p->info,
+                                    lower_only);
+            return;
+        }
+    }
+    reduce_to_standard<T>(p->s, n, nsp, B, H, ldh, sH, (const T*)p->Li, n, sL, A, W, p->info, lower_only);
 }
 
 template <typename T>
@@ -550,7 +599,7 @@ ks_status gevd_mixed(ks_plan* p, const T* H, double* eps, T* C, int il, int iu) 
     hipEvent_t e = pf.begin();
     // the lower triangle, then the upper one as its mirror (the residuals take
     // products with the whole matrix)
-    reduce_to_standard<T>(s, n, nsp, B, H, ldh, sH, Li, n, sL, A, W, p->info, true);
+    reduce_h<T>(p, H, A, W, true);
     mirror_lower<T>(s, order, A, order, sA, B);
     convert<T, L>(s, B, order, order, A, order, sA, A32, order, sA);
     pf.end(KS_PHASE_REDUCE, e);
@@ -748,9 +797,7 @@ template <typename T>
 ks_status gevd_impl(ks_plan* p, const T* H, const T* S, double* eps, T* C, int il, int iu,
                     uint32_t flags) {
     hipStream_t s = p->s;
-    int n = p->d.n, nsp = p->nsp, order = p->order, B = p->d.batch;
-    int ldh = p->d.ld_h, lds = p->d.ld_s;
-    T* L = (T*)p->L;
+    const int order = p->order, B = p->d.batch;
     T* A = (T*)p->A;
     T* W = (T*)p->W;
     T* tau = (T*)p->tau;
@@ -759,20 +806,17 @@ ks_status gevd_impl(ks_plan* p, const T* H, const T* S, double* eps, T* C, int i
     if (p->d.flags & KS_PLAN_LOWDIN) return gevd_lowdin<T>(p, H, S, eps, C, il, iu, flags);
     if (!(flags & KS_REUSE_S)) {
         hipEvent_t e = pf.begin();
-        herm_complete<T>(s, n, S, lds, (long)n * lds, L, n, (long)n * n, B, p->info);
-        // W (order^2 per matrix, free until the reduction) holds the inverse's intermediate
-        potrf_inv<T>(s, n, L, n, (long)n * n, Li, n, (long)n * n, (T*)p->W, (long)p->order * p->order, B,
-                     p->info);
+        factor_overlap<T>(p, S);
         pf.end(KS_PHASE_CHOLESKY, e);
         p->have_L = true;
     }
     if (p->d.precision == KS_MIXED) return gevd_mixed<T>(p, H, eps, C, il, iu);
     // every step below takes the whole batch of k-points in each launch
     const int ncols = iu - il + 1;
-    const long sA = (long)order * order, sL = (long)n * n, sH = (long)order * ldh;
+    const long sA = (long)order * order;
     hipEvent_t e = pf.begin();
     // only the lower triangle: the tridiagonalisation reads nothing else
-    reduce_to_standard<T>(s, n, nsp, B, H, ldh, sH, Li, n, sL, A, W, p->info, true);
+    reduce_h<T>(p, H, A, W, true);
     pf.end(KS_PHASE_REDUCE, e);
     e = pf.begin();
     tridiagonalize<T>(p, A, W, tau);
@@ -1392,7 +1436,7 @@ ks_status ks_plan_get_info(ks_plan* p, int32_t* info) {
         *info = 0;
         return KS_OK;
     }
-    *info = (h[0] == KS_ERR_NOT_POSDEF) ? h[1] : -h[0];
+    *info = (h[0] == KS_ERR_NOT_POSDEF || h[0] == KS_ERR_INVALID_ARG) ? h[1] : -h[0];
     return (ks_status)h[0];
 }
 

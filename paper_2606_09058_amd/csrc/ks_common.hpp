@@ -186,7 +186,13 @@ __host__ __device__ inline int s2_steps(int n, int s) { return (n - 1 - s + KB -
 inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
 enum Op { OP_N = 0, OP_T = 1, OP_C = 2 };
-enum Uplo { UPLO_FULL = 0, UPLO_LOWER = 1 };
+// Part of C a product writes: all of it, its lower triangle (col <= row), or
+// the lower triangle of a complex matrix seen as a real one of interleaved
+// (re, im) columns (real column c is complex column c / 2: c <= 2 row + 1).
+enum Uplo { UPLO_FULL = 0, UPLO_LOWER = 1, UPLO_LOWER2 = 2 };
+__host__ __device__ inline bool in_uplo(int uplo, int row, int col) {
+    return uplo == UPLO_FULL || (col >> (uplo - 1)) <= row;  // col <= 2 row + 1 iff col / 2 <= row
+}
 // Known-zero structure of an operand, used to shorten the K loop of a tile:
 // op(A) lower triangular (zero for k > m), op(B) upper triangular (zero for
 // k > n), op(A) upper triangular (zero for k < m).

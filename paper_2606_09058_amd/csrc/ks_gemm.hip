@@ -311,7 +311,7 @@ __device__ inline void gemm_tile(int m, int n, int K, double alpha, const T* A, 
                 for (int r = 0; r < 4; ++r) {
                     const int row = m0 + wm * 32 + i * 16 + out_row<T>(lane, r);
                     const int col = n0 + wn * 32 + j * 16 + (lane & 15);
-                    const bool ok = row < m && col < n && (uplo == UPLO_FULL || col <= row);
+                    const bool ok = row < m && col < n && in_uplo(uplo, row, col);
                     cv[j][r] = ok ? C[(long)row * ldc + col] : zero_<T>();
                 }
         }
@@ -321,7 +321,7 @@ __device__ inline void gemm_tile(int m, int n, int K, double alpha, const T* A, 
             for (int r = 0; r < 4; ++r) {
                 int row = m0 + wm * 32 + i * 16 + out_row<T>(lane, r);
                 int col = n0 + wn * 32 + j * 16 + (lane & 15);
-                if (row < m && col < n && (uplo == UPLO_FULL || col <= row)) {
+                if (row < m && col < n && in_uplo(uplo, row, col)) {
                     T v = alpha * acc_get(acc, i, j, r);
                     T* pc = C + (long)row * ldc + col;
                     if (acc_c) v += beta * (pre ? cv[j][r] : *pc);
@@ -338,7 +338,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(int m, int n, int K, double a
                                                    const double* kscale, long sk, int uplo,
                                                    const int* kdev, int tri) {
     int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-    if (uplo == UPLO_LOWER && m0 + BM - 1 < n0) return;  // tile strictly above the diagonal
+    if (!in_uplo(uplo, m0 + BM - 1, n0)) return;  // tile strictly above the diagonal
     long b = blockIdx.z;
     if (kdev) K = min(K, *kdev);  // inner size decided on the device (occupied window)
     // triangular operands: skip the K range where the operand is known to be zero
@@ -431,7 +431,7 @@ __global__ __launch_bounds__(256, 2) void gemm_big_kernel(int m, int n, int K, d
     __shared__ T sA[2][BKb][BM + LPAD];
     __shared__ T sB[2][BKb][BN + LPAD];
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-    if (uplo == UPLO_LOWER && m0 + BM - 1 < n0) return;  // tile strictly above the diagonal
+    if (!in_uplo(uplo, m0 + BM - 1, n0)) return;  // tile strictly above the diagonal
     const long b = blockIdx.z;
     A += b * sa;
     B += b * sb;
@@ -540,7 +540,7 @@ __global__ __launch_bounds__(256, 2) void gemm_big_kernel(int m, int n, int K, d
                 for (int r = 0; r < 4; ++r) {
                     const int row = m0 + wm * WM + i * 16 + out_row<T>(lane, r);
                     const int col = n0 + wn * WN + j * 16 + li;
-                    const bool ok = row < m && col < n && (uplo == UPLO_FULL || col <= row);
+                    const bool ok = row < m && col < n && in_uplo(uplo, row, col);
                     cv[j][r] = ok ? C[(long)row * ldc + col] : zero_<T>();
                 }
         }
@@ -550,7 +550,7 @@ __global__ __launch_bounds__(256, 2) void gemm_big_kernel(int m, int n, int K, d
             for (int r = 0; r < 4; ++r) {
                 const int row = m0 + wm * WM + i * 16 + out_row<T>(lane, r);
                 const int col = n0 + wn * WN + j * 16 + li;
-                if (row < m && col < n && (uplo == UPLO_FULL || col <= row)) {
+                if (row < m && col < n && in_uplo(uplo, row, col)) {
                     T v;
                     if constexpr (CX) {
                         const auto p1 = cre[i][j][r], p2 = cim[i][j][r];
@@ -571,7 +571,7 @@ static void launch(hipStream_t s, int m, int n, int k, double alpha, const T* A,
                    const T* B, int ldb, long sb, double beta, T* C, int ldc, long sc, int batch,
                    const double* kscale, long sk, Uplo uplo, const int* kdev, Tri tri) {
     constexpr int BBM = Big<T>::BM, BBN = Big<T>::BN;
-    const long big_tiles = (long)cdiv(m, BBM) * cdiv(n, BBN) * batch / (uplo == UPLO_LOWER ? 2 : 1);
+    const long big_tiles = (long)cdiv(m, BBM) * cdiv(n, BBN) * batch / (uplo != UPLO_FULL ? 2 : 1);
     // FP32 gains from large tiles at one round of workgroups, FP64 from two
     const long min_tiles = (sizeof(T) == 4 || std::is_same<T, cplx32>::value) ? BIG_MIN_TILES : 2 * BIG_MIN_TILES;
     if (!kscale && k >= g_big_min_k && big_tiles >= min_tiles) {

@@ -224,6 +224,23 @@ template <typename T>
 void reduce_to_standard(hipStream_t s, int n, int nsp, int batch, const T* H, int ldh, long sH, const T* Linv,
                         int ldi, long sL, T* A, T* W, int* info, bool lower_only = false);
 
+// A real overlap given in complex storage: dst (n x n real, ld ldd, stride sd)
+// = Re of the symmetric completion of src's lower triangle.  An imaginary part
+// other than zero on or below the diagonal records KS_ERR_INVALID_ARG (info =
+// its 1-based row), a non-finite entry KS_ERR_NONFINITE.
+void real_sym_complete(hipStream_t s, int n, const cplx* src, int lds, long ss, double* dst, int ldd, long sd,
+                       int batch, int* info);
+
+// The reduction of a complex H with a real factor Linv (real overlap):
+// A = M H M^T with M = I (x) Linv.  Both products take the complex matrices
+// as real ones of interleaved (re, im) columns, so a product with M costs two
+// real products per complex one instead of three; the right-hand product is
+// A = M (M H)^H (H Hermitian, M real), a conjugate transpose and a second
+// left product.  Same arguments and lower_only meaning as reduce_to_standard.
+void reduce_to_standard_real(hipStream_t s, int n, int nsp, int batch, const cplx* H, int ldh, long sH,
+                             const double* Linv, int ldi, long sL, cplx* A, cplx* W, int* info,
+                             bool lower_only = false);
+
 
 
 template <typename T, typename S>

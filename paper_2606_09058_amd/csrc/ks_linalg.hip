@@ -307,6 +307,110 @@ void reduce_to_standard(hipStream_t s, int n, int nsp, int batch, const T* H, in
     }
 }
 
+// dst = Re of the symmetric completion of src's lower triangle (tiles of 32
+// x 32 through LDS, as in herm_complete); the lower triangle's imaginary
+// parts must be zero.
+__global__ __launch_bounds__(256) void real_sym_complete_kernel(int n, const cplx* src, int lds, long ss,
+                                                                double* dst, int ldd, long sd, int* info) {
+    __shared__ double tile[32][33];
+    src += blockIdx.z * ss;
+    dst += blockIdx.z * sd;
+    const int bi = blockIdx.y * 32, bj = blockIdx.x * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    if (bj > bi) {
+        // upper tile: the mirrored lower tile (bj.., bi..), transposed
+        for (int r = ty; r < 32; r += 8) {
+            const int i = bj + r, j = bi + tx;
+            tile[r][tx] = (i < n && j < n) ? src[(long)i * lds + j].x : 0.0;
+        }
+        __syncthreads();
+        for (int r = ty; r < 32; r += 8) {
+            const int i = bi + r, j = bj + tx;
+            if (i < n && j < n) dst[(long)i * ldd + j] = tile[tx][r];
+        }
+    } else {
+        for (int r = ty; r < 32; r += 8) {
+            const int i = bi + r, j = bj + tx;
+            if (i < n && j < n) {
+                const int a = max(i, j), b = min(i, j);
+                const cplx v = src[(long)a * lds + b];
+                if (j <= i) {
+                    if (!finite_(v)) set_info(info, KS_ERR_NONFINITE, 0);
+                    else if (v.y != 0.0) set_info(info, KS_ERR_INVALID_ARG, i + 1);
+                }
+                dst[(long)i * ldd + j] = v.x;
+            }
+        }
+    }
+}
+
+void real_sym_complete(hipStream_t s, int n, const cplx* src, int lds, long ss, double* dst, int ldd, long sd,
+                       int batch, int* info) {
+    dim3 grid(cdiv(n, 32), cdiv(n, 32), batch);
+    hipLaunchKernelGGL(real_sym_complete_kernel, grid, dim3(256), 0, s, n, src, lds, ss, dst, ldd, sd, info);
+}
+
+// dst = src^H for a batch of n x n matrices (32 x 32 tiles through LDS).
+template <typename T>
+__global__ __launch_bounds__(256) void conj_transpose_kernel(int n, const T* src, int lds, long ss, T* dst,
+                                                             int ldd, long sd) {
+    __shared__ T tile[32][33];
+    src += blockIdx.z * ss;
+    dst += blockIdx.z * sd;
+    const int bi = blockIdx.y * 32, bj = blockIdx.x * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int r = ty; r < 32; r += 8) {
+        const int i = bj + r, j = bi + tx;  // source tile (bj.., bi..)
+        tile[r][tx] = (i < n && j < n) ? src[(long)i * lds + j] : zero_<T>();
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int i = bi + r, j = bj + tx;
+        if (i < n && j < n) dst[(long)i * ldd + j] = conj_(tile[tx][r]);
+    }
+}
+
+void reduce_to_standard_real(hipStream_t s, int n, int nsp, int batch, const cplx* H, int ldh, long sH,
+                             const double* Linv, int ldi, long sL, cplx* A, cplx* W, int* info,
+                             bool lower_only) {
+    const int order = n * nsp;
+    const long sA = (long)order * order;
+    const int ro = 2 * order;  // row length of an order x order complex matrix seen as real
+    // W = H (Hermitian completion of its lower triangle)
+    herm_complete<cplx>(s, order, H, ldh, sH, W, order, sA, batch, info);
+    for (int b = 0; b < batch; ++b) {
+        const double* Lb = Linv + b * sL;
+        // A = M W: spin row-block r of A is Linv times row-block r of W
+        gemm<double>(s, OP_N, OP_N, n, ro, n, 1.0, Lb, ldi, 0, (const double*)(W + b * sA), ro, (long)n * ro, 0.0,
+                     (double*)(A + b * sA), ro, (long)n * ro, nsp, nullptr, 0, UPLO_FULL, nullptr, TRI_A_LOWER);
+    }
+    // W = A^H = H M^T
+    hipLaunchKernelGGL((conj_transpose_kernel<cplx>), dim3(cdiv(order, 32), cdiv(order, 32), batch), dim3(256), 0,
+                       s, order, A, order, sA, W, order, sA);
+    for (int b = 0; b < batch; ++b) {
+        const double* Lb = Linv + b * sL;
+        const double* Wb = (const double*)(W + b * sA);
+        double* Ab = (double*)(A + b * sA);
+        if (!lower_only) {
+            gemm<double>(s, OP_N, OP_N, n, ro, n, 1.0, Lb, ldi, 0, Wb, ro, (long)n * ro, 0.0, Ab, ro, (long)n * ro,
+                         nsp, nullptr, 0, UPLO_FULL, nullptr, TRI_A_LOWER);
+            continue;
+        }
+        // lower triangle of A = M W: row-block 0 over its own columns, and
+        // for spinors row-block 1 over all of column-block 0 and its own
+        // columns of column-block 1
+        gemm<double>(s, OP_N, OP_N, n, 2 * n, n, 1.0, Lb, ldi, 0, Wb, ro, 0, 0.0, Ab, ro, 0, 1, nullptr, 0,
+                     UPLO_LOWER2, nullptr, TRI_A_LOWER);
+        if (nsp == 2) {
+            const long r1 = (long)n * ro;  // first element of row-block 1
+            gemm<double>(s, OP_N, OP_N, n, 2 * n, n, 1.0, Lb, ldi, 0, Wb + r1, ro, 0, 0.0, Ab + r1, ro, 0, 1,
+                         nullptr, 0, UPLO_FULL, nullptr, TRI_A_LOWER);
+            gemm<double>(s, OP_N, OP_N, n, 2 * n, n, 1.0, Lb, ldi, 0, Wb + r1 + 2 * n, ro, 0, 0.0, Ab + r1 + 2 * n,
+                         ro, 0, 1, nullptr, 0, UPLO_LOWER2, nullptr, TRI_A_LOWER);
+        }
+    }
+}
+
 #define KS_INST(T)                                                                                 \
     template void herm_complete<T>(hipStream_t, int, const T*, int, long, T*, int, long, int, int*); \
     template void reduce_to_standard<T>(hipStream_t, int, int, int, const T*, int, long, const T*, int, \

@@ -208,6 +208,22 @@ __global__ __launch_bounds__(64) void dc_leaf_kernel(int n, const int* leaf_lo, 
 }
 
 // ---------------------------------------------------------------- merges
+// The deflation test of two consecutive kept entries (d_p, z_p), (d_j, z_j):
+// the Givens rotation (c, s) with c = z_j / tau, s = -z_p / tau, tau =
+// hypot(z_p, z_j), zeroes z_p; the pair deflates if the off-diagonal it
+// leaves, (d_j - d_p) c s, is at most tol in magnitude.
+__device__ inline bool deflate_pair(double dp, double zp, double dj, double zj, double tol, double* c = nullptr,
+                                    double* s = nullptr, double* t = nullptr) {
+    const double tau = hypot(zj, zp);
+    const double cs = zj / tau, sn = -zp / tau;
+    if (c) {
+        *c = cs;
+        *s = sn;
+        *t = tau;
+    }
+    return fabs((dj - dp) * cs * sn) <= tol;
+}
+
 // One workgroup per merge: form (D, z), merge-sort, deflate.  With use_lds the
 // launch provides K0 doubles of dynamic LDS and the two sorted lists are
 // staged there for the merge's binary searches.
@@ -278,6 +294,75 @@ __global__ __launch_bounds__(256) void dc_deflate_kernel(int n, int nm, const in
     double tol = 0.0;
     for (int i = 0; i < 4; ++i) tol = fmax(tol, fmax(mx[0][i], mx[1][i]));
     tol *= 8.0 * DEPS;
+    // Deflation in merged order: entry j deflates if rho |z_j| <= tol, and two
+    // consecutive kept entries are rotated together (the rotated one carrying
+    // on) if the Givens rotation that zeroes the first one's z leaves an
+    // off-diagonal |(d_j - d_p) c s| <= tol.  Without such a pair the outcome
+    // is a stable partition into deflated and kept entries, which all threads
+    // form at once from contiguous chunks; a merge with a pair takes the
+    // sequential scan below (same tests, same arithmetic).
+    {
+        __shared__ int cnt_d[256], cnt_k[256], last_k[256];
+        __shared__ int any_pair;
+        const int per = (K0 + (int)blockDim.x - 1) / (int)blockDim.x;
+        const int c0 = min(K0, t * per), c1 = min(K0, c0 + per);
+        int nd = 0, nk = 0, firstk = -1, lastk = -1;
+        bool pair = false;
+        double dp = 0.0, zp = 0.0;
+        for (int j = c0; j < c1; ++j) {
+            const double dj = w.ds[lo + j], zj = w.zs[lo + j];
+            if (rho * fabs(zj) <= tol) {
+                ++nd;
+                continue;
+            }
+            if (lastk >= 0 && deflate_pair(dp, zp, dj, zj, tol)) pair = true;
+            if (firstk < 0) firstk = j;
+            lastk = j;
+            dp = dj;
+            zp = zj;
+            ++nk;
+        }
+        cnt_d[t] = nd;
+        cnt_k[t] = nk;
+        last_k[t] = lastk;
+        if (t == 0) any_pair = 0;
+        __syncthreads();
+        if (firstk >= 0) {
+            // the pair across the chunk boundary: the last kept entry before
+            int pk = -1;
+            for (int q = t - 1; q >= 0 && pk < 0; --q) pk = last_k[q];
+            if (pk >= 0 && deflate_pair(w.ds[lo + pk], w.zs[lo + pk], w.ds[lo + firstk], w.zs[lo + firstk], tol))
+                pair = true;
+        }
+        if (pair) any_pair = 1;
+        __syncthreads();
+        if (!any_pair) {
+            int od = 0, ok = 0;
+            for (int q = 0; q < t; ++q) {
+                od += cnt_d[q];
+                ok += cnt_k[q];
+            }
+            for (int j = c0; j < c1; ++j) {
+                const double dj = w.ds[lo + j], zj = w.zs[lo + j];
+                if (rho * fabs(zj) <= tol) {
+                    w.dfl[lo + od] = j;
+                    w.dfval[lo + od] = dj;
+                    ++od;
+                } else {
+                    w.ndl[lo + ok] = j;
+                    w.dnd[lo + ok] = dj;
+                    w.znd[lo + ok] = zj;
+                    ++ok;
+                }
+            }
+            if (t == (int)blockDim.x - 1) {
+                w.kk[G] = ok;
+                w.nrot[G] = 0;
+                w.rho[G] = rho;
+            }
+            return;
+        }
+    }
     // sequential deflation scan, streamed through LDS in chunks of 64
     if (t < 64) {
         int K = 0, nd = 0, nrot = 0, pj = -1;
@@ -305,12 +390,8 @@ __global__ __launch_bounds__(256) void dc_deflate_kernel(int n, int nm, const in
                         zpj = zj;
                         continue;
                     }
-                    double sn = zpj, cs = zj;
-                    double tau = hypot(cs, sn);
-                    double tt = dj - dpj;
-                    cs /= tau;
-                    sn = -sn / tau;
-                    if (fabs(tt * cs * sn) <= tol) {
+                    double cs, sn, tau;
+                    if (deflate_pair(dpj, zpj, dj, zj, tol, &cs, &sn, &tau)) {
                         w.rot_idx[2 * (lo + nrot)] = pj;
                         w.rot_idx[2 * (lo + nrot) + 1] = jj;
                         w.rot_cs[2 * (lo + nrot)] = cs;

@@ -24,6 +24,7 @@ KS_PLAN_GRAPH = 1
 KS_PLAN_AUTOTUNE = 2
 KS_PLAN_LOWDIN = 4
 KS_PLAN_TWOSTAGE = 8
+KS_PLAN_REAL_OVERLAP = 16
 KS_REUSE_S = 1
 
 STATUS = {

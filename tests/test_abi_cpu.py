@@ -51,7 +51,7 @@ def desc(n=100, batch=1, dtype=0, spin=0, prec=0, ldh=None, lds=None, flags=0):
 
 @pytest.mark.parametrize("bad", [
     dict(n=0), dict(batch=0), dict(dtype=2), dict(spin=3), dict(prec=7), dict(ldh=99),
-    dict(lds=50), dict(flags=16), dict(n=40000, spin=1, dtype=1),
+    dict(lds=50), dict(flags=32), dict(n=40000, spin=1, dtype=1),
 ])
 def test_plan_create_rejects_bad_descriptors_without_device(L, bad):
     h = ctypes.c_void_p()
@@ -125,6 +125,12 @@ def test_plan_flags_accepted(L):
     assert L.ks_plan_workspace_bytes(ctypes.byref(d)) > 0
     d = desc(flags=ks.KS_PLAN_GRAPH | ks.KS_PLAN_AUTOTUNE | ks.KS_PLAN_LOWDIN | ks.KS_PLAN_TWOSTAGE)
     assert L.ks_plan_workspace_bytes(ctypes.byref(d)) > 0
+    # the real-overlap flag is accepted on real (no effect) and complex plans
+    # and needs no workspace of its own
+    for dt, sp in ((0, 0), (1, 0), (1, 1)):
+        plain = L.ks_plan_workspace_bytes(ctypes.byref(desc(dtype=dt, spin=sp)))
+        flagged = L.ks_plan_workspace_bytes(ctypes.byref(desc(dtype=dt, spin=sp, flags=ks.KS_PLAN_REAL_OVERLAP)))
+        assert plain > 0 and flagged == plain
 
 
 def test_twostage_workspace(L):

@@ -27,6 +27,8 @@ def golden(name):
 
 # one-stage Householder tridiagonalisation, and the two-stage reduction
 ROUTES = [pytest.param(0, id="onestage"), pytest.param(ks.KS_PLAN_TWOSTAGE, id="twostage")]
+# spinor workloads with a real overlap: also the real-factor route
+NC_ROUTES = ROUTES + [pytest.param(ks.KS_PLAN_REAL_OVERLAP, id="real_overlap")]
 
 
 def gpu_solve(p, flags=0):
@@ -84,7 +86,7 @@ def test_supercell6656_full_size(flags):
                              p.order)
 
 
-@pytest.mark.parametrize("flags", ROUTES)
+@pytest.mark.parametrize("flags", NC_ROUTES)
 def test_noncollinear9984_full_size(flags):
     announce("noncollinear9984 full size", flags)
     p = I.workload("noncollinear9984")
@@ -102,7 +104,7 @@ def test_noncollinear9984_full_size(flags):
                              [host(out["rho"])], p.order)
 
 
-@pytest.mark.parametrize("flags", ROUTES)
+@pytest.mark.parametrize("flags", NC_ROUTES)
 def test_noncollinear4160_against_oracle(flags):
     """The spinor workload on a 160-atom lattice (order 4160 complex: 256-reflector
     back-transform blocks, large-tile complex GEMMs and divide-and-conquer merges

@@ -40,9 +40,9 @@ def window_top(eps_all, mu, buffer=0.4):
     return int(max((row < mu + buffer).sum() for row in e))
 
 
-def solve_mixed(p, iu):
+def solve_mixed(p, iu, flags=0):
     plan = ks.Plan(p.n, batch=p.batch, complex=np.iscomplexobj(p.H), noncollinear=p.nsp == 2,
-                   precision=ks.KS_MIXED)
+                   precision=ks.KS_MIXED, flags=flags)
     H = dev(p.H)
     S = dev(p.S.astype(p.H.dtype))
     out = plan.solve(H, S, p.n_electrons, p.kT, il=1, iu=iu, kweights=p.weights)
@@ -83,12 +83,13 @@ def test_mixed_collinear_vs_oracle(natoms, norb, cplx):
     check(p, g, o["eps"], [o["rho"]], o["mu"], iu)
 
 
-def test_mixed_noncollinear_vs_oracle():
-    announce("mixed noncollinear")
+@pytest.mark.parametrize("flags", [0, ks.KS_PLAN_REAL_OVERLAP])
+def test_mixed_noncollinear_vs_oracle(flags):
+    announce("mixed noncollinear", flags)
     p = I.noncollinear(seed=3, nx=6, ny=1, nz=1, lam_max=0.2)
     o = O.solve(p.H, p.S, p.n_electrons, p.kT, nsp=2)
     iu = window_top(o["eps"], o["mu"])
-    g = solve_mixed(p, iu)
+    g = solve_mixed(p, iu, flags)
     check(p, g, o["eps"], [o["rho"]], o["mu"], iu)
 
 

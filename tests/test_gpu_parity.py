@@ -70,13 +70,66 @@ def test_collinear_vs_oracle(natoms, norb, cplx):
     compare(p, g, o)
 
 
+@pytest.mark.parametrize("flags", [0, ks.KS_PLAN_REAL_OVERLAP])
 @pytest.mark.parametrize("natoms", [2, 7, 20])
-def test_noncollinear_vs_oracle(natoms):
-    announce("noncollinear", natoms)
+def test_noncollinear_vs_oracle(natoms, flags):
+    announce("noncollinear", natoms, flags)
     p = I.noncollinear(seed=natoms, nx=natoms, ny=1, nz=1, lam_max=0.2)
-    g, _ = solve_gpu(p)
+    g, _ = solve_gpu(p, flags=flags)
     o = O.solve(p.H, p.S, p.n_electrons, p.kT, nsp=2)
     compare(p, g, o)
+
+
+@pytest.mark.parametrize("natoms,batch", [(3, 1), (11, 3)])
+def test_real_overlap_collinear_complex_vs_oracle(natoms, batch):
+    """KS_PLAN_REAL_OVERLAP on collinear complex Hermitian H with a real S
+    (orders 39 and 143, the second a batch of three k-points sharing S): the
+    oracle on each matrix, and the complex-factor route of the same plan shape
+    to rounding."""
+    announce("real overlap collinear", natoms, batch)
+    base = I.toy(seed=40 + natoms, natoms=natoms, norb=13, edge=10 * (natoms / 8) ** (1 / 3) + 1,
+                 n_electrons=2.0 * round(0.3 * natoms * 13), kT=0.01)
+    rng = np.random.default_rng(natoms)
+    n = base.n
+    Hs = []
+    for _ in range(batch):
+        K = rng.normal(size=(n, n)) * 0.05
+        Hs.append(base.H + 1j * (K - K.T))
+    H = np.stack(Hs)
+    S = np.stack([base.S] * batch).astype(np.complex128)
+    res = {}
+    for flags in (0, ks.KS_PLAN_REAL_OVERLAP):
+        plan = ks.Plan(n, batch=batch, complex=True, flags=flags)
+        Hd, Sd = (dev(H), dev(S)) if batch > 1 else (dev(H[0]), dev(S[0]))
+        out = plan.solve(Hd, Sd, base.n_electrons, base.kT)
+        res[flags] = {k: host(v) for k, v in out.items()}
+    g = res[ks.KS_PLAN_REAL_OVERLAP]
+    eps_o, C_o = zip(*[O.gevd(H[b], S[b]) for b in range(batch)])
+    wk = np.full(batch, 1.0 / batch)
+    fr = O.fermi(np.array(eps_o), base.n_electrons, base.kT, 2.0, wk=wk)
+    assert np.abs(g["eps"].reshape(batch, -1) - np.array(eps_o)).max() < EPS_TOL
+    assert abs(float(g["mu"][0]) - fr["mu"]) < MU_TOL
+    for b in range(batch):
+        rho_b = O.density(C_o[b], fr["occ"][b])
+        assert np.abs(g["rho"].reshape(batch, n, n)[b] - rho_b).max() < RHO_TOL
+        r, orth = residuals(H[b], S[b], g["eps"].reshape(batch, -1)[b], g["C"].reshape(batch, n, n)[b])
+        assert r < RES_TOL and orth < ORTH_TOL, (r, orth)
+    assert np.abs(g["eps"] - res[0]["eps"]).max() < 1e-12
+    assert np.abs(g["rho"] - res[0]["rho"]).max() < 1e-12
+
+
+def test_real_overlap_flags_complex_S():
+    """KS_PLAN_REAL_OVERLAP with an imaginary part in the lower triangle of S:
+    KS_ERR_INVALID_ARG with info = the 1-based row of the offending entry."""
+    announce("real overlap with complex S")
+    p = I.noncollinear(seed=4, nx=3, ny=1, nz=1, lam_max=0.2)
+    S = p.S.astype(np.complex128)
+    S[17, 5] += 1e-3j
+    S[5, 17] -= 1e-3j
+    _, plan = solve_gpu(I.Problem(p.H, S, p.n_electrons, p.kT, p.nsp), check=False,
+                        flags=ks.KS_PLAN_REAL_OVERLAP)
+    st, info = plan.get_info()
+    assert st == 1 and info == 18, (st, info)
 
 
 @pytest.mark.parametrize("kind", ["real", "complex", "noncollinear", "window"])
