@@ -1046,12 +1046,24 @@ ks_status ks_plan_create(const ks_plan_desc* d, ks_plan** out) {
     if (d->flags & KS_PLAN_AUTOTUNE) {
         ks_tuning& tu = p->tuning;
         const long sA = (long)p->order * p->order;
-        if (p->is_c)
-            tu.ncand = hetrd_tune<cplx>(p->s, p->order, (cplx*)p->A, p->order, sA, d->batch, p->dv, p->ev,
-                                        (cplx*)p->tau, p->hc, tu.cand, tu.ms, 8, tu.seg_first, tu.seg_tiles);
+        // the symmetric product in the storage precision of the trailing matrix
+        // (FP32 in the mixed form)
+        const bool lo = d->precision == KS_MIXED;
+        if (p->is_c && lo)
+            tu.ncand = hetrd_tune<cplx, cplx32>(p->s, p->order, (cplx32*)p->A32, p->order, sA, d->batch, p->dv,
+                                                p->ev, (cplx*)p->tau, p->hc, tu.cand, tu.ms, 8, tu.seg_first,
+                                                tu.seg_tiles);
+        else if (p->is_c)
+            tu.ncand = hetrd_tune<cplx, cplx>(p->s, p->order, (cplx*)p->A, p->order, sA, d->batch, p->dv, p->ev,
+                                              (cplx*)p->tau, p->hc, tu.cand, tu.ms, 8, tu.seg_first, tu.seg_tiles);
+        else if (lo)
+            tu.ncand = hetrd_tune<double, float>(p->s, p->order, (float*)p->A32, p->order, sA, d->batch, p->dv,
+                                                 p->ev, (double*)p->tau, p->hr, tu.cand, tu.ms, 8, tu.seg_first,
+                                                 tu.seg_tiles);
         else
-            tu.ncand = hetrd_tune<double>(p->s, p->order, (double*)p->A, p->order, sA, d->batch, p->dv, p->ev,
-                                          (double*)p->tau, p->hr, tu.cand, tu.ms, 8, tu.seg_first, tu.seg_tiles);
+            tu.ncand = hetrd_tune<double, double>(p->s, p->order, (double*)p->A, p->order, sA, d->batch, p->dv,
+                                                  p->ev, (double*)p->tau, p->hr, tu.cand, tu.ms, 8, tu.seg_first,
+                                                  tu.seg_tiles);
         int best = 0;
         for (int c = 1; c < tu.ncand; ++c)
             if (tu.ms[c] < tu.ms[best]) best = c;

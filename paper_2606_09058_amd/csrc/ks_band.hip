@@ -592,14 +592,6 @@ __device__ __forceinline__ cplx load_coherent(const cplx* p) {
     return mk(__hip_atomic_load(&p->x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
               __hip_atomic_load(&p->y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
 }
-// A store that goes through to memory (an agent-scope relaxed atomic store).
-__device__ __forceinline__ void store_through(double* p, double v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void store_through(cplx* p, cplx v) {
-    __hip_atomic_store(&p->x, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&p->y, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 // One reflector of a group on the lane's window: x[Q .. Q+31] -= v (tau v^H x),
 // the coefficients read from LDS (broadcast).

@@ -107,6 +107,17 @@ __device__ inline double wave_sum(double v) {
 __device__ inline cplx wave_sum(cplx v) { return mk(wave_sum(v.x), wave_sum(v.y)); }
 __device__ inline double shfl_xor_(double v, int m) { return __shfl_xor(v, m, WAVE); }
 __device__ inline cplx shfl_xor_(cplx v, int m) { return mk(__shfl_xor(v.x, m, WAVE), __shfl_xor(v.y, m, WAVE)); }
+// A store that goes through to memory (an agent-scope relaxed atomic store):
+// the line is not left dirty in the writer's L2, so a reader on another XCD
+// needs no write-back of it.
+__device__ __forceinline__ void store_through(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_through(cplx* p, cplx v) {
+    __hip_atomic_store(&p->x, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&p->y, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Select field by field: a ternary on the whole struct keeps an array of it
 // out of registers.
 __device__ inline double pick(bool c, double a, double b) { return c ? a : b; }

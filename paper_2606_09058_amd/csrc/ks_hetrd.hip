@@ -113,11 +113,11 @@ __global__ __launch_bounds__(64) void colstart_kernel(int n, int k, int nb, cons
     if (r >= k && r < n) {
         c = widen(A[(long)r * lda + k]);  // column k below the diagonal (lower storage)
         if (r == k) c = from_re<T>(re_(c));
-        x[r] = c;
+        store_through(&x[r], c);
     }
     double a = (r < n && r >= k + 2) ? abs2_(c) : 0.0;
     a = wave_sum(a);
-    if (t == 0) partA[(long)blockIdx.x * (1 + 2 * nb)] = from_re<T>(a);
+    if (t == 0) store_through(&partA[(long)blockIdx.x * (1 + 2 * nb)], from_re<T>(a));
 }
 
 // The reflector H_k = I - tau v v^H of column k with H_k^H x = beta e_1 from
@@ -169,19 +169,19 @@ __device__ inline void panel_products(int k, int j, int nb, const T* x, const T*
             double beta;
             reflector<T>(partA, nA, ld, alpha, sc, tv, beta);
             if (lane == 0) {
-                pq[2 + 2 * nb] = sc;
-                pq[3 + 2 * nb] = tv;
-                pq[4 + 2 * nb] = from_re<T>(beta);
+                store_through(&pq[2 + 2 * nb], sc);
+                store_through(&pq[3 + 2 * nb], tv);
+                store_through(&pq[4 + 2 * nb], from_re<T>(beta));
             }
         }
-        if (lane == 0) pq[0] = alpha;
+        if (lane == 0) store_through(&pq[0], alpha);
     }
     __syncthreads();
     if (t < nv) {
         T P = zero_<T>();
         for (int q = 0; q < NW; q += 4) P += (part[q][t] + part[q + 1][t]) + (part[q + 2][t] + part[q + 3][t]);
-        if (t < j) pq[2 + t] = P;
-        else pq[2 + nb + (t - j)] = P;
+        if (t < j) store_through(&pq[2 + t], P);
+        else store_through(&pq[2 + nb + (t - j)], P);
     }
 }
 
@@ -449,16 +449,16 @@ __global__ __launch_bounds__((Sy<T, S>::THREADS), 4) void symv_kernel(int n, int
         for (int q = 0; q < NG; q += 4)
             cs += (cred[s][q][col] + cred[s][q + 1][col]) + (cred[s][q + 2][col] + cred[s][q + 3][col]);
         if (J == I) {
-            prow[((long)I * nch + c) * ST + col] = yrow[col] + cs;
+            store_through(&prow[((long)I * nch + c) * ST + col], yrow[col] + cs);
         } else {
-            pcol[((long)J * nt + I) * ST + col] = cs;
-            if (s == ntile - 1) prow[((long)I * nch + c) * ST + col] = yrow[col];
+            store_through(&pcol[((long)J * nt + I) * ST + col], cs);
+            if (s == ntile - 1) store_through(&prow[((long)I * nch + c) * ST + col], yrow[col]);
         }
     }
     if (t == 0) {
         double vsum = 0.0;
         for (int q = 0; q < NG; ++q) vsum += redd[q];
-        pvav[tri_index(I, SCH) + c] = vsum;
+        store_through(&pvav[tri_index(I, SCH) + c], vsum);
     }
 }
 
@@ -649,11 +649,11 @@ __global__ __launch_bounds__(64 * Wc<T>::NW) void wcol_kernel(int n, int k, int 
         xn = ar - cc - (v * conj_(w1) + w);
         if (r == k + 1) xn = from_re<T>(re_(xn));
         if (pp == 0) {
-            VWt[(long)j * n + r] = v;
-            VWt[(long)(nb + j) * n + r] = w;
-            WVc[(long)j * n + r] = conj_(w);
-            WVc[(long)(nb + j) * n + r] = conj_(v);
-            if (next) x[r] = xn;
+            store_through(&VWt[(long)j * n + r], v);
+            store_through(&VWt[(long)(nb + j) * n + r], w);
+            store_through(&WVc[(long)j * n + r], conj_(w));
+            store_through(&WVc[(long)(nb + j) * n + r], conj_(v));
+            if (next) store_through(&x[r], xn);
         }
     }
     if (!next) return;
@@ -665,7 +665,7 @@ __global__ __launch_bounds__(64 * Wc<T>::NW) void wcol_kernel(int n, int k, int 
     T* out = partN + (long)I * ldp;
     if (pp == 1) {
         const double a = wave_sum(abs2_(xe));
-        if (lr == 0) out[0] = from_re<T>(a);
+        if (lr == 0) store_through(&out[0], from_re<T>(a));
     }
     T prod[2 * WC_MAXU];
 #pragma unroll
@@ -680,7 +680,7 @@ __global__ __launch_bounds__(64 * Wc<T>::NW) void wcol_kernel(int n, int k, int 
     constexpr int LPQ = 64 / (2 * WC_MAXU);
     if (lr % LPQ == 0) {
         const int q = lr / LPQ, i = pp + WC_NW * (q >> 1);
-        if (i <= j) out[(q & 1) ? 1 + nb + i : 1 + i] = ps;
+        if (i <= j) store_through(&out[(q & 1) ? 1 + nb + i : 1 + i], ps);
     }
 }
 
@@ -806,8 +806,8 @@ void hetrd(hipStream_t s, int n, S* A, int lda, long sA, int batch, double* d, d
 // spread evenly over the tridiagonalisation: ms[c] is candidate c's total
 // (which estimates the whole solve's product time), and segment q of the
 // columns (around sample q) takes the candidate fastest at that sample.
-template <typename T>
-int hetrd_tune(hipStream_t s, int n, T* A, int lda, long sA, int batch, double* d, double* e, T* tau,
+template <typename T, typename S>
+int hetrd_tune(hipStream_t s, int n, S* A, int lda, long sA, int batch, double* d, double* e, T* tau,
                HetrdWork<T>& w, int* cand, double* ms, int reps, int* seg_first, int* seg_tiles) {
     int nc = 0;
     cand[nc++] = 2;
@@ -842,11 +842,11 @@ int hetrd_tune(hipStream_t s, int n, T* A, int lda, long sA, int batch, double* 
             for (int c0 = 0; c0 < nc; ++c0) {
                 const int c = (c0 + round) % nc;
                 const int k = ks_[q];
-                const int nA = partial_blocks<T>(n, k);
-                symv_launch<T, T>(s, cand[c], n, k, 0, A, lda, sA, batch, nA, w);  // warm
+                const int nA = partial_blocks<S>(n, k);
+                symv_launch<T, S>(s, cand[c], n, k, 0, A, lda, sA, batch, nA, w);  // warm
                 (void)hipEventRecord(e0, s);
                 for (int r = 0; r < reps; ++r)
-                    symv_launch<T, T>(s, cand[c], n, k, 0, A, lda, sA, batch, nA, w);
+                    symv_launch<T, S>(s, cand[c], n, k, 0, A, lda, sA, batch, nA, w);
                 (void)hipEventRecord(e1, s);
                 (void)hipEventSynchronize(e1);
                 float t = 0.f;
@@ -877,10 +877,14 @@ template void hetrd<double, float>(hipStream_t, int, float*, int, long, int, dou
                                    double*, HetrdWork<double>&);
 template void hetrd<cplx, cplx32>(hipStream_t, int, cplx32*, int, long, int, double*, double*, cplx*, cplx*,
                                   HetrdWork<cplx>&);
-template int hetrd_tune<double>(hipStream_t, int, double*, int, long, int, double*, double*, double*,
-                                HetrdWork<double>&, int*, double*, int, int*, int*);
-template int hetrd_tune<cplx>(hipStream_t, int, cplx*, int, long, int, double*, double*, cplx*,
-                              HetrdWork<cplx>&, int*, double*, int, int*, int*);
+template int hetrd_tune<double, double>(hipStream_t, int, double*, int, long, int, double*, double*, double*,
+                                        HetrdWork<double>&, int*, double*, int, int*, int*);
+template int hetrd_tune<cplx, cplx>(hipStream_t, int, cplx*, int, long, int, double*, double*, cplx*,
+                                    HetrdWork<cplx>&, int*, double*, int, int*, int*);
+template int hetrd_tune<double, float>(hipStream_t, int, float*, int, long, int, double*, double*, double*,
+                                       HetrdWork<double>&, int*, double*, int, int*, int*);
+template int hetrd_tune<cplx, cplx32>(hipStream_t, int, cplx32*, int, long, int, double*, double*, cplx*,
+                                      HetrdWork<cplx>&, int*, double*, int, int*, int*);
 template void fill_zero<double>(hipStream_t, double*, long);
 template void fill_zero<cplx>(hipStream_t, cplx*, long);
 template void fill_zero<int>(hipStream_t, int*, long);

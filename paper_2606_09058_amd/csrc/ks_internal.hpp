@@ -251,8 +251,8 @@ void hetrd(hipStream_t s, int n, S* A, int lda, long sA, int batch, double* d, d
 // and the time of `reps` launches of each at a few trailing sizes of an order-n
 // batch (the matrix contents do not matter for the timing).  Writes the
 // candidates to cand[] and times (ms) to ms[]; returns their number.
-template <typename T>
-int hetrd_tune(hipStream_t s, int n, T* A, int lda, long sA, int batch, double* d, double* e, T* tau,
+template <typename T, typename S>
+int hetrd_tune(hipStream_t s, int n, S* A, int lda, long sA, int batch, double* d, double* e, T* tau,
                HetrdWork<T>& w, int* cand, double* ms, int reps, int* seg_first, int* seg_tiles);
 
 // Two-stage reduction of a batch of Hermitian matrices (A: order n, row
