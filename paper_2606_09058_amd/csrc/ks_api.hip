@@ -234,10 +234,11 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
     size_t oDd[10];
     for (int i = 0; i < 10; ++i) oDd[i] = L.take(B * order * 8);
     size_t oRcs = L.take(B * 2 * order * 8);
-    size_t oDi[5];
-    for (int i = 0; i < 5; ++i) oDi[i] = L.take(B * order * sizeof(int));
+    size_t oDi[6];
+    for (int i = 0; i < 6; ++i) oDi[i] = L.take(B * order * sizeof(int));
     size_t oRidx = L.take(B * 2 * order * sizeof(int));
     size_t oKK = L.take(B * maxm * sizeof(int)), oNR = L.take(B * maxm * sizeof(int));
+    size_t oKK1 = L.take(B * maxm * sizeof(int));
     size_t oRho = L.take(B * maxm * 8);
     size_t oT1 = L.take((nm + 1) * sizeof(int)), oT2 = L.take((nm + 1) * sizeof(int));
     size_t oT3 = L.take((nm + 1) * sizeof(int));
@@ -415,8 +416,10 @@ size_t layout(const ks_plan_desc* d, ks_plan* p) {
     w.dfl = (int*)(b + oDi[2]);
     w.orig = (int*)(b + oDi[3]);
     w.fsrc = (int*)(b + oDi[4]);
+    w.gpos = (int*)(b + oDi[5]);
     w.rot_idx = (int*)(b + oRidx);
     w.kk = (int*)(b + oKK);
+    w.kk1 = (int*)(b + oKK1);
     w.nrot = (int*)(b + oNR);
     w.rho = (double*)(b + oRho);
     DcTree& t = p->tree;

@@ -226,13 +226,16 @@ void gemm_splitk(hipStream_t s, Op opa, Op opb, int m, int n, int k, double alph
                  const T* B, int ldb, double beta, T* C, int ldc, T* work, long work_elems, int batch = 1,
                  long sa = 0, long sb = 0, long sc = 0);
 
-// Grouped real GEMM for the divide-and-conquer merges: group g multiplies the
-// (rows_g x kk_g) block of A at (lo_g, lo_g) by the (kk_g x kk_g) block of B at
-// (lo_g, lo_g) into C at (lo_g, lo_g); all with row stride ld.  rows_g = hi_g -
-// lo_g comes from the host bounds, kk_g from device memory (deflation count).
-// A batch of matrices (ld x ld, consecutive) shares the launch; matrix b's
-// group g takes K = kk[b * ngroups + g].
-void gemm_grouped_dc(hipStream_t s, int ngroups, int batch, int max_rows, const int* d_lo, const int* d_hi,
-                     const int* d_kk, const double* A, const double* B, double* C, int ld);
+// Grouped real GEMM for the divide-and-conquer merges, C = A B with the
+// merge's (rows x K) block of A at (lo, lo), (K x K) block of B and C at
+// (lo, lo), row stride ld; K = kk[G] from device memory (deflation count) for
+// group G = b * ngroups + g (matrix b of a batch, ld x ld consecutive).  The
+// rows split at the tear mid: with kk1[G] = K1 >= 0 the first K1 columns of A
+// are zero below mid and the others above it (A's columns grouped by child),
+// so rows lo..mid-1 take columns 0..K1-1 only and rows mid..hi-1 columns
+// K1..K-1; kk1[G] < 0 takes all K for both.
+void gemm_grouped_dc(hipStream_t s, int ngroups, int batch, int max_rows, const int* d_lo, const int* d_mid,
+                     const int* d_hi, const int* d_kk, const int* d_kk1, const double* A, const double* B,
+                     double* C, int ld);
 
 }  // namespace ks

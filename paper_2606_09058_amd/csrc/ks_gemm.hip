@@ -690,23 +690,33 @@ template void gemm_splitk<cplx32>(hipStream_t, Op, Op, int, int, int, double, co
                                   const cplx32*, int, double, cplx32*, int, cplx32*, long, int, long, long, long);
 
 // ---------------------------------------------------------------- grouped
-__global__ __launch_bounds__(256) void gemm_grouped_dc_kernel(int nm, const int* lo, const int* hi,
-                                                              const int* kk, const double* A,
-                                                              const double* B, double* C, int ld) {
+__global__ __launch_bounds__(256) void gemm_grouped_dc_kernel(int nm, int part, const int* lo, const int* mid,
+                                                              const int* hi, const int* kk, const int* kk1,
+                                                              const double* A, const double* B, double* C,
+                                                              int ld) {
     const int G = blockIdx.z, g = G % nm;  // merge g of matrix G / nm of a batch
-    int l = lo[g], rows = hi[g] - l, K = kk[G];
-    int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const int l = lo[g], md = mid[g], K = kk[G], K1 = kk1[G];
+    // part 0: rows l .. md-1; part 1: rows md .. hi-1; inner range [k0, k1)
+    const int r0 = part == 0 ? l : md, rows = part == 0 ? md - l : hi[g] - md;
+    const int k0 = (K1 >= 0 && part == 1) ? K1 : 0, k1 = (K1 >= 0 && part == 0) ? K1 : K;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     if (m0 >= rows || n0 >= K) return;
-    long off = (long)(G / nm) * ld * ld + (long)l * ld + l;
-    gemm_tile<double, OP_N, OP_N>(rows, K, K, 1.0, A + off, ld, B + off, ld, 0.0, C + off, ld,
+    const long base = (long)(G / nm) * ld * ld;
+    gemm_tile<double, OP_N, OP_N>(rows, K, k1 - k0, 1.0, A + base + (long)r0 * ld + l + k0, ld,
+                                  B + base + (long)(l + k0) * ld + l, ld, 0.0, C + base + (long)r0 * ld + l, ld,
                                   nullptr, UPLO_FULL, m0, n0);
 }
 
-void gemm_grouped_dc(hipStream_t s, int ngroups, int batch, int max_rows, const int* d_lo, const int* d_hi,
-                     const int* d_kk, const double* A, const double* B, double* C, int ld) {
+void gemm_grouped_dc(hipStream_t s, int ngroups, int batch, int max_rows, const int* d_lo, const int* d_mid,
+                     const int* d_hi, const int* d_kk, const int* d_kk1, const double* A, const double* B,
+                     double* C, int ld) {
     if (ngroups <= 0 || max_rows <= 0 || batch <= 0) return;
-    dim3 grid(cdiv(max_rows, BN), cdiv(max_rows, BM), ngroups * batch);
-    hipLaunchKernelGGL(gemm_grouped_dc_kernel, grid, dim3(256), 0, s, ngroups, d_lo, d_hi, d_kk, A, B, C, ld);
+    // each part covers at most max_rows - max_rows / 2 rows (the tear splits a merge in halves)
+    const int half = max_rows - max_rows / 2;
+    dim3 grid(cdiv(max_rows, BN), cdiv(half, BM), ngroups * batch);
+    for (int part = 0; part < 2; ++part)
+        hipLaunchKernelGGL(gemm_grouped_dc_kernel, grid, dim3(256), 0, s, ngroups, part, d_lo, d_mid, d_hi, d_kk,
+                           d_kk1, A, B, C, ld);
 }
 
 }  // namespace ks

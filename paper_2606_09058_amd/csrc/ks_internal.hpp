@@ -180,6 +180,8 @@ struct DcWork {
     double* fval;
     int* fsrc;
     int* kk;        // per merge of the current level
+    int* kk1;       // per merge: kept columns of the first child (< 0: columns not grouped)
+    int* gpos;      // kept entry (secular order) -> its column in the child-grouped order
     int* nrot;
     double* rho;
 };

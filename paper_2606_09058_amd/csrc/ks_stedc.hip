@@ -50,6 +50,7 @@ __device__ inline DcWork dc_slice(DcWork w, int b, int n) {
     w.cinv += o;
     w.fval += o;
     w.fsrc += o;
+    w.gpos += o;
     return w;
 }
 
@@ -302,11 +303,11 @@ __global__ __launch_bounds__(256) void dc_deflate_kernel(int n, int nm, const in
     // form at once from contiguous chunks; a merge with a pair takes the
     // sequential scan below (same tests, same arithmetic).
     {
-        __shared__ int cnt_d[256], cnt_k[256], last_k[256];
+        __shared__ int cnt_d[256], cnt_k[256], cnt_k1[256], last_k[256];
         __shared__ int any_pair;
         const int per = (K0 + (int)blockDim.x - 1) / (int)blockDim.x;
         const int c0 = min(K0, t * per), c1 = min(K0, c0 + per);
-        int nd = 0, nk = 0, firstk = -1, lastk = -1;
+        int nd = 0, nk = 0, nk1 = 0, firstk = -1, lastk = -1;
         bool pair = false;
         double dp = 0.0, zp = 0.0;
         for (int j = c0; j < c1; ++j) {
@@ -321,9 +322,11 @@ __global__ __launch_bounds__(256) void dc_deflate_kernel(int n, int nm, const in
             dp = dj;
             zp = zj;
             ++nk;
+            nk1 += w.perm[lo + j] < n1;
         }
         cnt_d[t] = nd;
         cnt_k[t] = nk;
+        cnt_k1[t] = nk1;
         last_k[t] = lastk;
         if (t == 0) any_pair = 0;
         __syncthreads();
@@ -337,10 +340,17 @@ __global__ __launch_bounds__(256) void dc_deflate_kernel(int n, int nm, const in
         if (pair) any_pair = 1;
         __syncthreads();
         if (!any_pair) {
-            int od = 0, ok = 0;
-            for (int q = 0; q < t; ++q) {
-                od += cnt_d[q];
-                ok += cnt_k[q];
+            // without rotations every kept column belongs to one child: the
+            // merge product takes them grouped by child (first child's first,
+            // each group in secular order), which halves its flops
+            int od = 0, ok = 0, ok1 = 0, K1 = 0;
+            for (int q = 0; q < (int)blockDim.x; ++q) {
+                if (q < t) {
+                    od += cnt_d[q];
+                    ok += cnt_k[q];
+                    ok1 += cnt_k1[q];
+                }
+                K1 += cnt_k1[q];
             }
             for (int j = c0; j < c1; ++j) {
                 const double dj = w.ds[lo + j], zj = w.zs[lo + j];
@@ -349,14 +359,18 @@ __global__ __launch_bounds__(256) void dc_deflate_kernel(int n, int nm, const in
                     w.dfval[lo + od] = dj;
                     ++od;
                 } else {
+                    const bool first = w.perm[lo + j] < n1;
                     w.ndl[lo + ok] = j;
                     w.dnd[lo + ok] = dj;
                     w.znd[lo + ok] = zj;
+                    w.gpos[lo + ok] = first ? ok1 : K1 + (ok - ok1);
+                    ok1 += first;
                     ++ok;
                 }
             }
             if (t == (int)blockDim.x - 1) {
                 w.kk[G] = ok;
+                w.kk1[G] = K1;
                 w.nrot[G] = 0;
                 w.rho[G] = rho;
             }
@@ -426,6 +440,7 @@ __global__ __launch_bounds__(256) void dc_deflate_kernel(int n, int nm, const in
                 ++K;
             }
             w.kk[G] = K;
+            w.kk1[G] = -1;  // rotations may mix the children's columns
             w.nrot[G] = nrot;
             w.rho[G] = rho;
         }
@@ -625,11 +640,15 @@ __global__ __launch_bounds__(256) void dc_ugen_kernel(int n, int nm, const int* 
     if (i >= K || jr >= K) return;
     const double* d = w.dnd + lo;
     double u = w.zhat[lo + i] / ((d[i] - d[w.orig[lo + jr]]) - w.tau[lo + jr]);
-    U[(long)(lo + i) * n + lo + jr] = u * w.cinv[lo + jr];
+    // row i of U pairs with column i of the gathered eigenvectors: both in the
+    // child-grouped order when the merge has one
+    const int gi = w.kk1[G] >= 0 ? w.gpos[lo + i] : i;
+    U[(long)(lo + gi) * n + lo + jr] = u * w.cinv[lo + jr];
 }
 
-// Gather: Qp columns [0, K) = undeflated columns of Z in secular order; Z2
-// columns [K, K0) = deflated columns (both at the merge's block).
+// Gather: Qp columns [0, K) = undeflated columns of Z in secular order, or in
+// the child-grouped order gpos when the merge has one (kk1 >= 0); Z2 columns
+// [K, K0) = deflated columns (both at the merge's block).
 __global__ __launch_bounds__(256) void dc_gather_kernel(int n, int nm, const int* mlo, const int* mhi,
                                                         DcWork w, const double* Z, double* Qp, double* Z2) {
     const int G = blockIdx.z, g = G % nm, bm = G / nm;
@@ -645,7 +664,8 @@ __global__ __launch_bounds__(256) void dc_gather_kernel(int n, int nm, const int
     if (r >= hi || c >= K0) return;
     if (c < K) {
         int src = w.perm[lo + w.ndl[lo + c]];
-        Qp[(long)r * n + lo + c] = Z[(long)r * n + lo + src];
+        const int gc = w.kk1[G] >= 0 ? w.gpos[lo + c] : c;
+        Qp[(long)r * n + lo + gc] = Z[(long)r * n + lo + src];
     } else {
         int src = w.perm[lo + w.dfl[lo + (c - K)]];
         Z2[(long)r * n + lo + c] = Z[(long)r * n + lo + src];
@@ -746,7 +766,7 @@ void stedc(hipStream_t s, const DcTree& tr, int batch, const double* d, const do
         hipLaunchKernelGGL(dc_ugen_kernel, dim3(cdiv(mk, 256), mk, NG), dim3(256), 0, s, n, nm, mlo, w, U);
         hipLaunchKernelGGL(dc_gather_kernel, dim3(cdiv(mk, 256), mk, NG), dim3(256), 0, s, n, nm, mlo, mhi, w,
                            (const double*)Z, Qp, Z2);
-        gemm_grouped_dc(s, nm, B, mk, mlo, mhi, w.kk, Qp, U, Z2, n);
+        gemm_grouped_dc(s, nm, B, mk, mlo, mmid, mhi, w.kk, w.kk1, Qp, U, Z2, n);
         hipLaunchKernelGGL(dc_rank_kernel, dim3(cdiv(mk, 256), NG), dim3(256), 0, s, n, nm, mlo, mhi, w);
         hipLaunchKernelGGL(dc_permute_kernel, dim3(cdiv(mk, 256), mk, NG), dim3(256), 0, s, n, nm, mlo, mhi, w,
                            (const double*)Z2, Z, lam);
