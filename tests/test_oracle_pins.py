@@ -617,3 +617,26 @@ def test_known_spectrum_construction_matches_oracle():
     C = _known_rows(p, np.arange(p.order))
     rho = (C * r["occ"]) @ C.conj().T
     assert np.abs(rho - r["rho"]).max() < 1e-11
+
+
+@pytest.mark.parametrize("name", ["toy64", "supercell6656", "noncollinear4160", "noncollinear9984",
+                                  "kpoints16x1300", "diff2048"])
+def test_stored_oracle_values_are_self_consistent(name):
+    """Every stored oracle result (tests/golden/*.json) agrees with itself: the
+    eigenvalues ascend, the stored mu gives the electron count through the Fermi
+    function, and E_band is the occupation-weighted sum of the eigenvalues
+    (with the k weights of the workload, uniform here)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name + ".json")
+    g = json.load(open(path))
+    eps = np.array(g["eps"], dtype=float)
+    if eps.ndim == 1:
+        eps = eps[None]
+    assert np.all(np.diff(eps, axis=1) >= 0)
+    x = (eps - g["mu"]) / g["kT"]
+    f = g["g"] * np.where(x > 0, np.exp(-np.clip(x, 0, 700)) / (1 + np.exp(-np.clip(x, 0, 700))),
+                          1 / (1 + np.exp(np.clip(x, -700, 0))))
+    wk = np.full(eps.shape[0], 1.0 / eps.shape[0])
+    assert abs((wk[:, None] * f).sum() - g["n_electrons"]) < 1e-9 * g["n_electrons"]
+    assert abs((wk[:, None] * f * eps).sum() - g["eband"]) < 1e-9 * max(1.0, abs(g["eband"]))
