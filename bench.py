@@ -598,7 +598,10 @@ def compare_precisions(p, H, S, eps_all, mu, steps, buffer_ha=0.4):
         plan.check(form + " window steps")
         res[form + "_s_per_solve"] = e0.elapsed_time(e1) / steps / 1e3
         res[form + "_phases_ms"] = {k: v for k, v in phase_dict(prof, steps).items() if v > 0}
-        outs[form] = (eps.clone(), rho.clone(), float(eb.item()))
+        # host copies after the device has drained: the next form's plan and
+        # tensors reuse this memory
+        torch.cuda.synchronize()
+        outs[form] = (eps.cpu(), rho.cpu(), float(eb.cpu().item()))
         del plan, C, rho
         torch.cuda.empty_cache()
     ef, rf, bf = outs["fp64"]
