@@ -166,7 +166,7 @@ def test_gemm_rank_update_lower(L, m, n, k, fp32):
     assert np.array_equal(got[~low], C0.astype(np.float64)[~low])
 
 
-@pytest.mark.parametrize("n", [1, 31, 63, 64, 65, 100, 128, 257, 330])
+@pytest.mark.parametrize("n", [1, 31, 63, 64, 65, 100, 127, 128, 129, 200, 257, 330])
 @pytest.mark.parametrize("cplx", [False, True])
 def test_potrf_matches_oracle(L, n, cplx):
     """Blocked Cholesky (64-column blocks, ragged last block) against the oracle's
