@@ -18,6 +18,9 @@ struct ks_plan {
     bool is_c = false;
     size_t es = 8;
     hipStream_t s = nullptr;
+    // batches of two or more: a second stream for half of the tridiagonalisation
+    hipStream_t side = nullptr;
+    hipEvent_t side_fork = nullptr, side_join = nullptr;
     char* base = nullptr;      // the one workspace allocation
     size_t bytes = 0;
     void* L = nullptr;         // batch x n x n cached Cholesky factors
@@ -1026,6 +1029,17 @@ ks_status ks_plan_create(const ks_plan_desc* d, ks_plan** out) {
             return KS_ERR_NOT_SUPPORTED;
         }
     }
+    if (d->batch >= 2) {
+        if (hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&p->side_fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&p->side_join, hipEventDisableTiming) != hipSuccess) {
+            ks_plan_destroy(p);
+            return KS_ERR_HIP;
+        }
+        p->hr.side = p->hc.side = p->side;
+        p->hr.fork = p->hc.fork = p->side_fork;
+        p->hr.join = p->hc.join = p->side_join;
+    }
     p->kw_last = make_weights(p, nullptr);
     if (hipMemset(p->info, 0, 2 * sizeof(int)) != hipSuccess) {
         (void)hipFree(p->base);
@@ -1091,7 +1105,11 @@ ks_status ks_plan_create(const ks_plan_desc* d, ks_plan** out) {
 void ks_plan_destroy(ks_plan* p) {
     if (!p) return;
     (void)hipStreamSynchronize(p->s);
+    if (p->side) (void)hipStreamSynchronize(p->side);
     graph_release(p);
+    if (p->side_join) (void)hipEventDestroy(p->side_join);
+    if (p->side_fork) (void)hipEventDestroy(p->side_fork);
+    if (p->side) (void)hipStreamDestroy(p->side);
     if (p->rr) ks_plan_destroy(p->rr);
     if (p->ov) ks_plan_destroy(p->ov);
     if (p->base) (void)hipFree(p->base);

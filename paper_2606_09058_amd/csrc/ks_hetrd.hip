@@ -704,15 +704,16 @@ __global__ void last_diag_kernel(int n, const S* A, int lda, long sA, double* d)
 }
 
 // Launch the symmetric product of column k with sch tiles per workgroup.  With
-// events, the launch itself records them at the kernel's start and end (so
-// the sampled duration is the kernel's own, without the gap before it).
+// events (either may be null), the launch itself records them at the kernel's
+// start and end (so the sampled duration is the kernel's own, without the gap
+// before it).
 template <typename T, typename S>
 void symv_launch(hipStream_t s, int sch, int n, int k, int j, const S* A, int lda, long sA, int B, int nA,
                  const HetrdWork<T>& w, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
     const int nt = cdiv(n - tile_origin<S>(k), ST), nch = cdiv(nt, sch), nb = HETRD_NB;
     // one workgroup column beyond the tiles' for the panel products
     const dim3 grid(nch + 1, nt, B), block(Sy<T, S>::THREADS);
-    if (ev0) {
+    if (ev0 || ev1) {
         if (sch == 2)
             hipExtLaunchKernelGGL((symv_kernel<T, S, 2>), grid, block, 0, s, ev0, ev1, 0, n, k, j, nb, A, lda, sA,
                                   nA, nt, nch, w);
@@ -740,70 +741,127 @@ __global__ void narrow_panel_kernel(long cnt, const T* src, long ssrc, S* dst, l
     dst[blockIdx.y * sdst + i] = narrow(src[blockIdx.y * ssrc + i]);
 }
 
+// One group of matrices of a batch that hetrd reduces on one stream.
+template <typename T, typename S>
+struct TrdGroup {
+    hipStream_t s;
+    int B;
+    S* A;
+    double* d;
+    double* e;
+    T* tau;
+    T* Vall;
+    HetrdWork<T> w;
+};
+
 // S: storage type of the trailing matrix A (T, or FP32 in the mixed form, where
 // the rank-2NB trailing update runs on the FP32 matrix cores and everything
 // else, reflectors included, stays in FP64).
+// A batch of two or more matrices with a side stream in the workspace runs as
+// two groups, the second half on the side stream (forked from and joined back
+// to s by events), their launches issued column by column in turn: one group's
+// latency-bound column kernel then runs beside the other group's product.
 template <typename T, typename S>
 void hetrd(hipStream_t s, int n, S* A, int lda, long sA, int batch, double* d, double* e, T* tau, T* Vall,
            HetrdWork<T>& w) {
     constexpr bool lo = !std::is_same<T, S>::value;
     const int nb = HETRD_NB;
-    const int B = batch;
+    TrdGroup<T, S> g[2];
+    int ng = 1;
+    g[0] = {s, batch, A, d, e, tau, Vall, w};
+    if (w.side && batch >= 2) {
+        const int B0 = (batch + 1) / 2;
+        g[0].B = B0;
+        HetrdWork<T> w1 = w;
+        w1.prof = nullptr;
+        w1.VW += B0 * w.sVW;
+        w1.WV += B0 * w.sVW;
+        w1.x += B0 * w.sx;
+        w1.partPQ += B0 * w.spart;
+        w1.prow += B0 * w.sprow;
+        w1.pcol += B0 * w.spcol;
+        w1.pvav += B0 * w.spvav;
+        w1.pq += B0 * w.spq;
+        if (w.VWlo) w1.VWlo = (S*)w.VWlo + B0 * w.sVW;
+        if (w.WVlo) w1.WVlo = (S*)w.WVlo + B0 * w.sVW;
+        g[1] = {w.side, batch - B0, A + B0 * sA, d + (long)B0 * n, e + (long)B0 * n, tau + (long)B0 * n,
+                Vall + (long)B0 * n * n, w1};
+        ng = 2;
+        (void)hipEventRecord(w.fork, s);
+        (void)hipStreamWaitEvent(w.side, w.fork, 0);
+    }
     for (int k0 = 0; k0 < n - 1; k0 += nb) {
         int jb = min(nb, n - 1 - k0);
-        // The column kernels write every panel row the trailing update and the
-        // next columns read (rows k+1.. of column k); only a short last panel
-        // leaves panel columns unwritten that its update would read.
-        if (jb < nb) {
-            fill_zero<T>(s, w.VW, w.sVW * B);
-            fill_zero<T>(s, w.WV, w.sVW * B);
+        for (int q = 0; q < ng; ++q) {
+            TrdGroup<T, S>& G = g[q];
+            // The column kernels write every panel row the trailing update and
+            // the next columns read (rows k+1.. of column k); only a short last
+            // panel leaves panel columns unwritten that its update would read.
+            if (jb < nb) {
+                fill_zero<T>(G.s, G.w.VW, G.w.sVW * G.B);
+                fill_zero<T>(G.s, G.w.WV, G.w.sVW * G.B);
+            }
+            hipLaunchKernelGGL((colstart_kernel<T, S>), dim3(partial_blocks<S>(n, k0), 1, G.B), dim3(64), 0, G.s, n,
+                               k0, nb, G.A, lda, sA, G.w);
         }
-        hipLaunchKernelGGL((colstart_kernel<T, S>), dim3(partial_blocks<S>(n, k0), 1, B), dim3(64), 0, s, n, k0, nb,
-                           A, lda, sA, w);
         for (int j = 0; j < jb; ++j) {
             int k = k0 + j;
             int m = n - k - 1;
             const int sch = w.sch_for(k);
             int nt = cdiv(n - tile_origin<S>(k), ST), nch = cdiv(nt, sch);
             int nA = partial_blocks<S>(n, k);  // workgroups that wrote the partials of column k
+            // a sampled column is timed from the start of the first group's
+            // product to the end of the last group's (both groups' bytes)
             const bool smp = w.prof && w.prof->sample();
             hipEvent_t e0 = smp ? w.prof->take() : nullptr;
             hipEvent_t e1 = smp ? w.prof->take() : nullptr;
-            symv_launch<T, S>(s, sch, n, k, j, A, lda, sA, B, nA, w, e0, e1);
+            for (int q = 0; q < ng; ++q) {
+                TrdGroup<T, S>& G = g[q];
+                symv_launch<T, S>(G.s, sch, n, k, j, G.A, lda, sA, G.B, nA, G.w, q == 0 ? e0 : nullptr,
+                                  q == ng - 1 ? e1 : nullptr);
+                hipLaunchKernelGGL((wcol_kernel<T, S>), dim3(nt, 1, G.B), dim3(64 * Wc<T>::NW), 0, G.s, n, k, j, nb,
+                                   (int)(j + 1 < jb), G.A, lda, sA, nt, nch, sch, nA, G.d, G.e, G.tau, G.w);
+            }
             // algorithmic bytes of a Hermitian matrix-vector product: the lower
             // triangle once, in the storage precision
-            if (smp) w.prof->push(PROF_HEMV, e0, e1, (double)sizeof(S) * m * (m + 1) / 2.0 * B);
-            hipLaunchKernelGGL((wcol_kernel<T, S>), dim3(nt, 1, B), dim3(64 * Wc<T>::NW), 0, s, n, k, j, nb,
-                               (int)(j + 1 < jb), A, lda, sA, nt, nch, sch, nA, d, e, tau, w);
+            if (smp) w.prof->push(PROF_HEMV, e0, e1, (double)sizeof(S) * m * (m + 1) / 2.0 * batch);
         }
-        long tot = (long)n * jb;
-        hipLaunchKernelGGL((store_panel_kernel<T>), dim3(cdiv(tot, 256), 1, B), dim3(256), 0, s, n, k0, jb, w.VW,
-                           w.sVW, Vall);
-        int t0 = k0 + jb;
-        if (t0 < n) {
-            int mt = n - t0;
-            if constexpr (lo) {
-                S* VWs = (S*)w.VWlo;
-                S* WVs = (S*)w.WVlo;
-                const long cnt = w.sVW;
-                hipLaunchKernelGGL((narrow_panel_kernel<T, S>), dim3(cdiv(cnt, 256), B), dim3(256), 0, s, cnt, w.VW,
-                                   w.sVW, VWs, w.sVW);
-                hipLaunchKernelGGL((narrow_panel_kernel<T, S>), dim3(cdiv(cnt, 256), B), dim3(256), 0, s, cnt, w.WV,
-                                   w.sVW, WVs, w.sVW);
-                gemm<S>(s, OP_T, OP_N, mt, mt, 2 * nb, -1.0, VWs + t0, n, w.sVW, WVs + t0, n, w.sVW, 1.0,
-                        A + (long)t0 * lda + t0, lda, sA, B, nullptr, 0, UPLO_LOWER);
-            } else {
-                // complex rank-2NB updates take the large tiles whenever there
-                // are enough of them (measured at 2N = 9984: 702 -> 692 ms of
-                // tridiagonalisation); real ones keep the 64 x 64 tiles (large
-                // ones were 0.8 ms slower at N = 6656)
-                GemmPolicy pol(is_cplx<T>::value ? 2 * nb : gemm_big_min_k());
-                gemm<T>(s, OP_T, OP_N, mt, mt, 2 * nb, -1.0, w.VW + t0, n, w.sVW, w.WV + t0, n, w.sVW, 1.0,
-                        A + (long)t0 * lda + t0, lda, sA, B, nullptr, 0, UPLO_LOWER);
+        for (int q = 0; q < ng; ++q) {
+            TrdGroup<T, S>& G = g[q];
+            long tot = (long)n * jb;
+            hipLaunchKernelGGL((store_panel_kernel<T>), dim3(cdiv(tot, 256), 1, G.B), dim3(256), 0, G.s, n, k0, jb,
+                               G.w.VW, G.w.sVW, G.Vall);
+            int t0 = k0 + jb;
+            if (t0 < n) {
+                int mt = n - t0;
+                if constexpr (lo) {
+                    S* VWs = (S*)G.w.VWlo;
+                    S* WVs = (S*)G.w.WVlo;
+                    const long cnt = G.w.sVW;
+                    hipLaunchKernelGGL((narrow_panel_kernel<T, S>), dim3(cdiv(cnt, 256), G.B), dim3(256), 0, G.s, cnt,
+                                       G.w.VW, G.w.sVW, VWs, G.w.sVW);
+                    hipLaunchKernelGGL((narrow_panel_kernel<T, S>), dim3(cdiv(cnt, 256), G.B), dim3(256), 0, G.s, cnt,
+                                       G.w.WV, G.w.sVW, WVs, G.w.sVW);
+                    gemm<S>(G.s, OP_T, OP_N, mt, mt, 2 * nb, -1.0, VWs + t0, n, G.w.sVW, WVs + t0, n, G.w.sVW, 1.0,
+                            G.A + (long)t0 * lda + t0, lda, sA, G.B, nullptr, 0, UPLO_LOWER);
+                } else {
+                    // complex rank-2NB updates take the large tiles whenever there
+                    // are enough of them (measured at 2N = 9984: 702 -> 692 ms of
+                    // tridiagonalisation); real ones keep the 64 x 64 tiles (large
+                    // ones were 0.8 ms slower at N = 6656)
+                    GemmPolicy pol(is_cplx<T>::value ? 2 * nb : gemm_big_min_k());
+                    gemm<T>(G.s, OP_T, OP_N, mt, mt, 2 * nb, -1.0, G.w.VW + t0, n, G.w.sVW, G.w.WV + t0, n, G.w.sVW,
+                            1.0, G.A + (long)t0 * lda + t0, lda, sA, G.B, nullptr, 0, UPLO_LOWER);
+                }
             }
         }
     }
-    hipLaunchKernelGGL((last_diag_kernel<S>), dim3(B), dim3(1), 0, s, n, A, lda, sA, d);
+    for (int q = 0; q < ng; ++q)
+        hipLaunchKernelGGL((last_diag_kernel<S>), dim3(g[q].B), dim3(1), 0, g[q].s, n, g[q].A, lda, sA, g[q].d);
+    if (ng == 2) {
+        (void)hipEventRecord(w.join, w.side);
+        (void)hipStreamWaitEvent(s, w.join, 0);
+    }
 }
 
 

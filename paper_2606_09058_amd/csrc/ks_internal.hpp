@@ -115,6 +115,10 @@ struct HetrdWork {
     // strides (elements) between the buffers of consecutive matrices of a batch
     long sVW = 0, sx = 0, spart = 0, sprow = 0, spcol = 0, spvav = 0, spq = 0;
     long sbuf = 0;  // offset of the odd-column partial buffer
+    // batches of two or more: the stream of the second half and the events that
+    // fork it from and join it back to the caller's stream (none: one stream)
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     int sch = HETRD_SCH;  // tiles per workgroup of the symmetric product (tuned per plan)
     // tuned per column segment: columns from seg_first[i] use seg_sch[i]
     int nseg = 0;
