@@ -154,10 +154,15 @@ typedef struct {
  * current device.  KS_ERR_INVALID_ARG for a bad descriptor (no allocation is
  * attempted), KS_ERR_NOT_SUPPORTED for a valid but unsupported one,
  * KS_ERR_ALLOC if the workspace does not fit.  On success *out owns the
- * workspace until ks_plan_destroy. */
+ * workspace until ks_plan_destroy.  A plan for a batch of two or more also
+ * owns a side stream (non-blocking, default priority) and two events: the
+ * tridiagonalisation runs half of the batch there, forked from and joined
+ * back to the plan's stream within each ks_gevd call, so callers order work
+ * on the plan's stream alone (KS_ERR_HIP if they cannot be created). */
 ks_status ks_plan_create(const ks_plan_desc* desc, ks_plan** out);
 
-/* Free the plan's workspace (synchronizes its stream first).  NULL is a no-op. */
+/* Free the plan's workspace, side stream and events (synchronizes its streams
+ * first).  NULL is a no-op. */
 void ks_plan_destroy(ks_plan* plan);
 
 /* Generalized eigen-decomposition of every k-point (paper Sec. 2, H C = S C eps;
