@@ -43,7 +43,7 @@ WORKLOADS = {
                         "1536 electrons, kT=0.01 Ha, all eigenvectors",
     "toy64": "N=64 real symmetric toy (8 atoms x 8 orbitals), 32 electrons, kT=0.01 Ha",
     "kpoints16x1300": "16 k-points x N=1300 complex Hermitian (100-atom cell, 27 lattice vectors), "
-                      "400 electrons, kT=0.01 Ha, one common Fermi level, all k in each launch",
+                      "400 electrons, kT=0.01 Ha, one common Fermi level, the whole batch per call",
 }
 # tridiagonalisation routes: one-stage Householder, or dense -> band -> tridiagonal
 ROUTE_FLAGS = {"onestage": 0, "twostage": 8}

@@ -140,7 +140,8 @@ typedef struct ks_plan ks_plan; /* opaque: workspace, cached Cholesky factor, in
 typedef struct {
     int32_t n;          /* orbitals per spin block; order = n (collinear) or 2n   */
     int32_t batch;      /* k-points solved together (>= 1, <= 64): every kernel of  */
-                        /* the solve takes all of them in one launch               */
+                        /* the solve takes all of them in one launch, except the   */
+                        /* tridiagonalisation (two halves on two streams)          */
     int32_t dtype;      /* KS_REAL64 or KS_COMPLEX128; noncollinear needs complex  */
     int32_t spin;       /* KS_COLLINEAR (g = 2) or KS_NONCOLLINEAR (g = 1)         */
     int32_t precision;  /* KS_FP64 or KS_MIXED (FP32 trailing updates, refined)    */
